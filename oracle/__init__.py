@@ -1,0 +1,293 @@
+"""ctypes shim around the FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the plain, slow, obviously-correct reference the GPU
+library is checked against; it shares no code with the library.  Only ``tests/``, the smoke
+check and the benchmark's CPU-baseline leg import this module.
+
+Functions mirror the library's calls: ``Model`` (build_tree + set_dust), ``Model.locate``,
+``Model.trace``, ``Model.solve_temperature``, ``Model.render``, and ``lambda_iterate`` (the
+Lambda iteration of the paper's Eq. 2 driven from the oracle's own pieces).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no fp contraction)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class Stats(C.Structure):
+    _fields_ = [("crossings", C.c_uint64), ("scatterings", C.c_uint64), ("kills", C.c_uint64),
+                ("truncated", C.c_uint64), ("packets", C.c_uint64), ("dropped_zero_q", C.c_uint64),
+                ("e_emit", C.c_double), ("e_abs", C.c_double), ("e_esc", C.c_double),
+                ("e_killed", C.c_double), ("e_rr_gain", C.c_double), ("e_trunc", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+RECORD_DTYPE = np.dtype([("status", "<u4"), ("crossings", "<u4"), ("events", "<u4"),
+                         ("pad", "<u4"), ("node", "<i8"), ("birth", "<i8"), ("w", "<f8")])
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_SO)
+        P = C.c_void_p
+        L.om_build.restype = P
+        L.om_build.argtypes = [C.c_int32] * 3 + [C.c_double, C.c_int32, P, P, P, P]
+        L.om_free.argtypes = [P]
+        L.om_error.restype = C.c_char_p
+        L.om_n_nodes.restype = C.c_int64
+        L.om_n_nodes.argtypes = [P]
+        L.om_n_levels.restype = C.c_int32
+        L.om_n_levels.argtypes = [P]
+        L.om_level_offsets.argtypes = [P, P]
+        L.om_child.argtypes = [P, P]
+        L.om_node_rho.argtypes = [P, P]
+        L.om_locate.argtypes = [P, C.c_int64, P, P, P]
+        L.om_philox.argtypes = [C.c_uint32, C.c_uint32, C.c_int64, P, P]
+        L.om_set_dust.restype = C.c_int
+        L.om_set_dust.argtypes = [P, C.c_int32, P, P, P, P]
+        L.om_dnu.argtypes = [P, P]
+        L.om_trace.restype = C.c_int
+        L.om_trace.argtypes = [P, C.c_int32, C.c_int32, P, P, P, P, P, P, C.c_uint64, C.c_uint32,
+                               C.c_double, C.c_double, C.c_int64, C.c_int32, C.c_int64, C.c_int64,
+                               C.c_int32, P, P, P, C.c_int64, P]
+        L.om_solve_temperature.argtypes = [P, P, C.c_double, C.c_double, P]
+        L.om_emission.restype = C.c_double
+        L.om_emission.argtypes = [P, C.c_int64, C.c_double]
+        L.om_render.restype = C.c_int
+        L.om_render.argtypes = [P, P, C.c_int32, C.c_double, C.c_int32, P, P, P, P]
+        L.om_hg_mu.restype = C.c_double
+        L.om_hg_mu.argtypes = [C.c_double, C.c_double]
+        L.om_rotate.argtypes = [P, C.c_double, C.c_double]
+        L.om_uniform.restype = C.c_double
+        L.om_uniform.argtypes = [C.c_uint32]
+        L.om_cdf_pick.restype = C.c_int64
+        L.om_cdf_pick.argtypes = [P, C.c_int64, C.c_uint64]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class Model:
+    """One oct-tree model with its dust table, held by the oracle."""
+
+    def __init__(self, tree, dust=None):
+        L = lib()
+        self._keep = []
+        nl = tree.n_levels
+        root = np.ascontiguousarray(tree.root_rho, dtype=np.float64)
+        nref = np.array([len(r) for r in tree.refined] or [0], dtype=np.int64)
+        refs = [np.ascontiguousarray(r, dtype=np.int64) for r in tree.refined]
+        kids = [np.ascontiguousarray(k, dtype=np.float64) for k in tree.child_rho]
+        rp = (C.c_void_p * max(nl, 1))(*[_p(r).value for r in refs] or [None])
+        kp = (C.c_void_p * max(nl, 1))(*[_p(k).value for k in kids] or [None])
+        h = L.om_build(tree.nx, tree.ny, tree.nz, float(tree.root_cell_cm), nl, _p(root),
+                       _p(nref), C.cast(rp, C.c_void_p), C.cast(kp, C.c_void_p))
+        if not h:
+            raise OracleError(L.om_error().decode())
+        self.h = h
+        self.tree = tree
+        self.n_nodes = int(L.om_n_nodes(h))
+        self.n_levels = nl
+        off = np.zeros(nl + 2, dtype=np.int64)
+        L.om_level_offsets(h, _p(off))
+        self.offsets = off
+        ch = np.zeros(self.n_nodes, dtype=np.int64)
+        L.om_child(h, _p(ch))
+        self.child = ch
+        self.n_lambda = 0
+        if dust is not None:
+            self.set_dust(dust)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().om_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    @property
+    def leaf_mask(self):
+        return self.child < 0
+
+    def level_of_nodes(self):
+        lv = np.zeros(self.n_nodes, dtype=np.int32)
+        for l in range(self.n_levels + 1):
+            lv[self.offsets[l]:self.offsets[l + 1]] = l
+        return lv
+
+    def node_rho(self):
+        r = np.zeros(self.n_nodes)
+        lib().om_node_rho(self.h, _p(r))
+        return r
+
+    def set_dust(self, dust):
+        L = lib()
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in
+                (dust.lambda_um, dust.kappa_ext, dust.albedo, dust.hg_g)]
+        if L.om_set_dust(self.h, len(arrs[0]), *[_p(a) for a in arrs]) != 0:
+            raise OracleError(L.om_error().decode())
+        self.n_lambda = len(arrs[0])
+        self.dust = dust
+
+    def dnu(self):
+        d = np.zeros(self.n_lambda)
+        lib().om_dnu(self.h, _p(d))
+        return d
+
+    def locate(self, xyz):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        n = len(xyz)
+        lev = np.zeros(n, dtype=np.int32)
+        node = np.zeros(n, dtype=np.int64)
+        lib().om_locate(self.h, n, _p(xyz), _p(lev), _p(node))
+        return lev, node
+
+    def trace(self, sources, seed, iteration=0, model_index=0, rr_threshold=0.0, rr_prob=0.0,
+              max_events=0, per_lambda=False, pid_begin=0, pid_end=-1, lam_sel=-1,
+              t_node=None, rec_stride=0):
+        """Follow packets of ``sources`` (gen.Source list) -> (e_abs, e_esc, stats, records)."""
+        L = lib()
+        ns = len(sources)
+        nl = self.n_lambda
+        kind = np.array([s.kind for s in sources], dtype=np.int32)
+        pos = np.array([s.pos for s in sources], dtype=np.float64).reshape(-1)
+        dirs = np.array([s.dir for s in sources], dtype=np.float64).reshape(-1)
+        power = np.zeros(ns * nl)
+        for i, s in enumerate(sources):
+            if s.power is not None:
+                power[i * nl:(i + 1) * nl] = s.power
+        packets = np.array([s.packets for s in sources], dtype=np.int64)
+        e_abs = np.zeros(self.n_nodes * (nl if per_lambda else 1))
+        e_esc = np.zeros(nl)
+        st = Stats()
+        tn = None if t_node is None else np.ascontiguousarray(t_node, dtype=np.float64)
+        rec = None
+        pid_end = pid_end if pid_end >= 0 else int(packets.max())
+        if rec_stride > 0:
+            nrec = (pid_end - pid_begin + rec_stride - 1) // rec_stride
+            rec = np.zeros(ns * nl * nrec, dtype=RECORD_DTYPE)
+        rc = L.om_trace(self.h, model_index, ns, _p(kind), _p(pos), _p(dirs), _p(power),
+                        _p(packets), None if tn is None else _p(tn), C.c_uint64(seed),
+                        iteration, rr_threshold, rr_prob, max_events, int(per_lambda),
+                        pid_begin, pid_end, lam_sel, _p(e_abs), _p(e_esc), C.byref(st),
+                        rec_stride, None if rec is None else _p(rec))
+        if rc != 0:
+            raise OracleError(L.om_error().decode())
+        if per_lambda:
+            e_abs = e_abs.reshape(nl, self.n_nodes)
+        return e_abs, e_esc, st.as_dict(), rec
+
+    def solve_temperature(self, a_node, t_min=2.0, t_max=3000.0):
+        a = np.ascontiguousarray(a_node, dtype=np.float64)
+        t = np.zeros(self.n_nodes)
+        lib().om_solve_temperature(self.h, _p(a), t_min, t_max, _p(t))
+        return t
+
+    def emission(self, node, t):
+        return lib().om_emission(self.h, int(node), float(t))
+
+    def render(self, n_obs, npix, t_node, lambda_idx, width=0.0):
+        L = lib()
+        nv = np.ascontiguousarray(n_obs, dtype=np.float64)
+        li = np.ascontiguousarray(lambda_idx, dtype=np.int32)
+        tn = np.ascontiguousarray(t_node, dtype=np.float64)
+        img = np.zeros((len(li), npix, npix))
+        cr = C.c_uint64(0)
+        rc = L.om_render(self.h, _p(nv), npix, width, len(li), _p(li), _p(tn), _p(img),
+                         C.byref(cr))
+        if rc != 0:
+            raise OracleError(L.om_error().decode())
+        return img, int(cr.value)
+
+
+def philox(key0, key1, ctr):
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.zeros_like(ctr)
+    lib().om_philox(key0, key1, len(ctr), _p(ctr), _p(out))
+    return out
+
+
+def hg_mu(g, u):
+    return lib().om_hg_mu(float(g), float(u))
+
+
+def rotate(d, mu, phi):
+    v = np.ascontiguousarray(d, dtype=np.float64).copy()
+    lib().om_rotate(_p(v), float(mu), float(phi))
+    return v
+
+
+def cdf_pick(q, r):
+    q = np.ascontiguousarray(q, dtype=np.uint64)
+    return int(lib().om_cdf_pick(_p(q), len(q), C.c_uint64(int(r))))
+
+
+def uniform(x):
+    """The oracle's uniform mapping (2 (x >> 9) + 1) 2^-24, for tests."""
+    x = np.asarray(x, dtype=np.uint64)
+    return ((x >> np.uint64(9)).astype(np.float64) * 2.0 + 1.0) * 2.0 ** -24
+
+
+def lambda_iterate(model, star_sources, seed, n_max=30, tol=1e-3, n_fixed=None,
+                   dust_packets=None, rr_threshold=0.0, rr_prob=0.0, t_min=2.0, t_max=3000.0):
+    """Lambda iteration (paper Sect. 3.1 Eq. 2; constant-source field kept, Sect. 3.2):
+    A_stars from the constant sources once, T_0 = f(A_stars); then for n >= 1 the dust
+    emission of T_{n-1} is traced with key iteration n, T_n = f(A_stars + A_dust).
+    Stops when the mass-weighted mean |T_n - T_{n-1}|/T_{n-1} < tol, or after n_max steps
+    (or exactly n_fixed steps).  Returns (T history list, A_stars, per-step dust-trace stats)."""
+    import gen
+    a_stars, _, _, _ = model.trace(star_sources, seed, iteration=0, rr_threshold=rr_threshold,
+                                   rr_prob=rr_prob)
+    t = model.solve_temperature(a_stars, t_min, t_max)
+    hist = [t]
+    leaf = model.leaf_mask
+    lv = model.level_of_nodes()
+    mass = model.node_rho() * (model.tree.root_cell_cm * 2.0 ** -lv) ** 3
+    n_steps = n_fixed if n_fixed is not None else n_max
+    npk = dust_packets if dust_packets is not None else star_sources[0].packets
+    stats = []
+    for it in range(1, n_steps + 1):
+        src = [gen.Source(gen.SRC_DUST, 0, packets=npk)]
+        a_dust, _, st, _ = model.trace(src, seed, iteration=it, rr_threshold=rr_threshold,
+                                       rr_prob=rr_prob, t_node=t)
+        stats.append(st)
+        t_new = model.solve_temperature(a_stars + a_dust, t_min, t_max)
+        hist.append(t_new)
+        w = mass[leaf]
+        rel = np.abs(t_new[leaf] - t[leaf]) / t[leaf]
+        crit = float((w * rel).sum() / w.sum()) if w.sum() > 0 else 0.0
+        t = t_new
+        if n_fixed is None and crit < tol:
+            break
+    return hist, a_stars, stats

@@ -1,0 +1,108 @@
+/* FP64 CPU oracle for Monte Carlo continuum radiative transfer on an oct-tree.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Plain, slow, single-threaded C; shares no source with the GPU
+ * library.  Only the tests, the smoke check and the benchmark's CPU-baseline leg may load it.
+ *
+ * What it follows (Lunttila & Juvela, "Radiative transfer on hierarchial grids"):
+ *   - Sect. 2.1: nested-grid hierarchy, subgrid identification looked up at every crossing;
+ *   - Sect. 2.3: packets from internal sources and from the external field, continuous
+ *     absorption, Russian roulette with threshold n and probability p;
+ *   - Sect. 3.1 Eq. (2): Lambda iteration J_{n+1} = Lambda S_n + J_0, S_{n+1} = f(J_{n+1});
+ *   - Sect. 4: one dust component at its equilibrium temperature, frequencies one by one;
+ *   - Sect. 4.1: surface-brightness maps toward chosen directions.
+ * The in-grid tracking itself is not described in the paper (it defers to earlier work);
+ * the readings used here are listed in the header comment of oracle.c.
+ */
+#ifndef ORACLE_H
+#define ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct om_model om_model;
+
+/* Build a model from a tree description (root grid + per-level refined-cell lists + child
+ * densities, canonical order).  Returns NULL on invalid input (message in om_error()). */
+om_model* om_build(int32_t nx, int32_t ny, int32_t nz, double root_cell_cm, int32_t n_levels,
+                   const double* root_rho, const int64_t* n_refined,
+                   const int64_t* const* refined, const double* const* child_rho);
+void om_free(om_model* m);
+const char* om_error(void);
+
+int64_t om_n_nodes(const om_model* m);
+int32_t om_n_levels(const om_model* m);
+void om_level_offsets(const om_model* m, int64_t* off /* n_levels+2 */);
+void om_child(const om_model* m, int64_t* child /* n_nodes: oct index or -1 */);
+void om_node_rho(const om_model* m, double* rho);
+
+/* Point location: half-open cells.  level_out/node_out receive -1 outside. */
+void om_locate(const om_model* m, int64_t n, const double* xyz, int32_t* level_out,
+               int64_t* node_out);
+
+/* Philox4x32-10 blocks for explicit counters: ctr[4n] -> out[4n]. */
+void om_philox(uint32_t k0, uint32_t k1, int64_t n, const uint32_t* ctr, uint32_t* out);
+
+int om_set_dust(om_model* m, int32_t n_lambda, const double* lambda_um, const double* kappa,
+                const double* albedo, const double* hg_g);
+void om_dnu(const om_model* m, double* dnu);
+
+/* Source kinds */
+#define OM_BACKGROUND 0
+#define OM_POINT 1
+#define OM_DUST 2
+#define OM_BEAM 3
+
+typedef struct {
+  uint64_t crossings, scatterings, kills, truncated, packets, dropped_zero_q;
+  double e_emit, e_abs, e_esc, e_killed, e_rr_gain, e_trunc;
+} om_stats;
+
+/* One packet's end state (for sampled-history comparison). status: 0 escaped, 1 killed,
+   2 truncated.  node: canonical node where the packet ended (-1 if escaped); birth: node where
+   it started; w: its weight at the end. */
+typedef struct {
+  uint32_t status, crossings, events, pad;
+  int64_t node, birth;
+  double w;
+} om_record;
+
+/* Trace the packets of n_src sources.  For each source s and each wavelength i, packets
+ * 0..packets[s]-1 of stream (model<<20 | s<<12 | i) are followed.  power[s*n_lambda + i]
+ * is the background intensity times nothing (I_nu, per Hz) or the source luminosity L_nu;
+ * DUST sources take the temperatures t_node (canonical, leaves) instead.
+ * e_abs: [n_nodes] (lambda-integrated) or [n_lambda*n_nodes] if per_lambda.
+ * e_esc: [n_lambda].  rec (optional): one record per sampled packet, packet index j of
+ * (source s, wavelength i) is sampled when j % rec_stride == 0 and stored at
+ * (s*n_lambda + i)*nrec + (j-pid_begin)/rec_stride with nrec = ceil((pid_end-pid_begin)/rec_stride);
+ * only packets j in [pid_begin, min(pid_end, packets[s])) are traced, and only wavelength
+ * lam_sel unless it is negative. */
+int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kind,
+             const double* pos /*3n*/, const double* dir /*3n*/, const double* power,
+             const int64_t* packets, const double* t_node, uint64_t seed, uint32_t iteration,
+             double rr_threshold, double rr_prob, int64_t max_events, int32_t per_lambda,
+             int64_t pid_begin, int64_t pid_end, int32_t lam_sel,
+             double* e_abs, double* e_esc, om_stats* stats, int64_t rec_stride, om_record* rec);
+
+/* Equilibrium temperature per leaf: 4 pi m sum_i kappa_abs_i B_i(T) dnu_i = A. */
+void om_solve_temperature(const om_model* m, const double* a_node, double t_min, double t_max,
+                          double* t_node);
+/* Emitted power of a leaf at temperature T (the left-hand side above). */
+double om_emission(const om_model* m, int64_t node, double t);
+
+/* Surface-brightness map along rays toward the observer direction n. */
+int om_render(const om_model* m, const double n_obs[3], int32_t npix, double width,
+              int32_t n_sel, const int32_t* lambda_idx, const double* t_node, double* image,
+              uint64_t* crossings);
+
+/* Test hooks exposing single steps for the pins. */
+double om_hg_mu(double g, double u);
+void om_rotate(double* d, double mu, double phi);
+double om_uniform(uint32_t x);
+int64_t om_cdf_pick(const uint64_t* q, int64_t n, uint64_t r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
