@@ -1,0 +1,159 @@
+"""Benchmark: molecular-cloud workload (root 64^3, up to 3 levels, 32 wavelengths, 1e7 packets
+per wavelength, dust temperatures, 256^2 maps toward 3 axes) on one MI355X.
+
+A step is one pass of the whole path over the resident model: trace all packets (FP32-local
+persistent form), reduce the absorbed energy to FP64, solve the temperatures, render the maps.
+The plain FP64 form is timed on the same inputs for comparison.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_CROSSING_FP32 = 12.0   # packed density/subgrid word 4 B + FP32 accumulator RMW 8 B
+BYTES_PER_CROSSING_FP64 = 28.0   # FP64 density 8 B + child 4 B + FP64 accumulator RMW 16 B
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--packets", type=int, default=10_000_000, help="packets per wavelength")
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-packets", type=int, default=1 << 15,
+                    help="oracle sample: packets per wavelength")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--refill", type=float, default=0.0)
+    ap.add_argument("--trace-only", action="store_true", help="time only the transport step")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import gen
+    import paper_1206_3710_amd as rt
+
+    w = gen.c2(packets=a.packets)
+    tree, dust = w.trees[0], w.dusts[0]
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    nl = dust.n_lambda
+    lam_all = list(range(nl))
+    kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob, block_size=a.block,
+              blocks_per_cu=a.blocks_per_cu, refill_threshold=a.refill)
+
+    def step(precision, it):
+        r = ctx.trace_packets(w.sources, seed=w.seed, iteration=it, precision=precision, **kw)
+        t = time.perf_counter()
+        out = {"stats": r["stats"]}
+        if not a.trace_only:
+            ctx.solve_temperature(m, r["e_abs_node"], 2.0, 3000.0)
+            for d in w.map_dirs:
+                ctx.render_map(m, d, w.map_npix, lam_all)
+        out["post_s"] = time.perf_counter() - t
+        return out
+
+    for i in range(a.warmup):
+        step(rt.FP32_LOCAL, 1000 + i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    crossings = 0
+    kernel_ms = []
+    post = []
+    for i in range(a.steps):
+        o = step(rt.FP32_LOCAL, i)
+        crossings += o["stats"]["crossings"]
+        kernel_ms.append(o["stats"]["kernel_ms"])
+        post.append(o["post_s"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = crossings / dt
+    k_avg = sum(kernel_ms) / len(kernel_ms) / 1e3
+    cr_step = crossings / a.steps
+    achieved = cr_step * BYTES_PER_CROSSING_FP32 / k_avg / 1e9
+
+    # plain FP64 form on the same inputs
+    fp64 = None
+    if a.fp64_steps > 0:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c64 = 0
+        k64 = []
+        for i in range(a.fp64_steps):
+            o = step(rt.FP64, i)
+            c64 += o["stats"]["crossings"]
+            k64.append(o["stats"]["kernel_ms"])
+        torch.cuda.synchronize()
+        d64 = time.perf_counter() - t1
+        k64a = sum(k64) / len(k64) / 1e3
+        fp64 = {"crossings_per_s": c64 / d64, "ms_per_step": 1e3 * d64 / a.fp64_steps,
+                "trace_kernel_ms": 1e3 * k64a,
+                "trace_crossings_per_s": (c64 / a.fp64_steps) / k64a,
+                "hbm_frac_algorithmic": (c64 / a.fp64_steps) * BYTES_PER_CROSSING_FP64 / k64a / 1e9 / HBM_PEAK_GBS}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        ora = oracle.Model(tree, dust)
+        t2 = time.perf_counter()
+        _, _, sto, _ = ora.trace(w.sources, seed=w.seed, rr_threshold=w.rr_threshold,
+                                 rr_prob=w.rr_prob, pid_end=a.cpu_packets)
+        dc = time.perf_counter() - t2
+        cpu = {"value": sto["crossings"] / dc, "unit": "cell-crossings/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"first {a.cpu_packets} packets of each of the {nl} wavelengths "
+                         f"({sto['crossings']} crossings, {dc:.1f} s, single thread, "
+                         f"{platform.processor() or platform.machine()})"}
+
+    res = {
+        "metric": "cell-crossings/s (FP32-local form; FP64 form in fp64)",
+        "value": value,
+        "unit": "cell-crossings/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * dt / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "molecular cloud: root 64^3, 3 levels, 32 wavelengths 0.1-1000 um, "
+                               "1e7 packets/wavelength (isotropic field), roulette 1e-3/0.9, "
+                               "dust temperatures, 256^2 maps toward +x,+y,+z at 32 wavelengths"
+                               + (" (trace only)" if a.trace_only else ""),
+                   "nodes": tree.n_nodes, "leaves": tree.n_leaves,
+                   "packets_per_step": int(w.sources[0].packets * nl),
+                   "crossings_per_step": cr_step},
+        "trace_kernel_ms": 1e3 * k_avg,
+        "trace_crossings_per_s": cr_step / k_avg,
+        "post_trace_ms": 1e3 * sum(post) / len(post),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "trace_fp32_kernel", "bytes_per_crossing": BYTES_PER_CROSSING_FP32},
+        "fp64": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

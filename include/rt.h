@@ -1,0 +1,210 @@
+/* rt.h — C ABI of the MI355X (gfx950) Monte Carlo continuum radiative-transfer library for
+ * hierarchical (oct-tree) grids.
+ *
+ * The operations follow Lunttila & Juvela, "Radiative transfer on hierarchial grids":
+ *   rt_build_tree         the nested-grid hierarchy of Sect. 2.1 (refinement ratio one half);
+ *   rt_set_dust           the single-component dust model of Sect. 4 (opacity, albedo, and a
+ *                         Henyey-Greenstein asymmetry parameter for the phase function);
+ *   rt_trace_packets      the Monte Carlo formal solution of Sect. 2.3 (internal sources and the
+ *                         external field, continuous absorption, Russian roulette);
+ *   rt_solve_temperature  the dust model f(J) of Sect. 3.1 Eq. (1)-(2): equilibrium temperature
+ *                         of one grain component (Sect. 4);
+ *   rt_lambda_iterate     the Lambda iteration of Sect. 3.1 Eq. (2) with the constant-source
+ *                         field kept (Sect. 3.2);
+ *   rt_render_map         surface-brightness maps toward chosen directions (Sect. 4.1).
+ *
+ * Conventions
+ *   - Every call validates all of its arguments before it changes any state; on error it
+ *     returns a negative status, leaves the context unchanged and records a message that
+ *     rt_last_error() returns.  No C++ exception crosses this interface.
+ *   - Array arguments marked "host or device" may point to host memory or to device memory of
+ *     the context's GPU (for example torch tensors); the library classifies them itself.
+ *     Device outputs are written in order on the context's stream; calls return after the
+ *     stream has completed the work unless stated otherwise.
+ *   - The context owns every device buffer it allocates; the caller owns all arrays it passes.
+ *   - One context per host thread.
+ */
+#ifndef RT_H
+#define RT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rt_status;
+#define RT_OK 0
+#define RT_EINVAL (-1)   /* invalid argument */
+#define RT_ENOMEM (-2)   /* device or host allocation failed */
+#define RT_EDEVICE (-3)  /* HIP runtime error, or no usable gfx950 device */
+#define RT_ESTATE (-4)   /* call out of order (e.g. tracing before rt_set_dust) */
+
+#define RT_MAX_LEVELS 24
+
+typedef struct rt_ctx rt_ctx;
+
+/* Message describing the last failing call on ctx ("" if none).  Valid until the next call. */
+const char* rt_last_error(const rt_ctx* ctx);
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream` (a hipStream_t; NULL =
+ * the null stream).  Fails with RT_EDEVICE if the device is absent or not gfx950. */
+rt_status rt_create(rt_ctx** out, int32_t device, void* hip_stream);
+rt_status rt_destroy(rt_ctx* ctx);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Tree (Sect. 2.1).  Root grid of nx*ny*nz cells (x fastest); each refined cell is replaced by
+ * one oct of 8 cells of half its size.  Canonical order: level-0 index ix + nx*(iy + ny*iz);
+ * the octs of level l+1 follow the ascending level-l index of their parent, and cell
+ * b = bx + 2by + 4bz of oct o has level index 8o + b; node id = level offset + level index.
+ * Host arrays are read during the call only.                                                */
+typedef struct {
+  int32_t nx, ny, nz;            /* root cells per axis, >= 1 */
+  double root_cell_cm;           /* physical edge of a root cell (cm), > 0 */
+  int32_t n_levels;              /* refinement levels below the root, 0..RT_MAX_LEVELS */
+  const double* root_rho;        /* [nx*ny*nz] density (g cm^-3), finite, >= 0 */
+  const int64_t* n_refined;      /* [n_levels] number of refined cells at level l */
+  const int64_t* const* refined; /* [n_levels][n_refined[l]] strictly ascending level-l indices */
+  const double* const* child_rho;/* [n_levels][8*n_refined[l]] densities of level l+1 cells */
+} rt_tree_desc;
+
+/* Validates and uploads a tree; returns its model id and canonical node count.  Several
+ * models may live in one context (they are traced together by rt_trace_packets). */
+rt_status rt_build_tree(rt_ctx* ctx, const rt_tree_desc* desc, int32_t* model_out,
+                        int64_t* n_nodes_out);
+
+typedef struct {
+  int64_t n_nodes, n_leaves;
+  int32_t n_levels, n_lambda;
+  int64_t level_offset[RT_MAX_LEVELS + 2]; /* canonical node offset of each level */
+  int64_t node_base;        /* offset of this model in node-wise outputs (all models) */
+  int64_t lambda_base;      /* offset of this model in wavelength-wise outputs */
+  int64_t lambda_node_base; /* offset of this model in per-(wavelength, node) outputs */
+} rt_model_info;
+rt_status rt_get_model_info(rt_ctx* ctx, int32_t model, rt_model_info* out);
+
+/* Totals over all models of the context: node-wise, wavelength-wise and per-(wavelength,
+ * node) output lengths. */
+rt_status rt_get_sizes(rt_ctx* ctx, int64_t* nodes, int64_t* lambdas, int64_t* lambda_nodes);
+
+/* Point location with half-open cells [lo, hi): xyz [n][3] in root-cell units (host or
+ * device); outputs level and canonical node (host or device), -1 for points outside the root
+ * grid or NaN.  Bit-exact: no rounding is involved. */
+rt_status rt_locate(rt_ctx* ctx, int32_t model, int64_t n, const double* xyz, int32_t* level_out,
+                    int64_t* node_out);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Dust (Sect. 4): per wavelength (strictly ascending, um) the extinction opacity (cm^2 g^-1,
+ * > 0), albedo in [0, 1] and Henyey-Greenstein g in (-1, 1).  Frequency bandwidths are the
+ * trapezoid weights in nu of this grid (a single wavelength has bandwidth 1).  Host arrays. */
+rt_status rt_set_dust(rt_ctx* ctx, int32_t model, int32_t n_lambda, const double* lambda_um,
+                      const double* kappa_ext, const double* albedo, const double* hg_g);
+
+/* Per-leaf temperatures used by dust-emission sources and maps: canonical [n_nodes] (host or
+ * device, values of refined nodes ignored).  rt_solve_temperature also sets them. */
+rt_status rt_set_temperature(rt_ctx* ctx, int32_t model, const double* t_node);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Sources (Sect. 2.3) */
+#define RT_SRC_BACKGROUND 0 /* isotropic field I_nu outside the root box (power: I_nu, per sr) */
+#define RT_SRC_POINT 1      /* isotropic point source L_nu at pos (power: L_nu, erg/s/Hz) */
+#define RT_SRC_DUST 2       /* thermal dust emission of the model's current temperatures */
+#define RT_SRC_BEAM 3       /* pencil beam from pos along dir (power: L_nu); test source */
+
+typedef struct {
+  int32_t kind;
+  int32_t model;
+  double pos[3];                /* POINT, BEAM: root-cell units, inside the root grid */
+  double dir[3];                /* BEAM: direction (normalised by the library) */
+  const double* power;          /* host [n_lambda of the model]; NULL for DUST */
+  int64_t packets_per_lambda;   /* 1 .. 2^32 */
+} rt_source;
+
+#define RT_FP64 0        /* plain form: one packet per lane, global FP64 coordinates */
+#define RT_FP32_LOCAL 1  /* persistent packet queue, FP32 per-cell local coordinates */
+
+/* Per-packet end state, written for sampled packets (see rt_trace_opts.rec_stride). */
+typedef struct {
+  uint32_t status;     /* 0 escaped, 1 killed by roulette, 2 truncated at max_events */
+  uint32_t crossings;  /* leaf cells entered, including the birth cell */
+  uint32_t events;     /* scattering events reached */
+  uint32_t pad;
+  int64_t node;        /* canonical node where it ended (-1 escaped) */
+  int64_t birth;       /* canonical node where it started */
+  double w;            /* weight at the end (escaped, killed or truncated energy) */
+} rt_record;
+
+typedef struct {
+  uint64_t seed;            /* Philox key = (lo32(seed), hi32(seed) + iteration) */
+  uint32_t iteration;
+  int32_t precision;        /* RT_FP64 or RT_FP32_LOCAL */
+  double rr_threshold;      /* roulette when w < rr_threshold * w0 (relative); 0 = off */
+  double rr_prob;           /* kill probability p; survivors scaled by 1/(1-p) */
+  int64_t max_events;       /* per-packet scattering cap; 0 = 1e6 */
+  int32_t block_size;       /* threads per block (multiple of 64, <= 1024); 0 = default */
+  int32_t blocks_per_cu;    /* persistent form: resident blocks per CU; 0 = default */
+  float refill_threshold;   /* persistent form: service events/refills when fewer than this
+                               fraction of live lanes are crossing; 0 = default */
+  int32_t pad0;
+  int64_t rec_stride;       /* > 0: record packet j of each (source, wavelength) when
+                               j % rec_stride == 0 */
+  rt_record* records;       /* host or device; job-major: job (source-major, then wavelength)
+                               base = sum over earlier jobs of ceil(N/rec_stride) */
+} rt_trace_opts;
+
+typedef struct {
+  uint64_t crossings, scatterings, kills, truncated, packets;
+  double e_emit, e_abs, e_esc, e_killed, e_rr_gain, e_trunc;
+  double kernel_ms;         /* device time of the transport kernels (HIP events) */
+  double reduce_ms;         /* device time of the final FP64 reduction */
+} rt_trace_stats;
+
+/* Follow packets_per_lambda packets of every source at every wavelength of its model.  Packet
+ * j of (source s, wavelength i, model m) uses Philox stream (m << 20 | s << 12 | i).
+ * Outputs (host or device; NULL to skip):
+ *   e_abs_node         [total nodes] absorbed power per canonical node, all wavelengths;
+ *   e_abs_lambda_node  [total lambda_nodes] per (wavelength, node), model-major;
+ *   e_esc_lambda       [total lambdas] escaped power per wavelength.
+ * The absorbed energy is reduced to FP64 in a final pass in both precisions. */
+rt_status rt_trace_packets(rt_ctx* ctx, int32_t n_src, const rt_source* src,
+                           const rt_trace_opts* opts, double* e_abs_node,
+                           double* e_abs_lambda_node, double* e_esc_lambda,
+                           rt_trace_stats* stats);
+
+/* Equilibrium temperature per leaf (FP64): 4 pi m sum_i kappa_abs_i B_i(T) dnu_i = A, with A
+ * the absorbed power per canonical node (host or device).  A at or below the emission at
+ * t_min gives t_min, at or above the emission at t_max gives t_max; refined nodes get 0.
+ * Stores the result as the model's temperatures; t_node (host or device) may be NULL. */
+rt_status rt_solve_temperature(rt_ctx* ctx, int32_t model, const double* a_node, double t_min,
+                               double t_max, double* t_node);
+
+/* Lambda iteration (Sect. 3.1 Eq. 2, constant sources kept per Sect. 3.2): trace the constant
+ * sources once (key iteration 0) -> A_stars, T_0 = f(A_stars); for n >= 1 trace the dust
+ * emission of T_{n-1} (key iteration n, dust_packets per wavelength) -> A_dust,
+ * T_n = f(A_stars + A_dust); stop when the mass-weighted mean of |T_n - T_{n-1}| / T_{n-1} is
+ * below tol or after n_max steps.  crit [n_max] (host, may be NULL) receives the statistic of
+ * each step; t_node (host or device, may be NULL) the final temperatures. */
+rt_status rt_lambda_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
+                            const rt_trace_opts* opts, int64_t dust_packets, int32_t n_max,
+                            double tol, double t_min, double t_max, double* t_node,
+                            int32_t* n_done, double* crit);
+
+/* Surface-brightness map (Sect. 4.1) of a model with its current temperatures: orthographic
+ * view toward the observer direction n_obs; pixel (i, j) centre = box centre +
+ * ((i+0.5)/npix - 0.5) W e1 + ((j+0.5)/npix - 0.5) W e2 with e1 = z x n / |z x n| (x if n is
+ * along z), e2 = n x e1, W = width (<= 0: largest root extent).  Along each ray
+ * I <- I exp(-dtau) + (1 - a) B(T) (1 - exp(-dtau)).  image [n_sel][npix][npix] (host or
+ * device) in erg s^-1 cm^-2 Hz^-1 sr^-1; crossings (may be NULL) counts leaf entries. */
+rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32_t npix,
+                        double width, int32_t n_sel, const int32_t* lambda_idx,
+                        int32_t precision, double* image, uint64_t* crossings);
+
+/* Diagnostic: Philox4x32-10 blocks for explicit counters ctr[n][4] -> out[n][4] (host or
+ * device), computed on the GPU with the transport kernels' generator. */
+rt_status rt_philox(rt_ctx* ctx, uint32_t key0, uint32_t key1, int64_t n, const uint32_t* ctr,
+                    uint32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

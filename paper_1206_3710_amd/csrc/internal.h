@@ -1,0 +1,136 @@
+// Internal structures shared by the host runtime and the gfx950 kernels.
+//
+// Device node layout (all models of a context in one id space):
+//   model m occupies internal ids [base, base + n_int), base a multiple of 8;
+//   root cells at base + (ix + nx*(iy + ny*iz)); the root level is padded to a multiple of 8,
+//   so every oct (8 children) starts at a multiple of 8 and its id >> 3 indexes `up`.
+//   canonical id = internal - base                (root level)
+//                = internal - base - pad0         (deeper levels), pad0 = n_root_pad - n_root.
+// Per internal node:
+//   word[i]  int32: a leaf stores the float32 bits of its density (>= +0, so the int is >= 0);
+//            a refined cell stores ~first_child (negative): the subgrid identification entry
+//            of the paper's Sect. 2.1 packed into the density word (Sect. 3.4 footnote);
+//   rho64[i] FP64 density and child[i] first child or -1 (plain FP64 form);
+//   up[i>>3] parent id of the oct that starts at i (i a multiple of 8, level >= 1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rt.h"
+
+#define RT_JOBS_LDS 1024   // job starts staged in LDS when at most this many jobs
+#define RT_ESC_LDS 1024    // escape tallies staged in LDS when at most this many slots
+
+struct ModelDev {
+  int32_t n[3];
+  int32_t nlev;
+  int32_t base;        // internal id of root cell 0
+  int32_t n_root;      // nx*ny*nz
+  int32_t n_root_pad;  // n_root rounded up to a multiple of 8
+  int32_t n_int;       // internal ids used by this model (including padding)
+  double cell_cm;
+  int64_t canon_base;      // node-wise output offset
+  int64_t lam_base;        // wavelength-wise output offset
+  int64_t lamnode_base;    // per-(wavelength, node) output offset
+  int64_t leaf_base;       // offset into the leaf tables
+  int64_t n_leaves;
+  int64_t n_nodes;         // canonical node count
+  int32_t nl;
+  int32_t pad;
+  int64_t level_off[RT_MAX_LEVELS + 2];
+};
+
+struct JobDev {
+  uint64_t start;      // first global packet index of this job
+  uint64_t n;          // packets
+  int32_t model, kind, lam, src;
+  uint32_t stream;
+  int32_t esc_slot;    // wavelength-wise slot for escape tallies
+  double w0;           // initial weight (non-dust sources)
+  double pos[3];
+  double dir[3];
+  double kext, alb, g; // FP64 dust constants at this wavelength
+  float kc32, alb32, g32, pad32;  // FP32: kext * root_cell_cm, albedo, g
+  int64_t acc_off;     // element offset of this job's accumulator slot
+  int64_t rec_base;    // first record index (rec_stride > 0)
+  int64_t cdf_off;     // dust emission: offset of this (model, wavelength) table
+  uint64_t qtot;       // dust emission: total quantised luminosity
+};
+
+struct DevStats {
+  unsigned long long crossings, scatterings, kills, truncated, packets;
+  double e_emit, e_killed, e_rr_gain, e_trunc;
+};
+
+struct TraceParams {
+  const int32_t* word;
+  const double* rho64;
+  const int32_t* child;
+  const int32_t* up;
+  const ModelDev* models;
+  const JobDev* jobs;
+  int32_t n_jobs;
+  int32_t n_esc;
+  uint64_t total_packets;
+  unsigned long long* counter;
+  float* acc32;
+  double* acc64;
+  double* esc;
+  DevStats* stats;
+  rt_record* rec;
+  int64_t rec_stride;
+  uint32_t key0, key1;
+  double rr_thr, rr_p;
+  int64_t max_events;
+  float refill_thr;
+  int32_t pad;
+  // dust emission tables
+  const uint64_t* cdf_qpre;
+  const uint64_t* cdf_q;
+  const double* cdf_lum;
+  const int32_t* leaf_node;
+  const int32_t* leaf_coord;
+  const uint8_t* leaf_level;
+};
+
+// Launch wrappers (defined in the .hip files)
+hipError_t launch_trace_fp64(const TraceParams& p, int job, uint64_t n, int block, hipStream_t s);
+hipError_t launch_trace_fp32(const TraceParams& p, int grid, int block, hipStream_t s);
+hipError_t occupancy_trace_fp32(int block, int* blocks_per_cu);
+hipError_t launch_reduce_model(const ModelDev* models_dev, int model, int64_t n_nodes,
+                               const float* acc32, const double* acc64, int64_t slot_stride,
+                               int n_slots, double* e_node, double* e_lam_node, double* e_total,
+                               hipStream_t s);
+hipError_t launch_locate(const int32_t* child, const ModelDev* models, int model, int64_t n,
+                         const double* xyz, int32_t* lev, int64_t* node, hipStream_t s);
+hipError_t launch_philox(uint32_t k0, uint32_t k1, int64_t n, const uint32_t* ctr, uint32_t* out,
+                         hipStream_t s);
+hipError_t launch_add(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
+hipError_t launch_crit(const ModelDev* models, int model, int64_t n_nodes, const int32_t* child,
+                       const double* rho64, const double* t_new, const double* t_old, double* out,
+                       hipStream_t s);
+
+// Planck constants of one wavelength for the temperature solve, dust emission and maps.
+struct LamConst {
+  double kext, alb;
+  double kabs_dnu;   // (1 - albedo) * kappa_ext * dnu
+  double pre;        // 2 h nu^3 / c^2
+  double hnu;        // h nu
+  double dnu;
+};
+hipError_t launch_temperature(const ModelDev* models, int model, int64_t n_nodes,
+                              const int32_t* child, const double* rho64, const double* a_node,
+                              const LamConst* lc, int nl, double t_min, double t_max,
+                              double* t_out, hipStream_t s);
+hipError_t launch_dust_lum(const ModelDev* models, int model, int64_t n_leaves,
+                           const int32_t* leaf_node, const uint8_t* leaf_level,
+                           const double* rho64, const double* t_node, const LamConst* lc, int lam,
+                           double* lum, unsigned long long* lmax_bits, hipStream_t s);
+hipError_t launch_dust_quant(int64_t n_leaves, const double* lum,
+                             const unsigned long long* lmax_bits, uint64_t* q, hipStream_t s);
+hipError_t launch_render_fp64(const ModelDev* models, int model, const int32_t* child,
+                              const int32_t* up, const double* rho64, const double* t_node,
+                              const LamConst* lc, const int32_t* lam_idx, int n_sel,
+                              const double* view /* n, e1, e2, centre, W */, int npix,
+                              double* image, unsigned long long* crossings, hipStream_t s);

@@ -1,0 +1,153 @@
+// Small kernels: FP64 reduction of the absorbed-energy accumulators, point location and the
+// Philox diagnostic.
+#include "device.h"
+
+using namespace rtd;
+
+namespace {
+
+// Sum the wavelength slots of each node into FP64 (canonical order), optionally keep the
+// per-(wavelength, node) values, and add the model total.
+__global__ __launch_bounds__(256) void reduce_kernel(const ModelDev* __restrict__ models, int model,
+                                                     const float* __restrict__ acc32,
+                                                     const double* __restrict__ acc64,
+                                                     int64_t slot_stride, int n_slots,
+                                                     double* __restrict__ e_node,
+                                                     double* __restrict__ e_lam_node,
+                                                     double* __restrict__ e_total) {
+  __shared__ double s_part[4];
+  const ModelDev& m = models[model];
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double sum = 0.0;
+  if (c < m.n_nodes) {
+    const int64_t internal = m.base + (c < m.n_root ? c : c + (m.n_root_pad - m.n_root));
+    for (int s = 0; s < n_slots; ++s) {
+      const double v = acc32 ? (double)acc32[s * slot_stride + internal] : acc64[s * slot_stride + internal];
+      sum += v;
+      if (e_lam_node) e_lam_node[m.lamnode_base + s * m.n_nodes + c] = v;
+    }
+    if (e_node) e_node[m.canon_base + c] = sum;
+  }
+  sum = wave_sum(sum);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += s_part[i];
+    if (t != 0.0) unsafeAtomicAdd(e_total, t);
+  }
+}
+
+__global__ void locate_kernel(const int32_t* __restrict__ child, const ModelDev* __restrict__ models,
+                              int model, int64_t n, const double* __restrict__ xyz,
+                              int32_t* __restrict__ lev_out, int64_t* __restrict__ node_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const ModelDev& m = models[model];
+  const double P[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+  int lev = -1;
+  int32_t I[3];
+  const int32_t node = locate_walk(dims_of(m), P, lev, I, ChildPlain{child});
+  lev_out[i] = node < 0 ? -1 : lev;
+  node_out[i] = node < 0 ? -1 : canon_of(m, node);
+}
+
+__global__ void philox_kernel(uint32_t k0, uint32_t k1, int64_t n, const uint32_t* __restrict__ ctr,
+                              uint32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint4 r = philox(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);
+  out[4 * i] = r.x;
+  out[4 * i + 1] = r.y;
+  out[4 * i + 2] = r.z;
+  out[4 * i + 3] = r.w;
+}
+
+__global__ void add_kernel(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                           double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + b[i];
+}
+
+// Mass-weighted mean relative temperature change over the leaves (Lambda-iteration stopping
+// statistic): accumulates sum m |Tn - To| / To and sum m.
+__global__ __launch_bounds__(256) void crit_kernel(const ModelDev* __restrict__ models, int model,
+                                                   const int32_t* __restrict__ child,
+                                                   const double* __restrict__ rho64,
+                                                   const double* __restrict__ t_new,
+                                                   const double* __restrict__ t_old,
+                                                   double* __restrict__ out) {
+  __shared__ double s_a[4], s_b[4];
+  const ModelDev& m = models[model];
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double wa = 0.0, wb = 0.0;
+  if (c < m.n_nodes) {
+    const int64_t internal = m.base + (c < m.n_root ? c : c + (m.n_root_pad - m.n_root));
+    if (child[internal] < 0) {
+      int lev = 0;
+      while (lev < m.nlev && c >= m.level_off[lev + 1]) ++lev;
+      const double len = m.cell_cm * ldexp(1.0, -lev);
+      const double mass = rho64[internal] * (len * len * len);
+      wa = mass * (fabs(t_new[c] - t_old[c]) / t_old[c]);
+      wb = mass;
+    }
+  }
+  wa = wave_sum(wa);
+  wb = wave_sum(wb);
+  if ((threadIdx.x & 63) == 0) {
+    s_a[threadIdx.x >> 6] = wa;
+    s_b[threadIdx.x >> 6] = wb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+      ta += s_a[i];
+      tb += s_b[i];
+    }
+    if (tb != 0.0) {
+      unsafeAtomicAdd(out, ta);
+      unsafeAtomicAdd(out + 1, tb);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_add(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a, b, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_crit(const ModelDev* models, int model, int64_t n_nodes, const int32_t* child,
+                       const double* rho64, const double* t_new, const double* t_old, double* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(crit_kernel, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s, models,
+                     model, child, rho64, t_new, t_old, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_model(const ModelDev* models_dev, int model, int64_t n_nodes,
+                               const float* acc32, const double* acc64, int64_t slot_stride,
+                               int n_slots, double* e_node, double* e_lam_node, double* e_total,
+                               hipStream_t s) {
+  const int64_t grid = (n_nodes + 255) / 256;
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)grid), dim3(256), 0, s, models_dev, model, acc32,
+                     acc64, slot_stride, n_slots, e_node, e_lam_node, e_total);
+  return hipGetLastError();
+}
+
+hipError_t launch_locate(const int32_t* child, const ModelDev* models, int model, int64_t n,
+                         const double* xyz, int32_t* lev, int64_t* node, hipStream_t s) {
+  const int64_t grid = (n + 255) / 256;
+  hipLaunchKernelGGL(locate_kernel, dim3((unsigned)grid), dim3(256), 0, s, child, models, model, n,
+                     xyz, lev, node);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox(uint32_t k0, uint32_t k1, int64_t n, const uint32_t* ctr, uint32_t* out,
+                         hipStream_t s) {
+  const int64_t grid = (n + 255) / 256;
+  hipLaunchKernelGGL(philox_kernel, dim3((unsigned)grid), dim3(256), 0, s, k0, k1, n, ctr, out);
+  return hipGetLastError();
+}

@@ -1,0 +1,1070 @@
+// Host runtime behind the C ABI of include/rt.h: validation, the device layout of the
+// oct-tree, the job table, accumulator management and the calls into the gfx950 kernels.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+constexpr double kH = 6.62607015e-27;
+constexpr double kC = 2.99792458e10;
+constexpr double kPi = 3.14159265358979323846;
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= bytes && p) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      if (e != hipSuccess) return e;
+      p = nullptr;
+      bytes = 0;
+    }
+    size_t sz = std::max<size_t>(want, 256);
+    hipError_t e = hipMalloc(&p, sz);
+    if (e == hipSuccess) bytes = sz;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+struct HostModel {
+  int32_t n[3];
+  double cell_cm;
+  int32_t nlev;
+  int64_t n_root, n_root_pad, n_nodes, n_leaves, n_int, base, leaf_base;
+  std::vector<int64_t> level_off;
+  // dust
+  int32_t nl = 0;
+  std::vector<double> lam, kext, alb, g, nu, dnu;
+  std::vector<LamConst> lc;
+  DevBuf d_lc;
+  DevBuf d_T;
+  bool has_T = false;
+};
+
+}  // namespace
+
+struct rt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 0;
+  std::string err;
+  std::vector<HostModel> models;
+  // host mirrors of the device layout
+  std::vector<int32_t> h_word, h_child, h_up, h_leaf_node, h_leaf_coord;
+  std::vector<double> h_rho64;
+  std::vector<uint8_t> h_leaf_level;
+  int64_t total_int = 0, total_leaves = 0;
+  bool tree_dirty = true, table_dirty = true;
+  // device layout
+  DevBuf d_word, d_child, d_up, d_rho64, d_leaf_node, d_leaf_coord, d_leaf_level, d_models;
+  std::vector<ModelDev> h_models;
+  // work buffers
+  DevBuf acc, esc, stats, counter, jobs, records, out_node, out_lamnode, out_esc, e_total;
+  DevBuf cdf_lum, cdf_q, cdf_qpre, lmax, scan_tmp;
+  DevBuf tmp_in, tmp_out, tmp_out2, view, lamidx;
+  DevBuf it_astars, it_adust, it_sum, it_told, it_crit;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+};
+
+namespace {
+
+rt_status fail(rt_ctx* c, rt_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  else g_create_error = buf;
+  return code;
+}
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? RT_ENOMEM : RT_EDEVICE, "%s: %s", #x, \
+                  hipGetErrorString(e_));                                                \
+  } while (0)
+
+#define GUARD(...)                                                             \
+  try {                                                                        \
+    __VA_ARGS__                                                                \
+  } catch (const std::bad_alloc&) {                                            \
+    return fail(ctx, RT_ENOMEM, "host allocation failed");                     \
+  } catch (...) {                                                              \
+    return fail(ctx, RT_EDEVICE, "unexpected host exception");                 \
+  }
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// Device view of a caller array: the pointer itself when on the device, else a staged copy.
+rt_status stage_in(rt_ctx* ctx, const void* p, size_t bytes, DevBuf& tmp, const void** out) {
+  if (is_device_ptr(p)) {
+    *out = p;
+    return RT_OK;
+  }
+  HIPCHK(tmp.ensure(bytes));
+  if (bytes) HIPCHK(hipMemcpyAsync(tmp.p, p, bytes, hipMemcpyHostToDevice, ctx->stream));
+  *out = tmp.p;
+  return RT_OK;
+}
+
+// Device destination for a caller output; copy_back is set when it must be copied to the host.
+rt_status stage_out(rt_ctx* ctx, void* p, size_t bytes, DevBuf& tmp, void** out, bool* copy_back) {
+  *copy_back = false;
+  if (!p) {
+    *out = nullptr;
+    return RT_OK;
+  }
+  if (is_device_ptr(p)) {
+    *out = p;
+    return RT_OK;
+  }
+  HIPCHK(tmp.ensure(bytes));
+  *out = tmp.p;
+  *copy_back = true;
+  return RT_OK;
+}
+
+int64_t round8(int64_t v) { return (v + 7) & ~int64_t(7); }
+
+template <class T>
+rt_status upload(rt_ctx* ctx, DevBuf& b, const std::vector<T>& v) {
+  HIPCHK(b.ensure(v.size() * sizeof(T)));
+  if (!v.empty())
+    HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  return RT_OK;
+}
+
+rt_status check_model(rt_ctx* ctx, int32_t model) {
+  if (model < 0 || model >= (int32_t)ctx->models.size())
+    return fail(ctx, RT_EINVAL, "model %d does not exist", model);
+  return RT_OK;
+}
+
+// Bring the device copies of the trees and the model table up to date.
+rt_status sync_device(rt_ctx* ctx) {
+  HIPCHK(hipSetDevice(ctx->device));
+  if (ctx->tree_dirty) {
+    rt_status s;
+    if ((s = upload(ctx, ctx->d_word, ctx->h_word)) || (s = upload(ctx, ctx->d_child, ctx->h_child)) ||
+        (s = upload(ctx, ctx->d_up, ctx->h_up)) || (s = upload(ctx, ctx->d_rho64, ctx->h_rho64)) ||
+        (s = upload(ctx, ctx->d_leaf_node, ctx->h_leaf_node)) ||
+        (s = upload(ctx, ctx->d_leaf_coord, ctx->h_leaf_coord)) ||
+        (s = upload(ctx, ctx->d_leaf_level, ctx->h_leaf_level)))
+      return s;
+    ctx->tree_dirty = false;
+    ctx->table_dirty = true;
+  }
+  if (ctx->table_dirty) {
+    ctx->h_models.assign(ctx->models.size(), ModelDev{});
+    int64_t canon = 0, lam = 0, lamnode = 0;
+    for (size_t i = 0; i < ctx->models.size(); ++i) {
+      const HostModel& h = ctx->models[i];
+      ModelDev& m = ctx->h_models[i];
+      m.n[0] = h.n[0];
+      m.n[1] = h.n[1];
+      m.n[2] = h.n[2];
+      m.nlev = h.nlev;
+      m.base = (int32_t)h.base;
+      m.n_root = (int32_t)h.n_root;
+      m.n_root_pad = (int32_t)h.n_root_pad;
+      m.n_int = (int32_t)h.n_int;
+      m.cell_cm = h.cell_cm;
+      m.canon_base = canon;
+      m.lam_base = lam;
+      m.lamnode_base = lamnode;
+      m.leaf_base = h.leaf_base;
+      m.n_leaves = h.n_leaves;
+      m.n_nodes = h.n_nodes;
+      m.nl = h.nl;
+      for (int l = 0; l < RT_MAX_LEVELS + 2; ++l)
+        m.level_off[l] = l < (int)h.level_off.size() ? h.level_off[l] : h.n_nodes;
+      canon += h.n_nodes;
+      lam += h.nl;
+      lamnode += (int64_t)h.nl * h.n_nodes;
+    }
+    rt_status s = upload(ctx, ctx->d_models, ctx->h_models);
+    if (s) return s;
+    ctx->table_dirty = false;
+  }
+  return RT_OK;
+}
+
+void totals(const rt_ctx* ctx, int64_t* nodes, int64_t* lams, int64_t* lamnodes) {
+  int64_t a = 0, b = 0, c = 0;
+  for (const HostModel& h : ctx->models) {
+    a += h.n_nodes;
+    b += h.nl;
+    c += (int64_t)h.nl * h.n_nodes;
+  }
+  if (nodes) *nodes = a;
+  if (lams) *lams = b;
+  if (lamnodes) *lamnodes = c;
+}
+
+}  // namespace
+
+// =========================================================================================
+// C ABI
+// =========================================================================================
+extern "C" {
+
+const char* rt_last_error(const rt_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+rt_status rt_create(rt_ctx** out, int32_t device, void* hip_stream) {
+  rt_ctx* ctx = nullptr;
+  if (!out) return fail(nullptr, RT_EINVAL, "null output pointer");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    return fail(nullptr, RT_EDEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= count) return fail(nullptr, RT_EINVAL, "device %d out of range", device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+    return fail(nullptr, RT_EDEVICE, "cannot query device %d", device);
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, RT_EDEVICE, "device %d is %s; this library is built for gfx950", device,
+                prop.gcnArchName);
+  try {
+    ctx = new rt_ctx();
+  } catch (...) {
+    return fail(nullptr, RT_ENOMEM, "host allocation failed");
+  }
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->n_cu = prop.multiProcessorCount;
+  if (hipSetDevice(device) != hipSuccess || hipEventCreate(&ctx->ev0) != hipSuccess ||
+      hipEventCreate(&ctx->ev1) != hipSuccess || hipEventCreate(&ctx->ev2) != hipSuccess) {
+    delete ctx;
+    return fail(nullptr, RT_EDEVICE, "cannot initialise device %d", device);
+  }
+  *out = ctx;
+  return RT_OK;
+}
+
+rt_status rt_destroy(rt_ctx* ctx) {
+  if (!ctx) return RT_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  DevBuf* bufs[] = {&ctx->d_word, &ctx->d_child, &ctx->d_up, &ctx->d_rho64, &ctx->d_leaf_node,
+                    &ctx->d_leaf_coord, &ctx->d_leaf_level, &ctx->d_models, &ctx->acc, &ctx->esc,
+                    &ctx->stats, &ctx->counter, &ctx->jobs, &ctx->records, &ctx->out_node,
+                    &ctx->out_lamnode, &ctx->out_esc, &ctx->e_total, &ctx->cdf_lum, &ctx->cdf_q,
+                    &ctx->cdf_qpre, &ctx->lmax, &ctx->scan_tmp, &ctx->tmp_in, &ctx->tmp_out,
+                    &ctx->tmp_out2, &ctx->view, &ctx->lamidx, &ctx->it_astars, &ctx->it_adust,
+                    &ctx->it_sum, &ctx->it_told, &ctx->it_crit};
+  for (DevBuf* b : bufs) b->release();
+  for (HostModel& m : ctx->models) {
+    m.d_lc.release();
+    m.d_T.release();
+  }
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
+  delete ctx;
+  return RT_OK;
+}
+
+rt_status rt_build_tree(rt_ctx* ctx, const rt_tree_desc* d, int32_t* model_out, int64_t* n_nodes_out) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (!d || !model_out) return fail(ctx, RT_EINVAL, "null argument");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(ctx, RT_EINVAL, "root dimensions must be >= 1");
+    if (!(d->root_cell_cm > 0.0) || !std::isfinite(d->root_cell_cm))
+      return fail(ctx, RT_EINVAL, "root cell size must be finite and > 0");
+    if (d->n_levels < 0 || d->n_levels > RT_MAX_LEVELS)
+      return fail(ctx, RT_EINVAL, "n_levels must be in [0, %d]", RT_MAX_LEVELS);
+    if (!d->root_rho) return fail(ctx, RT_EINVAL, "null root densities");
+    if (d->n_levels > 0 && (!d->n_refined || !d->refined || !d->child_rho))
+      return fail(ctx, RT_EINVAL, "null refinement arrays");
+    if (ctx->models.size() >= 4096) return fail(ctx, RT_EINVAL, "at most 4096 models per context");
+    const int64_t nmax = std::max<int64_t>(d->nx, std::max<int64_t>(d->ny, d->nz));
+    if ((nmax << d->n_levels) >= (int64_t(1) << 30))
+      return fail(ctx, RT_EINVAL, "root size times 2^levels must stay below 2^30");
+    const int64_t n_root = (int64_t)d->nx * d->ny * d->nz;
+    std::vector<int64_t> off(d->n_levels + 2, 0);
+    int64_t cells = n_root;
+    for (int l = 0; l <= d->n_levels; ++l) {
+      off[l + 1] = off[l] + cells;
+      if (l < d->n_levels) {
+        const int64_t nr = d->n_refined[l];
+        if (nr < 0 || nr > cells) return fail(ctx, RT_EINVAL, "bad refined count at level %d", l);
+        if (nr > 0 && (!d->refined[l] || !d->child_rho[l]))
+          return fail(ctx, RT_EINVAL, "null refined list at level %d", l);
+        for (int64_t i = 0; i < nr; ++i) {
+          const int64_t v = d->refined[l][i];
+          if (v < 0 || v >= cells) return fail(ctx, RT_EINVAL, "refined index out of range at level %d", l);
+          if (i > 0 && v <= d->refined[l][i - 1])
+            return fail(ctx, RT_EINVAL, "refined list not strictly ascending at level %d", l);
+        }
+        cells = 8 * nr;
+      }
+    }
+    const int64_t n_nodes = off[d->n_levels + 1];
+    const int64_t base = round8(ctx->total_int);
+    const int64_t n_root_pad = round8(n_root);
+    const int64_t pad0 = n_root_pad - n_root;
+    const int64_t n_int = n_root_pad + (n_nodes - n_root);
+    if (base + n_int >= (int64_t(1) << 31) - 8)
+      return fail(ctx, RT_EINVAL, "total node count exceeds the 32-bit node index");
+    auto rho_of = [&](int64_t canon) -> double {
+      if (canon < n_root) return d->root_rho[canon];
+      int l = 0;
+      while (canon >= off[l + 2]) ++l;
+      return d->child_rho[l][canon - off[l + 1]];
+    };
+    for (int64_t i = 0; i < n_root; ++i) {
+      const double r = d->root_rho[i];
+      if (!(r >= 0.0) || !std::isfinite(r) || r > (double)FLT_MAX)
+        return fail(ctx, RT_EINVAL, "root density %lld must be finite, >= 0 and <= FLT_MAX", (long long)i);
+    }
+    for (int l = 0; l < d->n_levels; ++l)
+      for (int64_t i = 0; i < 8 * d->n_refined[l]; ++i) {
+        const double r = d->child_rho[l][i];
+        if (!(r >= 0.0) || !std::isfinite(r) || r > (double)FLT_MAX)
+          return fail(ctx, RT_EINVAL, "density at level %d must be finite, >= 0 and <= FLT_MAX", l + 1);
+      }
+    (void)rho_of;
+    // ---- all checks passed: build the device layout (host mirror) ----
+    HostModel hm;
+    hm.n[0] = d->nx;
+    hm.n[1] = d->ny;
+    hm.n[2] = d->nz;
+    hm.cell_cm = d->root_cell_cm;
+    hm.nlev = d->n_levels;
+    hm.n_root = n_root;
+    hm.n_root_pad = n_root_pad;
+    hm.n_nodes = n_nodes;
+    hm.n_int = n_int;
+    hm.base = base;
+    hm.level_off = off;
+    const int64_t end = base + n_int;
+    ctx->h_word.resize(end, 0);
+    ctx->h_child.resize(end, -1);
+    ctx->h_rho64.resize(end, 0.0);
+    ctx->h_up.resize(end / 8 + 1, -1);
+    auto internal = [&](int64_t canon) { return base + (canon < n_root ? canon : canon + pad0); };
+    auto set_leaf = [&](int64_t canon, double r) {
+      const int64_t i = internal(canon);
+      float f = (float)r;
+      if (f == 0.0f) f = 0.0f;  // +0
+      int32_t bits;
+      std::memcpy(&bits, &f, 4);
+      ctx->h_word[i] = bits;
+      ctx->h_rho64[i] = r;
+      ctx->h_child[i] = -1;
+    };
+    for (int64_t c = 0; c < n_root; ++c) set_leaf(c, d->root_rho[c]);
+    for (int l = 0; l < d->n_levels; ++l)
+      for (int64_t i = 0; i < 8 * d->n_refined[l]; ++i) set_leaf(off[l + 1] + i, d->child_rho[l][i]);
+    // coordinates at each node's own level, for the leaf table
+    std::vector<int32_t> coord(3 * n_nodes);
+    std::vector<uint8_t> level(n_nodes, 0);
+    for (int64_t c = 0; c < n_root; ++c) {
+      coord[3 * c] = (int32_t)(c % d->nx);
+      coord[3 * c + 1] = (int32_t)((c / d->nx) % d->ny);
+      coord[3 * c + 2] = (int32_t)(c / ((int64_t)d->nx * d->ny));
+    }
+    std::vector<char> refined(n_nodes, 0);
+    for (int l = 0; l < d->n_levels; ++l) {
+      for (int64_t o = 0; o < d->n_refined[l]; ++o) {
+        const int64_t pc = off[l] + d->refined[l][o];
+        const int64_t fc = off[l + 1] + 8 * o;
+        const int64_t pi = internal(pc), fi = internal(fc);
+        ctx->h_word[pi] = ~(int32_t)fi;
+        ctx->h_child[pi] = (int32_t)fi;
+        ctx->h_up[fi >> 3] = (int32_t)pi;
+        refined[pc] = 1;
+        for (int b = 0; b < 8; ++b) {
+          const int64_t cc = fc + b;
+          level[cc] = (uint8_t)(l + 1);
+          for (int a = 0; a < 3; ++a) coord[3 * cc + a] = 2 * coord[3 * pc + a] + ((b >> a) & 1);
+        }
+      }
+    }
+    hm.leaf_base = ctx->total_leaves;
+    int64_t nleaf = 0;
+    for (int64_t c = 0; c < n_nodes; ++c) {
+      if (refined[c]) continue;
+      ctx->h_leaf_node.push_back((int32_t)internal(c));
+      ctx->h_leaf_level.push_back(level[c]);
+      for (int a = 0; a < 3; ++a) ctx->h_leaf_coord.push_back(coord[3 * c + a]);
+      ++nleaf;
+    }
+    hm.n_leaves = nleaf;
+    ctx->total_leaves += nleaf;
+    ctx->total_int = end;
+    ctx->models.push_back(std::move(hm));
+    ctx->tree_dirty = true;
+    ctx->table_dirty = true;
+    *model_out = (int32_t)ctx->models.size() - 1;
+    if (n_nodes_out) *n_nodes_out = n_nodes;
+    return RT_OK;
+  })
+}
+
+rt_status rt_get_model_info(rt_ctx* ctx, int32_t model, rt_model_info* out) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  if (rt_status s = check_model(ctx, model)) return s;
+  if (!out) return fail(ctx, RT_EINVAL, "null output");
+  const HostModel& h = ctx->models[model];
+  std::memset(out, 0, sizeof *out);
+  out->n_nodes = h.n_nodes;
+  out->n_leaves = h.n_leaves;
+  out->n_levels = h.nlev;
+  out->n_lambda = h.nl;
+  for (int l = 0; l < RT_MAX_LEVELS + 2; ++l)
+    out->level_offset[l] = l < (int)h.level_off.size() ? h.level_off[l] : h.n_nodes;
+  for (int32_t i = 0; i < model; ++i) {
+    out->node_base += ctx->models[i].n_nodes;
+    out->lambda_base += ctx->models[i].nl;
+    out->lambda_node_base += (int64_t)ctx->models[i].nl * ctx->models[i].n_nodes;
+  }
+  return RT_OK;
+}
+
+rt_status rt_get_sizes(rt_ctx* ctx, int64_t* nodes, int64_t* lambdas, int64_t* lambda_nodes) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  totals(ctx, nodes, lambdas, lambda_nodes);
+  return RT_OK;
+}
+
+rt_status rt_locate(rt_ctx* ctx, int32_t model, int64_t n, const double* xyz, int32_t* level_out,
+                    int64_t* node_out) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (rt_status s = check_model(ctx, model)) return s;
+    if (n < 0) return fail(ctx, RT_EINVAL, "negative point count");
+    if (n == 0) return RT_OK;
+    if (!xyz || !level_out || !node_out) return fail(ctx, RT_EINVAL, "null array");
+    if (rt_status s = sync_device(ctx)) return s;
+    const void* dx;
+    if (rt_status s = stage_in(ctx, xyz, 24 * n, ctx->tmp_in, &dx)) return s;
+    void *dl, *dn;
+    bool cl, cn;
+    if (rt_status s = stage_out(ctx, level_out, 4 * n, ctx->tmp_out, &dl, &cl)) return s;
+    if (rt_status s = stage_out(ctx, node_out, 8 * n, ctx->tmp_out2, &dn, &cn)) return s;
+    HIPCHK(launch_locate(ctx->d_child.as<int32_t>(), ctx->d_models.as<ModelDev>(), model, n,
+                         static_cast<const double*>(dx), static_cast<int32_t*>(dl),
+                         static_cast<int64_t*>(dn), ctx->stream));
+    if (cl) HIPCHK(hipMemcpyAsync(level_out, dl, 4 * n, hipMemcpyDeviceToHost, ctx->stream));
+    if (cn) HIPCHK(hipMemcpyAsync(node_out, dn, 8 * n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+  })
+}
+
+rt_status rt_set_dust(rt_ctx* ctx, int32_t model, int32_t nl, const double* lam, const double* kappa,
+                      const double* albedo, const double* g) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (rt_status s = check_model(ctx, model)) return s;
+    if (nl < 1 || nl > 4096) return fail(ctx, RT_EINVAL, "n_lambda must be in [1, 4096]");
+    if (!lam || !kappa || !albedo || !g) return fail(ctx, RT_EINVAL, "null dust array");
+    for (int i = 0; i < nl; ++i) {
+      if (!(lam[i] > 0.0) || !std::isfinite(lam[i])) return fail(ctx, RT_EINVAL, "wavelength %d invalid", i);
+      if (i > 0 && !(lam[i] > lam[i - 1])) return fail(ctx, RT_EINVAL, "wavelengths must ascend strictly");
+      if (!(kappa[i] > 0.0) || !std::isfinite(kappa[i])) return fail(ctx, RT_EINVAL, "kappa %d must be > 0", i);
+      if (!(albedo[i] >= 0.0 && albedo[i] <= 1.0)) return fail(ctx, RT_EINVAL, "albedo %d outside [0,1]", i);
+      if (!(std::fabs(g[i]) < 1.0)) return fail(ctx, RT_EINVAL, "|g| must be < 1 (entry %d)", i);
+    }
+    HostModel& h = ctx->models[model];
+    h.nl = nl;
+    h.lam.assign(lam, lam + nl);
+    h.kext.assign(kappa, kappa + nl);
+    h.alb.assign(albedo, albedo + nl);
+    h.g.assign(g, g + nl);
+    h.nu.resize(nl);
+    h.dnu.resize(nl);
+    for (int i = 0; i < nl; ++i) h.nu[i] = kC / (lam[i] * 1e-4);
+    if (nl == 1) {
+      h.dnu[0] = 1.0;
+    } else {
+      h.dnu[0] = std::fabs(h.nu[1] - h.nu[0]) * 0.5;
+      h.dnu[nl - 1] = std::fabs(h.nu[nl - 1] - h.nu[nl - 2]) * 0.5;
+      for (int i = 1; i < nl - 1; ++i) h.dnu[i] = std::fabs(h.nu[i + 1] - h.nu[i - 1]) * 0.5;
+    }
+    h.lc.resize(nl);
+    for (int i = 0; i < nl; ++i) {
+      const double nu = h.nu[i];
+      h.lc[i].kext = h.kext[i];
+      h.lc[i].alb = h.alb[i];
+      h.lc[i].dnu = h.dnu[i];
+      h.lc[i].kabs_dnu = (1.0 - h.alb[i]) * h.kext[i] * h.dnu[i];
+      h.lc[i].pre = 2.0 * kH * nu * nu * nu / (kC * kC);
+      h.lc[i].hnu = kH * nu;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    if (rt_status s = upload(ctx, h.d_lc, h.lc)) return s;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->table_dirty = true;
+    return RT_OK;
+  })
+}
+
+rt_status rt_set_temperature(rt_ctx* ctx, int32_t model, const double* t_node) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (rt_status s = check_model(ctx, model)) return s;
+    if (!t_node) return fail(ctx, RT_EINVAL, "null temperatures");
+    HostModel& h = ctx->models[model];
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(h.d_T.ensure(8 * h.n_nodes));
+    HIPCHK(hipMemcpyAsync(h.d_T.p, t_node, 8 * h.n_nodes,
+                          is_device_ptr(t_node) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    h.has_T = true;
+    return RT_OK;
+  })
+}
+
+}  // extern "C"
+
+// -----------------------------------------------------------------------------------------
+// tracing
+// -----------------------------------------------------------------------------------------
+namespace {
+
+// Dust-emission tables of one (model, wavelength): luminosity, 32-bit quantised share of the
+// maximum and its exact 64-bit exclusive prefix sum; returns the total.
+rt_status build_dust_cdf(rt_ctx* ctx, int32_t model, int lam, int64_t off, uint64_t* qtot) {
+  HostModel& h = ctx->models[model];
+  const int64_t n = h.n_leaves;
+  double* lum = ctx->cdf_lum.as<double>() + off;
+  uint64_t* q = ctx->cdf_q.as<uint64_t>() + off;
+  uint64_t* qpre = ctx->cdf_qpre.as<uint64_t>() + off;
+  HIPCHK(ctx->lmax.ensure(16));
+  HIPCHK(hipMemsetAsync(ctx->lmax.p, 0, 16, ctx->stream));
+  HIPCHK(launch_dust_lum(ctx->d_models.as<ModelDev>(), model, n, ctx->d_leaf_node.as<int32_t>(),
+                         ctx->d_leaf_level.as<uint8_t>(), ctx->d_rho64.as<double>(),
+                         h.d_T.as<double>(), h.d_lc.as<LamConst>(), lam, lum,
+                         ctx->lmax.as<unsigned long long>(), ctx->stream));
+  HIPCHK(launch_dust_quant(n, lum, ctx->lmax.as<unsigned long long>(), q, ctx->stream));
+  size_t tmp = 0;
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, q, qpre, (int)n, ctx->stream));
+  HIPCHK(ctx->scan_tmp.ensure(tmp));
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(ctx->scan_tmp.p, tmp, q, qpre, (int)n, ctx->stream));
+  uint64_t last[2];
+  HIPCHK(hipMemcpyAsync(&last[0], qpre + n - 1, 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(&last[1], q + n - 1, 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *qtot = last[0] + last[1];
+  return RT_OK;
+}
+
+struct TraceOut {
+  double* e_node = nullptr;      // device [total nodes] or null
+  double* e_lamnode = nullptr;   // device [total lamnodes] or null
+  double* e_esc = nullptr;       // device [total lambdas]
+};
+
+rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_trace_opts* o,
+                     const TraceOut& out, rt_trace_stats* st_out) {
+  // ---- validation (no state changes before this block ends) ----
+  if (n_src < 1 || n_src > 255) return fail(ctx, RT_EINVAL, "n_src must be in [1, 255]");
+  if (!src || !o) return fail(ctx, RT_EINVAL, "null sources or options");
+  if (o->precision != RT_FP64 && o->precision != RT_FP32_LOCAL)
+    return fail(ctx, RT_EINVAL, "precision must be RT_FP64 or RT_FP32_LOCAL");
+  if (!(o->rr_threshold >= 0.0) || !std::isfinite(o->rr_threshold))
+    return fail(ctx, RT_EINVAL, "rr_threshold must be finite and >= 0");
+  if (!(o->rr_prob >= 0.0 && o->rr_prob < 1.0)) return fail(ctx, RT_EINVAL, "rr_prob must be in [0, 1)");
+  if (o->max_events < 0 || o->max_events > 0x7fffffff) return fail(ctx, RT_EINVAL, "bad max_events");
+  const int bs = o->block_size ? o->block_size : 256;
+  if (bs != 64 && bs != 128 && bs != 256 && !(bs == 512 && o->precision == RT_FP32_LOCAL))
+    return fail(ctx, RT_EINVAL, "block_size must be 64, 128, 256 (or 512 for the FP32 form)");
+  if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return fail(ctx, RT_EINVAL, "bad blocks_per_cu");
+  if (!(o->refill_threshold >= 0.0f && o->refill_threshold <= 1.0f))
+    return fail(ctx, RT_EINVAL, "refill_threshold must be in [0, 1]");
+  if (o->rec_stride < 0 || (o->rec_stride > 0 && !o->records))
+    return fail(ctx, RT_EINVAL, "records needed when rec_stride > 0");
+  for (int s = 0; s < n_src; ++s) {
+    const rt_source& S = src[s];
+    if (rt_status e = check_model(ctx, S.model)) return e;
+    const HostModel& h = ctx->models[S.model];
+    if (h.nl < 1) return fail(ctx, RT_ESTATE, "rt_set_dust not called for model %d", S.model);
+    if (S.kind < 0 || S.kind > 3) return fail(ctx, RT_EINVAL, "source %d: bad kind", s);
+    if (S.packets_per_lambda < 1 || S.packets_per_lambda > (int64_t(1) << 32))
+      return fail(ctx, RT_EINVAL, "source %d: packets_per_lambda must be in [1, 2^32]", s);
+    if (S.kind != RT_SRC_DUST) {
+      if (!S.power) return fail(ctx, RT_EINVAL, "source %d: null power", s);
+      for (int i = 0; i < h.nl; ++i)
+        if (!(S.power[i] >= 0.0) || !std::isfinite(S.power[i]))
+          return fail(ctx, RT_EINVAL, "source %d: power must be finite and >= 0", s);
+    } else if (!h.has_T) {
+      return fail(ctx, RT_ESTATE, "source %d: dust emission needs temperatures", s);
+    }
+    if (S.kind == RT_SRC_POINT || S.kind == RT_SRC_BEAM)
+      for (int a = 0; a < 3; ++a)
+        if (!(S.pos[a] >= 0.0 && S.pos[a] < (double)h.n[a]))
+          return fail(ctx, RT_EINVAL, "source %d: position outside the root grid", s);
+    if (S.kind == RT_SRC_BEAM) {
+      const double nb = std::sqrt(S.dir[0] * S.dir[0] + S.dir[1] * S.dir[1] + S.dir[2] * S.dir[2]);
+      if (!(nb > 0.0) || !std::isfinite(nb)) return fail(ctx, RT_EINVAL, "source %d: bad direction", s);
+    }
+  }
+  // ---- setup ----
+  if (rt_status e = sync_device(ctx)) return e;
+  int64_t tot_nodes, tot_lam, tot_lamnode;
+  totals(ctx, &tot_nodes, &tot_lam, &tot_lamnode);
+  int max_nl = 1;
+  for (const HostModel& h : ctx->models) max_nl = std::max(max_nl, h.nl);
+  const bool fp32 = o->precision == RT_FP32_LOCAL;
+  // per-wavelength accumulator slots: always for the FP32 form (FP32 sums stay short), for
+  // FP64 only when per-(wavelength, node) output is requested
+  int n_slots = (fp32 || out.e_lamnode) ? max_nl : 1;
+  const size_t elem = fp32 ? 4 : 8;
+  if (fp32 && !out.e_lamnode && (double)n_slots * ctx->total_int * elem > 96e9) n_slots = 1;
+  const int64_t stride = ctx->total_int;
+  HIPCHK(ctx->acc.ensure((size_t)n_slots * stride * elem));
+  HIPCHK(hipMemsetAsync(ctx->acc.p, 0, (size_t)n_slots * stride * elem, ctx->stream));
+  HIPCHK(ctx->stats.ensure(sizeof(DevStats)));
+  HIPCHK(hipMemsetAsync(ctx->stats.p, 0, sizeof(DevStats), ctx->stream));
+  HIPCHK(ctx->counter.ensure(8));
+  HIPCHK(hipMemsetAsync(ctx->counter.p, 0, 8, ctx->stream));
+  HIPCHK(ctx->e_total.ensure(8));
+  HIPCHK(hipMemsetAsync(ctx->e_total.p, 0, 8, ctx->stream));
+  HIPCHK(hipMemsetAsync(out.e_esc, 0, 8 * tot_lam, ctx->stream));
+
+  // job table: source-major, then wavelength
+  std::vector<JobDev> jobs;
+  int64_t cdf_total = 0;
+  for (int s = 0; s < n_src; ++s)
+    if (src[s].kind == RT_SRC_DUST) cdf_total += ctx->models[src[s].model].n_leaves * ctx->models[src[s].model].nl;
+  if (cdf_total > 0) {
+    HIPCHK(ctx->cdf_lum.ensure(8 * cdf_total));
+    HIPCHK(ctx->cdf_q.ensure(8 * cdf_total));
+    HIPCHK(ctx->cdf_qpre.ensure(8 * cdf_total));
+  }
+  uint64_t start = 0;
+  int64_t rec_base = 0, cdf_off = 0;
+  for (int s = 0; s < n_src; ++s) {
+    const rt_source& S = src[s];
+    const HostModel& h = ctx->models[S.model];
+    const ModelDev& md = ctx->h_models[S.model];
+    double bd[3] = {0.0, 0.0, 1.0};
+    if (S.kind == RT_SRC_BEAM) {
+      const double nb = std::sqrt(S.dir[0] * S.dir[0] + S.dir[1] * S.dir[1] + S.dir[2] * S.dir[2]);
+      for (int a = 0; a < 3; ++a) bd[a] = S.dir[a] / nb;
+    }
+    for (int i = 0; i < h.nl; ++i) {
+      JobDev J;
+      std::memset(&J, 0, sizeof J);
+      const uint64_t N = (uint64_t)S.packets_per_lambda;
+      J.start = start;
+      J.n = N;
+      J.model = S.model;
+      J.kind = S.kind;
+      J.lam = i;
+      J.src = s;
+      J.stream = ((uint32_t)S.model << 20) | ((uint32_t)s << 12) | (uint32_t)i;
+      J.esc_slot = (int32_t)(md.lam_base + i);
+      if (S.kind == RT_SRC_BACKGROUND) {
+        const double area = 2.0 * ((double)h.n[0] * h.n[1] + (double)h.n[1] * h.n[2] +
+                                   (double)h.n[0] * h.n[2]);
+        const double pin = kPi * S.power[i] * h.dnu[i] * (area * h.cell_cm * h.cell_cm);
+        J.w0 = pin / (double)N;
+      } else if (S.kind == RT_SRC_POINT || S.kind == RT_SRC_BEAM) {
+        J.w0 = S.power[i] * h.dnu[i] / (double)N;
+      }
+      for (int a = 0; a < 3; ++a) {
+        J.pos[a] = S.pos[a];
+        J.dir[a] = bd[a];
+      }
+      J.kext = h.kext[i];
+      J.alb = h.alb[i];
+      J.g = h.g[i];
+      J.kc32 = (float)(h.kext[i] * h.cell_cm);
+      J.alb32 = (float)h.alb[i];
+      J.g32 = (float)h.g[i];
+      J.acc_off = (n_slots > 1 ? (int64_t)i : 0) * stride;
+      J.rec_base = rec_base;
+      if (o->rec_stride > 0) rec_base += (int64_t)((N + o->rec_stride - 1) / o->rec_stride);
+      if (S.kind == RT_SRC_DUST) {
+        J.cdf_off = cdf_off;
+        uint64_t qtot = 0;
+        if (rt_status e = build_dust_cdf(ctx, S.model, i, cdf_off, &qtot)) return e;
+        J.qtot = qtot;
+        cdf_off += h.n_leaves;
+        if (qtot == 0) J.n = 0;  // nothing emits at this wavelength
+      }
+      start += J.n;
+      jobs.push_back(J);
+    }
+  }
+  if (rt_status e = upload(ctx, ctx->jobs, jobs)) return e;
+  void* rec_dev = nullptr;
+  bool rec_copy = false;
+  if (o->rec_stride > 0) {
+    if (rt_status e = stage_out(ctx, o->records, sizeof(rt_record) * rec_base, ctx->records, &rec_dev, &rec_copy))
+      return e;
+    HIPCHK(hipMemsetAsync(rec_dev, 0, sizeof(rt_record) * std::max<int64_t>(rec_base, 1), ctx->stream));
+  }
+
+  TraceParams p;
+  std::memset(&p, 0, sizeof p);
+  p.word = ctx->d_word.as<int32_t>();
+  p.rho64 = ctx->d_rho64.as<double>();
+  p.child = ctx->d_child.as<int32_t>();
+  p.up = ctx->d_up.as<int32_t>();
+  p.models = ctx->d_models.as<ModelDev>();
+  p.jobs = ctx->jobs.as<JobDev>();
+  p.n_jobs = (int32_t)jobs.size();
+  p.n_esc = (int32_t)tot_lam;
+  p.total_packets = start;
+  p.counter = ctx->counter.as<unsigned long long>();
+  p.acc32 = fp32 ? ctx->acc.as<float>() : nullptr;
+  p.acc64 = fp32 ? nullptr : ctx->acc.as<double>();
+  p.esc = out.e_esc;
+  p.stats = ctx->stats.as<DevStats>();
+  p.rec = static_cast<rt_record*>(rec_dev);
+  p.rec_stride = o->rec_stride;
+  p.key0 = (uint32_t)(o->seed & 0xffffffffu);
+  p.key1 = (uint32_t)(o->seed >> 32) + o->iteration;
+  p.rr_thr = o->rr_threshold;
+  p.rr_p = o->rr_prob;
+  p.max_events = o->max_events > 0 ? o->max_events : 1000000;
+  p.refill_thr = o->refill_threshold > 0.0f ? o->refill_threshold : 0.5f;
+  p.cdf_qpre = ctx->cdf_qpre.as<uint64_t>();
+  p.cdf_q = ctx->cdf_q.as<uint64_t>();
+  p.cdf_lum = ctx->cdf_lum.as<double>();
+  p.leaf_node = ctx->d_leaf_node.as<int32_t>();
+  p.leaf_coord = ctx->d_leaf_coord.as<int32_t>();
+  p.leaf_level = ctx->d_leaf_level.as<uint8_t>();
+
+  HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+  if (start > 0) {
+    if (fp32) {
+      int per_cu = o->blocks_per_cu;
+      if (per_cu == 0) {
+        HIPCHK(occupancy_trace_fp32(bs, &per_cu));
+        per_cu = std::max(per_cu, 1);
+      }
+      HIPCHK(launch_trace_fp32(p, ctx->n_cu * per_cu, bs, ctx->stream));
+    } else {
+      for (size_t k = 0; k < jobs.size(); ++k)
+        if (jobs[k].n > 0) HIPCHK(launch_trace_fp64(p, (int)k, jobs[k].n, bs, ctx->stream));
+    }
+  }
+  HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+  for (size_t m = 0; m < ctx->models.size(); ++m) {
+    const HostModel& h = ctx->models[m];
+    const int ns = n_slots > 1 ? std::max(h.nl, 1) : 1;
+    HIPCHK(launch_reduce_model(ctx->d_models.as<ModelDev>(), (int)m, h.n_nodes,
+                               fp32 ? ctx->acc.as<float>() : nullptr,
+                               fp32 ? nullptr : ctx->acc.as<double>(), stride, ns, out.e_node,
+                               n_slots > 1 ? out.e_lamnode : nullptr, ctx->e_total.as<double>(),
+                               ctx->stream));
+  }
+  HIPCHK(hipEventRecord(ctx->ev2, ctx->stream));
+  if (rec_copy)
+    HIPCHK(hipMemcpyAsync(o->records, rec_dev, sizeof(rt_record) * rec_base, hipMemcpyDeviceToHost,
+                          ctx->stream));
+  DevStats ds;
+  double etot = 0.0;
+  std::vector<double> esc(tot_lam);
+  HIPCHK(hipMemcpyAsync(&ds, ctx->stats.p, sizeof ds, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(&etot, ctx->e_total.p, 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(esc.data(), out.e_esc, 8 * tot_lam, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (st_out) {
+    float k_ms = 0.f, r_ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&k_ms, ctx->ev0, ctx->ev1));
+    HIPCHK(hipEventElapsedTime(&r_ms, ctx->ev1, ctx->ev2));
+    st_out->crossings = ds.crossings;
+    st_out->scatterings = ds.scatterings;
+    st_out->kills = ds.kills;
+    st_out->truncated = ds.truncated;
+    st_out->packets = ds.packets;
+    st_out->e_emit = ds.e_emit;
+    st_out->e_abs = etot;
+    double ee = 0.0;
+    for (double v : esc) ee += v;
+    st_out->e_esc = ee;
+    st_out->e_killed = ds.e_killed;
+    st_out->e_rr_gain = ds.e_rr_gain;
+    st_out->e_trunc = ds.e_trunc;
+    st_out->kernel_ms = k_ms;
+    st_out->reduce_ms = r_ms;
+  }
+  return RT_OK;
+}
+
+rt_status solve_T_impl(rt_ctx* ctx, int32_t model, const double* a_dev, double t_min, double t_max) {
+  HostModel& h = ctx->models[model];
+  HIPCHK(h.d_T.ensure(8 * h.n_nodes));
+  HIPCHK(launch_temperature(ctx->d_models.as<ModelDev>(), model, h.n_nodes, ctx->d_child.as<int32_t>(),
+                            ctx->d_rho64.as<double>(), a_dev, h.d_lc.as<LamConst>(), h.nl, t_min,
+                            t_max, h.d_T.as<double>(), ctx->stream));
+  h.has_T = true;
+  return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rt_status rt_trace_packets(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_trace_opts* o,
+                           double* e_abs_node, double* e_abs_lambda_node, double* e_esc_lambda,
+                           rt_trace_stats* stats) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    int64_t tn, tl, tln;
+    totals(ctx, &tn, &tl, &tln);
+    TraceOut out;
+    void* pn = nullptr;
+    void* pln = nullptr;
+    void* pe = nullptr;
+    bool cn = false, cln = false, ce = false;
+    if (rt_status s = stage_out(ctx, e_abs_node, 8 * tn, ctx->out_node, &pn, &cn)) return s;
+    if (rt_status s = stage_out(ctx, e_abs_lambda_node, 8 * std::max<int64_t>(tln, 1), ctx->out_lamnode, &pln, &cln))
+      return s;
+    if (e_esc_lambda) {
+      if (rt_status s = stage_out(ctx, e_esc_lambda, 8 * std::max<int64_t>(tl, 1), ctx->out_esc, &pe, &ce)) return s;
+    } else {
+      HIPCHK(ctx->out_esc.ensure(8 * std::max<int64_t>(tl, 1)));
+      pe = ctx->out_esc.p;
+    }
+    out.e_node = static_cast<double*>(pn);
+    out.e_lamnode = static_cast<double*>(pln);
+    out.e_esc = static_cast<double*>(pe);
+    if (rt_status s = trace_impl(ctx, n_src, src, o, out, stats)) return s;
+    if (cn) HIPCHK(hipMemcpyAsync(e_abs_node, pn, 8 * tn, hipMemcpyDeviceToHost, ctx->stream));
+    if (cln) HIPCHK(hipMemcpyAsync(e_abs_lambda_node, pln, 8 * tln, hipMemcpyDeviceToHost, ctx->stream));
+    if (ce) HIPCHK(hipMemcpyAsync(e_esc_lambda, pe, 8 * tl, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+  })
+}
+
+rt_status rt_solve_temperature(rt_ctx* ctx, int32_t model, const double* a_node, double t_min,
+                               double t_max, double* t_node) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (rt_status s = check_model(ctx, model)) return s;
+    if (!a_node) return fail(ctx, RT_EINVAL, "null absorbed power");
+    if (!(t_min > 0.0) || !(t_max > t_min) || !std::isfinite(t_max))
+      return fail(ctx, RT_EINVAL, "need 0 < t_min < t_max");
+    HostModel& h = ctx->models[model];
+    if (h.nl < 1) return fail(ctx, RT_ESTATE, "rt_set_dust not called for model %d", model);
+    if (rt_status s = sync_device(ctx)) return s;
+    const void* da;
+    if (rt_status s = stage_in(ctx, a_node, 8 * h.n_nodes, ctx->tmp_in, &da)) return s;
+    if (rt_status s = solve_T_impl(ctx, model, static_cast<const double*>(da), t_min, t_max)) return s;
+    if (t_node)
+      HIPCHK(hipMemcpyAsync(t_node, h.d_T.p, 8 * h.n_nodes,
+                            is_device_ptr(t_node) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                            ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+  })
+}
+
+rt_status rt_lambda_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
+                            const rt_trace_opts* opts, int64_t dust_packets, int32_t n_max,
+                            double tol, double t_min, double t_max, double* t_node,
+                            int32_t* n_done, double* crit) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (rt_status s = check_model(ctx, model)) return s;
+    if (n_max < 0 || n_max > 100000) return fail(ctx, RT_EINVAL, "bad n_max");
+    if (!(tol >= 0.0)) return fail(ctx, RT_EINVAL, "bad tol");
+    if (dust_packets < 1 || dust_packets > (int64_t(1) << 32)) return fail(ctx, RT_EINVAL, "bad dust_packets");
+    if (!(t_min > 0.0) || !(t_max > t_min)) return fail(ctx, RT_EINVAL, "need 0 < t_min < t_max");
+    if (!opts) return fail(ctx, RT_EINVAL, "null options");
+    for (int s = 0; s < n_src; ++s)
+      if (src && (src[s].model != model || src[s].kind == RT_SRC_DUST))
+        return fail(ctx, RT_EINVAL, "constant sources must belong to the model and not be dust");
+    HostModel& h = ctx->models[model];
+    if (h.nl < 1) return fail(ctx, RT_ESTATE, "rt_set_dust not called for model %d", model);
+    HIPCHK(hipSetDevice(ctx->device));
+    if (rt_status s = sync_device(ctx)) return s;
+    int64_t tn, tl, tln;
+    totals(ctx, &tn, &tl, &tln);
+    const int64_t cb = ctx->h_models[model].canon_base;
+    HIPCHK(ctx->it_astars.ensure(8 * tn));
+    HIPCHK(ctx->it_adust.ensure(8 * tn));
+    HIPCHK(ctx->it_sum.ensure(8 * h.n_nodes));
+    HIPCHK(ctx->it_told.ensure(8 * h.n_nodes));
+    HIPCHK(ctx->it_crit.ensure(16));
+    HIPCHK(ctx->out_esc.ensure(8 * std::max<int64_t>(tl, 1)));
+    TraceOut out;
+    out.e_esc = ctx->out_esc.as<double>();
+    rt_trace_opts o = *opts;
+    double* astars = ctx->it_astars.as<double>() + cb;
+    if (n_src > 0) {
+      out.e_node = ctx->it_astars.as<double>();
+      o.iteration = opts->iteration;
+      if (rt_status s = trace_impl(ctx, n_src, src, &o, out, nullptr)) return s;
+    } else {
+      HIPCHK(hipMemsetAsync(ctx->it_astars.p, 0, 8 * tn, ctx->stream));
+    }
+    if (rt_status s = solve_T_impl(ctx, model, astars, t_min, t_max)) return s;
+    int32_t n = 0;
+    for (int32_t it = 1; it <= n_max; ++it) {
+      rt_source ds;
+      std::memset(&ds, 0, sizeof ds);
+      ds.kind = RT_SRC_DUST;
+      ds.model = model;
+      ds.packets_per_lambda = dust_packets;
+      o.iteration = opts->iteration + (uint32_t)it;
+      out.e_node = ctx->it_adust.as<double>();
+      if (rt_status s = trace_impl(ctx, 1, &ds, &o, out, nullptr)) return s;
+      HIPCHK(launch_add(h.n_nodes, astars, ctx->it_adust.as<double>() + cb, ctx->it_sum.as<double>(),
+                        ctx->stream));
+      HIPCHK(hipMemcpyAsync(ctx->it_told.p, h.d_T.p, 8 * h.n_nodes, hipMemcpyDeviceToDevice, ctx->stream));
+      if (rt_status s = solve_T_impl(ctx, model, ctx->it_sum.as<double>(), t_min, t_max)) return s;
+      HIPCHK(hipMemsetAsync(ctx->it_crit.p, 0, 16, ctx->stream));
+      HIPCHK(launch_crit(ctx->d_models.as<ModelDev>(), model, h.n_nodes, ctx->d_child.as<int32_t>(),
+                         ctx->d_rho64.as<double>(), h.d_T.as<double>(), ctx->it_told.as<double>(),
+                         ctx->it_crit.as<double>(), ctx->stream));
+      double c2[2];
+      HIPCHK(hipMemcpyAsync(c2, ctx->it_crit.p, 16, hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      const double cval = c2[1] > 0.0 ? c2[0] / c2[1] : 0.0;
+      if (crit) crit[it - 1] = cval;
+      n = it;
+      if (cval < tol) break;
+    }
+    if (n_done) *n_done = n;
+    if (t_node)
+      HIPCHK(hipMemcpyAsync(t_node, h.d_T.p, 8 * h.n_nodes,
+                            is_device_ptr(t_node) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                            ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+  })
+}
+
+rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32_t npix, double width,
+                        int32_t n_sel, const int32_t* lambda_idx, int32_t precision, double* image,
+                        uint64_t* crossings) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (rt_status s = check_model(ctx, model)) return s;
+    if (!n_obs || !lambda_idx || !image) return fail(ctx, RT_EINVAL, "null argument");
+    if (npix < 1 || npix > 16384) return fail(ctx, RT_EINVAL, "npix must be in [1, 16384]");
+    if (n_sel < 1) return fail(ctx, RT_EINVAL, "n_sel must be >= 1");
+    if (precision != RT_FP64) return fail(ctx, RT_EINVAL, "maps are computed in RT_FP64");
+    HostModel& h = ctx->models[model];
+    if (h.nl < 1) return fail(ctx, RT_ESTATE, "rt_set_dust not called for model %d", model);
+    if (!h.has_T) return fail(ctx, RT_ESTATE, "model %d has no temperatures", model);
+    for (int q = 0; q < n_sel; ++q)
+      if (lambda_idx[q] < 0 || lambda_idx[q] >= h.nl) return fail(ctx, RT_EINVAL, "bad wavelength index");
+    const double nn = std::sqrt(n_obs[0] * n_obs[0] + n_obs[1] * n_obs[1] + n_obs[2] * n_obs[2]);
+    if (!(nn > 0.0) || !std::isfinite(nn)) return fail(ctx, RT_EINVAL, "bad view direction");
+    if (!std::isfinite(width)) return fail(ctx, RT_EINVAL, "bad width");
+    double v[13];
+    const double n[3] = {n_obs[0] / nn, n_obs[1] / nn, n_obs[2] / nn};
+    double e1[3], e2[3];
+    if (n[0] == 0.0 && n[1] == 0.0) {
+      e1[0] = 1.0;
+      e1[1] = 0.0;
+      e1[2] = 0.0;
+    } else {
+      const double ex = -n[1], ey = n[0];
+      const double en = std::sqrt(ex * ex + ey * ey);
+      e1[0] = ex / en;
+      e1[1] = ey / en;
+      e1[2] = 0.0;
+    }
+    e2[0] = n[1] * e1[2] - n[2] * e1[1];
+    e2[1] = n[2] * e1[0] - n[0] * e1[2];
+    e2[2] = n[0] * e1[1] - n[1] * e1[0];
+    double W = width;
+    if (!(W > 0.0)) W = std::max<double>(h.n[0], std::max<double>(h.n[1], h.n[2]));
+    for (int a = 0; a < 3; ++a) {
+      v[a] = n[a];
+      v[3 + a] = e1[a];
+      v[6 + a] = e2[a];
+      v[9 + a] = 0.5 * h.n[a];
+    }
+    v[12] = W;
+    if (rt_status s = sync_device(ctx)) return s;
+    HIPCHK(ctx->view.ensure(sizeof v));
+    HIPCHK(hipMemcpyAsync(ctx->view.p, v, sizeof v, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx->lamidx.ensure(4 * n_sel));
+    HIPCHK(hipMemcpyAsync(ctx->lamidx.p, lambda_idx, 4 * n_sel, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx->counter.ensure(8));
+    HIPCHK(hipMemsetAsync(ctx->counter.p, 0, 8, ctx->stream));
+    const size_t img_bytes = 8 * (size_t)n_sel * npix * npix;
+    void* dimg;
+    bool copy;
+    if (rt_status s = stage_out(ctx, image, img_bytes, ctx->tmp_out, &dimg, &copy)) return s;
+    for (int q0 = 0; q0 < n_sel; q0 += 16) {
+      const int nq = std::min(16, n_sel - q0);
+      HIPCHK(launch_render_fp64(ctx->d_models.as<ModelDev>(), model, ctx->d_child.as<int32_t>(),
+                                ctx->d_up.as<int32_t>(), ctx->d_rho64.as<double>(), h.d_T.as<double>(),
+                                h.d_lc.as<LamConst>(), ctx->lamidx.as<int32_t>() + q0, nq,
+                                ctx->view.as<double>(), npix,
+                                static_cast<double*>(dimg) + (size_t)q0 * npix * npix,
+                                q0 == 0 ? ctx->counter.as<unsigned long long>() : nullptr,
+                                ctx->stream));
+    }
+    if (copy) HIPCHK(hipMemcpyAsync(image, dimg, img_bytes, hipMemcpyDeviceToHost, ctx->stream));
+    unsigned long long cr = 0;
+    HIPCHK(hipMemcpyAsync(&cr, ctx->counter.p, 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (crossings) *crossings = cr;
+    return RT_OK;
+  })
+}
+
+rt_status rt_philox(rt_ctx* ctx, uint32_t key0, uint32_t key1, int64_t n, const uint32_t* ctr, uint32_t* out) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (n < 0) return fail(ctx, RT_EINVAL, "negative count");
+    if (n == 0) return RT_OK;
+    if (!ctr || !out) return fail(ctx, RT_EINVAL, "null array");
+    HIPCHK(hipSetDevice(ctx->device));
+    const void* dc;
+    if (rt_status s = stage_in(ctx, ctr, 16 * n, ctx->tmp_in, &dc)) return s;
+    void* dout;
+    bool copy;
+    if (rt_status s = stage_out(ctx, out, 16 * n, ctx->tmp_out, &dout, &copy)) return s;
+    HIPCHK(launch_philox(key0, key1, n, static_cast<const uint32_t*>(dc), static_cast<uint32_t*>(dout),
+                         ctx->stream));
+    if (copy) HIPCHK(hipMemcpyAsync(out, dout, 16 * n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+  })
+}
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+// Dust model f(J) of the paper's Sect. 3.1 (one grain component at its equilibrium
+// temperature, Sect. 4) and the per-leaf dust-emission luminosities used as a source.
+#include "device.h"
+
+using namespace rtd;
+
+namespace {
+
+constexpr double kK = 1.380649e-16;  // Boltzmann constant, erg/K
+
+// sum_i kappa_abs_i B_i(T) dnu_i and its T derivative.
+__device__ __forceinline__ void planck_sum(const LamConst* __restrict__ lc, int nl, double t,
+                                           double& s, double& ds) {
+  s = 0.0;
+  ds = 0.0;
+  const double kt = kK * t;
+  for (int i = 0; i < nl; ++i) {
+    const double x = lc[i].hnu / kt;
+    const double em = expm1(x);
+    const double b = lc[i].pre / em;
+    const double kabs = (1.0 - lc[i].alb) * lc[i].kext;
+    s += kabs * b * lc[i].dnu;
+    if (em < INFINITY) ds += kabs * (b * x * ((em + 1.0) / em) / t) * lc[i].dnu;
+  }
+}
+
+// Per leaf: the temperature at which the emitted power 4 pi m sum kappa_abs B(T) dnu equals
+// the absorbed power A.  Newton iteration on ln F(ln T), kept inside a shrinking bracket.
+__global__ __launch_bounds__(256) void temperature_kernel(
+    const ModelDev* __restrict__ models, int model, const int32_t* __restrict__ child,
+    const double* __restrict__ rho64, const double* __restrict__ a_node,
+    const LamConst* __restrict__ lc, int nl, double t_min, double t_max, double* __restrict__ t_out) {
+  const ModelDev& m = models[model];
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m.n_nodes) return;
+  const int64_t internal = m.base + (c < m.n_root ? c : c + (m.n_root_pad - m.n_root));
+  if (child[internal] >= 0) {
+    t_out[c] = 0.0;
+    return;
+  }
+  int lev = 0;
+  while (lev < m.nlev && c >= m.level_off[lev + 1]) ++lev;
+  const double len = m.cell_cm * ldexp(1.0, -lev);
+  const double mass = rho64[internal] * (len * len * len);
+  const double A = a_node[c];
+  const double fpi = 4.0 * kPi;
+  double s, ds;
+  planck_sum(lc, nl, t_min, s, ds);
+  const double flo = fpi * mass * s;
+  if (A <= flo) {
+    t_out[c] = t_min;
+    return;
+  }
+  planck_sum(lc, nl, t_max, s, ds);
+  const double fhi = fpi * mass * s;
+  if (A >= fhi) {
+    t_out[c] = t_max;
+    return;
+  }
+  double lo = log(t_min), hi = log(t_max);
+  const double la = log(A);
+  double u = lo + (la - log(flo)) / (log(fhi) - log(flo)) * (hi - lo);
+  if (!(u > lo && u < hi)) u = 0.5 * (lo + hi);
+  for (int it = 0; it < 200; ++it) {
+    const double t = exp(u);
+    planck_sum(lc, nl, t, s, ds);
+    const double f = fpi * mass * s;
+    if (f < A) lo = u;
+    else hi = u;
+    double un;
+    if (f > 0.0 && ds > 0.0) {
+      un = u - (log(f) - la) / (t * ds / s);
+      if (!(un > lo && un < hi)) un = 0.5 * (lo + hi);
+    } else {
+      un = 0.5 * (lo + hi);
+    }
+    const bool done = fabs(un - u) <= 1e-14 || hi - lo <= 1e-15;
+    u = un;
+    if (done) break;
+  }
+  t_out[c] = exp(u);
+}
+
+// Dust luminosity of every leaf at one wavelength (paper Sect. 4.2: packets are started from
+// a cell in proportion to its emission): 4 pi m kappa_abs B(T) dnu, and the maximum.
+__global__ __launch_bounds__(256) void dust_lum_kernel(
+    const ModelDev* __restrict__ models, int model, int64_t n_leaves,
+    const int32_t* __restrict__ leaf_node, const uint8_t* __restrict__ leaf_level,
+    const double* __restrict__ rho64, const double* __restrict__ t_node,
+    const LamConst* __restrict__ lc, int lam, double* __restrict__ lum,
+    unsigned long long* __restrict__ lmax_bits) {
+  const ModelDev& m = models[model];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double l = 0.0;
+  if (k < n_leaves) {
+    const int32_t node = leaf_node[m.leaf_base + k];
+    const int lev = leaf_level[m.leaf_base + k];
+    const double t = t_node[canon_of(m, node)];
+    const double len = m.cell_cm * ldexp(1.0, -lev);
+    const double mass = rho64[node] * (len * len * len);
+    const double kabs = (1.0 - lc[lam].alb) * lc[lam].kext;
+    double b = 0.0;
+    if (t > 0.0) b = lc[lam].pre / expm1(lc[lam].hnu / (kK * t));
+    l = 4.0 * kPi * mass * kabs * b * lc[lam].dnu;
+    lum[k] = l;
+  }
+  // non-negative doubles order like their bit patterns
+  unsigned long long bits = (unsigned long long)__double_as_longlong(l);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long other = __shfl_xor(bits, o, 64);
+    bits = other > bits ? other : bits;
+  }
+  if ((threadIdx.x & 63) == 0 && bits) atomicMax(lmax_bits, bits);
+}
+
+// Quantise each leaf's share of the maximum to 32 bits: q = floor(L / Lmax * 2^32).
+__global__ __launch_bounds__(256) void dust_quant_kernel(int64_t n, const double* __restrict__ lum,
+                                                         const unsigned long long* __restrict__ lmax_bits,
+                                                         uint64_t* __restrict__ q) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double lmax = __longlong_as_double((long long)*lmax_bits);
+  q[k] = lmax > 0.0 ? (uint64_t)floor((lum[k] / lmax) * 4294967296.0) : 0ull;
+}
+
+}  // namespace
+
+hipError_t launch_temperature(const ModelDev* models, int model, int64_t n_nodes,
+                              const int32_t* child, const double* rho64, const double* a_node,
+                              const LamConst* lc, int nl, double t_min, double t_max,
+                              double* t_out, hipStream_t s) {
+  hipLaunchKernelGGL(temperature_kernel, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s,
+                     models, model, child, rho64, a_node, lc, nl, t_min, t_max, t_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dust_lum(const ModelDev* models, int model, int64_t n_leaves,
+                           const int32_t* leaf_node, const uint8_t* leaf_level,
+                           const double* rho64, const double* t_node, const LamConst* lc, int lam,
+                           double* lum, unsigned long long* lmax_bits, hipStream_t s) {
+  hipLaunchKernelGGL(dust_lum_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, s,
+                     models, model, n_leaves, leaf_node, leaf_level, rho64, t_node, lc, lam, lum,
+                     lmax_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_dust_quant(int64_t n_leaves, const double* lum,
+                             const unsigned long long* lmax_bits, uint64_t* q, hipStream_t s) {
+  hipLaunchKernelGGL(dust_quant_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, s,
+                     n_leaves, lum, lmax_bits, q);
+  return hipGetLastError();
+}
