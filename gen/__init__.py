@@ -291,7 +291,7 @@ def _refine_top_down(rng, nx, ny, nz, cell_cm, root_rho, max_level, split_rule, 
 # ----------------------------------------------------------------------------------------
 
 def c3(seed: int = BASE_SEED + 3, root=(96, 96, 32), cell_au: float = 6.25, max_level: int = 6,
-       tau_split: float = 10.0, n_lambda: int = 50, packets: int = 30_000_000,
+       tau_split: float = 2.5, n_lambda: int = 50, packets: int = 30_000_000,
        star_t: float = 4000.0, star_r_rsun: float = 2.0, kappa_v: float = 200.0,
        tau_mid_1um: float = 1.0e3, r_in_au: float = 0.1, r_out_au: float = 300.0,
        near_star_cells: float = 4.0) -> Workload:

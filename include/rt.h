@@ -121,7 +121,10 @@ typedef struct {
 } rt_source;
 
 #define RT_FP64 0        /* plain form: one packet per lane, global FP64 coordinates */
-#define RT_FP32_LOCAL 1  /* persistent packet queue, FP32 per-cell local coordinates */
+#define RT_FP32_LOCAL 1  /* packet queues, FP32 per-cell local coordinates */
+
+#define RT_SCHED_REGIONS 0 /* grid by grid (paper Sect. 3.4, App. A) on LDS-sized regions */
+#define RT_SCHED_GLOBAL 1  /* one persistent packet-queue kernel over the whole tree */
 
 /* Per-packet end state, written for sampled packets (see rt_trace_opts.rec_stride). */
 typedef struct {
@@ -143,9 +146,12 @@ typedef struct {
   int64_t max_events;       /* per-packet scattering cap; 0 = 1e6 */
   int32_t block_size;       /* threads per block (multiple of 64, <= 1024); 0 = default */
   int32_t blocks_per_cu;    /* persistent form: resident blocks per CU; 0 = default */
-  float refill_threshold;   /* persistent form: service events/refills when fewer than this
+  float refill_threshold;   /* FP32-local form: service events/refills when fewer than this
                                fraction of live lanes are crossing; 0 = default */
-  int32_t pad0;
+  int32_t schedule;         /* FP32-local form: RT_SCHED_REGIONS (default) processes the tree
+                               region by region with LDS-resident nodes and accumulators;
+                               RT_SCHED_GLOBAL runs one persistent kernel over the whole tree
+                               with global atomics */
   int64_t rec_stride;       /* > 0: record packet j of each (source, wavelength) when
                                j % rec_stride == 0 */
   rt_record* records;       /* host or device; job-major: job (source-major, then wavelength)

@@ -20,6 +20,7 @@ RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ESTATE = 0, -1, -2, -3, -4
 RT_MAX_LEVELS = 24
 SRC_BACKGROUND, SRC_POINT, SRC_DUST, SRC_BEAM = 0, 1, 2, 3
 FP64, FP32_LOCAL = 0, 1
+SCHED_REGIONS, SCHED_GLOBAL = 0, 1
 
 EXPORTS = ["rt_last_error", "rt_create", "rt_destroy", "rt_build_tree", "rt_get_model_info",
            "rt_get_sizes", "rt_locate", "rt_set_dust", "rt_set_temperature", "rt_trace_packets",
@@ -55,7 +56,7 @@ class TraceOpts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("iteration", C.c_uint32), ("precision", C.c_int32),
                 ("rr_threshold", C.c_double), ("rr_prob", C.c_double), ("max_events", C.c_int64),
                 ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("refill_threshold", C.c_float), ("pad0", C.c_int32), ("rec_stride", C.c_int64),
+                ("refill_threshold", C.c_float), ("schedule", C.c_int32), ("rec_stride", C.c_int64),
                 ("records", C.c_void_p)]
 
 
@@ -215,7 +216,7 @@ class Context:
     def trace_packets(self, sources: Sequence, seed: int, iteration: int = 0, precision: int = FP64,
                       rr_threshold: float = 0.0, rr_prob: float = 0.0, max_events: int = 0,
                       block_size: int = 0, blocks_per_cu: int = 0, refill_threshold: float = 0.0,
-                      rec_stride: int = 0, per_lambda: bool = False):
+                      rec_stride: int = 0, per_lambda: bool = False, schedule: int = SCHED_REGIONS):
         """Trace the packets of ``sources`` (objects with kind, model, pos, dir, power,
         packets).  Returns a dict of device tensors and the statistics."""
         torch = _torch()
@@ -243,7 +244,7 @@ class Context:
             rec = torch.zeros(max(n_rec, 1) * RECORD_DTYPE.itemsize, dtype=torch.uint8,
                               device=self.tdev)
         opts = TraceOpts(seed, iteration, precision, rr_threshold, rr_prob, max_events, block_size,
-                         blocks_per_cu, refill_threshold, 0, rec_stride,
+                         blocks_per_cu, refill_threshold, schedule, rec_stride,
                          None if rec is None else rec.data_ptr())
         st = TraceStats()
         self._check(lib().rt_trace_packets(self.h, n, arr, C.byref(opts), _ptr(e_node),
@@ -277,7 +278,7 @@ class Context:
                             (C.c_double * 3)(*s.dir), _ptr(pw).value, int(s.packets))
         opts = TraceOpts(seed, iteration, precision, rr_threshold, rr_prob, kw.get("max_events", 0),
                          kw.get("block_size", 0), kw.get("blocks_per_cu", 0),
-                         kw.get("refill_threshold", 0.0), 0, 0, None)
+                         kw.get("refill_threshold", 0.0), kw.get("schedule", SCHED_REGIONS), 0, None)
         t = torch.empty(self.models[model], dtype=torch.float64, device=self.tdev)
         nd = C.c_int32()
         crit = np.zeros(max(n_max, 1))

@@ -1,0 +1,677 @@
+// Grid-by-grid form of the FP32-local transport (paper Sect. 3.4 and App. A: the model is
+// processed one grid at a time so that the grid's data stay in fast memory, and packets that
+// leave a grid wait in the neighbouring grid's boundary array).
+//
+// On gfx950 a "grid" is a region: a brick of root cells and all their descendants, small enough
+// that its node words and its absorbed-energy accumulators live in LDS.  A workgroup takes a
+// work item (a region and a run of packets queued for it), loads the region into LDS, follows
+// each packet with LDS lookups and LDS atomic deposits until the packet leaves the region,
+// escapes or ends, and finally adds the LDS accumulators to the region-major FP32 accumulators
+// with coalesced atomics.  Packets leaving the region are appended to the next sweep's queue
+// (96-byte records); the host sorts each sweep's queue by (wavelength slot, region) and repeats
+// until the queue is empty, streaming in new packets at every sweep.
+#include "device.h"
+
+using namespace rtd;
+
+namespace {
+
+enum : int { B_EMPTY = 0, B_CROSS = 1, B_EVENT = 2, B_DONE = 3, B_EXIT = 4 };
+
+constexpr uint32_t kMaxCrossings = 1u << 30;
+constexpr int kRecoverLevel = 2;
+constexpr int kEscLds = 256;
+
+__device__ __forceinline__ float pow2f(int e) { return __int_as_float((127 + e) << 23); }
+__device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
+__device__ __forceinline__ float rcp_or_inf(float d) { return d != 0.0f ? 1.0f / d : INFINITY; }
+__device__ __forceinline__ int32_t child_of(int32_t w) { return w < 0 ? ~w : -1; }
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// ------------------------------------------------------------------------------------------
+// emission into the queue
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void blk_emit_kernel(const BlkParams b, uint64_t g0, uint64_t g1) {
+  const TraceParams& p = b.t;
+  const uint64_t gid = g0 + (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool have = gid < g1;
+  PRec r;
+  uint32_t key = 0;
+  double e_emit = 0.0;
+  unsigned long long npk = 0;
+  if (have) {
+    int lo = 0, hi = p.n_jobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (p.jobs[mid].start <= gid) lo = mid;
+      else hi = mid - 1;
+    }
+    const JobDev& J = p.jobs[lo];
+    const ModelDev& md = p.models[J.model];
+    const Dims D = dims_of(md);
+    const uint32_t pid = (uint32_t)(gid - J.start);
+    Pk64 k;
+    emit64(p, J, D, md.n_leaves, md.leaf_base, pid, k, ChildWord{p.word});
+    const double sc = ldexp(1.0, k.lev);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      r.I[q] = k.I[q];
+      r.x[q] = clamp01((float)(k.P[q] * sc - (double)k.I[q]));
+      r.d[q] = (float)k.d[q];
+      r.O[q] = k.P[q];
+    }
+    r.lev = (uint8_t)k.lev;
+    r.ax = 0;
+    r.sg = 0;
+    r.flag = 0;
+    r.w0 = (float)k.w0;
+    r.w = r.w0;
+    r.tau = (float)k.tau;
+    r.birth = k.node;
+    r.pid = pid;
+    r.job = lo;
+    r.ev = 0;
+    r.ncross = 1;
+    const int32_t root = D.root(k.I[0] >> k.lev, k.I[1] >> k.lev, k.I[2] >> k.lev);
+    key = (uint32_t)J.slot * (uint32_t)b.n_regions + (uint32_t)b.root_region[root];
+    e_emit = k.w0;
+    npk = 1;
+  }
+  const uint64_t mask = __ballot(have);
+  if (mask) {
+    uint32_t blo = 0, bhi = 0;
+    if (lane == 0) {
+      const unsigned long long base = atomicAdd(b.u_count, (unsigned long long)__popcll(mask));
+      blo = (uint32_t)base;
+      bhi = (uint32_t)(base >> 32);
+    }
+    blo = __shfl(blo, 0, 64);
+    bhi = __shfl(bhi, 0, 64);
+    if (have) {
+      const uint64_t idx = (((uint64_t)bhi << 32) | blo) + lane_rank(mask);
+      b.u_out[idx] = r;
+      b.u_key[idx] = key;
+    }
+  }
+  e_emit = wave_sum(e_emit);
+  npk = wave_sum_u64(npk);
+  if (lane == 0 && npk) {
+    unsafeAtomicAdd(&p.stats->e_emit, e_emit);
+    atomicAdd(&p.stats->packets, npk);
+  }
+}
+
+__global__ void blk_iota_kernel(uint32_t n, uint32_t* v) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = i;
+}
+
+// Run boundaries of the sorted keys.
+__global__ void blk_runs_kernel(const uint32_t* __restrict__ k, uint32_t n, int32_t* kstart, int32_t* kend) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t key = k[i];
+  if (i == 0 || k[i - 1] != key) kstart[key] = (int32_t)i;
+  if (i == n - 1 || k[i + 1] != key) kend[key] = (int32_t)i + 1;
+}
+
+// Work items: each run of one (slot, region) key split into chunks (one block).
+__global__ __launch_bounds__(1024) void blk_items_kernel(int32_t n_keys, int32_t n_regions, int32_t chunk,
+                                                         const int32_t* __restrict__ kstart,
+                                                         const int32_t* __restrict__ kend,
+                                                         WorkItem* __restrict__ items,
+                                                         uint32_t* __restrict__ n_items) {
+  __shared__ uint32_t s_sum[1024];
+  uint32_t carry = 0;
+  for (int k0 = 0; k0 < n_keys; k0 += 1024) {
+    const int k = k0 + (int)threadIdx.x;
+    uint32_t cnt = 0, nch = 0;
+    if (k < n_keys) {
+      cnt = (uint32_t)(kend[k] - kstart[k]);
+      nch = (cnt + chunk - 1) / chunk;
+    }
+    s_sum[threadIdx.x] = nch;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const uint32_t v = threadIdx.x >= (unsigned)o ? s_sum[threadIdx.x - o] : 0u;
+      __syncthreads();
+      s_sum[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const uint32_t excl = carry + s_sum[threadIdx.x] - nch;
+    for (uint32_t c = 0; c < nch; ++c) {
+      WorkItem w;
+      w.region = k % n_regions;
+      w.slot = k / n_regions;
+      w.start = (uint32_t)kstart[k] + c * chunk;
+      w.count = min((uint32_t)chunk, cnt - c * chunk);
+      items[excl + c] = w;
+    }
+    carry += s_sum[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *n_items = carry;
+}
+
+// Land in the neighbour after a face crossing: from cell `cur` at level l (an ancestor-level
+// cell containing the neighbour J of the old cell Io at level L), descend along J's bits; a
+// coarser landing cell rescales the lateral local coordinates (recovered in FP64 from the
+// segment origin), a finer one descends by the near-side / midpoint rule.
+template <class WF>
+__device__ __forceinline__ void land(WF word_of, int ax, int sg, int L, int32_t Io0, int32_t Io1,
+                                     int32_t Io2, int32_t J0, int32_t J1, int32_t J2, int32_t cur, int l,
+                                     float& x0, float& x1, float& x2, double O0, double O1, double O2,
+                                     float d0, float d1, float d2, int32_t& node, int32_t& lev,
+                                     int32_t& I0, int32_t& I1, int32_t& I2, int32_t& raw) {
+  int32_t r = word_of(cur);
+  while (l < L && child_of(r) >= 0) {
+    ++l;
+    const int sh = L - l;
+    cur = child_of(r) + (((J0 >> sh) & 1) | (((J1 >> sh) & 1) << 1) | (((J2 >> sh) & 1) << 2));
+    r = word_of(cur);
+  }
+  const int sh = L - l;
+  I0 = J0 >> sh;
+  I1 = J1 >> sh;
+  I2 = J2 >> sh;
+  const float nearf = sg > 0 ? 0.0f : 1.0f;
+  if (l < L) {
+    const int kk = L - l;
+    const int32_t mask = (1 << kk) - 1;
+    const float scl = pow2f(-kk);
+    x0 = ax == 0 ? nearf : (x0 + (float)(Io0 & mask)) * scl;
+    x1 = ax == 1 ? nearf : (x1 + (float)(Io1 & mask)) * scl;
+    x2 = ax == 2 ? nearf : (x2 + (float)(Io2 & mask)) * scl;
+    if (L >= kRecoverLevel) {
+      const double hf = ldexp(1.0, -l), inv = ldexp(1.0, l);
+      const double F = (double)(sel3(ax, I0, I1, I2) + (sg > 0 ? 0 : 1)) * hf;
+      const double t = (F - sel3(ax, O0, O1, O2)) / (double)sel3(ax, d0, d1, d2);
+      if (ax != 0) x0 = clamp01((float)(fma(t, (double)d0, O0) * inv - (double)I0));
+      if (ax != 1) x1 = clamp01((float)(fma(t, (double)d1, O1) * inv - (double)I1));
+      if (ax != 2) x2 = clamp01((float)(fma(t, (double)d2, O2) * inv - (double)I2));
+    }
+  } else {
+    x0 = ax == 0 ? nearf : x0;
+    x1 = ax == 1 ? nearf : x1;
+    x2 = ax == 2 ? nearf : x2;
+    int32_t c = child_of(r);
+    while (c >= 0) {
+      const int b0 = ax == 0 ? (sg > 0 ? 0 : 1) : (x0 >= 0.5f ? 1 : 0);
+      const int b1 = ax == 1 ? (sg > 0 ? 0 : 1) : (x1 >= 0.5f ? 1 : 0);
+      const int b2 = ax == 2 ? (sg > 0 ? 0 : 1) : (x2 >= 0.5f ? 1 : 0);
+      x0 = 2.0f * x0 - (float)b0;
+      x1 = 2.0f * x1 - (float)b1;
+      x2 = 2.0f * x2 - (float)b2;
+      I0 = 2 * I0 + b0;
+      I1 = 2 * I1 + b1;
+      I2 = 2 * I2 + b2;
+      cur = c + (b0 | (b1 << 1) | (b2 << 2));
+      ++l;
+      r = word_of(cur);
+      c = child_of(r);
+    }
+  }
+  node = cur;
+  lev = l;
+  raw = r;
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int cap = b.cap;
+  int32_t* s_word = reinterpret_cast<int32_t*>(smem);
+  float* s_acc = reinterpret_cast<float*>(smem + 4 * (size_t)cap);
+  int32_t* s_up = reinterpret_cast<int32_t*>(smem + 8 * (size_t)cap);
+  __shared__ int s_item;
+  __shared__ uint32_t s_next;
+  __shared__ double s_misc[4];
+  __shared__ double s_esc[kEscLds];
+  const TraceParams& p = b.t;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const bool esc_lds = p.n_esc <= kEscLds;
+  for (int i = tid; i < kEscLds; i += BS) s_esc[i] = 0.0;
+  if (tid < 4) s_misc[tid] = 0.0;
+  const float rr_thr = (float)p.rr_thr, rr_p = (float)p.rr_p;
+  const float rr_gain = rr_p > 0.0f ? 1.0f / (1.0f - rr_p) : 1.0f;
+  unsigned long long c_cross = 0;
+  uint32_t c_scat = 0, c_kill = 0, c_trunc = 0;
+
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_item = (int)atomicAdd(b.item_counter, 1u);
+    __syncthreads();
+    const uint32_t item = (uint32_t)s_item;
+    if (item >= *b.n_items) break;
+    const WorkItem it = b.items[item];
+    const RegionDev R = b.regions[it.region];
+    const ModelDev& md = p.models[R.model];
+    const Dims D = dims_of(md);
+    const int bx = R.hi[0] - R.lo[0], by = R.hi[1] - R.lo[1];
+    const int nloc = min(R.n, cap);
+    const int nup = (nloc + 7) >> 3;
+    for (int i = tid; i < nloc; i += BS) {
+      s_word[i] = b.rword[R.gbase + i];
+      s_acc[i] = 0.0f;
+    }
+    for (int i = tid; i < nup; i += BS) s_up[i] = b.rup[(R.gbase >> 3) + i];
+    if (tid == 0) s_next = 0;
+    __syncthreads();
+    float* __restrict__ gacc = b.accb + (int64_t)it.slot * b.accb_stride + R.gbase;
+    const int32_t* __restrict__ gword = b.rword + R.gbase;
+    const int32_t* __restrict__ gup = b.rup + (R.gbase >> 3);
+    auto word_of = [&](int32_t l) -> int32_t { return l < nloc ? s_word[l] : gword[l]; };
+    auto up_of = [&](int32_t l) -> int32_t { return (l >> 3) < nup ? s_up[l >> 3] : gup[l >> 3]; };
+
+    int state = B_EMPTY;
+    int32_t node = 0, lev = 0, I0 = 0, I1 = 0, I2 = 0, birth = 0, job = 0;
+    float x0 = 0.f, x1 = 0.f, x2 = 0.f, d0 = 0.f, d1 = 0.f, d2 = 1.f;
+    float r0 = INFINITY, r1 = INFINITY, r2 = 1.f, w = 0.f, w0 = 0.f, tau = 0.f, rho = 0.f;
+    double O0 = 0.0, O1 = 0.0, O2 = 0.0;
+    uint32_t pid = 0, ev = 0, ncross = 0, stream = 0;
+    float kc = 0.f, alb = 0.f, g = 0.f;
+    int esc_slot = 0;
+    int32_t xax = 0, xsg = 0;
+    uint32_t xkey = 0;
+
+    for (;;) {
+      // ---------------- refill from this item's queue ----------------
+      const uint64_t need = __ballot(state == B_EMPTY);
+      if (need) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&s_next, (uint32_t)__popcll(need));
+        base = __shfl(base, 0, 64);
+        if (state == B_EMPTY) {
+          const uint32_t idx = base + lane_rank(need);
+          if (idx >= it.count) {
+            state = B_DONE;
+          } else {
+            const PRec rec = b.q_in[b.q_perm[it.start + idx]];
+            job = rec.job;
+            const JobDev& J = p.jobs[job];
+            kc = J.kc32;
+            alb = J.alb32;
+            g = J.g32;
+            stream = J.stream;
+            esc_slot = J.esc_slot;
+            x0 = rec.x[0];
+            x1 = rec.x[1];
+            x2 = rec.x[2];
+            d0 = rec.d[0];
+            d1 = rec.d[1];
+            d2 = rec.d[2];
+            r0 = rcp_or_inf(d0);
+            r1 = rcp_or_inf(d1);
+            r2 = rcp_or_inf(d2);
+            w = rec.w;
+            w0 = rec.w0;
+            tau = rec.tau;
+            O0 = rec.O[0];
+            O1 = rec.O[1];
+            O2 = rec.O[2];
+            pid = rec.pid;
+            ev = rec.ev;
+            ncross = rec.ncross;
+            birth = rec.birth;
+            const int L = rec.lev;
+            int32_t J0 = rec.I[0], J1 = rec.I[1], J2 = rec.I[2];
+            int ax = 0, sg = 1;
+            if (rec.flag) {
+              ax = rec.ax;
+              sg = rec.sg ? -1 : 1;
+              if (ax == 0) J0 += sg;
+              else if (ax == 1) J1 += sg;
+              else J2 += sg;
+            }
+            const int32_t R0 = J0 >> L, R1 = J1 >> L, R2 = J2 >> L;
+            const int32_t rootl = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
+            int32_t raw = 0;
+            const bool misplaced = R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] || R1 >= R.hi[1] ||
+                                   R2 < R.lo[2] || R2 >= R.hi[2];
+            if (misplaced) {
+              // a record queued for the wrong region (never expected): retire it as truncated
+              ++c_trunc;
+              atomicAdd(&s_misc[2], (double)w);
+              c_cross += ncross;
+            } else if (rec.flag) {
+              land(word_of, ax, sg, L, rec.I[0], rec.I[1], rec.I[2], J0, J1, J2, rootl, 0, x0, x1, x2, O0,
+                   O1, O2, d0, d1, d2, node, lev, I0, I1, I2, raw);
+              ++ncross;
+            } else {
+              // birth: walk down to the birth leaf along its coordinates
+              int32_t cur = rootl;
+              int32_t rr = word_of(cur);
+              for (int l = 1; l <= L && child_of(rr) >= 0; ++l) {
+                const int sh = L - l;
+                cur = child_of(rr) + (((J0 >> sh) & 1) | (((J1 >> sh) & 1) << 1) | (((J2 >> sh) & 1) << 2));
+                rr = word_of(cur);
+              }
+              node = cur;
+              lev = L;
+              I0 = J0;
+              I1 = J1;
+              I2 = J2;
+              raw = rr;
+            }
+            rho = __int_as_float(raw);
+            state = misplaced ? B_EMPTY : B_CROSS;
+          }
+        }
+      }
+      const uint64_t live = __ballot(state != B_DONE);
+      if (!live) break;
+      const int want = max(1, (int)(p.refill_thr * (float)__popcll(live)));
+
+      // ---------------- crossing phase (LDS lookups, LDS deposits) ----------------
+      for (;;) {
+        if (state == B_CROSS) {
+          const float se = kc * rho * pow2f(-lev);
+          const float ss = alb * se;
+          const float sa = se - ss;
+          const float tx = d0 != 0.0f ? (d0 > 0.0f ? 1.0f - x0 : -x0) * r0 : INFINITY;
+          const float ty = d1 != 0.0f ? (d1 > 0.0f ? 1.0f - x1 : -x1) * r1 : INFINITY;
+          const float tz = d2 != 0.0f ? (d2 > 0.0f ? 1.0f - x2 : -x2) * r2 : INFINITY;
+          int ax;
+          float texit;
+          if (tx <= ty && tx <= tz) {
+            ax = 0;
+            texit = tx;
+          } else if (ty <= tz) {
+            ax = 1;
+            texit = ty;
+          } else {
+            ax = 2;
+            texit = tz;
+          }
+          const float tsc = ss * texit;
+          const bool event = ss > 0.0f && tau <= tsc;
+          float s;
+          if (event) {
+            s = tau / ss;
+          } else {
+            s = texit;
+            tau -= tsc;
+          }
+          const float de = w * (-expm1f(-(sa * s)));
+          if (de > 0.0f) {
+            if (node < nloc) atomicAdd(&s_acc[node], de);
+            else unsafeAtomicAdd(gacc + node, de);
+            w -= de;
+          }
+          x0 = clamp01(fmaf(s, d0, x0));
+          x1 = clamp01(fmaf(s, d1, x1));
+          x2 = clamp01(fmaf(s, d2, x2));
+          if (event) {
+            state = B_EVENT;
+          } else {
+            const int sg = sel3(ax, d0, d1, d2) > 0.0f ? 1 : -1;
+            const int L = lev;
+            const int32_t Ia = sel3(ax, I0, I1, I2);
+            const int32_t Ja = Ia + sg;
+            if (Ja < 0 || Ja >= (D.na(ax) << L)) {
+              // escape through the root boundary
+              if (esc_lds) atomicAdd(&s_esc[esc_slot], (double)w);
+              else unsafeAtomicAdd(p.esc + esc_slot, (double)w);
+              if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
+                const JobDev& J = p.jobs[job];
+                rt_record rc{0u, ncross, ev, 0u, -1, canon_of(md, birth), (double)w};
+                p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
+              }
+              c_cross += ncross;
+              state = B_EMPTY;
+            } else {
+              int32_t cur = node;
+              int l = L;
+              while (l > 0 && ((Ja >> (L - l + 1)) != (Ia >> (L - l + 1)))) {
+                cur = up_of(cur);
+                --l;
+              }
+              const int32_t J0 = ax == 0 ? Ja : I0, J1 = ax == 1 ? Ja : I1, J2 = ax == 2 ? Ja : I2;
+              bool leave = false;
+              if (l == 0) {
+                const int32_t R0 = J0 >> L, R1 = J1 >> L, R2 = J2 >> L;
+                if (R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] || R1 >= R.hi[1] || R2 < R.lo[2] ||
+                    R2 >= R.hi[2]) {
+                  leave = true;
+                  xax = ax;
+                  xsg = sg;
+                  xkey = (uint32_t)it.slot * (uint32_t)b.n_regions + (uint32_t)b.root_region[D.root(R0, R1, R2)];
+                  state = B_EXIT;
+                } else {
+                  cur = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
+                }
+              } else {
+                cur += sg > 0 ? (1 << ax) : -(1 << ax);
+              }
+              if (!leave) {
+                int32_t raw;
+                land(word_of, ax, sg, L, I0, I1, I2, J0, J1, J2, cur, l, x0, x1, x2, O0, O1, O2, d0, d1, d2,
+                     node, lev, I0, I1, I2, raw);
+                rho = __int_as_float(raw);
+                if (++ncross >= kMaxCrossings) {
+                  ev = (uint32_t)p.max_events;
+                  state = B_EVENT;
+                }
+              }
+            }
+          }
+        }
+        if (__popcll(__ballot(state == B_CROSS)) < want) break;
+      }
+
+      // ---------------- packets leaving the region: append to the next queue ----------------
+      const uint64_t ex = __ballot(state == B_EXIT);
+      if (ex) {
+        uint32_t blo = 0, bhi = 0;
+        if (lane == 0) {
+          const unsigned long long base = atomicAdd(b.u_count, (unsigned long long)__popcll(ex));
+          blo = (uint32_t)base;
+          bhi = (uint32_t)(base >> 32);
+        }
+        blo = __shfl(blo, 0, 64);
+        bhi = __shfl(bhi, 0, 64);
+        if (state == B_EXIT) {
+          const uint64_t idx = (((uint64_t)bhi << 32) | blo) + lane_rank(ex);
+          PRec rc;
+          rc.I[0] = I0;
+          rc.I[1] = I1;
+          rc.I[2] = I2;
+          rc.lev = (uint8_t)lev;
+          rc.ax = (uint8_t)xax;
+          rc.sg = xsg > 0 ? 0 : 1;
+          rc.flag = 1;
+          rc.x[0] = x0;
+          rc.x[1] = x1;
+          rc.x[2] = x2;
+          rc.d[0] = d0;
+          rc.d[1] = d1;
+          rc.d[2] = d2;
+          rc.w = w;
+          rc.w0 = w0;
+          rc.tau = tau;
+          rc.birth = birth;
+          rc.O[0] = O0;
+          rc.O[1] = O1;
+          rc.O[2] = O2;
+          rc.pid = pid;
+          rc.job = job;
+          rc.ev = ev;
+          rc.ncross = ncross;
+          b.u_out[idx] = rc;
+          b.u_key[idx] = xkey;
+          state = B_EMPTY;
+        }
+      }
+
+      // ---------------- scattering events, serviced together ----------------
+      if (state == B_EVENT) {
+        ++ev;
+        if ((int64_t)ev > p.max_events) {
+          ++c_trunc;
+          atomicAdd(&s_misc[2], (double)w);
+          if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
+            const JobDev& J = p.jobs[job];
+            rt_record rc{2u, ncross, ev, 0u, (int64_t)b.rcanon[R.gbase + node], canon_of(md, birth), (double)w};
+            p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
+          }
+          c_cross += ncross;
+          state = B_EMPTY;
+        } else {
+          ++c_scat;
+          const double h = ldexp(1.0, -lev);
+          O0 = ((double)I0 + (double)x0) * h;
+          O1 = ((double)I1 + (double)x1) * h;
+          O2 = ((double)I2 + (double)x2) * h;
+          const uint4 xr = philox(pid, stream, ev, 0u, p.key0, p.key1);
+          bool killed = false;
+          if (rr_p > 0.0f && w < rr_thr * w0) {
+            if (unif32(xr.x) < rr_p) {
+              ++c_kill;
+              atomicAdd(&s_misc[0], (double)w);
+              if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
+                const JobDev& J = p.jobs[job];
+                rt_record rc{1u, ncross, ev, 0u, (int64_t)b.rcanon[R.gbase + node], canon_of(md, birth), (double)w};
+                p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
+              }
+              c_cross += ncross;
+              state = B_EMPTY;
+              killed = true;
+            } else {
+              const float nw = w * rr_gain;
+              atomicAdd(&s_misc[1], (double)nw - (double)w);
+              w = nw;
+            }
+          }
+          if (!killed) {
+            const float mu = hg_mu32(g, unif32(xr.y));
+            rotate32(d0, d1, d2, mu, kTwoPiF * unif32(xr.z));
+            r0 = rcp_or_inf(d0);
+            r1 = rcp_or_inf(d1);
+            r2 = rcp_or_inf(d2);
+            tau = -logf(unif32(xr.w));
+            state = B_CROSS;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nloc; i += BS) {
+      const float v = s_acc[i];
+      if (v != 0.0f) unsafeAtomicAdd(gacc + i, v);
+    }
+  }
+
+  const unsigned long long sc_cross = wave_sum_u64(c_cross);
+  const unsigned long long sc_scat = wave_sum_u64(c_scat);
+  const unsigned long long sc_kill = wave_sum_u64(c_kill);
+  const unsigned long long sc_trunc = wave_sum_u64(c_trunc);
+  if (lane == 0) {
+    if (sc_cross) atomicAdd(&p.stats->crossings, sc_cross);
+    if (sc_scat) atomicAdd(&p.stats->scatterings, sc_scat);
+    if (sc_kill) atomicAdd(&p.stats->kills, sc_kill);
+    if (sc_trunc) atomicAdd(&p.stats->truncated, sc_trunc);
+  }
+  __syncthreads();
+  if (esc_lds)
+    for (int i = tid; i < p.n_esc; i += BS)
+      if (s_esc[i] != 0.0) unsafeAtomicAdd(p.esc + i, s_esc[i]);
+  if (tid == 0) {
+    if (s_misc[0] != 0.0) unsafeAtomicAdd(&p.stats->e_killed, s_misc[0]);
+    if (s_misc[1] != 0.0) unsafeAtomicAdd(&p.stats->e_rr_gain, s_misc[1]);
+    if (s_misc[2] != 0.0) unsafeAtomicAdd(&p.stats->e_trunc, s_misc[2]);
+  }
+}
+
+// Region-major FP32 accumulators -> FP64 canonical outputs (one block row per region).
+__global__ __launch_bounds__(256) void blk_reduce_kernel(const ModelDev* __restrict__ models,
+                                                         const RegionDev* __restrict__ regions,
+                                                         const int32_t* __restrict__ rcanon,
+                                                         const float* __restrict__ accb, int64_t stride,
+                                                         int n_slots, double* __restrict__ e_node,
+                                                         double* __restrict__ e_lam_node,
+                                                         double* __restrict__ e_total) {
+  __shared__ double s_part[4];
+  const RegionDev& R = regions[blockIdx.y];
+  const ModelDev& m = models[R.model];
+  const int32_t l = blockIdx.x * 256 + threadIdx.x;
+  double sum = 0.0;
+  if (l < R.n) {
+    const int64_t gidx = R.gbase + l;
+    const int32_t c = rcanon[gidx];
+    if (c >= 0) {
+      const int ns = n_slots > 1 ? m.nl : 1;
+      for (int s = 0; s < ns; ++s) {
+        const double v = (double)accb[s * stride + gidx];
+        sum += v;
+        if (e_lam_node) e_lam_node[m.lamnode_base + (int64_t)s * m.n_nodes + c] = v;
+      }
+      if (e_node) e_node[m.canon_base + c] = sum;
+    }
+  }
+  sum = wave_sum(sum);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+    if (t != 0.0) unsafeAtomicAdd(e_total, t);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_blk_emit(const BlkParams& b, uint64_t g0, uint64_t g1, hipStream_t s) {
+  const uint64_t n = g1 - g0;
+  hipLaunchKernelGGL(blk_emit_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, g0, g1);
+  return hipGetLastError();
+}
+
+hipError_t launch_blk_iota(uint32_t n, uint32_t* v, hipStream_t s) {
+  hipLaunchKernelGGL(blk_iota_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_blk_items(const uint32_t* skeys, uint32_t n, int32_t n_keys, int32_t n_regions,
+                            int32_t chunk, int32_t* kstart, int32_t* kend, WorkItem* items,
+                            uint32_t* n_items, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(kstart, 0, sizeof(int32_t) * n_keys, s);
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(kend, 0, sizeof(int32_t) * n_keys, s);
+  if (e != hipSuccess) return e;
+  if (n > 0) hipLaunchKernelGGL(blk_runs_kernel, dim3((n + 255) / 256), dim3(256), 0, s, skeys, n, kstart, kend);
+  hipLaunchKernelGGL(blk_items_kernel, dim3(1), dim3(1024), 0, s, n_keys, n_regions, chunk, kstart, kend, items,
+                     n_items);
+  return hipGetLastError();
+}
+
+hipError_t attr_blk_pass(int block, int lds_bytes) {
+  switch (block) {
+    case 256: return hipFuncSetAttribute((const void*)blk_pass_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    case 512: return hipFuncSetAttribute((const void*)blk_pass_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    case 1024: return hipFuncSetAttribute((const void*)blk_pass_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s) {
+  switch (block) {
+    case 256: hipLaunchKernelGGL(blk_pass_kernel<256>, dim3(grid), dim3(256), lds_bytes, s, b); break;
+    case 512: hipLaunchKernelGGL(blk_pass_kernel<512>, dim3(grid), dim3(512), lds_bytes, s, b); break;
+    case 1024: hipLaunchKernelGGL(blk_pass_kernel<1024>, dim3(grid), dim3(1024), lds_bytes, s, b); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, int n_regions,
+                             int32_t max_region_nodes, const int32_t* rcanon, const float* accb,
+                             int64_t stride, int n_slots, double* e_node, double* e_lam_node,
+                             double* e_total, hipStream_t s) {
+  if (n_regions == 0) return hipSuccess;
+  hipLaunchKernelGGL(blk_reduce_kernel, dim3((max_region_nodes + 255) / 256, n_regions), dim3(256), 0, s, models,
+                     regions, rcanon, accb, stride, n_slots, e_node, e_lam_node, e_total);
+  return hipGetLastError();
+}

@@ -51,7 +51,8 @@ struct JobDev {
   double pos[3];
   double dir[3];
   double kext, alb, g; // FP64 dust constants at this wavelength
-  float kc32, alb32, g32, pad32;  // FP32: kext * root_cell_cm, albedo, g
+  float kc32, alb32, g32;  // FP32: kext * root_cell_cm, albedo, g
+  int32_t slot;        // accumulator slot (wavelength, or 0 when wavelengths are summed)
   int64_t acc_off;     // element offset of this job's accumulator slot
   int64_t rec_base;    // first record index (rec_stride > 0)
   int64_t cdf_off;     // dust emission: offset of this (model, wavelength) table
@@ -93,6 +94,75 @@ struct TraceParams {
   const int32_t* leaf_coord;
   const uint8_t* leaf_level;
 };
+
+// ------------------------------------------------------------------------------------------
+// Grid-by-grid (region-blocked) form.  A region is a brick of root cells [lo, hi) with all
+// their descendants, renumbered region-major: local ids [0, nb_pad) are the brick's root cells
+// (x fastest), then the octs level by level, each oct 8-aligned.  Region-major global id =
+// gbase + local.  rword: leaf -> float bits of the density, refined -> ~(local first child);
+// rup[g >> 3]: local parent of the oct starting at g; rcanon[g]: canonical id (-1 = padding).
+// ------------------------------------------------------------------------------------------
+struct RegionDev {
+  int32_t model;
+  int32_t lo[3], hi[3];
+  int32_t n;        // local ids used (including padding)
+  int64_t gbase;    // region-major global id of local 0 (multiple of 8)
+};
+
+// A packet waiting at a region boundary (or just born): 96 bytes.
+struct PRec {
+  int32_t I[3];          // integer coordinates of the cell it is in, at level lev
+  uint8_t lev, ax, sg, flag;  // flag 0: inside the cell; 1: about to cross axis ax (sg 0: +, 1: -)
+  float x[3], d[3];      // local coordinates in that cell, direction
+  float w, w0, tau;
+  int32_t birth;         // internal id of the birth leaf (records)
+  double O[3];           // FP64 segment origin (root-cell units)
+  uint32_t pid;
+  int32_t job;
+  uint32_t ev, ncross;
+};
+static_assert(sizeof(PRec) == 96, "packet record layout");
+
+struct WorkItem {
+  int32_t region, slot;
+  uint32_t start, count;
+};
+
+struct BlkParams {
+  TraceParams t;
+  const RegionDev* regions;
+  int32_t n_regions;
+  int32_t cap;               // node capacity of the LDS copy of a region
+  const int32_t* rword;
+  const int32_t* rup;
+  const int32_t* rcanon;     // region-major id -> canonical id within its model (-1 = padding)
+  const int32_t* root_region;  // per internal id of a root cell (old layout): its region
+  float* accb;               // [slots][G] region-major FP32 accumulators
+  int64_t accb_stride;       // G
+  // queues
+  PRec* u_out;               // append target
+  uint32_t* u_key;           // its sort keys (slot * n_regions + region)
+  unsigned long long* u_count;
+  const PRec* q_in;          // records of this sweep, read through q_perm
+  const uint32_t* q_perm;
+  const WorkItem* items;
+  const uint32_t* n_items;
+  uint32_t* item_counter;
+  int32_t n_slots_key;       // accumulator slots (wavelengths) in the key
+  int32_t chunk;             // packets per work item
+};
+
+hipError_t launch_blk_emit(const BlkParams& b, uint64_t g0, uint64_t g1, hipStream_t s);
+hipError_t launch_blk_iota(uint32_t n, uint32_t* v, hipStream_t s);
+hipError_t launch_blk_items(const uint32_t* skeys, uint32_t n, int32_t n_keys, int32_t n_regions,
+                            int32_t chunk, int32_t* kstart, int32_t* kend, WorkItem* items,
+                            uint32_t* n_items, hipStream_t s);
+hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s);
+hipError_t attr_blk_pass(int block, int lds_bytes);
+hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, int n_regions,
+                             int32_t max_region_nodes, const int32_t* rcanon, const float* accb,
+                             int64_t stride, int n_slots, double* e_node, double* e_lam_node,
+                             double* e_total, hipStream_t s);
 
 // Launch wrappers (defined in the .hip files)
 hipError_t launch_trace_fp64(const TraceParams& p, int job, uint64_t n, int block, hipStream_t s);

@@ -3,6 +3,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <array>
 #include <cfloat>
 #include <cmath>
 #include <cstdarg>
@@ -84,6 +85,17 @@ struct rt_ctx {
   DevBuf cdf_lum, cdf_q, cdf_qpre, lmax, scan_tmp;
   DevBuf tmp_in, tmp_out, tmp_out2, view, lamidx;
   DevBuf it_astars, it_adust, it_sum, it_told, it_crit;
+  // grid-by-grid schedule: region-major copy of the trees
+  int32_t reg_cap = 0;
+  bool reg_dirty = true;
+  std::vector<RegionDev> h_regions;
+  int64_t reg_G = 0;
+  int32_t reg_maxn = 0;
+  DevBuf d_regions, d_rword, d_rup, d_rcanon, d_root_region;
+  DevBuf q_rec[2], q_key[2], q_skey, q_perm, q_iota, q_kstart, q_kend, q_items, q_nitems, q_counters,
+      q_sort_tmp;
+  int64_t q_capacity = 0;
+  std::vector<int32_t> h_reg_nodes;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
 };
 
@@ -186,6 +198,7 @@ rt_status sync_device(rt_ctx* ctx) {
       return s;
     ctx->tree_dirty = false;
     ctx->table_dirty = true;
+    ctx->reg_dirty = true;
   }
   if (ctx->table_dirty) {
     ctx->h_models.assign(ctx->models.size(), ModelDev{});
@@ -219,6 +232,141 @@ rt_status sync_device(rt_ctx* ctx) {
     if (s) return s;
     ctx->table_dirty = false;
   }
+  return RT_OK;
+}
+
+// Partition every model into regions for the grid-by-grid schedule: bricks of root cells,
+// bisected along their longest side until the brick's nodes (root cells padded to 8 plus all
+// descendants) fit in `cap` or the brick is a single root cell; then renumber region-major.
+rt_status build_regions(rt_ctx* ctx, int32_t cap) {
+  if (!ctx->reg_dirty && ctx->reg_cap == cap) return RT_OK;
+  std::vector<RegionDev> regs;
+  std::vector<int32_t> rword, rup, rcanon, root_region(ctx->total_int, -1);
+  int64_t G = 0;
+  int32_t maxn = 0;
+  for (size_t mi = 0; mi < ctx->models.size(); ++mi) {
+    const HostModel& h = ctx->models[mi];
+    const int nx = h.n[0], ny = h.n[1], nz = h.n[2];
+    const int64_t nn = h.n_nodes, n_root = h.n_root;
+    const int64_t pad0 = h.n_root_pad - n_root;
+    auto internal = [&](int64_t c) { return h.base + (c < n_root ? c : c + pad0); };
+    // subtree sizes, bottom-up over levels (canonical order)
+    std::vector<int64_t> sz(nn, 1);
+    for (int l = h.nlev - 1; l >= 0; --l)
+      for (int64_t c = h.level_off[l]; c < h.level_off[l + 1]; ++c) {
+        const int32_t fc = ctx->h_child[internal(c)];
+        if (fc >= 0) {
+          const int64_t cc = (int64_t)fc - h.base - pad0;  // canonical first child
+          int64_t s = 1;
+          for (int b = 0; b < 8; ++b) s += sz[cc + b];
+          sz[c] = s;
+        }
+      }
+    // 3D prefix sums of the root-cell subtree sizes
+    const int64_t sx = nx + 1, sy = ny + 1;
+    std::vector<int64_t> P((size_t)(nx + 1) * (ny + 1) * (nz + 1), 0);
+    auto pidx = [&](int x, int y, int z) { return (size_t)x + sx * ((size_t)y + sy * (size_t)z); };
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+          P[pidx(x + 1, y + 1, z + 1)] = sz[x + (int64_t)nx * (y + (int64_t)ny * z)] + P[pidx(x, y + 1, z + 1)] +
+                                         P[pidx(x + 1, y, z + 1)] + P[pidx(x + 1, y + 1, z)] - P[pidx(x, y, z + 1)] -
+                                         P[pidx(x, y + 1, z)] - P[pidx(x + 1, y, z)] + P[pidx(x, y, z)];
+    auto box_sum = [&](const int lo[3], const int hi[3]) {
+      return P[pidx(hi[0], hi[1], hi[2])] - P[pidx(lo[0], hi[1], hi[2])] - P[pidx(hi[0], lo[1], hi[2])] -
+             P[pidx(hi[0], hi[1], lo[2])] + P[pidx(lo[0], lo[1], hi[2])] + P[pidx(lo[0], hi[1], lo[2])] +
+             P[pidx(hi[0], lo[1], lo[2])] - P[pidx(lo[0], lo[1], lo[2])];
+    };
+    std::vector<std::array<int, 6>> stack{{0, 0, 0, nx, ny, nz}}, boxes;
+    while (!stack.empty()) {
+      auto bx = stack.back();
+      stack.pop_back();
+      const int lo[3] = {bx[0], bx[1], bx[2]}, hi[3] = {bx[3], bx[4], bx[5]};
+      const int64_t nb = (int64_t)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+      const int64_t nodes = round8(nb) + (box_sum(lo, hi) - nb);
+      if (nodes <= cap || nb == 1) {
+        boxes.push_back(bx);
+        continue;
+      }
+      int a = 0;
+      for (int q = 1; q < 3; ++q)
+        if (hi[q] - lo[q] > hi[a] - lo[a]) a = q;
+      const int mid = (lo[a] + hi[a]) / 2;
+      auto b1 = bx, b2 = bx;
+      b1[3 + a] = mid;
+      b2[a] = mid;
+      stack.push_back(b2);
+      stack.push_back(b1);
+    }
+    for (const auto& bx : boxes) {
+      RegionDev R;
+      R.model = (int32_t)mi;
+      for (int q = 0; q < 3; ++q) {
+        R.lo[q] = bx[q];
+        R.hi[q] = bx[3 + q];
+      }
+      const int bxn = R.hi[0] - R.lo[0], byn = R.hi[1] - R.lo[1];
+      const int64_t nb = (int64_t)bxn * byn * (R.hi[2] - R.lo[2]);
+      R.gbase = G;
+      const int32_t rid = (int32_t)regs.size();
+      // local numbering: the brick's root cells, then octs level by level
+      std::vector<std::pair<int64_t, int32_t>> cur;  // (canonical, local)
+      cur.reserve(nb);
+      for (int z = R.lo[2]; z < R.hi[2]; ++z)
+        for (int y = R.lo[1]; y < R.hi[1]; ++y)
+          for (int x = R.lo[0]; x < R.hi[0]; ++x) {
+            const int64_t c = x + (int64_t)nx * (y + (int64_t)ny * z);
+            const int32_t l = (int32_t)((x - R.lo[0]) + bxn * ((y - R.lo[1]) + byn * (z - R.lo[2])));
+            cur.emplace_back(c, l);
+            root_region[internal(c)] = rid;
+          }
+      int64_t next = round8(nb);
+      std::vector<int32_t> lw, lc;  // local words, canonical ids
+      std::vector<std::pair<int32_t, int32_t>> lup;  // (first child local, parent local)
+      lw.assign(next, 0);
+      lc.assign(next, -1);
+      while (!cur.empty()) {
+        std::vector<std::pair<int64_t, int32_t>> nxt;
+        for (const auto& e : cur) {
+          const int64_t c = e.first;
+          const int32_t l = e.second;
+          const int32_t fc = ctx->h_child[internal(c)];
+          lc[l] = (int32_t)c;
+          if (fc < 0) {
+            lw[l] = ctx->h_word[internal(c)];
+          } else {
+            const int32_t first = (int32_t)next;
+            lw[l] = ~first;
+            lup.emplace_back(first, l);
+            next += 8;
+            lw.resize(next, 0);
+            lc.resize(next, -1);
+            const int64_t cc = (int64_t)fc - h.base - pad0;
+            for (int b = 0; b < 8; ++b) nxt.emplace_back(cc + b, first + b);
+          }
+        }
+        cur.swap(nxt);
+      }
+      R.n = (int32_t)next;
+      maxn = std::max(maxn, R.n);
+      rword.insert(rword.end(), lw.begin(), lw.end());
+      rcanon.insert(rcanon.end(), lc.begin(), lc.end());
+      rup.resize((G + next) / 8, -1);
+      for (const auto& u : lup) rup[(G + u.first) / 8] = u.second;
+      G += next;
+      regs.push_back(R);
+    }
+  }
+  ctx->h_regions = regs;
+  ctx->reg_G = G;
+  ctx->reg_maxn = maxn;
+  rt_status s;
+  if ((s = upload(ctx, ctx->d_regions, regs)) || (s = upload(ctx, ctx->d_rword, rword)) ||
+      (s = upload(ctx, ctx->d_rup, rup)) || (s = upload(ctx, ctx->d_rcanon, rcanon)) ||
+      (s = upload(ctx, ctx->d_root_region, root_region)))
+    return s;
+  ctx->reg_cap = cap;
+  ctx->reg_dirty = false;
   return RT_OK;
 }
 
@@ -288,7 +436,11 @@ rt_status rt_destroy(rt_ctx* ctx) {
                     &ctx->out_lamnode, &ctx->out_esc, &ctx->e_total, &ctx->cdf_lum, &ctx->cdf_q,
                     &ctx->cdf_qpre, &ctx->lmax, &ctx->scan_tmp, &ctx->tmp_in, &ctx->tmp_out,
                     &ctx->tmp_out2, &ctx->view, &ctx->lamidx, &ctx->it_astars, &ctx->it_adust,
-                    &ctx->it_sum, &ctx->it_told, &ctx->it_crit};
+                    &ctx->it_sum, &ctx->it_told, &ctx->it_crit, &ctx->d_regions, &ctx->d_rword,
+                    &ctx->d_rup, &ctx->d_rcanon, &ctx->d_root_region, &ctx->q_rec[0], &ctx->q_rec[1],
+                    &ctx->q_key[0], &ctx->q_key[1], &ctx->q_skey, &ctx->q_perm, &ctx->q_iota,
+                    &ctx->q_kstart, &ctx->q_kend, &ctx->q_items, &ctx->q_nitems, &ctx->q_counters,
+                    &ctx->q_sort_tmp};
   for (DevBuf* b : bufs) b->release();
   for (HostModel& m : ctx->models) {
     m.d_lc.release();
@@ -607,11 +759,17 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   if (!(o->rr_prob >= 0.0 && o->rr_prob < 1.0)) return fail(ctx, RT_EINVAL, "rr_prob must be in [0, 1)");
   if (o->max_events < 0 || o->max_events > 0x7fffffff) return fail(ctx, RT_EINVAL, "bad max_events");
   const int bs = o->block_size ? o->block_size : 256;
-  if (bs != 64 && bs != 128 && bs != 256 && !(bs == 512 && o->precision == RT_FP32_LOCAL))
+  if (bs != 64 && bs != 128 && bs != 256 && !(bs >= 512 && bs <= 1024 && o->precision == RT_FP32_LOCAL &&
+                                                 (bs == 512 || o->schedule == RT_SCHED_REGIONS)))
     return fail(ctx, RT_EINVAL, "block_size must be 64, 128, 256 (or 512 for the FP32 form)");
   if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return fail(ctx, RT_EINVAL, "bad blocks_per_cu");
   if (!(o->refill_threshold >= 0.0f && o->refill_threshold <= 1.0f))
     return fail(ctx, RT_EINVAL, "refill_threshold must be in [0, 1]");
+  if (o->schedule != RT_SCHED_REGIONS && o->schedule != RT_SCHED_GLOBAL)
+    return fail(ctx, RT_EINVAL, "schedule must be RT_SCHED_REGIONS or RT_SCHED_GLOBAL");
+  if (o->precision == RT_FP32_LOCAL && o->schedule == RT_SCHED_REGIONS && o->block_size &&
+      o->block_size != 256 && o->block_size != 512 && o->block_size != 1024)
+    return fail(ctx, RT_EINVAL, "the region schedule needs block_size 256, 512 or 1024");
   if (o->rec_stride < 0 || (o->rec_stride > 0 && !o->records))
     return fail(ctx, RT_EINVAL, "records needed when rec_stride > 0");
   for (int s = 0; s < n_src; ++s) {
@@ -714,6 +872,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
       J.alb32 = (float)h.alb[i];
       J.g32 = (float)h.g[i];
       J.acc_off = (n_slots > 1 ? (int64_t)i : 0) * stride;
+      J.slot = n_slots > 1 ? i : 0;
       J.rec_base = rec_base;
       if (o->rec_stride > 0) rec_base += (int64_t)((N + o->rec_stride - 1) / o->rec_stride);
       if (S.kind == RT_SRC_DUST) {
@@ -768,8 +927,113 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   p.leaf_coord = ctx->d_leaf_coord.as<int32_t>();
   p.leaf_level = ctx->d_leaf_level.as<uint8_t>();
 
+  const bool regions = fp32 && o->schedule == RT_SCHED_REGIONS;
+  int reg_lds = 0, reg_per_cu = 0;
+  if (regions) {
+    // LDS per block: node words + accumulators (4 + 4 B per node) + parent links (4 B per oct)
+    reg_per_cu = o->blocks_per_cu ? o->blocks_per_cu : (bs == 256 ? 2 : 1);
+    const int budget = 160 * 1024 / reg_per_cu - 4 * 1024;  // leave room for the static LDS
+    int32_t cap = (int32_t)((budget * 8 / 68) & ~7);
+    if (cap < 64) return fail(ctx, RT_EINVAL, "too many blocks per CU for the region schedule");
+    reg_lds = 8 * cap + 4 * (cap / 8);
+    if (rt_status e = build_regions(ctx, cap)) return e;
+    HIPCHK(attr_blk_pass(bs, reg_lds));
+    HIPCHK(ctx->acc.ensure((size_t)n_slots * ctx->reg_G * 4));
+    HIPCHK(hipMemsetAsync(ctx->acc.p, 0, (size_t)n_slots * ctx->reg_G * 4, ctx->stream));
+  }
   HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
-  if (start > 0) {
+  if (start > 0 && regions) {
+    const int n_regions = (int)ctx->h_regions.size();
+    const int64_t n_keys = (int64_t)n_slots * n_regions;
+    int end_bit = 1;
+    while ((int64_t(1) << end_bit) < n_keys) ++end_bit;
+    const int64_t capq = std::min<int64_t>(int64_t(1) << 25, std::max<int64_t>((int64_t)start, 4096));
+    const int64_t batch = std::min<int64_t>(int64_t(1) << 23, capq);
+    const int32_t chunk = 16 * bs;
+    if (ctx->q_capacity < capq) {
+      for (int k = 0; k < 2; ++k) {
+        HIPCHK(ctx->q_rec[k].ensure(sizeof(PRec) * capq));
+        HIPCHK(ctx->q_key[k].ensure(4 * capq));
+      }
+      HIPCHK(ctx->q_skey.ensure(4 * capq));
+      HIPCHK(ctx->q_perm.ensure(4 * capq));
+      HIPCHK(ctx->q_iota.ensure(4 * capq));
+      ctx->q_capacity = capq;
+    }
+    HIPCHK(ctx->q_kstart.ensure(4 * n_keys));
+    HIPCHK(ctx->q_kend.ensure(4 * n_keys));
+    HIPCHK(ctx->q_items.ensure(sizeof(WorkItem) * (capq / chunk + n_keys + 1)));
+    HIPCHK(ctx->q_nitems.ensure(16));
+    HIPCHK(ctx->q_counters.ensure(16));
+    HIPCHK(hipMemsetAsync(ctx->q_counters.p, 0, 16, ctx->stream));
+    size_t sort_bytes = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, ctx->q_key[0].as<uint32_t>(),
+                                              ctx->q_skey.as<uint32_t>(), ctx->q_iota.as<uint32_t>(),
+                                              ctx->q_perm.as<uint32_t>(), (int)capq, 0, end_bit, ctx->stream));
+    HIPCHK(ctx->q_sort_tmp.ensure(sort_bytes));
+    BlkParams b;
+    std::memset(&b, 0, sizeof b);
+    b.t = p;
+    b.t.acc32 = nullptr;
+    b.regions = ctx->d_regions.as<RegionDev>();
+    b.n_regions = n_regions;
+    b.cap = ctx->reg_cap;
+    b.rword = ctx->d_rword.as<int32_t>();
+    b.rup = ctx->d_rup.as<int32_t>();
+    b.rcanon = ctx->d_rcanon.as<int32_t>();
+    b.root_region = ctx->d_root_region.as<int32_t>();
+    b.accb = ctx->acc.as<float>();
+    b.accb_stride = ctx->reg_G;
+    b.items = ctx->q_items.as<WorkItem>();
+    b.n_items = ctx->q_nitems.as<uint32_t>();
+    b.item_counter = ctx->q_nitems.as<uint32_t>() + 1;
+    b.n_slots_key = n_slots;
+    b.chunk = chunk;
+    unsigned long long* counters = ctx->q_counters.as<unsigned long long>();
+    int in = 0;
+    uint64_t in_count = 0, emitted = 0;
+    int64_t sweeps = 0;
+    for (;;) {
+      if (emitted < start) {
+        const uint64_t n_emit = std::min<uint64_t>({(uint64_t)batch, (uint64_t)capq - in_count, start - emitted});
+        if (n_emit > 0) {
+          b.u_out = ctx->q_rec[in].as<PRec>();
+          b.u_key = ctx->q_key[in].as<uint32_t>();
+          b.u_count = counters + in;
+          HIPCHK(launch_blk_emit(b, emitted, emitted + n_emit, ctx->stream));
+          emitted += n_emit;
+          in_count += n_emit;
+        }
+      }
+      if (in_count == 0) {
+        if (emitted >= start) break;
+        continue;
+      }
+      const int out_b = 1 - in;
+      HIPCHK(launch_blk_iota((uint32_t)in_count, ctx->q_iota.as<uint32_t>(), ctx->stream));
+      HIPCHK(hipcub::DeviceRadixSort::SortPairs(ctx->q_sort_tmp.p, sort_bytes, ctx->q_key[in].as<uint32_t>(),
+                                                ctx->q_skey.as<uint32_t>(), ctx->q_iota.as<uint32_t>(),
+                                                ctx->q_perm.as<uint32_t>(), (int)in_count, 0, end_bit,
+                                                ctx->stream));
+      HIPCHK(launch_blk_items(ctx->q_skey.as<uint32_t>(), (uint32_t)in_count, (int32_t)n_keys, n_regions, chunk,
+                              ctx->q_kstart.as<int32_t>(), ctx->q_kend.as<int32_t>(), ctx->q_items.as<WorkItem>(),
+                              ctx->q_nitems.as<uint32_t>(), ctx->stream));
+      HIPCHK(hipMemsetAsync(counters + out_b, 0, 8, ctx->stream));
+      HIPCHK(hipMemsetAsync(ctx->q_nitems.as<uint32_t>() + 1, 0, 4, ctx->stream));
+      b.q_in = ctx->q_rec[in].as<PRec>();
+      b.q_perm = ctx->q_perm.as<uint32_t>();
+      b.u_out = ctx->q_rec[out_b].as<PRec>();
+      b.u_key = ctx->q_key[out_b].as<uint32_t>();
+      b.u_count = counters + out_b;
+      HIPCHK(launch_blk_pass(b, ctx->n_cu * reg_per_cu, bs, reg_lds, ctx->stream));
+      unsigned long long nc = 0;
+      HIPCHK(hipMemcpyAsync(&nc, counters + out_b, 8, hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      in_count = nc;
+      in = out_b;
+      if (++sweeps > 2000000) return fail(ctx, RT_EDEVICE, "region schedule did not drain");
+    }
+  } else if (start > 0) {
     if (fp32) {
       int per_cu = o->blocks_per_cu;
       if (per_cu == 0) {
@@ -783,14 +1047,21 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     }
   }
   HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
-  for (size_t m = 0; m < ctx->models.size(); ++m) {
-    const HostModel& h = ctx->models[m];
-    const int ns = n_slots > 1 ? std::max(h.nl, 1) : 1;
-    HIPCHK(launch_reduce_model(ctx->d_models.as<ModelDev>(), (int)m, h.n_nodes,
-                               fp32 ? ctx->acc.as<float>() : nullptr,
-                               fp32 ? nullptr : ctx->acc.as<double>(), stride, ns, out.e_node,
-                               n_slots > 1 ? out.e_lamnode : nullptr, ctx->e_total.as<double>(),
-                               ctx->stream));
+  if (regions) {
+    HIPCHK(launch_blk_reduce(ctx->d_models.as<ModelDev>(), ctx->d_regions.as<RegionDev>(),
+                             (int)ctx->h_regions.size(), ctx->reg_maxn, ctx->d_rcanon.as<int32_t>(),
+                             ctx->acc.as<float>(), ctx->reg_G, n_slots, out.e_node,
+                             n_slots > 1 ? out.e_lamnode : nullptr, ctx->e_total.as<double>(), ctx->stream));
+  } else {
+    for (size_t m = 0; m < ctx->models.size(); ++m) {
+      const HostModel& h = ctx->models[m];
+      const int ns = n_slots > 1 ? std::max(h.nl, 1) : 1;
+      HIPCHK(launch_reduce_model(ctx->d_models.as<ModelDev>(), (int)m, h.n_nodes,
+                                 fp32 ? ctx->acc.as<float>() : nullptr,
+                                 fp32 ? nullptr : ctx->acc.as<double>(), stride, ns, out.e_node,
+                                 n_slots > 1 ? out.e_lamnode : nullptr, ctx->e_total.as<double>(),
+                                 ctx->stream));
+    }
   }
   HIPCHK(hipEventRecord(ctx->ev2, ctx->stream));
   if (rec_copy)

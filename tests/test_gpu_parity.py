@@ -70,7 +70,7 @@ def test_locate_bit_exact(torch, seed, root, levels):
     assert np.array_equal(ng.cpu().numpy(), no)
 
 
-GPU_ONLY = ("block_size", "blocks_per_cu", "refill_threshold")
+GPU_ONLY = ("block_size", "blocks_per_cu", "refill_threshold", "schedule")
 
 
 def _trace_pair(torch, w, precision, **kw):
@@ -126,12 +126,16 @@ def _mc_noise(w, seed_b):
     return ea, rel_rms(eb, ea) / math.sqrt(2.0)
 
 
-@pytest.mark.parametrize("block,thr", [(256, 0.0), (64, 0.25), (512, 0.75)])
-def test_trace_fp32_local_c1(torch, block, thr):
-    """FP32-local persistent form: relative RMS error <= 1e-3 and below the MC noise."""
+@pytest.mark.parametrize("sched,block,thr,per_cu", [
+    (rt.SCHED_GLOBAL, 256, 0.0, 0), (rt.SCHED_GLOBAL, 64, 0.25, 0), (rt.SCHED_GLOBAL, 512, 0.75, 0),
+    (rt.SCHED_REGIONS, 256, 0.0, 0), (rt.SCHED_REGIONS, 512, 0.5, 0), (rt.SCHED_REGIONS, 256, 0.5, 16)])
+def test_trace_fp32_local_c1(torch, sched, block, thr, per_cu):
+    """FP32-local forms (one global queue; region by region, including small regions that
+    force many sweeps): relative RMS error <= 1e-3 and below the MC noise."""
     w = gen.c1("A")
     ora, eo, esco, sto, reco, r = _trace_pair(torch, w, rt.FP32_LOCAL, block_size=block,
-                                              refill_threshold=thr)
+                                              refill_threshold=thr, schedule=sched,
+                                              blocks_per_cu=per_cu)
     eg = r["e_abs_node"].cpu().numpy()
     _, noise = _mc_noise(w, w.seed + 1000)
     err = rel_rms(eg, eo)
@@ -336,3 +340,44 @@ def test_errors_leave_context_usable(torch):
         ctx.build_tree(gen.TreeDesc(2, 2, 2, 1.0, np.ones(8), [np.array([3, 1])], [np.ones(16)]))
     r = ctx.trace_packets(w.sources, seed=1)
     assert r["stats"]["packets"] == 100
+
+
+def test_region_overflow_and_records(torch):
+    """Region schedule where single root-cell subtrees exceed the LDS capacity (part of the
+    region stays in global memory): deposits, fates and crossing counts against the oracle."""
+    tree = gen.uniform_refined_tree((2, 2, 2), 3, rho=0.5, cell_cm=0.5)
+    rng = np.random.default_rng(3)
+    tree.child_rho[2] = rng.uniform(0.1, 2.0, len(tree.child_rho[2]))
+    dust = gen.Dust(np.array([1.0]), np.array([1.0]), np.array([0.5]), np.array([0.4]))
+    src = [gen.Source(gen.SRC_BACKGROUND, 0, power=np.array([1.0]), packets=40000),
+           gen.Source(gen.SRC_POINT, 0, pos=(1.01, 0.97, 1.03), power=np.array([2.0]), packets=40000)]
+    ora = oracle.Model(tree, dust)
+    eo, esco, sto, reco = ora.trace(src, seed=5, rec_stride=1)
+    ctx = new_ctx(torch)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    r = ctx.trace_packets(src, seed=5, precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS,
+                          blocks_per_cu=32, rec_stride=1)
+    eg = r["e_abs_node"].cpu().numpy()
+    assert rel_rms(eg, eo) <= 1e-3
+    rg = r["records"]
+    assert r["stats"]["packets"] == 80000 and r["stats"]["truncated"] == 0
+    same = np.mean(rg["crossings"] == reco["crossings"])
+    assert same > 0.99, same
+    assert np.array_equal(rg["birth"], reco["birth"])
+
+
+def test_region_and_global_schedules_agree(torch):
+    """The two FP32-local schedules follow the same arithmetic: per-node results agree far
+    below the Monte Carlo noise, and the crossing counts are equal."""
+    w = gen.c2(n_root=24, max_level=3, n_lambda=6, packets=20000)
+    ctx = new_ctx(torch)
+    m = ctx.build_tree(w.trees[0])
+    ctx.set_dust(m, w.dusts[0])
+    kw = dict(seed=w.seed, precision=rt.FP32_LOCAL, rr_threshold=w.rr_threshold, rr_prob=w.rr_prob)
+    a = ctx.trace_packets(w.sources, schedule=rt.SCHED_GLOBAL, **kw)
+    b = ctx.trace_packets(w.sources, schedule=rt.SCHED_REGIONS, blocks_per_cu=8, **kw)
+    ea, eb = a["e_abs_node"].cpu().numpy(), b["e_abs_node"].cpu().numpy()
+    assert rel_rms(eb, ea) < 1e-5
+    assert a["stats"]["crossings"] == b["stats"]["crossings"]
+    assert a["stats"]["scatterings"] == b["stats"]["scatterings"]
