@@ -35,7 +35,12 @@ def parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--refill", type=float, default=0.0)
+    ap.add_argument("--schedule", type=int, default=0, help="0: regions, 1: one global queue")
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--trace-only", action="store_true", help="time only the transport step")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 256 MiB device-to-device (reference for traffic counters)")
     return ap.parse_args()
 
 
@@ -49,6 +54,13 @@ def main():
     import gen
     import paper_1206_3710_amd as rt
 
+    if a.copy_calibration:
+        # 4 GiB device-to-device copy: reads and writes exceed every cache level
+        src_t = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
     w = gen.c2(packets=a.packets)
     tree, dust = w.trees[0], w.dusts[0]
     ctx = rt.Context(0)
@@ -58,9 +70,11 @@ def main():
     lam_all = list(range(nl))
     kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob, block_size=a.block,
               blocks_per_cu=a.blocks_per_cu, refill_threshold=a.refill)
+    kw32 = dict(kw, schedule=a.schedule, chunk_packets=a.chunk, batch_packets=a.batch)
 
     def step(precision, it):
-        r = ctx.trace_packets(w.sources, seed=w.seed, iteration=it, precision=precision, **kw)
+        r = ctx.trace_packets(w.sources, seed=w.seed, iteration=it, precision=precision,
+                              **(kw32 if precision == rt.FP32_LOCAL else kw))
         t = time.perf_counter()
         out = {"stats": r["stats"]}
         if not a.trace_only:

@@ -152,6 +152,9 @@ typedef struct {
                                region by region with LDS-resident nodes and accumulators;
                                RT_SCHED_GLOBAL runs one persistent kernel over the whole tree
                                with global atomics */
+  int32_t chunk_packets;    /* region schedule: packets per work item; 0 = 16 * block_size */
+  int32_t pad1;
+  int64_t batch_packets;    /* region schedule: packets emitted per sweep; 0 = 2^23 */
   int64_t rec_stride;       /* > 0: record packet j of each (source, wavelength) when
                                j % rec_stride == 0 */
   rt_record* records;       /* host or device; job-major: job (source-major, then wavelength)

@@ -35,7 +35,12 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 // emission into the queue
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void blk_emit_kernel(const BlkParams b, uint64_t g0, uint64_t g1) {
+  __shared__ uint64_t s_start[RT_JOBS_LDS];
   const TraceParams& p = b.t;
+  const bool jobs_lds = p.n_jobs <= RT_JOBS_LDS;
+  if (jobs_lds)
+    for (int i = threadIdx.x; i < p.n_jobs; i += 256) s_start[i] = p.jobs[i].start;
+  __syncthreads();
   const uint64_t gid = g0 + (uint64_t)blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool have = gid < g1;
@@ -47,7 +52,8 @@ __global__ __launch_bounds__(256) void blk_emit_kernel(const BlkParams b, uint64
     int lo = 0, hi = p.n_jobs - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (p.jobs[mid].start <= gid) lo = mid;
+      const uint64_t st = jobs_lds ? s_start[mid] : p.jobs[mid].start;
+      if (st <= gid) lo = mid;
       else hi = mid - 1;
     }
     const JobDev& J = p.jobs[lo];
@@ -220,6 +226,327 @@ __device__ __forceinline__ void land(WF word_of, int ax, int sg, int L, int32_t 
   raw = r;
 }
 
+// One work item: follow every queued packet of the item through its region.  FITS: the whole
+// region is in LDS (pure LDS lookups and deposits); otherwise nodes past the LDS capacity are
+// read and deposited in global memory.
+template <bool FITS>
+__device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it, const RegionDev& R,
+                                         const ModelDev& md, const Dims D, int nloc, int nup,
+                                         int32_t* s_word, float* s_acc, int32_t* s_up, uint32_t* s_next,
+                                         double* s_esc, double* s_misc, bool esc_lds, int lane,
+                                         unsigned long long& c_cross, uint32_t& c_scat, uint32_t& c_kill,
+                                         uint32_t& c_trunc) {
+  const TraceParams& p = b.t;
+  const float rr_thr = (float)p.rr_thr, rr_p = (float)p.rr_p;
+  const float rr_gain = rr_p > 0.0f ? 1.0f / (1.0f - rr_p) : 1.0f;
+  const int bx = R.hi[0] - R.lo[0], by = R.hi[1] - R.lo[1];
+  float* __restrict__ gacc = b.accb + (int64_t)it.slot * b.accb_stride + R.gbase;
+  const int32_t* __restrict__ gword = b.rword + R.gbase;
+  const int32_t* __restrict__ gup = b.rup + (R.gbase >> 3);
+  auto word_of = [&](int32_t l) -> int32_t {
+    if (FITS) return s_word[l];
+    return l < nloc ? s_word[l] : gword[l];
+  };
+  auto up_of = [&](int32_t l) -> int32_t {
+    if (FITS) return s_up[l >> 3];
+    return (l >> 3) < nup ? s_up[l >> 3] : gup[l >> 3];
+  };
+  auto deposit = [&](int32_t l, float v) {
+    if (FITS || l < nloc) atomicAdd(&s_acc[l], v);
+    else unsafeAtomicAdd(gacc + l, v);
+  };
+  int state = B_EMPTY;
+  int32_t node = 0, lev = 0, I0 = 0, I1 = 0, I2 = 0, birth = 0, job = 0;
+  float x0 = 0.f, x1 = 0.f, x2 = 0.f, d0 = 0.f, d1 = 0.f, d2 = 1.f;
+  float r0 = INFINITY, r1 = INFINITY, r2 = 1.f, w = 0.f, w0 = 0.f, tau = 0.f, rho = 0.f;
+  double O0 = 0.0, O1 = 0.0, O2 = 0.0;
+  uint32_t pid = 0, ev = 0, ncross = 0, stream = 0;
+  float kc = 0.f, alb = 0.f, g = 0.f;
+  int esc_slot = 0;
+  int32_t xax = 0, xsg = 0;
+  uint32_t xkey = 0;
+
+  for (;;) {
+    // ---------------- refill from this item's queue ----------------
+    const uint64_t need = __ballot(state == B_EMPTY);
+    if (need) {
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(s_next, (uint32_t)__popcll(need));
+      base = __shfl(base, 0, 64);
+      if (state == B_EMPTY) {
+        const uint32_t idx = base + lane_rank(need);
+        if (idx >= it.count) {
+          state = B_DONE;
+        } else {
+          const PRec rec = b.q_in[b.q_perm[it.start + idx]];
+          job = rec.job;
+          const JobDev& J = p.jobs[job];
+          kc = J.kc32;
+          alb = J.alb32;
+          g = J.g32;
+          stream = J.stream;
+          esc_slot = J.esc_slot;
+          x0 = rec.x[0];
+          x1 = rec.x[1];
+          x2 = rec.x[2];
+          d0 = rec.d[0];
+          d1 = rec.d[1];
+          d2 = rec.d[2];
+          r0 = rcp_or_inf(d0);
+          r1 = rcp_or_inf(d1);
+          r2 = rcp_or_inf(d2);
+          w = rec.w;
+          w0 = rec.w0;
+          tau = rec.tau;
+          O0 = rec.O[0];
+          O1 = rec.O[1];
+          O2 = rec.O[2];
+          pid = rec.pid;
+          ev = rec.ev;
+          ncross = rec.ncross;
+          birth = rec.birth;
+          const int L = rec.lev;
+          int32_t J0 = rec.I[0], J1 = rec.I[1], J2 = rec.I[2];
+          int ax = 0, sg = 1;
+          if (rec.flag) {
+            ax = rec.ax;
+            sg = rec.sg ? -1 : 1;
+            if (ax == 0) J0 += sg;
+            else if (ax == 1) J1 += sg;
+            else J2 += sg;
+          }
+          const int32_t R0 = J0 >> L, R1 = J1 >> L, R2 = J2 >> L;
+          const int32_t rootl = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
+          int32_t raw = 0;
+          const bool misplaced = R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] || R1 >= R.hi[1] ||
+                                 R2 < R.lo[2] || R2 >= R.hi[2];
+          if (misplaced) {
+            // a record queued for the wrong region (never expected): retire it as truncated
+            ++c_trunc;
+            atomicAdd(&s_misc[2], (double)w);
+            c_cross += ncross;
+          } else if (rec.flag) {
+            land(word_of, ax, sg, L, rec.I[0], rec.I[1], rec.I[2], J0, J1, J2, rootl, 0, x0, x1, x2, O0,
+                 O1, O2, d0, d1, d2, node, lev, I0, I1, I2, raw);
+            ++ncross;
+          } else {
+            // birth: walk down to the birth leaf along its coordinates
+            int32_t cur = rootl;
+            int32_t rr = word_of(cur);
+            for (int l = 1; l <= L && child_of(rr) >= 0; ++l) {
+              const int sh = L - l;
+              cur = child_of(rr) + (((J0 >> sh) & 1) | (((J1 >> sh) & 1) << 1) | (((J2 >> sh) & 1) << 2));
+              rr = word_of(cur);
+            }
+            node = cur;
+            lev = L;
+            I0 = J0;
+            I1 = J1;
+            I2 = J2;
+            raw = rr;
+          }
+          rho = __int_as_float(raw);
+          state = misplaced ? B_EMPTY : B_CROSS;
+        }
+      }
+    }
+    const uint64_t live = __ballot(state != B_DONE);
+    if (!live) break;
+    const int want = max(1, (int)(p.refill_thr * (float)__popcll(live)));
+
+    // ---------------- crossing phase (LDS lookups, LDS deposits) ----------------
+    for (;;) {
+      if (state == B_CROSS) {
+        const float se = kc * rho * pow2f(-lev);
+        const float ss = alb * se;
+        const float sa = se - ss;
+        const float tx = d0 != 0.0f ? (d0 > 0.0f ? 1.0f - x0 : -x0) * r0 : INFINITY;
+        const float ty = d1 != 0.0f ? (d1 > 0.0f ? 1.0f - x1 : -x1) * r1 : INFINITY;
+        const float tz = d2 != 0.0f ? (d2 > 0.0f ? 1.0f - x2 : -x2) * r2 : INFINITY;
+        int ax;
+        float texit;
+        if (tx <= ty && tx <= tz) {
+          ax = 0;
+          texit = tx;
+        } else if (ty <= tz) {
+          ax = 1;
+          texit = ty;
+        } else {
+          ax = 2;
+          texit = tz;
+        }
+        const float tsc = ss * texit;
+        const bool event = ss > 0.0f && tau <= tsc;
+        float s;
+        if (event) {
+          s = tau / ss;
+        } else {
+          s = texit;
+          tau -= tsc;
+        }
+        const float de = w * (-expm1f(-(sa * s)));
+        if (de > 0.0f) {
+          deposit(node, de);
+          w -= de;
+        }
+        x0 = clamp01(fmaf(s, d0, x0));
+        x1 = clamp01(fmaf(s, d1, x1));
+        x2 = clamp01(fmaf(s, d2, x2));
+        if (event) {
+          state = B_EVENT;
+        } else {
+          const int sg = sel3(ax, d0, d1, d2) > 0.0f ? 1 : -1;
+          const int L = lev;
+          const int32_t Ia = sel3(ax, I0, I1, I2);
+          const int32_t Ja = Ia + sg;
+          if (Ja < 0 || Ja >= (D.na(ax) << L)) {
+            // escape through the root boundary
+            if (esc_lds) atomicAdd(&s_esc[esc_slot], (double)w);
+            else unsafeAtomicAdd(p.esc + esc_slot, (double)w);
+            if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
+              const JobDev& J = p.jobs[job];
+              rt_record rc{0u, ncross, ev, 0u, -1, canon_of(md, birth), (double)w};
+              p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
+            }
+            c_cross += ncross;
+            state = B_EMPTY;
+          } else {
+            int32_t cur = node;
+            int l = L;
+            while (l > 0 && ((Ja >> (L - l + 1)) != (Ia >> (L - l + 1)))) {
+              cur = up_of(cur);
+              --l;
+            }
+            const int32_t J0 = ax == 0 ? Ja : I0, J1 = ax == 1 ? Ja : I1, J2 = ax == 2 ? Ja : I2;
+            bool leave = false;
+            if (l == 0) {
+              const int32_t R0 = J0 >> L, R1 = J1 >> L, R2 = J2 >> L;
+              if (R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] || R1 >= R.hi[1] || R2 < R.lo[2] ||
+                  R2 >= R.hi[2]) {
+                leave = true;
+                xax = ax;
+                xsg = sg;
+                xkey = (uint32_t)it.slot * (uint32_t)b.n_regions + (uint32_t)b.root_region[D.root(R0, R1, R2)];
+                state = B_EXIT;
+              } else {
+                cur = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
+              }
+            } else {
+              cur += sg > 0 ? (1 << ax) : -(1 << ax);
+            }
+            if (!leave) {
+              int32_t raw;
+              land(word_of, ax, sg, L, I0, I1, I2, J0, J1, J2, cur, l, x0, x1, x2, O0, O1, O2, d0, d1, d2,
+                   node, lev, I0, I1, I2, raw);
+              rho = __int_as_float(raw);
+              if (++ncross >= kMaxCrossings) {
+                ev = (uint32_t)p.max_events;
+                state = B_EVENT;
+              }
+            }
+          }
+        }
+      }
+      if (__popcll(__ballot(state == B_CROSS)) < want) break;
+    }
+
+    // ---------------- packets leaving the region: append to the next queue ----------------
+    const uint64_t ex = __ballot(state == B_EXIT);
+    if (ex) {
+      uint32_t blo = 0, bhi = 0;
+      if (lane == 0) {
+        const unsigned long long base = atomicAdd(b.u_count, (unsigned long long)__popcll(ex));
+        blo = (uint32_t)base;
+        bhi = (uint32_t)(base >> 32);
+      }
+      blo = __shfl(blo, 0, 64);
+      bhi = __shfl(bhi, 0, 64);
+      if (state == B_EXIT) {
+        const uint64_t idx = (((uint64_t)bhi << 32) | blo) + lane_rank(ex);
+        PRec rc;
+        rc.I[0] = I0;
+        rc.I[1] = I1;
+        rc.I[2] = I2;
+        rc.lev = (uint8_t)lev;
+        rc.ax = (uint8_t)xax;
+        rc.sg = xsg > 0 ? 0 : 1;
+        rc.flag = 1;
+        rc.x[0] = x0;
+        rc.x[1] = x1;
+        rc.x[2] = x2;
+        rc.d[0] = d0;
+        rc.d[1] = d1;
+        rc.d[2] = d2;
+        rc.w = w;
+        rc.w0 = w0;
+        rc.tau = tau;
+        rc.birth = birth;
+        rc.O[0] = O0;
+        rc.O[1] = O1;
+        rc.O[2] = O2;
+        rc.pid = pid;
+        rc.job = job;
+        rc.ev = ev;
+        rc.ncross = ncross;
+        b.u_out[idx] = rc;
+        b.u_key[idx] = xkey;
+        state = B_EMPTY;
+      }
+    }
+
+    // ---------------- scattering events, serviced together ----------------
+    if (state == B_EVENT) {
+      ++ev;
+      if ((int64_t)ev > p.max_events) {
+        ++c_trunc;
+        atomicAdd(&s_misc[2], (double)w);
+        if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
+          const JobDev& J = p.jobs[job];
+          rt_record rc{2u, ncross, ev, 0u, (int64_t)b.rcanon[R.gbase + node], canon_of(md, birth), (double)w};
+          p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
+        }
+        c_cross += ncross;
+        state = B_EMPTY;
+      } else {
+        ++c_scat;
+        const double h = ldexp(1.0, -lev);
+        O0 = ((double)I0 + (double)x0) * h;
+        O1 = ((double)I1 + (double)x1) * h;
+        O2 = ((double)I2 + (double)x2) * h;
+        const uint4 xr = philox(pid, stream, ev, 0u, p.key0, p.key1);
+        bool killed = false;
+        if (rr_p > 0.0f && w < rr_thr * w0) {
+          if (unif32(xr.x) < rr_p) {
+            ++c_kill;
+            atomicAdd(&s_misc[0], (double)w);
+            if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
+              const JobDev& J = p.jobs[job];
+              rt_record rc{1u, ncross, ev, 0u, (int64_t)b.rcanon[R.gbase + node], canon_of(md, birth), (double)w};
+              p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
+            }
+            c_cross += ncross;
+            state = B_EMPTY;
+            killed = true;
+          } else {
+            const float nw = w * rr_gain;
+            atomicAdd(&s_misc[1], (double)nw - (double)w);
+            w = nw;
+          }
+        }
+        if (!killed) {
+          const float mu = hg_mu32(g, unif32(xr.y));
+          rotate32(d0, d1, d2, mu, kTwoPiF * unif32(xr.z));
+          r0 = rcp_or_inf(d0);
+          r1 = rcp_or_inf(d1);
+          r2 = rcp_or_inf(d2);
+          tau = -logf(unif32(xr.w));
+          state = B_CROSS;
+        }
+      }
+    }
+  }
+}
+
 template <int BS>
 __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -236,8 +563,6 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   const bool esc_lds = p.n_esc <= kEscLds;
   for (int i = tid; i < kEscLds; i += BS) s_esc[i] = 0.0;
   if (tid < 4) s_misc[tid] = 0.0;
-  const float rr_thr = (float)p.rr_thr, rr_p = (float)p.rr_p;
-  const float rr_gain = rr_p > 0.0f ? 1.0f / (1.0f - rr_p) : 1.0f;
   unsigned long long c_cross = 0;
   uint32_t c_scat = 0, c_kill = 0, c_trunc = 0;
 
@@ -251,7 +576,6 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     const RegionDev R = b.regions[it.region];
     const ModelDev& md = p.models[R.model];
     const Dims D = dims_of(md);
-    const int bx = R.hi[0] - R.lo[0], by = R.hi[1] - R.lo[1];
     const int nloc = min(R.n, cap);
     const int nup = (nloc + 7) >> 3;
     for (int i = tid; i < nloc; i += BS) {
@@ -261,303 +585,13 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     for (int i = tid; i < nup; i += BS) s_up[i] = b.rup[(R.gbase >> 3) + i];
     if (tid == 0) s_next = 0;
     __syncthreads();
+    if (R.n <= cap)
+      run_item<true>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
+                     c_cross, c_scat, c_kill, c_trunc);
+    else
+      run_item<false>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
+                      c_cross, c_scat, c_kill, c_trunc);
     float* __restrict__ gacc = b.accb + (int64_t)it.slot * b.accb_stride + R.gbase;
-    const int32_t* __restrict__ gword = b.rword + R.gbase;
-    const int32_t* __restrict__ gup = b.rup + (R.gbase >> 3);
-    auto word_of = [&](int32_t l) -> int32_t { return l < nloc ? s_word[l] : gword[l]; };
-    auto up_of = [&](int32_t l) -> int32_t { return (l >> 3) < nup ? s_up[l >> 3] : gup[l >> 3]; };
-
-    int state = B_EMPTY;
-    int32_t node = 0, lev = 0, I0 = 0, I1 = 0, I2 = 0, birth = 0, job = 0;
-    float x0 = 0.f, x1 = 0.f, x2 = 0.f, d0 = 0.f, d1 = 0.f, d2 = 1.f;
-    float r0 = INFINITY, r1 = INFINITY, r2 = 1.f, w = 0.f, w0 = 0.f, tau = 0.f, rho = 0.f;
-    double O0 = 0.0, O1 = 0.0, O2 = 0.0;
-    uint32_t pid = 0, ev = 0, ncross = 0, stream = 0;
-    float kc = 0.f, alb = 0.f, g = 0.f;
-    int esc_slot = 0;
-    int32_t xax = 0, xsg = 0;
-    uint32_t xkey = 0;
-
-    for (;;) {
-      // ---------------- refill from this item's queue ----------------
-      const uint64_t need = __ballot(state == B_EMPTY);
-      if (need) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&s_next, (uint32_t)__popcll(need));
-        base = __shfl(base, 0, 64);
-        if (state == B_EMPTY) {
-          const uint32_t idx = base + lane_rank(need);
-          if (idx >= it.count) {
-            state = B_DONE;
-          } else {
-            const PRec rec = b.q_in[b.q_perm[it.start + idx]];
-            job = rec.job;
-            const JobDev& J = p.jobs[job];
-            kc = J.kc32;
-            alb = J.alb32;
-            g = J.g32;
-            stream = J.stream;
-            esc_slot = J.esc_slot;
-            x0 = rec.x[0];
-            x1 = rec.x[1];
-            x2 = rec.x[2];
-            d0 = rec.d[0];
-            d1 = rec.d[1];
-            d2 = rec.d[2];
-            r0 = rcp_or_inf(d0);
-            r1 = rcp_or_inf(d1);
-            r2 = rcp_or_inf(d2);
-            w = rec.w;
-            w0 = rec.w0;
-            tau = rec.tau;
-            O0 = rec.O[0];
-            O1 = rec.O[1];
-            O2 = rec.O[2];
-            pid = rec.pid;
-            ev = rec.ev;
-            ncross = rec.ncross;
-            birth = rec.birth;
-            const int L = rec.lev;
-            int32_t J0 = rec.I[0], J1 = rec.I[1], J2 = rec.I[2];
-            int ax = 0, sg = 1;
-            if (rec.flag) {
-              ax = rec.ax;
-              sg = rec.sg ? -1 : 1;
-              if (ax == 0) J0 += sg;
-              else if (ax == 1) J1 += sg;
-              else J2 += sg;
-            }
-            const int32_t R0 = J0 >> L, R1 = J1 >> L, R2 = J2 >> L;
-            const int32_t rootl = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
-            int32_t raw = 0;
-            const bool misplaced = R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] || R1 >= R.hi[1] ||
-                                   R2 < R.lo[2] || R2 >= R.hi[2];
-            if (misplaced) {
-              // a record queued for the wrong region (never expected): retire it as truncated
-              ++c_trunc;
-              atomicAdd(&s_misc[2], (double)w);
-              c_cross += ncross;
-            } else if (rec.flag) {
-              land(word_of, ax, sg, L, rec.I[0], rec.I[1], rec.I[2], J0, J1, J2, rootl, 0, x0, x1, x2, O0,
-                   O1, O2, d0, d1, d2, node, lev, I0, I1, I2, raw);
-              ++ncross;
-            } else {
-              // birth: walk down to the birth leaf along its coordinates
-              int32_t cur = rootl;
-              int32_t rr = word_of(cur);
-              for (int l = 1; l <= L && child_of(rr) >= 0; ++l) {
-                const int sh = L - l;
-                cur = child_of(rr) + (((J0 >> sh) & 1) | (((J1 >> sh) & 1) << 1) | (((J2 >> sh) & 1) << 2));
-                rr = word_of(cur);
-              }
-              node = cur;
-              lev = L;
-              I0 = J0;
-              I1 = J1;
-              I2 = J2;
-              raw = rr;
-            }
-            rho = __int_as_float(raw);
-            state = misplaced ? B_EMPTY : B_CROSS;
-          }
-        }
-      }
-      const uint64_t live = __ballot(state != B_DONE);
-      if (!live) break;
-      const int want = max(1, (int)(p.refill_thr * (float)__popcll(live)));
-
-      // ---------------- crossing phase (LDS lookups, LDS deposits) ----------------
-      for (;;) {
-        if (state == B_CROSS) {
-          const float se = kc * rho * pow2f(-lev);
-          const float ss = alb * se;
-          const float sa = se - ss;
-          const float tx = d0 != 0.0f ? (d0 > 0.0f ? 1.0f - x0 : -x0) * r0 : INFINITY;
-          const float ty = d1 != 0.0f ? (d1 > 0.0f ? 1.0f - x1 : -x1) * r1 : INFINITY;
-          const float tz = d2 != 0.0f ? (d2 > 0.0f ? 1.0f - x2 : -x2) * r2 : INFINITY;
-          int ax;
-          float texit;
-          if (tx <= ty && tx <= tz) {
-            ax = 0;
-            texit = tx;
-          } else if (ty <= tz) {
-            ax = 1;
-            texit = ty;
-          } else {
-            ax = 2;
-            texit = tz;
-          }
-          const float tsc = ss * texit;
-          const bool event = ss > 0.0f && tau <= tsc;
-          float s;
-          if (event) {
-            s = tau / ss;
-          } else {
-            s = texit;
-            tau -= tsc;
-          }
-          const float de = w * (-expm1f(-(sa * s)));
-          if (de > 0.0f) {
-            if (node < nloc) atomicAdd(&s_acc[node], de);
-            else unsafeAtomicAdd(gacc + node, de);
-            w -= de;
-          }
-          x0 = clamp01(fmaf(s, d0, x0));
-          x1 = clamp01(fmaf(s, d1, x1));
-          x2 = clamp01(fmaf(s, d2, x2));
-          if (event) {
-            state = B_EVENT;
-          } else {
-            const int sg = sel3(ax, d0, d1, d2) > 0.0f ? 1 : -1;
-            const int L = lev;
-            const int32_t Ia = sel3(ax, I0, I1, I2);
-            const int32_t Ja = Ia + sg;
-            if (Ja < 0 || Ja >= (D.na(ax) << L)) {
-              // escape through the root boundary
-              if (esc_lds) atomicAdd(&s_esc[esc_slot], (double)w);
-              else unsafeAtomicAdd(p.esc + esc_slot, (double)w);
-              if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
-                const JobDev& J = p.jobs[job];
-                rt_record rc{0u, ncross, ev, 0u, -1, canon_of(md, birth), (double)w};
-                p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
-              }
-              c_cross += ncross;
-              state = B_EMPTY;
-            } else {
-              int32_t cur = node;
-              int l = L;
-              while (l > 0 && ((Ja >> (L - l + 1)) != (Ia >> (L - l + 1)))) {
-                cur = up_of(cur);
-                --l;
-              }
-              const int32_t J0 = ax == 0 ? Ja : I0, J1 = ax == 1 ? Ja : I1, J2 = ax == 2 ? Ja : I2;
-              bool leave = false;
-              if (l == 0) {
-                const int32_t R0 = J0 >> L, R1 = J1 >> L, R2 = J2 >> L;
-                if (R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] || R1 >= R.hi[1] || R2 < R.lo[2] ||
-                    R2 >= R.hi[2]) {
-                  leave = true;
-                  xax = ax;
-                  xsg = sg;
-                  xkey = (uint32_t)it.slot * (uint32_t)b.n_regions + (uint32_t)b.root_region[D.root(R0, R1, R2)];
-                  state = B_EXIT;
-                } else {
-                  cur = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
-                }
-              } else {
-                cur += sg > 0 ? (1 << ax) : -(1 << ax);
-              }
-              if (!leave) {
-                int32_t raw;
-                land(word_of, ax, sg, L, I0, I1, I2, J0, J1, J2, cur, l, x0, x1, x2, O0, O1, O2, d0, d1, d2,
-                     node, lev, I0, I1, I2, raw);
-                rho = __int_as_float(raw);
-                if (++ncross >= kMaxCrossings) {
-                  ev = (uint32_t)p.max_events;
-                  state = B_EVENT;
-                }
-              }
-            }
-          }
-        }
-        if (__popcll(__ballot(state == B_CROSS)) < want) break;
-      }
-
-      // ---------------- packets leaving the region: append to the next queue ----------------
-      const uint64_t ex = __ballot(state == B_EXIT);
-      if (ex) {
-        uint32_t blo = 0, bhi = 0;
-        if (lane == 0) {
-          const unsigned long long base = atomicAdd(b.u_count, (unsigned long long)__popcll(ex));
-          blo = (uint32_t)base;
-          bhi = (uint32_t)(base >> 32);
-        }
-        blo = __shfl(blo, 0, 64);
-        bhi = __shfl(bhi, 0, 64);
-        if (state == B_EXIT) {
-          const uint64_t idx = (((uint64_t)bhi << 32) | blo) + lane_rank(ex);
-          PRec rc;
-          rc.I[0] = I0;
-          rc.I[1] = I1;
-          rc.I[2] = I2;
-          rc.lev = (uint8_t)lev;
-          rc.ax = (uint8_t)xax;
-          rc.sg = xsg > 0 ? 0 : 1;
-          rc.flag = 1;
-          rc.x[0] = x0;
-          rc.x[1] = x1;
-          rc.x[2] = x2;
-          rc.d[0] = d0;
-          rc.d[1] = d1;
-          rc.d[2] = d2;
-          rc.w = w;
-          rc.w0 = w0;
-          rc.tau = tau;
-          rc.birth = birth;
-          rc.O[0] = O0;
-          rc.O[1] = O1;
-          rc.O[2] = O2;
-          rc.pid = pid;
-          rc.job = job;
-          rc.ev = ev;
-          rc.ncross = ncross;
-          b.u_out[idx] = rc;
-          b.u_key[idx] = xkey;
-          state = B_EMPTY;
-        }
-      }
-
-      // ---------------- scattering events, serviced together ----------------
-      if (state == B_EVENT) {
-        ++ev;
-        if ((int64_t)ev > p.max_events) {
-          ++c_trunc;
-          atomicAdd(&s_misc[2], (double)w);
-          if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
-            const JobDev& J = p.jobs[job];
-            rt_record rc{2u, ncross, ev, 0u, (int64_t)b.rcanon[R.gbase + node], canon_of(md, birth), (double)w};
-            p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
-          }
-          c_cross += ncross;
-          state = B_EMPTY;
-        } else {
-          ++c_scat;
-          const double h = ldexp(1.0, -lev);
-          O0 = ((double)I0 + (double)x0) * h;
-          O1 = ((double)I1 + (double)x1) * h;
-          O2 = ((double)I2 + (double)x2) * h;
-          const uint4 xr = philox(pid, stream, ev, 0u, p.key0, p.key1);
-          bool killed = false;
-          if (rr_p > 0.0f && w < rr_thr * w0) {
-            if (unif32(xr.x) < rr_p) {
-              ++c_kill;
-              atomicAdd(&s_misc[0], (double)w);
-              if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
-                const JobDev& J = p.jobs[job];
-                rt_record rc{1u, ncross, ev, 0u, (int64_t)b.rcanon[R.gbase + node], canon_of(md, birth), (double)w};
-                p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
-              }
-              c_cross += ncross;
-              state = B_EMPTY;
-              killed = true;
-            } else {
-              const float nw = w * rr_gain;
-              atomicAdd(&s_misc[1], (double)nw - (double)w);
-              w = nw;
-            }
-          }
-          if (!killed) {
-            const float mu = hg_mu32(g, unif32(xr.y));
-            rotate32(d0, d1, d2, mu, kTwoPiF * unif32(xr.z));
-            r0 = rcp_or_inf(d0);
-            r1 = rcp_or_inf(d1);
-            r2 = rcp_or_inf(d2);
-            tau = -logf(unif32(xr.w));
-            state = B_CROSS;
-          }
-        }
-      }
-    }
     __syncthreads();
     for (int i = tid; i < nloc; i += BS) {
       const float v = s_acc[i];
@@ -651,6 +685,7 @@ hipError_t attr_blk_pass(int block, int lds_bytes) {
   switch (block) {
     case 256: return hipFuncSetAttribute((const void*)blk_pass_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     case 512: return hipFuncSetAttribute((const void*)blk_pass_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    case 768: return hipFuncSetAttribute((const void*)blk_pass_kernel<768>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     case 1024: return hipFuncSetAttribute((const void*)blk_pass_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     default: return hipErrorInvalidValue;
   }
@@ -660,6 +695,7 @@ hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_byte
   switch (block) {
     case 256: hipLaunchKernelGGL(blk_pass_kernel<256>, dim3(grid), dim3(256), lds_bytes, s, b); break;
     case 512: hipLaunchKernelGGL(blk_pass_kernel<512>, dim3(grid), dim3(512), lds_bytes, s, b); break;
+    case 768: hipLaunchKernelGGL(blk_pass_kernel<768>, dim3(grid), dim3(768), lds_bytes, s, b); break;
     case 1024: hipLaunchKernelGGL(blk_pass_kernel<1024>, dim3(grid), dim3(1024), lds_bytes, s, b); break;
     default: return hipErrorInvalidValue;
   }

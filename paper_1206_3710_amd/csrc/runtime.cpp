@@ -97,6 +97,9 @@ struct rt_ctx {
   int64_t q_capacity = 0;
   std::vector<int32_t> h_reg_nodes;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  // second stream: emission of the next batch runs beside the region pass
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
 };
 
 namespace {
@@ -418,7 +421,10 @@ rt_status rt_create(rt_ctx** out, int32_t device, void* hip_stream) {
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   ctx->n_cu = prop.multiProcessorCount;
   if (hipSetDevice(device) != hipSuccess || hipEventCreate(&ctx->ev0) != hipSuccess ||
-      hipEventCreate(&ctx->ev1) != hipSuccess || hipEventCreate(&ctx->ev2) != hipSuccess) {
+      hipEventCreate(&ctx->ev1) != hipSuccess || hipEventCreate(&ctx->ev2) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_a, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_b, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess) {
     delete ctx;
     return fail(nullptr, RT_EDEVICE, "cannot initialise device %d", device);
   }
@@ -449,6 +455,9 @@ rt_status rt_destroy(rt_ctx* ctx) {
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
+  if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
+  if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
   delete ctx;
   return RT_OK;
 }
@@ -758,7 +767,9 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     return fail(ctx, RT_EINVAL, "rr_threshold must be finite and >= 0");
   if (!(o->rr_prob >= 0.0 && o->rr_prob < 1.0)) return fail(ctx, RT_EINVAL, "rr_prob must be in [0, 1)");
   if (o->max_events < 0 || o->max_events > 0x7fffffff) return fail(ctx, RT_EINVAL, "bad max_events");
-  const int bs = o->block_size ? o->block_size : 256;
+  const bool region_sched = o->precision == RT_FP32_LOCAL && o->schedule == RT_SCHED_REGIONS;
+  // defaults from tuning on the molecular-cloud workload
+  const int bs = o->block_size ? o->block_size : (region_sched ? 768 : 256);
   if (bs != 64 && bs != 128 && bs != 256 && !(bs >= 512 && bs <= 1024 && o->precision == RT_FP32_LOCAL &&
                                                  (bs == 512 || o->schedule == RT_SCHED_REGIONS)))
     return fail(ctx, RT_EINVAL, "block_size must be 64, 128, 256 (or 512 for the FP32 form)");
@@ -768,8 +779,10 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   if (o->schedule != RT_SCHED_REGIONS && o->schedule != RT_SCHED_GLOBAL)
     return fail(ctx, RT_EINVAL, "schedule must be RT_SCHED_REGIONS or RT_SCHED_GLOBAL");
   if (o->precision == RT_FP32_LOCAL && o->schedule == RT_SCHED_REGIONS && o->block_size &&
-      o->block_size != 256 && o->block_size != 512 && o->block_size != 1024)
-    return fail(ctx, RT_EINVAL, "the region schedule needs block_size 256, 512 or 1024");
+      o->block_size != 256 && o->block_size != 512 && o->block_size != 768 && o->block_size != 1024)
+    return fail(ctx, RT_EINVAL, "the region schedule needs block_size 256, 512, 768 or 1024");
+  if (o->chunk_packets < 0 || o->batch_packets < 0)
+    return fail(ctx, RT_EINVAL, "chunk_packets and batch_packets must be >= 0");
   if (o->rec_stride < 0 || (o->rec_stride > 0 && !o->records))
     return fail(ctx, RT_EINVAL, "records needed when rec_stride > 0");
   for (int s = 0; s < n_src; ++s) {
@@ -919,7 +932,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   p.rr_thr = o->rr_threshold;
   p.rr_p = o->rr_prob;
   p.max_events = o->max_events > 0 ? o->max_events : 1000000;
-  p.refill_thr = o->refill_threshold > 0.0f ? o->refill_threshold : 0.5f;
+  p.refill_thr = o->refill_threshold > 0.0f ? o->refill_threshold : (region_sched ? 0.15f : 0.5f);
   p.cdf_qpre = ctx->cdf_qpre.as<uint64_t>();
   p.cdf_q = ctx->cdf_q.as<uint64_t>();
   p.cdf_lum = ctx->cdf_lum.as<double>();
@@ -931,7 +944,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   int reg_lds = 0, reg_per_cu = 0;
   if (regions) {
     // LDS per block: node words + accumulators (4 + 4 B per node) + parent links (4 B per oct)
-    reg_per_cu = o->blocks_per_cu ? o->blocks_per_cu : (bs == 256 ? 2 : 1);
+    reg_per_cu = o->blocks_per_cu ? o->blocks_per_cu : (bs <= 256 ? 2 : 1);
     const int budget = 160 * 1024 / reg_per_cu - 4 * 1024;  // leave room for the static LDS
     int32_t cap = (int32_t)((budget * 8 / 68) & ~7);
     if (cap < 64) return fail(ctx, RT_EINVAL, "too many blocks per CU for the region schedule");
@@ -948,8 +961,8 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     int end_bit = 1;
     while ((int64_t(1) << end_bit) < n_keys) ++end_bit;
     const int64_t capq = std::min<int64_t>(int64_t(1) << 25, std::max<int64_t>((int64_t)start, 4096));
-    const int64_t batch = std::min<int64_t>(int64_t(1) << 23, capq);
-    const int32_t chunk = 16 * bs;
+    const int64_t batch = std::min<int64_t>(o->batch_packets > 0 ? o->batch_packets : int64_t(1) << 23, capq);
+    const int32_t chunk = o->chunk_packets > 0 ? o->chunk_packets : 16 * bs;
     if (ctx->q_capacity < capq) {
       for (int k = 0; k < 2; ++k) {
         HIPCHK(ctx->q_rec[k].ensure(sizeof(PRec) * capq));
@@ -993,22 +1006,18 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     int in = 0;
     uint64_t in_count = 0, emitted = 0;
     int64_t sweeps = 0;
-    for (;;) {
-      if (emitted < start) {
-        const uint64_t n_emit = std::min<uint64_t>({(uint64_t)batch, (uint64_t)capq - in_count, start - emitted});
-        if (n_emit > 0) {
-          b.u_out = ctx->q_rec[in].as<PRec>();
-          b.u_key = ctx->q_key[in].as<uint32_t>();
-          b.u_count = counters + in;
-          HIPCHK(launch_blk_emit(b, emitted, emitted + n_emit, ctx->stream));
-          emitted += n_emit;
-          in_count += n_emit;
-        }
-      }
-      if (in_count == 0) {
-        if (emitted >= start) break;
-        continue;
-      }
+    // first batch on the main stream; later batches are emitted on the second stream while the
+    // region pass of the previous sweep runs (both append to the same queue)
+    {
+      const uint64_t n_emit = std::min<uint64_t>((uint64_t)batch, start);
+      b.u_out = ctx->q_rec[0].as<PRec>();
+      b.u_key = ctx->q_key[0].as<uint32_t>();
+      b.u_count = counters;
+      HIPCHK(launch_blk_emit(b, 0, n_emit, ctx->stream));
+      emitted = n_emit;
+      in_count = n_emit;
+    }
+    while (in_count > 0) {
       const int out_b = 1 - in;
       HIPCHK(launch_blk_iota((uint32_t)in_count, ctx->q_iota.as<uint32_t>(), ctx->stream));
       HIPCHK(hipcub::DeviceRadixSort::SortPairs(ctx->q_sort_tmp.p, sort_bytes, ctx->q_key[in].as<uint32_t>(),
@@ -1020,17 +1029,39 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
                               ctx->q_nitems.as<uint32_t>(), ctx->stream));
       HIPCHK(hipMemsetAsync(counters + out_b, 0, 8, ctx->stream));
       HIPCHK(hipMemsetAsync(ctx->q_nitems.as<uint32_t>() + 1, 0, 4, ctx->stream));
-      b.q_in = ctx->q_rec[in].as<PRec>();
-      b.q_perm = ctx->q_perm.as<uint32_t>();
       b.u_out = ctx->q_rec[out_b].as<PRec>();
       b.u_key = ctx->q_key[out_b].as<uint32_t>();
       b.u_count = counters + out_b;
+      uint64_t n_emit = 0;
+      if (emitted < start) {
+        n_emit = std::min<uint64_t>({(uint64_t)batch, (uint64_t)capq - in_count, start - emitted});
+        if (n_emit > 0) {
+          HIPCHK(hipEventRecord(ctx->ev_a, ctx->stream));
+          HIPCHK(hipStreamWaitEvent(ctx->aux, ctx->ev_a, 0));
+          HIPCHK(launch_blk_emit(b, emitted, emitted + n_emit, ctx->aux));
+          HIPCHK(hipEventRecord(ctx->ev_b, ctx->aux));
+          emitted += n_emit;
+        }
+      }
+      b.q_in = ctx->q_rec[in].as<PRec>();
+      b.q_perm = ctx->q_perm.as<uint32_t>();
       HIPCHK(launch_blk_pass(b, ctx->n_cu * reg_per_cu, bs, reg_lds, ctx->stream));
+      if (n_emit > 0) HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_b, 0));
       unsigned long long nc = 0;
       HIPCHK(hipMemcpyAsync(&nc, counters + out_b, 8, hipMemcpyDeviceToHost, ctx->stream));
       HIPCHK(hipStreamSynchronize(ctx->stream));
       in_count = nc;
       in = out_b;
+      if (in_count == 0 && emitted < start) {
+        // nothing in flight (e.g. every packet of the batch left at once): emit the next batch
+        const uint64_t ne = std::min<uint64_t>((uint64_t)batch, start - emitted);
+        b.u_out = ctx->q_rec[in].as<PRec>();
+        b.u_key = ctx->q_key[in].as<uint32_t>();
+        b.u_count = counters + in;
+        HIPCHK(launch_blk_emit(b, emitted, emitted + ne, ctx->stream));
+        emitted += ne;
+        in_count = ne;
+      }
       if (++sweeps > 2000000) return fail(ctx, RT_EDEVICE, "region schedule did not drain");
     }
   } else if (start > 0) {
