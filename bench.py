@@ -21,6 +21,23 @@ BYTES_PER_CROSSING_FP32 = 12.0   # packed density/subgrid word 4 B + FP32 accumu
 BYTES_PER_CROSSING_FP64 = 28.0   # FP64 density 8 B + child 4 B + FP64 accumulator RMW 16 B
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the region pass kernel, from two rocprofv3 --pmc runs of one trace step
+# (FETCH_SIZE, then WRITE_SIZE), each scaled by what the same counter reads for a 4 GiB
+# device-to-device copy (fetch x2.0, write x1.0), per leaf crossing.  Valid only for the kernel
+# sources the counters were taken on.
+PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
+                "sha256": "e422a8208624f3b815d9593b1322e094da0e492964c87ad680be9e8eedb62b06",
+                "fetch_bytes_per_crossing": 10.577, "write_bytes_per_crossing": 4.310}
+
+
+def pass_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PASS_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_1206_3710_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -30,7 +47,7 @@ def parse():
     ap.add_argument("--packets", type=int, default=10_000_000, help="packets per wavelength")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-packets", type=int, default=1 << 15,
+    ap.add_argument("--cpu-packets", type=int, default=1 << 18,
                     help="oracle sample: packets per wavelength")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
@@ -40,7 +57,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--trace-only", action="store_true", help="time only the transport step")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="first copy 256 MiB device-to-device (reference for traffic counters)")
+                    help="first copy 4 GiB device-to-device (reference for traffic counters)")
     return ap.parse_args()
 
 
@@ -90,18 +107,30 @@ def main():
     t0 = time.perf_counter()
     crossings = 0
     kernel_ms = []
+    main_ms, main_n = [], []
     post = []
     for i in range(a.steps):
         o = step(rt.FP32_LOCAL, i)
         crossings += o["stats"]["crossings"]
         kernel_ms.append(o["stats"]["kernel_ms"])
+        main_ms.append(o["stats"]["main_ms"])
+        main_n.append(o["stats"]["main_launches"])
         post.append(o["post_s"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = crossings / dt
     k_avg = sum(kernel_ms) / len(kernel_ms) / 1e3
     cr_step = crossings / a.steps
-    achieved = cr_step * BYTES_PER_CROSSING_FP32 / k_avg / 1e9
+    # dominant kernel: per-launch durations from HIP events on its own stream (summed by the
+    # library), algorithmic bytes = crossings handled x bytes per crossing
+    launches = sum(main_n) / a.steps
+    main_launch_s = sum(main_ms) / sum(main_n) / 1e3
+    bytes_per_launch = cr_step / launches * BYTES_PER_CROSSING_FP32
+    achieved = bytes_per_launch / main_launch_s / 1e9
+    traffic = None
+    if a.schedule == 0 and pass_sources_sha() == PASS_TRAFFIC["sha256"]:
+        traffic = cr_step / launches * (PASS_TRAFFIC["fetch_bytes_per_crossing"]
+                                        + PASS_TRAFFIC["write_bytes_per_crossing"])
 
     # plain FP64 form on the same inputs
     fp64 = None
@@ -160,8 +189,11 @@ def main():
         "trace_crossings_per_s": cr_step / k_avg,
         "post_trace_ms": 1e3 * sum(post) / len(post),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "trace_fp32_kernel", "bytes_per_crossing": BYTES_PER_CROSSING_FP32},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "blk_pass_kernel<%d>" % (a.block or 768) if a.schedule == 0
+                               else "trace_fp32_kernel<%d>" % (a.block or 256),
+                     "launches_per_step": launches, "avg_launch_ms": 1e3 * main_launch_s,
+                     "bytes_per_crossing": BYTES_PER_CROSSING_FP32},
         "fp64": fp64,
         "cpu_baseline": cpu,
     }

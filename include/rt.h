@@ -164,8 +164,15 @@ typedef struct {
 typedef struct {
   uint64_t crossings, scatterings, kills, truncated, packets;
   double e_emit, e_abs, e_esc, e_killed, e_rr_gain, e_trunc;
-  double kernel_ms;         /* device time of the transport kernels (HIP events) */
+  double kernel_ms;         /* device time from the first transport launch to the last (HIP
+                               events on the context stream), emission and queue sorting
+                               included */
   double reduce_ms;         /* device time of the final FP64 reduction */
+  double main_ms;           /* summed durations of the launches of the dominant transport
+                               kernel (FP64: the per-job kernel; FP32-local: the persistent
+                               kernel, or the region pass of every sweep), HIP events recorded
+                               on the stream each launch runs on */
+  uint64_t main_launches;   /* number of those launches */
 } rt_trace_stats;
 
 /* Follow packets_per_lambda packets of every source at every wavelength of its model.  Packet

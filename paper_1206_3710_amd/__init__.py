@@ -66,7 +66,7 @@ class TraceStats(C.Structure):
                 ("truncated", C.c_uint64), ("packets", C.c_uint64), ("e_emit", C.c_double),
                 ("e_abs", C.c_double), ("e_esc", C.c_double), ("e_killed", C.c_double),
                 ("e_rr_gain", C.c_double), ("e_trunc", C.c_double), ("kernel_ms", C.c_double),
-                ("reduce_ms", C.c_double)]
+                ("reduce_ms", C.c_double), ("main_ms", C.c_double), ("main_launches", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

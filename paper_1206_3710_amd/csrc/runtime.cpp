@@ -100,6 +100,7 @@ struct rt_ctx {
   // second stream: emission of the next batch runs beside the region pass
   hipStream_t aux = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr;  // around each region pass
 };
 
 namespace {
@@ -424,6 +425,7 @@ rt_status rt_create(rt_ctx** out, int32_t device, void* hip_stream) {
       hipEventCreate(&ctx->ev1) != hipSuccess || hipEventCreate(&ctx->ev2) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_a, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_b, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&ctx->ev_p0) != hipSuccess || hipEventCreate(&ctx->ev_p1) != hipSuccess ||
       hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess) {
     delete ctx;
     return fail(nullptr, RT_EDEVICE, "cannot initialise device %d", device);
@@ -457,6 +459,8 @@ rt_status rt_destroy(rt_ctx* ctx) {
   if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
   if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
   if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
+  if (ctx->ev_p0) (void)hipEventDestroy(ctx->ev_p0);
+  if (ctx->ev_p1) (void)hipEventDestroy(ctx->ev_p1);
   if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
   delete ctx;
   return RT_OK;
@@ -954,6 +958,8 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     HIPCHK(ctx->acc.ensure((size_t)n_slots * ctx->reg_G * 4));
     HIPCHK(hipMemsetAsync(ctx->acc.p, 0, (size_t)n_slots * ctx->reg_G * 4, ctx->stream));
   }
+  double main_ms = 0.0;
+  uint64_t main_launches = 0;
   HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
   if (start > 0 && regions) {
     const int n_regions = (int)ctx->h_regions.size();
@@ -1045,11 +1051,17 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
       }
       b.q_in = ctx->q_rec[in].as<PRec>();
       b.q_perm = ctx->q_perm.as<uint32_t>();
+      HIPCHK(hipEventRecord(ctx->ev_p0, ctx->stream));
       HIPCHK(launch_blk_pass(b, ctx->n_cu * reg_per_cu, bs, reg_lds, ctx->stream));
+      HIPCHK(hipEventRecord(ctx->ev_p1, ctx->stream));
       if (n_emit > 0) HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_b, 0));
       unsigned long long nc = 0;
       HIPCHK(hipMemcpyAsync(&nc, counters + out_b, 8, hipMemcpyDeviceToHost, ctx->stream));
       HIPCHK(hipStreamSynchronize(ctx->stream));
+      float pass_ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&pass_ms, ctx->ev_p0, ctx->ev_p1));
+      main_ms += pass_ms;
+      ++main_launches;
       in_count = nc;
       in = out_b;
       if (in_count == 0 && emitted < start) {
@@ -1072,9 +1084,14 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
         per_cu = std::max(per_cu, 1);
       }
       HIPCHK(launch_trace_fp32(p, ctx->n_cu * per_cu, bs, ctx->stream));
+      main_launches = 1;
     } else {
+      // back-to-back launches on one stream: their summed durations are the span ev0 -> ev1
       for (size_t k = 0; k < jobs.size(); ++k)
-        if (jobs[k].n > 0) HIPCHK(launch_trace_fp64(p, (int)k, jobs[k].n, bs, ctx->stream));
+        if (jobs[k].n > 0) {
+          HIPCHK(launch_trace_fp64(p, (int)k, jobs[k].n, bs, ctx->stream));
+          ++main_launches;
+        }
     }
   }
   HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
@@ -1124,6 +1141,8 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     st_out->e_trunc = ds.e_trunc;
     st_out->kernel_ms = k_ms;
     st_out->reduce_ms = r_ms;
+    st_out->main_ms = regions ? main_ms : k_ms;
+    st_out->main_launches = main_launches;
   }
   return RT_OK;
 }
