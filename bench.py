@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--schedule", type=int, default=0, help="0: regions, 1: one global queue")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--tail-park", type=int, default=0)
     ap.add_argument("--trace-only", action="store_true", help="time only the transport step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 4 GiB device-to-device (reference for traffic counters)")
@@ -87,7 +88,8 @@ def main():
     lam_all = list(range(nl))
     kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob, block_size=a.block,
               blocks_per_cu=a.blocks_per_cu, refill_threshold=a.refill)
-    kw32 = dict(kw, schedule=a.schedule, chunk_packets=a.chunk, batch_packets=a.batch)
+    kw32 = dict(kw, schedule=a.schedule, chunk_packets=a.chunk, batch_packets=a.batch,
+                tail_park=a.tail_park)
 
     def step(precision, it):
         r = ctx.trace_packets(w.sources, seed=w.seed, iteration=it, precision=precision,

@@ -153,7 +153,9 @@ typedef struct {
                                RT_SCHED_GLOBAL runs one persistent kernel over the whole tree
                                with global atomics */
   int32_t chunk_packets;    /* region schedule: packets per work item; 0 = 16 * block_size */
-  int32_t pad1;
+  int32_t tail_park;        /* region schedule: crossing rounds a wave keeps following its last
+                               packets after its work item's queue is empty before it re-queues
+                               them for the next sweep; 0 = default (16), < 0 = never */
   int64_t batch_packets;    /* region schedule: packets emitted per sweep; 0 = 2^23 */
   int64_t rec_stride;       /* > 0: record packet j of each (source, wavelength) when
                                j % rec_stride == 0 */

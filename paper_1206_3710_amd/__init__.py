@@ -57,7 +57,7 @@ class TraceOpts(C.Structure):
                 ("rr_threshold", C.c_double), ("rr_prob", C.c_double), ("max_events", C.c_int64),
                 ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_threshold", C.c_float), ("schedule", C.c_int32),
-                ("chunk_packets", C.c_int32), ("pad1", C.c_int32), ("batch_packets", C.c_int64),
+                ("chunk_packets", C.c_int32), ("tail_park", C.c_int32), ("batch_packets", C.c_int64),
                 ("rec_stride", C.c_int64), ("records", C.c_void_p)]
 
 
@@ -218,7 +218,7 @@ class Context:
                       rr_threshold: float = 0.0, rr_prob: float = 0.0, max_events: int = 0,
                       block_size: int = 0, blocks_per_cu: int = 0, refill_threshold: float = 0.0,
                       rec_stride: int = 0, per_lambda: bool = False, schedule: int = SCHED_REGIONS,
-                      chunk_packets: int = 0, batch_packets: int = 0):
+                      chunk_packets: int = 0, batch_packets: int = 0, tail_park: int = 0):
         """Trace the packets of ``sources`` (objects with kind, model, pos, dir, power,
         packets).  Returns a dict of device tensors and the statistics."""
         torch = _torch()
@@ -246,7 +246,7 @@ class Context:
             rec = torch.zeros(max(n_rec, 1) * RECORD_DTYPE.itemsize, dtype=torch.uint8,
                               device=self.tdev)
         opts = TraceOpts(seed, iteration, precision, rr_threshold, rr_prob, max_events, block_size,
-                         blocks_per_cu, refill_threshold, schedule, chunk_packets, 0,
+                         blocks_per_cu, refill_threshold, schedule, chunk_packets, tail_park,
                          batch_packets, rec_stride, None if rec is None else rec.data_ptr())
         st = TraceStats()
         self._check(lib().rt_trace_packets(self.h, n, arr, C.byref(opts), _ptr(e_node),
@@ -281,7 +281,8 @@ class Context:
         opts = TraceOpts(seed, iteration, precision, rr_threshold, rr_prob, kw.get("max_events", 0),
                          kw.get("block_size", 0), kw.get("blocks_per_cu", 0),
                          kw.get("refill_threshold", 0.0), kw.get("schedule", SCHED_REGIONS),
-                         kw.get("chunk_packets", 0), 0, kw.get("batch_packets", 0), 0, None)
+                         kw.get("chunk_packets", 0), kw.get("tail_park", 0),
+                         kw.get("batch_packets", 0), 0, None)
         t = torch.empty(self.models[model], dtype=torch.float64, device=self.tdev)
         nd = C.c_int32()
         crit = np.zeros(max(n_max, 1))

@@ -24,7 +24,7 @@ constexpr int kEscLds = 256;
 
 __device__ __forceinline__ float pow2f(int e) { return __int_as_float((127 + e) << 23); }
 __device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
-__device__ __forceinline__ float rcp_or_inf(float d) { return d != 0.0f ? 1.0f / d : INFINITY; }
+
 __device__ __forceinline__ int32_t child_of(int32_t w) { return w < 0 ? ~w : -1; }
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
@@ -258,12 +258,17 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   int state = B_EMPTY;
   int32_t node = 0, lev = 0, I0 = 0, I1 = 0, I2 = 0, birth = 0, job = 0;
   float x0 = 0.f, x1 = 0.f, x2 = 0.f, d0 = 0.f, d1 = 0.f, d2 = 1.f;
-  float r0 = INFINITY, r1 = INFINITY, r2 = 1.f, w = 0.f, w0 = 0.f, tau = 0.f, rho = 0.f;
+  float n0 = 0.f, n1 = 0.f, n2 = -1.f, c0 = INFINITY, c1 = INFINITY, c2 = 1.f;
+  float w = 0.f, w0 = 0.f, tau = 0.f, rho = 0.f;
   double O0 = 0.0, O1 = 0.0, O2 = 0.0;
   uint32_t pid = 0, ev = 0, ncross = 0, stream = 0;
-  float kc = 0.f, alb = 0.f, g = 0.f;
+  float ks = 0.f, ka = 0.f, g = 0.f;  // scattering / absorption opacity per root-cell length per unit density
   int esc_slot = 0;
   int32_t xax = 0, xsg = 0;
+  bool xpark = false;          // re-queued in this region without crossing a face
+  bool pool_done = false;      // this item's packets are all taken (wave-uniform)
+  int tail_it = 0;             // crossing rounds since then (wave-uniform)
+  const uint32_t own_key = (uint32_t)it.slot * (uint32_t)b.n_regions + (uint32_t)it.region;
   uint32_t xkey = 0;
 
   for (;;) {
@@ -273,6 +278,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
       uint32_t base = 0;
       if (lane == 0) base = atomicAdd(s_next, (uint32_t)__popcll(need));
       base = __shfl(base, 0, 64);
+      if (base + (uint32_t)__popcll(need) >= it.count) pool_done = true;
       if (state == B_EMPTY) {
         const uint32_t idx = base + lane_rank(need);
         if (idx >= it.count) {
@@ -281,8 +287,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           const PRec rec = b.q_in[b.q_perm[it.start + idx]];
           job = rec.job;
           const JobDev& J = p.jobs[job];
-          kc = J.kc32;
-          alb = J.alb32;
+          ks = J.kc32 * J.alb32;
+          ka = J.kc32 - ks;
           g = J.g32;
           stream = J.stream;
           esc_slot = J.esc_slot;
@@ -292,9 +298,9 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           d0 = rec.d[0];
           d1 = rec.d[1];
           d2 = rec.d[2];
-          r0 = rcp_or_inf(d0);
-          r1 = rcp_or_inf(d1);
-          r2 = rcp_or_inf(d2);
+          exit_coef(d0, n0, c0);
+          exit_coef(d1, n1, c1);
+          exit_coef(d2, n2, c2);
           w = rec.w;
           w0 = rec.w0;
           tau = rec.tau;
@@ -357,35 +363,24 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
     // ---------------- crossing phase (LDS lookups, LDS deposits) ----------------
     for (;;) {
       if (state == B_CROSS) {
-        const float se = kc * rho * pow2f(-lev);
-        const float ss = alb * se;
-        const float sa = se - ss;
-        const float tx = d0 != 0.0f ? (d0 > 0.0f ? 1.0f - x0 : -x0) * r0 : INFINITY;
-        const float ty = d1 != 0.0f ? (d1 > 0.0f ? 1.0f - x1 : -x1) * r1 : INFINITY;
-        const float tz = d2 != 0.0f ? (d2 > 0.0f ? 1.0f - x2 : -x2) * r2 : INFINITY;
-        int ax;
-        float texit;
-        if (tx <= ty && tx <= tz) {
-          ax = 0;
-          texit = tx;
-        } else if (ty <= tz) {
-          ax = 1;
-          texit = ty;
-        } else {
-          ax = 2;
-          texit = tz;
-        }
+        // density times the cell size in root-cell units (local lengths are in cell units)
+        const float f = ldexpf(rho, -lev);
+        const float ss = ks * f;
+        const float sa = ka * f;
+        const float tx = fmaf(x0, n0, c0);
+        const float ty = fmaf(x1, n1, c1);
+        const float tz = fmaf(x2, n2, c2);
+        const float texit = fminf(tx, fminf(ty, tz));
+        const int ax = tx == texit ? 0 : (ty == texit ? 1 : 2);  // ties to the lowest axis
         const float tsc = ss * texit;
         const bool event = ss > 0.0f && tau <= tsc;
-        float s;
-        if (event) {
-          s = tau / ss;
-        } else {
-          s = texit;
-          tau -= tsc;
-        }
-        const float de = w * (-expm1f(-(sa * s)));
-        if (de > 0.0f) {
+        const float s = event ? tau * __builtin_amdgcn_rcpf(ss) : texit;
+        if (!event) tau -= tsc;
+        const float de = w * one_minus_exp(sa * s);
+        if (FITS) {
+          deposit(node, de);
+          w -= de;
+        } else if (de > 0.0f) {
           deposit(node, de);
           w -= de;
         }
@@ -447,10 +442,19 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           }
         }
       }
+      if (pool_done && ++tail_it >= b.tail_park) break;
       if (__popcll(__ballot(state == B_CROSS)) < want) break;
     }
 
     // ---------------- packets leaving the region: append to the next queue ----------------
+    // the item's queue is empty and the wave has been finishing its last packets for a while:
+    // re-queue the ones still crossing (for this same region, next sweep) so that the block
+    // does not wait for a few long histories
+    if (pool_done && tail_it >= b.tail_park && state == B_CROSS) {
+      state = B_EXIT;
+      xpark = true;
+      xkey = own_key;
+    }
     const uint64_t ex = __ballot(state == B_EXIT);
     if (ex) {
       uint32_t blo = 0, bhi = 0;
@@ -470,7 +474,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         rc.lev = (uint8_t)lev;
         rc.ax = (uint8_t)xax;
         rc.sg = xsg > 0 ? 0 : 1;
-        rc.flag = 1;
+        rc.flag = xpark ? 0 : 1;
         rc.x[0] = x0;
         rc.x[1] = x1;
         rc.x[2] = x2;
@@ -490,6 +494,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         rc.ncross = ncross;
         b.u_out[idx] = rc;
         b.u_key[idx] = xkey;
+        xpark = false;
         state = B_EMPTY;
       }
     }
@@ -536,9 +541,9 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         if (!killed) {
           const float mu = hg_mu32(g, unif32(xr.y));
           rotate32(d0, d1, d2, mu, kTwoPiF * unif32(xr.z));
-          r0 = rcp_or_inf(d0);
-          r1 = rcp_or_inf(d1);
-          r2 = rcp_or_inf(d2);
+          exit_coef(d0, n0, c0);
+          exit_coef(d1, n1, c1);
+          exit_coef(d2, n2, c2);
           tau = -logf(unif32(xr.w));
           state = B_CROSS;
         }

@@ -322,6 +322,35 @@ __device__ __forceinline__ void rotate64(double d[3], double mu, double phi) {
   d[2] = nz / nn;
 }
 
+// ---- FP32-local segment arithmetic (shared by both FP32-local schedules) ----
+// Exit-distance coefficients of one axis: t = fma(x, n, c) is the distance, in local cell
+// units, to the face the packet moves toward: (1 - x)/d for d > 0, -x/d for d < 0, infinite
+// for d = 0 (components below 1e-30 count as 0, so the reciprocal stays finite).
+__device__ __forceinline__ void exit_coef(float d, float& n, float& c) {
+  const bool z = !(fabsf(d) >= 1e-30f);
+  const float r = 1.0f / (z ? 1.0f : d);
+  n = z ? 0.0f : -r;
+  c = z ? INFINITY : (d > 0.0f ? r : 0.0f);
+}
+
+// 1 - exp(-q) for q >= 0 (the absorbed fraction of a segment).  Below 1/2 the Taylor
+// polynomial to q^8 (truncation below 2e-8 relative); above, the hardware base-2 exponential,
+// whose error of about one ulp of exp(-q) <= 0.61 stays below 2e-7 relative of the result.
+__device__ __forceinline__ float one_minus_exp(float q) {
+  // 1 - e^-q = q (1 - q Q(q)), Q(q) = 1/2! - q/3! + q^2/4! - ... + q^6/8!, in Horner form
+  float p = 2.48015873e-5f;         // 1/8!
+  p = fmaf(p, q, -1.98412698e-4f);  // -1/7!
+  p = fmaf(p, q, 1.38888889e-3f);   // 1/6!
+  p = fmaf(p, q, -8.33333333e-3f);  // -1/5!
+  p = fmaf(p, q, 4.16666667e-2f);   // 1/4!
+  p = fmaf(p, q, -1.66666667e-1f);  // -1/3!
+  p = fmaf(p, q, 0.5f);             // 1/2!
+  p = fmaf(p, -q, 1.0f);
+  const float small = p * q;
+  const float large = 1.0f - __builtin_amdgcn_exp2f(q * -1.44269504f);
+  return q < 0.5f ? small : large;
+}
+
 __device__ __forceinline__ float hg_mu32(float g, float u) {
   float mu;
   if (fabsf(g) >= 1e-6f) {

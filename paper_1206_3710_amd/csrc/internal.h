@@ -109,10 +109,11 @@ struct RegionDev {
   int64_t gbase;    // region-major global id of local 0 (multiple of 8)
 };
 
-// A packet waiting at a region boundary (or just born): 96 bytes.
+// A packet waiting at a region boundary, just born, or re-queued inside its cell: 96 bytes.
 struct PRec {
   int32_t I[3];          // integer coordinates of the cell it is in, at level lev
-  uint8_t lev, ax, sg, flag;  // flag 0: inside the cell; 1: about to cross axis ax (sg 0: +, 1: -)
+  uint8_t lev, ax, sg, flag;  // flag 0: inside the cell (born or re-queued, no crossing
+                              // counted on resume); 1: about to cross axis ax (sg 0: +, 1: -)
   float x[3], d[3];      // local coordinates in that cell, direction
   float w, w0, tau;
   int32_t birth;         // internal id of the birth leaf (records)
@@ -150,6 +151,8 @@ struct BlkParams {
   uint32_t* item_counter;
   int32_t n_slots_key;       // accumulator slots (wavelengths) in the key
   int32_t chunk;             // packets per work item
+  int32_t tail_park;         // crossing rounds after an item's queue runs dry before the
+                             // packets still in flight are re-queued (INT32_MAX = never)
 };
 
 hipError_t launch_blk_emit(const BlkParams& b, uint64_t g0, uint64_t g1, hipStream_t s);

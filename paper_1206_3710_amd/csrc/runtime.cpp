@@ -1008,6 +1008,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     b.item_counter = ctx->q_nitems.as<uint32_t>() + 1;
     b.n_slots_key = n_slots;
     b.chunk = chunk;
+    b.tail_park = o->tail_park < 0 ? INT32_MAX : (o->tail_park > 0 ? o->tail_park : 16);
     unsigned long long* counters = ctx->q_counters.as<unsigned long long>();
     int in = 0;
     uint64_t in_count = 0, emitted = 0;

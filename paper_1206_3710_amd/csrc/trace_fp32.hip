@@ -31,7 +31,6 @@ constexpr int kRecoverLevel = 2;
 
 __device__ __forceinline__ float pow2f(int e) { return __int_as_float((127 + e) << 23); }
 __device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
-__device__ __forceinline__ float rcp_or_inf(float d) { return d != 0.0f ? 1.0f / d : INFINITY; }
 
 template <int BS>
 __global__ __launch_bounds__(BS) void trace_fp32_kernel(const TraceParams p) {
@@ -56,12 +55,12 @@ __global__ __launch_bounds__(BS) void trace_fp32_kernel(const TraceParams p) {
   int state = ST_EMIT;
   int32_t node = 0, lev = 0, I0 = 0, I1 = 0, I2 = 0, birth = 0;
   float x0 = 0.f, x1 = 0.f, x2 = 0.f, d0 = 0.f, d1 = 0.f, d2 = 1.f;
-  float r0 = INFINITY, r1 = INFINITY, r2 = 1.f;
+  float n0 = 0.f, n1 = 0.f, n2 = -1.f, c0 = INFINITY, c1 = INFINITY, c2 = 1.f;
   float w = 0.f, w0 = 0.f, tau = 0.f, rho = 0.f;
   double O0 = 0.0, O1 = 0.0, O2 = 0.0;
   uint32_t pid = 0, ev = 0, ncross = 0;
   int job = 0;
-  float kc = 0.f, alb = 0.f, g = 0.f;
+  float ks = 0.f, ka = 0.f, g = 0.f;  // scattering / absorption opacity per root-cell length per unit density
   uint32_t stream = 0;
   int64_t acc_off = 0;
   int esc_slot = 0;
@@ -102,8 +101,8 @@ __global__ __launch_bounds__(BS) void trace_fp32_kernel(const TraceParams p) {
           const ModelDev& md = p.models[J.model];
           pid = (uint32_t)(gid - J.start);
           D = dims_of(md);
-          kc = J.kc32;
-          alb = J.alb32;
+          ks = J.kc32 * J.alb32;
+          ka = J.kc32 - ks;
           g = J.g32;
           stream = J.stream;
           acc_off = J.acc_off;
@@ -126,9 +125,9 @@ __global__ __launch_bounds__(BS) void trace_fp32_kernel(const TraceParams p) {
           d0 = (float)k.d[0];
           d1 = (float)k.d[1];
           d2 = (float)k.d[2];
-          r0 = rcp_or_inf(d0);
-          r1 = rcp_or_inf(d1);
-          r2 = rcp_or_inf(d2);
+          exit_coef(d0, n0, c0);
+          exit_coef(d1, n1, c1);
+          exit_coef(d2, n2, c2);
           w0 = (float)k.w0;
           w = w0;
           tau = (float)k.tau;
@@ -148,34 +147,20 @@ __global__ __launch_bounds__(BS) void trace_fp32_kernel(const TraceParams p) {
     // ---------------- crossing phase ----------------
     for (;;) {
       if (state == ST_CROSS) {
-        const float se = kc * rho * pow2f(-lev);  // extinction per local unit
-        const float ss = alb * se;
-        const float sa = se - ss;
-        const float tx = d0 != 0.0f ? (d0 > 0.0f ? 1.0f - x0 : -x0) * r0 : INFINITY;
-        const float ty = d1 != 0.0f ? (d1 > 0.0f ? 1.0f - x1 : -x1) * r1 : INFINITY;
-        const float tz = d2 != 0.0f ? (d2 > 0.0f ? 1.0f - x2 : -x2) * r2 : INFINITY;
-        int ax;
-        float texit;
-        if (tx <= ty && tx <= tz) {
-          ax = 0;
-          texit = tx;
-        } else if (ty <= tz) {
-          ax = 1;
-          texit = ty;
-        } else {
-          ax = 2;
-          texit = tz;
-        }
+        // density times the cell size in root-cell units (local lengths are in cell units)
+        const float f = ldexpf(rho, -lev);
+        const float ss = ks * f;
+        const float sa = ka * f;
+        const float tx = fmaf(x0, n0, c0);
+        const float ty = fmaf(x1, n1, c1);
+        const float tz = fmaf(x2, n2, c2);
+        const float texit = fminf(tx, fminf(ty, tz));
+        const int ax = tx == texit ? 0 : (ty == texit ? 1 : 2);  // ties to the lowest axis
         const float tsc = ss * texit;
         const bool event = ss > 0.0f && tau <= tsc;
-        float s;
-        if (event) {
-          s = tau / ss;
-        } else {
-          s = texit;
-          tau -= tsc;
-        }
-        const float de = w * (-expm1f(-(sa * s)));
+        const float s = event ? tau * __builtin_amdgcn_rcpf(ss) : texit;
+        if (!event) tau -= tsc;
+        const float de = w * one_minus_exp(sa * s);
         if (de > 0.0f) {
           unsafeAtomicAdd(p.acc32 + acc_off + node, de);
           w -= de;
@@ -302,9 +287,9 @@ __global__ __launch_bounds__(BS) void trace_fp32_kernel(const TraceParams p) {
         if (!killed) {
           const float mu = hg_mu32(g, unif32(xr.y));
           rotate32(d0, d1, d2, mu, kTwoPiF * unif32(xr.z));
-          r0 = rcp_or_inf(d0);
-          r1 = rcp_or_inf(d1);
-          r2 = rcp_or_inf(d2);
+          exit_coef(d0, n0, c0);
+          exit_coef(d1, n1, c1);
+          exit_coef(d2, n2, c2);
           tau = -logf(unif32(xr.w));
           state = ST_CROSS;
         }

@@ -381,3 +381,24 @@ def test_region_and_global_schedules_agree(torch):
     assert rel_rms(eb, ea) < 1e-5
     assert a["stats"]["crossings"] == b["stats"]["crossings"]
     assert a["stats"]["scatterings"] == b["stats"]["scatterings"]
+
+
+def test_region_tail_parking(torch):
+    """Packets re-queued inside their cell when a work item's queue runs dry (forced after every
+    crossing round here) resume without a counted crossing: same crossings, scatterings and
+    per-packet fates as without re-queueing, and the same per-node result to FP32 rounding."""
+    w = gen.c2(n_root=24, max_level=3, n_lambda=4, packets=20000)
+    ctx = new_ctx(torch)
+    m = ctx.build_tree(w.trees[0])
+    ctx.set_dust(m, w.dusts[0])
+    kw = dict(seed=w.seed, precision=rt.FP32_LOCAL, rr_threshold=w.rr_threshold, rr_prob=w.rr_prob,
+              schedule=rt.SCHED_REGIONS, blocks_per_cu=8, rec_stride=7)
+    a = ctx.trace_packets(w.sources, tail_park=-1, **kw)
+    b = ctx.trace_packets(w.sources, tail_park=1, **kw)
+    for k in ("crossings", "scatterings", "kills", "packets"):
+        assert a["stats"][k] == b["stats"][k], k
+    ra, rb = a["records"], b["records"]
+    for f in ("status", "crossings", "events", "node", "birth"):
+        assert np.array_equal(ra[f], rb[f]), f
+    ea, eb = a["e_abs_node"].cpu().numpy(), b["e_abs_node"].cpu().numpy()
+    assert rel_rms(eb, ea) < 1e-5
