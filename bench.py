@@ -1,9 +1,16 @@
-"""Benchmark: molecular-cloud workload (root 64^3, up to 3 levels, 32 wavelengths, 1e7 packets
-per wavelength, dust temperatures, 256^2 maps toward 3 axes) on one MI355X.
+"""Benchmark on one MI355X.  Prints one JSON line.
 
-A step is one pass of the whole path over the resident model: trace all packets (FP32-local
-persistent form), reduce the absorbed energy to FP64, solve the temperatures, render the maps.
-The plain FP64 form is timed on the same inputs for comparison.  Prints one JSON line.
+Default workload: the molecular cloud (root 64^3, up to 3 levels, 32 wavelengths, 1e7 packets
+per wavelength, dust temperatures, 256^2 maps toward 3 axes).  A step is one pass of the whole
+path over the resident model: trace all packets (FP32-local form, region schedule), reduce the
+absorbed energy to FP64, solve the temperatures, render the maps.  The plain FP64 form is timed
+on the same inputs for comparison.
+
+--workload disc: the circumstellar disc (root 96x96x32, 6 levels, 50 wavelengths); the star is
+traced once before timing, and a step is one Lambda-iteration step from those temperatures:
+trace the dust emission (3e7 packets per wavelength), solve the temperatures of A_stars +
+A_dust.  --workload clouds: 64 uneven clouds, 16 wavelengths, 1e6 packets per (model,
+wavelength), all traced in one call; a step is that trace.
 """
 from __future__ import annotations
 
@@ -30,6 +37,18 @@ PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
                 "fetch_bytes_per_crossing": 10.577, "write_bytes_per_crossing": 4.310}
 
 
+WORKLOADS = {
+    "cloud": "molecular cloud: root 64^3, 3 levels, 32 wavelengths 0.1-1000 um, %d packets/"
+             "wavelength (isotropic field), roulette 1e-3/0.9, dust temperatures, 256^2 maps "
+             "toward +x,+y,+z at 32 wavelengths",
+    "disc": "circumstellar disc: root 96x96x32, 6 levels, 50 wavelengths; one Lambda-iteration "
+            "step: dust emission of T_0 (%d packets/wavelength), roulette 1e-3/0.9, FP64 "
+            "temperatures of A_stars + A_dust",
+    "clouds": "64 uneven clouds (roots 16^3-48^3, 1-4 levels), 16 wavelengths, %d packets per "
+              "(model, wavelength), one trace call",
+}
+
+
 def pass_sources_sha():
     import hashlib
     h = hashlib.sha256()
@@ -44,7 +63,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--packets", type=int, default=10_000_000, help="packets per wavelength")
+    ap.add_argument("--workload", choices=["cloud", "disc", "clouds"], default="cloud")
+    ap.add_argument("--packets", type=int, default=0,
+                    help="packets per wavelength (0: 1e7 cloud, 3e7 disc, 1e6 clouds)")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-packets", type=int, default=1 << 18,
@@ -79,27 +100,47 @@ def main():
         dst_t.copy_(src_t)
         torch.cuda.synchronize()
         del src_t, dst_t
-    w = gen.c2(packets=a.packets)
+    if a.workload == "cloud":
+        w = gen.c2(packets=a.packets or 10_000_000)
+    elif a.workload == "disc":
+        w = gen.c3(packets=a.packets or 30_000_000)
+    else:
+        w = gen.c4(packets=a.packets or 1_000_000)
     tree, dust = w.trees[0], w.dusts[0]
     ctx = rt.Context(0)
-    m = ctx.build_tree(tree)
-    ctx.set_dust(m, dust)
+    for t_, d_ in zip(w.trees, w.dusts):
+        m = ctx.build_tree(t_)
+        ctx.set_dust(m, d_)
+    m = 0
     nl = dust.n_lambda
     lam_all = list(range(nl))
     kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob, block_size=a.block,
               blocks_per_cu=a.blocks_per_cu, refill_threshold=a.refill)
     kw32 = dict(kw, schedule=a.schedule, chunk_packets=a.chunk, batch_packets=a.batch,
                 tail_park=a.tail_park)
+    if a.workload == "disc":
+        # constant sources once (FP64 form), then every timed step re-emits from T_0
+        a_stars = ctx.trace_packets(w.sources, seed=w.seed, iteration=0, precision=rt.FP64,
+                                    **kw)["e_abs_node"]
+        t0_disc = ctx.solve_temperature(m, a_stars, 2.0, 3000.0)
+        dust_src = [gen.Source(gen.SRC_DUST, 0, packets=w.sources[0].packets)]
 
     def step(precision, it):
-        r = ctx.trace_packets(w.sources, seed=w.seed, iteration=it, precision=precision,
-                              **(kw32 if precision == rt.FP32_LOCAL else kw))
+        kwp = kw32 if precision == rt.FP32_LOCAL else kw
+        if a.workload == "disc":
+            ctx.set_temperature(m, t0_disc)
+            r = ctx.trace_packets(dust_src, seed=w.seed, iteration=1 + it, precision=precision, **kwp)
+        else:
+            r = ctx.trace_packets(w.sources, seed=w.seed, iteration=it, precision=precision, **kwp)
         t = time.perf_counter()
         out = {"stats": r["stats"], "e_abs": r["e_abs_node"]}
         if not a.trace_only:
-            ctx.solve_temperature(m, r["e_abs_node"], 2.0, 3000.0)
-            for d in w.map_dirs:
-                ctx.render_map(m, d, w.map_npix, lam_all)
+            if a.workload == "cloud":
+                ctx.solve_temperature(m, r["e_abs_node"], 2.0, 3000.0)
+                for d in w.map_dirs:
+                    ctx.render_map(m, d, w.map_npix, lam_all)
+            elif a.workload == "disc":
+                ctx.solve_temperature(m, a_stars + r["e_abs_node"], 2.0, 3000.0)
         out["post_s"] = time.perf_counter() - t
         return out
 
@@ -133,7 +174,7 @@ def main():
     bytes_per_launch = cr_step / launches * BYTES_PER_CROSSING_FP32
     achieved = bytes_per_launch / main_launch_s / 1e9
     traffic = None
-    if a.schedule == 0 and pass_sources_sha() == PASS_TRAFFIC["sha256"]:
+    if a.workload == "cloud" and a.schedule == 0 and pass_sources_sha() == PASS_TRAFFIC["sha256"]:
         traffic = cr_step / launches * (PASS_TRAFFIC["fetch_bytes_per_crossing"]
                                         + PASS_TRAFFIC["write_bytes_per_crossing"])
 
@@ -170,13 +211,16 @@ def main():
     if not a.no_cpu_baseline:
         import oracle
         ora = oracle.Model(tree, dust)
+        src0 = [gen.Source(w.sources[0].kind, 0, pos=w.sources[0].pos, power=w.sources[0].power,
+                           packets=w.sources[0].packets)]
+        what = {"cloud": "", "disc": " of the star", "clouds": " of the first model"}[a.workload]
         t2 = time.perf_counter()
-        _, _, sto, _ = ora.trace(w.sources, seed=w.seed, rr_threshold=w.rr_threshold,
+        _, _, sto, _ = ora.trace(src0, seed=w.seed, rr_threshold=w.rr_threshold,
                                  rr_prob=w.rr_prob, pid_end=a.cpu_packets)
         dc = time.perf_counter() - t2
         cpu = {"value": sto["crossings"] / dc, "unit": "cell-crossings/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"first {a.cpu_packets} packets of each of the {nl} wavelengths "
+               "sample": f"first {a.cpu_packets} packets{what} at each of the {nl} wavelengths "
                          f"({sto['crossings']} crossings, {dc:.1f} s, single thread, "
                          f"{platform.processor() or platform.machine()})"}
 
@@ -193,12 +237,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "molecular cloud: root 64^3, 3 levels, 32 wavelengths 0.1-1000 um, "
-                               "1e7 packets/wavelength (isotropic field), roulette 1e-3/0.9, "
-                               "dust temperatures, 256^2 maps toward +x,+y,+z at 32 wavelengths"
+        "config": {"workload": WORKLOADS[a.workload] % w.sources[0].packets
                                + (" (trace only)" if a.trace_only else ""),
-                   "nodes": tree.n_nodes, "leaves": tree.n_leaves,
-                   "packets_per_step": int(w.sources[0].packets * nl),
+                   "nodes": sum(t_.n_nodes for t_ in w.trees),
+                   "leaves": sum(t_.n_leaves for t_ in w.trees),
+                   "packets_per_step": int(sum(s.packets for s in w.sources) * nl),
                    "crossings_per_step": cr_step},
         "trace_kernel_ms": 1e3 * k_avg,
         "trace_crossings_per_s": cr_step / k_avg,

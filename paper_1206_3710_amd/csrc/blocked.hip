@@ -396,7 +396,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           const int32_t Ja = Ia + sg;
           if (Ja < 0 || Ja >= (D.na(ax) << L)) {
             // escape through the root boundary
-            if (esc_lds) atomicAdd(&s_esc[esc_slot], (double)w);
+            // a region belongs to one model: its escapes are tallied per wavelength in LDS
+            if (esc_lds) atomicAdd(&s_esc[esc_slot - (int)md.lam_base], (double)w);
             else unsafeAtomicAdd(p.esc + esc_slot, (double)w);
             if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
               const JobDev& J = p.jobs[job];
@@ -565,8 +566,6 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   __shared__ double s_esc[kEscLds];
   const TraceParams& p = b.t;
   const int tid = threadIdx.x, lane = tid & 63;
-  const bool esc_lds = p.n_esc <= kEscLds;
-  for (int i = tid; i < kEscLds; i += BS) s_esc[i] = 0.0;
   if (tid < 4) s_misc[tid] = 0.0;
   unsigned long long c_cross = 0;
   uint32_t c_scat = 0, c_kill = 0, c_trunc = 0;
@@ -583,10 +582,13 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     const Dims D = dims_of(md);
     const int nloc = min(R.n, cap);
     const int nup = (nloc + 7) >> 3;
+    const bool esc_lds = md.nl <= kEscLds;
     for (int i = tid; i < nloc; i += BS) {
       s_word[i] = b.rword[R.gbase + i];
       s_acc[i] = 0.0f;
     }
+    if (esc_lds)
+      for (int i = tid; i < md.nl; i += BS) s_esc[i] = 0.0;
     for (int i = tid; i < nup; i += BS) s_up[i] = b.rup[(R.gbase >> 3) + i];
     if (tid == 0) s_next = 0;
     __syncthreads();
@@ -602,6 +604,9 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
       const float v = s_acc[i];
       if (v != 0.0f) unsafeAtomicAdd(gacc + i, v);
     }
+    if (esc_lds)
+      for (int i = tid; i < md.nl; i += BS)
+        if (s_esc[i] != 0.0) unsafeAtomicAdd(p.esc + md.lam_base + i, s_esc[i]);
   }
 
   const unsigned long long sc_cross = wave_sum_u64(c_cross);
@@ -615,9 +620,6 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     if (sc_trunc) atomicAdd(&p.stats->truncated, sc_trunc);
   }
   __syncthreads();
-  if (esc_lds)
-    for (int i = tid; i < p.n_esc; i += BS)
-      if (s_esc[i] != 0.0) unsafeAtomicAdd(p.esc + i, s_esc[i]);
   if (tid == 0) {
     if (s_misc[0] != 0.0) unsafeAtomicAdd(&p.stats->e_killed, s_misc[0]);
     if (s_misc[1] != 0.0) unsafeAtomicAdd(&p.stats->e_rr_gain, s_misc[1]);
