@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--tail-park", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (it runs, untimed, unless launch parameters are given)")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
     ap.add_argument("--trace-only", action="store_true", help="time only the transport step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 4 GiB device-to-device (reference for traffic counters)")
@@ -124,6 +127,21 @@ def main():
                                     **kw)["e_abs_node"]
         t0_disc = ctx.solve_temperature(m, a_stars, 2.0, 3000.0)
         dust_src = [gen.Source(gen.SRC_DUST, 0, packets=w.sources[0].packets)]
+
+    tuned = None
+    explicit = a.block or a.blocks_per_cu or a.refill or a.chunk or a.batch or a.tail_park
+    if not a.no_autotune and not explicit:
+        # launch parameters from the autotuner (packet-id prefix of the workload, untimed)
+        t_tune = time.perf_counter()
+        if a.workload == "disc":
+            ctx.set_temperature(m, t0_disc)
+        tune_src = dust_src if a.workload == "disc" else w.sources
+        params, rate = ctx.autotune(tune_src, seed=w.seed, precision=rt.FP32_LOCAL,
+                                    schedule=a.schedule, sample_fraction=0.125,
+                                    cache=a.tune_cache, rr_threshold=w.rr_threshold,
+                                    rr_prob=w.rr_prob)
+        tuned = dict(params, sample_crossings_per_s=rate, seconds=time.perf_counter() - t_tune)
+        kw32.update(params)
 
     def step(precision, it):
         kwp = kw32 if precision == rt.FP32_LOCAL else kw
@@ -248,10 +266,11 @@ def main():
         "post_trace_ms": 1e3 * sum(post) / len(post),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "blk_pass_kernel<%d>" % (a.block or 768) if a.schedule == 0
-                               else "trace_fp32_kernel<%d>" % (a.block or 256),
+                     "kernel": "blk_pass_kernel<%d>" % (kw32["block_size"] or 768) if a.schedule == 0
+                               else "trace_fp32_kernel<%d>" % (kw32["block_size"] or 256),
                      "launches_per_step": launches, "avg_launch_ms": 1e3 * main_launch_s,
                      "bytes_per_crossing": BYTES_PER_CROSSING_FP32},
+        "autotune": tuned,
         "fp64": fp64,
         "accuracy": acc if fp64 is not None else None,
         "cpu_baseline": cpu,

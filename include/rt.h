@@ -144,7 +144,9 @@ typedef struct {
   double rr_threshold;      /* roulette when w < rr_threshold * w0 (relative); 0 = off */
   double rr_prob;           /* kill probability p; survivors scaled by 1/(1-p) */
   int64_t max_events;       /* per-packet scattering cap; 0 = 1e6 */
-  int32_t block_size;       /* threads per block (multiple of 64, <= 1024); 0 = default */
+  int32_t block_size;       /* threads per block; 0 = default.  FP64: 64, 128, 256 (default
+                               256); FP32-local one queue: 64-512 (256); FP32-local regions:
+                               256, 512, 768, 1024 (768) */
   int32_t blocks_per_cu;    /* persistent form: resident blocks per CU; 0 = default */
   float refill_threshold;   /* FP32-local form: service events/refills when fewer than this
                                fraction of live lanes are crossing; 0 = default */
@@ -216,6 +218,23 @@ rt_status rt_lambda_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_
 rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32_t npix,
                         double width, int32_t n_sel, const int32_t* lambda_idx,
                         int32_t precision, double* image, uint64_t* crossings);
+
+/* Autotuner for the launch parameters of rt_trace_packets (the FP32-local form's block size,
+ * blocks per CU, refill threshold, tail rounds, packets per work item and packets emitted
+ * per sweep; the FP64 form's block size).  Traces a packet-id prefix of every source
+ * (sample_fraction of its packets, at least 2^16 per wavelength where available) for each
+ * candidate of one parameter at a time, holding the others at the best so far, and keeps
+ * the configuration with the most crossings per second of device time (best of two runs).
+ * base: the options to start from (precision and schedule select what is tuned; zero fields
+ * start at the library defaults); best receives base with the tuned fields filled in;
+ * best_rate (may be NULL) the crossings per second of the sample.  cache_path (may be NULL):
+ * a text file of earlier results keyed by the workload signature (device CU count, form,
+ * sample fraction, model sizes, sources); a hit returns the cached result without tracing,
+ * a miss appends the new result.  Uses the context's trace buffers; models, dust and
+ * temperatures are unchanged. */
+rt_status rt_autotune(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_trace_opts* base,
+                      double sample_fraction, const char* cache_path, rt_trace_opts* best,
+                      double* best_rate);
 
 /* Diagnostic: Philox4x32-10 blocks for explicit counters ctr[n][4] -> out[n][4] (host or
  * device), computed on the GPU with the transport kernels' generator. */

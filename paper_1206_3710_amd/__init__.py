@@ -24,7 +24,8 @@ SCHED_REGIONS, SCHED_GLOBAL = 0, 1
 
 EXPORTS = ["rt_last_error", "rt_create", "rt_destroy", "rt_build_tree", "rt_get_model_info",
            "rt_get_sizes", "rt_locate", "rt_set_dust", "rt_set_temperature", "rt_trace_packets",
-           "rt_solve_temperature", "rt_lambda_iterate", "rt_render_map", "rt_philox"]
+           "rt_solve_temperature", "rt_lambda_iterate", "rt_render_map", "rt_autotune",
+           "rt_philox"]
 
 
 class RTError(RuntimeError):
@@ -101,6 +102,7 @@ def lib():
             "rt_solve_temperature": (I32, [P, I32, P, D, D, P]),
             "rt_lambda_iterate": (I32, [P, I32, I32, P, P, I64, I32, D, D, D, P, P, P]),
             "rt_render_map": (I32, [P, I32, P, I32, D, I32, P, I32, P, P]),
+            "rt_autotune": (I32, [P, I32, P, P, D, C.c_char_p, P, P]),
             "rt_philox": (I32, [P, U32, U32, I64, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -264,6 +266,39 @@ class Context:
         t = torch.empty(self.models[model], dtype=torch.float64, device=self.tdev)
         self._check(lib().rt_solve_temperature(self.h, model, _ptr(a), t_min, t_max, _ptr(t)))
         return t
+
+    def autotune(self, sources: Sequence, seed: int, precision: int = FP32_LOCAL,
+                 schedule: int = SCHED_REGIONS, sample_fraction: float = 0.125,
+                 cache: Optional[str] = None, iteration: int = 0, rr_threshold: float = 0.0,
+                 rr_prob: float = 0.0, **start):
+        """Tune the launch parameters of trace_packets on a packet prefix of ``sources``.
+        Returns (keyword arguments for trace_packets, crossings per second of the sample)."""
+        n = len(sources)
+        arr = (Source * n)()
+        keep = []
+        for i, s in enumerate(sources):
+            pw = None
+            if s.power is not None:
+                pw = np.ascontiguousarray(s.power, dtype=np.float64)
+                keep.append(pw)
+            arr[i] = Source(int(s.kind), int(s.model), (C.c_double * 3)(*s.pos),
+                            (C.c_double * 3)(*s.dir), None if pw is None else _ptr(pw).value,
+                            int(s.packets))
+        base = TraceOpts(seed, iteration, precision, rr_threshold, rr_prob,
+                         start.get("max_events", 0), start.get("block_size", 0),
+                         start.get("blocks_per_cu", 0), start.get("refill_threshold", 0.0),
+                         schedule, start.get("chunk_packets", 0), start.get("tail_park", 0),
+                         start.get("batch_packets", 0), 0, None)
+        best = TraceOpts()
+        rate = C.c_double()
+        self._check(lib().rt_autotune(self.h, n, arr, C.byref(base), sample_fraction,
+                                      None if cache is None else cache.encode(), C.byref(best),
+                                      C.byref(rate)))
+        tuned = {"block_size": best.block_size, "blocks_per_cu": best.blocks_per_cu,
+                 "refill_threshold": round(best.refill_threshold, 6),
+                 "chunk_packets": best.chunk_packets, "tail_park": best.tail_park,
+                 "batch_packets": best.batch_packets}
+        return tuned, rate.value
 
     def lambda_iterate(self, model: int, sources: Sequence, seed: int, dust_packets: int,
                        n_max: int = 30, tol: float = 1e-3, t_min: float = 2.0,

@@ -774,9 +774,13 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   const bool region_sched = o->precision == RT_FP32_LOCAL && o->schedule == RT_SCHED_REGIONS;
   // defaults from tuning on the molecular-cloud workload
   const int bs = o->block_size ? o->block_size : (region_sched ? 768 : 256);
-  if (bs != 64 && bs != 128 && bs != 256 && !(bs >= 512 && bs <= 1024 && o->precision == RT_FP32_LOCAL &&
-                                                 (bs == 512 || o->schedule == RT_SCHED_REGIONS)))
-    return fail(ctx, RT_EINVAL, "block_size must be 64, 128, 256 (or 512 for the FP32 form)");
+  const bool bs_ok = region_sched ? (bs == 256 || bs == 512 || bs == 768 || bs == 1024)
+                    : o->precision == RT_FP32_LOCAL ? (bs == 64 || bs == 128 || bs == 256 || bs == 512)
+                                                     : (bs == 64 || bs == 128 || bs == 256);
+  if (!bs_ok)
+    return fail(ctx, RT_EINVAL,
+                "block_size must be 64, 128 or 256 (FP64), 64-512 (FP32-local, one queue) or "
+                "256, 512, 768, 1024 (FP32-local, regions)");
   if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return fail(ctx, RT_EINVAL, "bad blocks_per_cu");
   if (!(o->refill_threshold >= 0.0f && o->refill_threshold <= 1.0f))
     return fail(ctx, RT_EINVAL, "refill_threshold must be in [0, 1]");
@@ -1365,6 +1369,177 @@ rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32
     HIPCHK(hipMemcpyAsync(&cr, ctx->counter.p, 8, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (crossings) *crossings = cr;
+    return RT_OK;
+  })
+}
+
+// ---- autotuner ------------------------------------------------------------------------
+// Coordinate search over the launch parameters of the requested form: every candidate value of
+// one parameter is timed with the others held at the best so far (device time of the whole
+// trace, HIP events, best of two runs) on a packet-id prefix of every source; parameters are
+// visited in order of their measured influence.  Results are cached per workload signature.
+
+static std::string tune_signature(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_trace_opts* o,
+                                  double frac) {
+  char buf[256];
+  std::string s;
+  snprintf(buf, sizeof buf, "cu%d p%d s%d f%.6g", ctx->n_cu, o->precision, o->schedule, frac);
+  s += buf;
+  for (size_t m = 0; m < ctx->models.size(); ++m) {
+    const HostModel& h = ctx->models[m];
+    snprintf(buf, sizeof buf, " m%lld.%d.%d", (long long)h.n_nodes, h.nlev, h.nl);
+    s += buf;
+  }
+  for (int32_t i = 0; i < n_src; ++i) {
+    snprintf(buf, sizeof buf, " s%d.%d.%lld", (int)src[i].kind, src[i].model, (long long)src[i].packets_per_lambda);
+    s += buf;
+  }
+  return s;
+}
+
+static bool tune_cache_lookup(const char* path, const std::string& sig, rt_trace_opts* t, double* rate) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[4096];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char* bar = strchr(line, '|');
+    if (!bar) continue;
+    *bar = 0;
+    if (sig != line) continue;
+    int bs, bpc, tail, chunk;
+    float thr;
+    long long batch;
+    double rt_;
+    if (sscanf(bar + 1, "%d %d %f %d %d %lld %lf", &bs, &bpc, &thr, &tail, &chunk, &batch, &rt_) == 7) {
+      t->block_size = bs;
+      t->blocks_per_cu = bpc;
+      t->refill_threshold = thr;
+      t->tail_park = tail;
+      t->chunk_packets = chunk;
+      t->batch_packets = batch;
+      *rate = rt_;
+      found = true;  // the last matching line wins
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+rt_status rt_autotune(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_trace_opts* base,
+                      double sample_fraction, const char* cache_path, rt_trace_opts* best,
+                      double* best_rate) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (!base || !best || !src || n_src <= 0) return fail(ctx, RT_EINVAL, "null argument");
+    if (!(sample_fraction > 0.0) || sample_fraction > 1.0)
+      return fail(ctx, RT_EINVAL, "sample_fraction must be in (0, 1]");
+    HIPCHK(hipSetDevice(ctx->device));
+    const std::string sig = tune_signature(ctx, n_src, src, base, sample_fraction);
+    rt_trace_opts cur = *base;
+    cur.rec_stride = 0;
+    cur.records = nullptr;
+    double rate = 0.0;
+    if (tune_cache_lookup(cache_path, sig, &cur, &rate)) {
+      cur.rec_stride = base->rec_stride;
+      cur.records = base->records;
+      *best = cur;
+      if (best_rate) *best_rate = rate;
+      return RT_OK;
+    }
+    // packet-id prefix of every source (at least 2^16 packets per wavelength when available)
+    std::vector<rt_source> sample(src, src + n_src);
+    for (auto& s : sample) {
+      const int64_t n = s.packets_per_lambda;
+      int64_t k = (int64_t)std::ceil((double)n * sample_fraction);
+      k = std::max<int64_t>(k, std::min<int64_t>(n, 65536));
+      s.packets_per_lambda = std::max<int64_t>(1, std::min(n, k));
+    }
+    int64_t tn, tl, tln;
+    totals(ctx, &tn, &tl, &tln);
+    TraceOut out;
+    HIPCHK(ctx->out_node.ensure(8 * std::max<int64_t>(tn, 1)));
+    HIPCHK(ctx->out_esc.ensure(8 * std::max<int64_t>(tl, 1)));
+    out.e_node = ctx->out_node.as<double>();
+    out.e_esc = ctx->out_esc.as<double>();
+    auto measure = [&](const rt_trace_opts& t, double* r) -> rt_status {
+      double bestv = 0.0;
+      for (int rep = 0; rep < 2; ++rep) {
+        rt_trace_stats st;
+        if (rt_status e = trace_impl(ctx, n_src, sample.data(), &t, out, &st)) return e;
+        if (st.kernel_ms > 0.0) bestv = std::max(bestv, (double)st.crossings / (st.kernel_ms * 1e-3));
+      }
+      *r = bestv;
+      return RT_OK;
+    };
+    // starting point: the library defaults made explicit
+    const bool regions = base->precision == RT_FP32_LOCAL && base->schedule == RT_SCHED_REGIONS;
+    const bool global32 = base->precision == RT_FP32_LOCAL && !regions;
+    if (regions) {
+      if (!cur.block_size) cur.block_size = 768;
+      if (!cur.blocks_per_cu) cur.blocks_per_cu = 1;
+      if (!(cur.refill_threshold > 0.0f)) cur.refill_threshold = 0.15f;
+      if (!cur.tail_park) cur.tail_park = 16;
+      if (!cur.chunk_packets) cur.chunk_packets = 16 * cur.block_size;
+      if (!cur.batch_packets) cur.batch_packets = int64_t(1) << 23;
+    } else if (global32) {
+      if (!cur.block_size) cur.block_size = 256;
+      if (!(cur.refill_threshold > 0.0f)) cur.refill_threshold = 0.5f;
+    } else if (!cur.block_size) {
+      cur.block_size = 256;
+    }
+    if (rt_status e = measure(cur, &rate)) return e;
+    struct Axis {
+      int kind;
+      std::vector<double> v;
+    };
+    std::vector<Axis> axes;
+    if (regions) {
+      axes = {{0, {512, 768, 1024}},   {2, {0.08, 0.15, 0.25}}, {4, {8, 16, 32}},
+              {3, {8, 16, 32, -1}},    {5, {22, 23, 24}}};
+    } else if (global32) {
+      axes = {{0, {64, 128, 256, 512}}, {2, {0.25, 0.5, 0.75}}, {1, {1, 2, 4}}};
+    } else {
+      axes = {{0, {64, 128, 256}}};
+    }
+    for (const Axis& ax : axes) {
+      rt_trace_opts keep = cur;
+      for (double v : ax.v) {
+        rt_trace_opts t = keep;
+        switch (ax.kind) {
+          case 0: {
+            const int old = t.block_size;
+            t.block_size = (int)v;
+            if (regions) t.chunk_packets = t.chunk_packets / old * t.block_size;
+            break;
+          }
+          case 1: t.blocks_per_cu = (int)v; break;
+          case 2: t.refill_threshold = (float)v; break;
+          case 3: t.tail_park = (int)v; break;
+          case 4: t.chunk_packets = (int)v * t.block_size; break;
+          case 5: t.batch_packets = int64_t(1) << (int)v; break;
+        }
+        if (memcmp(&t, &keep, sizeof t) == 0) continue;
+        double rv = 0.0;
+        if (rt_status e = measure(t, &rv)) return e;
+        if (rv > rate) {
+          rate = rv;
+          cur = t;
+        }
+      }
+    }
+    if (cache_path) {
+      if (FILE* f = fopen(cache_path, "a")) {
+        fprintf(f, "%s|%d %d %.6g %d %d %lld %.9g\n", sig.c_str(), cur.block_size, cur.blocks_per_cu,
+                (double)cur.refill_threshold, cur.tail_park, cur.chunk_packets, (long long)cur.batch_packets, rate);
+        fclose(f);
+      }
+    }
+    cur.rec_stride = base->rec_stride;
+    cur.records = base->records;
+    *best = cur;
+    if (best_rate) *best_rate = rate;
     return RT_OK;
   })
 }

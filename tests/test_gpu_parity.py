@@ -402,3 +402,30 @@ def test_region_tail_parking(torch):
         assert np.array_equal(ra[f], rb[f]), f
     ea, eb = a["e_abs_node"].cpu().numpy(), b["e_abs_node"].cpu().numpy()
     assert rel_rms(eb, ea) < 1e-5
+
+
+def test_autotune_and_cache(torch, tmp_path):
+    """The autotuner returns candidate launch parameters, a second call is answered from its
+    cache file, and tracing with the tuned parameters gives the same histories as the
+    defaults (launch parameters change only the processing order)."""
+    w = gen.c2(n_root=24, max_level=3, n_lambda=4, packets=40000)
+    ctx = new_ctx(torch)
+    m = ctx.build_tree(w.trees[0])
+    ctx.set_dust(m, w.dusts[0])
+    cache = str(tmp_path / "tune.txt")
+    kw = dict(seed=w.seed, rr_threshold=w.rr_threshold, rr_prob=w.rr_prob)
+    p1, r1 = ctx.autotune(w.sources, precision=rt.FP32_LOCAL, sample_fraction=0.5, cache=cache, **kw)
+    assert r1 > 0
+    assert p1["block_size"] in (512, 768, 1024) and p1["blocks_per_cu"] == 1
+    assert p1["tail_park"] in (8, 16, 32, -1) and p1["chunk_packets"] % p1["block_size"] == 0
+    p2, r2 = ctx.autotune(w.sources, precision=rt.FP32_LOCAL, sample_fraction=0.5, cache=cache, **kw)
+    assert p2 == p1 and r2 == pytest.approx(r1, rel=1e-6)
+    assert len(open(cache).read().strip().splitlines()) == 1
+    a = ctx.trace_packets(w.sources, precision=rt.FP32_LOCAL, **kw)
+    b = ctx.trace_packets(w.sources, precision=rt.FP32_LOCAL, **kw, **p1)
+    for k in ("crossings", "scatterings", "kills", "packets"):
+        assert a["stats"][k] == b["stats"][k], k
+    ea, eb = a["e_abs_node"].cpu().numpy(), b["e_abs_node"].cpu().numpy()
+    assert rel_rms(eb, ea) < 1e-5
+    p64, _ = ctx.autotune(w.sources, precision=rt.FP64, sample_fraction=0.25, **kw)
+    assert p64["block_size"] in (64, 128, 256)
