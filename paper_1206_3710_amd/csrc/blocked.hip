@@ -269,7 +269,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   bool pool_done = false;      // this item's packets are all taken (wave-uniform)
   int tail_it = 0;             // crossing rounds since then (wave-uniform)
   const uint32_t own_key = (uint32_t)it.slot * (uint32_t)b.n_regions + (uint32_t)it.region;
-  uint32_t xkey = 0;
+  uint32_t xkey = 0;  // leaving: internal id of the root cell entered (its region is looked up
+                      // when the record is written, outside the crossing loop)
 
   for (;;) {
     // ---------------- refill from this item's queue ----------------
@@ -422,7 +423,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
                 leave = true;
                 xax = ax;
                 xsg = sg;
-                xkey = (uint32_t)it.slot * (uint32_t)b.n_regions + (uint32_t)b.root_region[D.root(R0, R1, R2)];
+                xkey = (uint32_t)D.root(R0, R1, R2);
                 state = B_EXIT;
               } else {
                 cur = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
@@ -454,7 +455,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
     if (pool_done && tail_it >= b.tail_park && state == B_CROSS) {
       state = B_EXIT;
       xpark = true;
-      xkey = own_key;
+      xkey = 0;
     }
     const uint64_t ex = __ballot(state == B_EXIT);
     if (ex) {
@@ -494,7 +495,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         rc.ev = ev;
         rc.ncross = ncross;
         b.u_out[idx] = rc;
-        b.u_key[idx] = xkey;
+        b.u_key[idx] = xpark ? own_key
+                             : (uint32_t)it.slot * (uint32_t)b.n_regions + (uint32_t)b.root_region[xkey];
         xpark = false;
         state = B_EMPTY;
       }
