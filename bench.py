@@ -46,6 +46,9 @@ WORKLOADS = {
             "temperatures of A_stars + A_dust",
     "clouds": "64 uneven clouds (roots 16^3-48^3, 1-4 levels), 16 wavelengths, %d packets per "
               "(model, wavelength), one trace call",
+    "deep": "deep-hierarchy cloud: root 256^3, 5 levels (1.13e8 nodes, 1.0e8 leaves), 64 cores of "
+            "central tau_V 1e3, 100 wavelengths, %d packets/wavelength, roulette 1e-3/0.9, dust "
+            "temperatures, 512^2 maps toward the 8 body diagonals at 100 wavelengths",
 }
 
 
@@ -63,9 +66,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["cloud", "disc", "clouds"], default="cloud")
+    ap.add_argument("--workload", choices=["cloud", "disc", "clouds", "deep"], default="cloud")
     ap.add_argument("--packets", type=int, default=0,
-                    help="packets per wavelength (0: 1e7 cloud, 3e7 disc, 1e6 clouds)")
+                    help="packets per wavelength (0: 1e7 cloud and deep, 3e7 disc, 1e6 clouds)")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-packets", type=int, default=1 << 18,
@@ -107,6 +110,8 @@ def main():
         w = gen.c2(packets=a.packets or 10_000_000)
     elif a.workload == "disc":
         w = gen.c3(packets=a.packets or 30_000_000)
+    elif a.workload == "deep":
+        w = gen.c5(packets=a.packets or 10_000_000)
     else:
         w = gen.c4(packets=a.packets or 1_000_000)
     tree, dust = w.trees[0], w.dusts[0]
@@ -153,7 +158,7 @@ def main():
         t = time.perf_counter()
         out = {"stats": r["stats"], "e_abs": r["e_abs_node"]}
         if not a.trace_only:
-            if a.workload == "cloud":
+            if a.workload in ("cloud", "deep"):
                 ctx.solve_temperature(m, r["e_abs_node"], 2.0, 3000.0)
                 for d in w.map_dirs:
                     ctx.render_map(m, d, w.map_npix, lam_all)
@@ -231,7 +236,8 @@ def main():
         ora = oracle.Model(tree, dust)
         src0 = [gen.Source(w.sources[0].kind, 0, pos=w.sources[0].pos, power=w.sources[0].power,
                            packets=w.sources[0].packets)]
-        what = {"cloud": "", "disc": " of the star", "clouds": " of the first model"}[a.workload]
+        what = {"cloud": "", "disc": " of the star", "clouds": " of the first model",
+                "deep": ""}[a.workload]
         t2 = time.perf_counter()
         _, _, sto, _ = ora.trace(src0, seed=w.seed, rr_threshold=w.rr_threshold,
                                  rr_prob=w.rr_prob, pid_end=a.cpu_packets)

@@ -387,6 +387,76 @@ def c4(seed: int = BASE_SEED + 4, n_models: int = 64, n_lambda: int = 16,
     return Workload("c4", trees, dusts, srcs, seed, rr_threshold=1e-3, rr_prob=0.9)
 
 
+# ----------------------------------------------------------------------------------------
+# C5: large deep-hierarchy cloud
+# ----------------------------------------------------------------------------------------
+
+def c5(seed: int = BASE_SEED + 5, n_root: int = 256, max_level: int = 5, n_lambda: int = 100,
+       packets: int = 10_000_000, sigma_ln: float = 2.0, spectral_index: float = -3.6,
+       mean_tau_v: float = 1.0, size_pc: float = 8.0, kappa_v: float = 200.0,
+       n_cores: int = 64, core_rc=(1.0, 4.0), core_tau: float = 1.0e3,
+       tau_split: float = 6.0, map_npix: int = 512) -> Workload:
+    """Large deep-hierarchy cloud: root 256^3 fBm log-normal field (P(k) ~ k^-3.6,
+    sigma_ln 2, mean V-band tau across the cube 1) plus 64 Plummer-like cores
+    rho_c / (1 + r^2/r_c^2)^2 (r_c uniform in 1-4 root cells, seeded centres) whose central
+    column tau_V = pi/2 kappa_V rho_c r_c is 1e3, point-sampled at root-cell centres; refined
+    top-down while the V-band cell optical depth exceeds ``tau_split`` (at most 5 levels),
+    children from the mass-conserving cascade.  The default ``tau_split`` gives 1.009e8 leaves
+    (1.129e8 nodes) for the default seed (found with ``c5_tau_split_for``).  100 wavelengths, isotropic field,
+    1e7 packets per wavelength, maps 512^2 toward the 8 body diagonals."""
+    rng = np.random.default_rng(seed)
+    g, top_frac = power_law_field(rng, n_root, spectral_index)
+    rho = np.exp(sigma_ln * g - 0.5 * sigma_ln * sigma_ln)          # [z, y, x]
+    cell_cm = size_pc * PC_CM / n_root
+    rho *= mean_tau_v / (kappa_v * rho.mean() * n_root * cell_cm)
+    cores = []
+    ax = np.arange(n_root) + 0.5
+    for _ in range(n_cores):
+        c = rng.uniform(0.0, n_root, 3)
+        rc = rng.uniform(core_rc[0], core_rc[1])
+        rho_c = core_tau / (kappa_v * 0.5 * np.pi * rc * cell_cm)
+        cores.append((c, rc, rho_c))
+        h = int(np.ceil(12 * rc))
+        lo = np.maximum(np.floor(c - h).astype(int), 0)
+        hi = np.minimum(np.ceil(c + h).astype(int), n_root)
+        dz = ax[lo[2]:hi[2], None, None] - c[2]
+        dy = ax[None, lo[1]:hi[1], None] - c[1]
+        dx = ax[None, None, lo[0]:hi[0]] - c[0]
+        r2 = (dx * dx + dy * dy + dz * dz) / (rc * rc)
+        rho[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] += rho_c / (1.0 + r2) ** 2
+    rho = rho.reshape(-1)
+    var_top = sigma_ln * sigma_ln * top_frac
+    tree = _refine_top_down(rng, n_root, n_root, n_root, cell_cm, rho, max_level,
+                            lambda lvl, r: kappa_v * r * cell_cm * 2.0 ** -lvl > tau_split,
+                            lambda lvl: np.sqrt(var_top * 2.0 ** (-0.6 * (lvl + 1))))
+    dust = shared_dust(n_lambda, kappa_v)
+    bg = background_spectrum(dust.lambda_um)
+    src = [Source(SRC_BACKGROUND, 0, power=bg, packets=packets)]
+    s3 = 1.0 / np.sqrt(3.0)
+    dirs = [(sx * s3, sy * s3, sz * s3) for sx in (1, -1) for sy in (1, -1) for sz in (1, -1)]
+    return Workload("c5", [tree], [dust], src, seed, rr_threshold=1e-3, rr_prob=0.9,
+                    map_dirs=dirs, map_npix=map_npix,
+                    meta={"cores": [(tuple(c), rc, rho_c) for c, rc, rho_c in cores],
+                          "tau_split": tau_split, "size_pc": size_pc})
+
+
+def c5_tau_split_for(leaves: float = 1.0e8, seed: int = BASE_SEED + 5, tol: float = 0.1,
+                     **kw) -> float:
+    """Bisection (in log tau_split) for the split threshold that gives ``leaves`` leaf cells
+    within ``tol``; each probe builds the whole tree."""
+    lo, hi = 0.1, 100.0
+    for _ in range(40):
+        mid = float(np.sqrt(lo * hi))
+        n = c5(seed=seed, tau_split=mid, packets=1, **kw).trees[0].n_leaves
+        if abs(n / leaves - 1.0) <= tol:
+            return mid
+        if n > leaves:
+            lo = mid
+        else:
+            hi = mid
+    return float(np.sqrt(lo * hi))
+
+
 def random_tree(rng, root=(2, 2, 2), max_level=3, p_refine=0.35, cell_cm=1.0,
                 rho_range=(0.0, 2.0), uniform_rho=None) -> TreeDesc:
     """Small random tree for brute-force checks: each cell refined with probability p_refine

@@ -175,7 +175,7 @@ class Model:
 
     def trace(self, sources, seed, iteration=0, model_index=0, rr_threshold=0.0, rr_prob=0.0,
               max_events=0, per_lambda=False, pid_begin=0, pid_end=-1, lam_sel=-1,
-              t_node=None, rec_stride=0):
+              t_node=None, rec_stride=0, deposits=True):
         """Follow packets of ``sources`` (gen.Source list) -> (e_abs, e_esc, stats, records)."""
         L = lib()
         ns = len(sources)
@@ -188,7 +188,7 @@ class Model:
             if s.power is not None:
                 power[i * nl:(i + 1) * nl] = s.power
         packets = np.array([s.packets for s in sources], dtype=np.int64)
-        e_abs = np.zeros(self.n_nodes * (nl if per_lambda else 1))
+        e_abs = np.zeros(self.n_nodes * (nl if per_lambda else 1)) if deposits else None
         e_esc = np.zeros(nl)
         st = Stats()
         tn = None if t_node is None else np.ascontiguousarray(t_node, dtype=np.float64)
@@ -200,11 +200,12 @@ class Model:
         rc = L.om_trace(self.h, model_index, ns, _p(kind), _p(pos), _p(dirs), _p(power),
                         _p(packets), None if tn is None else _p(tn), C.c_uint64(seed),
                         iteration, rr_threshold, rr_prob, max_events, int(per_lambda),
-                        pid_begin, pid_end, lam_sel, _p(e_abs), _p(e_esc), C.byref(st),
+                        pid_begin, pid_end, lam_sel, None if e_abs is None else _p(e_abs),
+                        _p(e_esc), C.byref(st),
                         rec_stride, None if rec is None else _p(rec))
         if rc != 0:
             raise OracleError(L.om_error().decode())
-        if per_lambda:
+        if per_lambda and e_abs is not None:
             e_abs = e_abs.reshape(nl, self.n_nodes)
         return e_abs, e_esc, st.as_dict(), rec
 

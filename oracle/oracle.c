@@ -369,7 +369,8 @@ typedef struct {
   int lam;
   double rr_thr, rr_p;
   int64_t max_events;
-  double* e_abs;            /* already offset for the wavelength if per-lambda */
+  double* e_abs;            /* already offset for the wavelength if per-lambda; NULL: only totalled */
+  double e_abs_total;       /* sum of the deposits when e_abs is NULL */
   double* e_esc;
   om_stats* st;
 } tctx;
@@ -441,7 +442,8 @@ static int propagate(tctx* c, packet* p) {
     }
     if (sa > 0.0 && s > 0.0) {
       double de = p->w * (-expm1(-(sa * s)));
-      c->e_abs[p->node] += de;
+      if (c->e_abs) c->e_abs[p->node] += de;
+      else c->e_abs_total += de;
       p->w = p->w - de;
     }
     for (int b = 0; b < 3; ++b) p->P[b] = fma(s, p->d[b], p->P[b]);
@@ -587,6 +589,8 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
   c.max_events = max_events > 0 ? max_events : 1000000;
   c.e_esc = e_esc;
   c.st = stats;
+  c.e_abs = NULL;
+  c.e_abs_total = 0.0;
   for (int s = 0; s < n_src; ++s) {
     const int64_t N = packets[s];
     int64_t jb = pid_begin < 0 ? 0 : pid_begin;
@@ -602,7 +606,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
       if (lam_sel >= 0 && lam != lam_sel) continue;
       c.lam = lam;
       c.stream = ((uint32_t)model_index << 20) | ((uint32_t)s << 12) | (uint32_t)lam;
-      c.e_abs = per_lambda ? e_abs + (int64_t)lam * nn : e_abs;
+      c.e_abs = e_abs ? (per_lambda ? e_abs + (int64_t)lam * nn : e_abs) : NULL;
       double w0 = 0.0;
       dust_cdf dc;
       memset(&dc, 0, sizeof dc);
@@ -697,7 +701,10 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
   }
   double ea = 0.0, ee = 0.0;
   int64_t ntot = per_lambda ? nn * nl : nn;
-  for (int64_t i = 0; i < ntot; ++i) ea += e_abs[i];
+  if (e_abs)
+    for (int64_t i = 0; i < ntot; ++i) ea += e_abs[i];
+  else
+    ea = c.e_abs_total;
   for (int i = 0; i < nl; ++i) ee += e_esc[i];
   stats->e_abs = ea;
   stats->e_esc = ee;

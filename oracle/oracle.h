@@ -72,7 +72,8 @@ typedef struct {
  * 0..packets[s]-1 of stream (model<<20 | s<<12 | i) are followed.  power[s*n_lambda + i]
  * is the background intensity times nothing (I_nu, per Hz) or the source luminosity L_nu;
  * DUST sources take the temperatures t_node (canonical, leaves) instead.
- * e_abs: [n_nodes] (lambda-integrated) or [n_lambda*n_nodes] if per_lambda.
+ * e_abs: [n_nodes] (lambda-integrated) or [n_lambda*n_nodes] if per_lambda; NULL to only
+ * total the deposits in stats (single-packet replays on large trees).
  * e_esc: [n_lambda].  rec (optional): one record per sampled packet, packet index j of
  * (source s, wavelength i) is sampled when j % rec_stride == 0 and stored at
  * (s*n_lambda + i)*nrec + (j-pid_begin)/rec_stride with nrec = ceil((pid_end-pid_begin)/rec_stride);
