@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (it runs, untimed, unless launch parameters are given)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay captured graphs of the sweeps (no per-launch durations)")
     ap.add_argument("--trace-only", action="store_true", help="time only the transport step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 4 GiB device-to-device (reference for traffic counters)")
@@ -125,7 +127,7 @@ def main():
     kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob, block_size=a.block,
               blocks_per_cu=a.blocks_per_cu, refill_threshold=a.refill)
     kw32 = dict(kw, schedule=a.schedule, chunk_packets=a.chunk, batch_packets=a.batch,
-                tail_park=a.tail_park)
+                tail_park=a.tail_park, sweep_graph=1 if a.graph else 0)
     if a.workload == "disc":
         # constant sources once (FP64 form), then every timed step re-emits from T_0
         a_stars = ctx.trace_packets(w.sources, seed=w.seed, iteration=0, precision=rt.FP64,
@@ -193,9 +195,12 @@ def main():
     # dominant kernel: per-launch durations from HIP events on its own stream (summed by the
     # library), algorithmic bytes = crossings handled x bytes per crossing
     launches = sum(main_n) / a.steps
-    main_launch_s = sum(main_ms) / sum(main_n) / 1e3
     bytes_per_launch = cr_step / launches * BYTES_PER_CROSSING_FP32
-    achieved = bytes_per_launch / main_launch_s / 1e9
+    if sum(main_ms) > 0:
+        main_launch_s = sum(main_ms) / sum(main_n) / 1e3
+        achieved = bytes_per_launch / main_launch_s / 1e9
+    else:  # replayed sweep graphs report no per-launch durations
+        main_launch_s, achieved = float("nan"), float("nan")
     traffic = None
     if a.workload == "cloud" and a.schedule == 0 and pass_sources_sha() == PASS_TRAFFIC["sha256"]:
         traffic = cr_step / launches * (PASS_TRAFFIC["fetch_bytes_per_crossing"]

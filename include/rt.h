@@ -163,6 +163,10 @@ typedef struct {
                                j % rec_stride == 0 */
   rt_record* records;       /* host or device; job-major: job (source-major, then wavelength)
                                base = sum over earlier jobs of ceil(N/rec_stride) */
+  int32_t sweep_graph;      /* region schedule: > 0 replays a captured HIP graph of 16 sweeps
+                               until the queues drain (per-pass durations are then not
+                               reported); <= 0 (default) launches the same kernels directly */
+  int32_t pad2;
 } rt_trace_opts;
 
 typedef struct {

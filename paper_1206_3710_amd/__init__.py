@@ -59,7 +59,8 @@ class TraceOpts(C.Structure):
                 ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_threshold", C.c_float), ("schedule", C.c_int32),
                 ("chunk_packets", C.c_int32), ("tail_park", C.c_int32), ("batch_packets", C.c_int64),
-                ("rec_stride", C.c_int64), ("records", C.c_void_p)]
+                ("rec_stride", C.c_int64), ("records", C.c_void_p), ("sweep_graph", C.c_int32),
+                ("pad2", C.c_int32)]
 
 
 class TraceStats(C.Structure):
@@ -220,7 +221,8 @@ class Context:
                       rr_threshold: float = 0.0, rr_prob: float = 0.0, max_events: int = 0,
                       block_size: int = 0, blocks_per_cu: int = 0, refill_threshold: float = 0.0,
                       rec_stride: int = 0, per_lambda: bool = False, schedule: int = SCHED_REGIONS,
-                      chunk_packets: int = 0, batch_packets: int = 0, tail_park: int = 0):
+                      chunk_packets: int = 0, batch_packets: int = 0, tail_park: int = 0,
+                      sweep_graph: int = 0):
         """Trace the packets of ``sources`` (objects with kind, model, pos, dir, power,
         packets).  Returns a dict of device tensors and the statistics."""
         torch = _torch()
@@ -249,7 +251,8 @@ class Context:
                               device=self.tdev)
         opts = TraceOpts(seed, iteration, precision, rr_threshold, rr_prob, max_events, block_size,
                          blocks_per_cu, refill_threshold, schedule, chunk_packets, tail_park,
-                         batch_packets, rec_stride, None if rec is None else rec.data_ptr())
+                         batch_packets, rec_stride, None if rec is None else rec.data_ptr(),
+                         sweep_graph, 0)
         st = TraceStats()
         self._check(lib().rt_trace_packets(self.h, n, arr, C.byref(opts), _ptr(e_node),
                                            _ptr(e_lam), _ptr(e_esc), C.byref(st)))

@@ -16,8 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhiert.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["runtime.cpp", "trace_fp64.hip", "trace_fp32.hip", "blocked.hip", "misc.hip",
-           "thermal.hip", "render.hip"]
+SOURCES = ["runtime.cpp", "trace_fp64.hip", "trace_fp32.hip", "blocked.hip", "sweep.hip",
+           "misc.hip", "thermal.hip", "render.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -8,8 +8,9 @@
 // each packet with LDS lookups and LDS atomic deposits until the packet leaves the region,
 // escapes or ends, and finally adds the LDS accumulators to the region-major FP32 accumulators
 // with coalesced atomics.  Packets leaving the region are appended to the next sweep's queue
-// (96-byte records); the host sorts each sweep's queue by (wavelength slot, region) and repeats
-// until the queue is empty, streaming in new packets at every sweep.
+// (96-byte records); each sweep's queue is put in (wavelength slot, region) order on the device
+// (sweep.hip) and sweeps repeat until the queue is empty, new packets streaming in at every
+// sweep.
 #include "device.h"
 
 using namespace rtd;
@@ -34,7 +35,8 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 // ------------------------------------------------------------------------------------------
 // emission into the queue
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void blk_emit_kernel(const BlkParams b, uint64_t g0, uint64_t g1) {
+__global__ __launch_bounds__(256) void blk_emit_kernel(const BlkParams b, const SweepState* __restrict__ st) {
+  const uint64_t g0 = st->e0, g1 = st->e0 + st->ne;
   __shared__ uint64_t s_start[RT_JOBS_LDS];
   const TraceParams& p = b.t;
   const bool jobs_lds = p.n_jobs <= RT_JOBS_LDS;
@@ -109,58 +111,6 @@ __global__ __launch_bounds__(256) void blk_emit_kernel(const BlkParams b, uint64
     unsafeAtomicAdd(&p.stats->e_emit, e_emit);
     atomicAdd(&p.stats->packets, npk);
   }
-}
-
-__global__ void blk_iota_kernel(uint32_t n, uint32_t* v) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[i] = i;
-}
-
-// Run boundaries of the sorted keys.
-__global__ void blk_runs_kernel(const uint32_t* __restrict__ k, uint32_t n, int32_t* kstart, int32_t* kend) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t key = k[i];
-  if (i == 0 || k[i - 1] != key) kstart[key] = (int32_t)i;
-  if (i == n - 1 || k[i + 1] != key) kend[key] = (int32_t)i + 1;
-}
-
-// Work items: each run of one (slot, region) key split into chunks (one block).
-__global__ __launch_bounds__(1024) void blk_items_kernel(int32_t n_keys, int32_t n_regions, int32_t chunk,
-                                                         const int32_t* __restrict__ kstart,
-                                                         const int32_t* __restrict__ kend,
-                                                         WorkItem* __restrict__ items,
-                                                         uint32_t* __restrict__ n_items) {
-  __shared__ uint32_t s_sum[1024];
-  uint32_t carry = 0;
-  for (int k0 = 0; k0 < n_keys; k0 += 1024) {
-    const int k = k0 + (int)threadIdx.x;
-    uint32_t cnt = 0, nch = 0;
-    if (k < n_keys) {
-      cnt = (uint32_t)(kend[k] - kstart[k]);
-      nch = (cnt + chunk - 1) / chunk;
-    }
-    s_sum[threadIdx.x] = nch;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const uint32_t v = threadIdx.x >= (unsigned)o ? s_sum[threadIdx.x - o] : 0u;
-      __syncthreads();
-      s_sum[threadIdx.x] += v;
-      __syncthreads();
-    }
-    const uint32_t excl = carry + s_sum[threadIdx.x] - nch;
-    for (uint32_t c = 0; c < nch; ++c) {
-      WorkItem w;
-      w.region = k % n_regions;
-      w.slot = k / n_regions;
-      w.start = (uint32_t)kstart[k] + c * chunk;
-      w.count = min((uint32_t)chunk, cnt - c * chunk);
-      items[excl + c] = w;
-    }
-    carry += s_sum[1023];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *n_items = carry;
 }
 
 // Land in the neighbour after a face crossing: from cell `cur` at level l (an ancestor-level
@@ -666,27 +616,8 @@ __global__ __launch_bounds__(256) void blk_reduce_kernel(const ModelDev* __restr
 
 }  // namespace
 
-hipError_t launch_blk_emit(const BlkParams& b, uint64_t g0, uint64_t g1, hipStream_t s) {
-  const uint64_t n = g1 - g0;
-  hipLaunchKernelGGL(blk_emit_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, g0, g1);
-  return hipGetLastError();
-}
-
-hipError_t launch_blk_iota(uint32_t n, uint32_t* v, hipStream_t s) {
-  hipLaunchKernelGGL(blk_iota_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_blk_items(const uint32_t* skeys, uint32_t n, int32_t n_keys, int32_t n_regions,
-                            int32_t chunk, int32_t* kstart, int32_t* kend, WorkItem* items,
-                            uint32_t* n_items, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(kstart, 0, sizeof(int32_t) * n_keys, s);
-  if (e != hipSuccess) return e;
-  e = hipMemsetAsync(kend, 0, sizeof(int32_t) * n_keys, s);
-  if (e != hipSuccess) return e;
-  if (n > 0) hipLaunchKernelGGL(blk_runs_kernel, dim3((n + 255) / 256), dim3(256), 0, s, skeys, n, kstart, kend);
-  hipLaunchKernelGGL(blk_items_kernel, dim3(1), dim3(1024), 0, s, n_keys, n_regions, chunk, kstart, kend, items,
-                     n_items);
+hipError_t launch_blk_emit(const BlkParams& b, const SweepState* st, uint64_t batch, hipStream_t s) {
+  hipLaunchKernelGGL(blk_emit_kernel, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, b, st);
   return hipGetLastError();
 }
 

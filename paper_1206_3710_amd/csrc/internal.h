@@ -155,11 +155,23 @@ struct BlkParams {
                              // packets still in flight are re-queued (INT32_MAX = never)
 };
 
-hipError_t launch_blk_emit(const BlkParams& b, uint64_t g0, uint64_t g1, hipStream_t s);
-hipError_t launch_blk_iota(uint32_t n, uint32_t* v, hipStream_t s);
-hipError_t launch_blk_items(const uint32_t* skeys, uint32_t n, int32_t n_keys, int32_t n_regions,
-                            int32_t chunk, int32_t* kstart, int32_t* kend, WorkItem* items,
-                            uint32_t* n_items, hipStream_t s);
+// Device-resident state of the sweeps of one trace (all sizes the sweep launches need).
+struct SweepState {
+  unsigned long long count[2];  // records appended to queue buffer 0 / 1
+  unsigned long long emitted;   // packets emitted so far (global packet index)
+  unsigned long long total;     // packets to emit
+  unsigned long long e0, ne;    // this sweep's emission range [e0, e0 + ne)
+  unsigned long long n_in;      // records in this sweep's input buffer
+  uint32_t n_items, item_counter;
+  uint32_t done;                // a sweep found nothing queued and nothing left to emit
+  uint32_t sweeps;              // sweeps that had packets to follow
+  unsigned long long log_in[16];  // records in the input of each sweep of the current block
+};
+
+hipError_t launch_blk_emit(const BlkParams& b, const SweepState* st, uint64_t batch, hipStream_t s);
+hipError_t launch_sweep_sort(SweepState* st, int in, int slot, uint64_t batch, uint64_t capq, const uint32_t* keys,
+                             int n_keys, int n_regions, int chunk, uint32_t* hist, uint32_t* kfill,
+                             uint32_t* perm, WorkItem* items, int grid, hipStream_t s);
 hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s);
 hipError_t attr_blk_pass(int block, int lds_bytes);
 hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, int n_regions,

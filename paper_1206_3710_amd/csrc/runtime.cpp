@@ -92,15 +92,18 @@ struct rt_ctx {
   int64_t reg_G = 0;
   int32_t reg_maxn = 0;
   DevBuf d_regions, d_rword, d_rup, d_rcanon, d_root_region;
-  DevBuf q_rec[2], q_key[2], q_skey, q_perm, q_iota, q_kstart, q_kend, q_items, q_nitems, q_counters,
-      q_sort_tmp;
+  DevBuf q_rec[2], q_key[2], q_perm, q_hist, q_kfill, q_items, q_state;
   int64_t q_capacity = 0;
+  // sweep graph: kSweepBlock sweeps captured once per trace configuration, replayed
+  hipGraphExec_t sweep_exec = nullptr;
+  std::vector<char> sweep_sig;             // launch parameters the graph was captured with
+  std::vector<hipEvent_t> sweep_ev;        // 2 per sweep of the block: around each pass
   std::vector<int32_t> h_reg_nodes;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
   // second stream: emission of the next batch runs beside the region pass
   hipStream_t aux = nullptr;
-  hipEvent_t ev_a = nullptr, ev_b = nullptr;
-  hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr;  // around each region pass
+  hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
+  hipStream_t work = nullptr;  // the sweeps of the region schedule (capturable: never the null stream)
 };
 
 namespace {
@@ -425,8 +428,9 @@ rt_status rt_create(rt_ctx** out, int32_t device, void* hip_stream) {
       hipEventCreate(&ctx->ev1) != hipSuccess || hipEventCreate(&ctx->ev2) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_a, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_b, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreate(&ctx->ev_p0) != hipSuccess || hipEventCreate(&ctx->ev_p1) != hipSuccess ||
-      hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->ev_c, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->work, hipStreamNonBlocking) != hipSuccess) {
     delete ctx;
     return fail(nullptr, RT_EDEVICE, "cannot initialise device %d", device);
   }
@@ -446,9 +450,8 @@ rt_status rt_destroy(rt_ctx* ctx) {
                     &ctx->tmp_out2, &ctx->view, &ctx->lamidx, &ctx->it_astars, &ctx->it_adust,
                     &ctx->it_sum, &ctx->it_told, &ctx->it_crit, &ctx->d_regions, &ctx->d_rword,
                     &ctx->d_rup, &ctx->d_rcanon, &ctx->d_root_region, &ctx->q_rec[0], &ctx->q_rec[1],
-                    &ctx->q_key[0], &ctx->q_key[1], &ctx->q_skey, &ctx->q_perm, &ctx->q_iota,
-                    &ctx->q_kstart, &ctx->q_kend, &ctx->q_items, &ctx->q_nitems, &ctx->q_counters,
-                    &ctx->q_sort_tmp};
+                    &ctx->q_key[0], &ctx->q_key[1], &ctx->q_perm, &ctx->q_hist, &ctx->q_kfill,
+                    &ctx->q_items, &ctx->q_state};
   for (DevBuf* b : bufs) b->release();
   for (HostModel& m : ctx->models) {
     m.d_lc.release();
@@ -459,9 +462,11 @@ rt_status rt_destroy(rt_ctx* ctx) {
   if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
   if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
   if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
-  if (ctx->ev_p0) (void)hipEventDestroy(ctx->ev_p0);
-  if (ctx->ev_p1) (void)hipEventDestroy(ctx->ev_p1);
+  if (ctx->sweep_exec) (void)hipGraphExecDestroy(ctx->sweep_exec);
+  for (hipEvent_t e : ctx->sweep_ev) (void)hipEventDestroy(e);
+  if (ctx->ev_c) (void)hipEventDestroy(ctx->ev_c);
   if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+  if (ctx->work) (void)hipStreamDestroy(ctx->work);
   delete ctx;
   return RT_OK;
 }
@@ -968,8 +973,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   if (start > 0 && regions) {
     const int n_regions = (int)ctx->h_regions.size();
     const int64_t n_keys = (int64_t)n_slots * n_regions;
-    int end_bit = 1;
-    while ((int64_t(1) << end_bit) < n_keys) ++end_bit;
+    if (n_keys > (int64_t(1) << 28)) return fail(ctx, RT_EINVAL, "too many (wavelength, region) keys");
     const int64_t capq = std::min<int64_t>(int64_t(1) << 25, std::max<int64_t>((int64_t)start, 4096));
     const int64_t batch = std::min<int64_t>(o->batch_packets > 0 ? o->batch_packets : int64_t(1) << 23, capq);
     const int32_t chunk = o->chunk_packets > 0 ? o->chunk_packets : 16 * bs;
@@ -978,22 +982,22 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
         HIPCHK(ctx->q_rec[k].ensure(sizeof(PRec) * capq));
         HIPCHK(ctx->q_key[k].ensure(4 * capq));
       }
-      HIPCHK(ctx->q_skey.ensure(4 * capq));
       HIPCHK(ctx->q_perm.ensure(4 * capq));
-      HIPCHK(ctx->q_iota.ensure(4 * capq));
       ctx->q_capacity = capq;
     }
-    HIPCHK(ctx->q_kstart.ensure(4 * n_keys));
-    HIPCHK(ctx->q_kend.ensure(4 * n_keys));
+    HIPCHK(ctx->q_hist.ensure(4 * n_keys));
+    HIPCHK(ctx->q_kfill.ensure(4 * n_keys));
     HIPCHK(ctx->q_items.ensure(sizeof(WorkItem) * (capq / chunk + n_keys + 1)));
-    HIPCHK(ctx->q_nitems.ensure(16));
-    HIPCHK(ctx->q_counters.ensure(16));
-    HIPCHK(hipMemsetAsync(ctx->q_counters.p, 0, 16, ctx->stream));
-    size_t sort_bytes = 0;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, ctx->q_key[0].as<uint32_t>(),
-                                              ctx->q_skey.as<uint32_t>(), ctx->q_iota.as<uint32_t>(),
-                                              ctx->q_perm.as<uint32_t>(), (int)capq, 0, end_bit, ctx->stream));
-    HIPCHK(ctx->q_sort_tmp.ensure(sort_bytes));
+    HIPCHK(ctx->q_state.ensure(sizeof(SweepState)));
+    SweepState* st = ctx->q_state.as<SweepState>();
+    SweepState init;  // stays alive until the first synchronisation below
+    {
+      std::memset(&init, 0, sizeof init);
+      init.total = start;
+      HIPCHK(hipEventRecord(ctx->ev_c, ctx->stream));
+      HIPCHK(hipStreamWaitEvent(ctx->work, ctx->ev_c, 0));
+      HIPCHK(hipMemcpyAsync(st, &init, sizeof init, hipMemcpyHostToDevice, ctx->work));
+    }
     BlkParams b;
     std::memset(&b, 0, sizeof b);
     b.t = p;
@@ -1007,80 +1011,97 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     b.root_region = ctx->d_root_region.as<int32_t>();
     b.accb = ctx->acc.as<float>();
     b.accb_stride = ctx->reg_G;
+    b.q_perm = ctx->q_perm.as<uint32_t>();
     b.items = ctx->q_items.as<WorkItem>();
-    b.n_items = ctx->q_nitems.as<uint32_t>();
-    b.item_counter = ctx->q_nitems.as<uint32_t>() + 1;
+    b.n_items = &st->n_items;
+    b.item_counter = &st->item_counter;
     b.n_slots_key = n_slots;
     b.chunk = chunk;
     b.tail_park = o->tail_park < 0 ? INT32_MAX : (o->tail_park > 0 ? o->tail_park : 16);
-    unsigned long long* counters = ctx->q_counters.as<unsigned long long>();
-    int in = 0;
-    uint64_t in_count = 0, emitted = 0;
-    int64_t sweeps = 0;
-    // first batch on the main stream; later batches are emitted on the second stream while the
-    // region pass of the previous sweep runs (both append to the same queue)
+    const int grid_pass = ctx->n_cu * reg_per_cu;
+    const int grid_sort = ctx->n_cu * 4;
+    // kSweepBlock sweeps (an even number: buffer 0 is always the input of the first) are
+    // enqueued as one unit; the pass of sweep k is bracketed by events 2k, 2k+1
+    constexpr int kSweepBlock = 16;
+    if ((int)ctx->sweep_ev.size() < 2 * kSweepBlock) {
+      while ((int)ctx->sweep_ev.size() < 2 * kSweepBlock) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        ctx->sweep_ev.push_back(e);
+      }
+    }
+    auto enqueue_block = [&](bool capturing) -> hipError_t {
+      for (int k = 0; k < kSweepBlock; ++k) {
+        const int in = k & 1, out = 1 - in;
+        hipError_t e = launch_sweep_sort(st, in, k, (uint64_t)batch, (uint64_t)capq, ctx->q_key[in].as<uint32_t>(),
+                                         (int)n_keys, n_regions, chunk, ctx->q_hist.as<uint32_t>(),
+                                         ctx->q_kfill.as<uint32_t>(), ctx->q_perm.as<uint32_t>(),
+                                         ctx->q_items.as<WorkItem>(), grid_sort, ctx->work);
+        if (e != hipSuccess) return e;
+        BlkParams bk = b;
+        bk.q_in = ctx->q_rec[in].as<PRec>();
+        bk.u_out = ctx->q_rec[out].as<PRec>();
+        bk.u_key = ctx->q_key[out].as<uint32_t>();
+        bk.u_count = &st->count[out];
+        // this sweep's new packets are born on the second stream while the pass runs
+        if ((e = hipEventRecord(ctx->ev_a, ctx->work)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(ctx->aux, ctx->ev_a, 0)) != hipSuccess) return e;
+        if ((e = launch_blk_emit(bk, st, (uint64_t)batch, ctx->aux)) != hipSuccess) return e;
+        if ((e = hipEventRecord(ctx->ev_b, ctx->aux)) != hipSuccess) return e;
+        if (!capturing && (e = hipEventRecord(ctx->sweep_ev[2 * k], ctx->work)) != hipSuccess) return e;
+        if ((e = launch_blk_pass(bk, grid_pass, bs, reg_lds, ctx->work)) != hipSuccess) return e;
+        if (!capturing && (e = hipEventRecord(ctx->sweep_ev[2 * k + 1], ctx->work)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(ctx->work, ctx->ev_b, 0)) != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
+    // capture the block as a graph (once per set of launch parameters), replay it until a
+    // sweep finds the queues empty and nothing left to emit
+    std::vector<char> sig(sizeof b + 6 * sizeof(int64_t));
     {
-      const uint64_t n_emit = std::min<uint64_t>((uint64_t)batch, start);
-      b.u_out = ctx->q_rec[0].as<PRec>();
-      b.u_key = ctx->q_key[0].as<uint32_t>();
-      b.u_count = counters;
-      HIPCHK(launch_blk_emit(b, 0, n_emit, ctx->stream));
-      emitted = n_emit;
-      in_count = n_emit;
+      const int64_t extra[6] = {batch, capq, n_keys, grid_pass, bs, reg_lds};
+      std::memcpy(sig.data(), &b, sizeof b);
+      std::memcpy(sig.data() + sizeof b, extra, sizeof extra);
     }
-    while (in_count > 0) {
-      const int out_b = 1 - in;
-      HIPCHK(launch_blk_iota((uint32_t)in_count, ctx->q_iota.as<uint32_t>(), ctx->stream));
-      HIPCHK(hipcub::DeviceRadixSort::SortPairs(ctx->q_sort_tmp.p, sort_bytes, ctx->q_key[in].as<uint32_t>(),
-                                                ctx->q_skey.as<uint32_t>(), ctx->q_iota.as<uint32_t>(),
-                                                ctx->q_perm.as<uint32_t>(), (int)in_count, 0, end_bit,
-                                                ctx->stream));
-      HIPCHK(launch_blk_items(ctx->q_skey.as<uint32_t>(), (uint32_t)in_count, (int32_t)n_keys, n_regions, chunk,
-                              ctx->q_kstart.as<int32_t>(), ctx->q_kend.as<int32_t>(), ctx->q_items.as<WorkItem>(),
-                              ctx->q_nitems.as<uint32_t>(), ctx->stream));
-      HIPCHK(hipMemsetAsync(counters + out_b, 0, 8, ctx->stream));
-      HIPCHK(hipMemsetAsync(ctx->q_nitems.as<uint32_t>() + 1, 0, 4, ctx->stream));
-      b.u_out = ctx->q_rec[out_b].as<PRec>();
-      b.u_key = ctx->q_key[out_b].as<uint32_t>();
-      b.u_count = counters + out_b;
-      uint64_t n_emit = 0;
-      if (emitted < start) {
-        n_emit = std::min<uint64_t>({(uint64_t)batch, (uint64_t)capq - in_count, start - emitted});
-        if (n_emit > 0) {
-          HIPCHK(hipEventRecord(ctx->ev_a, ctx->stream));
-          HIPCHK(hipStreamWaitEvent(ctx->aux, ctx->ev_a, 0));
-          HIPCHK(launch_blk_emit(b, emitted, emitted + n_emit, ctx->aux));
-          HIPCHK(hipEventRecord(ctx->ev_b, ctx->aux));
-          emitted += n_emit;
-        }
+    const bool use_graph = o->sweep_graph > 0;
+    if (use_graph && (!ctx->sweep_exec || sig != ctx->sweep_sig)) {
+      if (ctx->sweep_exec) {
+        HIPCHK(hipGraphExecDestroy(ctx->sweep_exec));
+        ctx->sweep_exec = nullptr;
       }
-      b.q_in = ctx->q_rec[in].as<PRec>();
-      b.q_perm = ctx->q_perm.as<uint32_t>();
-      HIPCHK(hipEventRecord(ctx->ev_p0, ctx->stream));
-      HIPCHK(launch_blk_pass(b, ctx->n_cu * reg_per_cu, bs, reg_lds, ctx->stream));
-      HIPCHK(hipEventRecord(ctx->ev_p1, ctx->stream));
-      if (n_emit > 0) HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_b, 0));
-      unsigned long long nc = 0;
-      HIPCHK(hipMemcpyAsync(&nc, counters + out_b, 8, hipMemcpyDeviceToHost, ctx->stream));
-      HIPCHK(hipStreamSynchronize(ctx->stream));
-      float pass_ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&pass_ms, ctx->ev_p0, ctx->ev_p1));
-      main_ms += pass_ms;
-      ++main_launches;
-      in_count = nc;
-      in = out_b;
-      if (in_count == 0 && emitted < start) {
-        // nothing in flight (e.g. every packet of the batch left at once): emit the next batch
-        const uint64_t ne = std::min<uint64_t>((uint64_t)batch, start - emitted);
-        b.u_out = ctx->q_rec[in].as<PRec>();
-        b.u_key = ctx->q_key[in].as<uint32_t>();
-        b.u_count = counters + in;
-        HIPCHK(launch_blk_emit(b, emitted, emitted + ne, ctx->stream));
-        emitted += ne;
-        in_count = ne;
-      }
-      if (++sweeps > 2000000) return fail(ctx, RT_EDEVICE, "region schedule did not drain");
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(ctx->work, hipStreamCaptureModeThreadLocal));
+      const hipError_t ce = enqueue_block(true);
+      const hipError_t ee = hipStreamEndCapture(ctx->work, &graph);
+      HIPCHK(ce);
+      HIPCHK(ee);
+      const hipError_t ie = hipGraphInstantiate(&ctx->sweep_exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPCHK(ie);
+      ctx->sweep_sig = sig;
     }
+    for (int64_t blk = 0;; ++blk) {
+      if (use_graph) HIPCHK(hipGraphLaunch(ctx->sweep_exec, ctx->work));
+      else HIPCHK(enqueue_block(false));
+      SweepState hs;
+      HIPCHK(hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, ctx->work));
+      HIPCHK(hipStreamSynchronize(ctx->work));
+      // passes of sweeps that had packets to follow (events recorded by a replayed graph are
+      // not timed: graph replays report no per-launch durations)
+      for (int k = 0; k < kSweepBlock; ++k) {
+        if (hs.log_in[k] == 0) continue;
+        ++main_launches;
+        if (use_graph) continue;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->sweep_ev[2 * k], ctx->sweep_ev[2 * k + 1]));
+        main_ms += ms;
+      }
+      if (hs.done) break;
+      if (blk > 2000000 / kSweepBlock) return fail(ctx, RT_EDEVICE, "region schedule did not drain");
+    }
+    // later work on the caller's stream (the reduction) follows the sweeps
+    HIPCHK(hipEventRecord(ctx->ev_c, ctx->work));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_c, 0));
   } else if (start > 0) {
     if (fp32) {
       int per_cu = o->blocks_per_cu;

@@ -1,0 +1,163 @@
+// Device-driven sweeps of the region schedule (grid-by-grid processing, paper Sect. 3.4 and
+// App. A).  Every size a sweep needs (queue lengths, the packets still to be emitted, the
+// number of work items) lives in device memory, so a run of sweeps is a fixed sequence of
+// launches: it is captured once as a HIP graph and replayed until the queues drain.
+//
+// One sweep, on queue buffer `in` (its records were appended during the previous sweep):
+//   begin    clear the other buffer's count, pick this sweep's emission range
+//   hist     count the records per key (slot * n_regions + region)
+//   scan     exclusive offsets per key; cut each key's run into work items
+//   scatter  record index -> its place in key order (the permutation the pass reads through)
+//   pass     the region pass (blocked.hip) appends leaving packets to the other buffer, while
+//   emit     on a second stream appends newly born packets to the same buffer.
+#include "device.h"
+
+using namespace rtd;
+
+namespace {
+
+constexpr int kHistLds = 8192;  // keys counted in LDS (larger key sets use global atomics)
+
+__global__ void sw_begin_kernel(SweepState* st, int in, int slot, uint64_t batch, uint64_t capq) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int out = 1 - in;
+  const unsigned long long n_in = st->count[in];
+  st->count[out] = 0;
+  st->item_counter = 0;
+  st->n_items = 0;
+  const unsigned long long rem = st->total - st->emitted;
+  unsigned long long ne = rem < batch ? rem : batch;
+  const unsigned long long room = capq > n_in ? capq - n_in : 0;
+  if (ne > room) ne = room;
+  st->e0 = st->emitted;
+  st->ne = ne;
+  st->emitted += ne;
+  st->n_in = n_in;
+  st->log_in[slot] = n_in;
+  if (n_in == 0 && ne == 0) st->done = 1u;
+  if (n_in > 0) st->sweeps += 1u;
+}
+
+__global__ void sw_zero_kernel(uint32_t* __restrict__ a, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void sw_hist_kernel(const uint32_t* __restrict__ keys,
+                                                      const SweepState* __restrict__ st,
+                                                      uint32_t* __restrict__ hist, int n_keys) {
+  __shared__ uint32_t s_h[kHistLds];
+  const uint64_t n = st->n_in;
+  const bool lds = n_keys <= kHistLds;
+  if (lds) {
+    for (int k = threadIdx.x; k < n_keys; k += 256) s_h[k] = 0u;
+    __syncthreads();
+  }
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    const uint32_t k = keys[i];
+    if (lds) atomicAdd(&s_h[k], 1u);
+    else atomicAdd(&hist[k], 1u);
+  }
+  if (lds) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < n_keys; k += 256)
+      if (s_h[k]) atomicAdd(&hist[k], s_h[k]);
+  }
+}
+
+// One block: exclusive key offsets (written as scatter cursors) and the work items.
+__global__ __launch_bounds__(1024) void sw_scan_kernel(const uint32_t* __restrict__ hist, int n_keys,
+                                                       int n_regions, int chunk, uint32_t* __restrict__ kfill,
+                                                       WorkItem* __restrict__ items, SweepState* st) {
+  __shared__ uint32_t s_a[1024], s_b[1024];
+  uint32_t carry_r = 0, carry_i = 0;
+  const int t = threadIdx.x;
+  for (int k0 = 0; k0 < n_keys; k0 += 1024) {
+    const int k = k0 + t;
+    const uint32_t cnt = k < n_keys ? hist[k] : 0u;
+    const uint32_t nch = (cnt + (uint32_t)chunk - 1u) / (uint32_t)chunk;
+    s_a[t] = cnt;
+    s_b[t] = nch;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const uint32_t va = t >= o ? s_a[t - o] : 0u;
+      const uint32_t vb = t >= o ? s_b[t - o] : 0u;
+      __syncthreads();
+      s_a[t] += va;
+      s_b[t] += vb;
+      __syncthreads();
+    }
+    const uint32_t start = carry_r + s_a[t] - cnt;
+    const uint32_t ifirst = carry_i + s_b[t] - nch;
+    if (k < n_keys) {
+      kfill[k] = start;
+      for (uint32_t c = 0; c < nch; ++c) {
+        WorkItem w;
+        w.region = k % n_regions;
+        w.slot = k / n_regions;
+        w.start = start + c * (uint32_t)chunk;
+        w.count = min((uint32_t)chunk, cnt - c * (uint32_t)chunk);
+        items[ifirst + c] = w;
+      }
+    }
+    carry_r += s_a[1023];
+    carry_i += s_b[1023];
+    __syncthreads();
+  }
+  if (t == 0) st->n_items = carry_i;
+}
+
+// Record index -> position in key order.  A block takes tiles of 4096 records: their ranks
+// within the tile come from LDS counters, one global atomic per (tile, key) reserves the
+// tile's range of each key.
+__global__ __launch_bounds__(256) void sw_scatter_kernel(const uint32_t* __restrict__ keys,
+                                                         const SweepState* __restrict__ st,
+                                                         uint32_t* __restrict__ kfill,
+                                                         uint32_t* __restrict__ perm, int n_keys) {
+  constexpr int kPer = 16, kTile = 256 * kPer;
+  __shared__ uint32_t s_c[kHistLds];
+  const uint64_t n = st->n_in;
+  if (n_keys > kHistLds) {
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+      perm[atomicAdd(&kfill[keys[i]], 1u)] = (uint32_t)i;
+    return;
+  }
+  for (uint64_t t0 = (uint64_t)blockIdx.x * kTile; t0 < n; t0 += (uint64_t)gridDim.x * kTile) {
+    for (int k = threadIdx.x; k < n_keys; k += 256) s_c[k] = 0u;
+    __syncthreads();
+    uint32_t key[kPer], rank[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const uint64_t i = t0 + (uint64_t)j * 256 + threadIdx.x;
+      key[j] = i < n ? keys[i] : 0u;
+      rank[j] = i < n ? atomicAdd(&s_c[key[j]], 1u) : 0u;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < n_keys; k += 256) {
+      const uint32_t c = s_c[k];
+      if (c) s_c[k] = atomicAdd(&kfill[k], c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const uint64_t i = t0 + (uint64_t)j * 256 + threadIdx.x;
+      if (i < n) perm[s_c[key[j]] + rank[j]] = (uint32_t)i;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_sweep_sort(SweepState* st, int in, int slot, uint64_t batch, uint64_t capq, const uint32_t* keys,
+                             int n_keys, int n_regions, int chunk, uint32_t* hist, uint32_t* kfill,
+                             uint32_t* perm, WorkItem* items, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(sw_begin_kernel, dim3(1), dim3(64), 0, s, st, in, slot, batch, capq);
+  hipLaunchKernelGGL(sw_zero_kernel, dim3((n_keys + 255) / 256 < 1024 ? (n_keys + 255) / 256 : 1024), dim3(256),
+                     0, s, hist, n_keys);
+  hipLaunchKernelGGL(sw_hist_kernel, dim3(grid), dim3(256), 0, s, keys, (const SweepState*)st, hist, n_keys);
+  hipLaunchKernelGGL(sw_scan_kernel, dim3(1), dim3(1024), 0, s, (const uint32_t*)hist, n_keys, n_regions, chunk,
+                     kfill, items, st);
+  hipLaunchKernelGGL(sw_scatter_kernel, dim3(grid), dim3(256), 0, s, keys, (const SweepState*)st, kfill, perm,
+                     n_keys);
+  return hipGetLastError();
+}

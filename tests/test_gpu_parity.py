@@ -429,3 +429,25 @@ def test_autotune_and_cache(torch, tmp_path):
     assert rel_rms(eb, ea) < 1e-5
     p64, _ = ctx.autotune(w.sources, precision=rt.FP64, sample_fraction=0.25, **kw)
     assert p64["block_size"] in (64, 128, 256)
+
+
+def test_sweep_graph_replay_matches_direct_launches(torch):
+    """The sweeps of the region schedule replayed from a captured HIP graph (16 sweeps per
+    replay, twice in a row to reuse the instantiated graph) give the histories of direct
+    launches: equal counts and per-packet records, per-node results to FP32 summation order."""
+    w = gen.c2(n_root=24, max_level=3, n_lambda=4, packets=60000)
+    ctx = new_ctx(torch)
+    m = ctx.build_tree(w.trees[0])
+    ctx.set_dust(m, w.dusts[0])
+    kw = dict(seed=w.seed, precision=rt.FP32_LOCAL, rr_threshold=w.rr_threshold, rr_prob=w.rr_prob,
+              schedule=rt.SCHED_REGIONS, blocks_per_cu=8, batch_packets=20000, rec_stride=11)
+    a = ctx.trace_packets(w.sources, **kw)
+    for _ in range(2):
+        b = ctx.trace_packets(w.sources, sweep_graph=1, **kw)
+        for k in ("crossings", "scatterings", "kills", "packets"):
+            assert a["stats"][k] == b["stats"][k], k
+        assert b["stats"]["main_launches"] == a["stats"]["main_launches"]
+        for f in ("status", "crossings", "events", "node", "birth"):
+            assert np.array_equal(a["records"][f], b["records"][f]), f
+        ea, eb = a["e_abs_node"].cpu().numpy(), b["e_abs_node"].cpu().numpy()
+        assert rel_rms(eb, ea) < 1e-5
