@@ -33,8 +33,8 @@ HBM_PEAK_GBS = 8000.0
 # device-to-device copy (fetch x2.0, write x1.0), per leaf crossing.  Valid only for the kernel
 # sources the counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "e422a8208624f3b815d9593b1322e094da0e492964c87ad680be9e8eedb62b06",
-                "fetch_bytes_per_crossing": 10.577, "write_bytes_per_crossing": 4.310}
+                "sha256": "506b67c4fb4ad2076b61096a0e62810d6a82138bf48c284e5596413d639b75e8",
+                "fetch_bytes_per_crossing": 10.584, "write_bytes_per_crossing": 4.306}
 
 
 WORKLOADS = {
