@@ -32,6 +32,34 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Region holding the cell reached from the root along level-L coordinates J (a birth leaf,
+// or the neighbour across a face).  Below level L (a coarse cell entering a split cell through
+// face ax with sign sg) the child is picked as the landing picks it: the near side on the
+// crossing axis, the midpoint on the others (y: local coordinates in the level-L cell).
+__device__ __forceinline__ int32_t region_walk(const BlkParams& b, const Dims& D, int L, int32_t J0, int32_t J1,
+                                               int32_t J2, int ax, int sg, float y0, float y1, float y2) {
+  int32_t e = b.root_region[D.root(J0 >> L, J1 >> L, J2 >> L)];
+  int l = 0;
+  while (e < 0) {
+    ++l;
+    int oc;
+    if (l <= L) {
+      const int sh = L - l;
+      oc = ((J0 >> sh) & 1) | (((J1 >> sh) & 1) << 1) | (((J2 >> sh) & 1) << 2);
+    } else {
+      const int b0 = ax == 0 ? (sg > 0 ? 0 : 1) : (y0 >= 0.5f ? 1 : 0);
+      const int b1 = ax == 1 ? (sg > 0 ? 0 : 1) : (y1 >= 0.5f ? 1 : 0);
+      const int b2 = ax == 2 ? (sg > 0 ? 0 : 1) : (y2 >= 0.5f ? 1 : 0);
+      y0 = 2.0f * y0 - (float)b0;
+      y1 = 2.0f * y1 - (float)b1;
+      y2 = 2.0f * y2 - (float)b2;
+      oc = b0 | (b1 << 1) | (b2 << 2);
+    }
+    e = b.split_tab[(size_t)(~e) * 8 + oc];
+  }
+  return e;
+}
+
 // ------------------------------------------------------------------------------------------
 // emission into the queue
 // ------------------------------------------------------------------------------------------
@@ -84,8 +112,8 @@ __global__ __launch_bounds__(256) void blk_emit_kernel(const BlkParams b, const 
     r.job = lo;
     r.ev = 0;
     r.ncross = 1;
-    const int32_t root = D.root(k.I[0] >> k.lev, k.I[1] >> k.lev, k.I[2] >> k.lev);
-    key = (uint32_t)J.slot * (uint32_t)b.n_regions + (uint32_t)b.root_region[root];
+    key = (uint32_t)J.slot * (uint32_t)b.n_regions +
+          (uint32_t)region_walk(b, D, k.lev, k.I[0], k.I[1], k.I[2], -1, 1, 0.5f, 0.5f, 0.5f);
     e_emit = k.w0;
     npk = 1;
   }
@@ -190,7 +218,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   const float rr_thr = (float)p.rr_thr, rr_p = (float)p.rr_p;
   const float rr_gain = rr_p > 0.0f ? 1.0f / (1.0f - rr_p) : 1.0f;
   const int bx = R.hi[0] - R.lo[0], by = R.hi[1] - R.lo[1];
-  float* __restrict__ gacc = b.accb + (int64_t)it.slot * b.accb_stride + R.gbase;
+  float* __restrict__ gacc = b.accb64 ? nullptr : b.accb + (int64_t)it.slot * b.accb_stride + R.gbase;
+  double* __restrict__ gacc64 = b.accb64 ? b.accb64 + R.gbase : nullptr;
   const int32_t* __restrict__ gword = b.rword + R.gbase;
   const int32_t* __restrict__ gup = b.rup + (R.gbase >> 3);
   auto word_of = [&](int32_t l) -> int32_t {
@@ -203,6 +232,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   };
   auto deposit = [&](int32_t l, float v) {
     if (FITS || l < nloc) atomicAdd(&s_acc[l], v);
+    else if (gacc64) unsafeAtomicAdd(gacc64 + l, (double)v);
     else unsafeAtomicAdd(gacc + l, v);
   };
   int state = B_EMPTY;
@@ -219,8 +249,6 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   bool pool_done = false;      // this item's packets are all taken (wave-uniform)
   int tail_it = 0;             // crossing rounds since then (wave-uniform)
   const uint32_t own_key = (uint32_t)it.slot * (uint32_t)b.n_regions + (uint32_t)it.region;
-  uint32_t xkey = 0;  // leaving: internal id of the root cell entered (its region is looked up
-                      // when the record is written, outside the crossing loop)
 
   for (;;) {
     // ---------------- refill from this item's queue ----------------
@@ -272,25 +300,47 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
             else if (ax == 1) J1 += sg;
             else J2 += sg;
           }
-          const int32_t R0 = J0 >> L, R1 = J1 >> L, R2 = J2 >> L;
+          // the cell of this region's brick (level R.rl) that holds the packet
+          int Lj = L;  // level of J
+          if (L < R.rl) {
+            // entering a split cell from a coarser neighbour: descend to the brick's level as
+            // the landing would (near side on the crossing axis, midpoint on the others)
+            x0 = ax == 0 ? (sg > 0 ? 0.0f : 1.0f) : x0;
+            x1 = ax == 1 ? (sg > 0 ? 0.0f : 1.0f) : x1;
+            x2 = ax == 2 ? (sg > 0 ? 0.0f : 1.0f) : x2;
+            for (int l = L + 1; l <= R.rl; ++l) {
+              const int b0 = ax == 0 ? (sg > 0 ? 0 : 1) : (x0 >= 0.5f ? 1 : 0);
+              const int b1 = ax == 1 ? (sg > 0 ? 0 : 1) : (x1 >= 0.5f ? 1 : 0);
+              const int b2 = ax == 2 ? (sg > 0 ? 0 : 1) : (x2 >= 0.5f ? 1 : 0);
+              x0 = 2.0f * x0 - (float)b0;
+              x1 = 2.0f * x1 - (float)b1;
+              x2 = 2.0f * x2 - (float)b2;
+              J0 = 2 * J0 + b0;
+              J1 = 2 * J1 + b1;
+              J2 = 2 * J2 + b2;
+            }
+            Lj = R.rl;
+          }
+          const int shr = Lj - R.rl;
+          const int32_t R0 = J0 >> shr, R1 = J1 >> shr, R2 = J2 >> shr;
           const int32_t rootl = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
           int32_t raw = 0;
-          const bool misplaced = R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] || R1 >= R.hi[1] ||
-                                 R2 < R.lo[2] || R2 >= R.hi[2];
+          const bool misplaced = (L < R.rl && !rec.flag) || R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] ||
+                                 R1 >= R.hi[1] || R2 < R.lo[2] || R2 >= R.hi[2];
           if (misplaced) {
             // a record queued for the wrong region (never expected): retire it as truncated
             ++c_trunc;
             atomicAdd(&s_misc[2], (double)w);
             c_cross += ncross;
           } else if (rec.flag) {
-            land(word_of, ax, sg, L, rec.I[0], rec.I[1], rec.I[2], J0, J1, J2, rootl, 0, x0, x1, x2, O0,
+            land(word_of, ax, sg, Lj, rec.I[0], rec.I[1], rec.I[2], J0, J1, J2, rootl, R.rl, x0, x1, x2, O0,
                  O1, O2, d0, d1, d2, node, lev, I0, I1, I2, raw);
             ++ncross;
           } else {
             // birth: walk down to the birth leaf along its coordinates
             int32_t cur = rootl;
             int32_t rr = word_of(cur);
-            for (int l = 1; l <= L && child_of(rr) >= 0; ++l) {
+            for (int l = R.rl + 1; l <= L && child_of(rr) >= 0; ++l) {
               const int sh = L - l;
               cur = child_of(rr) + (((J0 >> sh) & 1) | (((J1 >> sh) & 1) << 1) | (((J2 >> sh) & 1) << 2));
               rr = word_of(cur);
@@ -360,20 +410,22 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           } else {
             int32_t cur = node;
             int l = L;
-            while (l > 0 && ((Ja >> (L - l + 1)) != (Ia >> (L - l + 1)))) {
+            while (l > R.rl && ((Ja >> (L - l + 1)) != (Ia >> (L - l + 1)))) {
               cur = up_of(cur);
               --l;
             }
             const int32_t J0 = ax == 0 ? Ja : I0, J1 = ax == 1 ? Ja : I1, J2 = ax == 2 ? Ja : I2;
             bool leave = false;
-            if (l == 0) {
-              const int32_t R0 = J0 >> L, R1 = J1 >> L, R2 = J2 >> L;
+            if (l == R.rl) {
+              const int sh = L - R.rl;
+              const int32_t R0 = J0 >> sh, R1 = J1 >> sh, R2 = J2 >> sh;
               if (R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] || R1 >= R.hi[1] || R2 < R.lo[2] ||
                   R2 >= R.hi[2]) {
+                // the neighbour lies in another region: its region is looked up when the record
+                // is written, outside the crossing loop
                 leave = true;
                 xax = ax;
                 xsg = sg;
-                xkey = (uint32_t)D.root(R0, R1, R2);
                 state = B_EXIT;
               } else {
                 cur = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
@@ -405,7 +457,6 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
     if (pool_done && tail_it >= b.tail_park && state == B_CROSS) {
       state = B_EXIT;
       xpark = true;
-      xkey = 0;
     }
     const uint64_t ex = __ballot(state == B_EXIT);
     if (ex) {
@@ -445,8 +496,13 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         rc.ev = ev;
         rc.ncross = ncross;
         b.u_out[idx] = rc;
-        b.u_key[idx] = xpark ? own_key
-                             : (uint32_t)it.slot * (uint32_t)b.n_regions + (uint32_t)b.root_region[xkey];
+        uint32_t key = own_key;
+        if (!xpark) {
+          const int32_t K0 = I0 + (xax == 0 ? xsg : 0), K1 = I1 + (xax == 1 ? xsg : 0), K2 = I2 + (xax == 2 ? xsg : 0);
+          key = (uint32_t)it.slot * (uint32_t)b.n_regions +
+                (uint32_t)region_walk(b, D, lev, K0, K1, K2, xax, xsg, x0, x1, x2);
+        }
+        b.u_key[idx] = key;
         xpark = false;
         state = B_EMPTY;
       }
@@ -550,11 +606,19 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     else
       run_item<false>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
                       c_cross, c_scat, c_kill, c_trunc);
-    float* __restrict__ gacc = b.accb + (int64_t)it.slot * b.accb_stride + R.gbase;
     __syncthreads();
-    for (int i = tid; i < nloc; i += BS) {
-      const float v = s_acc[i];
-      if (v != 0.0f) unsafeAtomicAdd(gacc + i, v);
+    if (b.accb64) {
+      double* __restrict__ gacc64 = b.accb64 + R.gbase;
+      for (int i = tid; i < nloc; i += BS) {
+        const float v = s_acc[i];
+        if (v != 0.0f) unsafeAtomicAdd(gacc64 + i, (double)v);
+      }
+    } else {
+      float* __restrict__ gacc = b.accb + (int64_t)it.slot * b.accb_stride + R.gbase;
+      for (int i = tid; i < nloc; i += BS) {
+        const float v = s_acc[i];
+        if (v != 0.0f) unsafeAtomicAdd(gacc + i, v);
+      }
     }
     if (esc_lds)
       for (int i = tid; i < md.nl; i += BS)
@@ -583,7 +647,8 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
 __global__ __launch_bounds__(256) void blk_reduce_kernel(const ModelDev* __restrict__ models,
                                                          const RegionDev* __restrict__ regions,
                                                          const int32_t* __restrict__ rcanon,
-                                                         const float* __restrict__ accb, int64_t stride,
+                                                         const float* __restrict__ accb,
+                                                         const double* __restrict__ accb64, int64_t stride,
                                                          int n_slots, double* __restrict__ e_node,
                                                          double* __restrict__ e_lam_node,
                                                          double* __restrict__ e_total) {
@@ -596,11 +661,15 @@ __global__ __launch_bounds__(256) void blk_reduce_kernel(const ModelDev* __restr
     const int64_t gidx = R.gbase + l;
     const int32_t c = rcanon[gidx];
     if (c >= 0) {
-      const int ns = n_slots > 1 ? m.nl : 1;
-      for (int s = 0; s < ns; ++s) {
-        const double v = (double)accb[s * stride + gidx];
-        sum += v;
-        if (e_lam_node) e_lam_node[m.lamnode_base + (int64_t)s * m.n_nodes + c] = v;
+      if (accb64) {
+        sum = accb64[gidx];
+      } else {
+        const int ns = n_slots > 1 ? m.nl : 1;
+        for (int s = 0; s < ns; ++s) {
+          const double v = (double)accb[s * stride + gidx];
+          sum += v;
+          if (e_lam_node) e_lam_node[m.lamnode_base + (int64_t)s * m.n_nodes + c] = v;
+        }
       }
       if (e_node) e_node[m.canon_base + c] = sum;
     }
@@ -644,10 +713,10 @@ hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_byte
 
 hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, int n_regions,
                              int32_t max_region_nodes, const int32_t* rcanon, const float* accb,
-                             int64_t stride, int n_slots, double* e_node, double* e_lam_node,
+                             const double* accb64, int64_t stride, int n_slots, double* e_node, double* e_lam_node,
                              double* e_total, hipStream_t s) {
   if (n_regions == 0) return hipSuccess;
   hipLaunchKernelGGL(blk_reduce_kernel, dim3((max_region_nodes + 255) / 256, n_regions), dim3(256), 0, s, models,
-                     regions, rcanon, accb, stride, n_slots, e_node, e_lam_node, e_total);
+                     regions, rcanon, accb, accb64, stride, n_slots, e_node, e_lam_node, e_total);
   return hipGetLastError();
 }

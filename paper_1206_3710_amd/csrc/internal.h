@@ -96,16 +96,19 @@ struct TraceParams {
 };
 
 // ------------------------------------------------------------------------------------------
-// Grid-by-grid (region-blocked) form.  A region is a brick of root cells [lo, hi) with all
-// their descendants, renumbered region-major: local ids [0, nb_pad) are the brick's root cells
+// Grid-by-grid (region-blocked) form.  A region is a brick of cells [lo, hi) at one level rl
+// (root cells, or children of a cell whose subtree is too large for one region) with all
+// their descendants, renumbered region-major: local ids [0, nb_pad) are the brick's cells
 // (x fastest), then the octs level by level, each oct 8-aligned.  Region-major global id =
 // gbase + local.  rword: leaf -> float bits of the density, refined -> ~(local first child);
 // rup[g >> 3]: local parent of the oct starting at g; rcanon[g]: canonical id (-1 = padding).
 // ------------------------------------------------------------------------------------------
 struct RegionDev {
   int32_t model;
-  int32_t lo[3], hi[3];
+  int32_t rl;       // level of the brick's cells (0: root cells; > 0: children of a split cell)
+  int32_t lo[3], hi[3];  // the brick, in level-rl coordinates
   int32_t n;        // local ids used (including padding)
+  int32_t pad;
   int64_t gbase;    // region-major global id of local 0 (multiple of 8)
 };
 
@@ -137,8 +140,12 @@ struct BlkParams {
   const int32_t* rword;
   const int32_t* rup;
   const int32_t* rcanon;     // region-major id -> canonical id within its model (-1 = padding)
-  const int32_t* root_region;  // per internal id of a root cell (old layout): its region
-  float* accb;               // [slots][G] region-major FP32 accumulators
+  const int32_t* root_region;  // per internal id of a root cell (old layout): its region, or
+                               // ~s when the cell is split (split_tab entry s)
+  const int32_t* split_tab;    // 8 per split cell, by child octant: region id, or ~s (split again)
+  float* accb;               // [slots][G] region-major FP32 accumulators (per-wavelength output)
+  double* accb64;            // [G] region-major FP64 accumulators (wavelength-integrated output);
+                             // when set, every key has slot 0 and accb is unused
   int64_t accb_stride;       // G
   // queues
   PRec* u_out;               // append target
@@ -176,6 +183,7 @@ hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_byte
 hipError_t attr_blk_pass(int block, int lds_bytes);
 hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, int n_regions,
                              int32_t max_region_nodes, const int32_t* rcanon, const float* accb,
+                             const double* accb64,
                              int64_t stride, int n_slots, double* e_node, double* e_lam_node,
                              double* e_total, hipStream_t s);
 

@@ -91,7 +91,7 @@ struct rt_ctx {
   std::vector<RegionDev> h_regions;
   int64_t reg_G = 0;
   int32_t reg_maxn = 0;
-  DevBuf d_regions, d_rword, d_rup, d_rcanon, d_root_region;
+  DevBuf d_regions, d_rword, d_rup, d_rcanon, d_root_region, d_split;
   DevBuf q_rec[2], q_key[2], q_perm, q_hist, q_kfill, q_items, q_state;
   int64_t q_capacity = 0;
   // sweep graph: kSweepBlock sweeps captured once per trace configuration, replayed
@@ -248,7 +248,8 @@ rt_status sync_device(rt_ctx* ctx) {
 rt_status build_regions(rt_ctx* ctx, int32_t cap) {
   if (!ctx->reg_dirty && ctx->reg_cap == cap) return RT_OK;
   std::vector<RegionDev> regs;
-  std::vector<int32_t> rword, rup, rcanon, root_region(ctx->total_int, -1);
+  std::vector<int32_t> rword, rup, rcanon, root_region(ctx->total_int, INT32_MIN);
+  std::vector<int32_t> split_tab;  // 8 entries per split cell: region id, or ~(split index)
   int64_t G = 0;
   int32_t maxn = 0;
   for (size_t mi = 0; mi < ctx->models.size(); ++mi) {
@@ -284,48 +285,96 @@ rt_status build_regions(rt_ctx* ctx, int32_t cap) {
              P[pidx(hi[0], hi[1], lo[2])] + P[pidx(lo[0], lo[1], hi[2])] + P[pidx(lo[0], hi[1], lo[2])] +
              P[pidx(hi[0], lo[1], lo[2])] - P[pidx(lo[0], lo[1], lo[2])];
     };
-    std::vector<std::array<int, 6>> stack{{0, 0, 0, nx, ny, nz}}, boxes;
+    // Bricks of cells at one level: root-grid bricks by bisection of the longest axis until
+    // the subtree nodes fit `cap`; a single cell whose subtree is still too large is split,
+    // and the brick of its 8 children (one level down) is bisected in turn.
+    struct Box {
+      int level;
+      int64_t parent;  // canonical id of the split cell whose children the brick holds (-1: root)
+      int32_t split;   // that cell's split-table index
+      int lo[3], hi[3];
+    };
+    auto cell_of = [&](const Box& bx, int x, int y, int z) -> int64_t {
+      if (bx.level == 0) return x + (int64_t)nx * (y + (int64_t)ny * z);
+      const int64_t fc = (int64_t)ctx->h_child[internal(bx.parent)] - h.base - pad0;
+      return fc + ((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
+    };
+    auto nodes_of = [&](const Box& bx) -> int64_t {
+      const int64_t nb = (int64_t)(bx.hi[0] - bx.lo[0]) * (bx.hi[1] - bx.lo[1]) * (bx.hi[2] - bx.lo[2]);
+      int64_t s = 0;
+      if (bx.level == 0) {
+        s = box_sum(bx.lo, bx.hi);
+      } else {
+        for (int z = bx.lo[2]; z < bx.hi[2]; ++z)
+          for (int y = bx.lo[1]; y < bx.hi[1]; ++y)
+            for (int x = bx.lo[0]; x < bx.hi[0]; ++x) s += sz[cell_of(bx, x, y, z)];
+      }
+      return round8(nb) + (s - nb);
+    };
+    std::vector<Box> stack{{0, -1, -1, {0, 0, 0}, {nx, ny, nz}}}, boxes;
     while (!stack.empty()) {
-      auto bx = stack.back();
+      Box bx = stack.back();
       stack.pop_back();
-      const int lo[3] = {bx[0], bx[1], bx[2]}, hi[3] = {bx[3], bx[4], bx[5]};
-      const int64_t nb = (int64_t)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
-      const int64_t nodes = round8(nb) + (box_sum(lo, hi) - nb);
-      if (nodes <= cap || nb == 1) {
+      const int64_t nb = (int64_t)(bx.hi[0] - bx.lo[0]) * (bx.hi[1] - bx.lo[1]) * (bx.hi[2] - bx.lo[2]);
+      const int64_t nodes = nodes_of(bx);
+      if (nodes <= cap) {
         boxes.push_back(bx);
         continue;
       }
-      int a = 0;
-      for (int q = 1; q < 3; ++q)
-        if (hi[q] - lo[q] > hi[a] - lo[a]) a = q;
-      const int mid = (lo[a] + hi[a]) / 2;
-      auto b1 = bx, b2 = bx;
-      b1[3 + a] = mid;
-      b2[a] = mid;
-      stack.push_back(b2);
-      stack.push_back(b1);
+      if (nb > 1) {
+        int a = 0;
+        for (int q = 1; q < 3; ++q)
+          if (bx.hi[q] - bx.lo[q] > bx.hi[a] - bx.lo[a]) a = q;
+        const int mid = (bx.lo[a] + bx.hi[a]) / 2;
+        Box b1 = bx, b2 = bx;
+        b1.hi[a] = mid;
+        b2.lo[a] = mid;
+        stack.push_back(b2);
+        stack.push_back(b1);
+        continue;
+      }
+      // one cell with too large a subtree: split it (its refined children keep their own data)
+      const int64_t c = cell_of(bx, bx.lo[0], bx.lo[1], bx.lo[2]);
+      if (ctx->h_child[internal(c)] < 0) {  // a single leaf always fits; guard anyway
+        boxes.push_back(bx);
+        continue;
+      }
+      const int32_t s = (int32_t)(split_tab.size() / 8);
+      split_tab.resize(split_tab.size() + 8, INT32_MIN);
+      if (bx.level == 0) {
+        root_region[internal(c)] = ~s;
+      } else {
+        const int b = (bx.lo[0] & 1) | ((bx.lo[1] & 1) << 1) | ((bx.lo[2] & 1) << 2);
+        split_tab[(size_t)bx.split * 8 + b] = ~s;
+      }
+      // the brick of its children, in coordinates one level down
+      Box kid{bx.level + 1, c, s, {2 * bx.lo[0], 2 * bx.lo[1], 2 * bx.lo[2]},
+              {2 * bx.lo[0] + 2, 2 * bx.lo[1] + 2, 2 * bx.lo[2] + 2}};
+      stack.push_back(kid);
     }
     for (const auto& bx : boxes) {
       RegionDev R;
       R.model = (int32_t)mi;
+      R.rl = bx.level;
       for (int q = 0; q < 3; ++q) {
-        R.lo[q] = bx[q];
-        R.hi[q] = bx[3 + q];
+        R.lo[q] = bx.lo[q];
+        R.hi[q] = bx.hi[q];
       }
       const int bxn = R.hi[0] - R.lo[0], byn = R.hi[1] - R.lo[1];
       const int64_t nb = (int64_t)bxn * byn * (R.hi[2] - R.lo[2]);
       R.gbase = G;
       const int32_t rid = (int32_t)regs.size();
-      // local numbering: the brick's root cells, then octs level by level
+      // local numbering: the brick's cells, then octs level by level
       std::vector<std::pair<int64_t, int32_t>> cur;  // (canonical, local)
       cur.reserve(nb);
       for (int z = R.lo[2]; z < R.hi[2]; ++z)
         for (int y = R.lo[1]; y < R.hi[1]; ++y)
           for (int x = R.lo[0]; x < R.hi[0]; ++x) {
-            const int64_t c = x + (int64_t)nx * (y + (int64_t)ny * z);
+            const int64_t c = cell_of(bx, x, y, z);
             const int32_t l = (int32_t)((x - R.lo[0]) + bxn * ((y - R.lo[1]) + byn * (z - R.lo[2])));
             cur.emplace_back(c, l);
-            root_region[internal(c)] = rid;
+            if (bx.level == 0) root_region[internal(c)] = rid;
+            else split_tab[(size_t)bx.split * 8 + ((x & 1) | ((y & 1) << 1) | ((z & 1) << 2))] = rid;
           }
       int64_t next = round8(nb);
       std::vector<int32_t> lw, lc;  // local words, canonical ids
@@ -371,6 +420,26 @@ rt_status build_regions(rt_ctx* ctx, int32_t cap) {
   if ((s = upload(ctx, ctx->d_regions, regs)) || (s = upload(ctx, ctx->d_rword, rword)) ||
       (s = upload(ctx, ctx->d_rup, rup)) || (s = upload(ctx, ctx->d_rcanon, rcanon)) ||
       (s = upload(ctx, ctx->d_root_region, root_region)))
+    return s;
+  // every root cell has a region or a split entry; every split entry is a region or a split
+  // created after its parent (so a walk down the table always ends)
+  for (size_t mi = 0; mi < ctx->models.size(); ++mi) {
+    const HostModel& h = ctx->models[mi];
+    for (int64_t c = 0; c < h.n_root; ++c) {
+      const int32_t e = root_region[h.base + c];
+      if (e == INT32_MIN) return fail(ctx, RT_EDEVICE, "region layout: root cell without region");
+      if (e < 0 && (size_t)(~e) * 8 >= split_tab.size())
+        return fail(ctx, RT_EDEVICE, "region layout: bad split index");
+    }
+  }
+  for (size_t i = 0; i < split_tab.size(); ++i) {
+    const int32_t e = split_tab[i];
+    if (e == INT32_MIN || (e >= 0 && e >= (int32_t)regs.size()) ||
+        (e < 0 && ((size_t)(~e) <= i / 8 || (size_t)(~e) * 8 >= split_tab.size())))
+      return fail(ctx, RT_EDEVICE, "region layout: bad split table entry");
+  }
+  if (split_tab.empty()) split_tab.assign(8, -1);
+  if ((s = upload(ctx, ctx->d_split, split_tab)))
     return s;
   ctx->reg_cap = cap;
   ctx->reg_dirty = false;
@@ -449,7 +518,7 @@ rt_status rt_destroy(rt_ctx* ctx) {
                     &ctx->cdf_qpre, &ctx->lmax, &ctx->scan_tmp, &ctx->tmp_in, &ctx->tmp_out,
                     &ctx->tmp_out2, &ctx->view, &ctx->lamidx, &ctx->it_astars, &ctx->it_adust,
                     &ctx->it_sum, &ctx->it_told, &ctx->it_crit, &ctx->d_regions, &ctx->d_rword,
-                    &ctx->d_rup, &ctx->d_rcanon, &ctx->d_root_region, &ctx->q_rec[0], &ctx->q_rec[1],
+                    &ctx->d_rup, &ctx->d_rcanon, &ctx->d_root_region, &ctx->d_split, &ctx->q_rec[0], &ctx->q_rec[1],
                     &ctx->q_key[0], &ctx->q_key[1], &ctx->q_perm, &ctx->q_hist, &ctx->q_kfill,
                     &ctx->q_items, &ctx->q_state};
   for (DevBuf* b : bufs) b->release();
@@ -830,9 +899,11 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   int max_nl = 1;
   for (const HostModel& h : ctx->models) max_nl = std::max(max_nl, h.nl);
   const bool fp32 = o->precision == RT_FP32_LOCAL;
-  // per-wavelength accumulator slots: always for the FP32 form (FP32 sums stay short), for
-  // FP64 only when per-(wavelength, node) output is requested
-  int n_slots = (fp32 || out.e_lamnode) ? max_nl : 1;
+  // per-wavelength accumulator slots: for the one-queue FP32 form (its global FP32 sums stay
+  // short), and whenever per-(wavelength, node) output is requested.  The region schedule sums
+  // each work item in LDS and flushes to FP64 accumulators, so it needs no slots otherwise.
+  const bool region_form = fp32 && o->schedule == RT_SCHED_REGIONS;
+  int n_slots = ((fp32 && !region_form) || out.e_lamnode) ? max_nl : 1;
   const size_t elem = fp32 ? 4 : 8;
   if (fp32 && !out.e_lamnode && (double)n_slots * ctx->total_int * elem > 96e9) n_slots = 1;
   const int64_t stride = ctx->total_int;
@@ -964,8 +1035,10 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     reg_lds = 8 * cap + 4 * (cap / 8);
     if (rt_status e = build_regions(ctx, cap)) return e;
     HIPCHK(attr_blk_pass(bs, reg_lds));
-    HIPCHK(ctx->acc.ensure((size_t)n_slots * ctx->reg_G * 4));
-    HIPCHK(hipMemsetAsync(ctx->acc.p, 0, (size_t)n_slots * ctx->reg_G * 4, ctx->stream));
+    // per-wavelength output: FP32 slots; wavelength-integrated: one FP64 accumulator per node
+    const size_t racc = n_slots > 1 ? (size_t)n_slots * ctx->reg_G * 4 : (size_t)ctx->reg_G * 8;
+    HIPCHK(ctx->acc.ensure(racc));
+    HIPCHK(hipMemsetAsync(ctx->acc.p, 0, racc, ctx->stream));
   }
   double main_ms = 0.0;
   uint64_t main_launches = 0;
@@ -1009,7 +1082,9 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     b.rup = ctx->d_rup.as<int32_t>();
     b.rcanon = ctx->d_rcanon.as<int32_t>();
     b.root_region = ctx->d_root_region.as<int32_t>();
-    b.accb = ctx->acc.as<float>();
+    b.split_tab = ctx->d_split.as<int32_t>();
+    b.accb = n_slots > 1 ? ctx->acc.as<float>() : nullptr;
+    b.accb64 = n_slots > 1 ? nullptr : ctx->acc.as<double>();
     b.accb_stride = ctx->reg_G;
     b.q_perm = ctx->q_perm.as<uint32_t>();
     b.items = ctx->q_items.as<WorkItem>();
@@ -1124,7 +1199,8 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   if (regions) {
     HIPCHK(launch_blk_reduce(ctx->d_models.as<ModelDev>(), ctx->d_regions.as<RegionDev>(),
                              (int)ctx->h_regions.size(), ctx->reg_maxn, ctx->d_rcanon.as<int32_t>(),
-                             ctx->acc.as<float>(), ctx->reg_G, n_slots, out.e_node,
+                             n_slots > 1 ? ctx->acc.as<float>() : nullptr,
+                             n_slots > 1 ? nullptr : ctx->acc.as<double>(), ctx->reg_G, n_slots, out.e_node,
                              n_slots > 1 ? out.e_lamnode : nullptr, ctx->e_total.as<double>(), ctx->stream));
   } else {
     for (size_t m = 0; m < ctx->models.size(); ++m) {

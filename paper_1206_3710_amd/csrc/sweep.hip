@@ -16,7 +16,34 @@ using namespace rtd;
 
 namespace {
 
-constexpr int kHistLds = 8192;  // keys counted in LDS (larger key sets use global atomics)
+constexpr int kHistLds = 16384;  // keys counted in LDS (larger key sets use global atomics)
+constexpr int kAgg = 4;          // distinct keys per wave counted with one atomic each
+
+// Add 1 per valid lane to cnt[key]; returns each lane's rank among the lanes (and earlier
+// callers) with its key.  Lanes sharing one of the first kAgg distinct keys of the wave are
+// counted with a single atomic per key (queues are often dominated by a few regions, whose
+// counters would otherwise serialise); the remaining lanes use one atomic each.
+__device__ __forceinline__ uint32_t agg_count(uint32_t* cnt, uint32_t key, bool valid) {
+  const int lane = threadIdx.x & 63;
+  uint64_t todo = __ballot(valid);
+  uint32_t rank = 0;
+  bool done = !valid;
+  for (int it = 0; it < kAgg && todo; ++it) {
+    const int leader = __builtin_ctzll(todo);
+    const uint32_t kl = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+    const uint64_t same = __ballot(valid && key == kl) & todo;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&cnt[kl], (uint32_t)__popcll(same));
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+    if ((same >> lane) & 1ull) {
+      rank = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+      done = true;
+    }
+    todo &= ~same;
+  }
+  if (!done) rank = atomicAdd(&cnt[key], 1u);
+  return rank;
+}
 
 __global__ void sw_begin_kernel(SweepState* st, int in, int slot, uint64_t batch, uint64_t capq) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -52,10 +79,13 @@ __global__ __launch_bounds__(256) void sw_hist_kernel(const uint32_t* __restrict
     for (int k = threadIdx.x; k < n_keys; k += 256) s_h[k] = 0u;
     __syncthreads();
   }
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
-    const uint32_t k = keys[i];
-    if (lds) atomicAdd(&s_h[k], 1u);
-    else atomicAdd(&hist[k], 1u);
+  // whole waves iterate together (agg_count needs every lane of the wave)
+  const uint64_t span = (uint64_t)gridDim.x * 256;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * 256; i0 < n; i0 += span) {
+    const uint64_t i = i0 + threadIdx.x;
+    const bool v = i < n;
+    const uint32_t k = v ? keys[i] : 0u;
+    (void)agg_count(lds ? s_h : hist, k, v);
   }
   if (lds) {
     __syncthreads();
@@ -117,8 +147,13 @@ __global__ __launch_bounds__(256) void sw_scatter_kernel(const uint32_t* __restr
   __shared__ uint32_t s_c[kHistLds];
   const uint64_t n = st->n_in;
   if (n_keys > kHistLds) {
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
-      perm[atomicAdd(&kfill[keys[i]], 1u)] = (uint32_t)i;
+    const uint64_t span = (uint64_t)gridDim.x * 256;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * 256; i0 < n; i0 += span) {
+      const uint64_t i = i0 + threadIdx.x;
+      const bool v = i < n;
+      const uint32_t pos = agg_count(kfill, v ? keys[i] : 0u, v);
+      if (v) perm[pos] = (uint32_t)i;
+    }
     return;
   }
   for (uint64_t t0 = (uint64_t)blockIdx.x * kTile; t0 < n; t0 += (uint64_t)gridDim.x * kTile) {
@@ -129,7 +164,7 @@ __global__ __launch_bounds__(256) void sw_scatter_kernel(const uint32_t* __restr
     for (int j = 0; j < kPer; ++j) {
       const uint64_t i = t0 + (uint64_t)j * 256 + threadIdx.x;
       key[j] = i < n ? keys[i] : 0u;
-      rank[j] = i < n ? atomicAdd(&s_c[key[j]], 1u) : 0u;
+      rank[j] = agg_count(s_c, key[j], i < n);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < n_keys; k += 256) {

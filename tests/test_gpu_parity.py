@@ -342,22 +342,33 @@ def test_errors_leave_context_usable(torch):
     assert r["stats"]["packets"] == 100
 
 
-def test_region_overflow_and_records(torch):
-    """Region schedule where single root-cell subtrees exceed the LDS capacity (part of the
-    region stays in global memory): deposits, fates and crossing counts against the oracle."""
-    tree = gen.uniform_refined_tree((2, 2, 2), 3, rho=0.5, cell_cm=0.5)
+@pytest.mark.parametrize("levels,per_cu", [(3, 32), (4, 32), (4, 16)])
+def test_split_regions_and_records(torch, levels, per_cu):
+    """Region schedule with a small LDS capacity (many blocks per CU), so that single root-cell
+    subtrees are larger than a region and are split into bricks of their children, one or two
+    levels down: deposits, fates and crossing counts against the oracle, including packets that
+    enter a split cell from a coarser neighbour (a point source in a coarse cell)."""
+    # root cells 0-6 refined uniformly to `levels` levels; root cell 7 stays a leaf, so packets
+    # leaving it enter split cells from a coarser level
     rng = np.random.default_rng(3)
-    tree.child_rho[2] = rng.uniform(0.1, 2.0, len(tree.child_rho[2]))
+    refined, kids = [np.arange(7, dtype=np.int64)], []
+    n = 7 * 8
+    for lvl in range(1, levels):
+        kids.append(np.full(n, 0.5))
+        refined.append(np.arange(n, dtype=np.int64))
+        n *= 8
+    kids.append(rng.uniform(0.1, 2.0, n))
+    tree = gen.TreeDesc(2, 2, 2, 0.5, np.full(8, 0.5), refined, kids)
     dust = gen.Dust(np.array([1.0]), np.array([1.0]), np.array([0.5]), np.array([0.4]))
     src = [gen.Source(gen.SRC_BACKGROUND, 0, power=np.array([1.0]), packets=40000),
-           gen.Source(gen.SRC_POINT, 0, pos=(1.01, 0.97, 1.03), power=np.array([2.0]), packets=40000)]
+           gen.Source(gen.SRC_POINT, 0, pos=(1.51, 1.47, 1.53), power=np.array([2.0]), packets=40000)]
     ora = oracle.Model(tree, dust)
     eo, esco, sto, reco = ora.trace(src, seed=5, rec_stride=1)
     ctx = new_ctx(torch)
     m = ctx.build_tree(tree)
     ctx.set_dust(m, dust)
     r = ctx.trace_packets(src, seed=5, precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS,
-                          blocks_per_cu=32, rec_stride=1)
+                          blocks_per_cu=per_cu, rec_stride=1)
     eg = r["e_abs_node"].cpu().numpy()
     assert rel_rms(eg, eo) <= 1e-3
     rg = r["records"]
@@ -365,6 +376,8 @@ def test_region_overflow_and_records(torch):
     same = np.mean(rg["crossings"] == reco["crossings"])
     assert same > 0.99, same
     assert np.array_equal(rg["birth"], reco["birth"])
+    r64 = ctx.trace_packets(src, seed=5, precision=rt.FP64)
+    assert r["stats"]["crossings"] == pytest.approx(r64["stats"]["crossings"], rel=1e-3)
 
 
 def test_region_and_global_schedules_agree(torch):
