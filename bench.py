@@ -163,7 +163,7 @@ def main():
             if a.workload in ("cloud", "deep"):
                 ctx.solve_temperature(m, r["e_abs_node"], 2.0, 3000.0)
                 for d in w.map_dirs:
-                    ctx.render_map(m, d, w.map_npix, lam_all)
+                    ctx.render_map(m, d, w.map_npix, lam_all, precision=precision)
             elif a.workload == "disc":
                 ctx.solve_temperature(m, a_stars + r["e_abs_node"], 2.0, 3000.0)
         out["post_s"] = time.perf_counter() - t

@@ -218,7 +218,9 @@ rt_status rt_lambda_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_
  * ((i+0.5)/npix - 0.5) W e1 + ((j+0.5)/npix - 0.5) W e2 with e1 = z x n / |z x n| (x if n is
  * along z), e2 = n x e1, W = width (<= 0: largest root extent).  Along each ray
  * I <- I exp(-dtau) + (1 - a) B(T) (1 - exp(-dtau)).  image [n_sel][npix][npix] (host or
- * device) in erg s^-1 cm^-2 Hz^-1 sr^-1; crossings (may be NULL) counts leaf entries. */
+ * device) in erg s^-1 cm^-2 Hz^-1 sr^-1; crossings (may be NULL) counts leaf entries.
+ * precision: RT_FP64, or RT_FP32_LOCAL (the same FP64 ray geometry, hence the same cells;
+ * the transfer per wavelength evaluated in FP32). */
 rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32_t npix,
                         double width, int32_t n_sel, const int32_t* lambda_idx,
                         int32_t precision, double* image, uint64_t* crossings);

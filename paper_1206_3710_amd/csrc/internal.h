@@ -222,8 +222,8 @@ hipError_t launch_dust_lum(const ModelDev* models, int model, int64_t n_leaves,
                            double* lum, unsigned long long* lmax_bits, hipStream_t s);
 hipError_t launch_dust_quant(int64_t n_leaves, const double* lum,
                              const unsigned long long* lmax_bits, uint64_t* q, hipStream_t s);
-hipError_t launch_render_fp64(const ModelDev* models, int model, const int32_t* child,
-                              const int32_t* up, const double* rho64, const double* t_node,
-                              const LamConst* lc, const int32_t* lam_idx, int n_sel,
-                              const double* view /* n, e1, e2, centre, W */, int npix,
-                              double* image, unsigned long long* crossings, hipStream_t s);
+hipError_t launch_render(bool f32, const ModelDev* models, int model, const int32_t* child,
+                         const int32_t* up, const double* rho64, const double* t_node,
+                         const LamConst* lc, const int32_t* lam_idx, int n_sel,
+                         const double* view /* n, e1, e2, centre, W */, int npix,
+                         double* image, unsigned long long* crossings, hipStream_t s);

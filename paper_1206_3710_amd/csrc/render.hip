@@ -2,6 +2,10 @@
 // view, I <- I exp(-dtau) + (1 - a) B(T) (1 - exp(-dtau)) cell by cell.  Up to NS wavelengths
 // are carried in registers per pass; the host splits longer selections into passes.
 // Built with -ffp-contract=off like the FP64 trace.
+//
+// Two forms share the ray geometry (FP64, so both visit the same cells): the FP64 form
+// evaluates the transfer in FP64; the FP32 form evaluates it per wavelength in FP32 (hardware
+// exponentials, constants staged in LDS), which is where the work of a map is.
 #include "device.h"
 
 using namespace rtd;
@@ -10,8 +14,8 @@ namespace {
 
 constexpr double kK = 1.380649e-16;
 
-template <int NS>
-__global__ __launch_bounds__(256) void render_fp64_kernel(
+template <int NS, bool F32>
+__global__ __launch_bounds__(256) void render_kernel(
     const ModelDev* __restrict__ models, int model, const int32_t* __restrict__ child,
     const int32_t* __restrict__ up, const double* __restrict__ rho64,
     const double* __restrict__ t_node, const LamConst* __restrict__ lc,
@@ -20,6 +24,19 @@ __global__ __launch_bounds__(256) void render_fp64_kernel(
   const ModelDev& m = models[model];
   const Dims D = dims_of(m);
   const ChildPlain ch{child};
+  // FP32 form: per-wavelength constants kappa_ext * cell size, 1 - albedo, 2 h nu^3 / c^2,
+  // h nu / k
+  __shared__ float s_kc[NS], s_a1[NS], s_pre[NS], s_hk[NS];
+  if (F32) {
+    if (threadIdx.x < NS && (int)threadIdx.x < n_sel) {
+      const LamConst& L = lc[lam_idx[threadIdx.x]];
+      s_kc[threadIdx.x] = (float)(L.kext * m.cell_cm);
+      s_a1[threadIdx.x] = (float)(1.0 - L.alb);
+      s_pre[threadIdx.x] = (float)L.pre;
+      s_hk[threadIdx.x] = (float)(L.hnu / kK);
+    }
+    __syncthreads();
+  }
   const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long ncross = 0;
   if (pix < (int64_t)npix * npix) {
@@ -30,9 +47,12 @@ __global__ __launch_bounds__(256) void render_fp64_kernel(
     double Q[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) Q[a] = view[9 + a] + ox * view[3 + a] + oy * view[6 + a];
-    double I[NS];
+    double I[F32 ? 1 : NS];
+    float I32[F32 ? NS : 1];
 #pragma unroll
-    for (int q = 0; q < NS; ++q) I[q] = 0.0;
+    for (int q = 0; q < (F32 ? 1 : NS); ++q) I[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < (F32 ? NS : 1); ++q) I32[q] = 0.0f;
     double tn = -INFINITY, tf = INFINITY;
     int ax = -1;
     bool miss = false;
@@ -85,7 +105,21 @@ __global__ __launch_bounds__(256) void render_fp64_kernel(
           }
         }
         const double s = texit;
-        if (rho > 0.0 && s > 0.0) {
+        if (F32 && rho > 0.0 && s > 0.0) {
+          const float tc = (float)t_node[canon_of(m, node)];
+          const float f = (float)(rho * s);
+          const float inv_t = tc > 0.0f ? 1.0f / tc : 0.0f;
+#pragma unroll
+          for (int q = 0; q < NS; ++q) {
+            if (q < n_sel) {
+              const float dtau = s_kc[q] * f;
+              const float att = __builtin_amdgcn_exp2f(dtau * -1.44269504f);
+              const float em = one_minus_exp(dtau);
+              const float b = tc > 0.0f ? s_pre[q] / expm1f(s_hk[q] * inv_t) : 0.0f;
+              I32[q] = fmaf(I32[q], att, s_a1[q] * b * em);
+            }
+          }
+        } else if (!F32 && rho > 0.0 && s > 0.0) {
           const double tc = t_node[canon_of(m, node)];
 #pragma unroll
           for (int q = 0; q < NS; ++q) {
@@ -132,7 +166,7 @@ __global__ __launch_bounds__(256) void render_fp64_kernel(
     }
 #pragma unroll
     for (int q = 0; q < NS; ++q)
-      if (q < n_sel) image[((int64_t)q * npix + j) * npix + i] = I[q];
+      if (q < n_sel) image[((int64_t)q * npix + j) * npix + i] = F32 ? (double)I32[q] : I[F32 ? 0 : q];
   }
   if (crossings) {
     ncross = wave_sum_u64(ncross);
@@ -142,23 +176,26 @@ __global__ __launch_bounds__(256) void render_fp64_kernel(
 
 }  // namespace
 
-hipError_t launch_render_fp64(const ModelDev* models, int model, const int32_t* child,
-                              const int32_t* up, const double* rho64, const double* t_node,
-                              const LamConst* lc, const int32_t* lam_idx, int n_sel,
-                              const double* view, int npix, double* image,
-                              unsigned long long* crossings, hipStream_t s) {
+hipError_t launch_render(bool f32, const ModelDev* models, int model, const int32_t* child,
+                         const int32_t* up, const double* rho64, const double* t_node,
+                         const LamConst* lc, const int32_t* lam_idx, int n_sel,
+                         const double* view, int npix, double* image,
+                         unsigned long long* crossings, hipStream_t s) {
   const int64_t n = (int64_t)npix * npix;
   const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  if (n_sel <= 4)
-    hipLaunchKernelGGL(render_fp64_kernel<4>, grid, block, 0, s, models, model, child, up, rho64,
-                       t_node, lc, lam_idx, n_sel, view, npix, image, crossings);
-  else if (n_sel <= 8)
-    hipLaunchKernelGGL(render_fp64_kernel<8>, grid, block, 0, s, models, model, child, up, rho64,
-                       t_node, lc, lam_idx, n_sel, view, npix, image, crossings);
-  else if (n_sel <= 16)
-    hipLaunchKernelGGL(render_fp64_kernel<16>, grid, block, 0, s, models, model, child, up, rho64,
-                       t_node, lc, lam_idx, n_sel, view, npix, image, crossings);
-  else
-    return hipErrorInvalidValue;
+#define RT_RENDER(NS, F)                                                                        \
+  hipLaunchKernelGGL((render_kernel<NS, F>), grid, block, 0, s, models, model, child, up, rho64, \
+                     t_node, lc, lam_idx, n_sel, view, npix, image, crossings)
+  if (n_sel > 16) return hipErrorInvalidValue;
+  if (f32) {
+    if (n_sel <= 4) RT_RENDER(4, true);
+    else if (n_sel <= 8) RT_RENDER(8, true);
+    else RT_RENDER(16, true);
+  } else {
+    if (n_sel <= 4) RT_RENDER(4, false);
+    else if (n_sel <= 8) RT_RENDER(8, false);
+    else RT_RENDER(16, false);
+  }
+#undef RT_RENDER
   return hipGetLastError();
 }

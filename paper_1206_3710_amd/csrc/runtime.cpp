@@ -1405,7 +1405,8 @@ rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32
     if (!n_obs || !lambda_idx || !image) return fail(ctx, RT_EINVAL, "null argument");
     if (npix < 1 || npix > 16384) return fail(ctx, RT_EINVAL, "npix must be in [1, 16384]");
     if (n_sel < 1) return fail(ctx, RT_EINVAL, "n_sel must be >= 1");
-    if (precision != RT_FP64) return fail(ctx, RT_EINVAL, "maps are computed in RT_FP64");
+    if (precision != RT_FP64 && precision != RT_FP32_LOCAL)
+      return fail(ctx, RT_EINVAL, "precision must be RT_FP64 or RT_FP32_LOCAL");
     HostModel& h = ctx->models[model];
     if (h.nl < 1) return fail(ctx, RT_ESTATE, "rt_set_dust not called for model %d", model);
     if (!h.has_T) return fail(ctx, RT_ESTATE, "model %d has no temperatures", model);
@@ -1453,7 +1454,8 @@ rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32
     if (rt_status s = stage_out(ctx, image, img_bytes, ctx->tmp_out, &dimg, &copy)) return s;
     for (int q0 = 0; q0 < n_sel; q0 += 16) {
       const int nq = std::min(16, n_sel - q0);
-      HIPCHK(launch_render_fp64(ctx->d_models.as<ModelDev>(), model, ctx->d_child.as<int32_t>(),
+      HIPCHK(launch_render(precision == RT_FP32_LOCAL, ctx->d_models.as<ModelDev>(), model,
+                           ctx->d_child.as<int32_t>(),
                                 ctx->d_up.as<int32_t>(), ctx->d_rho64.as<double>(), h.d_T.as<double>(),
                                 h.d_lc.as<LamConst>(), ctx->lamidx.as<int32_t>() + q0, nq,
                                 ctx->view.as<double>(), npix,

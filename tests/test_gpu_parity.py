@@ -464,3 +464,27 @@ def test_sweep_graph_replay_matches_direct_launches(torch):
             assert np.array_equal(a["records"][f], b["records"][f]), f
         ea, eb = a["e_abs_node"].cpu().numpy(), b["e_abs_node"].cpu().numpy()
         assert rel_rms(eb, ea) < 1e-5
+
+
+def test_render_fp32_transfer_against_fp64(torch):
+    """Maps with the transfer in FP32: the same cells as the FP64 map (equal crossing counts),
+    each pixel within 1e-4 relative of it (a few hundred FP32 steps of a few roundings each)."""
+    w = gen.c2(n_root=24, max_level=3, n_lambda=12, packets=20000)
+    ctx = new_ctx(torch)
+    m = ctx.build_tree(w.trees[0])
+    ctx.set_dust(m, w.dusts[0])
+    r = ctx.trace_packets(w.sources, seed=w.seed, precision=rt.FP64)
+    ctx.solve_temperature(m, r["e_abs_node"], 2.0, 3000.0)
+    lam = list(range(12))
+    for d in [(1.0, 0.0, 0.0), (0.3, -0.5, 0.81)]:
+        i64, c64 = ctx.render_map(m, d, 48, lam, precision=rt.FP64)
+        i32, c32 = ctx.render_map(m, d, 48, lam, precision=rt.FP32_LOCAL)
+        assert c32 == c64 > 0
+        a64, a32 = i64.cpu().numpy(), i32.cpu().numpy()
+        # values below the FP32 range of a wavelength's map (far Wien tail at dust temperatures)
+        # count against the brightest map of the selection
+        floor = 1e-7 * np.abs(a64).max()
+        err = np.abs(a32 - a64)
+        rel = err / np.maximum(np.abs(a64), floor)
+        print("max relative error per wavelength", rel.max(axis=(1, 2)))
+        assert np.all(err <= 1e-4 * np.abs(a64) + floor)
