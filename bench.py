@@ -33,8 +33,8 @@ HBM_PEAK_GBS = 8000.0
 # device-to-device copy (fetch x2.0, write x1.0), per leaf crossing.  Valid only for the kernel
 # sources the counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "506b67c4fb4ad2076b61096a0e62810d6a82138bf48c284e5596413d639b75e8",
-                "fetch_bytes_per_crossing": 10.584, "write_bytes_per_crossing": 4.306}
+                "sha256": "360903e475716071e6a7d0317807615d6fee07e6f7de3c0a759a6300d581ab9b",
+                "fetch_bytes_per_crossing": 10.212, "write_bytes_per_crossing": 4.703}
 
 
 WORKLOADS = {
