@@ -37,7 +37,9 @@ class Stats(C.Structure):
     _fields_ = [("crossings", C.c_uint64), ("scatterings", C.c_uint64), ("kills", C.c_uint64),
                 ("truncated", C.c_uint64), ("packets", C.c_uint64), ("dropped_zero_q", C.c_uint64),
                 ("e_emit", C.c_double), ("e_abs", C.c_double), ("e_esc", C.c_double),
-                ("e_killed", C.c_double), ("e_rr_gain", C.c_double), ("e_trunc", C.c_double)]
+                ("e_killed", C.c_double), ("e_rr_gain", C.c_double), ("e_trunc", C.c_double),
+                ("splits", C.c_uint64), ("split_kills", C.c_uint64), ("e_split_killed", C.c_double),
+                ("e_split_gain", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -72,7 +74,9 @@ def lib():
         L.om_trace.restype = C.c_int
         L.om_trace.argtypes = [P, C.c_int32, C.c_int32, P, P, P, P, P, P, C.c_uint64, C.c_uint32,
                                C.c_double, C.c_double, C.c_int64, C.c_int32, C.c_int64, C.c_int64,
-                               C.c_int32, P, P, P, C.c_int64, P]
+                               C.c_int32, P, P, P, C.c_int64, P, C.c_int32]
+        L.om_branch_id.restype = C.c_uint32
+        L.om_branch_id.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
         L.om_solve_temperature.argtypes = [P, P, C.c_double, C.c_double, P]
         L.om_emission.restype = C.c_double
         L.om_emission.argtypes = [P, C.c_int64, C.c_double]
@@ -175,7 +179,7 @@ class Model:
 
     def trace(self, sources, seed, iteration=0, model_index=0, rr_threshold=0.0, rr_prob=0.0,
               max_events=0, per_lambda=False, pid_begin=0, pid_end=-1, lam_sel=-1,
-              t_node=None, rec_stride=0, deposits=True):
+              t_node=None, rec_stride=0, deposits=True, split_n=1):
         """Follow packets of ``sources`` (gen.Source list) -> (e_abs, e_esc, stats, records)."""
         L = lib()
         ns = len(sources)
@@ -202,7 +206,7 @@ class Model:
                         iteration, rr_threshold, rr_prob, max_events, int(per_lambda),
                         pid_begin, pid_end, lam_sel, None if e_abs is None else _p(e_abs),
                         _p(e_esc), C.byref(st),
-                        rec_stride, None if rec is None else _p(rec))
+                        rec_stride, None if rec is None else _p(rec), split_n)
         if rc != 0:
             raise OracleError(L.om_error().decode())
         if per_lambda and e_abs is not None:
@@ -252,6 +256,10 @@ def rotate(d, mu, phi):
 def cdf_pick(q, r):
     q = np.ascontiguousarray(q, dtype=np.uint64)
     return int(lib().om_cdf_pick(_p(q), len(q), C.c_uint64(int(r))))
+
+
+def branch_id(b, n, c):
+    return int(lib().om_branch_id(b, n, c))
 
 
 def uniform(x):

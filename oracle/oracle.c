@@ -360,6 +360,7 @@ typedef struct {
   int64_t node, I[3];
   int lev;
   uint32_t k, crossings;
+  uint32_t br;              /* branch of the package (0: the emitted package and its main line) */
 } packet;
 
 typedef struct {
@@ -373,7 +374,34 @@ typedef struct {
   double e_abs_total;       /* sum of the deposits when e_abs is NULL */
   double* e_esc;
   om_stats* st;
+  int32_t split_n;          /* package splitting factor at subgrid entry (1: none) */
+  packet* stack;            /* split packages waiting to be followed */
+  int64_t n_stack, cap_stack;
 } tctx;
+
+/* Branch identifier of child c of branch b split at the package's crossing number n: the
+ * MurmurHash3 32-bit finaliser (A. Appleby) of a mix of the three, limited to 30 bits so that
+ * it fits above the two block bits of the fourth Philox counter word, and never 0. */
+static uint32_t branch_id(uint32_t b, uint32_t n, uint32_t c) {
+  uint32_t h = b * 0x9E3779B1u ^ n * 0x85EBCA77u ^ (c + 1u) * 0xC2B2AE3Du;
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  h &= 0x3FFFFFFFu;
+  return h ? h : 1u;
+}
+
+uint32_t om_branch_id(uint32_t b, uint32_t n, uint32_t c) { return branch_id(b, n, c); }
+
+static void push_packet(tctx* c, const packet* q) {
+  if (c->n_stack == c->cap_stack) {
+    c->cap_stack = c->cap_stack ? 2 * c->cap_stack : 64;
+    c->stack = (packet*)realloc(c->stack, sizeof(packet) * (size_t)c->cap_stack);
+  }
+  c->stack[c->n_stack++] = *q;
+}
 
 /* Henyey-Greenstein cosine by inverse CDF (R7). */
 static double hg_mu(double g, double u) {
@@ -410,7 +438,7 @@ static void rotate(double d[3], double mu, double phi) {
 }
 
 /* Result codes of a propagation */
-enum { PK_ESCAPED = 0, PK_KILLED = 1, PK_TRUNC = 2 };
+enum { PK_ESCAPED = 0, PK_KILLED = 1, PK_TRUNC = 2, PK_SPLITKILL = 3 };
 
 static int propagate(tctx* c, packet* p) {
   const om_model* m = c->m;
@@ -460,7 +488,7 @@ static int propagate(tctx* c, packet* p) {
         return PK_TRUNC;
       }
       c->st->scatterings += 1;
-      uint32_t ctr[4] = {c->pid, c->stream, p->k, 0u}, x[4];
+      uint32_t ctr[4] = {c->pid, c->stream, p->k, p->br << 2}, x[4];
       philox10(c->key0, c->key1, ctr, x);
       if (c->rr_p > 0.0 && p->w < c->rr_thr * p->w0) {
         if (unif(x[0]) < c->rr_p) {
@@ -479,11 +507,42 @@ static int propagate(tctx* c, packet* p) {
     }
     p->P[ax] = face_ax;
     int sgn = p->d[ax] > 0.0 ? 1 : -1;
+    const int old_lev = p->lev;
     if (cross_face(m, ax, sgn, p->P, &p->node, &p->lev, p->I)) {
       c->e_esc[c->lam] += p->w;
       return PK_ESCAPED;
     }
     p->crossings += 1;
+    if (c->split_n > 1 && p->lev > old_lev) {
+      /* entering a subgrid: split_n packages of equal weight; this one continues, the others
+         (new branches) draw their own free paths and wait on the stack */
+      const double wn = p->w / (double)c->split_n;
+      for (int ch = 1; ch < c->split_n; ++ch) {
+        packet q = *p;
+        q.w = wn;
+        q.crossings = 0;
+        q.br = branch_id(p->br, p->crossings, (uint32_t)ch);
+        uint32_t ctr[4] = {c->pid, c->stream, p->crossings, (q.br << 2) | 2u}, x[4];
+        philox10(c->key0, c->key1, ctr, x);
+        q.tau = -log(unif(x[0]));
+        push_packet(c, &q);
+      }
+      p->w = wn;
+      c->st->splits += 1;
+    } else if (c->split_n > 1 && p->lev < old_lev) {
+      /* leaving a subgrid: survives with probability 1/split_n, weight multiplied by split_n */
+      uint32_t ctr[4] = {c->pid, c->stream, p->crossings, (p->br << 2) | 3u}, x[4];
+      philox10(c->key0, c->key1, ctr, x);
+      if (unif(x[0]) < 1.0 / (double)c->split_n) {
+        const double nw = p->w * (double)c->split_n;
+        c->st->e_split_gain += nw - p->w;
+        p->w = nw;
+      } else {
+        c->st->split_kills += 1;
+        c->st->e_split_killed += p->w;
+        return PK_SPLITKILL;
+      }
+    }
   }
 }
 
@@ -557,8 +616,9 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
              const double* t_node, uint64_t seed, uint32_t iteration, double rr_threshold,
              double rr_prob, int64_t max_events, int32_t per_lambda, int64_t pid_begin,
              int64_t pid_end, int32_t lam_sel, double* e_abs, double* e_esc, om_stats* stats,
-             int64_t rec_stride, om_record* rec) {
+             int64_t rec_stride, om_record* rec, int32_t split_n) {
   if (m->nl < 1) { seterr("dust not set"); return -1; }
+  if (split_n < 1 || split_n > 64) { seterr("split factor must be in [1, 64]"); return -1; }
   if (n_src < 1 || n_src > 255) { seterr("bad source count"); return -1; }
   for (int s = 0; s < n_src; ++s) {
     if (kind[s] < 0 || kind[s] > 3) { seterr("bad source kind"); return -1; }
@@ -591,6 +651,10 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
   c.st = stats;
   c.e_abs = NULL;
   c.e_abs_total = 0.0;
+  c.split_n = split_n;
+  c.stack = NULL;
+  c.n_stack = 0;
+  c.cap_stack = 0;
   for (int s = 0; s < n_src; ++s) {
     const int64_t N = packets[s];
     int64_t jb = pid_begin < 0 ? 0 : pid_begin;
@@ -695,6 +759,12 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
           r->birth = birth;
           r->w = p.w;
         }
+        /* the packages split off this one, and theirs in turn */
+        while (c.n_stack > 0) {
+          packet q = c.stack[--c.n_stack];
+          propagate(&c, &q);
+          stats->crossings += q.crossings;
+        }
       }
       if (kind[s] == OM_DUST) dust_cdf_free(&dc);
     }
@@ -708,6 +778,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
   for (int i = 0; i < nl; ++i) ee += e_esc[i];
   stats->e_abs = ea;
   stats->e_esc = ee;
+  free(c.stack);
   return 0;
 }
 

@@ -57,10 +57,13 @@ void om_dnu(const om_model* m, double* dnu);
 typedef struct {
   uint64_t crossings, scatterings, kills, truncated, packets, dropped_zero_q;
   double e_emit, e_abs, e_esc, e_killed, e_rr_gain, e_trunc;
+  uint64_t splits, split_kills;
+  double e_split_killed, e_split_gain;
 } om_stats;
 
 /* One packet's end state (for sampled-history comparison). status: 0 escaped, 1 killed,
-   2 truncated.  node: canonical node where the packet ended (-1 if escaped); birth: node where
+   2 truncated, 3 killed leaving a subgrid (package splitting).  node: canonical node where the
+   packet ended (-1 if escaped); birth: node where
    it started; w: its weight at the end. */
 typedef struct {
   uint32_t status, crossings, events, pad;
@@ -78,13 +81,19 @@ typedef struct {
  * (source s, wavelength i) is sampled when j % rec_stride == 0 and stored at
  * (s*n_lambda + i)*nrec + (j-pid_begin)/rec_stride with nrec = ceil((pid_end-pid_begin)/rec_stride);
  * only packets j in [pid_begin, min(pid_end, packets[s])) are traced, and only wavelength
- * lam_sel unless it is negative. */
+ * lam_sel unless it is negative.  split_n > 1 turns on package splitting at subgrid entry
+ * (Sect. 2.3): a package whose crossing lands in a deeper leaf continues with 1/split_n of its
+ * weight and split_n - 1 packages of the same weight start there (each a new branch, with its
+ * own free path); a package whose crossing lands in a shallower leaf survives with probability
+ * 1/split_n, its weight multiplied by split_n.  A record follows the emitted package's main
+ * line (the branch that keeps its identifier). */
 int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kind,
              const double* pos /*3n*/, const double* dir /*3n*/, const double* power,
              const int64_t* packets, const double* t_node, uint64_t seed, uint32_t iteration,
              double rr_threshold, double rr_prob, int64_t max_events, int32_t per_lambda,
              int64_t pid_begin, int64_t pid_end, int32_t lam_sel,
-             double* e_abs, double* e_esc, om_stats* stats, int64_t rec_stride, om_record* rec);
+             double* e_abs, double* e_esc, om_stats* stats, int64_t rec_stride, om_record* rec,
+             int32_t split_n);
 
 /* Equilibrium temperature per leaf: 4 pi m sum_i kappa_abs_i B_i(T) dnu_i = A. */
 void om_solve_temperature(const om_model* m, const double* a_node, double t_min, double t_max,
@@ -102,6 +111,7 @@ double om_hg_mu(double g, double u);
 void om_rotate(double* d, double mu, double phi);
 double om_uniform(uint32_t x);
 int64_t om_cdf_pick(const uint64_t* q, int64_t n, uint64_t r);
+uint32_t om_branch_id(uint32_t b, uint32_t n, uint32_t c);
 
 #ifdef __cplusplus
 }

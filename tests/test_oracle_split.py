@@ -1,0 +1,131 @@
+"""Pins of the oracle's package splitting at subgrid entry with Russian roulette at subgrid exit
+(paper Sect. 2.3; the noise study of Sect. 4.1, Table 1).
+
+Splitting and the exit roulette keep every expectation unchanged, so the pins are the exact
+energy identity, closed forms in expectation, agreement in expectation with the unsplit
+estimator, and the reduction of the noise in the refined cells that the paper reports for the
+external field."""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+
+def energy_gap(st):
+    lhs = st["e_emit"] + st["e_rr_gain"] + st["e_split_gain"]
+    rhs = st["e_abs"] + st["e_esc"] + st["e_killed"] + st["e_trunc"] + st["e_split_killed"]
+    return abs(lhs - rhs) / lhs
+
+
+def test_split_factor_one_changes_nothing():
+    w = gen.c1("A", packets=5000)
+    o = oracle.Model(w.trees[0], w.dusts[0])
+    a = o.trace(w.sources, seed=w.seed, rec_stride=7)
+    b = o.trace(w.sources, seed=w.seed, rec_stride=7, split_n=1)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[3], b[3])
+    assert b[2]["splits"] == 0 and b[2]["split_kills"] == 0
+
+
+@pytest.mark.parametrize("n,rr", [(2, False), (4, True), (8, True)])
+def test_split_energy_identity(n, rr):
+    """Emitted + roulette gains = absorbed + escaped + killed + truncated, to rounding."""
+    w = gen.c1("A", packets=8000)
+    o = oracle.Model(w.trees[0], w.dusts[0])
+    kw = dict(rr_threshold=1e-2, rr_prob=0.8) if rr else {}
+    _, _, st, _ = o.trace(w.sources, seed=w.seed, split_n=n, **kw)
+    assert st["splits"] > 0 and st["split_kills"] > 0
+    assert energy_gap(st) < 1e-12
+
+
+def test_branch_ids_distinct():
+    """Children of one split, and splits at different crossings or on different branches, get
+    different nonzero 30-bit branch identifiers."""
+    ids = set()
+    for b in (0, 1, 12345, 0x3FFFFFFF):
+        for n in range(1, 200):
+            for c in range(1, 8):
+                v = oracle.branch_id(b, n, c)
+                assert 0 < v < (1 << 30)
+                ids.add((b, n, c, v))
+    vals = [v for (_, _, _, v) in ids]
+    assert len(set(vals)) == len(vals)
+
+
+def _refined_box(levels):
+    """4^3 root, side 1 per root cell, with the central 2^3 root cells refined `levels` deep."""
+    refined, kids = [], []
+    centre = np.array([ix + 4 * (iy + 4 * iz) for iz in (1, 2) for iy in (1, 2) for ix in (1, 2)])
+    refined.append(np.sort(centre).astype(np.int64))
+    n = 8 * 8
+    for _ in range(1, levels):
+        kids.append(np.full(n, 1.0))
+        refined.append(np.arange(n, dtype=np.int64))
+        n *= 8
+    kids.append(np.full(n, 1.0))
+    return gen.TreeDesc(4, 4, 4, 1.0, np.full(64, 1.0), refined, kids)
+
+
+@pytest.mark.parametrize("n", [2, 4])
+def test_split_unbiased_beam_closed_form(n):
+    """Pure absorber, uniform density, beam straight through the refined block: every history
+    is a straight line, the mean escaped energy is w0 exp(-tau) and the mean absorbed energy
+    w0 (1 - exp(-tau)); splitting at the block's entry and the roulette at its exit leave the
+    mean unchanged, with variance e^-2tau (1 - 1/n) per emitted packet."""
+    tree = _refined_box(2)
+    kappa = 0.2
+    dust = gen.Dust(np.array([1.0]), np.array([kappa]), np.array([0.0]), np.array([0.0]))
+    o = oracle.Model(tree, dust)
+    npk = 20000
+    src = [gen.Source(gen.SRC_BEAM, 0, pos=(0.3, 1.7, 2.2), dir=(1.0, 0.0, 0.0),
+                      power=np.array([1.0]), packets=npk)]
+    _, esc, st, _ = o.trace(src, seed=11, split_n=n)
+    w0 = st["e_emit"] / npk
+    tau = kappa * 1.0 * (4.0 - 0.3)
+    assert st["splits"] == npk  # one level increase on the way in
+    mean = esc[0] / npk
+    sd = w0 * math.exp(-tau) * math.sqrt((1.0 - 1.0 / n) / npk)
+    assert abs(mean - w0 * math.exp(-tau)) < 4.0 * sd
+    assert abs(st["e_abs"] / npk - w0 * (1.0 - math.exp(-tau))) < 4.0 * sd + 1e-12 * w0
+
+
+def _per_level(o, e):
+    lv = o.level_of_nodes()
+    return np.array([e[lv == l].sum() for l in range(int(lv.max()) + 1)])
+
+
+def test_split_unbiased_per_level():
+    """Scattering cloud in an isotropic field: the absorbed energy per hierarchy level agrees
+    in expectation with and without splitting (means over 8 independent seeds, within 4 combined
+    standard errors)."""
+    w = gen.c1("A", packets=6000)
+    o = oracle.Model(w.trees[0], w.dusts[0])
+    runs = {1: [], 4: []}
+    for n in runs:
+        for k in range(8):
+            e, _, _, _ = o.trace(w.sources, seed=w.seed + 100 * k, split_n=n)
+            runs[n].append(_per_level(o, e))
+    a, b = np.array(runs[1]), np.array(runs[4])
+    se = np.sqrt(a.var(axis=0, ddof=1) / len(a) + b.var(axis=0, ddof=1) / len(b))
+    assert np.all(np.abs(a.mean(axis=0) - b.mean(axis=0)) < 4.0 * se)
+
+
+def test_split_reduces_noise_in_refined_cells():
+    """The paper's finding for the external field (Table 1): with the same number of emitted
+    packages, splitting lowers the cell-by-cell noise in the deepest level.  Strongly scattering
+    medium (albedo 0.9), block refined three levels deep in an isotropic field; noise is the
+    relative RMS difference (Eq. 7 form) of 6 independent runs from their mean."""
+    tree = _refined_box(3)
+    dust = gen.Dust(np.array([1.0]), np.array([1.0]), np.array([0.9]), np.array([0.3]))
+    o = oracle.Model(tree, dust)
+    src = [gen.Source(gen.SRC_BACKGROUND, 0, power=np.array([1.0]), packets=3000)]
+    deep = (o.level_of_nodes() == 3) & o.leaf_mask
+
+    def noise(n):
+        es = np.array([o.trace(src, seed=3 + 7 * k, split_n=n)[0][deep] for k in range(6)])
+        ref = es.mean(axis=0)
+        return float(np.sqrt(((es - ref) ** 2).mean() / (ref ** 2).mean()))
+    n1, n4 = noise(1), noise(4)
+    assert n4 < 0.85 * n1, (n1, n4)
