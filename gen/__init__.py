@@ -494,6 +494,23 @@ def uniform_refined_tree(root=(2, 2, 2), level=2, rho=1.0, cell_cm=1.0) -> TreeD
     return TreeDesc(nx, ny, nz, cell_cm, np.full(nx * ny * nz, float(rho)), refined, kids)
 
 
+def refined_block(levels: int, n: int = 4, rho: float = 1.0) -> TreeDesc:
+    """n^3 root cells of side 1, uniform density; the central 2^3 root cells (n = 4) or the
+    root cells of index 1..n-2 on every axis are refined ``levels`` deep, the rest stay root
+    leaves.  Packets crossing into the block enter a deeper leaf and leave it into a shallower
+    one (the subgrid entries and exits of package splitting)."""
+    inner = [i for i in range(1, n - 1)]
+    centre = np.array([ix + n * (iy + n * iz) for iz in inner for iy in inner for ix in inner])
+    refined, kids = [np.sort(centre).astype(np.int64)], []
+    m = 8 * len(centre)
+    for _ in range(1, levels):
+        kids.append(np.full(m, float(rho)))
+        refined.append(np.arange(m, dtype=np.int64))
+        m *= 8
+    kids.append(np.full(m, float(rho)))
+    return TreeDesc(n, n, n, 1.0, np.full(n ** 3, float(rho)), refined, kids)
+
+
 def describe(w: Workload) -> dict:
     out = {"name": w.name, "models": len(w.trees)}
     out["nodes"] = int(sum(t.n_nodes for t in w.trees))

@@ -443,7 +443,6 @@ enum { PK_ESCAPED = 0, PK_KILLED = 1, PK_TRUNC = 2, PK_SPLITKILL = 3 };
 static int propagate(tctx* c, packet* p) {
   const om_model* m = c->m;
   const double kext = m->kext[c->lam], alb = m->alb[c->lam], g = m->g[c->lam];
-  p->crossings = 1;
   for (;;) {
     double rho = m->rho[p->node];
     double se = (kext * rho) * m->cell_cm;
@@ -520,7 +519,7 @@ static int propagate(tctx* c, packet* p) {
       for (int ch = 1; ch < c->split_n; ++ch) {
         packet q = *p;
         q.w = wn;
-        q.crossings = 0;
+        q.crossings = 0; /* its cell was counted by the package it split from */
         q.br = branch_id(p->br, p->crossings, (uint32_t)ch);
         uint32_t ctr[4] = {c->pid, c->stream, p->crossings, (q.br << 2) | 2u}, x[4];
         philox10(c->key0, c->key1, ctr, x);
@@ -687,6 +686,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
       for (int64_t j = jb; j < je; ++j) {
         packet p;
         memset(&p, 0, sizeof p);
+        p.crossings = 1; /* the birth cell counts as entered */
         c.pid = (uint32_t)j;
         uint32_t ctr0[4] = {(uint32_t)j, c.stream, 0u, 0u}, ctr1[4] = {(uint32_t)j, c.stream, 0u, 1u};
         uint32_t b0[4], b1[4];

@@ -54,27 +54,13 @@ def test_branch_ids_distinct():
     assert len(set(vals)) == len(vals)
 
 
-def _refined_box(levels):
-    """4^3 root, side 1 per root cell, with the central 2^3 root cells refined `levels` deep."""
-    refined, kids = [], []
-    centre = np.array([ix + 4 * (iy + 4 * iz) for iz in (1, 2) for iy in (1, 2) for ix in (1, 2)])
-    refined.append(np.sort(centre).astype(np.int64))
-    n = 8 * 8
-    for _ in range(1, levels):
-        kids.append(np.full(n, 1.0))
-        refined.append(np.arange(n, dtype=np.int64))
-        n *= 8
-    kids.append(np.full(n, 1.0))
-    return gen.TreeDesc(4, 4, 4, 1.0, np.full(64, 1.0), refined, kids)
-
-
 @pytest.mark.parametrize("n", [2, 4])
 def test_split_unbiased_beam_closed_form(n):
     """Pure absorber, uniform density, beam straight through the refined block: every history
     is a straight line, the mean escaped energy is w0 exp(-tau) and the mean absorbed energy
     w0 (1 - exp(-tau)); splitting at the block's entry and the roulette at its exit leave the
     mean unchanged, with variance e^-2tau (1 - 1/n) per emitted packet."""
-    tree = _refined_box(2)
+    tree = gen.refined_block(2)
     kappa = 0.2
     dust = gen.Dust(np.array([1.0]), np.array([kappa]), np.array([0.0]), np.array([0.0]))
     o = oracle.Model(tree, dust)
@@ -89,6 +75,27 @@ def test_split_unbiased_beam_closed_form(n):
     sd = w0 * math.exp(-tau) * math.sqrt((1.0 - 1.0 / n) / npk)
     assert abs(mean - w0 * math.exp(-tau)) < 4.0 * sd
     assert abs(st["e_abs"] / npk - w0 * (1.0 - math.exp(-tau))) < 4.0 * sd + 1e-12 * w0
+
+
+def test_split_crossing_count_closed_form():
+    """Pure absorber, beam along x through the block refined 2 levels deep: the package as
+    emitted enters its birth cell, 8 level-2 cells and the root cell behind the block (10
+    cells, split at the first level-2 cell, roulette at the last crossing); each of the N - 1
+    new packages starts in that first level-2 cell, already counted, and enters the other 7
+    and the root cell behind (8).  No event happens, so the total is exact whatever the
+    roulette decides."""
+    tree = gen.refined_block(2)
+    dust = gen.Dust(np.array([1.0]), np.array([0.2]), np.array([0.0]), np.array([0.0]))
+    o = oracle.Model(tree, dust)
+    npk = 500
+    src = [gen.Source(gen.SRC_BEAM, 0, pos=(0.3, 1.7, 2.2), dir=(1.0, 0.0, 0.0),
+                      power=np.array([1.0]), packets=npk)]
+    for n in (1, 2, 5):
+        _, _, st, rec = o.trace(src, seed=4, split_n=n, rec_stride=1)
+        assert st["crossings"] == npk * (10 + 8 * (n - 1)), (n, st["crossings"])
+        assert np.all(rec["crossings"] == 10)
+        if n > 1:
+            assert st["splits"] == npk
 
 
 def _per_level(o, e):
@@ -117,7 +124,7 @@ def test_split_reduces_noise_in_refined_cells():
     packages, splitting lowers the cell-by-cell noise in the deepest level.  Strongly scattering
     medium (albedo 0.9), block refined three levels deep in an isotropic field; noise is the
     relative RMS difference (Eq. 7 form) of 6 independent runs from their mean."""
-    tree = _refined_box(3)
+    tree = gen.refined_block(3)
     dust = gen.Dust(np.array([1.0]), np.array([1.0]), np.array([0.9]), np.array([0.3]))
     o = oracle.Model(tree, dust)
     src = [gen.Source(gen.SRC_BACKGROUND, 0, power=np.array([1.0]), packets=3000)]
