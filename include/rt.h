@@ -128,7 +128,8 @@ typedef struct {
 
 /* Per-packet end state, written for sampled packets (see rt_trace_opts.rec_stride). */
 typedef struct {
-  uint32_t status;     /* 0 escaped, 1 killed by roulette, 2 truncated at max_events */
+  uint32_t status;     /* 0 escaped, 1 killed by roulette, 2 truncated at max_events,
+                          3 killed by the roulette at a subgrid exit (package splitting) */
   uint32_t crossings;  /* leaf cells entered, including the birth cell */
   uint32_t events;     /* scattering events reached */
   uint32_t pad;
@@ -166,7 +167,15 @@ typedef struct {
   int32_t sweep_graph;      /* region schedule: > 0 replays a captured HIP graph of 16 sweeps
                                until the queues drain (per-pass durations are then not
                                reported); <= 0 (default) launches the same kernels directly */
-  int32_t pad2;
+  int32_t split_n;          /* package splitting (paper Sect. 2.3), region schedule only: at a
+                               face crossing into a deeper leaf the package becomes split_n
+                               packages of 1/split_n its weight (the new ones draw their own
+                               free path); at a crossing into a shallower leaf it survives with
+                               probability 1/split_n and its weight is multiplied by split_n.
+                               0 or 1 = off, at most 64.  Records (rec_stride) follow the
+                               package as emitted (branch 0).  A split that would overrun the
+                               sweep's queue room is skipped (counted in split_skips); either
+                               choice leaves every expectation unchanged */
 } rt_trace_opts;
 
 typedef struct {
@@ -181,6 +190,13 @@ typedef struct {
                                kernel, or the region pass of every sweep), HIP events recorded
                                on the stream each launch runs on */
   uint64_t main_launches;   /* number of those launches */
+  uint64_t splits;          /* crossings at which a package was split */
+  uint64_t split_kills;     /* packages ended by the roulette at a subgrid exit */
+  uint64_t split_skips;     /* splits skipped for lack of queue room */
+  double e_split_killed;    /* weight of those packages */
+  double e_split_gain;      /* weight added to the survivors of that roulette; energy balance:
+                               e_emit + e_rr_gain + e_split_gain = e_abs + e_esc + e_killed +
+                               e_trunc + e_split_killed */
 } rt_trace_stats;
 
 /* Follow packets_per_lambda packets of every source at every wavelength of its model.  Packet

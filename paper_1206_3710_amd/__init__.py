@@ -60,7 +60,7 @@ class TraceOpts(C.Structure):
                 ("refill_threshold", C.c_float), ("schedule", C.c_int32),
                 ("chunk_packets", C.c_int32), ("tail_park", C.c_int32), ("batch_packets", C.c_int64),
                 ("rec_stride", C.c_int64), ("records", C.c_void_p), ("sweep_graph", C.c_int32),
-                ("pad2", C.c_int32)]
+                ("split_n", C.c_int32)]
 
 
 class TraceStats(C.Structure):
@@ -68,7 +68,9 @@ class TraceStats(C.Structure):
                 ("truncated", C.c_uint64), ("packets", C.c_uint64), ("e_emit", C.c_double),
                 ("e_abs", C.c_double), ("e_esc", C.c_double), ("e_killed", C.c_double),
                 ("e_rr_gain", C.c_double), ("e_trunc", C.c_double), ("kernel_ms", C.c_double),
-                ("reduce_ms", C.c_double), ("main_ms", C.c_double), ("main_launches", C.c_uint64)]
+                ("reduce_ms", C.c_double), ("main_ms", C.c_double), ("main_launches", C.c_uint64),
+                ("splits", C.c_uint64), ("split_kills", C.c_uint64), ("split_skips", C.c_uint64),
+                ("e_split_killed", C.c_double), ("e_split_gain", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -222,9 +224,11 @@ class Context:
                       block_size: int = 0, blocks_per_cu: int = 0, refill_threshold: float = 0.0,
                       rec_stride: int = 0, per_lambda: bool = False, schedule: int = SCHED_REGIONS,
                       chunk_packets: int = 0, batch_packets: int = 0, tail_park: int = 0,
-                      sweep_graph: int = 0):
+                      sweep_graph: int = 0, split_n: int = 1):
         """Trace the packets of ``sources`` (objects with kind, model, pos, dir, power,
-        packets).  Returns a dict of device tensors and the statistics."""
+        packets).  ``split_n`` > 1 turns on package splitting at subgrid entry with the
+        roulette at subgrid exit (region schedule).  Returns a dict of device tensors and the
+        statistics."""
         torch = _torch()
         n = len(sources)
         arr = (Source * n)()
@@ -252,7 +256,7 @@ class Context:
         opts = TraceOpts(seed, iteration, precision, rr_threshold, rr_prob, max_events, block_size,
                          blocks_per_cu, refill_threshold, schedule, chunk_packets, tail_park,
                          batch_packets, rec_stride, None if rec is None else rec.data_ptr(),
-                         sweep_graph, 0)
+                         sweep_graph, split_n)
         st = TraceStats()
         self._check(lib().rt_trace_packets(self.h, n, arr, C.byref(opts), _ptr(e_node),
                                            _ptr(e_lam), _ptr(e_esc), C.byref(st)))
@@ -291,7 +295,7 @@ class Context:
                          start.get("max_events", 0), start.get("block_size", 0),
                          start.get("blocks_per_cu", 0), start.get("refill_threshold", 0.0),
                          schedule, start.get("chunk_packets", 0), start.get("tail_park", 0),
-                         start.get("batch_packets", 0), 0, None)
+                         start.get("batch_packets", 0), 0, None, 0, start.get("split_n", 0))
         best = TraceOpts()
         rate = C.c_double()
         self._check(lib().rt_autotune(self.h, n, arr, C.byref(base), sample_fraction,

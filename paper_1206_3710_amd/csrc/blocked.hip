@@ -17,7 +17,9 @@ using namespace rtd;
 
 namespace {
 
-enum : int { B_EMPTY = 0, B_CROSS = 1, B_EVENT = 2, B_DONE = 3, B_EXIT = 4 };
+// lane states; B_SPLIT / B_ROUL: just crossed into a deeper / shallower leaf with package
+// splitting on (Sect. 2.3), waiting for the split or the exit roulette
+enum : int { B_EMPTY = 0, B_CROSS = 1, B_EVENT = 2, B_DONE = 3, B_EXIT = 4, B_SPLIT = 5, B_ROUL = 6 };
 
 constexpr uint32_t kMaxCrossings = 1u << 30;
 constexpr int kRecoverLevel = 2;
@@ -213,7 +215,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
                                          int32_t* s_word, float* s_acc, int32_t* s_up, uint32_t* s_next,
                                          double* s_esc, double* s_misc, bool esc_lds, int lane,
                                          unsigned long long& c_cross, uint32_t& c_scat, uint32_t& c_kill,
-                                         uint32_t& c_trunc) {
+                                         uint32_t& c_trunc, uint32_t& c_split, uint32_t& c_skill,
+                                         uint32_t& c_sskip) {
   const TraceParams& p = b.t;
   const float rr_thr = (float)p.rr_thr, rr_p = (float)p.rr_p;
   const float rr_gain = rr_p > 0.0f ? 1.0f / (1.0f - rr_p) : 1.0f;
@@ -242,6 +245,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   float w = 0.f, w0 = 0.f, tau = 0.f, rho = 0.f;
   double O0 = 0.0, O1 = 0.0, O2 = 0.0;
   uint32_t pid = 0, ev = 0, ncross = 0, stream = 0;
+  uint32_t br = 0;             // branch identifier (0: the package as emitted)
+  const bool splitting = p.split_n > 1;
   float ks = 0.f, ka = 0.f, g = 0.f;  // scattering / absorption opacity per root-cell length per unit density
   int esc_slot = 0;
   int32_t xax = 0, xsg = 0;
@@ -290,10 +295,12 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           ev = rec.ev;
           ncross = rec.ncross;
           birth = rec.birth;
+          br = (rec.flag & 2) ? (uint32_t)rec.birth : 0u;
+          const bool crossing = rec.flag & 1;
           const int L = rec.lev;
           int32_t J0 = rec.I[0], J1 = rec.I[1], J2 = rec.I[2];
           int ax = 0, sg = 1;
-          if (rec.flag) {
+          if (crossing) {
             ax = rec.ax;
             sg = rec.sg ? -1 : 1;
             if (ax == 0) J0 += sg;
@@ -325,14 +332,14 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           const int32_t R0 = J0 >> shr, R1 = J1 >> shr, R2 = J2 >> shr;
           const int32_t rootl = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
           int32_t raw = 0;
-          const bool misplaced = (L < R.rl && !rec.flag) || R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] ||
+          const bool misplaced = (L < R.rl && !crossing) || R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] ||
                                  R1 >= R.hi[1] || R2 < R.lo[2] || R2 >= R.hi[2];
           if (misplaced) {
             // a record queued for the wrong region (never expected): retire it as truncated
             ++c_trunc;
             atomicAdd(&s_misc[2], (double)w);
             c_cross += ncross;
-          } else if (rec.flag) {
+          } else if (crossing) {
             land(word_of, ax, sg, Lj, rec.I[0], rec.I[1], rec.I[2], J0, J1, J2, rootl, R.rl, x0, x1, x2, O0,
                  O1, O2, d0, d1, d2, node, lev, I0, I1, I2, raw);
             ++ncross;
@@ -354,6 +361,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           }
           rho = __int_as_float(raw);
           state = misplaced ? B_EMPTY : B_CROSS;
+          if (!misplaced && crossing && splitting && lev != L) state = lev > L ? B_SPLIT : B_ROUL;
         }
       }
     }
@@ -400,7 +408,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
             // a region belongs to one model: its escapes are tallied per wavelength in LDS
             if (esc_lds) atomicAdd(&s_esc[esc_slot - (int)md.lam_base], (double)w);
             else unsafeAtomicAdd(p.esc + esc_slot, (double)w);
-            if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
+            if (p.rec_stride > 0 && br == 0 && (pid % (uint32_t)p.rec_stride) == 0) {
               const JobDev& J = p.jobs[job];
               rt_record rc{0u, ncross, ev, 0u, -1, canon_of(md, birth), (double)w};
               p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
@@ -441,6 +449,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
               if (++ncross >= kMaxCrossings) {
                 ev = (uint32_t)p.max_events;
                 state = B_EVENT;
+              } else if (splitting && lev != L) {
+                state = lev > L ? B_SPLIT : B_ROUL;
               }
             }
           }
@@ -477,7 +487,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         rc.lev = (uint8_t)lev;
         rc.ax = (uint8_t)xax;
         rc.sg = xsg > 0 ? 0 : 1;
-        rc.flag = xpark ? 0 : 1;
+        rc.flag = (xpark ? 0 : 1) | (br ? 2 : 0);
         rc.x[0] = x0;
         rc.x[1] = x1;
         rc.x[2] = x2;
@@ -487,7 +497,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         rc.w = w;
         rc.w0 = w0;
         rc.tau = tau;
-        rc.birth = birth;
+        rc.birth = br ? (int32_t)br : birth;
         rc.O[0] = O0;
         rc.O[1] = O1;
         rc.O[2] = O2;
@@ -508,13 +518,103 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
       }
     }
 
+    // ---------------- package splitting at subgrid entry, roulette at exit (Sect. 2.3) ----------------
+    if (splitting && __ballot(state == B_SPLIT || state == B_ROUL)) {
+      const uint32_t N = (uint32_t)p.split_n;
+      if (state == B_ROUL) {
+        // survives with probability 1/N: (2 m + 1) 2^-24 < 1/N  <=>  (2 m + 1) N < 2^24
+        const uint4 xr = philox(pid, stream, ncross, (br << 2) | 3u, p.key0, p.key1);
+        if ((2u * (xr.x >> 9) + 1u) * (uint64_t)N < (1ull << 24)) {
+          const float nw = w * (float)N;
+          atomicAdd(&s_misc[4], (double)nw - (double)w);
+          w = nw;
+          state = B_CROSS;
+        } else {
+          ++c_skill;
+          atomicAdd(&s_misc[3], (double)w);
+          if (p.rec_stride > 0 && br == 0 && (pid % (uint32_t)p.rec_stride) == 0) {
+            const JobDev& J = p.jobs[job];
+            rt_record rc{3u, ncross, ev, 0u, (int64_t)b.rcanon[R.gbase + node], canon_of(md, birth), (double)w};
+            p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
+          }
+          c_cross += ncross;
+          state = B_EMPTY;
+        }
+      }
+      const uint64_t sm = __ballot(state == B_SPLIT);
+      if (sm) {
+        // N - 1 new packages per splitting lane, in the region's own queue for the next sweep;
+        // a wave takes them from the sweep's split room, or skips splits that do not fit
+        const uint32_t per = N - 1u;
+        const uint32_t nsplit = (uint32_t)__popcll(sm);
+        uint32_t n_ok = 0, blo = 0, bhi = 0;
+        if (lane == 0) {
+          const unsigned long long used = atomicAdd(b.split_used, (unsigned long long)nsplit * per);
+          const unsigned long long room = *b.split_room;
+          const unsigned long long fit = used < room ? (room - used) / per : 0ull;
+          n_ok = fit < nsplit ? (uint32_t)fit : nsplit;
+          if (n_ok) {
+            const unsigned long long base = atomicAdd(b.u_count, (unsigned long long)n_ok * per);
+            blo = (uint32_t)base;
+            bhi = (uint32_t)(base >> 32);
+          }
+        }
+        n_ok = __shfl(n_ok, 0, 64);
+        blo = __shfl(blo, 0, 64);
+        bhi = __shfl(bhi, 0, 64);
+        if (state == B_SPLIT) {
+          const uint32_t r = lane_rank(sm);
+          if (r < n_ok) {
+            const float wn = w / (float)N;
+            uint64_t idx = (((uint64_t)bhi << 32) | blo) + (uint64_t)r * per;
+            PRec rc;
+            rc.I[0] = I0;
+            rc.I[1] = I1;
+            rc.I[2] = I2;
+            rc.lev = (uint8_t)lev;
+            rc.ax = 0;
+            rc.sg = 0;
+            rc.flag = 2;
+            rc.x[0] = x0;
+            rc.x[1] = x1;
+            rc.x[2] = x2;
+            rc.d[0] = d0;
+            rc.d[1] = d1;
+            rc.d[2] = d2;
+            rc.w = wn;
+            rc.w0 = w0;
+            rc.O[0] = O0;
+            rc.O[1] = O1;
+            rc.O[2] = O2;
+            rc.pid = pid;
+            rc.job = job;
+            rc.ev = ev;
+            rc.ncross = 0;
+            for (uint32_t c = 1; c < N; ++c, ++idx) {
+              const uint32_t bc = branch_id(br, ncross, c);
+              const uint4 xr = philox(pid, stream, ncross, (bc << 2) | 2u, p.key0, p.key1);
+              rc.tau = -logf(unif32(xr.x));
+              rc.birth = (int32_t)bc;
+              b.u_out[idx] = rc;
+              b.u_key[idx] = own_key;
+            }
+            w = wn;
+            ++c_split;
+          } else {
+            ++c_sskip;
+          }
+          state = B_CROSS;
+        }
+      }
+    }
+
     // ---------------- scattering events, serviced together ----------------
     if (state == B_EVENT) {
       ++ev;
       if ((int64_t)ev > p.max_events) {
         ++c_trunc;
         atomicAdd(&s_misc[2], (double)w);
-        if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
+        if (p.rec_stride > 0 && br == 0 && (pid % (uint32_t)p.rec_stride) == 0) {
           const JobDev& J = p.jobs[job];
           rt_record rc{2u, ncross, ev, 0u, (int64_t)b.rcanon[R.gbase + node], canon_of(md, birth), (double)w};
           p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
@@ -527,13 +627,13 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         O0 = ((double)I0 + (double)x0) * h;
         O1 = ((double)I1 + (double)x1) * h;
         O2 = ((double)I2 + (double)x2) * h;
-        const uint4 xr = philox(pid, stream, ev, 0u, p.key0, p.key1);
+        const uint4 xr = philox(pid, stream, ev, br << 2, p.key0, p.key1);
         bool killed = false;
         if (rr_p > 0.0f && w < rr_thr * w0) {
           if (unif32(xr.x) < rr_p) {
             ++c_kill;
             atomicAdd(&s_misc[0], (double)w);
-            if (p.rec_stride > 0 && (pid % (uint32_t)p.rec_stride) == 0) {
+            if (p.rec_stride > 0 && br == 0 && (pid % (uint32_t)p.rec_stride) == 0) {
               const JobDev& J = p.jobs[job];
               rt_record rc{1u, ncross, ev, 0u, (int64_t)b.rcanon[R.gbase + node], canon_of(md, birth), (double)w};
               p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
@@ -548,8 +648,9 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           }
         }
         if (!killed) {
-          const float mu = hg_mu32(g, unif32(xr.y));
-          rotate32(d0, d1, d2, mu, kTwoPiF * unif32(xr.z));
+          float mu, st;
+          hg_angle32(g, unif32(xr.y), mu, st);
+          rotate32(d0, d1, d2, mu, st, kTwoPiF * unif32(xr.z));
           exit_coef(d0, n0, c0);
           exit_coef(d1, n1, c1);
           exit_coef(d2, n2, c2);
@@ -570,13 +671,13 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   int32_t* s_up = reinterpret_cast<int32_t*>(smem + 8 * (size_t)cap);
   __shared__ int s_item;
   __shared__ uint32_t s_next;
-  __shared__ double s_misc[4];
+  __shared__ double s_misc[5];
   __shared__ double s_esc[kEscLds];
   const TraceParams& p = b.t;
   const int tid = threadIdx.x, lane = tid & 63;
-  if (tid < 4) s_misc[tid] = 0.0;
+  if (tid < 5) s_misc[tid] = 0.0;
   unsigned long long c_cross = 0;
-  uint32_t c_scat = 0, c_kill = 0, c_trunc = 0;
+  uint32_t c_scat = 0, c_kill = 0, c_trunc = 0, c_split = 0, c_skill = 0, c_sskip = 0;
 
   for (;;) {
     __syncthreads();
@@ -602,10 +703,10 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     __syncthreads();
     if (R.n <= cap)
       run_item<true>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
-                     c_cross, c_scat, c_kill, c_trunc);
+                     c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip);
     else
       run_item<false>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
-                      c_cross, c_scat, c_kill, c_trunc);
+                      c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip);
     __syncthreads();
     if (b.accb64) {
       double* __restrict__ gacc64 = b.accb64 + R.gbase;
@@ -635,11 +736,23 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     if (sc_kill) atomicAdd(&p.stats->kills, sc_kill);
     if (sc_trunc) atomicAdd(&p.stats->truncated, sc_trunc);
   }
+  if (p.split_n > 1) {
+    const unsigned long long sc_split = wave_sum_u64(c_split);
+    const unsigned long long sc_skill = wave_sum_u64(c_skill);
+    const unsigned long long sc_sskip = wave_sum_u64(c_sskip);
+    if (lane == 0) {
+      if (sc_split) atomicAdd(&p.stats->splits, sc_split);
+      if (sc_skill) atomicAdd(&p.stats->split_kills, sc_skill);
+      if (sc_sskip) atomicAdd(&p.stats->split_skips, sc_sskip);
+    }
+  }
   __syncthreads();
   if (tid == 0) {
     if (s_misc[0] != 0.0) unsafeAtomicAdd(&p.stats->e_killed, s_misc[0]);
     if (s_misc[1] != 0.0) unsafeAtomicAdd(&p.stats->e_rr_gain, s_misc[1]);
     if (s_misc[2] != 0.0) unsafeAtomicAdd(&p.stats->e_trunc, s_misc[2]);
+    if (s_misc[3] != 0.0) unsafeAtomicAdd(&p.stats->e_split_killed, s_misc[3]);
+    if (s_misc[4] != 0.0) unsafeAtomicAdd(&p.stats->e_split_gain, s_misc[4]);
   }
 }
 

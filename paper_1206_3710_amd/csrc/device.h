@@ -322,6 +322,20 @@ __device__ __forceinline__ void rotate64(double d[3], double mu, double phi) {
   d[2] = nz / nn;
 }
 
+// Branch identifier of child c of branch b split off at crossing number n (package splitting,
+// Sect. 2.3): the MurmurHash3 32-bit finaliser of a mix of the three, 30 bits, never 0.  A
+// branch's random numbers use Philox counter word 3 = (branch << 2) | block.
+__device__ __forceinline__ uint32_t branch_id(uint32_t b, uint32_t n, uint32_t c) {
+  uint32_t h = b * 0x9E3779B1u ^ n * 0x85EBCA77u ^ (c + 1u) * 0xC2B2AE3Du;
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  h &= 0x3FFFFFFFu;
+  return h ? h : 1u;
+}
+
 // ---- FP32-local segment arithmetic (shared by both FP32-local schedules) ----
 // Exit-distance coefficients of one axis: t = fma(x, n, c) is the distance, in local cell
 // units, to the face the packet moves toward: (1 - x)/d for d > 0, -x/d for d < 0, infinite
@@ -351,20 +365,27 @@ __device__ __forceinline__ float one_minus_exp(float q) {
   return q < 0.5f ? small : large;
 }
 
-__device__ __forceinline__ float hg_mu32(float g, float u) {
-  float mu;
-  if (fabsf(g) >= 1e-6f) {
-    const float gg = g * g;
-    const float frac = (1.0f - gg) / (1.0f - g + 2.0f * g * u);
-    mu = (1.0f + gg - frac * frac) / (2.0f * g);
-  } else {
-    mu = 2.0f * u - 1.0f;
-  }
-  return fminf(fmaxf(mu, -1.0f), 1.0f);
+// Henyey-Greenstein polar angle by inversion of its CDF (FP32), returned as its cosine and
+// sine.  With a = 1 - g + 2 g u and t = (1 - g^2) / a, the inversion gives
+//   1 - mu = (1 - g)(1 - u)(t + 1 - g) / a,   1 + mu = (1 + g) u (1 + g + t) / a,
+// products of positive factors (a itself is formed as (1 - g)(1 - u) + (1 + g) u), so both keep
+// full relative accuracy and sin = sqrt((1 - mu)(1 + mu)) stays accurate for near-forward and
+// near-backward scattering, where sqrt(1 - mu^2) would carry an error of about 2^-24 / sin.
+// 1 - u is exact for the uniforms of unif32.  g = 0 reduces to mu = 2u - 1 (isotropic).
+__device__ __forceinline__ void hg_angle32(float g, float u, float& mu, float& st) {
+  const float gm = 1.0f - g, gp = 1.0f + g, um = 1.0f - u;
+  const float ra = 1.0f / (gm * um + gp * u);
+  const float t = gm * gp * ra;
+  const float om = gm * um * (t + gm) * ra;
+  const float op = gp * u * (gp + t) * ra;
+  mu = fminf(fmaxf(0.5f * (op - om), -1.0f), 1.0f);
+  st = sqrtf(om * op);
 }
 
-__device__ __forceinline__ void rotate32(float& dx, float& dy, float& dz, float mu, float phi) {
-  const float st = sqrtf(fmaxf(1.0f - mu * mu, 0.0f));
+// Direction change by polar angle (cosine mu, sine st) and azimuth phi (Wang, Jacques & Zheng
+// 1995 form).  The sine of the old direction's polar angle is taken from its x and y components,
+// which keeps its relative accuracy for directions close to the z axis.
+__device__ __forceinline__ void rotate32(float& dx, float& dy, float& dz, float mu, float st, float phi) {
   float sp, cp;
   sincosf(phi, &sp, &cp);
   float nx, ny, nz;
@@ -373,7 +394,7 @@ __device__ __forceinline__ void rotate32(float& dx, float& dy, float& dz, float 
     ny = st * sp;
     nz = dz > 0.0f ? mu : -mu;
   } else {
-    const float tmp = sqrtf(1.0f - dz * dz);
+    const float tmp = sqrtf(dx * dx + dy * dy);
     const float r = st / tmp;
     nx = r * (dx * dz * cp - dy * sp) + dx * mu;
     ny = r * (dy * dz * cp + dx * sp) + dy * mu;

@@ -62,6 +62,8 @@ struct JobDev {
 struct DevStats {
   unsigned long long crossings, scatterings, kills, truncated, packets;
   double e_emit, e_killed, e_rr_gain, e_trunc;
+  unsigned long long splits, split_kills, split_skips;
+  double e_split_killed, e_split_gain;
 };
 
 struct TraceParams {
@@ -85,7 +87,7 @@ struct TraceParams {
   double rr_thr, rr_p;
   int64_t max_events;
   float refill_thr;
-  int32_t pad;
+  int32_t split_n;           // package splitting factor at subgrid entry (1: none)
   // dust emission tables
   const uint64_t* cdf_qpre;
   const uint64_t* cdf_q;
@@ -115,11 +117,13 @@ struct RegionDev {
 // A packet waiting at a region boundary, just born, or re-queued inside its cell: 96 bytes.
 struct PRec {
   int32_t I[3];          // integer coordinates of the cell it is in, at level lev
-  uint8_t lev, ax, sg, flag;  // flag 0: inside the cell (born or re-queued, no crossing
-                              // counted on resume); 1: about to cross axis ax (sg 0: +, 1: -)
+  uint8_t lev, ax, sg, flag;  // flag bit 0 clear: inside the cell (born, re-queued or split
+                              // off, no crossing counted on resume); set: about to cross axis
+                              // ax (sg 0: +, 1: -).  Bit 1: a split-off branch, `birth` holds
+                              // its branch identifier
   float x[3], d[3];      // local coordinates in that cell, direction
   float w, w0, tau;
-  int32_t birth;         // internal id of the birth leaf (records)
+  int32_t birth;         // internal id of the birth leaf (records), or the branch id
   double O[3];           // FP64 segment origin (root-cell units)
   uint32_t pid;
   int32_t job;
@@ -160,6 +164,8 @@ struct BlkParams {
   int32_t chunk;             // packets per work item
   int32_t tail_park;         // crossing rounds after an item's queue runs dry before the
                              // packets still in flight are re-queued (INT32_MAX = never)
+  const unsigned long long* split_room;  // queue room for split-off packages in this sweep
+  unsigned long long* split_used;        // records reserved for them so far
 };
 
 // Device-resident state of the sweeps of one trace (all sizes the sweep launches need).
@@ -172,6 +178,9 @@ struct SweepState {
   uint32_t n_items, item_counter;
   uint32_t done;                // a sweep found nothing queued and nothing left to emit
   uint32_t sweeps;              // sweeps that had packets to follow
+  unsigned long long split_room;  // queue room for split-off packages in this sweep
+  unsigned long long split_used;  // records reserved for them so far
+  unsigned long long cap_all;     // allocated records per queue buffer
   unsigned long long log_in[16];  // records in the input of each sweep of the current block
 };
 

@@ -865,6 +865,9 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     return fail(ctx, RT_EINVAL, "the region schedule needs block_size 256, 512, 768 or 1024");
   if (o->chunk_packets < 0 || o->batch_packets < 0)
     return fail(ctx, RT_EINVAL, "chunk_packets and batch_packets must be >= 0");
+  if (o->split_n < 0 || o->split_n > 64) return fail(ctx, RT_EINVAL, "split_n must be in [0, 64]");
+  if (o->split_n > 1 && !region_sched)
+    return fail(ctx, RT_EINVAL, "package splitting needs the FP32-local region schedule");
   if (o->rec_stride < 0 || (o->rec_stride > 0 && !o->records))
     return fail(ctx, RT_EINVAL, "records needed when rec_stride > 0");
   for (int s = 0; s < n_src; ++s) {
@@ -1017,6 +1020,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   p.rr_p = o->rr_prob;
   p.max_events = o->max_events > 0 ? o->max_events : 1000000;
   p.refill_thr = o->refill_threshold > 0.0f ? o->refill_threshold : (region_sched ? 0.15f : 0.5f);
+  p.split_n = o->split_n > 1 ? o->split_n : 1;
   p.cdf_qpre = ctx->cdf_qpre.as<uint64_t>();
   p.cdf_q = ctx->cdf_q.as<uint64_t>();
   p.cdf_lum = ctx->cdf_lum.as<double>();
@@ -1050,23 +1054,27 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     const int64_t capq = std::min<int64_t>(int64_t(1) << 25, std::max<int64_t>((int64_t)start, 4096));
     const int64_t batch = std::min<int64_t>(o->batch_packets > 0 ? o->batch_packets : int64_t(1) << 23, capq);
     const int32_t chunk = o->chunk_packets > 0 ? o->chunk_packets : 16 * bs;
-    if (ctx->q_capacity < capq) {
+    // records per queue buffer: emission keeps each sweep's input + births within capq; with
+    // package splitting a second capq holds the packages split off during a sweep
+    const int64_t cap_all = p.split_n > 1 ? 2 * capq : capq;
+    if (ctx->q_capacity < cap_all) {
       for (int k = 0; k < 2; ++k) {
-        HIPCHK(ctx->q_rec[k].ensure(sizeof(PRec) * capq));
-        HIPCHK(ctx->q_key[k].ensure(4 * capq));
+        HIPCHK(ctx->q_rec[k].ensure(sizeof(PRec) * cap_all));
+        HIPCHK(ctx->q_key[k].ensure(4 * cap_all));
       }
-      HIPCHK(ctx->q_perm.ensure(4 * capq));
-      ctx->q_capacity = capq;
+      HIPCHK(ctx->q_perm.ensure(4 * cap_all));
+      ctx->q_capacity = cap_all;
     }
     HIPCHK(ctx->q_hist.ensure(4 * n_keys));
     HIPCHK(ctx->q_kfill.ensure(4 * n_keys));
-    HIPCHK(ctx->q_items.ensure(sizeof(WorkItem) * (capq / chunk + n_keys + 1)));
+    HIPCHK(ctx->q_items.ensure(sizeof(WorkItem) * (cap_all / chunk + n_keys + 1)));
     HIPCHK(ctx->q_state.ensure(sizeof(SweepState)));
     SweepState* st = ctx->q_state.as<SweepState>();
     SweepState init;  // stays alive until the first synchronisation below
     {
       std::memset(&init, 0, sizeof init);
       init.total = start;
+      init.cap_all = (unsigned long long)cap_all;
       HIPCHK(hipEventRecord(ctx->ev_c, ctx->stream));
       HIPCHK(hipStreamWaitEvent(ctx->work, ctx->ev_c, 0));
       HIPCHK(hipMemcpyAsync(st, &init, sizeof init, hipMemcpyHostToDevice, ctx->work));
@@ -1090,6 +1098,8 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     b.items = ctx->q_items.as<WorkItem>();
     b.n_items = &st->n_items;
     b.item_counter = &st->item_counter;
+    b.split_room = &st->split_room;
+    b.split_used = &st->split_used;
     b.n_slots_key = n_slots;
     b.chunk = chunk;
     b.tail_park = o->tail_park < 0 ? INT32_MAX : (o->tail_park > 0 ? o->tail_park : 16);
@@ -1134,7 +1144,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     // sweep finds the queues empty and nothing left to emit
     std::vector<char> sig(sizeof b + 6 * sizeof(int64_t));
     {
-      const int64_t extra[6] = {batch, capq, n_keys, grid_pass, bs, reg_lds};
+      const int64_t extra[6] = {batch, capq, n_keys, grid_pass, bs, reg_lds};  // b holds split_n
       std::memcpy(sig.data(), &b, sizeof b);
       std::memcpy(sig.data() + sizeof b, extra, sizeof extra);
     }
@@ -1245,6 +1255,11 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     st_out->reduce_ms = r_ms;
     st_out->main_ms = regions ? main_ms : k_ms;
     st_out->main_launches = main_launches;
+    st_out->splits = ds.splits;
+    st_out->split_kills = ds.split_kills;
+    st_out->split_skips = ds.split_skips;
+    st_out->e_split_killed = ds.e_split_killed;
+    st_out->e_split_gain = ds.e_split_gain;
   }
   return RT_OK;
 }

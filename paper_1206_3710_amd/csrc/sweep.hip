@@ -59,6 +59,11 @@ __global__ void sw_begin_kernel(SweepState* st, int in, int slot, uint64_t batch
   st->e0 = st->emitted;
   st->ne = ne;
   st->emitted += ne;
+  // split-off packages may use what the worst case of exits (every input packet) and this
+  // sweep's births leave of the other buffer
+  const unsigned long long need = n_in + ne;
+  st->split_room = st->cap_all > need ? st->cap_all - need : 0;
+  st->split_used = 0;
   st->n_in = n_in;
   st->log_in[slot] = n_in;
   if (n_in == 0 && ne == 0) st->done = 1u;

@@ -285,8 +285,9 @@ __global__ __launch_bounds__(BS) void trace_fp32_kernel(const TraceParams p) {
           }
         }
         if (!killed) {
-          const float mu = hg_mu32(g, unif32(xr.y));
-          rotate32(d0, d1, d2, mu, kTwoPiF * unif32(xr.z));
+          float mu, st;
+          hg_angle32(g, unif32(xr.y), mu, st);
+          rotate32(d0, d1, d2, mu, st, kTwoPiF * unif32(xr.z));
           exit_coef(d0, n0, c0);
           exit_coef(d1, n1, c1);
           exit_coef(d2, n2, c2);

@@ -447,13 +447,17 @@ def test_autotune_and_cache(torch, tmp_path):
 def test_sweep_graph_replay_matches_direct_launches(torch):
     """The sweeps of the region schedule replayed from a captured HIP graph (16 sweeps per
     replay, twice in a row to reuse the instantiated graph) give the histories of direct
-    launches: equal counts and per-packet records, per-node results to FP32 summation order."""
+    launches: equal counts and per-packet records, per-node results to FP32 summation order.
+    Tail parking is off: which packets a wave re-queues depends on the order in which the waves
+    of a block take their packets, so with it the number of sweeps may differ by one between
+    any two runs."""
     w = gen.c2(n_root=24, max_level=3, n_lambda=4, packets=60000)
     ctx = new_ctx(torch)
     m = ctx.build_tree(w.trees[0])
     ctx.set_dust(m, w.dusts[0])
     kw = dict(seed=w.seed, precision=rt.FP32_LOCAL, rr_threshold=w.rr_threshold, rr_prob=w.rr_prob,
-              schedule=rt.SCHED_REGIONS, blocks_per_cu=8, batch_packets=20000, rec_stride=11)
+              schedule=rt.SCHED_REGIONS, blocks_per_cu=8, batch_packets=20000, rec_stride=11,
+              tail_park=-1)
     a = ctx.trace_packets(w.sources, **kw)
     for _ in range(2):
         b = ctx.trace_packets(w.sources, sweep_graph=1, **kw)

@@ -1,0 +1,188 @@
+"""GPU parity of package splitting at subgrid entry with the roulette at subgrid exit (paper
+Sect. 2.3) in the FP32-local region schedule, against the oracle run with the same split
+factor on the same seeded inputs.
+
+Every branch draws from the counter-based stream with its own branch identifier, so the
+oracle and the GPU follow the same histories: the sampled main-line records (the package as
+emitted) must reproduce the oracle's fates, the split and roulette counts must agree to the
+fraction of FP32-rerouted histories, and the absorbed energy per node must agree far below the
+Monte Carlo noise.  Splitting only rescales the main line's weight by powers of N, exactly, in
+both precisions.  A run that exhausts the sweep's queue room skips splits: it must stay
+energy-conserving and unbiased (closed forms of a beam through a pure absorber)."""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+rt = pytest.importorskip("paper_1206_3710_amd")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def rel_rms(a, ref):
+    return float(np.sqrt(((a - ref) ** 2).sum() / (ref ** 2).sum()))
+
+
+def energy_gap(st):
+    lhs = st["e_emit"] + st["e_rr_gain"] + st["e_split_gain"]
+    rhs = st["e_abs"] + st["e_esc"] + st["e_killed"] + st["e_trunc"] + st["e_split_killed"]
+    return abs(lhs - rhs) / lhs
+
+
+def _box_case():
+    """Scattering block refined 3 levels deep in an isotropic field, plus a point source in a
+    coarse root cell."""
+    tree = gen.refined_block(3)
+    dust = gen.Dust(np.array([1.0]), np.array([1.0]), np.array([0.9]), np.array([0.3]))
+    src = [gen.Source(gen.SRC_BACKGROUND, 0, power=np.array([1.0]), packets=20000),
+           gen.Source(gen.SRC_POINT, 0, pos=(0.4, 0.6, 3.5), power=np.array([3.0]), packets=20000)]
+    return tree, dust, src, 17
+
+
+def _c1_case():
+    w = gen.c1("A", packets=40000)
+    return w.trees[0], w.dusts[0], w.sources, w.seed
+
+
+def _run(torch, tree, dust, src, seed, **kw):
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    r = ctx.trace_packets(src, seed=seed, precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS, **kw)
+    ctx.close()
+    return r
+
+
+def test_split_factor_one_changes_nothing(torch):
+    """split_n 1 is the unsplit path: identical records and counts."""
+    tree, dust, src, seed = _c1_case()
+    kw = dict(rr_threshold=1e-2, rr_prob=0.8, rec_stride=13)
+    a = _run(torch, tree, dust, src, seed, **kw)
+    b = _run(torch, tree, dust, src, seed, split_n=1, **kw)
+    for k in ("crossings", "scatterings", "kills", "packets"):
+        assert a["stats"][k] == b["stats"][k], k
+    assert b["stats"]["splits"] == 0 and b["stats"]["split_kills"] == 0
+    for f in ("status", "crossings", "events", "node", "birth", "w"):
+        assert np.array_equal(a["records"][f], b["records"][f]), f
+
+
+@pytest.mark.parametrize("case,n,per_cu", [("c1", 2, 0), ("c1", 4, 16), ("box", 4, 0), ("box", 8, 8)])
+def test_split_parity_against_oracle(torch, case, n, per_cu):
+    tree, dust, src, seed = _c1_case() if case == "c1" else _box_case()
+    kw = dict(rr_threshold=1e-2, rr_prob=0.8)
+    ora = oracle.Model(tree, dust)
+    eo, _, sto, reco = ora.trace(src, seed=seed, rec_stride=1, split_n=n, **kw)
+    # a few thousand births per sweep keep the split-off packages within the sweep's room
+    r = _run(torch, tree, dust, src, seed, rec_stride=1, split_n=n, blocks_per_cu=per_cu,
+             batch_packets=4096, **kw)
+    st = r["stats"]
+    assert st["split_skips"] == 0
+    assert sto["splits"] > 0 and sto["split_kills"] > 0
+    # main line: the package as emitted, one record per packet
+    rg = r["records"]
+    assert len(rg) == len(reco)
+    assert np.array_equal(rg["birth"], reco["birth"])
+    same = ((rg["status"] == reco["status"]) & (rg["crossings"] == reco["crossings"])
+            & (rg["events"] == reco["events"]) & (rg["node"] == reco["node"]))
+    assert same.mean() >= 0.99, same.mean()
+    assert np.any(reco["status"] == 3) and np.any(rg["status"] == 3)
+    # FP32 weights: the step model of the full-size test (2^-24 (8 n + n^2 / 2), n = crossings
+    # + events + 1) holds for all but a few packets (a grazing exit stretches the effect of the
+    # FP32 direction error); none is off by more than 1e-4, far below a factor of N
+    steps = rg["crossings"].astype(np.float64) + rg["events"] + 1.0
+    tol = 2.0 ** -24 * (8.0 * steps + 0.5 * steps * steps) * np.abs(reco["w"])
+    dw = np.abs(rg["w"] - reco["w"])
+    assert np.mean(dw[same] > tol[same]) <= 1e-3
+    bad = same & (dw > 1e-4 * np.abs(reco["w"]))
+    assert not bad.any(), (rg[bad][:5], reco[bad][:5])
+    # all branches: counts agree to the fraction of rerouted histories
+    for k in ("splits", "split_kills", "crossings", "scatterings"):
+        assert abs(st[k] - sto[k]) <= 0.01 * sto[k] + 5, (k, st[k], sto[k])
+    assert st["packets"] == sto["packets"] and st["truncated"] == 0
+    assert energy_gap(st) < 1e-5, energy_gap(st)
+    # per node: far below the Monte Carlo noise of an independent split realisation
+    eg = r["e_abs_node"].cpu().numpy()
+    eb, _, _, _ = ora.trace(src, seed=seed + 1000, split_n=n, **kw)
+    noise = rel_rms(eb, eo) / math.sqrt(2.0)
+    err = rel_rms(eg, eo)
+    print(f"{case} split {n}: rel RMS {err:.3e}, noise {noise:.3e}, splits {st['splits']}")
+    assert err <= 1e-3 and err < 0.25 * noise, (err, noise)
+
+
+@pytest.mark.parametrize("n", [2, 4, 8])
+def test_split_scales_main_line_by_powers_of_n(torch, n):
+    """Without the roulette at events nothing in a history depends on the size of its weight:
+    with and without splitting the package as emitted follows the same path, and its final
+    weight differs by N^k exactly (a split divides it by N, a surviving exit roulette multiplies
+    it by N; both exact for N a power of two), on the GPU as in the oracle.  In the small cloud
+    packets born in, or escaping from, refined cells end with k = +1 or -1."""
+    tree, dust, src, seed = _c1_case()
+    ora = oracle.Model(tree, dust)
+    _, _, _, ro1 = ora.trace(src, seed=seed, rec_stride=1)
+    _, _, _, ron = ora.trace(src, seed=seed, rec_stride=1, split_n=n)
+    g1 = _run(torch, tree, dust, src, seed, rec_stride=1)["records"]
+    gn = _run(torch, tree, dust, src, seed, rec_stride=1, split_n=n, batch_packets=4096)["records"]
+    for f in ("crossings", "events"):
+        esc = gn["status"] == 0
+        assert np.array_equal(gn[f][esc], g1[f][esc]), f
+    both = ((gn["status"] == 0) & (ron["status"] == 0) & (ro1["status"] == 0)
+            & (gn["crossings"] == ron["crossings"]) & (gn["events"] == ron["events"]))
+    assert both.sum() > 10000
+    rg = gn["w"][both] / g1["w"][both]
+    ro = ron["w"][both] / ro1["w"][both]
+    assert np.array_equal(rg, ro)
+    k = np.log2(ro) / math.log2(n)
+    assert np.array_equal(k, np.round(k)) and np.any(k < 0) and np.any(k > 0)
+
+
+@pytest.mark.parametrize("n", [4, 16])
+def test_split_room_exhausted_stays_unbiased(torch, n):
+    """4096 beam packets enter the refined block in one sweep, so the N - 1 new packages of
+    every split do not all fit in the sweep's queue room: the splits that do not fit are
+    skipped.  The run conserves energy, and the mean escaped energy of a pure absorber stays
+    w0 exp(-tau) within 4 standard deviations of the worst case (every split skipped, the exit
+    roulette alone: variance (N - 1) w0^2 exp(-2 tau) per packet)."""
+    tree = gen.refined_block(2)
+    kappa = 0.2
+    dust = gen.Dust(np.array([1.0]), np.array([kappa]), np.array([0.0]), np.array([0.0]))
+    npk = 4096
+    src = [gen.Source(gen.SRC_BEAM, 0, pos=(0.3, 1.7, 2.2), dir=(1.0, 0.0, 0.0),
+                      power=np.array([1.0]), packets=npk)]
+    r = _run(torch, tree, dust, src, 11, split_n=n)
+    st = r["stats"]
+    assert st["split_skips"] > 0 and st["splits"] > 0
+    assert st["splits"] + st["split_skips"] == npk  # one subgrid entry per packet
+    # each package as emitted enters 10 cells, each new package 8 (see the oracle's pin)
+    assert st["crossings"] == 10 * npk + 8 * (n - 1) * st["splits"]
+    assert energy_gap(st) < 1e-5
+    w0 = st["e_emit"] / npk
+    tau = kappa * (4.0 - 0.3)
+    esc = float(r["e_esc"].cpu().numpy()[0]) / npk
+    sd = w0 * math.exp(-tau) * math.sqrt((n - 1.0) / npk)
+    assert abs(esc - w0 * math.exp(-tau)) < 4.0 * sd, (esc, w0 * math.exp(-tau), sd)
+
+
+def test_split_rejected_outside_region_schedule(torch):
+    tree, dust, src, seed = _c1_case()
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    for kw in (dict(precision=rt.FP64), dict(precision=rt.FP32_LOCAL, schedule=rt.SCHED_GLOBAL)):
+        with pytest.raises(rt.RTError):
+            ctx.trace_packets(src, seed=seed, split_n=2, **kw)
+    with pytest.raises(rt.RTError):
+        ctx.trace_packets(src, seed=seed, precision=rt.FP32_LOCAL, split_n=65)
+    r = ctx.trace_packets(src, seed=seed, precision=rt.FP32_LOCAL, split_n=2)
+    assert r["stats"]["splits"] > 0
+    ctx.close()
