@@ -11,6 +11,15 @@ traced once before timing, and a step is one Lambda-iteration step from those te
 trace the dust emission (3e7 packets per wavelength), solve the temperatures of A_stars +
 A_dust.  --workload clouds: 64 uneven clouds, 16 wavelengths, 1e6 packets per (model,
 wavelength), all traced in one call; a step is that trace.
+
+--split-study (cloud and deep workloads) adds, after the timed steps, the package-splitting
+study of Sect. 4.1 (Table 1): the radiation field at the wavelength nearest 4 um, traced 20
+times with and 20 times without splitting (factor 4) from the same small number of packets,
+once for the external field and once for a star embedded in the densest deepest cell; the RMS
+difference per hierarchy level (Eq. 7) from the mean of all runs, normalised to the largest
+value, and the time per run.  It is reported in "splitting" and is not part of the timed
+steps (it is off by default so that a kernel profile of the default run covers the timed
+steps only).
 """
 from __future__ import annotations
 
@@ -52,6 +61,98 @@ WORKLOADS = {
 }
 
 
+def node_geometry(tree):
+    """Level, leaf flag, density and integer coordinates (at the node's level) of every
+    canonical node of a tree description: root cells in x-fastest order, then each level's octs
+    in the ascending order of their parents, cell b = bx + 2 by + 4 bz within its oct."""
+    import numpy as np
+    nx, ny, nz = tree.nx, tree.ny, tree.nz
+    idx = np.arange(nx * ny * nz, dtype=np.int64)
+    coords = [np.stack([idx % nx, (idx // nx) % ny, idx // (nx * ny)], axis=1)]
+    rho = [np.asarray(tree.root_rho, dtype=np.float64)]
+    leaf = [np.ones(len(idx), dtype=bool)]
+    b = np.arange(8)
+    off = np.stack([b & 1, (b >> 1) & 1, (b >> 2) & 1], axis=1)
+    for l, (ref, kids) in enumerate(zip(tree.refined, tree.child_rho)):
+        leaf[l][ref] = False
+        parent = coords[l][ref]
+        coords.append((2 * parent[:, None, :] + off[None, :, :]).reshape(-1, 3))
+        rho.append(np.asarray(kids, dtype=np.float64))
+        leaf.append(np.ones(8 * len(ref), dtype=bool))
+    level = np.concatenate([np.full(len(r), l, dtype=np.int32) for l, r in enumerate(rho)])
+    return level, np.concatenate(leaf), np.concatenate(rho), np.concatenate(coords)
+
+
+def split_study(rt, gen, w, kw32, runs=20, packets=1_000_000, split_n=4, lam_um=4.0):
+    """Noise per hierarchy level (Eq. 7) with and without package splitting, Sect. 4.1.  The
+    per-run fields stay on the GPU (20 x 2 runs of the deep cloud's 1e8 leaves fit easily)."""
+    import numpy as np
+    import torch
+    tree, dust = w.trees[0], w.dusts[0]
+    i = int(np.argmin(np.abs(np.log(dust.lambda_um / lam_um))))
+    d1 = gen.Dust(dust.lambda_um[i:i + 1], dust.kappa_ext[i:i + 1], dust.albedo[i:i + 1],
+                  dust.hg_g[i:i + 1])
+    level, leaf, rho, coords = node_geometry(tree)
+    # J ~ absorbed power / cell mass at one wavelength (kappa_abs is the same in every cell)
+    mass = rho * 8.0 ** (-level.astype(np.float64))
+    use = leaf & (mass > 0)
+    deep = use & (level == level.max())
+    k = np.flatnonzero(deep)[np.argmax(rho[deep])]
+    star = tuple(float(c) for c in (coords[k] + 0.5) * 2.0 ** -int(level[k]))
+    n_lev = int(level.max()) + 1
+    dev = torch.device("cuda", 0)
+    p_bg = float(w.sources[0].power[i])
+    use_idx = torch.from_numpy(np.flatnonzero(use)).to(dev)
+    # dimensionless: absorbed power per unit source power, per mean cell mass
+    inv_mass = torch.from_numpy(mass[use].mean() / mass[use] / p_bg).to(dev)
+    lv = torch.from_numpy(level[use].astype(np.int64)).to(dev)
+    n_cells = torch.bincount(lv, minlength=n_lev).double()
+    del level, leaf, rho, coords, mass, use, deep
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, d1)
+    cases = {"external": [gen.Source(gen.SRC_BACKGROUND, m, power=np.array([p_bg]), packets=packets)],
+             "internal": [gen.Source(gen.SRC_POINT, m, pos=star, power=np.array([p_bg]), packets=packets)]}
+    kw = {k_: v for k_, v in kw32.items() if k_ != "sweep_graph"}
+    out = {"wavelength_um": float(dust.lambda_um[i]), "packets": packets, "runs": runs,
+           "split_n": split_n, "star_root_cell_units": star,
+           "cells_per_level": [int(v) for v in n_cells.tolist()]}
+    for name, src in cases.items():
+        js, ms, cr, sp = {1: [], split_n: []}, {1: [], split_n: []}, {1: [], split_n: []}, []
+        for r in range(runs):
+            for n in (1, split_n):
+                res = ctx.trace_packets(src, seed=w.seed + 7919 * r, precision=rt.FP32_LOCAL,
+                                        split_n=n, **kw)
+                js[n].append((res["e_abs_node"][use_idx] * inv_mass).float())
+                ms[n].append(res["stats"]["kernel_ms"])
+                cr[n].append(res["stats"]["crossings"])
+                if n > 1:
+                    sp.append(res["stats"]["splits"])
+        ref = torch.stack(js[1] + js[split_n]).double().mean(dim=0)
+        noise = {}
+        for n in (1, split_n):
+            acc = torch.zeros(n_lev, dtype=torch.float64, device=dev)
+            for j in js[n]:
+                d2 = (j.double() - ref) ** 2
+                acc += torch.sqrt(torch.bincount(lv, weights=d2, minlength=n_lev) / n_cells)
+            noise[n] = (acc / len(js[n])).tolist()
+        del js, ref
+        top = max(max(noise[1]), max(noise[split_n]))
+        t1, tn = float(np.mean(ms[1])), float(np.mean(ms[split_n]))
+        out[name] = {
+            "noise_per_level_split": [v / top for v in noise[split_n]],
+            "noise_per_level_no_split": [v / top for v in noise[1]],
+            "ms_per_run_split": tn, "ms_per_run_no_split": t1,
+            "crossings_per_run_split": float(np.mean(cr[split_n])),
+            "crossings_per_run_no_split": float(np.mean(cr[1])),
+            "splits_per_run": float(np.mean(sp)),
+            # packets needed for equal noise scale as noise^2: speed-up at the deepest level
+            "gain_deepest_level": (noise[1][-1] / noise[split_n][-1]) ** 2 * t1 / tn,
+        }
+    ctx.close()
+    return out
+
+
 def pass_sources_sha():
     import hashlib
     h = hashlib.sha256()
@@ -86,6 +187,8 @@ def parse():
     ap.add_argument("--graph", action="store_true",
                     help="replay captured graphs of the sweeps (no per-launch durations)")
     ap.add_argument("--trace-only", action="store_true", help="time only the transport step")
+    ap.add_argument("--split-study", action="store_true",
+                    help="add the package-splitting noise study (cloud and deep workloads)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 4 GiB device-to-device (reference for traffic counters)")
     return ap.parse_args()
@@ -253,6 +356,10 @@ def main():
                          f"({sto['crossings']} crossings, {dc:.1f} s, single thread, "
                          f"{platform.processor() or platform.machine()})"}
 
+    splitting = None
+    if a.workload in ("cloud", "deep") and a.schedule == 0 and a.split_study:
+        splitting = split_study(rt, gen, w, kw32)
+
     res = {
         "metric": "cell-crossings/s (FP32-local form; FP64 form in fp64)",
         "value": value,
@@ -285,6 +392,7 @@ def main():
         "fp64": fp64,
         "accuracy": acc if fp64 is not None else None,
         "cpu_baseline": cpu,
+        "splitting": splitting,
     }
     print(json.dumps(res))
     ctx.close()

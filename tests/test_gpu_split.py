@@ -186,3 +186,26 @@ def test_split_rejected_outside_region_schedule(torch):
     r = ctx.trace_packets(src, seed=seed, precision=rt.FP32_LOCAL, split_n=2)
     assert r["stats"]["splits"] > 0
     ctx.close()
+
+
+def test_split_reduces_noise_in_refined_block(torch):
+    """The oracle's noise pin on the GPU: strongly scattering block refined three levels deep in
+    an isotropic field, same number of emitted packages; splitting by 4 lowers the relative RMS
+    difference (Eq. 7 form) of the deepest cells between 6 independent runs and their mean."""
+    tree = gen.refined_block(3)
+    dust = gen.Dust(np.array([1.0]), np.array([1.0]), np.array([0.9]), np.array([0.3]))
+    src = [gen.Source(gen.SRC_BACKGROUND, 0, power=np.array([1.0]), packets=3000)]
+    o = oracle.Model(tree, dust)
+    deep = (o.level_of_nodes() == 3) & o.leaf_mask
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+
+    def noise(n):
+        es = np.array([ctx.trace_packets(src, seed=3 + 7 * k, precision=rt.FP32_LOCAL, split_n=n)
+                       ["e_abs_node"].cpu().numpy()[deep] for k in range(6)])
+        ref = es.mean(axis=0)
+        return float(np.sqrt(((es - ref) ** 2).mean() / (ref ** 2).mean()))
+    n1, n4 = noise(1), noise(4)
+    ctx.close()
+    assert n4 < 0.85 * n1, (n1, n4)
