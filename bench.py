@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # device-to-device copy (fetch x2.0, write x1.0), per leaf crossing.  Valid only for the kernel
 # sources the counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "360903e475716071e6a7d0317807615d6fee07e6f7de3c0a759a6300d581ab9b",
-                "fetch_bytes_per_crossing": 10.212, "write_bytes_per_crossing": 4.703}
+                "sha256": "0c6455f22da55ae76b341650c21468dd2c02bf72188d56ce9133dac7eaf58e2d",
+                "fetch_bytes_per_crossing": 10.238, "write_bytes_per_crossing": 4.440}
 
 
 WORKLOADS = {

@@ -208,8 +208,9 @@ __device__ __forceinline__ void land(WF word_of, int ax, int sg, int L, int32_t 
 
 // One work item: follow every queued packet of the item through its region.  FITS: the whole
 // region is in LDS (pure LDS lookups and deposits); otherwise nodes past the LDS capacity are
-// read and deposited in global memory.
-template <bool FITS>
+// read and deposited in global memory.  SPLIT: package splitting is on (split_n > 1); the
+// unsplit instance carries none of its state or code.
+template <bool FITS, bool SPLIT>
 __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it, const RegionDev& R,
                                          const ModelDev& md, const Dims D, int nloc, int nup,
                                          int32_t* s_word, float* s_acc, int32_t* s_up, uint32_t* s_next,
@@ -246,7 +247,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   double O0 = 0.0, O1 = 0.0, O2 = 0.0;
   uint32_t pid = 0, ev = 0, ncross = 0, stream = 0;
   uint32_t br = 0;             // branch identifier (0: the package as emitted)
-  const bool splitting = p.split_n > 1;
+  constexpr bool splitting = SPLIT;
   float ks = 0.f, ka = 0.f, g = 0.f;  // scattering / absorption opacity per root-cell length per unit density
   int esc_slot = 0;
   int32_t xax = 0, xsg = 0;
@@ -295,7 +296,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           ev = rec.ev;
           ncross = rec.ncross;
           birth = rec.birth;
-          br = (rec.flag & 2) ? (uint32_t)rec.birth : 0u;
+          br = (SPLIT && (rec.flag & 2)) ? (uint32_t)rec.birth : 0u;
           const bool crossing = rec.flag & 1;
           const int L = rec.lev;
           int32_t J0 = rec.I[0], J1 = rec.I[1], J2 = rec.I[2];
@@ -662,7 +663,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   }
 }
 
-template <int BS>
+template <int BS, bool SPLIT>
 __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int cap = b.cap;
@@ -702,10 +703,10 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     if (tid == 0) s_next = 0;
     __syncthreads();
     if (R.n <= cap)
-      run_item<true>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
+      run_item<true, SPLIT>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
                      c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip);
     else
-      run_item<false>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
+      run_item<false, SPLIT>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
                       c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip);
     __syncthreads();
     if (b.accb64) {
@@ -736,7 +737,7 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     if (sc_kill) atomicAdd(&p.stats->kills, sc_kill);
     if (sc_trunc) atomicAdd(&p.stats->truncated, sc_trunc);
   }
-  if (p.split_n > 1) {
+  if (SPLIT) {
     const unsigned long long sc_split = wave_sum_u64(c_split);
     const unsigned long long sc_skill = wave_sum_u64(c_skill);
     const unsigned long long sc_sskip = wave_sum_u64(c_sskip);
@@ -803,25 +804,41 @@ hipError_t launch_blk_emit(const BlkParams& b, const SweepState* st, uint64_t ba
   return hipGetLastError();
 }
 
-hipError_t attr_blk_pass(int block, int lds_bytes) {
+template <bool SPLIT>
+static const void* pass_fn(int block) {
   switch (block) {
-    case 256: return hipFuncSetAttribute((const void*)blk_pass_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    case 512: return hipFuncSetAttribute((const void*)blk_pass_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    case 768: return hipFuncSetAttribute((const void*)blk_pass_kernel<768>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    case 1024: return hipFuncSetAttribute((const void*)blk_pass_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    default: return hipErrorInvalidValue;
+    case 256: return (const void*)blk_pass_kernel<256, SPLIT>;
+    case 512: return (const void*)blk_pass_kernel<512, SPLIT>;
+    case 768: return (const void*)blk_pass_kernel<768, SPLIT>;
+    case 1024: return (const void*)blk_pass_kernel<1024, SPLIT>;
+    default: return nullptr;
   }
 }
 
-hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s) {
+hipError_t attr_blk_pass(int block, int lds_bytes) {
+  for (const void* f : {pass_fn<false>(block), pass_fn<true>(block)}) {
+    if (!f) return hipErrorInvalidValue;
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <bool SPLIT>
+static hipError_t launch_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s) {
   switch (block) {
-    case 256: hipLaunchKernelGGL(blk_pass_kernel<256>, dim3(grid), dim3(256), lds_bytes, s, b); break;
-    case 512: hipLaunchKernelGGL(blk_pass_kernel<512>, dim3(grid), dim3(512), lds_bytes, s, b); break;
-    case 768: hipLaunchKernelGGL(blk_pass_kernel<768>, dim3(grid), dim3(768), lds_bytes, s, b); break;
-    case 1024: hipLaunchKernelGGL(blk_pass_kernel<1024>, dim3(grid), dim3(1024), lds_bytes, s, b); break;
+    case 256: hipLaunchKernelGGL((blk_pass_kernel<256, SPLIT>), dim3(grid), dim3(256), lds_bytes, s, b); break;
+    case 512: hipLaunchKernelGGL((blk_pass_kernel<512, SPLIT>), dim3(grid), dim3(512), lds_bytes, s, b); break;
+    case 768: hipLaunchKernelGGL((blk_pass_kernel<768, SPLIT>), dim3(grid), dim3(768), lds_bytes, s, b); break;
+    case 1024: hipLaunchKernelGGL((blk_pass_kernel<1024, SPLIT>), dim3(grid), dim3(1024), lds_bytes, s, b); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s) {
+  return b.t.split_n > 1 ? launch_pass<true>(b, grid, block, lds_bytes, s)
+                         : launch_pass<false>(b, grid, block, lds_bytes, s);
 }
 
 hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, int n_regions,
