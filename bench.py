@@ -174,6 +174,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-packets", type=int, default=1 << 18,
                     help="oracle sample: packets per wavelength")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="processes for the all-core oracle figure (1: skip it)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--refill", type=float, default=0.0)
@@ -190,8 +192,66 @@ def parse():
     ap.add_argument("--split-study", action="store_true",
                     help="add the package-splitting noise study (cloud and deep workloads)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="first copy 4 GiB device-to-device (reference for traffic counters)")
+                    help="no effect: the 4 GiB device-to-device copy always runs first")
     return ap.parse_args()
+
+
+_ORA = {}
+
+
+def _oracle_init(tree, dust):
+    import oracle
+    _ORA["model"] = oracle.Model(tree, dust)
+
+
+def _oracle_chunk(args):
+    src, seed, rr_t, rr_p, b, e = args
+    _, _, st, _ = _ORA["model"].trace(src, seed=seed, rr_threshold=rr_t, rr_prob=rr_p,
+                                      pid_begin=b, pid_end=e)
+    return st["crossings"]
+
+
+def cpu_baselines(a, gen, w, tree, dust, nl):
+    """The oracle on the host cores: one thread on a packet prefix (the reported baseline), and
+    the same oracle in one process per core on a prefix 16 times longer.  Runs before anything
+    touches the GPU (the worker processes are started fresh, not forked)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    import oracle
+    src0 = [gen.Source(w.sources[0].kind, 0, pos=w.sources[0].pos, power=w.sources[0].power,
+                       packets=w.sources[0].packets)]
+    what = {"cloud": "", "disc": " of the star", "clouds": " of the first model",
+            "deep": ""}[a.workload]
+    cpu_name = platform.processor() or platform.machine()
+    ora = oracle.Model(tree, dust)
+    t2 = time.perf_counter()
+    _, _, sto, _ = ora.trace(src0, seed=w.seed, rr_threshold=w.rr_threshold,
+                             rr_prob=w.rr_prob, pid_end=a.cpu_packets)
+    dc = time.perf_counter() - t2
+    del ora
+    cpu = {"value": sto["crossings"] / dc, "unit": "cell-crossings/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"first {a.cpu_packets} packets{what} at each of the {nl} wavelengths "
+                     f"({sto['crossings']} crossings, {dc:.1f} s, single thread, {cpu_name})"}
+    workers = min(a.cpu_workers, os.cpu_count() or 1)
+    if workers <= 1:
+        return cpu, None
+    n_all = min(16 * a.cpu_packets, int(w.sources[0].packets))
+    edges = [n_all * k // (4 * workers) for k in range(4 * workers + 1)]
+    tasks = [(src0, w.seed, w.rr_threshold, w.rr_prob, edges[k], edges[k + 1])
+             for k in range(4 * workers) if edges[k + 1] > edges[k]]
+    # a pool whose workers die raises instead of waiting
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn"), initializer=_oracle_init,
+                             initargs=(tree, dust)) as pool:
+        list(pool.map(_oracle_chunk, [(src0, w.seed, w.rr_threshold, w.rr_prob, 0, 1)] * workers))
+        t3 = time.perf_counter()
+        cr = sum(pool.map(_oracle_chunk, tasks))
+        d3 = time.perf_counter() - t3
+    cpu_all = {"value": cr / d3, "unit": "cell-crossings/s", "cores": workers, "kind": "oracle",
+               "sample": f"first {n_all} packets{what} at each of the {nl} wavelengths, "
+                         f"{len(tasks)} packet ranges over {workers} processes ({cr} crossings, "
+                         f"{d3:.1f} s, {cpu_name})"}
+    return cpu, cpu_all
 
 
 def main():
@@ -200,17 +260,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
-    import torch
     import gen
-    import paper_1206_3710_amd as rt
 
-    if a.copy_calibration:
-        # 4 GiB device-to-device copy: reads and writes exceed every cache level
-        src_t = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
-        dst_t = torch.empty_like(src_t)
-        dst_t.copy_(src_t)
-        torch.cuda.synchronize()
-        del src_t, dst_t
     if a.workload == "cloud":
         w = gen.c2(packets=a.packets or 10_000_000)
     elif a.workload == "disc":
@@ -220,6 +271,27 @@ def main():
     else:
         w = gen.c4(packets=a.packets or 1_000_000)
     tree, dust = w.trees[0], w.dusts[0]
+    cpu, cpu_all = None, None
+    if not a.no_cpu_baseline:
+        cpu, cpu_all = cpu_baselines(a, gen, w, tree, dust, dust.n_lambda)
+
+    import torch
+    import paper_1206_3710_amd as rt
+    # 4 GiB device-to-device copy: reads and writes exceed every cache level; its rate is the
+    # measured bandwidth the roofline is also reported against, and its counters calibrate the
+    # traffic figures
+    src_t = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+    dst_t = torch.empty_like(src_t)
+    dst_t.copy_(src_t)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    dst_t.copy_(src_t)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * 4.0 * (1 << 30) / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del src_t, dst_t
+    torch.cuda.empty_cache()
     ctx = rt.Context(0)
     for t_, d_ in zip(w.trees, w.dusts):
         m = ctx.build_tree(t_)
@@ -338,24 +410,6 @@ def main():
                 "trace_crossings_per_s": (c64 / a.fp64_steps) / k64a,
                 "hbm_frac_algorithmic": (c64 / a.fp64_steps) * BYTES_PER_CROSSING_FP64 / k64a / 1e9 / HBM_PEAK_GBS}
 
-    cpu = None
-    if not a.no_cpu_baseline:
-        import oracle
-        ora = oracle.Model(tree, dust)
-        src0 = [gen.Source(w.sources[0].kind, 0, pos=w.sources[0].pos, power=w.sources[0].power,
-                           packets=w.sources[0].packets)]
-        what = {"cloud": "", "disc": " of the star", "clouds": " of the first model",
-                "deep": ""}[a.workload]
-        t2 = time.perf_counter()
-        _, _, sto, _ = ora.trace(src0, seed=w.seed, rr_threshold=w.rr_threshold,
-                                 rr_prob=w.rr_prob, pid_end=a.cpu_packets)
-        dc = time.perf_counter() - t2
-        cpu = {"value": sto["crossings"] / dc, "unit": "cell-crossings/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"first {a.cpu_packets} packets{what} at each of the {nl} wavelengths "
-                         f"({sto['crossings']} crossings, {dc:.1f} s, single thread, "
-                         f"{platform.processor() or platform.machine()})"}
-
     splitting = None
     if a.workload in ("cloud", "deep") and a.schedule == 0 and a.split_study:
         splitting = split_study(rt, gen, w, kw32)
@@ -384,6 +438,8 @@ def main():
         "post_trace_ms": 1e3 * sum(post) / len(post),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "copy_gbs": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
                      "kernel": "blk_pass_kernel<%d>" % (kw32["block_size"] or 768) if a.schedule == 0
                                else "trace_fp32_kernel<%d>" % (kw32["block_size"] or 256),
                      "launches_per_step": launches, "avg_launch_ms": 1e3 * main_launch_s,
@@ -392,6 +448,7 @@ def main():
         "fp64": fp64,
         "accuracy": acc if fp64 is not None else None,
         "cpu_baseline": cpu,
+        "cpu_all_cores": cpu_all,
         "splitting": splitting,
     }
     print(json.dumps(res))
