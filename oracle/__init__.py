@@ -74,7 +74,11 @@ def lib():
         L.om_trace.restype = C.c_int
         L.om_trace.argtypes = [P, C.c_int32, C.c_int32, P, P, P, P, P, P, C.c_uint64, C.c_uint32,
                                C.c_double, C.c_double, C.c_int64, C.c_int32, C.c_int64, C.c_int64,
-                               C.c_int32, P, P, P, C.c_int64, P, C.c_int32]
+                               C.c_int32, P, P, P, C.c_int64, P, C.c_int32, P]
+        L.om_hg_phase.restype = C.c_double
+        L.om_hg_phase.argtypes = [C.c_double, C.c_double]
+        L.om_peel_column.restype = C.c_int
+        L.om_peel_column.argtypes = [P, P, C.c_int32, C.c_int64, P, P]
         L.om_branch_id.restype = C.c_uint32
         L.om_branch_id.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
         L.om_solve_temperature.argtypes = [P, P, C.c_double, C.c_double, P]
@@ -99,6 +103,15 @@ def _p(a):
 
 class OracleError(RuntimeError):
     pass
+
+
+class PeelOpts(C.Structure):
+    _fields_ = [("n_dir", C.c_int32), ("n_obs", C.c_void_p), ("npix", C.c_int32),
+                ("width", C.c_double), ("tiles", C.c_int32), ("image", C.c_void_p)]
+
+
+def hg_phase(g, mu):
+    return lib().om_hg_phase(float(g), float(mu))
 
 
 class Model:
@@ -179,8 +192,10 @@ class Model:
 
     def trace(self, sources, seed, iteration=0, model_index=0, rr_threshold=0.0, rr_prob=0.0,
               max_events=0, per_lambda=False, pid_begin=0, pid_end=-1, lam_sel=-1,
-              t_node=None, rec_stride=0, deposits=True, split_n=1):
-        """Follow packets of ``sources`` (gen.Source list) -> (e_abs, e_esc, stats, records)."""
+              t_node=None, rec_stride=0, deposits=True, split_n=1, peel=None):
+        """Follow packets of ``sources`` (gen.Source list) -> (e_abs, e_esc, stats, records).
+        ``peel``: dict(n_obs=[[x, y, z], ...], npix=, width=0.0, tiles=0) turns on the peel-off
+        images, returned in stats["peel_image"] as [n_dir, n_lambda, npix, npix]."""
         L = lib()
         ns = len(sources)
         nl = self.n_lambda
@@ -201,17 +216,39 @@ class Model:
         if rec_stride > 0:
             nrec = (pid_end - pid_begin + rec_stride - 1) // rec_stride
             rec = np.zeros(ns * nl * nrec, dtype=RECORD_DTYPE)
+        po, img = None, None
+        if peel is not None:
+            nobs = np.ascontiguousarray(peel["n_obs"], dtype=np.float64).reshape(-1, 3)
+            npix = int(peel["npix"])
+            img = np.zeros((len(nobs), nl, npix, npix))
+            po = PeelOpts(len(nobs), _p(nobs).value, npix, float(peel.get("width", 0.0)),
+                          int(peel.get("tiles", 0)), _p(img).value)
         rc = L.om_trace(self.h, model_index, ns, _p(kind), _p(pos), _p(dirs), _p(power),
                         _p(packets), None if tn is None else _p(tn), C.c_uint64(seed),
                         iteration, rr_threshold, rr_prob, max_events, int(per_lambda),
                         pid_begin, pid_end, lam_sel, None if e_abs is None else _p(e_abs),
                         _p(e_esc), C.byref(st),
-                        rec_stride, None if rec is None else _p(rec), split_n)
+                        rec_stride, None if rec is None else _p(rec), split_n,
+                        None if po is None else C.byref(po))
         if rc != 0:
             raise OracleError(L.om_error().decode())
+        if img is not None:
+            out = st.as_dict()
+            out["peel_image"] = img
+            if per_lambda and e_abs is not None:
+                e_abs = e_abs.reshape(nl, self.n_nodes)
+            return e_abs, e_esc, out, rec
         if per_lambda and e_abs is not None:
             e_abs = e_abs.reshape(nl, self.n_nodes)
         return e_abs, e_esc, st.as_dict(), rec
+
+    def peel_column(self, n_obs, xyz, tiles=0):
+        """Column (density x length, root-cell units) from each point toward n_obs."""
+        nv = np.ascontiguousarray(n_obs, dtype=np.float64)
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        col = np.zeros(len(x))
+        lib().om_peel_column(self.h, _p(nv), int(tiles), len(x), _p(x), _p(col))
+        return col
 
     def solve_temperature(self, a_node, t_min=2.0, t_max=3000.0):
         a = np.ascontiguousarray(a_node, dtype=np.float64)

@@ -363,6 +363,20 @@ typedef struct {
   uint32_t br;              /* branch of the package (0: the emitted package and its main line) */
 } packet;
 
+/* Peel-off state (Sect. 2.4): observer frames, image geometry, extinction tables. */
+#define OM_MAXDIR 16
+typedef struct {
+  int32_t n_dir;
+  double n[OM_MAXDIR][3], e1[OM_MAXDIR][3], e2[OM_MAXDIR][3];
+  int32_t npix;
+  double W, C[3], pix_cm2;  /* image width (root-cell units), centre, pixel area (cm^2) */
+  int32_t tiles;            /* tiles per face side; 0: columns marched to the border */
+  int64_t* root_tab;        /* [n_root] ordinal of a refined root cell, -1 for a root leaf */
+  int64_t n_tab;
+  double* tab;              /* [n_dir][n_tab][6][tiles^2] column from each tile centre */
+  double* image;            /* [n_dir][n_lambda][npix][npix] */
+} peel_ctx;
+
 typedef struct {
   const om_model* m;
   uint32_t key0, key1;
@@ -377,6 +391,7 @@ typedef struct {
   int32_t split_n;          /* package splitting factor at subgrid entry (1: none) */
   packet* stack;            /* split packages waiting to be followed */
   int64_t n_stack, cap_stack;
+  const peel_ctx* peel;     /* NULL: no peel-off */
 } tctx;
 
 /* Branch identifier of child c of branch b split at the package's crossing number n: the
@@ -437,6 +452,183 @@ static void rotate(double d[3], double mu, double phi) {
   d[0] = nx / nn; d[1] = ny / nn; d[2] = nz / nn;
 }
 
+/* ------------------------------------------------------------------------------------ */
+/* peel-off (Sect. 2.4)                                                                  */
+/* ------------------------------------------------------------------------------------ */
+
+/* Image frame of an observer direction, as for the maps: e1 = z x n / |z x n| (x when n is
+   along z), e2 = n x e1. */
+static void view_frame(const double n_in[3], double n[3], double e1[3], double e2[3]) {
+  double nn = sqrt(n_in[0] * n_in[0] + n_in[1] * n_in[1] + n_in[2] * n_in[2]);
+  for (int a = 0; a < 3; ++a) n[a] = n_in[a] / nn;
+  if (n[0] == 0.0 && n[1] == 0.0) {
+    e1[0] = 1.0; e1[1] = 0.0; e1[2] = 0.0;
+  } else {
+    double en = sqrt(n[1] * n[1] + n[0] * n[0]);
+    e1[0] = -n[1] / en; e1[1] = n[0] / en; e1[2] = 0.0;
+  }
+  e2[0] = n[1] * e1[2] - n[2] * e1[1];
+  e2[1] = n[2] * e1[0] - n[0] * e1[2];
+  e2[2] = n[0] * e1[1] - n[1] * e1[0];
+}
+
+/* One step of a column march along n from P inside leaf (node, lev, I): adds density x
+   length (root-cell units) up to the leaf's exit face and moves P onto it.  Returns the exit
+   axis; *sg its direction. */
+static int march_step(const om_model* m, const double n[3], double P[3], int64_t node, int lev,
+                      const int64_t I[3], double* col, int* sg) {
+  double h = ldexp(1.0, -lev);
+  double texit = INFINITY, face_ax = 0.0;
+  int ax = -1;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] != 0.0) {
+      double face = n[a] > 0.0 ? (double)(I[a] + 1) * h : (double)I[a] * h;
+      double t = (face - P[a]) / n[a];
+      if (t < texit) { texit = t; ax = a; face_ax = face; }
+    }
+  }
+  *col += m->rho[node] * texit;
+  for (int b = 0; b < 3; ++b) P[b] = fma(texit, n[b], P[b]);
+  for (int b = 0; b < 3; ++b) {
+    double lo = (double)I[b] * h, hi = (double)(I[b] + 1) * h;
+    if (P[b] < lo) P[b] = lo;
+    if (P[b] > hi) P[b] = hi;
+  }
+  P[ax] = face_ax;
+  *sg = n[ax] > 0.0 ? 1 : -1;
+  return ax;
+}
+
+/* Column from P (inside leaf node) along n to the border of the model. */
+static double column_exact(const om_model* m, const double n[3], const double P0[3], int64_t node,
+                           int lev, const int64_t I0[3]) {
+  double P[3] = {P0[0], P0[1], P0[2]}, col = 0.0;
+  int64_t I[3] = {I0[0], I0[1], I0[2]};
+  for (;;) {
+    int sg;
+    int ax = march_step(m, n, P, node, lev, I, &col, &sg);
+    if (cross_face(m, ax, sg, P, &node, &lev, I)) return col;
+  }
+}
+
+/* Tile of a face point: lateral axes in increasing order, [0, 1) of the root cell split into
+   `tiles` parts each. */
+static int64_t face_tile(const double P[3], const int64_t R[3], int a, int tiles) {
+  int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+  int64_t tx = (int64_t)floor((P[b1] - (double)R[b1]) * tiles);
+  int64_t ty = (int64_t)floor((P[b2] - (double)R[b2]) * tiles);
+  if (tx < 0) tx = 0;
+  if (tx > tiles - 1) tx = tiles - 1;
+  if (ty < 0) ty = 0;
+  if (ty > tiles - 1) ty = tiles - 1;
+  return ty * tiles + tx;
+}
+
+/* Column with the extinction tables: from P inside a refined root cell, march to that root
+   cell's outer boundary and add the table value of the tile it leaves through; from P in a
+   root leaf, march through root leaves until the border, or until the ray enters a refined
+   root cell, and add the table value of the tile it enters through. */
+static double column_tabled(const om_model* m, const peel_ctx* pc, int q, const double n[3],
+                            const double P0[3], int64_t node, int lev, const int64_t I0[3]) {
+  double P[3] = {P0[0], P0[1], P0[2]}, col = 0.0;
+  int64_t I[3] = {I0[0], I0[1], I0[2]};
+  const int T = pc->tiles, T2 = pc->tiles * pc->tiles;
+  int64_t R[3] = {I[0] >> lev, I[1] >> lev, I[2] >> lev};
+  int64_t t0 = pc->root_tab[root_index(m, R)];
+  for (;;) {
+    int sg;
+    int ax = march_step(m, n, P, node, lev, I, &col, &sg);
+    int64_t J = I[ax] + sg;
+    if (t0 >= 0) {
+      if ((J >> lev) != R[ax]) {  /* leaving the refined root cell R */
+        int64_t k = ((int64_t)q * pc->n_tab + t0) * 6 + 2 * ax + (sg > 0 ? 1 : 0);
+        return col + pc->tab[k * T2 + face_tile(P, R, ax, T)];
+      }
+      cross_face(m, ax, sg, P, &node, &lev, I);
+    } else {
+      if (J < 0 || J >= (int64_t)m->n[ax]) return col;  /* leaves the model */
+      int64_t Rn[3] = {I[0], I[1], I[2]};
+      Rn[ax] = J;
+      int64_t tn = pc->root_tab[root_index(m, Rn)];
+      if (tn >= 0) {  /* enters a refined root cell through its face on the -sg side */
+        int64_t k = ((int64_t)q * pc->n_tab + tn) * 6 + 2 * ax + (sg > 0 ? 0 : 1);
+        return col + pc->tab[k * T2 + face_tile(P, Rn, ax, T)];
+      }
+      I[ax] = J;
+      node = root_index(m, I);
+    }
+  }
+}
+
+/* Extinction tables: for every direction, refined root cell, face and tile, the column from
+   the tile centre along n to the border (0 where n is parallel to the face, or leaves the
+   model through it). */
+static void build_tables(const om_model* m, peel_ctx* pc) {
+  int64_t nroot = (int64_t)m->n[0] * m->n[1] * m->n[2];
+  pc->root_tab = (int64_t*)malloc(sizeof(int64_t) * (size_t)nroot);
+  pc->n_tab = 0;
+  for (int64_t r = 0; r < nroot; ++r) pc->root_tab[r] = m->child[r] >= 0 ? pc->n_tab++ : -1;
+  const int T = pc->tiles, T2 = T * T;
+  pc->tab = (double*)calloc((size_t)(pc->n_dir * pc->n_tab * 6 * T2 + 1), sizeof(double));
+  for (int q = 0; q < pc->n_dir; ++q) {
+    const double* n = pc->n[q];
+    for (int64_t r = 0; r < nroot; ++r) {
+      int64_t t = pc->root_tab[r];
+      if (t < 0) continue;
+      int64_t R[3] = {r % m->n[0], (r / m->n[0]) % m->n[1], r / ((int64_t)m->n[0] * m->n[1])};
+      for (int f = 0; f < 6; ++f) {
+        int a = f / 2, hi = f % 2;
+        if (n[a] == 0.0) continue;
+        int sg = n[a] > 0.0 ? 1 : -1;
+        int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+        for (int ty = 0; ty < T; ++ty)
+          for (int tx = 0; tx < T; ++tx) {
+            double Q[3];
+            Q[a] = (double)(R[a] + hi);
+            Q[b1] = (double)R[b1] + ((double)tx + 0.5) / (double)T;
+            Q[b2] = (double)R[b2] + ((double)ty + 0.5) / (double)T;
+            if ((sg > 0 && Q[a] >= (double)m->n[a]) || (sg < 0 && Q[a] <= 0.0)) continue;
+            int lev;
+            int64_t I[3];
+            int64_t node = locate_face(m, Q, a, sg, &lev, I);
+            pc->tab[(((int64_t)q * pc->n_tab + t) * 6 + f) * T2 + ty * T + tx] =
+                column_exact(m, n, Q, node, lev, I);
+          }
+      }
+    }
+  }
+}
+
+/* Henyey-Greenstein phase function per steradian. */
+static double hg_phase(double g, double mu) {
+  double den = 1.0 + g * g - 2.0 * g * mu;
+  return (1.0 - g * g) / (4.0 * OM_PI * den * sqrt(den));
+}
+
+/* At a scattering event: the part of the packet scattered toward each observer and escaping,
+   as surface brightness in the pixel the event projects onto. */
+static void peel_event(const tctx* c, const packet* p, double g) {
+  const peel_ctx* pc = c->peel;
+  const om_model* m = c->m;
+  for (int q = 0; q < pc->n_dir; ++q) {
+    const double* n = pc->n[q];
+    double mu = p->d[0] * n[0] + p->d[1] * n[1] + p->d[2] * n[2];
+    double col = pc->tiles > 0 ? column_tabled(m, pc, q, n, p->P, p->node, p->lev, p->I)
+                               : column_exact(m, n, p->P, p->node, p->lev, p->I);
+    double tau = (m->kext[c->lam] * m->cell_cm) * col;
+    double val = p->w * hg_phase(g, mu) * exp(-tau) / (m->dnu[c->lam] * pc->pix_cm2);
+    double u = 0.0, v = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      u += (p->P[a] - pc->C[a]) * pc->e1[q][a];
+      v += (p->P[a] - pc->C[a]) * pc->e2[q][a];
+    }
+    int64_t i = (int64_t)floor((u / pc->W + 0.5) * pc->npix);
+    int64_t j = (int64_t)floor((v / pc->W + 0.5) * pc->npix);
+    if (i < 0 || j < 0 || i >= pc->npix || j >= pc->npix) continue;
+    pc->image[(((int64_t)q * m->nl + c->lam) * pc->npix + j) * pc->npix + i] += val;
+  }
+}
+
 /* Result codes of a propagation */
 enum { PK_ESCAPED = 0, PK_KILLED = 1, PK_TRUNC = 2, PK_SPLITKILL = 3 };
 
@@ -487,6 +679,7 @@ static int propagate(tctx* c, packet* p) {
         return PK_TRUNC;
       }
       c->st->scatterings += 1;
+      if (c->peel) peel_event(c, p, g);
       uint32_t ctr[4] = {c->pid, c->stream, p->k, p->br << 2}, x[4];
       philox10(c->key0, c->key1, ctr, x);
       if (c->rr_p > 0.0 && p->w < c->rr_thr * p->w0) {
@@ -615,9 +808,14 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
              const double* t_node, uint64_t seed, uint32_t iteration, double rr_threshold,
              double rr_prob, int64_t max_events, int32_t per_lambda, int64_t pid_begin,
              int64_t pid_end, int32_t lam_sel, double* e_abs, double* e_esc, om_stats* stats,
-             int64_t rec_stride, om_record* rec, int32_t split_n) {
+             int64_t rec_stride, om_record* rec, int32_t split_n, const om_peel_opts* peel) {
   if (m->nl < 1) { seterr("dust not set"); return -1; }
   if (split_n < 1 || split_n > 64) { seterr("split factor must be in [1, 64]"); return -1; }
+  if (peel && (peel->n_dir < 1 || peel->n_dir > OM_MAXDIR || peel->npix < 1 || peel->tiles < 0 ||
+               !peel->n_obs || !peel->image)) {
+    seterr("bad peel-off arguments");
+    return -1;
+  }
   if (n_src < 1 || n_src > 255) { seterr("bad source count"); return -1; }
   for (int s = 0; s < n_src; ++s) {
     if (kind[s] < 0 || kind[s] > 3) { seterr("bad source kind"); return -1; }
@@ -654,6 +852,27 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
   c.stack = NULL;
   c.n_stack = 0;
   c.cap_stack = 0;
+  c.peel = NULL;
+  peel_ctx pc;
+  memset(&pc, 0, sizeof pc);
+  if (peel) {
+    pc.n_dir = peel->n_dir;
+    for (int q = 0; q < pc.n_dir; ++q) view_frame(peel->n_obs + 3 * q, pc.n[q], pc.e1[q], pc.e2[q]);
+    pc.npix = peel->npix;
+    pc.W = peel->width;
+    if (!(pc.W > 0.0)) {
+      pc.W = m->n[0];
+      if (m->n[1] > pc.W) pc.W = m->n[1];
+      if (m->n[2] > pc.W) pc.W = m->n[2];
+    }
+    for (int a = 0; a < 3; ++a) pc.C[a] = 0.5 * m->n[a];
+    double side = pc.W / (double)pc.npix * m->cell_cm;
+    pc.pix_cm2 = side * side;
+    pc.tiles = peel->tiles;
+    pc.image = peel->image;
+    if (pc.tiles > 0) build_tables(m, &pc);
+    c.peel = &pc;
+  }
   for (int s = 0; s < n_src; ++s) {
     const int64_t N = packets[s];
     int64_t jb = pid_begin < 0 ? 0 : pid_begin;
@@ -779,6 +998,8 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
   stats->e_abs = ea;
   stats->e_esc = ee;
   free(c.stack);
+  free(pc.root_tab);
+  free(pc.tab);
   return 0;
 }
 
@@ -915,6 +1136,29 @@ int om_render(const om_model* m, const double n_obs[3], int32_t npix, double wid
 /* ------------------------------------------------------------------------------------ */
 
 double om_hg_mu(double g, double u) { return hg_mu(g, u); }
+
+double om_hg_phase(double g, double mu) { return hg_phase(g, mu); }
+
+int om_peel_column(const om_model* m, const double n_obs[3], int32_t tiles, int64_t npts,
+                   const double* xyz, double* col) {
+  peel_ctx pc;
+  memset(&pc, 0, sizeof pc);
+  pc.n_dir = 1;
+  view_frame(n_obs, pc.n[0], pc.e1[0], pc.e2[0]);
+  pc.tiles = tiles;
+  if (tiles > 0) build_tables(m, &pc);
+  for (int64_t i = 0; i < npts; ++i) {
+    int lev;
+    int64_t I[3];
+    int64_t node = locate_walk(m, xyz + 3 * i, &lev, I);
+    if (node < 0) { col[i] = NAN; continue; }
+    col[i] = tiles > 0 ? column_tabled(m, &pc, 0, pc.n[0], xyz + 3 * i, node, lev, I)
+                       : column_exact(m, pc.n[0], xyz + 3 * i, node, lev, I);
+  }
+  free(pc.root_tab);
+  free(pc.tab);
+  return 0;
+}
 
 void om_rotate(double* d, double mu, double phi) { rotate(d, mu, phi); }
 

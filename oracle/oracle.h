@@ -87,13 +87,31 @@ typedef struct {
  * own free path); a package whose crossing lands in a shallower leaf survives with probability
  * 1/split_n, its weight multiplied by split_n.  A record follows the emitted package's main
  * line (the branch that keeps its identifier). */
+/* Peel-off (Sect. 2.4): at every scattering event (before the event roulette) the part of
+ * the packet scattered toward each observer direction and escaping, w Phi_HG(d.n)
+ * exp(-tau(P -> border along n)), is added as surface brightness (per Hz, per pixel area in
+ * cm^2, per steradian) to the pixel the event position projects onto (the map geometry of
+ * om_render).  tiles > 0: tau from extinction tables on the faces of every refined root cell
+ * (tiles x tiles per face, the column from each tile centre): a ray from inside a refined root
+ * cell is marched to that cell's boundary, a ray from a root leaf through root leaves until it
+ * enters a refined root cell or leaves the model, and the table value of the tile it crosses is
+ * added.  tiles = 0: the column is marched to the border. */
+typedef struct {
+  int32_t n_dir;          /* 1..16 */
+  const double* n_obs;    /* [n_dir][3], any length > 0 */
+  int32_t npix;
+  double width;           /* root-cell units; <= 0: largest root extent */
+  int32_t tiles;
+  double* image;          /* [n_dir][n_lambda][npix][npix], added to */
+} om_peel_opts;
+
 int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kind,
              const double* pos /*3n*/, const double* dir /*3n*/, const double* power,
              const int64_t* packets, const double* t_node, uint64_t seed, uint32_t iteration,
              double rr_threshold, double rr_prob, int64_t max_events, int32_t per_lambda,
              int64_t pid_begin, int64_t pid_end, int32_t lam_sel,
              double* e_abs, double* e_esc, om_stats* stats, int64_t rec_stride, om_record* rec,
-             int32_t split_n);
+             int32_t split_n, const om_peel_opts* peel);
 
 /* Equilibrium temperature per leaf: 4 pi m sum_i kappa_abs_i B_i(T) dnu_i = A. */
 void om_solve_temperature(const om_model* m, const double* a_node, double t_min, double t_max,
@@ -112,6 +130,11 @@ void om_rotate(double* d, double mu, double phi);
 double om_uniform(uint32_t x);
 int64_t om_cdf_pick(const uint64_t* q, int64_t n, uint64_t r);
 uint32_t om_branch_id(uint32_t b, uint32_t n, uint32_t c);
+double om_hg_phase(double g, double mu);
+/* Peel-off column (density x length, root-cell units) from each point toward n_obs, marched
+ * to the border (tiles = 0) or with the extinction tables. */
+int om_peel_column(const om_model* m, const double n_obs[3], int32_t tiles, int64_t npts,
+                   const double* xyz, double* col);
 
 #ifdef __cplusplus
 }
