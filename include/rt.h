@@ -11,7 +11,9 @@
  *                         of one grain component (Sect. 4);
  *   rt_lambda_iterate     the Lambda iteration of Sect. 3.1 Eq. (2) with the constant-source
  *                         field kept (Sect. 3.2);
- *   rt_render_map         surface-brightness maps toward chosen directions (Sect. 4.1).
+ *   rt_render_map         surface-brightness maps toward chosen directions (Sect. 4.1);
+ *   rt_peel_map           images of the scattered light by peel-off, with precomputed
+ *                         extinction tables (Sect. 2.4).
  *
  * Conventions
  *   - Every call validates all of its arguments before it changes any state; on error it
@@ -197,6 +199,8 @@ typedef struct {
   double e_split_gain;      /* weight added to the survivors of that roulette; energy balance:
                                e_emit + e_rr_gain + e_split_gain = e_abs + e_esc + e_killed +
                                e_trunc + e_split_killed */
+  uint64_t peel_events;     /* rt_peel_map: scattering events peeled off */
+  double table_ms;          /* rt_peel_map: device time of the extinction-table build */
 } rt_trace_stats;
 
 /* Follow packets_per_lambda packets of every source at every wavelength of its model.  Packet
@@ -240,6 +244,40 @@ rt_status rt_lambda_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_
 rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32_t npix,
                         double width, int32_t n_sel, const int32_t* lambda_idx,
                         int32_t precision, double* image, uint64_t* crossings);
+
+/* Peel-off images of the scattered light (Sect. 2.4).  The sources (all of one model) are
+ * traced as by rt_trace_packets with the same options (RT_FP64, or RT_FP32_LOCAL with the
+ * region schedule); at every scattering event, before the event roulette, the part of the
+ * packet scattered toward each observer direction n and escaping, w Phi_HG(d.n) exp(-tau),
+ * is added to the pixel the event position projects onto (the map geometry of
+ * rt_render_map), divided by the wavelength's bandwidth and the pixel area: the image is the
+ * scattered surface brightness in erg s^-1 cm^-2 Hz^-1 sr^-1.  tau = kappa_ext times the
+ * column density from the event to the model border along n:
+ *   tiles = 0  marched cell by cell to the border;
+ *   tiles > 0  extinction tables on the six faces of every refined root cell, tiles x tiles
+ *              per face, each entry the column from the tile centre to the border: a ray from
+ *              inside a refined root cell is marched to that cell's boundary, a ray from a root
+ *              leaf through root leaves until it enters a refined root cell or leaves the
+ *              model, and the table entry of the tile it crosses completes the column (the
+ *              paper's accelerated peel-off; an approximation of the order of a tile).
+ * Events are kept per batch (a sweep of the region schedule, a (source, wavelength) job of the
+ * FP64 form) in a device buffer of event_buffer entries (80 B each); a batch with more events
+ * than that fails the call with RT_EDEVICE, naming the count, after the trace (lower
+ * batch_packets or raise event_buffer).  The absorbed energy is not returned. */
+typedef struct {
+  int32_t n_dir;            /* observer directions, 1..16 */
+  int32_t npix;             /* pixels per image side, 1..16384 */
+  const double* n_obs;      /* [n_dir][3] host: direction toward each observer, any length > 0 */
+  double width;             /* image side in root-cell units; <= 0: the largest root extent */
+  int32_t tiles;            /* tiles per face side of the extinction tables, 0..64 */
+  int32_t pad;
+  int64_t event_buffer;     /* events kept per batch; 0 = 2^24 */
+  double* image;            /* [n_dir][n_lambda of the model][npix][npix] host or device,
+                               overwritten */
+} rt_peel_opts;
+
+rt_status rt_peel_map(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_trace_opts* opts,
+                      const rt_peel_opts* peel, rt_trace_stats* stats);
 
 /* Autotuner for the launch parameters of rt_trace_packets (the FP32-local form's block size,
  * blocks per CU, refill threshold, tail rounds, packets per work item and packets emitted

@@ -24,8 +24,8 @@ SCHED_REGIONS, SCHED_GLOBAL = 0, 1
 
 EXPORTS = ["rt_last_error", "rt_create", "rt_destroy", "rt_build_tree", "rt_get_model_info",
            "rt_get_sizes", "rt_locate", "rt_set_dust", "rt_set_temperature", "rt_trace_packets",
-           "rt_solve_temperature", "rt_lambda_iterate", "rt_render_map", "rt_autotune",
-           "rt_philox"]
+           "rt_solve_temperature", "rt_lambda_iterate", "rt_render_map", "rt_peel_map",
+           "rt_autotune", "rt_philox"]
 
 
 class RTError(RuntimeError):
@@ -63,6 +63,12 @@ class TraceOpts(C.Structure):
                 ("split_n", C.c_int32)]
 
 
+class PeelOpts(C.Structure):
+    _fields_ = [("n_dir", C.c_int32), ("npix", C.c_int32), ("n_obs", C.c_void_p),
+                ("width", C.c_double), ("tiles", C.c_int32), ("pad", C.c_int32),
+                ("event_buffer", C.c_int64), ("image", C.c_void_p)]
+
+
 class TraceStats(C.Structure):
     _fields_ = [("crossings", C.c_uint64), ("scatterings", C.c_uint64), ("kills", C.c_uint64),
                 ("truncated", C.c_uint64), ("packets", C.c_uint64), ("e_emit", C.c_double),
@@ -70,7 +76,8 @@ class TraceStats(C.Structure):
                 ("e_rr_gain", C.c_double), ("e_trunc", C.c_double), ("kernel_ms", C.c_double),
                 ("reduce_ms", C.c_double), ("main_ms", C.c_double), ("main_launches", C.c_uint64),
                 ("splits", C.c_uint64), ("split_kills", C.c_uint64), ("split_skips", C.c_uint64),
-                ("e_split_killed", C.c_double), ("e_split_gain", C.c_double)]
+                ("e_split_killed", C.c_double), ("e_split_gain", C.c_double),
+                ("peel_events", C.c_uint64), ("table_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -105,6 +112,7 @@ def lib():
             "rt_solve_temperature": (I32, [P, I32, P, D, D, P]),
             "rt_lambda_iterate": (I32, [P, I32, I32, P, P, I64, I32, D, D, D, P, P, P]),
             "rt_render_map": (I32, [P, I32, P, I32, D, I32, P, I32, P, P]),
+            "rt_peel_map": (I32, [P, I32, P, P, P, P]),
             "rt_autotune": (I32, [P, I32, P, P, D, C.c_char_p, P, P]),
             "rt_philox": (I32, [P, U32, U32, I64, P, P]),
         }
@@ -114,6 +122,22 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def _source_array(sources):
+    """ctypes array of rt_source for gen.Source-like objects, and the power arrays it points to."""
+    n = len(sources)
+    arr = (Source * n)()
+    keep = []
+    for i, s in enumerate(sources):
+        pw = None
+        if s.power is not None:
+            pw = np.ascontiguousarray(s.power, dtype=np.float64)
+            keep.append(pw)
+        arr[i] = Source(int(s.kind), int(s.model), (C.c_double * 3)(*s.pos),
+                        (C.c_double * 3)(*s.dir), None if pw is None else _ptr(pw).value,
+                        int(s.packets))
+    return arr, keep
 
 
 def _ptr(a):
@@ -231,17 +255,8 @@ class Context:
         statistics."""
         torch = _torch()
         n = len(sources)
-        arr = (Source * n)()
-        keep = []
+        arr, keep = _source_array(sources)
         n_rec = 0
-        for i, s in enumerate(sources):
-            pw = None
-            if s.power is not None:
-                pw = np.ascontiguousarray(s.power, dtype=np.float64)
-                keep.append(pw)
-            arr[i] = Source(int(s.kind), int(s.model), (C.c_double * 3)(*s.pos),
-                            (C.c_double * 3)(*s.dir), None if pw is None else _ptr(pw).value,
-                            int(s.packets))
         tn, tl, tln = self.sizes()
         e_node = torch.zeros(tn, dtype=torch.float64, device=self.tdev)
         e_lam = torch.zeros(max(tln, 1), dtype=torch.float64, device=self.tdev) if per_lambda else None
@@ -266,6 +281,28 @@ class Context:
         if rec is not None:
             out["records"] = np.frombuffer(rec.cpu().numpy().tobytes(), dtype=RECORD_DTYPE)[:n_rec]
         return out
+
+    def peel_map(self, sources: Sequence, seed: int, n_obs, npix: int, width: float = 0.0,
+                 tiles: int = 0, event_buffer: int = 0, iteration: int = 0, precision: int = FP64,
+                 rr_threshold: float = 0.0, rr_prob: float = 0.0, max_events: int = 0,
+                 block_size: int = 0, blocks_per_cu: int = 0, refill_threshold: float = 0.0,
+                 schedule: int = SCHED_REGIONS, chunk_packets: int = 0, batch_packets: int = 0,
+                 tail_park: int = 0, split_n: int = 1):
+        """Peel-off images of the scattered light toward the directions ``n_obs`` ([n_dir, 3]):
+        a device tensor [n_dir, n_lambda, npix, npix] and the statistics."""
+        torch = _torch()
+        n = len(sources)
+        arr, keep = _source_array(sources)
+        nv = np.ascontiguousarray(n_obs, dtype=np.float64).reshape(-1, 3)
+        nl = self.model_info(int(sources[0].model))["n_lambda"]
+        img = torch.zeros((len(nv), nl, npix, npix), dtype=torch.float64, device=self.tdev)
+        po = PeelOpts(len(nv), npix, _ptr(nv).value, width, tiles, 0, event_buffer, img.data_ptr())
+        opts = TraceOpts(seed, iteration, precision, rr_threshold, rr_prob, max_events, block_size,
+                         blocks_per_cu, refill_threshold, schedule, chunk_packets, tail_park,
+                         batch_packets, 0, None, 0, split_n)
+        st = TraceStats()
+        self._check(lib().rt_peel_map(self.h, n, arr, C.byref(opts), C.byref(po), C.byref(st)))
+        return img, st.as_dict()
 
     def solve_temperature(self, model: int, a_node, t_min: float = 2.0, t_max: float = 3000.0):
         torch = _torch()

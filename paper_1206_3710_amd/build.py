@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libhiert.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["runtime.cpp", "trace_fp64.hip", "trace_fp32.hip", "blocked.hip", "sweep.hip",
-           "misc.hip", "thermal.hip", "render.hip"]
+           "misc.hip", "thermal.hip", "render.hip", "peel.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

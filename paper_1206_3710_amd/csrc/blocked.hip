@@ -209,8 +209,9 @@ __device__ __forceinline__ void land(WF word_of, int ax, int sg, int L, int32_t 
 // One work item: follow every queued packet of the item through its region.  FITS: the whole
 // region is in LDS (pure LDS lookups and deposits); otherwise nodes past the LDS capacity are
 // read and deposited in global memory.  SPLIT: package splitting is on (split_n > 1); the
-// unsplit instance carries none of its state or code.
-template <bool FITS, bool SPLIT>
+// unsplit instance carries none of its state or code.  PEEL: scattering events are kept for
+// the peel-off.
+template <bool FITS, bool SPLIT, bool PEEL>
 __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it, const RegionDev& R,
                                          const ModelDev& md, const Dims D, int nloc, int nup,
                                          int32_t* s_word, float* s_acc, int32_t* s_up, uint32_t* s_next,
@@ -628,6 +629,39 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         O0 = ((double)I0 + (double)x0) * h;
         O1 = ((double)I1 + (double)x1) * h;
         O2 = ((double)I2 + (double)x2) * h;
+        if (PEEL) {
+          // kept for the peel-off, with the weight before the event roulette (one reservation
+          // per wave)
+          const uint64_t pm = __ballot(1);
+          const int leader = __builtin_ctzll(pm);
+          uint32_t plo = 0, phi = 0;
+          if (lane == leader) {
+            const unsigned long long base = atomicAdd(p.peel_count, (unsigned long long)__popcll(pm));
+            plo = (uint32_t)base;
+            phi = (uint32_t)(base >> 32);
+          }
+          plo = __shfl(plo, leader, 64);
+          phi = __shfl(phi, leader, 64);
+          const uint64_t idx = (((uint64_t)phi << 32) | plo) + lane_rank(pm);
+          if (idx < p.peel_cap) {
+            PeelEv e;
+            e.P[0] = O0;
+            e.P[1] = O1;
+            e.P[2] = O2;
+            e.d[0] = (double)d0;
+            e.d[1] = (double)d1;
+            e.d[2] = (double)d2;
+            e.w = (double)w;
+            const int32_t c = b.rcanon[R.gbase + node];
+            e.node = md.base + (c < md.n_root ? c : c + (md.n_root_pad - md.n_root));
+            e.job = job;
+            e.I[0] = I0;
+            e.I[1] = I1;
+            e.I[2] = I2;
+            e.lev = lev;
+            p.peel_ev[idx] = e;
+          }
+        }
         const uint4 xr = philox(pid, stream, ev, br << 2, p.key0, p.key1);
         bool killed = false;
         if (rr_p > 0.0f && w < rr_thr * w0) {
@@ -663,7 +697,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   }
 }
 
-template <int BS, bool SPLIT>
+template <int BS, bool SPLIT, bool PEEL>
 __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int cap = b.cap;
@@ -703,10 +737,10 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     if (tid == 0) s_next = 0;
     __syncthreads();
     if (R.n <= cap)
-      run_item<true, SPLIT>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
+      run_item<true, SPLIT, PEEL>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
                      c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip);
     else
-      run_item<false, SPLIT>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
+      run_item<false, SPLIT, PEEL>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
                       c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip);
     __syncthreads();
     if (b.accb64) {
@@ -804,19 +838,20 @@ hipError_t launch_blk_emit(const BlkParams& b, const SweepState* st, uint64_t ba
   return hipGetLastError();
 }
 
-template <bool SPLIT>
+template <bool SPLIT, bool PEEL>
 static const void* pass_fn(int block) {
   switch (block) {
-    case 256: return (const void*)blk_pass_kernel<256, SPLIT>;
-    case 512: return (const void*)blk_pass_kernel<512, SPLIT>;
-    case 768: return (const void*)blk_pass_kernel<768, SPLIT>;
-    case 1024: return (const void*)blk_pass_kernel<1024, SPLIT>;
+    case 256: return (const void*)blk_pass_kernel<256, SPLIT, PEEL>;
+    case 512: return (const void*)blk_pass_kernel<512, SPLIT, PEEL>;
+    case 768: return (const void*)blk_pass_kernel<768, SPLIT, PEEL>;
+    case 1024: return (const void*)blk_pass_kernel<1024, SPLIT, PEEL>;
     default: return nullptr;
   }
 }
 
 hipError_t attr_blk_pass(int block, int lds_bytes) {
-  for (const void* f : {pass_fn<false>(block), pass_fn<true>(block)}) {
+  for (const void* f : {pass_fn<false, false>(block), pass_fn<true, false>(block), pass_fn<false, true>(block),
+                        pass_fn<true, true>(block)}) {
     if (!f) return hipErrorInvalidValue;
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
@@ -824,21 +859,24 @@ hipError_t attr_blk_pass(int block, int lds_bytes) {
   return hipSuccess;
 }
 
-template <bool SPLIT>
+template <bool SPLIT, bool PEEL>
 static hipError_t launch_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s) {
   switch (block) {
-    case 256: hipLaunchKernelGGL((blk_pass_kernel<256, SPLIT>), dim3(grid), dim3(256), lds_bytes, s, b); break;
-    case 512: hipLaunchKernelGGL((blk_pass_kernel<512, SPLIT>), dim3(grid), dim3(512), lds_bytes, s, b); break;
-    case 768: hipLaunchKernelGGL((blk_pass_kernel<768, SPLIT>), dim3(grid), dim3(768), lds_bytes, s, b); break;
-    case 1024: hipLaunchKernelGGL((blk_pass_kernel<1024, SPLIT>), dim3(grid), dim3(1024), lds_bytes, s, b); break;
+    case 256: hipLaunchKernelGGL((blk_pass_kernel<256, SPLIT, PEEL>), dim3(grid), dim3(256), lds_bytes, s, b); break;
+    case 512: hipLaunchKernelGGL((blk_pass_kernel<512, SPLIT, PEEL>), dim3(grid), dim3(512), lds_bytes, s, b); break;
+    case 768: hipLaunchKernelGGL((blk_pass_kernel<768, SPLIT, PEEL>), dim3(grid), dim3(768), lds_bytes, s, b); break;
+    case 1024: hipLaunchKernelGGL((blk_pass_kernel<1024, SPLIT, PEEL>), dim3(grid), dim3(1024), lds_bytes, s, b); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s) {
-  return b.t.split_n > 1 ? launch_pass<true>(b, grid, block, lds_bytes, s)
-                         : launch_pass<false>(b, grid, block, lds_bytes, s);
+  const bool split = b.t.split_n > 1, peel = b.t.peel_ev != nullptr;
+  if (split) return peel ? launch_pass<true, true>(b, grid, block, lds_bytes, s)
+                         : launch_pass<true, false>(b, grid, block, lds_bytes, s);
+  return peel ? launch_pass<false, true>(b, grid, block, lds_bytes, s)
+              : launch_pass<false, false>(b, grid, block, lds_bytes, s);
 }
 
 hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, int n_regions,

@@ -66,6 +66,19 @@ struct DevStats {
   double e_split_killed, e_split_gain;
 };
 
+// A scattering event kept for the peel-off (Sect. 2.4): position (root-cell units), incoming
+// direction and weight before the event roulette, the leaf it is in (internal id, level,
+// integer coordinates at that level) and its job.
+struct PeelEv {
+  double P[3];
+  double d[3];
+  double w;
+  int32_t node;
+  int32_t job;
+  int32_t I[3];
+  int32_t lev;
+};
+
 struct TraceParams {
   const int32_t* word;
   const double* rho64;
@@ -95,6 +108,34 @@ struct TraceParams {
   const int32_t* leaf_node;
   const int32_t* leaf_coord;
   const uint8_t* leaf_level;
+  // peel-off: scattering events of the current batch (null when off)
+  PeelEv* peel_ev;
+  unsigned long long* peel_count;
+  unsigned long long peel_cap;
+};
+
+#define RT_PEEL_MAXDIR 16
+
+struct PeelDir {
+  double n[3], e1[3], e2[3];
+};
+
+// Peel-off images and extinction tables of one model (Sect. 2.4).
+struct PeelParams {
+  PeelDir dir[RT_PEEL_MAXDIR];
+  int32_t n_dir, npix, tiles, model;
+  double W, C[3], pix_cm2;
+  const double* dnu;            // [n_lambda of the model] bandwidths
+  const int32_t* root_tab;      // [n_root] ordinal of a refined root cell, -1 for a root leaf
+  const int32_t* tab_root;      // [n_tab] root index of each ordinal
+  int64_t n_tab;
+  double* tab;                  // [n_dir][n_tab][6][tiles^2]
+  double* image;                // [n_dir][n_lambda][npix][npix]
+  const PeelEv* ev;
+  unsigned long long* count;    // events of the batch
+  unsigned long long* lost;     // events beyond the buffer, all batches
+  unsigned long long* done;     // events peeled, all batches
+  unsigned long long cap;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -184,6 +225,8 @@ struct SweepState {
   unsigned long long log_in[16];  // records in the input of each sweep of the current block
 };
 
+hipError_t launch_peel_tables(const TraceParams& p, const PeelParams& q, hipStream_t s);
+hipError_t launch_peel(const TraceParams& p, const PeelParams& q, int grid, hipStream_t s);
 hipError_t launch_blk_emit(const BlkParams& b, const SweepState* st, uint64_t batch, hipStream_t s);
 hipError_t launch_sweep_sort(SweepState* st, int in, int slot, uint64_t batch, uint64_t capq, const uint32_t* keys,
                              int n_keys, int n_regions, int chunk, uint32_t* hist, uint32_t* kfill,

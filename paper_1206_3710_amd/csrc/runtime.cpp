@@ -85,6 +85,8 @@ struct rt_ctx {
   DevBuf cdf_lum, cdf_q, cdf_qpre, lmax, scan_tmp;
   DevBuf tmp_in, tmp_out, tmp_out2, view, lamidx;
   DevBuf it_astars, it_adust, it_sum, it_told, it_crit;
+  // peel-off
+  DevBuf peel_ev, peel_ctr, peel_tab, peel_roottab, peel_tabroot, peel_dnu, peel_img;
   // grid-by-grid schedule: region-major copy of the trees
   int32_t reg_cap = 0;
   bool reg_dirty = true;
@@ -832,6 +834,7 @@ struct TraceOut {
   double* e_node = nullptr;      // device [total nodes] or null
   double* e_lamnode = nullptr;   // device [total lamnodes] or null
   double* e_esc = nullptr;       // device [total lambdas]
+  const PeelParams* peel = nullptr;  // peel-off after every batch (rt_peel_map)
 };
 
 rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_trace_opts* o,
@@ -1027,6 +1030,12 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   p.leaf_node = ctx->d_leaf_node.as<int32_t>();
   p.leaf_coord = ctx->d_leaf_coord.as<int32_t>();
   p.leaf_level = ctx->d_leaf_level.as<uint8_t>();
+  if (out.peel) {
+    p.peel_ev = const_cast<PeelEv*>(out.peel->ev);
+    p.peel_count = out.peel->count;
+    p.peel_cap = out.peel->cap;
+  }
+  const int grid_peel = ctx->n_cu * 8;
 
   const bool regions = fp32 && o->schedule == RT_SCHED_REGIONS;
   int reg_lds = 0, reg_per_cu = 0;
@@ -1115,6 +1124,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
         ctx->sweep_ev.push_back(e);
       }
     }
+    const PeelParams* peelp = out.peel;
     auto enqueue_block = [&](bool capturing) -> hipError_t {
       for (int k = 0; k < kSweepBlock; ++k) {
         const int in = k & 1, out = 1 - in;
@@ -1136,17 +1146,19 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
         if (!capturing && (e = hipEventRecord(ctx->sweep_ev[2 * k], ctx->work)) != hipSuccess) return e;
         if ((e = launch_blk_pass(bk, grid_pass, bs, reg_lds, ctx->work)) != hipSuccess) return e;
         if (!capturing && (e = hipEventRecord(ctx->sweep_ev[2 * k + 1], ctx->work)) != hipSuccess) return e;
+        if (peelp && (e = launch_peel(bk.t, *peelp, grid_peel, ctx->work)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(ctx->work, ctx->ev_b, 0)) != hipSuccess) return e;
       }
       return hipSuccess;
     };
     // capture the block as a graph (once per set of launch parameters), replay it until a
     // sweep finds the queues empty and nothing left to emit
-    std::vector<char> sig(sizeof b + 6 * sizeof(int64_t));
+    std::vector<char> sig(sizeof b + 6 * sizeof(int64_t) + (out.peel ? sizeof(PeelParams) : 0));
     {
       const int64_t extra[6] = {batch, capq, n_keys, grid_pass, bs, reg_lds};  // b holds split_n
       std::memcpy(sig.data(), &b, sizeof b);
       std::memcpy(sig.data() + sizeof b, extra, sizeof extra);
+      if (out.peel) std::memcpy(sig.data() + sizeof b + sizeof extra, out.peel, sizeof(PeelParams));
     }
     const bool use_graph = o->sweep_graph > 0;
     if (use_graph && (!ctx->sweep_exec || sig != ctx->sweep_sig)) {
@@ -1202,6 +1214,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
         if (jobs[k].n > 0) {
           HIPCHK(launch_trace_fp64(p, (int)k, jobs[k].n, bs, ctx->stream));
           ++main_launches;
+          if (out.peel) HIPCHK(launch_peel(p, *out.peel, grid_peel, ctx->stream));
         }
     }
   }
@@ -1483,6 +1496,134 @@ rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32
     HIPCHK(hipMemcpyAsync(&cr, ctx->counter.p, 8, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (crossings) *crossings = cr;
+    return RT_OK;
+  })
+}
+
+// ---- peel-off (Sect. 2.4) ---------------------------------------------------------------
+rt_status rt_peel_map(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_trace_opts* o,
+                      const rt_peel_opts* po, rt_trace_stats* stats) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!po || !o || !src) return fail(ctx, RT_EINVAL, "null argument");
+    if (po->n_dir < 1 || po->n_dir > RT_PEEL_MAXDIR) return fail(ctx, RT_EINVAL, "n_dir must be in [1, 16]");
+    if (po->npix < 1 || po->npix > 16384) return fail(ctx, RT_EINVAL, "npix must be in [1, 16384]");
+    if (po->tiles < 0 || po->tiles > 64) return fail(ctx, RT_EINVAL, "tiles must be in [0, 64]");
+    if (po->event_buffer < 0) return fail(ctx, RT_EINVAL, "event_buffer must be >= 0");
+    if (!po->n_obs || !po->image) return fail(ctx, RT_EINVAL, "null directions or image");
+    if (!std::isfinite(po->width)) return fail(ctx, RT_EINVAL, "bad width");
+    if (!(o->precision == RT_FP64 || (o->precision == RT_FP32_LOCAL && o->schedule == RT_SCHED_REGIONS)))
+      return fail(ctx, RT_EINVAL, "peel-off needs RT_FP64 or the FP32-local region schedule");
+    if (n_src < 1 || n_src > 255) return fail(ctx, RT_EINVAL, "n_src must be in [1, 255]");
+    const int32_t model = src[0].model;
+    if (rt_status s = check_model(ctx, model)) return s;
+    for (int s = 1; s < n_src; ++s)
+      if (src[s].model != model) return fail(ctx, RT_EINVAL, "peel-off sources must share one model");
+    HostModel& h = ctx->models[model];
+    if (h.nl < 1) return fail(ctx, RT_ESTATE, "rt_set_dust not called for model %d", model);
+    PeelParams q;
+    std::memset(&q, 0, sizeof q);
+    q.n_dir = po->n_dir;
+    for (int d = 0; d < po->n_dir; ++d) {
+      const double* v = po->n_obs + 3 * d;
+      const double nn = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      if (!(nn > 0.0) || !std::isfinite(nn)) return fail(ctx, RT_EINVAL, "bad observer direction %d", d);
+      PeelDir& V = q.dir[d];
+      for (int a = 0; a < 3; ++a) V.n[a] = v[a] / nn;
+      // image frame of the maps: e1 = z x n / |z x n| (x when n is along z), e2 = n x e1
+      if (V.n[0] == 0.0 && V.n[1] == 0.0) {
+        V.e1[0] = 1.0;
+        V.e1[1] = 0.0;
+        V.e1[2] = 0.0;
+      } else {
+        const double en = std::sqrt(V.n[1] * V.n[1] + V.n[0] * V.n[0]);
+        V.e1[0] = -V.n[1] / en;
+        V.e1[1] = V.n[0] / en;
+        V.e1[2] = 0.0;
+      }
+      V.e2[0] = V.n[1] * V.e1[2] - V.n[2] * V.e1[1];
+      V.e2[1] = V.n[2] * V.e1[0] - V.n[0] * V.e1[2];
+      V.e2[2] = V.n[0] * V.e1[1] - V.n[1] * V.e1[0];
+    }
+    q.npix = po->npix;
+    q.tiles = po->tiles;
+    q.model = model;
+    q.W = po->width > 0.0 ? po->width : (double)std::max(h.n[0], std::max(h.n[1], h.n[2]));
+    for (int a = 0; a < 3; ++a) q.C[a] = 0.5 * h.n[a];
+    const double side = q.W / (double)q.npix * h.cell_cm;
+    q.pix_cm2 = side * side;
+    if (rt_status s = sync_device(ctx)) return s;
+    // refined root cells: table ordinals
+    std::vector<int32_t> root_tab(h.n_root, -1), tab_root;
+    for (int64_t r = 0; r < h.n_root; ++r)
+      if (ctx->h_child[h.base + r] >= 0) {
+        root_tab[r] = (int32_t)tab_root.size();
+        tab_root.push_back((int32_t)r);
+      }
+    q.n_tab = (int64_t)tab_root.size();
+    if (rt_status e = upload(ctx, ctx->peel_roottab, root_tab)) return e;
+    if (rt_status e = upload(ctx, ctx->peel_tabroot, tab_root.empty() ? std::vector<int32_t>(1, 0) : tab_root))
+      return e;
+    if (rt_status e = upload(ctx, ctx->peel_dnu, h.dnu)) return e;
+    q.root_tab = ctx->peel_roottab.as<int32_t>();
+    q.tab_root = ctx->peel_tabroot.as<int32_t>();
+    q.dnu = ctx->peel_dnu.as<double>();
+    const size_t tab_n = (size_t)q.n_dir * q.n_tab * 6 * q.tiles * q.tiles;
+    HIPCHK(ctx->peel_tab.ensure(8 * std::max<size_t>(tab_n, 1)));
+    q.tab = ctx->peel_tab.as<double>();
+    const size_t img_n = (size_t)q.n_dir * h.nl * q.npix * q.npix;
+    HIPCHK(ctx->peel_img.ensure(8 * img_n));
+    HIPCHK(hipMemsetAsync(ctx->peel_img.p, 0, 8 * img_n, ctx->stream));
+    q.image = ctx->peel_img.as<double>();
+    q.cap = po->event_buffer > 0 ? (unsigned long long)po->event_buffer : (1ull << 24);
+    HIPCHK(ctx->peel_ev.ensure(sizeof(PeelEv) * q.cap));
+    HIPCHK(ctx->peel_ctr.ensure(3 * sizeof(unsigned long long)));
+    HIPCHK(hipMemsetAsync(ctx->peel_ctr.p, 0, 3 * sizeof(unsigned long long), ctx->stream));
+    q.ev = ctx->peel_ev.as<PeelEv>();
+    q.count = ctx->peel_ctr.as<unsigned long long>();
+    q.lost = q.count + 1;
+    q.done = q.count + 2;
+    // extinction tables (device, FP64 marches from every tile centre)
+    double table_ms = 0.0;
+    if (tab_n > 0) {
+      TraceParams tp;
+      std::memset(&tp, 0, sizeof tp);
+      tp.child = ctx->d_child.as<int32_t>();
+      tp.up = ctx->d_up.as<int32_t>();
+      tp.rho64 = ctx->d_rho64.as<double>();
+      tp.models = ctx->d_models.as<ModelDev>();
+      HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+      HIPCHK(launch_peel_tables(tp, q, ctx->stream));
+      HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+      HIPCHK(hipEventSynchronize(ctx->ev1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+      table_ms = ms;
+    }
+    int64_t tn, tl, tln;
+    totals(ctx, &tn, &tl, &tln);
+    HIPCHK(ctx->out_esc.ensure(8 * std::max<int64_t>(tl, 1)));
+    TraceOut out;
+    out.e_esc = ctx->out_esc.as<double>();
+    out.peel = &q;
+    if (rt_status s = trace_impl(ctx, n_src, src, o, out, stats)) return s;
+    unsigned long long ctr[3] = {0, 0, 0};
+    HIPCHK(hipMemcpyAsync(ctr, q.count, sizeof ctr, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctr[1] > 0)
+      return fail(ctx, RT_EDEVICE,
+                  "peel-off event buffer too small: %llu events of a batch did not fit in %llu (raise "
+                  "event_buffer or lower batch_packets)",
+                  (unsigned long long)ctr[1], (unsigned long long)q.cap);
+    HIPCHK(hipMemcpyAsync(po->image, q.image, 8 * img_n,
+                          is_device_ptr(po->image) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (stats) {
+      stats->peel_events = ctr[2];
+      stats->table_ms = table_ms;
+    }
     return RT_OK;
   })
 }

@@ -82,6 +82,23 @@ __global__ __launch_bounds__(256) void trace_fp64_kernel(const TraceParams p, co
           break;
         }
         ++c_scat;
+        if (p.peel_ev) {
+          // kept for the peel-off with the weight before the event roulette
+          const unsigned long long idx = atomicAdd(p.peel_count, 1ull);
+          if (idx < p.peel_cap) {
+            PeelEv& e = p.peel_ev[idx];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              e.P[b] = k.P[b];
+              e.d[b] = k.d[b];
+              e.I[b] = k.I[b];
+            }
+            e.w = w;
+            e.node = k.node;
+            e.job = job_idx;
+            e.lev = k.lev;
+          }
+        }
         const uint4 x = philox((uint32_t)j, job.stream, ev, 0u, p.key0, p.key1);
         if (p.rr_p > 0.0 && w < p.rr_thr * w0) {
           if (unif64(x.x) < p.rr_p) {
