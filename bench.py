@@ -153,6 +153,76 @@ def split_study(rt, gen, w, kw32, runs=20, packets=1_000_000, split_n=4, lam_um=
     return out
 
 
+def peel_study(rt, gen, w, kw32, workload, packets=1_000_000, runs=3, tiles=4, lam_um=0.55):
+    """Peel-off toward 5 observers (Sect. 2.4; the paper times its accelerated peel-off this
+    way): time per run of the plain trace, of the trace with the columns marched to the border,
+    and with extinction tables; the tables' effect on the images against their noise."""
+    import numpy as np
+    import torch
+    tree, dust = w.trees[0], w.dusts[0]
+    i = int(np.argmin(np.abs(np.log(dust.lambda_um / lam_um))))
+    d1 = gen.Dust(dust.lambda_um[i:i + 1], dust.kappa_ext[i:i + 1], dust.albedo[i:i + 1],
+                  dust.hg_g[i:i + 1])
+    s0 = w.sources[0]
+    src = [gen.Source(s0.kind, 0, pos=s0.pos, dir=s0.dir, power=np.array([float(s0.power[i])]),
+                      packets=packets)]
+    if workload == "disc":
+        el = np.radians(2.0)  # 2 degrees above the disc plane, five azimuths
+        dirs = [[np.cos(el) * np.cos(a), np.cos(el) * np.sin(a), np.sin(el)]
+                for a in np.radians([0.0, 72.0, 144.0, 216.0, 288.0])]
+    else:
+        dirs = [[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1], [1, -1, 0.5]]
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, d1)
+    kw = {k_: v for k_, v in kw32.items() if k_ not in ("sweep_graph", "batch_packets")}
+    kw.update(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob, precision=rt.FP32_LOCAL,
+              batch_packets=1 << 18)
+    npix = 256
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, 1e3 * (time.perf_counter() - t0)
+    fn_plain = lambda r_: ctx.trace_packets(src, seed=w.seed + r_, **kw)
+    fn_peel = lambda r_, t_: ctx.peel_map(src, seed=w.seed + r_, n_obs=dirs, npix=npix, tiles=t_,
+                                          event_buffer=1 << 26, **kw)
+    fn_plain(99)
+    fn_peel(99, 0)
+    fn_peel(99, tiles)
+    ms = {"plain": [], "marched": [], "tabled": []}
+    imgs = {"marched": [], "tabled": []}
+    events = 0
+    for r_ in range(runs):
+        ms["plain"].append(timed(lambda: fn_plain(r_))[1])
+        (a, st), t_a = timed(lambda: fn_peel(r_, 0))
+        (b, sb), t_b = timed(lambda: fn_peel(r_, tiles))
+        ms["marched"].append(t_a)
+        ms["tabled"].append(t_b)
+        imgs["marched"].append(a.double().cpu().numpy())
+        imgs["tabled"].append(b.double().cpu().numpy())
+        events = st["peel_events"]
+        table_ms = sb["table_ms"]
+
+    def rel(x, ref):
+        return float(np.sqrt(((x - ref) ** 2).sum() / (ref ** 2).sum()))
+    ref = imgs["marched"][0]
+    out = {"wavelength_um": float(dust.lambda_um[i]), "packets": packets, "runs": runs,
+           "observers": dirs if isinstance(dirs[0], list) else [list(map(float, d)) for d in dirs],
+           "npix": npix, "tiles": tiles, "events_per_run": int(events),
+           "ms_per_run": {k_: float(np.median(v)) for k_, v in ms.items()},
+           "table_ms": float(table_ms),
+           "peel_ms_marched": float(np.median(ms["marched"]) - np.median(ms["plain"])),
+           "peel_ms_tabled": float(np.median(ms["tabled"]) - np.median(ms["plain"])),
+           "speedup_total": float(np.median(ms["marched"]) / np.median(ms["tabled"])),
+           "tables_rel_rms_vs_marched": rel(imgs["tabled"][0], ref),
+           "noise_rel_rms": rel(imgs["marched"][1], ref) / float(np.sqrt(2.0)) if runs > 1 else None}
+    ctx.close()
+    return out
+
+
 def pass_sources_sha():
     import hashlib
     h = hashlib.sha256()
@@ -191,6 +261,8 @@ def parse():
     ap.add_argument("--trace-only", action="store_true", help="time only the transport step")
     ap.add_argument("--split-study", action="store_true",
                     help="add the package-splitting noise study (cloud and deep workloads)")
+    ap.add_argument("--peel-study", action="store_true",
+                    help="add the peel-off timing study (cloud, disc and deep workloads)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="no effect: the 4 GiB device-to-device copy always runs first")
     return ap.parse_args()
@@ -414,6 +486,10 @@ def main():
     if a.workload in ("cloud", "deep") and a.schedule == 0 and a.split_study:
         splitting = split_study(rt, gen, w, kw32)
 
+    peeling = None
+    if a.workload in ("cloud", "disc", "deep") and a.schedule == 0 and a.peel_study:
+        peeling = peel_study(rt, gen, w, kw32, a.workload)
+
     res = {
         "metric": "cell-crossings/s (FP32-local form; FP64 form in fp64)",
         "value": value,
@@ -450,6 +526,7 @@ def main():
         "cpu_baseline": cpu,
         "cpu_all_cores": cpu_all,
         "splitting": splitting,
+        "peel_off": peeling,
     }
     print(json.dumps(res))
     ctx.close()
