@@ -74,7 +74,8 @@ def lib():
         L.om_trace.restype = C.c_int
         L.om_trace.argtypes = [P, C.c_int32, C.c_int32, P, P, P, P, P, P, C.c_uint64, C.c_uint32,
                                C.c_double, C.c_double, C.c_int64, C.c_int32, C.c_int64, C.c_int64,
-                               C.c_int32, P, P, P, C.c_int64, P, C.c_int32, P]
+                               C.c_int32, P, P, P, C.c_int64, P, C.c_int32, P, P, P]
+        L.om_emission_all.argtypes = [P, P, P]
         L.om_hg_phase.restype = C.c_double
         L.om_hg_phase.argtypes = [C.c_double, C.c_double]
         L.om_peel_column.restype = C.c_int
@@ -192,10 +193,12 @@ class Model:
 
     def trace(self, sources, seed, iteration=0, model_index=0, rr_threshold=0.0, rr_prob=0.0,
               max_events=0, per_lambda=False, pid_begin=0, pid_end=-1, lam_sel=-1,
-              t_node=None, rec_stride=0, deposits=True, split_n=1, peel=None):
+              t_node=None, rec_stride=0, deposits=True, split_n=1, peel=None, self_absorption=False):
         """Follow packets of ``sources`` (gen.Source list) -> (e_abs, e_esc, stats, records).
         ``peel``: dict(n_obs=[[x, y, z], ...], npix=, width=0.0, tiles=0) turns on the peel-off
-        images, returned in stats["peel_image"] as [n_dir, n_lambda, npix, npix]."""
+        images, returned in stats["peel_image"] as [n_dir, n_lambda, npix, npix].
+        ``self_absorption``: stats["e_self"] and stats["e_emit_node"] per node (the diagonal
+        part of the accelerated Lambda iteration)."""
         L = lib()
         ns = len(sources)
         nl = self.n_lambda
@@ -216,6 +219,8 @@ class Model:
         if rec_stride > 0:
             nrec = (pid_end - pid_begin + rec_stride - 1) // rec_stride
             rec = np.zeros(ns * nl * nrec, dtype=RECORD_DTYPE)
+        e_self = np.zeros(self.n_nodes) if self_absorption else None
+        e_emit_node = np.zeros(self.n_nodes) if self_absorption else None
         po, img = None, None
         if peel is not None:
             nobs = np.ascontiguousarray(peel["n_obs"], dtype=np.float64).reshape(-1, 3)
@@ -229,12 +234,18 @@ class Model:
                         pid_begin, pid_end, lam_sel, None if e_abs is None else _p(e_abs),
                         _p(e_esc), C.byref(st),
                         rec_stride, None if rec is None else _p(rec), split_n,
-                        None if po is None else C.byref(po))
+                        None if po is None else C.byref(po),
+                        None if e_self is None else _p(e_self),
+                        None if e_emit_node is None else _p(e_emit_node))
         if rc != 0:
             raise OracleError(L.om_error().decode())
-        if img is not None:
+        if img is not None or e_self is not None:
             out = st.as_dict()
-            out["peel_image"] = img
+            if img is not None:
+                out["peel_image"] = img
+            if e_self is not None:
+                out["e_self"] = e_self
+                out["e_emit_node"] = e_emit_node
             if per_lambda and e_abs is not None:
                 e_abs = e_abs.reshape(nl, self.n_nodes)
             return e_abs, e_esc, out, rec
@@ -249,6 +260,13 @@ class Model:
         col = np.zeros(len(x))
         lib().om_peel_column(self.h, _p(nv), int(tiles), len(x), _p(x), _p(col))
         return col
+
+    def emission_all(self, t_node):
+        """Emitted power of every leaf at temperatures t_node (0 for refined nodes)."""
+        tn = np.ascontiguousarray(t_node, dtype=np.float64)
+        out = np.zeros(self.n_nodes)
+        lib().om_emission_all(self.h, _p(tn), _p(out))
+        return out
 
     def solve_temperature(self, a_node, t_min=2.0, t_max=3000.0):
         a = np.ascontiguousarray(a_node, dtype=np.float64)
@@ -305,9 +323,21 @@ def uniform(x):
     return ((x >> np.uint64(9)).astype(np.float64) * 2.0 + 1.0) * 2.0 ** -24
 
 
+def ali_step_absorbed(a_stars, a_dust, e_self, e_emit_node):
+    """Absorbed power that the accelerated Lambda iteration (Sect. 3.1 Eq. 3) balances with the
+    new emission E(T): with lambda* = e_self / e_emit the fraction of a cell's own emission it
+    absorbs before its packets first leave it, E(T)(1 - lambda*) = A_stars + A_dust - e_self,
+    i.e. E(T) = (A_stars + A_dust - e_self) / (1 - lambda*)."""
+    lam = np.where(e_emit_node > 0.0, e_self / np.where(e_emit_node > 0.0, e_emit_node, 1.0), 0.0)
+    lam = np.minimum(lam, 1.0 - 1e-9)
+    return (a_stars + a_dust - e_self) / (1.0 - lam)
+
+
 def lambda_iterate(model, star_sources, seed, n_max=30, tol=1e-3, n_fixed=None,
-                   dust_packets=None, rr_threshold=0.0, rr_prob=0.0, t_min=2.0, t_max=3000.0):
-    """Lambda iteration (paper Sect. 3.1 Eq. 2; constant-source field kept, Sect. 3.2):
+                   dust_packets=None, rr_threshold=0.0, rr_prob=0.0, t_min=2.0, t_max=3000.0,
+                   ali=False):
+    """Lambda iteration (paper Sect. 3.1 Eq. 2; constant-source field kept, Sect. 3.2), or with
+    ali=True the accelerated iteration with the diagonal operator (Eq. 3, ali_step_absorbed):
     A_stars from the constant sources once, T_0 = f(A_stars); then for n >= 1 the dust
     emission of T_{n-1} is traced with key iteration n, T_n = f(A_stars + A_dust).
     Stops when the mass-weighted mean |T_n - T_{n-1}|/T_{n-1} < tol, or after n_max steps
@@ -326,9 +356,13 @@ def lambda_iterate(model, star_sources, seed, n_max=30, tol=1e-3, n_fixed=None,
     for it in range(1, n_steps + 1):
         src = [gen.Source(gen.SRC_DUST, 0, packets=npk)]
         a_dust, _, st, _ = model.trace(src, seed, iteration=it, rr_threshold=rr_threshold,
-                                       rr_prob=rr_prob, t_node=t)
+                                       rr_prob=rr_prob, t_node=t, self_absorption=ali)
         stats.append(st)
-        t_new = model.solve_temperature(a_stars + a_dust, t_min, t_max)
+        if ali:
+            a_new = ali_step_absorbed(a_stars, a_dust, st["e_self"], st["e_emit_node"])
+        else:
+            a_new = a_stars + a_dust
+        t_new = model.solve_temperature(a_new, t_min, t_max)
         hist.append(t_new)
         w = mass[leaf]
         rel = np.abs(t_new[leaf] - t[leaf]) / t[leaf]

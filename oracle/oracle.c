@@ -392,6 +392,11 @@ typedef struct {
   packet* stack;            /* split packages waiting to be followed */
   int64_t n_stack, cap_stack;
   const peel_ctx* peel;     /* NULL: no peel-off */
+  /* accelerated Lambda iteration (Sect. 3.1 Eq. 3): NULL when off */
+  double* e_self;           /* absorbed by dust-emission packets in their birth cell before their
+                               first crossing (the diagonal operator's part) */
+  double* e_emit_node;      /* energy emitted by dust-emission packets, per birth cell */
+  int dust;                 /* the current source is dust emission */
 } tctx;
 
 /* Branch identifier of child c of branch b split at the package's crossing number n: the
@@ -663,6 +668,7 @@ static int propagate(tctx* c, packet* p) {
       double de = p->w * (-expm1(-(sa * s)));
       if (c->e_abs) c->e_abs[p->node] += de;
       else c->e_abs_total += de;
+      if (c->e_self && c->dust && p->crossings == 1) c->e_self[p->node] += de;
       p->w = p->w - de;
     }
     for (int b = 0; b < 3; ++b) p->P[b] = fma(s, p->d[b], p->P[b]);
@@ -808,7 +814,8 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
              const double* t_node, uint64_t seed, uint32_t iteration, double rr_threshold,
              double rr_prob, int64_t max_events, int32_t per_lambda, int64_t pid_begin,
              int64_t pid_end, int32_t lam_sel, double* e_abs, double* e_esc, om_stats* stats,
-             int64_t rec_stride, om_record* rec, int32_t split_n, const om_peel_opts* peel) {
+             int64_t rec_stride, om_record* rec, int32_t split_n, const om_peel_opts* peel,
+             double* e_self, double* e_emit_node) {
   if (m->nl < 1) { seterr("dust not set"); return -1; }
   if (split_n < 1 || split_n > 64) { seterr("split factor must be in [1, 64]"); return -1; }
   if (peel && (peel->n_dir < 1 || peel->n_dir > OM_MAXDIR || peel->npix < 1 || peel->tiles < 0 ||
@@ -853,6 +860,9 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
   c.n_stack = 0;
   c.cap_stack = 0;
   c.peel = NULL;
+  c.e_self = e_self;
+  c.e_emit_node = e_emit_node;
+  c.dust = 0;
   peel_ctx pc;
   memset(&pc, 0, sizeof pc);
   if (peel) {
@@ -875,6 +885,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
   }
   for (int s = 0; s < n_src; ++s) {
     const int64_t N = packets[s];
+    c.dust = kind[s] == OM_DUST;
     int64_t jb = pid_begin < 0 ? 0 : pid_begin;
     int64_t je = pid_end < 0 || pid_end > N ? N : pid_end;
     int64_t nrec = rec_stride > 0 ? (pid_end - pid_begin + rec_stride - 1) / rec_stride : 0;
@@ -966,6 +977,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
         int64_t birth = p.node;
         stats->packets += 1;
         stats->e_emit += p.w0;
+        if (c.e_emit_node && c.dust) c.e_emit_node[birth] += p.w0;
         int res = propagate(&c, &p);
         stats->crossings += p.crossings;
         if (rec && rec_stride > 0 && ((j - pid_begin) % rec_stride) == 0) {
@@ -1138,6 +1150,10 @@ int om_render(const om_model* m, const double n_obs[3], int32_t npix, double wid
 double om_hg_mu(double g, double u) { return hg_mu(g, u); }
 
 double om_hg_phase(double g, double mu) { return hg_phase(g, mu); }
+
+void om_emission_all(const om_model* m, const double* t_node, double* out) {
+  for (int64_t i = 0; i < m->nnodes; ++i) out[i] = m->child[i] < 0 ? om_emission(m, i, t_node[i]) : 0.0;
+}
 
 int om_peel_column(const om_model* m, const double n_obs[3], int32_t tiles, int64_t npts,
                    const double* xyz, double* col) {

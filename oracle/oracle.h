@@ -111,7 +111,11 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
              double rr_threshold, double rr_prob, int64_t max_events, int32_t per_lambda,
              int64_t pid_begin, int64_t pid_end, int32_t lam_sel,
              double* e_abs, double* e_esc, om_stats* stats, int64_t rec_stride, om_record* rec,
-             int32_t split_n, const om_peel_opts* peel);
+             int32_t split_n, const om_peel_opts* peel, double* e_self, double* e_emit_node);
+
+/* e_self, e_emit_node ([n_nodes], added to; NULL = off): for the accelerated Lambda iteration
+ * (Sect. 3.1 Eq. 3, diagonal operator), the energy that dust-emission packets deposit in their
+ * birth cell before their first crossing, and the energy they start with, per birth cell. */
 
 /* Equilibrium temperature per leaf: 4 pi m sum_i kappa_abs_i B_i(T) dnu_i = A. */
 void om_solve_temperature(const om_model* m, const double* a_node, double t_min, double t_max,
@@ -131,6 +135,8 @@ double om_uniform(uint32_t x);
 int64_t om_cdf_pick(const uint64_t* q, int64_t n, uint64_t r);
 uint32_t om_branch_id(uint32_t b, uint32_t n, uint32_t c);
 double om_hg_phase(double g, double mu);
+/* Emitted power of every leaf at t_node (0 for refined nodes). */
+void om_emission_all(const om_model* m, const double* t_node, double* out);
 /* Peel-off column (density x length, root-cell units) from each point toward n_obs, marched
  * to the border (tiles = 0) or with the extinction tables. */
 int om_peel_column(const om_model* m, const double n_obs[3], int32_t tiles, int64_t npts,
