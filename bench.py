@@ -223,6 +223,47 @@ def peel_study(rt, gen, w, kw32, workload, packets=1_000_000, runs=3, tiles=4, l
     return out
 
 
+def ali_study(rt, gen, steps=24, ref_steps=60, packets=300_000):
+    """Accelerated against plain Lambda iteration (Sect. 3.1, Eqs. 2 and 3) on an optically
+    thick cube around a star (gen.thick_cube): the mass-weighted mean relative distance of the
+    temperatures after k steps to a long accelerated run, and the time per step."""
+    import numpy as np
+    import torch
+    w = gen.thick_cube(packets=packets)
+    tree, dust = w.trees[0], w.dusts[0]
+    level, leaf, rho, _ = node_geometry(tree)
+    mass = (rho * 8.0 ** (-level.astype(np.float64)))[leaf]
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    kw = dict(precision=rt.FP32_LOCAL)
+    checkpoints = [k for k in (1, 2, 4, 8, 12, 16, 24, 32, 48) if k <= steps]
+
+    def run(ali, ks):
+        hist, ms = [], []
+        for k in ks:  # every call starts again from the constant sources
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t_, _, _ = ctx.lambda_iterate(m, w.sources, seed=w.seed, dust_packets=packets, n_max=k,
+                                          tol=0.0, ali=ali, **kw)
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t0))
+            hist.append(t_.cpu().numpy()[leaf])
+        return hist, ms
+    ref = run(True, [ref_steps])[0][-1]
+    out = {"model": "optically thick cube: root 16^3 refined once (32768 leaves), 12 wavelengths, "
+                    "3000 K star at the centre",
+           "packets_per_lambda": packets, "checkpoints": checkpoints,
+           "reference": f"{ref_steps} accelerated steps"}
+    for name, ali in (("plain", False), ("accelerated", True)):
+        hist, ms = run(ali, checkpoints)
+        dist = [float((mass * np.abs(h - ref) / ref).sum() / mass.sum()) for h in hist]
+        out[name] = {"distance_to_reference": dist,
+                     "ms_per_step": float((ms[-1] - ms[0]) / max(checkpoints[-1] - checkpoints[0], 1))}
+    ctx.close()
+    return out
+
+
 def pass_sources_sha():
     import hashlib
     h = hashlib.sha256()
@@ -261,6 +302,8 @@ def parse():
     ap.add_argument("--trace-only", action="store_true", help="time only the transport step")
     ap.add_argument("--split-study", action="store_true",
                     help="add the package-splitting noise study (cloud and deep workloads)")
+    ap.add_argument("--ali-study", action="store_true",
+                    help="add the accelerated-iteration convergence study (a thick cube)")
     ap.add_argument("--peel-study", action="store_true",
                     help="add the peel-off timing study (cloud, disc and deep workloads)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -486,6 +529,10 @@ def main():
     if a.workload in ("cloud", "deep") and a.schedule == 0 and a.split_study:
         splitting = split_study(rt, gen, w, kw32)
 
+    accel = None
+    if a.schedule == 0 and a.ali_study:
+        accel = ali_study(rt, gen)
+
     peeling = None
     if a.workload in ("cloud", "disc", "deep") and a.schedule == 0 and a.peel_study:
         peeling = peel_study(rt, gen, w, kw32, a.workload)
@@ -527,6 +574,7 @@ def main():
         "cpu_all_cores": cpu_all,
         "splitting": splitting,
         "peel_off": peeling,
+        "accelerated_iteration": accel,
     }
     print(json.dumps(res))
     ctx.close()

@@ -511,6 +511,21 @@ def refined_block(levels: int, n: int = 4, rho: float = 1.0) -> TreeDesc:
     return TreeDesc(n, n, n, 1.0, np.full(n ** 3, float(rho)), refined, kids)
 
 
+def thick_cube(n_root: int = 16, seed: int = BASE_SEED + 6, packets: int = 1_000_000) -> Workload:
+    """Optically thick dust cube around a star, for the convergence of the Lambda iteration:
+    root n_root^3 cells of 1 cm refined once everywhere, density 1 g cm^-3, 12 wavelengths
+    1-1000 um with kappa = 30 (lambda / um)^-1.5 cm^2 g^-1 (a leaf is optically thick below
+    about 10 um), albedo 0.1, isotropic scattering, and a 3000 K blackbody star of unit
+    surface at the centre."""
+    lam = np.logspace(0.0, 3.0, 12)
+    dust = Dust(lam, 30.0 * lam ** -1.5, np.full(12, 0.1), np.zeros(12))
+    tree = uniform_refined_tree((n_root, n_root, n_root), 1, rho=1.0, cell_cm=1.0)
+    c = 0.5 * n_root
+    star = [Source(SRC_POINT, 0, pos=(c + 0.05, c - 0.05, c + 0.02),
+                   power=planck_nu_input(lam, 3000.0), packets=packets)]
+    return Workload("thick_cube", [tree], [dust], star, seed, meta={"n_root": n_root})
+
+
 def describe(w: Workload) -> dict:
     out = {"name": w.name, "models": len(w.trees)}
     out["nodes"] = int(sum(t.n_nodes for t in w.trees))

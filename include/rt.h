@@ -11,6 +11,7 @@
  *                         of one grain component (Sect. 4);
  *   rt_lambda_iterate     the Lambda iteration of Sect. 3.1 Eq. (2) with the constant-source
  *                         field kept (Sect. 3.2);
+ *   rt_ali_iterate        the same with the accelerated iteration (Sect. 3.1 Eq. 3);
  *   rt_render_map         surface-brightness maps toward chosen directions (Sect. 4.1);
  *   rt_peel_map           images of the scattered light by peel-off, with precomputed
  *                         extinction tables (Sect. 2.4).
@@ -232,6 +233,17 @@ rt_status rt_lambda_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_
                             const rt_trace_opts* opts, int64_t dust_packets, int32_t n_max,
                             double tol, double t_min, double t_max, double* t_node,
                             int32_t* n_done, double* crit);
+
+/* Accelerated Lambda iteration with a diagonal operator (Sect. 3.1, Eq. 3), otherwise as
+ * rt_lambda_iterate (same arguments, stopping rule and outputs).  Each dust-emission trace also
+ * tallies, per cell, the energy its own packets deposit in it before they first leave it
+ * (A_self) and the energy they start with (E_emit); lambda* = A_self / E_emit is the diagonal
+ * operator, and T_n balances E(T_n) (1 - lambda*) = A_stars + A_dust - A_self, which has the
+ * Lambda iteration's fixed point and converges faster where cells are optically thick.
+ * RT_FP64, or RT_FP32_LOCAL with the region schedule. */
+rt_status rt_ali_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
+                         const rt_trace_opts* opts, int64_t dust_packets, int32_t n_max, double tol,
+                         double t_min, double t_max, double* t_node, int32_t* n_done, double* crit);
 
 /* Surface-brightness map (Sect. 4.1) of a model with its current temperatures: orthographic
  * view toward the observer direction n_obs; pixel (i, j) centre = box centre +

@@ -24,7 +24,7 @@ SCHED_REGIONS, SCHED_GLOBAL = 0, 1
 
 EXPORTS = ["rt_last_error", "rt_create", "rt_destroy", "rt_build_tree", "rt_get_model_info",
            "rt_get_sizes", "rt_locate", "rt_set_dust", "rt_set_temperature", "rt_trace_packets",
-           "rt_solve_temperature", "rt_lambda_iterate", "rt_render_map", "rt_peel_map",
+           "rt_solve_temperature", "rt_lambda_iterate", "rt_ali_iterate", "rt_render_map", "rt_peel_map",
            "rt_autotune", "rt_philox"]
 
 
@@ -111,6 +111,7 @@ def lib():
             "rt_trace_packets": (I32, [P, I32, P, P, P, P, P, P]),
             "rt_solve_temperature": (I32, [P, I32, P, D, D, P]),
             "rt_lambda_iterate": (I32, [P, I32, I32, P, P, I64, I32, D, D, D, P, P, P]),
+            "rt_ali_iterate": (I32, [P, I32, I32, P, P, I64, I32, D, D, D, P, P, P]),
             "rt_render_map": (I32, [P, I32, P, I32, D, I32, P, I32, P, P]),
             "rt_peel_map": (I32, [P, I32, P, P, P, P]),
             "rt_autotune": (I32, [P, I32, P, P, D, C.c_char_p, P, P]),
@@ -347,7 +348,9 @@ class Context:
     def lambda_iterate(self, model: int, sources: Sequence, seed: int, dust_packets: int,
                        n_max: int = 30, tol: float = 1e-3, t_min: float = 2.0,
                        t_max: float = 3000.0, precision: int = FP64, rr_threshold: float = 0.0,
-                       rr_prob: float = 0.0, iteration: int = 0, **kw):
+                       rr_prob: float = 0.0, iteration: int = 0, ali: bool = False, **kw):
+        """Lambda iteration (ali=True: the accelerated one with the diagonal operator).
+        Returns (temperatures, steps taken, stopping statistic per step)."""
         torch = _torch()
         n = len(sources)
         arr = (Source * max(n, 1))()
@@ -365,9 +368,9 @@ class Context:
         t = torch.empty(self.models[model], dtype=torch.float64, device=self.tdev)
         nd = C.c_int32()
         crit = np.zeros(max(n_max, 1))
-        self._check(lib().rt_lambda_iterate(self.h, model, n, arr, C.byref(opts), dust_packets,
-                                            n_max, tol, t_min, t_max, _ptr(t), C.byref(nd),
-                                            _ptr(crit)))
+        fn = lib().rt_ali_iterate if ali else lib().rt_lambda_iterate
+        self._check(fn(self.h, model, n, arr, C.byref(opts), dust_packets, n_max, tol, t_min, t_max,
+                       _ptr(t), C.byref(nd), _ptr(crit)))
         return t, int(nd.value), crit[: nd.value]
 
     def render_map(self, model: int, n_obs, npix: int, lambda_idx, width: float = 0.0,

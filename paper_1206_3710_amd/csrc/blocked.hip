@@ -118,6 +118,8 @@ __global__ __launch_bounds__(256) void blk_emit_kernel(const BlkParams b, const 
           (uint32_t)region_walk(b, D, k.lev, k.I[0], k.I[1], k.I[2], -1, 1, 0.5f, 0.5f, 0.5f);
     e_emit = k.w0;
     npk = 1;
+    if (p.emit_acc && J.kind == RT_SRC_DUST)
+      unsafeAtomicAdd(p.emit_acc + md.canon_base + canon_of(md, k.node), k.w0);
   }
   const uint64_t mask = __ballot(have);
   if (mask) {
@@ -248,6 +250,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   double O0 = 0.0, O1 = 0.0, O2 = 0.0;
   uint32_t pid = 0, ev = 0, ncross = 0, stream = 0;
   uint32_t br = 0;             // branch identifier (0: the package as emitted)
+  bool dust_lane = false;      // the packet comes from dust emission
+  const bool self_on = p.self_acc != nullptr;
   constexpr bool splitting = SPLIT;
   float ks = 0.f, ka = 0.f, g = 0.f;  // scattering / absorption opacity per root-cell length per unit density
   int esc_slot = 0;
@@ -278,6 +282,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           g = J.g32;
           stream = J.stream;
           esc_slot = J.esc_slot;
+          dust_lane = J.kind == RT_SRC_DUST;
           x0 = rec.x[0];
           x1 = rec.x[1];
           x2 = rec.x[2];
@@ -395,6 +400,10 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           deposit(node, de);
           w -= de;
         }
+        // accelerated Lambda iteration: what a dust-emission packet absorbs in its birth cell
+        // before it first leaves it
+        if (self_on && ncross == 1u && dust_lane && de > 0.0f)
+          unsafeAtomicAdd(p.self_acc + md.canon_base + b.rcanon[R.gbase + node], (double)de);
         x0 = clamp01(fmaf(s, d0, x0));
         x1 = clamp01(fmaf(s, d1, x1));
         x2 = clamp01(fmaf(s, d2, x2));

@@ -108,6 +108,10 @@ struct TraceParams {
   const int32_t* leaf_node;
   const int32_t* leaf_coord;
   const uint8_t* leaf_level;
+  // accelerated Lambda iteration: absorption of dust-emission packets in their birth cell
+  // before their first crossing, per canonical node (null when off)
+  double* self_acc;
+  double* emit_acc;          // energy emitted by dust-emission packets, per birth node
   // peel-off: scattering events of the current batch (null when off)
   PeelEv* peel_ev;
   unsigned long long* peel_count;
@@ -225,6 +229,8 @@ struct SweepState {
   unsigned long long log_in[16];  // records in the input of each sweep of the current block
 };
 
+hipError_t launch_ali_absorbed(int64_t n, const double* a_stars, const double* a_dust, const double* e_self,
+                               const double* e_emit, double* out, hipStream_t s);
 hipError_t launch_peel_tables(const TraceParams& p, const PeelParams& q, hipStream_t s);
 hipError_t launch_peel(const TraceParams& p, const PeelParams& q, int grid, hipStream_t s);
 hipError_t launch_blk_emit(const BlkParams& b, const SweepState* st, uint64_t batch, hipStream_t s);

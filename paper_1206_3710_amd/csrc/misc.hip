@@ -69,6 +69,19 @@ __global__ void add_kernel(int64_t n, const double* __restrict__ a, const double
   if (i < n) out[i] = a[i] + b[i];
 }
 
+// Absorbed power balanced by the accelerated Lambda iteration (Sect. 3.1, Eq. 3) with a
+// diagonal operator: lambda* = e_self / e_emit is the part of a cell's own emission it absorbs
+// on its packets' first visit; E(T)(1 - lambda*) = A_stars + A_dust - e_self.
+__global__ void ali_kernel(int64_t n, const double* __restrict__ a_stars, const double* __restrict__ a_dust,
+                           const double* __restrict__ e_self, const double* __restrict__ e_emit,
+                           double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double lam = e_emit[i] > 0.0 ? e_self[i] / e_emit[i] : 0.0;
+  lam = lam < 1.0 - 1e-9 ? lam : 1.0 - 1e-9;
+  out[i] = (a_stars[i] + a_dust[i] - e_self[i]) / (1.0 - lam);
+}
+
 // Mass-weighted mean relative temperature change over the leaves (Lambda-iteration stopping
 // statistic): accumulates sum m |Tn - To| / To and sum m.
 __global__ __launch_bounds__(256) void crit_kernel(const ModelDev* __restrict__ models, int model,
@@ -113,6 +126,13 @@ __global__ __launch_bounds__(256) void crit_kernel(const ModelDev* __restrict__ 
 }
 
 }  // namespace
+
+hipError_t launch_ali_absorbed(int64_t n, const double* a_stars, const double* a_dust, const double* e_self,
+                               const double* e_emit, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(ali_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a_stars, a_dust, e_self,
+                     e_emit, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_add(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {
   hipLaunchKernelGGL(add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a, b, out);

@@ -84,7 +84,7 @@ struct rt_ctx {
   DevBuf acc, esc, stats, counter, jobs, records, out_node, out_lamnode, out_esc, e_total;
   DevBuf cdf_lum, cdf_q, cdf_qpre, lmax, scan_tmp;
   DevBuf tmp_in, tmp_out, tmp_out2, view, lamidx;
-  DevBuf it_astars, it_adust, it_sum, it_told, it_crit;
+  DevBuf it_astars, it_adust, it_sum, it_told, it_crit, it_self, it_emit;
   // peel-off
   DevBuf peel_ev, peel_ctr, peel_tab, peel_roottab, peel_tabroot, peel_dnu, peel_img;
   // grid-by-grid schedule: region-major copy of the trees
@@ -835,6 +835,8 @@ struct TraceOut {
   double* e_lamnode = nullptr;   // device [total lamnodes] or null
   double* e_esc = nullptr;       // device [total lambdas]
   const PeelParams* peel = nullptr;  // peel-off after every batch (rt_peel_map)
+  double* self_acc = nullptr;        // accelerated Lambda iteration tallies (device, total nodes)
+  double* emit_acc = nullptr;
 };
 
 rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_trace_opts* o,
@@ -1030,6 +1032,8 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   p.leaf_node = ctx->d_leaf_node.as<int32_t>();
   p.leaf_coord = ctx->d_leaf_coord.as<int32_t>();
   p.leaf_level = ctx->d_leaf_level.as<uint8_t>();
+  p.self_acc = out.self_acc;
+  p.emit_acc = out.emit_acc;
   if (out.peel) {
     p.peel_ev = const_cast<PeelEv*>(out.peel->ev);
     p.peel_count = out.peel->count;
@@ -1348,12 +1352,14 @@ rt_status rt_solve_temperature(rt_ctx* ctx, int32_t model, const double* a_node,
   })
 }
 
-rt_status rt_lambda_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
-                            const rt_trace_opts* opts, int64_t dust_packets, int32_t n_max,
-                            double tol, double t_min, double t_max, double* t_node,
-                            int32_t* n_done, double* crit) {
+static rt_status lambda_iterate_impl(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
+                                     const rt_trace_opts* opts, int64_t dust_packets, int32_t n_max,
+                                     double tol, double t_min, double t_max, double* t_node,
+                                     int32_t* n_done, double* crit, bool ali) {
   if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
   GUARD({
+    if (ali && opts && opts->precision == RT_FP32_LOCAL && opts->schedule != RT_SCHED_REGIONS)
+      return fail(ctx, RT_EINVAL, "the accelerated iteration needs RT_FP64 or the region schedule");
     if (rt_status s = check_model(ctx, model)) return s;
     if (n_max < 0 || n_max > 100000) return fail(ctx, RT_EINVAL, "bad n_max");
     if (!(tol >= 0.0)) return fail(ctx, RT_EINVAL, "bad tol");
@@ -1375,6 +1381,10 @@ rt_status rt_lambda_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_
     HIPCHK(ctx->it_sum.ensure(8 * h.n_nodes));
     HIPCHK(ctx->it_told.ensure(8 * h.n_nodes));
     HIPCHK(ctx->it_crit.ensure(16));
+    if (ali) {
+      HIPCHK(ctx->it_self.ensure(8 * tn));
+      HIPCHK(ctx->it_emit.ensure(8 * tn));
+    }
     HIPCHK(ctx->out_esc.ensure(8 * std::max<int64_t>(tl, 1)));
     TraceOut out;
     out.e_esc = ctx->out_esc.as<double>();
@@ -1397,9 +1407,20 @@ rt_status rt_lambda_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_
       ds.packets_per_lambda = dust_packets;
       o.iteration = opts->iteration + (uint32_t)it;
       out.e_node = ctx->it_adust.as<double>();
+      if (ali) {
+        HIPCHK(hipMemsetAsync(ctx->it_self.p, 0, 8 * tn, ctx->stream));
+        HIPCHK(hipMemsetAsync(ctx->it_emit.p, 0, 8 * tn, ctx->stream));
+        out.self_acc = ctx->it_self.as<double>();
+        out.emit_acc = ctx->it_emit.as<double>();
+      }
       if (rt_status s = trace_impl(ctx, 1, &ds, &o, out, nullptr)) return s;
-      HIPCHK(launch_add(h.n_nodes, astars, ctx->it_adust.as<double>() + cb, ctx->it_sum.as<double>(),
-                        ctx->stream));
+      if (ali)
+        HIPCHK(launch_ali_absorbed(h.n_nodes, astars, ctx->it_adust.as<double>() + cb,
+                                   ctx->it_self.as<double>() + cb, ctx->it_emit.as<double>() + cb,
+                                   ctx->it_sum.as<double>(), ctx->stream));
+      else
+        HIPCHK(launch_add(h.n_nodes, astars, ctx->it_adust.as<double>() + cb, ctx->it_sum.as<double>(),
+                          ctx->stream));
       HIPCHK(hipMemcpyAsync(ctx->it_told.p, h.d_T.p, 8 * h.n_nodes, hipMemcpyDeviceToDevice, ctx->stream));
       if (rt_status s = solve_T_impl(ctx, model, ctx->it_sum.as<double>(), t_min, t_max)) return s;
       HIPCHK(hipMemsetAsync(ctx->it_crit.p, 0, 16, ctx->stream));
@@ -1422,6 +1443,21 @@ rt_status rt_lambda_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RT_OK;
   })
+}
+
+rt_status rt_lambda_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
+                            const rt_trace_opts* opts, int64_t dust_packets, int32_t n_max,
+                            double tol, double t_min, double t_max, double* t_node,
+                            int32_t* n_done, double* crit) {
+  return lambda_iterate_impl(ctx, model, n_src, src, opts, dust_packets, n_max, tol, t_min, t_max, t_node,
+                             n_done, crit, false);
+}
+
+rt_status rt_ali_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
+                         const rt_trace_opts* opts, int64_t dust_packets, int32_t n_max, double tol,
+                         double t_min, double t_max, double* t_node, int32_t* n_done, double* crit) {
+  return lambda_iterate_impl(ctx, model, n_src, src, opts, dust_packets, n_max, tol, t_min, t_max, t_node,
+                             n_done, crit, true);
 }
 
 rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32_t npix, double width,

@@ -26,6 +26,8 @@ __global__ __launch_bounds__(256) void trace_fp64_kernel(const TraceParams p, co
     double tau = k.tau;
     c_pk = 1;
     t_emit = w0;
+    if (p.emit_acc && job.kind == RT_SRC_DUST)
+      unsafeAtomicAdd(p.emit_acc + md.canon_base + canon_of(md, k.node), w0);
     const double kext = job.kext, alb = job.alb, g = job.g, cm = md.cell_cm;
     double* __restrict__ acc = p.acc64 + job.acc_off;
     uint32_t crossings = 1, ev = 0, status = 0;
@@ -63,6 +65,9 @@ __global__ __launch_bounds__(256) void trace_fp64_kernel(const TraceParams p, co
       if (sa > 0.0 && s > 0.0) {
         const double de = w * (-expm1(-(sa * s)));
         unsafeAtomicAdd(acc + k.node, de);
+        // accelerated Lambda iteration: absorption in the birth cell before the first crossing
+        if (p.self_acc && crossings == 1 && job.kind == RT_SRC_DUST)
+          unsafeAtomicAdd(p.self_acc + md.canon_base + canon_of(md, k.node), de);
         w = w - de;
       }
 #pragma unroll

@@ -1,0 +1,120 @@
+"""GPU parity of the accelerated Lambda iteration with a diagonal operator (paper Sect. 3.1,
+Eq. 3) against the oracle's: the FP64 form follows the oracle's histories, so the temperatures
+after each step agree to the solver's precision; the FP32-local region form agrees below the
+Monte Carlo noise; on an optically thick cube the GPU's accelerated iteration runs ahead of its
+plain one as the oracle's does."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from tests import brute
+
+pytestmark = pytest.mark.gpu
+
+rt = pytest.importorskip("paper_1206_3710_amd")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _small_case():
+    lam = np.logspace(-1, 3, 10)
+    kap = 3.0 * (lam / 0.55) ** -1.6
+    alb = np.clip(0.5 * (1 - np.log10(lam / 0.1) / 4), 0, 0.5)
+    dust = gen.Dust(lam, kap, alb, alb.copy())
+    tree = gen.uniform_refined_tree((4, 4, 4), 1, rho=1.0, cell_cm=1.0)
+    tree.child_rho[0] = tree.child_rho[0] * np.linspace(0.5, 1.5, len(tree.child_rho[0]))
+    nu = brute.CL / (lam * 1e-4)
+    star = [gen.Source(gen.SRC_POINT, 0, pos=(2.1, 1.9, 2.05), power=1e-2 * brute.planck_nu(nu, 5000.0),
+                       packets=4000)]
+    return tree, dust, star
+
+
+def _thick_case():
+    lam = np.logspace(0, 3, 12)
+    dust = gen.Dust(lam, 30.0 * lam ** -1.5, np.full(12, 0.1), np.zeros(12))
+    tree = gen.uniform_refined_tree((4, 4, 4), 1, rho=1.0, cell_cm=1.0)
+    nu = brute.CL / (lam * 1e-4)
+    star = [gen.Source(gen.SRC_POINT, 0, pos=(2.05, 1.95, 2.02), power=brute.planck_nu(nu, 3000.0),
+                       packets=6000)]
+    return tree, dust, star
+
+
+def _ctx(tree, dust):
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    return ctx, m
+
+
+def test_ali_fp64_against_oracle(torch):
+    """Three accelerated steps: temperatures within 1e-6 of the oracle's."""
+    tree, dust, star = _small_case()
+    ora = oracle.Model(tree, dust)
+    hist, _, _ = oracle.lambda_iterate(ora, star, seed=31, n_fixed=3, dust_packets=4000, ali=True)
+    plain, _, _ = oracle.lambda_iterate(ora, star, seed=31, n_fixed=3, dust_packets=4000)
+    ctx, m = _ctx(tree, dust)
+    tg, nd, _ = ctx.lambda_iterate(m, star, seed=31, dust_packets=4000, n_max=3, tol=0.0, ali=True)
+    ctx.close()
+    assert nd == 3
+    leaf = ora.leaf_mask
+    np.testing.assert_allclose(tg.cpu().numpy(), hist[-1], rtol=1e-6)
+    # the accelerated update changed something (the cells are not optically thin)
+    assert np.max(np.abs(hist[-1][leaf] - plain[-1][leaf]) / plain[-1][leaf]) > 1e-3
+
+
+def test_ali_fp32_regions_against_oracle(torch):
+    """Region schedule, three accelerated steps: the mass-weighted relative temperature
+    difference to the oracle is below that between two oracle runs with different seeds."""
+    tree, dust, star = _small_case()
+    ora = oracle.Model(tree, dust)
+    ha, _, _ = oracle.lambda_iterate(ora, star, seed=31, n_fixed=3, dust_packets=4000, ali=True)
+    hb, _, _ = oracle.lambda_iterate(ora, star, seed=77, n_fixed=3, dust_packets=4000, ali=True)
+    ctx, m = _ctx(tree, dust)
+    tg, _, _ = ctx.lambda_iterate(m, star, seed=31, dust_packets=4000, n_max=3, tol=0.0, ali=True,
+                                  precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS)
+    ctx.close()
+    leaf = ora.leaf_mask
+    lv = ora.level_of_nodes()
+    w = (ora.node_rho() * 8.0 ** -lv.astype(float))[leaf]
+
+    def diff(t, ref):
+        return float((w * np.abs(t[leaf] - ref[leaf]) / ref[leaf]).sum() / w.sum())
+    err = diff(tg.cpu().numpy(), ha[-1])
+    noise = diff(hb[-1], ha[-1])
+    assert err < 0.2 * noise, (err, noise)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ali_runs_ahead_on_thick_cube(torch, precision):
+    """Optically thick cube around a star, 8 steps each: the accelerated iteration's mean
+    temperature is more than 8 % above the plain one's (both rise toward the same
+    equilibrium)."""
+    tree, dust, star = _thick_case()
+    kw = dict(precision=rt.FP64) if precision == "fp64" else dict(precision=rt.FP32_LOCAL)
+    ctx, m = _ctx(tree, dust)
+    o = oracle.Model(tree, dust)
+    leaf = o.leaf_mask
+    mean = {}
+    for ali in (False, True):
+        t, _, _ = ctx.lambda_iterate(m, star, seed=5, dust_packets=6000, n_max=8, tol=0.0, ali=ali, **kw)
+        mean[ali] = float(np.mean(t.cpu().numpy()[leaf]))
+    ctx.close()
+    assert mean[True] > 1.08 * mean[False], mean
+
+
+def test_ali_rejects_the_global_schedule(torch):
+    tree, dust, star = _small_case()
+    ctx, m = _ctx(tree, dust)
+    with pytest.raises(rt.RTError):
+        ctx.lambda_iterate(m, star, seed=1, dust_packets=100, n_max=1, ali=True,
+                           precision=rt.FP32_LOCAL, schedule=rt.SCHED_GLOBAL)
+    t, nd, _ = ctx.lambda_iterate(m, star, seed=1, dust_packets=100, n_max=1, ali=True)
+    assert nd == 1 and float(t.max()) > 0
+    ctx.close()
