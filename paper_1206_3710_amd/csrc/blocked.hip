@@ -212,8 +212,9 @@ __device__ __forceinline__ void land(WF word_of, int ax, int sg, int L, int32_t 
 // region is in LDS (pure LDS lookups and deposits); otherwise nodes past the LDS capacity are
 // read and deposited in global memory.  SPLIT: package splitting is on (split_n > 1); the
 // unsplit instance carries none of its state or code.  PEEL: scattering events are kept for
-// the peel-off.
-template <bool FITS, bool SPLIT, bool PEEL>
+// the peel-off.  ALI: the self-absorption of dust-emission packets is tallied for the
+// accelerated Lambda iteration.
+template <bool FITS, bool SPLIT, bool PEEL, bool ALI>
 __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it, const RegionDev& R,
                                          const ModelDev& md, const Dims D, int nloc, int nup,
                                          int32_t* s_word, float* s_acc, int32_t* s_up, uint32_t* s_next,
@@ -251,7 +252,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   uint32_t pid = 0, ev = 0, ncross = 0, stream = 0;
   uint32_t br = 0;             // branch identifier (0: the package as emitted)
   bool dust_lane = false;      // the packet comes from dust emission
-  const bool self_on = p.self_acc != nullptr;
+  constexpr bool self_on = ALI;
   constexpr bool splitting = SPLIT;
   float ks = 0.f, ka = 0.f, g = 0.f;  // scattering / absorption opacity per root-cell length per unit density
   int esc_slot = 0;
@@ -706,7 +707,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   }
 }
 
-template <int BS, bool SPLIT, bool PEEL>
+template <int BS, bool SPLIT, bool PEEL, bool ALI>
 __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int cap = b.cap;
@@ -746,10 +747,10 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     if (tid == 0) s_next = 0;
     __syncthreads();
     if (R.n <= cap)
-      run_item<true, SPLIT, PEEL>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
+      run_item<true, SPLIT, PEEL, ALI>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
                      c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip);
     else
-      run_item<false, SPLIT, PEEL>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
+      run_item<false, SPLIT, PEEL, ALI>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
                       c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip);
     __syncthreads();
     if (b.accb64) {
@@ -847,20 +848,23 @@ hipError_t launch_blk_emit(const BlkParams& b, const SweepState* st, uint64_t ba
   return hipGetLastError();
 }
 
-template <bool SPLIT, bool PEEL>
+// Instances: any combination of splitting and peel-off, and the accelerated-iteration tally
+// with or without splitting (the peel-off never runs inside a Lambda iteration).
+template <bool SPLIT, bool PEEL, bool ALI>
 static const void* pass_fn(int block) {
   switch (block) {
-    case 256: return (const void*)blk_pass_kernel<256, SPLIT, PEEL>;
-    case 512: return (const void*)blk_pass_kernel<512, SPLIT, PEEL>;
-    case 768: return (const void*)blk_pass_kernel<768, SPLIT, PEEL>;
-    case 1024: return (const void*)blk_pass_kernel<1024, SPLIT, PEEL>;
+    case 256: return (const void*)blk_pass_kernel<256, SPLIT, PEEL, ALI>;
+    case 512: return (const void*)blk_pass_kernel<512, SPLIT, PEEL, ALI>;
+    case 768: return (const void*)blk_pass_kernel<768, SPLIT, PEEL, ALI>;
+    case 1024: return (const void*)blk_pass_kernel<1024, SPLIT, PEEL, ALI>;
     default: return nullptr;
   }
 }
 
 hipError_t attr_blk_pass(int block, int lds_bytes) {
-  for (const void* f : {pass_fn<false, false>(block), pass_fn<true, false>(block), pass_fn<false, true>(block),
-                        pass_fn<true, true>(block)}) {
+  for (const void* f : {pass_fn<false, false, false>(block), pass_fn<true, false, false>(block),
+                        pass_fn<false, true, false>(block), pass_fn<true, true, false>(block),
+                        pass_fn<false, false, true>(block), pass_fn<true, false, true>(block)}) {
     if (!f) return hipErrorInvalidValue;
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
@@ -868,24 +872,29 @@ hipError_t attr_blk_pass(int block, int lds_bytes) {
   return hipSuccess;
 }
 
-template <bool SPLIT, bool PEEL>
+template <bool SPLIT, bool PEEL, bool ALI>
 static hipError_t launch_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s) {
   switch (block) {
-    case 256: hipLaunchKernelGGL((blk_pass_kernel<256, SPLIT, PEEL>), dim3(grid), dim3(256), lds_bytes, s, b); break;
-    case 512: hipLaunchKernelGGL((blk_pass_kernel<512, SPLIT, PEEL>), dim3(grid), dim3(512), lds_bytes, s, b); break;
-    case 768: hipLaunchKernelGGL((blk_pass_kernel<768, SPLIT, PEEL>), dim3(grid), dim3(768), lds_bytes, s, b); break;
-    case 1024: hipLaunchKernelGGL((blk_pass_kernel<1024, SPLIT, PEEL>), dim3(grid), dim3(1024), lds_bytes, s, b); break;
+    case 256: hipLaunchKernelGGL((blk_pass_kernel<256, SPLIT, PEEL, ALI>), dim3(grid), dim3(256), lds_bytes, s, b); break;
+    case 512: hipLaunchKernelGGL((blk_pass_kernel<512, SPLIT, PEEL, ALI>), dim3(grid), dim3(512), lds_bytes, s, b); break;
+    case 768: hipLaunchKernelGGL((blk_pass_kernel<768, SPLIT, PEEL, ALI>), dim3(grid), dim3(768), lds_bytes, s, b); break;
+    case 1024: hipLaunchKernelGGL((blk_pass_kernel<1024, SPLIT, PEEL, ALI>), dim3(grid), dim3(1024), lds_bytes, s, b); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s) {
-  const bool split = b.t.split_n > 1, peel = b.t.peel_ev != nullptr;
-  if (split) return peel ? launch_pass<true, true>(b, grid, block, lds_bytes, s)
-                         : launch_pass<true, false>(b, grid, block, lds_bytes, s);
-  return peel ? launch_pass<false, true>(b, grid, block, lds_bytes, s)
-              : launch_pass<false, false>(b, grid, block, lds_bytes, s);
+  const bool split = b.t.split_n > 1, peel = b.t.peel_ev != nullptr, ali = b.t.self_acc != nullptr;
+  if (ali) {
+    if (peel) return hipErrorInvalidValue;
+    return split ? launch_pass<true, false, true>(b, grid, block, lds_bytes, s)
+                 : launch_pass<false, false, true>(b, grid, block, lds_bytes, s);
+  }
+  if (split) return peel ? launch_pass<true, true, false>(b, grid, block, lds_bytes, s)
+                         : launch_pass<true, false, false>(b, grid, block, lds_bytes, s);
+  return peel ? launch_pass<false, true, false>(b, grid, block, lds_bytes, s)
+              : launch_pass<false, false, false>(b, grid, block, lds_bytes, s);
 }
 
 hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, int n_regions,
