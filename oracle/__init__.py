@@ -74,7 +74,8 @@ def lib():
         L.om_trace.restype = C.c_int
         L.om_trace.argtypes = [P, C.c_int32, C.c_int32, P, P, P, P, P, P, C.c_uint64, C.c_uint32,
                                C.c_double, C.c_double, C.c_int64, C.c_int32, C.c_int64, C.c_int64,
-                               C.c_int32, P, P, P, C.c_int64, P, C.c_int32, P, P, P]
+                               C.c_int32, P, P, P, C.c_int64, P, C.c_int32, P, P, P, P, C.c_int64]
+        L.om_node_coords.argtypes = [P, P]
         L.om_emission_all.argtypes = [P, P, P]
         L.om_hg_phase.restype = C.c_double
         L.om_hg_phase.argtypes = [C.c_double, C.c_double]
@@ -193,12 +194,15 @@ class Model:
 
     def trace(self, sources, seed, iteration=0, model_index=0, rr_threshold=0.0, rr_prob=0.0,
               max_events=0, per_lambda=False, pid_begin=0, pid_end=-1, lam_sel=-1,
-              t_node=None, rec_stride=0, deposits=True, split_n=1, peel=None, self_absorption=False):
+              t_node=None, rec_stride=0, deposits=True, split_n=1, peel=None, self_absorption=False,
+              level_arrays=False, subtree=-1):
         """Follow packets of ``sources`` (gen.Source list) -> (e_abs, e_esc, stats, records).
         ``peel``: dict(n_obs=[[x, y, z], ...], npix=, width=0.0, tiles=0) turns on the peel-off
         images, returned in stats["peel_image"] as [n_dir, n_lambda, npix, npix].
         ``self_absorption``: stats["e_self"] and stats["e_emit_node"] per node (the diagonal
-        part of the accelerated Lambda iteration)."""
+        part of the accelerated Lambda iteration).  ``level_arrays``: stats["e_lvl"]
+        [n_levels + 1, n_nodes], the deposits by the shallowest level visited; ``subtree``: a
+        refined node whose subtree alone emits and holds the packages (subiterations)."""
         L = lib()
         ns = len(sources)
         nl = self.n_lambda
@@ -219,6 +223,7 @@ class Model:
         if rec_stride > 0:
             nrec = (pid_end - pid_begin + rec_stride - 1) // rec_stride
             rec = np.zeros(ns * nl * nrec, dtype=RECORD_DTYPE)
+        e_lvl = np.zeros((self.n_levels + 1) * self.n_nodes) if level_arrays else None
         e_self = np.zeros(self.n_nodes) if self_absorption else None
         e_emit_node = np.zeros(self.n_nodes) if self_absorption else None
         po, img = None, None
@@ -236,16 +241,19 @@ class Model:
                         rec_stride, None if rec is None else _p(rec), split_n,
                         None if po is None else C.byref(po),
                         None if e_self is None else _p(e_self),
-                        None if e_emit_node is None else _p(e_emit_node))
+                        None if e_emit_node is None else _p(e_emit_node),
+                        None if e_lvl is None else _p(e_lvl), int(subtree))
         if rc != 0:
             raise OracleError(L.om_error().decode())
-        if img is not None or e_self is not None:
+        if img is not None or e_self is not None or e_lvl is not None:
             out = st.as_dict()
             if img is not None:
                 out["peel_image"] = img
             if e_self is not None:
                 out["e_self"] = e_self
                 out["e_emit_node"] = e_emit_node
+            if e_lvl is not None:
+                out["e_lvl"] = e_lvl.reshape(self.n_levels + 1, self.n_nodes)
             if per_lambda and e_abs is not None:
                 e_abs = e_abs.reshape(nl, self.n_nodes)
             return e_abs, e_esc, out, rec
@@ -260,6 +268,22 @@ class Model:
         col = np.zeros(len(x))
         lib().om_peel_column(self.h, _p(nv), int(tiles), len(x), _p(x), _p(col))
         return col
+
+    def node_coords(self):
+        """Integer coordinates of every node at its own level, [n_nodes, 3]."""
+        out = np.zeros(3 * self.n_nodes, dtype=np.int32)
+        lib().om_node_coords(self.h, _p(out))
+        return out.reshape(-1, 3)
+
+    def subtree_mask(self, root):
+        """Nodes of the subtree below refined node ``root`` (all nodes for -1)."""
+        if root < 0:
+            return np.ones(self.n_nodes, dtype=bool)
+        lv = self.level_of_nodes()
+        xyz = self.node_coords().astype(np.int64)
+        lr, cr = int(lv[root]), xyz[root]
+        sh = np.maximum(lv - lr, 0)[:, None]
+        return (lv > lr) & np.all((xyz >> sh) == cr[None, :], axis=1)
 
     def emission_all(self, t_node):
         """Emitted power of every leaf at temperatures t_node (0 for refined nodes)."""
@@ -331,6 +355,37 @@ def ali_step_absorbed(a_stars, a_dust, e_self, e_emit_node):
     lam = np.where(e_emit_node > 0.0, e_self / np.where(e_emit_node > 0.0, e_emit_node, 1.0), 0.0)
     lam = np.minimum(lam, 1.0 - 1e-9)
     return (a_stars + a_dust - e_self) / (1.0 - lam)
+
+
+def subiterate(model, star_sources, seed, schedule, dust_packets, rr_threshold=0.0, rr_prob=0.0,
+               t_min=2.0, t_max=3000.0):
+    """Lambda iteration with subiterations on complete subtrees (paper Sect. 3.1 and App. B).
+    ``schedule``: the subtree root of each step, a refined node or -1 for the whole model.  Each
+    cell keeps one absorbed-energy array per hierarchy level above or at its own; a step with
+    root r (level l_r) traces the dust emission of r's subtree only, keeps its packages inside
+    it, and replaces the arrays of levels > l_r (all levels for the whole model) of the cells in
+    the subtree with what it deposits; the temperatures of those cells then follow from
+    A_stars + the sum of their arrays (Eq. 9).  Key iteration of step k is k.  Returns
+    (temperature after each step, A_stars, per-step trace statistics)."""
+    import gen
+    a_stars, _, _, _ = model.trace(star_sources, seed, iteration=0, rr_threshold=rr_threshold,
+                                   rr_prob=rr_prob)
+    t = model.solve_temperature(a_stars, t_min, t_max)
+    lv = model.level_of_nodes()
+    arrays = np.zeros((model.n_levels + 1, model.n_nodes))
+    hist, stats = [t.copy()], []
+    for it, root in enumerate(schedule, start=1):
+        lo = 0 if root < 0 else int(lv[root]) + 1
+        mask = model.subtree_mask(root)
+        src = [gen.Source(gen.SRC_DUST, 0, packets=dust_packets)]
+        _, _, st, _ = model.trace(src, seed, iteration=it, rr_threshold=rr_threshold,
+                                  rr_prob=rr_prob, t_node=t, level_arrays=True, subtree=root)
+        stats.append(st)
+        arrays[lo:, mask] = st["e_lvl"][lo:, mask]
+        t_new = model.solve_temperature(a_stars + arrays.sum(axis=0), t_min, t_max)
+        t = np.where(mask, t_new, t)
+        hist.append(t.copy())
+    return hist, a_stars, stats
 
 
 def lambda_iterate(model, star_sources, seed, n_max=30, tol=1e-3, n_fixed=None,

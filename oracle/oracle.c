@@ -361,6 +361,7 @@ typedef struct {
   int lev;
   uint32_t k, crossings;
   uint32_t br;              /* branch of the package (0: the emitted package and its main line) */
+  int mlev;                 /* shallowest hierarchy level visited (subiterations, App. B) */
 } packet;
 
 /* Peel-off state (Sect. 2.4): observer frames, image geometry, extinction tables. */
@@ -397,6 +398,12 @@ typedef struct {
                                first crossing (the diagonal operator's part) */
   double* e_emit_node;      /* energy emitted by dust-emission packets, per birth cell */
   int dust;                 /* the current source is dust emission */
+  /* subiterations (Sect. 3.1, App. B) */
+  double* e_lvl;            /* [n_levels + 1][n_nodes]: deposits by the shallowest level the
+                               package visited; NULL when off */
+  int64_t sub_node;         /* refined cell whose subtree is iterated; -1: the whole model */
+  int sub_lev;
+  int64_t sub_I[3];
 } tctx;
 
 /* Branch identifier of child c of branch b split at the package's crossing number n: the
@@ -634,6 +641,13 @@ static void peel_event(const tctx* c, const packet* p, double g) {
   }
 }
 
+/* Is the cell (lev, I) inside the subtree of the refined cell (sub_lev, sub_I)? */
+static int in_subtree(const tctx* c, int lev, const int64_t I[3]) {
+  if (lev <= c->sub_lev) return 0;
+  const int sh = lev - c->sub_lev;
+  return (I[0] >> sh) == c->sub_I[0] && (I[1] >> sh) == c->sub_I[1] && (I[2] >> sh) == c->sub_I[2];
+}
+
 /* Result codes of a propagation */
 enum { PK_ESCAPED = 0, PK_KILLED = 1, PK_TRUNC = 2, PK_SPLITKILL = 3 };
 
@@ -669,6 +683,7 @@ static int propagate(tctx* c, packet* p) {
       if (c->e_abs) c->e_abs[p->node] += de;
       else c->e_abs_total += de;
       if (c->e_self && c->dust && p->crossings == 1) c->e_self[p->node] += de;
+      if (c->e_lvl) c->e_lvl[(int64_t)p->mlev * m->nnodes + p->node] += de;
       p->w = p->w - de;
     }
     for (int b = 0; b < 3; ++b) p->P[b] = fma(s, p->d[b], p->P[b]);
@@ -710,6 +725,12 @@ static int propagate(tctx* c, packet* p) {
       c->e_esc[c->lam] += p->w;
       return PK_ESCAPED;
     }
+    if (c->sub_node >= 0 && !in_subtree(c, p->lev, p->I)) {
+      /* a subiteration follows packets only inside its subtree */
+      c->e_esc[c->lam] += p->w;
+      return PK_ESCAPED;
+    }
+    if (p->lev < p->mlev) p->mlev = p->lev;
     p->crossings += 1;
     if (c->split_n > 1 && p->lev > old_lev) {
       /* entering a subgrid: split_n packages of equal weight; this one continues, the others
@@ -764,7 +785,7 @@ typedef struct {
   double dropped;
 } dust_cdf;
 
-static void dust_cdf_build(const om_model* m, const double* t_node, int lam, dust_cdf* d) {
+static void dust_cdf_build(const om_model* m, const tctx* c, const double* t_node, int lam, dust_cdf* d) {
   int64_t nl = 0;
   for (int64_t i = 0; i < m->nnodes; ++i) nl += m->child[i] < 0;
   d->nleaf = nl;
@@ -778,6 +799,10 @@ static void dust_cdf_build(const om_model* m, const double* t_node, int lam, dus
   for (int64_t i = 0; i < m->nnodes; ++i) {
     if (m->child[i] >= 0) continue;
     double l = 4.0 * OM_PI * cell_mass(m, i) * kabs * planck(m->nu[lam], t_node[i]) * m->dnu[lam];
+    if (c && c->sub_node >= 0) {
+      int64_t I[3] = {m->coord[3 * i], m->coord[3 * i + 1], m->coord[3 * i + 2]};
+      if (!in_subtree(c, m->level[i], I)) l = 0.0;  /* only the subtree's cells emit */
+    }
     d->leaf[j] = i;
     d->lum[j] = l;
     if (l > lmax) lmax = l;
@@ -815,7 +840,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
              double rr_prob, int64_t max_events, int32_t per_lambda, int64_t pid_begin,
              int64_t pid_end, int32_t lam_sel, double* e_abs, double* e_esc, om_stats* stats,
              int64_t rec_stride, om_record* rec, int32_t split_n, const om_peel_opts* peel,
-             double* e_self, double* e_emit_node) {
+             double* e_self, double* e_emit_node, double* e_lvl, int64_t sub_node) {
   if (m->nl < 1) { seterr("dust not set"); return -1; }
   if (split_n < 1 || split_n > 64) { seterr("split factor must be in [1, 64]"); return -1; }
   if (peel && (peel->n_dir < 1 || peel->n_dir > OM_MAXDIR || peel->npix < 1 || peel->tiles < 0 ||
@@ -863,6 +888,18 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
   c.e_self = e_self;
   c.e_emit_node = e_emit_node;
   c.dust = 0;
+  c.e_lvl = e_lvl;
+  c.sub_node = sub_node;
+  c.sub_lev = 0;
+  c.sub_I[0] = c.sub_I[1] = c.sub_I[2] = 0;
+  if (sub_node >= 0) {
+    if (sub_node >= m->nnodes || m->child[sub_node] < 0) {
+      seterr("the subtree root must be a refined node");
+      return -1;
+    }
+    c.sub_lev = m->level[sub_node];
+    for (int a = 0; a < 3; ++a) c.sub_I[a] = m->coord[3 * sub_node + a];
+  }
   peel_ctx pc;
   memset(&pc, 0, sizeof pc);
   if (peel) {
@@ -910,7 +947,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
       } else if (kind[s] == OM_POINT || kind[s] == OM_BEAM) {
         w0 = power[(int64_t)s * nl + lam] * m->dnu[lam] / (double)N;
       } else {
-        dust_cdf_build(m, t_node, lam, &dc);
+        dust_cdf_build(m, &c, t_node, lam, &dc);
         if (dc.qtot == 0) { dust_cdf_free(&dc); continue; }
       }
       for (int64_t j = jb; j < je; ++j) {
@@ -974,6 +1011,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
           p.w0 = dc.lum[k] * ((double)dc.qtot / ((double)dc.q[k] * (double)N));
         }
         p.w = p.w0;
+        p.mlev = kind[s] == OM_BACKGROUND ? 0 : p.lev;  /* external packets enter through the root grid */
         int64_t birth = p.node;
         stats->packets += 1;
         stats->e_emit += p.w0;
@@ -1150,6 +1188,10 @@ int om_render(const om_model* m, const double n_obs[3], int32_t npix, double wid
 double om_hg_mu(double g, double u) { return hg_mu(g, u); }
 
 double om_hg_phase(double g, double mu) { return hg_phase(g, mu); }
+
+void om_node_coords(const om_model* m, int32_t* out) {
+  for (int64_t i = 0; i < 3 * m->nnodes; ++i) out[i] = m->coord[i];
+}
 
 void om_emission_all(const om_model* m, const double* t_node, double* out) {
   for (int64_t i = 0; i < m->nnodes; ++i) out[i] = m->child[i] < 0 ? om_emission(m, i, t_node[i]) : 0.0;

@@ -111,11 +111,19 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
              double rr_threshold, double rr_prob, int64_t max_events, int32_t per_lambda,
              int64_t pid_begin, int64_t pid_end, int32_t lam_sel,
              double* e_abs, double* e_esc, om_stats* stats, int64_t rec_stride, om_record* rec,
-             int32_t split_n, const om_peel_opts* peel, double* e_self, double* e_emit_node);
+             int32_t split_n, const om_peel_opts* peel, double* e_self, double* e_emit_node,
+             double* e_lvl, int64_t sub_node);
 
 /* e_self, e_emit_node ([n_nodes], added to; NULL = off): for the accelerated Lambda iteration
  * (Sect. 3.1 Eq. 3, diagonal operator), the energy that dust-emission packets deposit in their
  * birth cell before their first crossing, and the energy they start with, per birth cell. */
+
+/* Subiterations (Sect. 3.1, App. B).  e_lvl ([n_levels + 1][n_nodes], added to; NULL = off):
+ * every deposit also goes to the array of the shallowest hierarchy level the package has
+ * visited (0 for the external field, which enters through the root grid; otherwise the birth
+ * level, lowered at every crossing into a shallower cell).  sub_node >= 0 (a refined node):
+ * only the leaves of its subtree emit dust, and a package leaving the subtree is ended there
+ * (tallied as escaped). */
 
 /* Equilibrium temperature per leaf: 4 pi m sum_i kappa_abs_i B_i(T) dnu_i = A. */
 void om_solve_temperature(const om_model* m, const double* a_node, double t_min, double t_max,
@@ -137,6 +145,8 @@ uint32_t om_branch_id(uint32_t b, uint32_t n, uint32_t c);
 double om_hg_phase(double g, double mu);
 /* Emitted power of every leaf at t_node (0 for refined nodes). */
 void om_emission_all(const om_model* m, const double* t_node, double* out);
+/* Integer coordinates of every node at its own level: out[3 n_nodes]. */
+void om_node_coords(const om_model* m, int32_t* out);
 /* Peel-off column (density x length, root-cell units) from each point toward n_obs, marched
  * to the border (tiles = 0) or with the extinction tables. */
 int om_peel_column(const om_model* m, const double n_obs[3], int32_t tiles, int64_t npts,
