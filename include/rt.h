@@ -12,6 +12,7 @@
  *   rt_lambda_iterate     the Lambda iteration of Sect. 3.1 Eq. (2) with the constant-source
  *                         field kept (Sect. 3.2);
  *   rt_ali_iterate        the same with the accelerated iteration (Sect. 3.1 Eq. 3);
+ *   rt_subiter_*          subiterations on complete subtrees (Sect. 3.1, 3.3, App. B);
  *   rt_render_map         surface-brightness maps toward chosen directions (Sect. 4.1);
  *   rt_peel_map           images of the scattered light by peel-off, with precomputed
  *                         extinction tables (Sect. 2.4).
@@ -244,6 +245,30 @@ rt_status rt_lambda_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_
 rt_status rt_ali_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
                          const rt_trace_opts* opts, int64_t dust_packets, int32_t n_max, double tol,
                          double t_min, double t_max, double* t_node, int32_t* n_done, double* crit);
+
+/* Subiterations on complete subtrees (Sect. 3.1, Sect. 3.3, App. B), RT_FP64 form.
+ * rt_subiter_begin traces the constant sources (key iteration opts->iteration) into A_stars,
+ * solves T_0 and clears the model's per-level arrays (one absorbed-energy array per hierarchy
+ * level at or above each cell's own).
+ * rt_subiter_step takes one step with the subtree below `root`, a refined canonical node of
+ * the model, or the whole model (root = -1): the dust emission of the subtree's leaves at the
+ * current temperatures is traced with key `iteration`; every deposit is filed under the
+ * shallowest level its package has visited (0 for the external field), and a package leaving
+ * the subtree is ended there.  The arrays of levels below the root's of the subtree's leaves
+ * are replaced by the new deposits, each subtree leaf's energy imbalance |A - E(T_old)| /
+ * E(T_old) is recorded, and the temperatures follow from A_stars plus the sum of each leaf's
+ * arrays (Eq. 9).  crit (may be NULL): mass-weighted mean |T_new - T_old| / T_old over all
+ * leaves; t_node (host or device, may be NULL): the temperatures after the step.
+ * rt_subiter_select picks the next subtree (Sect. 3.3): the lowest common ancestor of every
+ * leaf whose last recorded imbalance is within frac of the largest; root = -1 when that is the
+ * whole model.  max_imbalance (may be NULL) receives the largest. */
+rt_status rt_subiter_begin(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
+                           const rt_trace_opts* opts, double t_min, double t_max);
+rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust_packets,
+                          uint32_t iteration, const rt_trace_opts* opts, double* crit,
+                          double* t_node, rt_trace_stats* stats);
+rt_status rt_subiter_select(rt_ctx* ctx, int32_t model, double frac, int64_t* root,
+                            double* max_imbalance);
 
 /* Surface-brightness map (Sect. 4.1) of a model with its current temperatures: orthographic
  * view toward the observer direction n_obs; pixel (i, j) centre = box centre +

@@ -24,7 +24,8 @@ SCHED_REGIONS, SCHED_GLOBAL = 0, 1
 
 EXPORTS = ["rt_last_error", "rt_create", "rt_destroy", "rt_build_tree", "rt_get_model_info",
            "rt_get_sizes", "rt_locate", "rt_set_dust", "rt_set_temperature", "rt_trace_packets",
-           "rt_solve_temperature", "rt_lambda_iterate", "rt_ali_iterate", "rt_render_map", "rt_peel_map",
+           "rt_solve_temperature", "rt_lambda_iterate", "rt_ali_iterate", "rt_subiter_begin",
+           "rt_subiter_step", "rt_subiter_select", "rt_render_map", "rt_peel_map",
            "rt_autotune", "rt_philox"]
 
 
@@ -112,6 +113,9 @@ def lib():
             "rt_solve_temperature": (I32, [P, I32, P, D, D, P]),
             "rt_lambda_iterate": (I32, [P, I32, I32, P, P, I64, I32, D, D, D, P, P, P]),
             "rt_ali_iterate": (I32, [P, I32, I32, P, P, I64, I32, D, D, D, P, P, P]),
+            "rt_subiter_begin": (I32, [P, I32, I32, P, P, D, D]),
+            "rt_subiter_step": (I32, [P, I32, I64, I64, U32, P, P, P, P]),
+            "rt_subiter_select": (I32, [P, I32, D, P, P]),
             "rt_render_map": (I32, [P, I32, P, I32, D, I32, P, I32, P, P]),
             "rt_peel_map": (I32, [P, I32, P, P, P, P]),
             "rt_autotune": (I32, [P, I32, P, P, D, C.c_char_p, P, P]),
@@ -372,6 +376,34 @@ class Context:
         self._check(fn(self.h, model, n, arr, C.byref(opts), dust_packets, n_max, tol, t_min, t_max,
                        _ptr(t), C.byref(nd), _ptr(crit)))
         return t, int(nd.value), crit[: nd.value]
+
+    def subiter_begin(self, model: int, sources: Sequence, seed: int, t_min: float = 2.0,
+                      t_max: float = 3000.0, iteration: int = 0, rr_threshold: float = 0.0,
+                      rr_prob: float = 0.0):
+        """Subiterations (FP64 form): trace the constant sources, T_0, clear the level arrays."""
+        arr, keep = _source_array(sources) if sources else ((Source * 1)(), [])
+        opts = TraceOpts(seed, iteration, FP64, rr_threshold, rr_prob)
+        self._check(lib().rt_subiter_begin(self.h, model, len(sources), arr, C.byref(opts), t_min, t_max))
+
+    def subiter_step(self, model: int, root: int, dust_packets: int, seed: int, iteration: int,
+                     rr_threshold: float = 0.0, rr_prob: float = 0.0):
+        """One (sub)iteration step below refined node ``root`` (-1: the whole model).
+        Returns (temperatures, stopping statistic, trace statistics)."""
+        torch = _torch()
+        opts = TraceOpts(seed, 0, FP64, rr_threshold, rr_prob)
+        t = torch.empty(self.models[model], dtype=torch.float64, device=self.tdev)
+        crit = C.c_double()
+        st = TraceStats()
+        self._check(lib().rt_subiter_step(self.h, model, int(root), int(dust_packets), int(iteration),
+                                          C.byref(opts), C.byref(crit), _ptr(t), C.byref(st)))
+        return t, float(crit.value), st.as_dict()
+
+    def subiter_select(self, model: int, frac: float = 0.25):
+        """Next subtree root from the recorded energy imbalance: (root, largest imbalance)."""
+        root = C.c_int64()
+        mx = C.c_double()
+        self._check(lib().rt_subiter_select(self.h, model, frac, C.byref(root), C.byref(mx)))
+        return int(root.value), float(mx.value)
 
     def render_map(self, model: int, n_obs, npix: int, lambda_idx, width: float = 0.0,
                    precision: int = FP64):

@@ -112,6 +112,13 @@ struct TraceParams {
   // before their first crossing, per canonical node (null when off)
   double* self_acc;
   double* emit_acc;          // energy emitted by dust-emission packets, per birth node
+  // subiterations: every deposit also goes to the array of the shallowest level the packet
+  // visited, lvl_acc[level * lvl_stride + canonical output index]; sub_lev >= 0 confines the
+  // packets to the subtree below the refined cell (sub_lev, sub_I)
+  double* lvl_acc;
+  int64_t lvl_stride;
+  int32_t sub_lev;
+  int32_t sub_I[3];
   // peel-off: scattering events of the current batch (null when off)
   PeelEv* peel_ev;
   unsigned long long* peel_count;
@@ -229,6 +236,14 @@ struct SweepState {
   unsigned long long log_in[16];  // records in the input of each sweep of the current block
 };
 
+// Is the cell (lev, I) inside the subtree below the refined cell (sub_lev, sub_I)?
+__host__ __device__ inline bool in_subtree(int sub_lev, const int32_t sub_I[3], int lev, int32_t I0, int32_t I1,
+                                           int32_t I2) {
+  if (lev <= sub_lev) return false;
+  const int sh = lev - sub_lev;
+  return (I0 >> sh) == sub_I[0] && (I1 >> sh) == sub_I[1] && (I2 >> sh) == sub_I[2];
+}
+
 hipError_t launch_ali_absorbed(int64_t n, const double* a_stars, const double* a_dust, const double* e_self,
                                const double* e_emit, double* out, hipStream_t s);
 hipError_t launch_peel_tables(const TraceParams& p, const PeelParams& q, hipStream_t s);
@@ -277,7 +292,13 @@ hipError_t launch_temperature(const ModelDev* models, int model, int64_t n_nodes
 hipError_t launch_dust_lum(const ModelDev* models, int model, int64_t n_leaves,
                            const int32_t* leaf_node, const uint8_t* leaf_level,
                            const double* rho64, const double* t_node, const LamConst* lc, int lam,
-                           double* lum, unsigned long long* lmax_bits, hipStream_t s);
+                           double* lum, unsigned long long* lmax_bits, const int32_t* leaf_coord,
+                           int sub_lev, const int32_t sub_I[3], hipStream_t s);
+hipError_t launch_subiter_update(const ModelDev* models, int model, int64_t n_leaves, const int32_t* leaf_node,
+                                 const uint8_t* leaf_level, const int32_t* leaf_coord, const double* rho64,
+                                 const LamConst* lc, int nl, int sub_lev, const int32_t sub_I[3], int lo,
+                                 const double* lvl_new, int64_t lvl_stride, double* arrays, const double* a_stars,
+                                 const double* t_old, double* a_tot, double* imb, hipStream_t s);
 hipError_t launch_dust_quant(int64_t n_leaves, const double* lum,
                              const unsigned long long* lmax_bits, uint64_t* q, hipStream_t s);
 hipError_t launch_render(bool f32, const ModelDev* models, int model, const int32_t* child,

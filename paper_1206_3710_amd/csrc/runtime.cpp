@@ -61,6 +61,10 @@ struct HostModel {
   DevBuf d_lc;
   DevBuf d_T;
   bool has_T = false;
+  // subiterations (App. B): constant-source absorption, per-level arrays, last imbalance
+  DevBuf sub_astars, sub_arrays, sub_imb;
+  double sub_tmin = 0.0, sub_tmax = 0.0;
+  bool sub_ready = false;
 };
 
 }  // namespace
@@ -805,7 +809,8 @@ namespace {
 
 // Dust-emission tables of one (model, wavelength): luminosity, 32-bit quantised share of the
 // maximum and its exact 64-bit exclusive prefix sum; returns the total.
-rt_status build_dust_cdf(rt_ctx* ctx, int32_t model, int lam, int64_t off, uint64_t* qtot) {
+rt_status build_dust_cdf(rt_ctx* ctx, int32_t model, int lam, int64_t off, uint64_t* qtot, int sub_lev,
+                         const int32_t sub_I[3]) {
   HostModel& h = ctx->models[model];
   const int64_t n = h.n_leaves;
   double* lum = ctx->cdf_lum.as<double>() + off;
@@ -816,7 +821,8 @@ rt_status build_dust_cdf(rt_ctx* ctx, int32_t model, int lam, int64_t off, uint6
   HIPCHK(launch_dust_lum(ctx->d_models.as<ModelDev>(), model, n, ctx->d_leaf_node.as<int32_t>(),
                          ctx->d_leaf_level.as<uint8_t>(), ctx->d_rho64.as<double>(),
                          h.d_T.as<double>(), h.d_lc.as<LamConst>(), lam, lum,
-                         ctx->lmax.as<unsigned long long>(), ctx->stream));
+                         ctx->lmax.as<unsigned long long>(), ctx->d_leaf_coord.as<int32_t>(), sub_lev, sub_I,
+                         ctx->stream));
   HIPCHK(launch_dust_quant(n, lum, ctx->lmax.as<unsigned long long>(), q, ctx->stream));
   size_t tmp = 0;
   HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, q, qpre, (int)n, ctx->stream));
@@ -837,6 +843,10 @@ struct TraceOut {
   const PeelParams* peel = nullptr;  // peel-off after every batch (rt_peel_map)
   double* self_acc = nullptr;        // accelerated Lambda iteration tallies (device, total nodes)
   double* emit_acc = nullptr;
+  double* lvl_acc = nullptr;         // subiterations: per-level deposits (device, [levels][total nodes])
+  int64_t lvl_stride = 0;
+  int32_t sub_lev = -1;              // subtree root (level, coordinates); -1 = whole model
+  int32_t sub_I[3] = {0, 0, 0};
 };
 
 rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_trace_opts* o,
@@ -983,7 +993,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
       if (S.kind == RT_SRC_DUST) {
         J.cdf_off = cdf_off;
         uint64_t qtot = 0;
-        if (rt_status e = build_dust_cdf(ctx, S.model, i, cdf_off, &qtot)) return e;
+        if (rt_status e = build_dust_cdf(ctx, S.model, i, cdf_off, &qtot, out.sub_lev, out.sub_I)) return e;
         J.qtot = qtot;
         cdf_off += h.n_leaves;
         if (qtot == 0) J.n = 0;  // nothing emits at this wavelength
@@ -1034,6 +1044,12 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   p.leaf_level = ctx->d_leaf_level.as<uint8_t>();
   p.self_acc = out.self_acc;
   p.emit_acc = out.emit_acc;
+  p.lvl_acc = out.lvl_acc;
+  p.lvl_stride = out.lvl_stride;
+  p.sub_lev = out.sub_lev;
+  for (int a = 0; a < 3; ++a) p.sub_I[a] = out.sub_I[a];
+  if ((out.lvl_acc || out.sub_lev >= 0) && fp32)
+    return fail(ctx, RT_EINVAL, "subiterations are implemented in the RT_FP64 form");
   if (out.peel) {
     p.peel_ev = const_cast<PeelEv*>(out.peel->ev);
     p.peel_count = out.peel->count;
@@ -1458,6 +1474,194 @@ rt_status rt_ali_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_sou
                          double t_min, double t_max, double* t_node, int32_t* n_done, double* crit) {
   return lambda_iterate_impl(ctx, model, n_src, src, opts, dust_packets, n_max, tol, t_min, t_max, t_node,
                              n_done, crit, true);
+}
+
+rt_status rt_subiter_begin(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
+                           const rt_trace_opts* opts, double t_min, double t_max) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (rt_status s = check_model(ctx, model)) return s;
+    if (!opts) return fail(ctx, RT_EINVAL, "null options");
+    if (opts->precision != RT_FP64) return fail(ctx, RT_EINVAL, "subiterations are implemented in the RT_FP64 form");
+    if (!(t_min > 0.0) || !(t_max > t_min)) return fail(ctx, RT_EINVAL, "need 0 < t_min < t_max");
+    for (int s = 0; s < n_src; ++s)
+      if (src && (src[s].model != model || src[s].kind == RT_SRC_DUST))
+        return fail(ctx, RT_EINVAL, "constant sources must belong to the model and not be dust");
+    HostModel& h = ctx->models[model];
+    if (h.nl < 1) return fail(ctx, RT_ESTATE, "rt_set_dust not called for model %d", model);
+    HIPCHK(hipSetDevice(ctx->device));
+    if (rt_status s = sync_device(ctx)) return s;
+    int64_t tn, tl, tln;
+    totals(ctx, &tn, &tl, &tln);
+    const int64_t cb = ctx->h_models[model].canon_base;
+    HIPCHK(ctx->it_astars.ensure(8 * tn));
+    HIPCHK(ctx->out_esc.ensure(8 * std::max<int64_t>(tl, 1)));
+    if (n_src > 0) {
+      TraceOut out;
+      out.e_esc = ctx->out_esc.as<double>();
+      out.e_node = ctx->it_astars.as<double>();
+      if (rt_status s = trace_impl(ctx, n_src, src, opts, out, nullptr)) return s;
+    } else {
+      HIPCHK(hipMemsetAsync(ctx->it_astars.p, 0, 8 * tn, ctx->stream));
+    }
+    HIPCHK(h.sub_astars.ensure(8 * h.n_nodes));
+    HIPCHK(hipMemcpyAsync(h.sub_astars.p, ctx->it_astars.as<double>() + cb, 8 * h.n_nodes,
+                          hipMemcpyDeviceToDevice, ctx->stream));
+    const size_t na = (size_t)(h.nlev + 1) * h.n_nodes;
+    HIPCHK(h.sub_arrays.ensure(8 * na));
+    HIPCHK(hipMemsetAsync(h.sub_arrays.p, 0, 8 * na, ctx->stream));
+    HIPCHK(h.sub_imb.ensure(8 * h.n_nodes));
+    HIPCHK(hipMemsetAsync(h.sub_imb.p, 0, 8 * h.n_nodes, ctx->stream));
+    if (rt_status s = solve_T_impl(ctx, model, h.sub_astars.as<double>(), t_min, t_max)) return s;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    h.sub_tmin = t_min;
+    h.sub_tmax = t_max;
+    h.sub_ready = true;
+    return RT_OK;
+  })
+}
+
+rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust_packets, uint32_t iteration,
+                          const rt_trace_opts* opts, double* crit, double* t_node, rt_trace_stats* stats) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (rt_status s = check_model(ctx, model)) return s;
+    if (!opts) return fail(ctx, RT_EINVAL, "null options");
+    if (opts->precision != RT_FP64) return fail(ctx, RT_EINVAL, "subiterations are implemented in the RT_FP64 form");
+    HostModel& h = ctx->models[model];
+    if (!h.sub_ready) return fail(ctx, RT_ESTATE, "rt_subiter_begin not called for model %d", model);
+    if (dust_packets < 1 || dust_packets > (int64_t(1) << 32)) return fail(ctx, RT_EINVAL, "bad dust_packets");
+    if (root < -1 || root >= h.n_nodes) return fail(ctx, RT_EINVAL, "bad subtree root");
+    int32_t sub_lev = -1, sub_I[3] = {0, 0, 0};
+    if (root >= 0) {
+      // canonical -> internal, its level and coordinates; it must be refined
+      const int64_t internal = h.base + (root < h.n_root ? root : root + (h.n_root_pad - h.n_root));
+      if (ctx->h_child[internal] < 0) return fail(ctx, RT_EINVAL, "the subtree root must be a refined node");
+      int lev = 0;
+      while (lev < h.nlev && root >= h.level_off[lev + 1]) ++lev;
+      int64_t li = root - h.level_off[lev];
+      // coordinates: walk the level index back to the root (oct o, child b = bx + 2 by + 4 bz)
+      int32_t I[3] = {0, 0, 0};
+      int sh = 0;
+      int64_t cur = internal;
+      for (int l = lev; l > 0; --l) {
+        const int b = (int)(cur & 7);
+        I[0] |= (b & 1) << sh;
+        I[1] |= ((b >> 1) & 1) << sh;
+        I[2] |= ((b >> 2) & 1) << sh;
+        ++sh;
+        cur = ctx->h_up[cur >> 3];
+      }
+      const int64_t r = cur - h.base;
+      I[0] |= (int32_t)(r % h.n[0]) << sh;
+      I[1] |= (int32_t)((r / h.n[0]) % h.n[1]) << sh;
+      I[2] |= (int32_t)(r / ((int64_t)h.n[0] * h.n[1])) << sh;
+      (void)li;
+      sub_lev = lev;
+      for (int a = 0; a < 3; ++a) sub_I[a] = I[a];
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    if (rt_status s = sync_device(ctx)) return s;
+    int64_t tn, tl, tln;
+    totals(ctx, &tn, &tl, &tln);
+    const int64_t cb = ctx->h_models[model].canon_base;
+    const size_t nlv = (size_t)(h.nlev + 1);
+    HIPCHK(ctx->it_adust.ensure(8 * tn));
+    HIPCHK(ctx->it_sum.ensure(8 * h.n_nodes));
+    HIPCHK(ctx->it_told.ensure(8 * h.n_nodes));
+    HIPCHK(ctx->it_crit.ensure(16));
+    HIPCHK(ctx->it_self.ensure(8 * nlv * tn));  // per-level deposits of this step
+    HIPCHK(hipMemsetAsync(ctx->it_self.p, 0, 8 * nlv * tn, ctx->stream));
+    HIPCHK(ctx->out_esc.ensure(8 * std::max<int64_t>(tl, 1)));
+    HIPCHK(hipMemcpyAsync(ctx->it_told.p, h.d_T.p, 8 * h.n_nodes, hipMemcpyDeviceToDevice, ctx->stream));
+    rt_source ds;
+    std::memset(&ds, 0, sizeof ds);
+    ds.kind = RT_SRC_DUST;
+    ds.model = model;
+    ds.packets_per_lambda = dust_packets;
+    rt_trace_opts o = *opts;
+    o.iteration = iteration;
+    TraceOut out;
+    out.e_esc = ctx->out_esc.as<double>();
+    out.e_node = ctx->it_adust.as<double>();
+    out.lvl_acc = ctx->it_self.as<double>();
+    out.lvl_stride = tn;
+    out.sub_lev = sub_lev;
+    for (int a = 0; a < 3; ++a) out.sub_I[a] = sub_I[a];
+    if (rt_status s = trace_impl(ctx, 1, &ds, &o, out, stats)) return s;
+    HIPCHK(launch_subiter_update(ctx->d_models.as<ModelDev>(), model, h.n_leaves, ctx->d_leaf_node.as<int32_t>(),
+                                 ctx->d_leaf_level.as<uint8_t>(), ctx->d_leaf_coord.as<int32_t>(),
+                                 ctx->d_rho64.as<double>(), h.d_lc.as<LamConst>(), h.nl, sub_lev, sub_I,
+                                 sub_lev + 1, ctx->it_self.as<double>(), tn, h.sub_arrays.as<double>(),
+                                 h.sub_astars.as<double>(), ctx->it_told.as<double>(), ctx->it_sum.as<double>(),
+                                 h.sub_imb.as<double>(), ctx->stream));
+    if (rt_status s = solve_T_impl(ctx, model, ctx->it_sum.as<double>(), h.sub_tmin, h.sub_tmax)) return s;
+    HIPCHK(hipMemsetAsync(ctx->it_crit.p, 0, 16, ctx->stream));
+    HIPCHK(launch_crit(ctx->d_models.as<ModelDev>(), model, h.n_nodes, ctx->d_child.as<int32_t>(),
+                       ctx->d_rho64.as<double>(), h.d_T.as<double>(), ctx->it_told.as<double>(),
+                       ctx->it_crit.as<double>(), ctx->stream));
+    double c2[2];
+    HIPCHK(hipMemcpyAsync(c2, ctx->it_crit.p, 16, hipMemcpyDeviceToHost, ctx->stream));
+    if (t_node)
+      HIPCHK(hipMemcpyAsync(t_node, h.d_T.p, 8 * h.n_nodes,
+                            is_device_ptr(t_node) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (crit) *crit = c2[1] > 0.0 ? c2[0] / c2[1] : 0.0;
+    return RT_OK;
+  })
+}
+
+rt_status rt_subiter_select(rt_ctx* ctx, int32_t model, double frac, int64_t* root, double* max_imbalance) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (rt_status s = check_model(ctx, model)) return s;
+    if (!root || !(frac > 0.0 && frac <= 1.0)) return fail(ctx, RT_EINVAL, "need frac in (0, 1] and root");
+    HostModel& h = ctx->models[model];
+    if (!h.sub_ready) return fail(ctx, RT_ESTATE, "rt_subiter_begin not called for model %d", model);
+    HIPCHK(hipSetDevice(ctx->device));
+    std::vector<double> imb(h.n_nodes);
+    HIPCHK(hipMemcpyAsync(imb.data(), h.sub_imb.p, 8 * h.n_nodes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double mx = 0.0;
+    for (double v : imb) mx = std::max(mx, v);
+    if (max_imbalance) *max_imbalance = mx;
+    // the lowest common ancestor of every leaf within frac of the largest imbalance; a common
+    // ancestor above the root level means the whole model
+    auto internal_of = [&](int64_t c) { return h.base + (c < h.n_root ? c : c + (h.n_root_pad - h.n_root)); };
+    auto canon_of_h = [&](int64_t i) {
+      const int64_t c = i - h.base;
+      return c < h.n_root ? c : c - (h.n_root_pad - h.n_root);
+    };
+    auto level_of = [&](int64_t c) {
+      int l = 0;
+      while (l < h.nlev && c >= h.level_off[l + 1]) ++l;
+      return l;
+    };
+    auto parent = [&](int64_t c) -> int64_t {  // canonical parent, -1 for a root cell
+      if (c < h.n_root) return -1;
+      const int64_t i = internal_of(c);
+      return canon_of_h(ctx->h_up[i >> 3]);
+    };
+    int64_t lca = -2;  // none yet
+    for (int64_t c = 0; c < h.n_nodes && lca != -1; ++c) {
+      if (!(mx > 0.0) || imb[c] < frac * mx) continue;
+      int64_t a = parent(c);
+      if (lca == -2) {
+        lca = a;
+        continue;
+      }
+      // walk both up to the same level, then together
+      int64_t x = lca, y = a;
+      while (x >= 0 && y >= 0 && x != y) {
+        const int lx = level_of(x), ly = level_of(y);
+        if (lx >= ly) x = parent(x);
+        if (ly >= lx) y = parent(y);
+      }
+      lca = (x >= 0 && y >= 0) ? x : -1;
+    }
+    *root = lca < 0 ? -1 : lca;
+    return RT_OK;
+  })
 }
 
 rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32_t npix, double width,

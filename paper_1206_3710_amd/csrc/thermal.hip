@@ -88,7 +88,8 @@ __global__ __launch_bounds__(256) void dust_lum_kernel(
     const int32_t* __restrict__ leaf_node, const uint8_t* __restrict__ leaf_level,
     const double* __restrict__ rho64, const double* __restrict__ t_node,
     const LamConst* __restrict__ lc, int lam, double* __restrict__ lum,
-    unsigned long long* __restrict__ lmax_bits) {
+    unsigned long long* __restrict__ lmax_bits, const int32_t* __restrict__ leaf_coord, int sub_lev,
+    int32_t s0, int32_t s1, int32_t s2) {
   const ModelDev& m = models[model];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double l = 0.0;
@@ -102,6 +103,11 @@ __global__ __launch_bounds__(256) void dust_lum_kernel(
     double b = 0.0;
     if (t > 0.0) b = lc[lam].pre / expm1(lc[lam].hnu / (kK * t));
     l = 4.0 * kPi * mass * kabs * b * lc[lam].dnu;
+    if (sub_lev >= 0) {  // a subiteration: only the leaves of the subtree emit
+      const int32_t* xyz = leaf_coord + 3 * (m.leaf_base + k);
+      const int32_t sI[3] = {s0, s1, s2};
+      if (!in_subtree(sub_lev, sI, lev, xyz[0], xyz[1], xyz[2])) l = 0.0;
+    }
     lum[k] = l;
   }
   // non-negative doubles order like their bit patterns
@@ -124,7 +130,57 @@ __global__ __launch_bounds__(256) void dust_quant_kernel(int64_t n, const double
   q[k] = lmax > 0.0 ? (uint64_t)floor((lum[k] / lmax) * 4294967296.0) : 0ull;
 }
 
+// After a (sub)iteration step (App. B): for every leaf of the subtree, replace its arrays of
+// levels >= lo by the step's deposits and record the energy imbalance |A - E(T_old)| / E(T_old)
+// between what it now absorbs and what it emitted; for every leaf, A_tot = A_stars + the sum of
+// its arrays (Eq. 9), from which the temperatures are solved.
+__global__ __launch_bounds__(256) void subiter_update_kernel(
+    const ModelDev* __restrict__ models, int model, int64_t n_leaves, const int32_t* __restrict__ leaf_node,
+    const uint8_t* __restrict__ leaf_level, const int32_t* __restrict__ leaf_coord,
+    const double* __restrict__ rho64, const LamConst* __restrict__ lc, int nl, int sub_lev, int32_t s0,
+    int32_t s1, int32_t s2, int lo, const double* __restrict__ lvl_new, int64_t lvl_stride,
+    double* __restrict__ arrays, const double* __restrict__ a_stars, const double* __restrict__ t_old,
+    double* __restrict__ a_tot, double* __restrict__ imb) {
+  const ModelDev& m = models[model];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_leaves) return;
+  const int32_t node = leaf_node[m.leaf_base + k];
+  const int lev = leaf_level[m.leaf_base + k];
+  const int64_t c = canon_of(m, node);
+  const int32_t* xyz = leaf_coord + 3 * (m.leaf_base + k);
+  const int32_t sI[3] = {s0, s1, s2};
+  const bool inside = sub_lev < 0 || in_subtree(sub_lev, sI, lev, xyz[0], xyz[1], xyz[2]);
+  double sum = 0.0;
+  for (int l = 0; l <= m.nlev; ++l) {
+    double* a = arrays + (int64_t)l * m.n_nodes + c;
+    if (inside && l >= lo) *a = lvl_new[(int64_t)l * lvl_stride + m.canon_base + c];
+    sum += *a;
+  }
+  const double at = a_stars[c] + sum;
+  a_tot[c] = at;
+  if (inside) {
+    const double len = m.cell_cm * ldexp(1.0, -lev);
+    const double mass = rho64[node] * (len * len * len);
+    double s, ds;
+    planck_sum(lc, nl, t_old[c], s, ds);
+    const double e = 4.0 * kPi * mass * s;
+    imb[c] = e > 0.0 ? fabs(at - e) / e : 0.0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_subiter_update(const ModelDev* models, int model, int64_t n_leaves, const int32_t* leaf_node,
+                                 const uint8_t* leaf_level, const int32_t* leaf_coord, const double* rho64,
+                                 const LamConst* lc, int nl, int sub_lev, const int32_t sub_I[3], int lo,
+                                 const double* lvl_new, int64_t lvl_stride, double* arrays, const double* a_stars,
+                                 const double* t_old, double* a_tot, double* imb, hipStream_t s) {
+  if (n_leaves == 0) return hipSuccess;
+  hipLaunchKernelGGL(subiter_update_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, s, models,
+                     model, n_leaves, leaf_node, leaf_level, leaf_coord, rho64, lc, nl, sub_lev, sub_I[0], sub_I[1],
+                     sub_I[2], lo, lvl_new, lvl_stride, arrays, a_stars, t_old, a_tot, imb);
+  return hipGetLastError();
+}
 
 hipError_t launch_temperature(const ModelDev* models, int model, int64_t n_nodes,
                               const int32_t* child, const double* rho64, const double* a_node,
@@ -138,10 +194,11 @@ hipError_t launch_temperature(const ModelDev* models, int model, int64_t n_nodes
 hipError_t launch_dust_lum(const ModelDev* models, int model, int64_t n_leaves,
                            const int32_t* leaf_node, const uint8_t* leaf_level,
                            const double* rho64, const double* t_node, const LamConst* lc, int lam,
-                           double* lum, unsigned long long* lmax_bits, hipStream_t s) {
+                           double* lum, unsigned long long* lmax_bits, const int32_t* leaf_coord,
+                           int sub_lev, const int32_t sub_I[3], hipStream_t s) {
   hipLaunchKernelGGL(dust_lum_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, s,
                      models, model, n_leaves, leaf_node, leaf_level, rho64, t_node, lc, lam, lum,
-                     lmax_bits);
+                     lmax_bits, leaf_coord, sub_lev, sub_I[0], sub_I[1], sub_I[2]);
   return hipGetLastError();
 }
 

@@ -28,6 +28,8 @@ __global__ __launch_bounds__(256) void trace_fp64_kernel(const TraceParams p, co
     t_emit = w0;
     if (p.emit_acc && job.kind == RT_SRC_DUST)
       unsafeAtomicAdd(p.emit_acc + md.canon_base + canon_of(md, k.node), w0);
+    // shallowest level visited: the external field enters through the root grid
+    int mlev = job.kind == RT_SRC_BACKGROUND ? 0 : k.lev;
     const double kext = job.kext, alb = job.alb, g = job.g, cm = md.cell_cm;
     double* __restrict__ acc = p.acc64 + job.acc_off;
     uint32_t crossings = 1, ev = 0, status = 0;
@@ -68,6 +70,8 @@ __global__ __launch_bounds__(256) void trace_fp64_kernel(const TraceParams p, co
         // accelerated Lambda iteration: absorption in the birth cell before the first crossing
         if (p.self_acc && crossings == 1 && job.kind == RT_SRC_DUST)
           unsafeAtomicAdd(p.self_acc + md.canon_base + canon_of(md, k.node), de);
+        if (p.lvl_acc)
+          unsafeAtomicAdd(p.lvl_acc + (int64_t)mlev * p.lvl_stride + md.canon_base + canon_of(md, k.node), de);
         w = w - de;
       }
 #pragma unroll
@@ -148,6 +152,13 @@ __global__ __launch_bounds__(256) void trace_fp64_kernel(const TraceParams p, co
         ++k.lev;
         c = p.child[k.node];
       }
+      if (p.sub_lev >= 0 && !in_subtree(p.sub_lev, p.sub_I, k.lev, k.I[0], k.I[1], k.I[2])) {
+        // a subiteration follows packets only inside its subtree
+        t_esc = w;
+        status = 0;
+        break;
+      }
+      if (k.lev < mlev) mlev = k.lev;
       if (++crossings >= (1u << 30)) {  // guards termination; never reached by valid input
         c_trunc = 1;
         t_trunc = w;

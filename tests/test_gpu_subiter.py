@@ -1,0 +1,135 @@
+"""GPU parity of subiterations on complete subtrees (paper Sect. 3.1, Sect. 3.3, App. B) in the
+FP64 form against the oracle: the temperatures after each step of a schedule that mixes
+whole-model steps and subtree steps agree to the solver's precision, and the automatic choice
+of the next subtree is the lowest common ancestor of the most imbalanced leaves, as computed
+from the oracle's state."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from tests import brute
+
+pytestmark = pytest.mark.gpu
+
+rt = pytest.importorskip("paper_1206_3710_amd")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _dust():
+    lam = np.logspace(-1, 3, 10)
+    kap = 3.0 * (lam / 0.55) ** -1.6
+    alb = np.clip(0.5 * (1 - np.log10(lam / 0.1) / 4), 0, 0.5)
+    return gen.Dust(lam, kap, alb, alb.copy()), lam
+
+
+def _block_case():
+    dust, lam = _dust()
+    tree = gen.refined_block(2)
+    rng = np.random.default_rng(6)
+    tree.child_rho = [rng.uniform(0.5, 2.0, len(c)) for c in tree.child_rho]
+    nu = brute.CL / (lam * 1e-4)
+    star = [gen.Source(gen.SRC_POINT, 0, pos=(2.1, 1.9, 2.05), power=1e-2 * brute.planck_nu(nu, 5000.0),
+                       packets=3000)]
+    return tree, dust, star
+
+
+def _core_case():
+    """4^3 thin root cells; root cell (1, 1, 1) refined two levels deep and dense, with the star
+    inside it."""
+    dust, lam = _dust()
+    rho = np.full(64, 0.05)
+    core = 1 + 4 * (1 + 4 * 1)
+    tree = gen.TreeDesc(4, 4, 4, 1.0, rho, [np.array([core], dtype=np.int64), np.arange(8, dtype=np.int64)],
+                        [np.full(8, 20.0), np.full(64, 20.0)])
+    nu = brute.CL / (lam * 1e-4)
+    star = [gen.Source(gen.SRC_POINT, 0, pos=(1.55, 1.45, 1.6), power=1e-2 * brute.planck_nu(nu, 5000.0),
+                       packets=4000)]
+    return tree, dust, star, core
+
+
+def test_subiterations_fp64_against_oracle(torch):
+    tree, dust, star = _block_case()
+    root = 2 + 4 * (1 + 4 * 2)
+    schedule = [-1, root, root, -1]
+    o = oracle.Model(tree, dust)
+    hist, _, _ = oracle.subiterate(o, star, seed=8, schedule=schedule, dust_packets=3000)
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    ctx.subiter_begin(m, star, seed=8)
+    for k, r in enumerate(schedule, start=1):
+        t, crit, st = ctx.subiter_step(m, r, dust_packets=3000, seed=8, iteration=k)
+        np.testing.assert_allclose(t.cpu().numpy(), hist[k], rtol=1e-6, err_msg=f"step {k}")
+        assert crit >= 0.0 and st["packets"] > 0
+    ctx.close()
+
+
+def _reference_select(o, imbalance, frac):
+    """Lowest common ancestor of the leaves within frac of the largest imbalance (-1: the whole
+    model), from the oracle's tree."""
+    mx = imbalance.max()
+    lv = o.level_of_nodes()
+    flagged = np.flatnonzero(imbalance >= frac * mx)
+    chains = []
+    for c in flagged:
+        mask_anc = [a for a in range(o.n_nodes) if o.child[a] >= 0 and o.subtree_mask(a)[c]]
+        chains.append(set(mask_anc))
+    common = set.intersection(*chains) if chains else set()
+    if not common:
+        return -1
+    return max(common, key=lambda a: lv[a])
+
+
+def test_subtree_selection(torch):
+    """After a whole-model step of a thin cloud with a dense refined core around the star, the
+    chosen subtree is the one the oracle's imbalances give: with the threshold at 90 % of the
+    largest imbalance it lies in the core."""
+    tree, dust, star, core = _core_case()
+    o = oracle.Model(tree, dust)
+    hist, a_stars, stats = oracle.subiterate(o, star, seed=3, schedule=[-1], dust_packets=4000)
+    a_tot = a_stars + stats[0]["e_lvl"].sum(axis=0)
+    e_old = o.emission_all(hist[0])
+    leaf = o.leaf_mask
+    imb = np.where(leaf & (e_old > 0), np.abs(a_tot - e_old) / np.where(e_old > 0, e_old, 1.0), 0.0)
+    ref = _reference_select(o, imb, 0.9)
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    ctx.subiter_begin(m, star, seed=3)
+    ctx.subiter_step(m, -1, dust_packets=4000, seed=3, iteration=1)
+    root, mx = ctx.subiter_select(m, 0.9)
+    ctx.close()
+    assert abs(mx - imb.max()) <= 1e-6 * imb.max()
+    assert root == ref, (root, ref)
+    assert root == core or (root >= 0 and o.subtree_mask(core)[root])
+    # a looser threshold takes in the thin cells around the core: the whole model
+    ctx2 = rt.Context(0)
+    m2 = ctx2.build_tree(tree)
+    ctx2.set_dust(m2, dust)
+    ctx2.subiter_begin(m2, star, seed=3)
+    ctx2.subiter_step(m2, -1, dust_packets=4000, seed=3, iteration=1)
+    assert ctx2.subiter_select(m2, 0.25)[0] == _reference_select(o, imb, 0.25) == -1
+    ctx2.close()
+
+
+def test_subiterations_need_the_fp64_form(torch):
+    tree, dust, star = _block_case()
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    with pytest.raises(rt.RTError):
+        ctx.subiter_step(m, -1, dust_packets=10, seed=1, iteration=1)  # before begin
+    ctx.subiter_begin(m, star, seed=1)
+    with pytest.raises(rt.RTError):
+        ctx.subiter_step(m, 0, dust_packets=10, seed=1, iteration=1)  # a root leaf is no subtree
+    t, _, _ = ctx.subiter_step(m, -1, dust_packets=100, seed=1, iteration=1)
+    assert float(t.max()) > 0.0
+    ctx.close()
