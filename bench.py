@@ -264,6 +264,48 @@ def ali_study(rt, gen, steps=24, ref_steps=60, packets=300_000):
     return out
 
 
+def subiter_study(rt, gen, steps=12, ref_steps=40, packets=200_000, frac=0.5):
+    """Subiterations (Sect. 3.1, 3.3, App. B) against whole-model iterations on a thin cloud with
+    one dense core around a star (gen.core_cloud), FP64 form: the mass-weighted mean relative
+    distance of the temperatures to a long whole-model run after every step, against the
+    cumulative cell crossings spent; the subtrees come from the automatic choice."""
+    import numpy as np
+    w = gen.core_cloud(packets=packets)
+    tree, dust = w.trees[0], w.dusts[0]
+    level, leaf, rho, _ = node_geometry(tree)
+    mass = (rho * 8.0 ** (-level.astype(np.float64)))[leaf]
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    rr = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob)
+
+    def run(n, auto):
+        ctx.subiter_begin(m, w.sources, seed=w.seed, **rr)
+        out, cross, roots, ms = [], 0, [], 0.0
+        for k in range(1, n + 1):
+            root = -1
+            if auto and k > 1:
+                root, _ = ctx.subiter_select(m, frac)
+            t0 = time.perf_counter()
+            t_, _, st = ctx.subiter_step(m, root, dust_packets=packets, seed=w.seed, iteration=k, **rr)
+            ms += 1e3 * (time.perf_counter() - t0)
+            cross += st["crossings"]
+            roots.append(int(root))
+            out.append((cross, t_.cpu().numpy()[leaf]))
+        return out, roots, ms
+    ref = run(ref_steps, False)[0][-1][1]
+    res = {"model": "thin cloud 15^3 with one dense core refined 3 levels around a 5000 K star",
+           "packets_per_lambda": packets, "frac": frac, "reference": f"{ref_steps} whole-model steps"}
+    for name, auto in (("whole_model", False), ("subiterations", True)):
+        hist, roots, ms = run(steps, auto)
+        res[name] = {"crossings": [int(c) for c, _ in hist],
+                     "distance_to_reference": [float((mass * np.abs(h - ref) / ref).sum() / mass.sum())
+                                               for _, h in hist],
+                     "roots": roots, "ms_total": ms}
+    ctx.close()
+    return res
+
+
 def pass_sources_sha():
     import hashlib
     h = hashlib.sha256()
@@ -304,6 +346,8 @@ def parse():
                     help="add the package-splitting noise study (cloud and deep workloads)")
     ap.add_argument("--ali-study", action="store_true",
                     help="add the accelerated-iteration convergence study (a thick cube)")
+    ap.add_argument("--subiter-study", action="store_true",
+                    help="add the subiteration study (a thin cloud with a dense core)")
     ap.add_argument("--peel-study", action="store_true",
                     help="add the peel-off timing study (cloud, disc and deep workloads)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -533,6 +577,10 @@ def main():
     if a.schedule == 0 and a.ali_study:
         accel = ali_study(rt, gen)
 
+    subiters = None
+    if a.subiter_study:
+        subiters = subiter_study(rt, gen)
+
     peeling = None
     if a.workload in ("cloud", "disc", "deep") and a.schedule == 0 and a.peel_study:
         peeling = peel_study(rt, gen, w, kw32, a.workload)
@@ -575,6 +623,7 @@ def main():
         "splitting": splitting,
         "peel_off": peeling,
         "accelerated_iteration": accel,
+        "subiterations": subiters,
     }
     print(json.dumps(res))
     ctx.close()

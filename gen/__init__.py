@@ -526,6 +526,38 @@ def thick_cube(n_root: int = 16, seed: int = BASE_SEED + 6, packets: int = 1_000
     return Workload("thick_cube", [tree], [dust], star, seed, meta={"n_root": n_root})
 
 
+def core_cloud(n_root: int = 15, levels: int = 3, seed: int = BASE_SEED + 7,
+               packets: int = 100_000) -> Workload:
+    """A thin cloud with one dense core, for subiterations: n_root^3 root cells of 1 cm (n_root
+    odd) of density 0.02 g cm^-3; the central root cell is refined ``levels`` deep everywhere and
+    its leaves take rho = 0.02 + 60 / (1 + r^2 / 0.12^2)^2 at their centres (r in cm from the
+    cube centre); a 5000 K star of unit surface at the centre; 10 wavelengths 0.1-1000 um,
+    kappa = 3 (lambda / 0.55 um)^-1.6, albedo and g falling from 0.5 as for the shared dust."""
+    c = n_root // 2
+    core = c + n_root * (c + n_root * c)
+    refined, kids = [np.array([core], dtype=np.int64)], []
+    centres = np.array([[c + 0.5, c + 0.5, c + 0.5]])
+    for lvl in range(1, levels + 1):
+        h = 2.0 ** -lvl
+        b = np.arange(8)
+        off = np.stack([b & 1, (b >> 1) & 1, (b >> 2) & 1], axis=1) - 0.5
+        centres = (centres[:, None, :] + 0.5 * h * off[None, :, :] * 2.0).reshape(-1, 3)
+        r2 = ((centres - (c + 0.5)) ** 2).sum(axis=1)
+        rho = 0.02 + 60.0 / (1.0 + r2 / 0.12 ** 2) ** 2
+        kids.append(rho)
+        if lvl < levels:
+            refined.append(np.arange(len(rho), dtype=np.int64))
+    tree = TreeDesc(n_root, n_root, n_root, 1.0, np.full(n_root ** 3, 0.02), refined, kids)
+    lam = np.logspace(-1.0, 3.0, 10)
+    kap = 3.0 * (lam / 0.55) ** -1.6
+    alb = np.clip(0.5 * (1.0 - np.log10(lam / 0.1) / 4.0), 0.0, 0.5)
+    dust = Dust(lam, kap, alb, alb.copy())
+    star = [Source(SRC_POINT, 0, pos=(c + 0.51, c + 0.49, c + 0.505),
+                   power=planck_nu_input(lam, 5000.0), packets=packets)]
+    return Workload("core_cloud", [tree], [dust], star, seed, rr_threshold=1e-3, rr_prob=0.9,
+                    meta={"core_root_cell": int(core)})
+
+
 def describe(w: Workload) -> dict:
     out = {"name": w.name, "models": len(w.trees)}
     out["nodes"] = int(sum(t.n_nodes for t in w.trees))
