@@ -264,44 +264,57 @@ def ali_study(rt, gen, steps=24, ref_steps=60, packets=300_000):
     return out
 
 
-def subiter_study(rt, gen, steps=12, ref_steps=40, packets=200_000, frac=0.5):
+def subiter_study(rt, gen, ref_steps=40, packets=200_000, frac=0.5, stall=0.8):
     """Subiterations (Sect. 3.1, 3.3, App. B) against whole-model iterations on a thin cloud with
-    one dense core around a star (gen.core_cloud), FP64 form: the mass-weighted mean relative
-    distance of the temperatures to a long whole-model run after every step, against the
-    cumulative cell crossings spent; the subtrees come from the automatic choice."""
+    one dense core around a star (gen.core_cloud), FP64 form: after k steps, the mass-weighted
+    mean relative distance of the temperatures to a long whole-model run, over all leaves and
+    over the core's, against the cell crossings spent.  The subiterations follow the automatic
+    iteration (rt_subiter_run)."""
     import numpy as np
     w = gen.core_cloud(packets=packets)
     tree, dust = w.trees[0], w.dusts[0]
     level, leaf, rho, _ = node_geometry(tree)
     mass = (rho * 8.0 ** (-level.astype(np.float64)))[leaf]
+    core = (level > 0)[leaf]
     ctx = rt.Context(0)
     m = ctx.build_tree(tree)
     ctx.set_dust(m, dust)
     rr = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob)
 
-    def run(n, auto):
-        ctx.subiter_begin(m, w.sources, seed=w.seed, **rr)
-        out, cross, roots, ms = [], 0, [], 0.0
-        for k in range(1, n + 1):
-            root = -1
-            if auto and k > 1:
-                root, _ = ctx.subiter_select(m, frac)
-            t0 = time.perf_counter()
-            t_, _, st = ctx.subiter_step(m, root, dust_packets=packets, seed=w.seed, iteration=k, **rr)
-            ms += 1e3 * (time.perf_counter() - t0)
-            cross += st["crossings"]
-            roots.append(int(root))
-            out.append((cross, t_.cpu().numpy()[leaf]))
-        return out, roots, ms
-    ref = run(ref_steps, False)[0][-1][1]
+    def dist(h, ref, sel):
+        return float((mass[sel] * np.abs(h[sel] - ref[sel]) / ref[sel]).sum() / mass[sel].sum())
+
+    ctx.subiter_begin(m, w.sources, seed=w.seed, **rr)
+    for k in range(1, ref_steps + 1):
+        t_, _, _ = ctx.subiter_step(m, -1, dust_packets=packets, seed=w.seed, iteration=k, **rr)
+    ref = t_.cpu().numpy()[leaf]
+    checkpoints = [1, 2, 3, 4, 6, 8, 12, 16]
     res = {"model": "thin cloud 15^3 with one dense core refined 3 levels around a 5000 K star",
-           "packets_per_lambda": packets, "frac": frac, "reference": f"{ref_steps} whole-model steps"}
-    for name, auto in (("whole_model", False), ("subiterations", True)):
-        hist, roots, ms = run(steps, auto)
-        res[name] = {"crossings": [int(c) for c, _ in hist],
-                     "distance_to_reference": [float((mass * np.abs(h - ref) / ref).sum() / mass.sum())
-                                               for _, h in hist],
-                     "roots": roots, "ms_total": ms}
+           "packets_per_lambda": packets, "frac": frac, "stall": stall, "checkpoints": checkpoints,
+           "reference": f"{ref_steps} whole-model steps"}
+    all_leaves = np.ones(len(ref), dtype=bool)
+    for name in ("whole_model", "subiterations"):
+        rows = {"crossings": [], "distance_all": [], "distance_core": []}
+        roots = None
+        t0 = time.perf_counter()
+        for n in checkpoints:
+            ctx.subiter_begin(m, w.sources, seed=w.seed, **rr)
+            if name == "whole_model":
+                cross = 0
+                for k in range(1, n + 1):
+                    t_, _, st = ctx.subiter_step(m, -1, dust_packets=packets, seed=w.seed, iteration=k, **rr)
+                    cross += st["crossings"]
+            else:
+                t_, roots, _, cs = ctx.subiter_run(m, n, dust_packets=packets, seed=w.seed, frac=frac,
+                                                   stall=stall, **rr)
+                cross = int(cs.sum())
+            h = t_.cpu().numpy()[leaf]
+            rows["crossings"].append(int(cross))
+            rows["distance_all"].append(dist(h, ref, all_leaves))
+            rows["distance_core"].append(dist(h, ref, core))
+        rows["roots_of_longest_run"] = [int(r) for r in roots] if roots is not None else None
+        rows["s_total"] = time.perf_counter() - t0
+        res[name] = rows
     ctx.close()
     return res
 

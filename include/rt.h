@@ -269,6 +269,16 @@ rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust
                           double* t_node, rt_trace_stats* stats);
 rt_status rt_subiter_select(rt_ctx* ctx, int32_t model, double frac, int64_t* root,
                             double* max_imbalance);
+/* Automatic iteration (Sect. 3.3): n_steps steps after rt_subiter_begin, the first on the whole
+ * model, each later one on the subtree rt_subiter_select(frac) picks; when it picks the subtree
+ * of the step before and the largest imbalance has not dropped below stall times its previous
+ * value (the Monte Carlo noise limit of that subtree), the step takes the whole model instead.
+ * Key iterations first_iteration, first_iteration + 1, ...  roots, crit, crossings [n_steps]
+ * (host, may be NULL): the subtree root, the stopping statistic and the cell crossings of each
+ * step; t_node (host or device, may be NULL): the temperatures after the last step. */
+rt_status rt_subiter_run(rt_ctx* ctx, int32_t model, int32_t n_steps, double frac, double stall,
+                         int64_t dust_packets, uint32_t first_iteration, const rt_trace_opts* opts,
+                         int64_t* roots, double* crit, uint64_t* crossings, double* t_node);
 
 /* Surface-brightness map (Sect. 4.1) of a model with its current temperatures: orthographic
  * view toward the observer direction n_obs; pixel (i, j) centre = box centre +

@@ -25,7 +25,7 @@ SCHED_REGIONS, SCHED_GLOBAL = 0, 1
 EXPORTS = ["rt_last_error", "rt_create", "rt_destroy", "rt_build_tree", "rt_get_model_info",
            "rt_get_sizes", "rt_locate", "rt_set_dust", "rt_set_temperature", "rt_trace_packets",
            "rt_solve_temperature", "rt_lambda_iterate", "rt_ali_iterate", "rt_subiter_begin",
-           "rt_subiter_step", "rt_subiter_select", "rt_render_map", "rt_peel_map",
+           "rt_subiter_step", "rt_subiter_select", "rt_subiter_run", "rt_render_map", "rt_peel_map",
            "rt_autotune", "rt_philox"]
 
 
@@ -116,6 +116,7 @@ def lib():
             "rt_subiter_begin": (I32, [P, I32, I32, P, P, D, D]),
             "rt_subiter_step": (I32, [P, I32, I64, I64, U32, P, P, P, P]),
             "rt_subiter_select": (I32, [P, I32, D, P, P]),
+            "rt_subiter_run": (I32, [P, I32, I32, D, D, I64, U32, P, P, P, P, P]),
             "rt_render_map": (I32, [P, I32, P, I32, D, I32, P, I32, P, P]),
             "rt_peel_map": (I32, [P, I32, P, P, P, P]),
             "rt_autotune": (I32, [P, I32, P, P, D, C.c_char_p, P, P]),
@@ -404,6 +405,22 @@ class Context:
         mx = C.c_double()
         self._check(lib().rt_subiter_select(self.h, model, frac, C.byref(root), C.byref(mx)))
         return int(root.value), float(mx.value)
+
+    def subiter_run(self, model: int, n_steps: int, dust_packets: int, seed: int, frac: float = 0.5,
+                    stall: float = 0.8, first_iteration: int = 1, rr_threshold: float = 0.0,
+                    rr_prob: float = 0.0):
+        """Automatic iteration after subiter_begin: (temperatures after the last step, roots,
+        stopping statistics, crossings per step)."""
+        torch = _torch()
+        opts = TraceOpts(seed, 0, FP64, rr_threshold, rr_prob)
+        roots = np.zeros(n_steps, dtype=np.int64)
+        crit = np.zeros(n_steps)
+        cross = np.zeros(n_steps, dtype=np.uint64)
+        t = torch.empty(self.models[model], dtype=torch.float64, device=self.tdev)
+        self._check(lib().rt_subiter_run(self.h, model, n_steps, frac, stall, int(dust_packets),
+                                         int(first_iteration), C.byref(opts), _ptr(roots), _ptr(crit),
+                                         _ptr(cross), _ptr(t)))
+        return t, roots, crit, cross
 
     def render_map(self, model: int, n_obs, npix: int, lambda_idx, width: float = 0.0,
                    precision: int = FP64):

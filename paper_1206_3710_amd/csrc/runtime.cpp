@@ -1664,6 +1664,38 @@ rt_status rt_subiter_select(rt_ctx* ctx, int32_t model, double frac, int64_t* ro
   })
 }
 
+rt_status rt_subiter_run(rt_ctx* ctx, int32_t model, int32_t n_steps, double frac, double stall,
+                         int64_t dust_packets, uint32_t first_iteration, const rt_trace_opts* opts,
+                         int64_t* roots, double* crit, uint64_t* crossings, double* t_node) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  if (n_steps < 1 || n_steps > 100000) return fail(ctx, RT_EINVAL, "bad n_steps");
+  if (!(stall > 0.0 && stall <= 1.0)) return fail(ctx, RT_EINVAL, "stall must be in (0, 1]");
+  int64_t prev_root = -2;
+  double prev_max = 0.0;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    int64_t root = -1;
+    if (k > 0) {
+      double mx = 0.0;
+      if (rt_status s = rt_subiter_select(ctx, model, frac, &root, &mx)) return s;
+      // the same subtree again without a clear drop of the largest imbalance: the noise limit
+      // of that subtree; take the whole model instead (Sect. 3.3)
+      if (root >= 0 && root == prev_root && mx > stall * prev_max) root = -1;
+      prev_max = mx;
+    }
+    rt_trace_stats st;
+    std::memset(&st, 0, sizeof st);
+    double c = 0.0;
+    if (rt_status s = rt_subiter_step(ctx, model, root, dust_packets, first_iteration + (uint32_t)k, opts, &c,
+                                      k == n_steps - 1 ? t_node : nullptr, &st))
+      return s;
+    prev_root = root;
+    if (roots) roots[k] = root;
+    if (crit) crit[k] = c;
+    if (crossings) crossings[k] = st.crossings;
+  }
+  return RT_OK;
+}
+
 rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32_t npix, double width,
                         int32_t n_sel, const int32_t* lambda_idx, int32_t precision, double* image,
                         uint64_t* crossings) {

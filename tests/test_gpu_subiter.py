@@ -133,3 +133,25 @@ def test_subiterations_need_the_fp64_form(torch):
     t, _, _ = ctx.subiter_step(m, -1, dust_packets=100, seed=1, iteration=1)
     assert float(t.max()) > 0.0
     ctx.close()
+
+
+def test_automatic_iteration_replays_as_steps(torch):
+    """rt_subiter_run is a sequence of subiter_step calls on the roots it reports: replaying
+    those roots step by step gives the same temperatures; the first step takes the whole
+    model and the later ones valid subtree roots."""
+    tree, dust, star, core = _core_case()
+    o = oracle.Model(tree, dust)
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    ctx.subiter_begin(m, star, seed=4)
+    t_run, roots, crit, cross = ctx.subiter_run(m, 6, dust_packets=3000, seed=4, frac=0.9, stall=0.8)
+    assert roots[0] == -1 and np.all(cross > 0) and np.all(crit >= 0.0)
+    for r in roots:
+        assert r == -1 or o.child[r] >= 0
+    assert np.any(roots[1:] >= 0)
+    ctx.subiter_begin(m, star, seed=4)
+    for k, r in enumerate(roots, start=1):
+        t_step, _, _ = ctx.subiter_step(m, int(r), dust_packets=3000, seed=4, iteration=k)
+    ctx.close()
+    np.testing.assert_allclose(t_step.cpu().numpy(), t_run.cpu().numpy(), rtol=1e-9)
