@@ -266,11 +266,13 @@ def ali_study(rt, gen, steps=24, ref_steps=60, packets=300_000):
 
 def subiter_study(rt, gen, ref_steps=40, packets=200_000, frac=0.5, stall=0.8):
     """Subiterations (Sect. 3.1, 3.3, App. B) against whole-model iterations on a thin cloud with
-    one dense core around a star (gen.core_cloud), FP64 form: after k steps, the mass-weighted
-    mean relative distance of the temperatures to a long whole-model run, over all leaves and
-    over the core's, against the cell crossings spent.  The subiterations follow the automatic
-    iteration (rt_subiter_run)."""
+    one dense core around a star (gen.core_cloud), in the FP64 form and in the FP32-local region
+    schedule: after k steps, the mass-weighted mean relative distance of the temperatures to a
+    long whole-model run (FP64 form), over all leaves and over the core's, against the cell
+    crossings and the time spent.  The subiterations follow the automatic iteration
+    (rt_subiter_run)."""
     import numpy as np
+    import torch
     w = gen.core_cloud(packets=packets)
     tree, dust = w.trees[0], w.dusts[0]
     level, leaf, rho, _ = node_geometry(tree)
@@ -288,33 +290,41 @@ def subiter_study(rt, gen, ref_steps=40, packets=200_000, frac=0.5, stall=0.8):
     for k in range(1, ref_steps + 1):
         t_, _, _ = ctx.subiter_step(m, -1, dust_packets=packets, seed=w.seed, iteration=k, **rr)
     ref = t_.cpu().numpy()[leaf]
+    print("# subiteration study: reference done", file=sys.stderr, flush=True)
     checkpoints = [1, 2, 3, 4, 6, 8, 12, 16]
     res = {"model": "thin cloud 15^3 with one dense core refined 3 levels around a 5000 K star",
            "packets_per_lambda": packets, "frac": frac, "stall": stall, "checkpoints": checkpoints,
-           "reference": f"{ref_steps} whole-model steps"}
+           "reference": f"{ref_steps} whole-model steps, FP64 form"}
     all_leaves = np.ones(len(ref), dtype=bool)
-    for name in ("whole_model", "subiterations"):
-        rows = {"crossings": [], "distance_all": [], "distance_core": []}
-        roots = None
-        t0 = time.perf_counter()
-        for n in checkpoints:
-            ctx.subiter_begin(m, w.sources, seed=w.seed, **rr)
-            if name == "whole_model":
-                cross = 0
-                for k in range(1, n + 1):
-                    t_, _, st = ctx.subiter_step(m, -1, dust_packets=packets, seed=w.seed, iteration=k, **rr)
-                    cross += st["crossings"]
-            else:
-                t_, roots, _, cs = ctx.subiter_run(m, n, dust_packets=packets, seed=w.seed, frac=frac,
-                                                   stall=stall, **rr)
-                cross = int(cs.sum())
-            h = t_.cpu().numpy()[leaf]
-            rows["crossings"].append(int(cross))
-            rows["distance_all"].append(dist(h, ref, all_leaves))
-            rows["distance_core"].append(dist(h, ref, core))
-        rows["roots_of_longest_run"] = [int(r) for r in roots] if roots is not None else None
-        rows["s_total"] = time.perf_counter() - t0
-        res[name] = rows
+    forms = {"fp64": dict(precision=rt.FP64),
+             "fp32_regions": dict(precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS)}
+    for form, kw in forms.items():
+        res[form] = {}
+        for name in ("whole_model", "subiterations"):
+            rows = {"crossings": [], "seconds": [], "distance_all": [], "distance_core": []}
+            roots = None
+            for n in checkpoints:
+                ctx.subiter_begin(m, w.sources, seed=w.seed, **rr, **kw)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if name == "whole_model":
+                    cross = 0
+                    for k in range(1, n + 1):
+                        t_, _, st = ctx.subiter_step(m, -1, dust_packets=packets, seed=w.seed, iteration=k,
+                                                     **rr, **kw)
+                        cross += st["crossings"]
+                else:
+                    t_, roots, _, cs = ctx.subiter_run(m, n, dust_packets=packets, seed=w.seed, frac=frac,
+                                                       stall=stall, **rr, **kw)
+                    cross = int(cs.sum())
+                h = t_.cpu().numpy()[leaf]
+                rows["seconds"].append(time.perf_counter() - t0)
+                rows["crossings"].append(int(cross))
+                rows["distance_all"].append(dist(h, ref, all_leaves))
+                rows["distance_core"].append(dist(h, ref, core))
+            rows["roots_of_longest_run"] = [int(r) for r in roots] if roots is not None else None
+            res[form][name] = rows
+        print(f"# subiteration study: {form} done", file=sys.stderr, flush=True)
     ctx.close()
     return res
 

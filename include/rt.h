@@ -246,7 +246,8 @@ rt_status rt_ali_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_sou
                          const rt_trace_opts* opts, int64_t dust_packets, int32_t n_max, double tol,
                          double t_min, double t_max, double* t_node, int32_t* n_done, double* crit);
 
-/* Subiterations on complete subtrees (Sect. 3.1, Sect. 3.3, App. B), RT_FP64 form.
+/* Subiterations on complete subtrees (Sect. 3.1, Sect. 3.3, App. B), in the RT_FP64 form or
+ * the RT_FP32_LOCAL region schedule (without package splitting; RT_EINVAL otherwise).
  * rt_subiter_begin traces the constant sources (key iteration opts->iteration) into A_stars,
  * solves T_0 and clears the model's per-level arrays (one absorbed-energy array per hierarchy
  * level at or above each cell's own).

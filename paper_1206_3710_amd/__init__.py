@@ -378,20 +378,29 @@ class Context:
                        _ptr(t), C.byref(nd), _ptr(crit)))
         return t, int(nd.value), crit[: nd.value]
 
+    @staticmethod
+    def _sub_opts(seed, iteration, precision, rr_threshold, rr_prob, kw):
+        return TraceOpts(seed, iteration, precision, rr_threshold, rr_prob, kw.get("max_events", 0),
+                         kw.get("block_size", 0), kw.get("blocks_per_cu", 0),
+                         kw.get("refill_threshold", 0.0), kw.get("schedule", SCHED_REGIONS),
+                         kw.get("chunk_packets", 0), kw.get("tail_park", 0),
+                         kw.get("batch_packets", 0), 0, None, 0, kw.get("split_n", 0))
+
     def subiter_begin(self, model: int, sources: Sequence, seed: int, t_min: float = 2.0,
                       t_max: float = 3000.0, iteration: int = 0, rr_threshold: float = 0.0,
-                      rr_prob: float = 0.0):
-        """Subiterations (FP64 form): trace the constant sources, T_0, clear the level arrays."""
+                      rr_prob: float = 0.0, precision: int = FP64, **kw):
+        """Subiterations (FP64 form, or FP32_LOCAL with the region schedule): trace the
+        constant sources, T_0, clear the level arrays."""
         arr, keep = _source_array(sources) if sources else ((Source * 1)(), [])
-        opts = TraceOpts(seed, iteration, FP64, rr_threshold, rr_prob)
+        opts = self._sub_opts(seed, iteration, precision, rr_threshold, rr_prob, kw)
         self._check(lib().rt_subiter_begin(self.h, model, len(sources), arr, C.byref(opts), t_min, t_max))
 
     def subiter_step(self, model: int, root: int, dust_packets: int, seed: int, iteration: int,
-                     rr_threshold: float = 0.0, rr_prob: float = 0.0):
+                     rr_threshold: float = 0.0, rr_prob: float = 0.0, precision: int = FP64, **kw):
         """One (sub)iteration step below refined node ``root`` (-1: the whole model).
         Returns (temperatures, stopping statistic, trace statistics)."""
         torch = _torch()
-        opts = TraceOpts(seed, 0, FP64, rr_threshold, rr_prob)
+        opts = self._sub_opts(seed, 0, precision, rr_threshold, rr_prob, kw)
         t = torch.empty(self.models[model], dtype=torch.float64, device=self.tdev)
         crit = C.c_double()
         st = TraceStats()
@@ -408,11 +417,11 @@ class Context:
 
     def subiter_run(self, model: int, n_steps: int, dust_packets: int, seed: int, frac: float = 0.5,
                     stall: float = 0.8, first_iteration: int = 1, rr_threshold: float = 0.0,
-                    rr_prob: float = 0.0):
+                    rr_prob: float = 0.0, precision: int = FP64, **kw):
         """Automatic iteration after subiter_begin: (temperatures after the last step, roots,
         stopping statistics, crossings per step)."""
         torch = _torch()
-        opts = TraceOpts(seed, 0, FP64, rr_threshold, rr_prob)
+        opts = self._sub_opts(seed, 0, precision, rr_threshold, rr_prob, kw)
         roots = np.zeros(n_steps, dtype=np.int64)
         crit = np.zeros(n_steps)
         cross = np.zeros(n_steps, dtype=np.uint64)

@@ -105,7 +105,10 @@ __global__ __launch_bounds__(256) void blk_emit_kernel(const BlkParams b, const 
     r.lev = (uint8_t)k.lev;
     r.ax = 0;
     r.sg = 0;
-    r.flag = 0;
+    // subiterations: the shallowest level visited starts at the birth cell's (0 for the external
+    // field, which enters through the root grid) and is the slot of the queue key
+    const uint32_t mslot = b.lvl_slots > 0 ? (J.kind == RT_SRC_BACKGROUND ? 0u : (uint32_t)k.lev) : (uint32_t)J.slot;
+    r.flag = b.lvl_slots > 0 ? (uint8_t)(mslot << 2) : 0;
     r.w0 = (float)k.w0;
     r.w = r.w0;
     r.tau = (float)k.tau;
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(256) void blk_emit_kernel(const BlkParams b, const 
     r.job = lo;
     r.ev = 0;
     r.ncross = 1;
-    key = (uint32_t)J.slot * (uint32_t)b.n_regions +
+    key = mslot * (uint32_t)b.n_regions +
           (uint32_t)region_walk(b, D, k.lev, k.I[0], k.I[1], k.I[2], -1, 1, 0.5f, 0.5f, 0.5f);
     e_emit = k.w0;
     npk = 1;
@@ -213,8 +216,11 @@ __device__ __forceinline__ void land(WF word_of, int ax, int sg, int L, int32_t 
 // read and deposited in global memory.  SPLIT: package splitting is on (split_n > 1); the
 // unsplit instance carries none of its state or code.  PEEL: scattering events are kept for
 // the peel-off.  ALI: the self-absorption of dust-emission packets is tallied for the
-// accelerated Lambda iteration.
-template <bool FITS, bool SPLIT, bool PEEL, bool ALI>
+// accelerated Lambda iteration.  LVL: subiterations (Sect. 3.1, App. B): deposits go to the
+// array of the shallowest level the package has visited (its `mlev`, which is also the slot of
+// its queue key, so that a work item's LDS sums belong to one array), and with a subtree set a
+// package that would cross out of it ends there as escaped.
+template <bool FITS, bool SPLIT, bool PEEL, bool ALI, bool LVL>
 __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it, const RegionDev& R,
                                          const ModelDev& md, const Dims D, int nloc, int nup,
                                          int32_t* s_word, float* s_acc, int32_t* s_up, uint32_t* s_next,
@@ -227,7 +233,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   const float rr_gain = rr_p > 0.0f ? 1.0f / (1.0f - rr_p) : 1.0f;
   const int bx = R.hi[0] - R.lo[0], by = R.hi[1] - R.lo[1];
   float* __restrict__ gacc = b.accb64 ? nullptr : b.accb + (int64_t)it.slot * b.accb_stride + R.gbase;
-  double* __restrict__ gacc64 = b.accb64 ? b.accb64 + R.gbase : nullptr;
+  double* __restrict__ gacc64 =
+      b.accb64 ? b.accb64 + (LVL ? (int64_t)it.slot * b.accb_stride : int64_t(0)) + R.gbase : nullptr;
   const int32_t* __restrict__ gword = b.rword + R.gbase;
   const int32_t* __restrict__ gup = b.rup + (R.gbase >> 3);
   auto word_of = [&](int32_t l) -> int32_t {
@@ -238,8 +245,12 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
     if (FITS) return s_up[l >> 3];
     return (l >> 3) < nup ? s_up[l >> 3] : gup[l >> 3];
   };
+  int mlev = 0;                // shallowest level visited (LVL)
   auto deposit = [&](int32_t l, float v) {
-    if (FITS || l < nloc) atomicAdd(&s_acc[l], v);
+    // a package whose shallowest level dropped below the item's slot during the item deposits
+    // straight into its own array
+    if (LVL && mlev != it.slot) unsafeAtomicAdd(b.accb64 + (int64_t)mlev * b.accb_stride + R.gbase + l, (double)v);
+    else if (FITS || l < nloc) atomicAdd(&s_acc[l], v);
     else if (gacc64) unsafeAtomicAdd(gacc64 + l, (double)v);
     else unsafeAtomicAdd(gacc + l, v);
   };
@@ -304,6 +315,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           ncross = rec.ncross;
           birth = rec.birth;
           br = (SPLIT && (rec.flag & 2)) ? (uint32_t)rec.birth : 0u;
+          if (LVL) mlev = rec.flag >> 2;
           const bool crossing = rec.flag & 1;
           const int L = rec.lev;
           int32_t J0 = rec.I[0], J1 = rec.I[1], J2 = rec.I[2];
@@ -368,6 +380,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
             raw = rr;
           }
           rho = __int_as_float(raw);
+          if (LVL && lev < mlev) mlev = lev;
           state = misplaced ? B_EMPTY : B_CROSS;
           if (!misplaced && crossing && splitting && lev != L) state = lev > L ? B_SPLIT : B_ROUL;
         }
@@ -415,8 +428,14 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           const int L = lev;
           const int32_t Ia = sel3(ax, I0, I1, I2);
           const int32_t Ja = Ia + sg;
-          if (Ja < 0 || Ja >= (D.na(ax) << L)) {
-            // escape through the root boundary
+          // a subiteration follows packages only inside its subtree: crossing out of it ends
+          // them as escaped (the test on the neighbour at the old level is exact, since the
+          // subtree root is refined and the packet is below it)
+          const bool sub_out = LVL && p.sub_lev >= 0 &&
+                               !in_subtree(p.sub_lev, p.sub_I, L, ax == 0 ? Ja : I0, ax == 1 ? Ja : I1,
+                                           ax == 2 ? Ja : I2);
+          if (Ja < 0 || Ja >= (D.na(ax) << L) || sub_out) {
+            // escape through the root boundary (or out of the subtree)
             // a region belongs to one model: its escapes are tallied per wavelength in LDS
             if (esc_lds) atomicAdd(&s_esc[esc_slot - (int)md.lam_base], (double)w);
             else unsafeAtomicAdd(p.esc + esc_slot, (double)w);
@@ -458,6 +477,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
               land(word_of, ax, sg, L, I0, I1, I2, J0, J1, J2, cur, l, x0, x1, x2, O0, O1, O2, d0, d1, d2,
                    node, lev, I0, I1, I2, raw);
               rho = __int_as_float(raw);
+              if (LVL && lev < mlev) mlev = lev;
               if (++ncross >= kMaxCrossings) {
                 ev = (uint32_t)p.max_events;
                 state = B_EVENT;
@@ -499,7 +519,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         rc.lev = (uint8_t)lev;
         rc.ax = (uint8_t)xax;
         rc.sg = xsg > 0 ? 0 : 1;
-        rc.flag = (xpark ? 0 : 1) | (br ? 2 : 0);
+        rc.flag = (xpark ? 0 : 1) | (br ? 2 : 0) | (LVL ? mlev << 2 : 0);
         rc.x[0] = x0;
         rc.x[1] = x1;
         rc.x[2] = x2;
@@ -518,10 +538,11 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         rc.ev = ev;
         rc.ncross = ncross;
         b.u_out[idx] = rc;
-        uint32_t key = own_key;
+        const uint32_t kslot = LVL ? (uint32_t)mlev : (uint32_t)it.slot;
+        uint32_t key = LVL ? kslot * (uint32_t)b.n_regions + (uint32_t)it.region : own_key;
         if (!xpark) {
           const int32_t K0 = I0 + (xax == 0 ? xsg : 0), K1 = I1 + (xax == 1 ? xsg : 0), K2 = I2 + (xax == 2 ? xsg : 0);
-          key = (uint32_t)it.slot * (uint32_t)b.n_regions +
+          key = kslot * (uint32_t)b.n_regions +
                 (uint32_t)region_walk(b, D, lev, K0, K1, K2, xax, xsg, x0, x1, x2);
         }
         b.u_key[idx] = key;
@@ -707,7 +728,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   }
 }
 
-template <int BS, bool SPLIT, bool PEEL, bool ALI>
+template <int BS, bool SPLIT, bool PEEL, bool ALI, bool LVL>
 __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int cap = b.cap;
@@ -747,14 +768,14 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     if (tid == 0) s_next = 0;
     __syncthreads();
     if (R.n <= cap)
-      run_item<true, SPLIT, PEEL, ALI>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
+      run_item<true, SPLIT, PEEL, ALI, LVL>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
                      c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip);
     else
-      run_item<false, SPLIT, PEEL, ALI>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
+      run_item<false, SPLIT, PEEL, ALI, LVL>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
                       c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip);
     __syncthreads();
     if (b.accb64) {
-      double* __restrict__ gacc64 = b.accb64 + R.gbase;
+      double* __restrict__ gacc64 = b.accb64 + (LVL ? (int64_t)it.slot * b.accb_stride : int64_t(0)) + R.gbase;
       for (int i = tid; i < nloc; i += BS) {
         const float v = s_acc[i];
         if (v != 0.0f) unsafeAtomicAdd(gacc64 + i, (double)v);
@@ -809,6 +830,7 @@ __global__ __launch_bounds__(256) void blk_reduce_kernel(const ModelDev* __restr
                                                          const double* __restrict__ accb64, int64_t stride,
                                                          int n_slots, double* __restrict__ e_node,
                                                          double* __restrict__ e_lam_node,
+                                                         double* __restrict__ lvl_out, int64_t lvl_stride,
                                                          double* __restrict__ e_total) {
   __shared__ double s_part[4];
   const RegionDev& R = regions[blockIdx.y];
@@ -820,7 +842,12 @@ __global__ __launch_bounds__(256) void blk_reduce_kernel(const ModelDev* __restr
     const int32_t c = rcanon[gidx];
     if (c >= 0) {
       if (accb64) {
-        sum = accb64[gidx];
+        // one FP64 slot, or one per level (subiterations): the arrays and their sum
+        for (int s = 0; s < n_slots; ++s) {
+          const double v = accb64[s * stride + gidx];
+          sum += v;
+          if (lvl_out) lvl_out[s * lvl_stride + m.canon_base + c] = v;
+        }
       } else {
         const int ns = n_slots > 1 ? m.nl : 1;
         for (int s = 0; s < ns; ++s) {
@@ -848,23 +875,25 @@ hipError_t launch_blk_emit(const BlkParams& b, const SweepState* st, uint64_t ba
   return hipGetLastError();
 }
 
-// Instances: any combination of splitting and peel-off, and the accelerated-iteration tally
-// with or without splitting (the peel-off never runs inside a Lambda iteration).
-template <bool SPLIT, bool PEEL, bool ALI>
+// Instances: any combination of splitting and peel-off, the accelerated-iteration tally with or
+// without splitting (the peel-off never runs inside a Lambda iteration), and the per-level
+// arrays of subiterations on their own.
+template <bool SPLIT, bool PEEL, bool ALI, bool LVL>
 static const void* pass_fn(int block) {
   switch (block) {
-    case 256: return (const void*)blk_pass_kernel<256, SPLIT, PEEL, ALI>;
-    case 512: return (const void*)blk_pass_kernel<512, SPLIT, PEEL, ALI>;
-    case 768: return (const void*)blk_pass_kernel<768, SPLIT, PEEL, ALI>;
-    case 1024: return (const void*)blk_pass_kernel<1024, SPLIT, PEEL, ALI>;
+    case 256: return (const void*)blk_pass_kernel<256, SPLIT, PEEL, ALI, LVL>;
+    case 512: return (const void*)blk_pass_kernel<512, SPLIT, PEEL, ALI, LVL>;
+    case 768: return (const void*)blk_pass_kernel<768, SPLIT, PEEL, ALI, LVL>;
+    case 1024: return (const void*)blk_pass_kernel<1024, SPLIT, PEEL, ALI, LVL>;
     default: return nullptr;
   }
 }
 
 hipError_t attr_blk_pass(int block, int lds_bytes) {
-  for (const void* f : {pass_fn<false, false, false>(block), pass_fn<true, false, false>(block),
-                        pass_fn<false, true, false>(block), pass_fn<true, true, false>(block),
-                        pass_fn<false, false, true>(block), pass_fn<true, false, true>(block)}) {
+  for (const void* f : {pass_fn<false, false, false, false>(block), pass_fn<true, false, false, false>(block),
+                        pass_fn<false, true, false, false>(block), pass_fn<true, true, false, false>(block),
+                        pass_fn<false, false, true, false>(block), pass_fn<true, false, true, false>(block),
+                        pass_fn<false, false, false, true>(block)}) {
     if (!f) return hipErrorInvalidValue;
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
@@ -872,13 +901,13 @@ hipError_t attr_blk_pass(int block, int lds_bytes) {
   return hipSuccess;
 }
 
-template <bool SPLIT, bool PEEL, bool ALI>
+template <bool SPLIT, bool PEEL, bool ALI, bool LVL>
 static hipError_t launch_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s) {
   switch (block) {
-    case 256: hipLaunchKernelGGL((blk_pass_kernel<256, SPLIT, PEEL, ALI>), dim3(grid), dim3(256), lds_bytes, s, b); break;
-    case 512: hipLaunchKernelGGL((blk_pass_kernel<512, SPLIT, PEEL, ALI>), dim3(grid), dim3(512), lds_bytes, s, b); break;
-    case 768: hipLaunchKernelGGL((blk_pass_kernel<768, SPLIT, PEEL, ALI>), dim3(grid), dim3(768), lds_bytes, s, b); break;
-    case 1024: hipLaunchKernelGGL((blk_pass_kernel<1024, SPLIT, PEEL, ALI>), dim3(grid), dim3(1024), lds_bytes, s, b); break;
+    case 256: hipLaunchKernelGGL((blk_pass_kernel<256, SPLIT, PEEL, ALI, LVL>), dim3(grid), dim3(256), lds_bytes, s, b); break;
+    case 512: hipLaunchKernelGGL((blk_pass_kernel<512, SPLIT, PEEL, ALI, LVL>), dim3(grid), dim3(512), lds_bytes, s, b); break;
+    case 768: hipLaunchKernelGGL((blk_pass_kernel<768, SPLIT, PEEL, ALI, LVL>), dim3(grid), dim3(768), lds_bytes, s, b); break;
+    case 1024: hipLaunchKernelGGL((blk_pass_kernel<1024, SPLIT, PEEL, ALI, LVL>), dim3(grid), dim3(1024), lds_bytes, s, b); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -886,23 +915,28 @@ static hipError_t launch_pass(const BlkParams& b, int grid, int block, int lds_b
 
 hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s) {
   const bool split = b.t.split_n > 1, peel = b.t.peel_ev != nullptr, ali = b.t.self_acc != nullptr;
+  if (b.lvl_slots > 0) {
+    // the per-level arrays need one FP64 accumulator slot per level; nothing else rides along
+    if (split || peel || ali || !b.accb64) return hipErrorInvalidValue;
+    return launch_pass<false, false, false, true>(b, grid, block, lds_bytes, s);
+  }
   if (ali) {
     if (peel) return hipErrorInvalidValue;
-    return split ? launch_pass<true, false, true>(b, grid, block, lds_bytes, s)
-                 : launch_pass<false, false, true>(b, grid, block, lds_bytes, s);
+    return split ? launch_pass<true, false, true, false>(b, grid, block, lds_bytes, s)
+                 : launch_pass<false, false, true, false>(b, grid, block, lds_bytes, s);
   }
-  if (split) return peel ? launch_pass<true, true, false>(b, grid, block, lds_bytes, s)
-                         : launch_pass<true, false, false>(b, grid, block, lds_bytes, s);
-  return peel ? launch_pass<false, true, false>(b, grid, block, lds_bytes, s)
-              : launch_pass<false, false, false>(b, grid, block, lds_bytes, s);
+  if (split) return peel ? launch_pass<true, true, false, false>(b, grid, block, lds_bytes, s)
+                         : launch_pass<true, false, false, false>(b, grid, block, lds_bytes, s);
+  return peel ? launch_pass<false, true, false, false>(b, grid, block, lds_bytes, s)
+              : launch_pass<false, false, false, false>(b, grid, block, lds_bytes, s);
 }
 
 hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, int n_regions,
                              int32_t max_region_nodes, const int32_t* rcanon, const float* accb,
                              const double* accb64, int64_t stride, int n_slots, double* e_node, double* e_lam_node,
-                             double* e_total, hipStream_t s) {
+                             double* lvl_out, int64_t lvl_stride, double* e_total, hipStream_t s) {
   if (n_regions == 0) return hipSuccess;
   hipLaunchKernelGGL(blk_reduce_kernel, dim3((max_region_nodes + 255) / 256, n_regions), dim3(256), 0, s, models,
-                     regions, rcanon, accb, accb64, stride, n_slots, e_node, e_lam_node, e_total);
+                     regions, rcanon, accb, accb64, stride, n_slots, e_node, e_lam_node, lvl_out, lvl_stride, e_total);
   return hipGetLastError();
 }

@@ -201,7 +201,8 @@ struct BlkParams {
   const int32_t* split_tab;    // 8 per split cell, by child octant: region id, or ~s (split again)
   float* accb;               // [slots][G] region-major FP32 accumulators (per-wavelength output)
   double* accb64;            // [G] region-major FP64 accumulators (wavelength-integrated output);
-                             // when set, every key has slot 0 and accb is unused
+                             // when set, every key has slot 0 and accb is unused; with
+                             // lvl_slots > 0, [lvl_slots][G]
   int64_t accb_stride;       // G
   // queues
   PRec* u_out;               // append target
@@ -212,7 +213,9 @@ struct BlkParams {
   const WorkItem* items;
   const uint32_t* n_items;
   uint32_t* item_counter;
-  int32_t n_slots_key;       // accumulator slots (wavelengths) in the key
+  int32_t n_slots_key;       // accumulator slots (wavelengths, or levels) in the key
+  int32_t lvl_slots;         // > 0: subiterations; the slots are the shallowest level visited
+                             // (levels 0..lvl_slots-1), accumulated in FP64 (accb64)
   int32_t chunk;             // packets per work item
   int32_t tail_park;         // crossing rounds after an item's queue runs dry before the
                              // packets still in flight are re-queued (INT32_MAX = never)
@@ -258,7 +261,7 @@ hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, i
                              int32_t max_region_nodes, const int32_t* rcanon, const float* accb,
                              const double* accb64,
                              int64_t stride, int n_slots, double* e_node, double* e_lam_node,
-                             double* e_total, hipStream_t s);
+                             double* lvl_out, int64_t lvl_stride, double* e_total, hipStream_t s);
 
 // Launch wrappers (defined in the .hip files)
 hipError_t launch_trace_fp64(const TraceParams& p, int job, uint64_t n, int block, hipStream_t s);

@@ -1048,8 +1048,13 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   p.lvl_stride = out.lvl_stride;
   p.sub_lev = out.sub_lev;
   for (int a = 0; a < 3; ++a) p.sub_I[a] = out.sub_I[a];
-  if ((out.lvl_acc || out.sub_lev >= 0) && fp32)
-    return fail(ctx, RT_EINVAL, "subiterations are implemented in the RT_FP64 form");
+  if ((out.lvl_acc || out.sub_lev >= 0) && fp32) {
+    if (o->schedule != RT_SCHED_REGIONS)
+      return fail(ctx, RT_EINVAL, "subiterations run in the RT_FP64 form or the region schedule");
+    if (!out.lvl_acc || p.split_n > 1 || out.peel || out.self_acc || out.e_lamnode)
+      return fail(ctx, RT_EINVAL, "subiterations in the region schedule take no splitting, peel-off, "
+                                  "accelerated tally or per-wavelength output");
+  }
   if (out.peel) {
     p.peel_ev = const_cast<PeelEv*>(out.peel->ev);
     p.peel_count = out.peel->count;
@@ -1058,6 +1063,11 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   const int grid_peel = ctx->n_cu * 8;
 
   const bool regions = fp32 && o->schedule == RT_SCHED_REGIONS;
+  // subiterations in the region schedule: the key slots are the shallowest level visited
+  int n_lvl = 0;
+  if (regions && out.lvl_acc)
+    for (const HostModel& h : ctx->models) n_lvl = std::max(n_lvl, h.nlev + 1);
+  const int key_slots = n_lvl > 0 ? n_lvl : n_slots;
   int reg_lds = 0, reg_per_cu = 0;
   if (regions) {
     // LDS per block: node words + accumulators (4 + 4 B per node) + parent links (4 B per oct)
@@ -1068,8 +1078,10 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     reg_lds = 8 * cap + 4 * (cap / 8);
     if (rt_status e = build_regions(ctx, cap)) return e;
     HIPCHK(attr_blk_pass(bs, reg_lds));
-    // per-wavelength output: FP32 slots; wavelength-integrated: one FP64 accumulator per node
-    const size_t racc = n_slots > 1 ? (size_t)n_slots * ctx->reg_G * 4 : (size_t)ctx->reg_G * 8;
+    // per-wavelength output: FP32 slots; wavelength-integrated: one FP64 accumulator per node;
+    // subiterations: one FP64 accumulator per (level, node)
+    const size_t racc = n_lvl > 0 ? (size_t)n_lvl * ctx->reg_G * 8
+                                  : (n_slots > 1 ? (size_t)n_slots * ctx->reg_G * 4 : (size_t)ctx->reg_G * 8);
     HIPCHK(ctx->acc.ensure(racc));
     HIPCHK(hipMemsetAsync(ctx->acc.p, 0, racc, ctx->stream));
   }
@@ -1078,7 +1090,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
   if (start > 0 && regions) {
     const int n_regions = (int)ctx->h_regions.size();
-    const int64_t n_keys = (int64_t)n_slots * n_regions;
+    const int64_t n_keys = (int64_t)key_slots * n_regions;
     if (n_keys > (int64_t(1) << 28)) return fail(ctx, RT_EINVAL, "too many (wavelength, region) keys");
     const int64_t capq = std::min<int64_t>(int64_t(1) << 25, std::max<int64_t>((int64_t)start, 4096));
     const int64_t batch = std::min<int64_t>(o->batch_packets > 0 ? o->batch_packets : int64_t(1) << 23, capq);
@@ -1120,16 +1132,17 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     b.rcanon = ctx->d_rcanon.as<int32_t>();
     b.root_region = ctx->d_root_region.as<int32_t>();
     b.split_tab = ctx->d_split.as<int32_t>();
-    b.accb = n_slots > 1 ? ctx->acc.as<float>() : nullptr;
-    b.accb64 = n_slots > 1 ? nullptr : ctx->acc.as<double>();
+    b.accb = (n_slots > 1 && n_lvl == 0) ? ctx->acc.as<float>() : nullptr;
+    b.accb64 = (n_slots > 1 && n_lvl == 0) ? nullptr : ctx->acc.as<double>();
     b.accb_stride = ctx->reg_G;
+    b.lvl_slots = n_lvl;
     b.q_perm = ctx->q_perm.as<uint32_t>();
     b.items = ctx->q_items.as<WorkItem>();
     b.n_items = &st->n_items;
     b.item_counter = &st->item_counter;
     b.split_room = &st->split_room;
     b.split_used = &st->split_used;
-    b.n_slots_key = n_slots;
+    b.n_slots_key = key_slots;
     b.chunk = chunk;
     b.tail_park = o->tail_park < 0 ? INT32_MAX : (o->tail_park > 0 ? o->tail_park : 16);
     const int grid_pass = ctx->n_cu * reg_per_cu;
@@ -1242,9 +1255,11 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   if (regions) {
     HIPCHK(launch_blk_reduce(ctx->d_models.as<ModelDev>(), ctx->d_regions.as<RegionDev>(),
                              (int)ctx->h_regions.size(), ctx->reg_maxn, ctx->d_rcanon.as<int32_t>(),
-                             n_slots > 1 ? ctx->acc.as<float>() : nullptr,
-                             n_slots > 1 ? nullptr : ctx->acc.as<double>(), ctx->reg_G, n_slots, out.e_node,
-                             n_slots > 1 ? out.e_lamnode : nullptr, ctx->e_total.as<double>(), ctx->stream));
+                             (n_slots > 1 && n_lvl == 0) ? ctx->acc.as<float>() : nullptr,
+                             (n_slots > 1 && n_lvl == 0) ? nullptr : ctx->acc.as<double>(), ctx->reg_G,
+                             key_slots, out.e_node, (n_slots > 1 && n_lvl == 0) ? out.e_lamnode : nullptr,
+                             n_lvl > 0 ? out.lvl_acc : nullptr, out.lvl_stride, ctx->e_total.as<double>(),
+                             ctx->stream));
   } else {
     for (size_t m = 0; m < ctx->models.size(); ++m) {
       const HostModel& h = ctx->models[m];
@@ -1482,7 +1497,8 @@ rt_status rt_subiter_begin(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_s
   GUARD({
     if (rt_status s = check_model(ctx, model)) return s;
     if (!opts) return fail(ctx, RT_EINVAL, "null options");
-    if (opts->precision != RT_FP64) return fail(ctx, RT_EINVAL, "subiterations are implemented in the RT_FP64 form");
+    if (!(opts->precision == RT_FP64 || (opts->precision == RT_FP32_LOCAL && opts->schedule == RT_SCHED_REGIONS)))
+      return fail(ctx, RT_EINVAL, "subiterations run in the RT_FP64 form or the region schedule");
     if (!(t_min > 0.0) || !(t_max > t_min)) return fail(ctx, RT_EINVAL, "need 0 < t_min < t_max");
     for (int s = 0; s < n_src; ++s)
       if (src && (src[s].model != model || src[s].kind == RT_SRC_DUST))
@@ -1527,7 +1543,8 @@ rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust
   GUARD({
     if (rt_status s = check_model(ctx, model)) return s;
     if (!opts) return fail(ctx, RT_EINVAL, "null options");
-    if (opts->precision != RT_FP64) return fail(ctx, RT_EINVAL, "subiterations are implemented in the RT_FP64 form");
+    if (!(opts->precision == RT_FP64 || (opts->precision == RT_FP32_LOCAL && opts->schedule == RT_SCHED_REGIONS)))
+      return fail(ctx, RT_EINVAL, "subiterations run in the RT_FP64 form or the region schedule");
     HostModel& h = ctx->models[model];
     if (!h.sub_ready) return fail(ctx, RT_ESTATE, "rt_subiter_begin not called for model %d", model);
     if (dust_packets < 1 || dust_packets > (int64_t(1) << 32)) return fail(ctx, RT_EINVAL, "bad dust_packets");
@@ -1565,7 +1582,10 @@ rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust
     int64_t tn, tl, tln;
     totals(ctx, &tn, &tl, &tln);
     const int64_t cb = ctx->h_models[model].canon_base;
-    const size_t nlv = (size_t)(h.nlev + 1);
+    // level arrays for every level of every model on the device (the region schedule's
+    // reduction writes one per level of the deepest model)
+    size_t nlv = 1;
+    for (const HostModel& hm : ctx->models) nlv = std::max(nlv, (size_t)(hm.nlev + 1));
     HIPCHK(ctx->it_adust.ensure(8 * tn));
     HIPCHK(ctx->it_sum.ensure(8 * h.n_nodes));
     HIPCHK(ctx->it_told.ensure(8 * h.n_nodes));

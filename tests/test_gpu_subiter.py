@@ -1,8 +1,8 @@
-"""GPU parity of subiterations on complete subtrees (paper Sect. 3.1, Sect. 3.3, App. B) in the
-FP64 form against the oracle: the temperatures after each step of a schedule that mixes
-whole-model steps and subtree steps agree to the solver's precision, and the automatic choice
-of the next subtree is the lowest common ancestor of the most imbalanced leaves, as computed
-from the oracle's state."""
+"""GPU parity of subiterations on complete subtrees (paper Sect. 3.1, Sect. 3.3, App. B) against
+the oracle: in the FP64 form the temperatures after each step of a schedule that mixes
+whole-model steps and subtree steps agree to the solver's precision, in the FP32-local region
+schedule far below the Monte Carlo noise; the automatic choice of the next subtree is the lowest
+common ancestor of the most imbalanced leaves, as computed from the oracle's state."""
 import numpy as np
 import pytest
 
@@ -120,7 +120,7 @@ def test_subtree_selection(torch):
     ctx2.close()
 
 
-def test_subiterations_need_the_fp64_form(torch):
+def test_subiterations_check_their_arguments(torch):
     tree, dust, star = _block_case()
     ctx = rt.Context(0)
     m = ctx.build_tree(tree)
@@ -156,3 +156,76 @@ def test_automatic_iteration_replays_as_steps(torch):
         t_step, _, _ = ctx.subiter_step(m, int(r), dust_packets=4000, seed=3, iteration=k)
     ctx.close()
     np.testing.assert_allclose(t_step.cpu().numpy(), t_run.cpu().numpy(), rtol=1e-9)
+
+
+def _mass_weighted_diff(o, t, ref):
+    leaf = o.leaf_mask
+    lv = o.level_of_nodes()
+    w = (o.node_rho() * 8.0 ** -lv.astype(float))[leaf]
+    return float((w * np.abs(t[leaf] - ref[leaf]) / ref[leaf]).sum() / w.sum())
+
+
+def test_subiterations_regions_against_oracle(torch):
+    """The region schedule (FP32-local) on the same schedule of whole-model and subtree steps:
+    the queue is keyed by the shallowest level visited, so each step's level arrays and hence
+    its temperatures follow the oracle's; the mass-weighted temperature difference stays far
+    below that between two oracle runs with different seeds, and nothing outside the subtree
+    changes in a subtree step."""
+    tree, dust, star = _block_case()
+    root = 2 + 4 * (1 + 4 * 2)
+    schedule = [-1, root, root, -1]
+    o = oracle.Model(tree, dust)
+    ha, _, _ = oracle.subiterate(o, star, seed=8, schedule=schedule, dust_packets=3000)
+    hb, _, _ = oracle.subiterate(o, star, seed=41, schedule=schedule, dust_packets=3000)
+    inside = o.subtree_mask(root)
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    kw = dict(precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS)
+    ctx.subiter_begin(m, star, seed=8, **kw)
+    prev = None
+    for k, r in enumerate(schedule, start=1):
+        t, crit, st = ctx.subiter_step(m, r, dust_packets=3000, seed=8, iteration=k, **kw)
+        t = t.cpu().numpy()
+        err = _mass_weighted_diff(o, t, ha[k])
+        noise = _mass_weighted_diff(o, hb[k], ha[k])
+        assert err < 0.1 * noise, (k, err, noise)
+        assert st["packets"] > 0 and crit >= 0.0
+        if r >= 0:
+            assert np.array_equal(t[~inside], prev[~inside])
+        prev = t
+    ctx.close()
+
+
+def test_subtree_selection_regions(torch):
+    """The region schedule's whole-model step records the same imbalances as the FP64 form's up
+    to the FP32 rounding of the histories: the same subtree is chosen."""
+    tree, dust, star, core = _core_case()
+    picks = {}
+    for name, kw in (("fp64", dict(precision=rt.FP64)),
+                     ("regions", dict(precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS))):
+        ctx = rt.Context(0)
+        m = ctx.build_tree(tree)
+        ctx.set_dust(m, dust)
+        ctx.subiter_begin(m, star, seed=3, **kw)
+        ctx.subiter_step(m, -1, dust_packets=4000, seed=3, iteration=1, **kw)
+        picks[name] = ctx.subiter_select(m, 0.9)
+        ctx.close()
+    assert picks["regions"][0] == picks["fp64"][0], picks
+    assert abs(picks["regions"][1] - picks["fp64"][1]) <= 1e-3 * picks["fp64"][1], picks
+
+
+def test_subiterations_regions_reject_other_options(torch):
+    tree, dust, star = _block_case()
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    kw = dict(precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS)
+    with pytest.raises(rt.RTError):  # the one-queue FP32 form keeps no level arrays
+        ctx.subiter_begin(m, star, seed=1, precision=rt.FP32_LOCAL, schedule=rt.SCHED_GLOBAL)
+    ctx.subiter_begin(m, star, seed=1, **kw)
+    with pytest.raises(rt.RTError):  # no package splitting inside a subiteration
+        ctx.subiter_step(m, -1, dust_packets=100, seed=1, iteration=1, split_n=2, **kw)
+    t, _, _ = ctx.subiter_step(m, -1, dust_packets=100, seed=1, iteration=1, **kw)
+    assert float(t.max()) > 0.0
+    ctx.close()
