@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # device-to-device copy (fetch x2.0, write x1.0), per leaf crossing.  Valid only for the kernel
 # sources the counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "c1844dc0c9d2e0ab526e24b1b3b3eba9b7c8f7334eb0a6487c049863f38a60c0",
-                "fetch_bytes_per_crossing": 10.021, "write_bytes_per_crossing": 4.468}
+                "sha256": "06d9d57a3b243eaf65fa2c53b38ba06e0080b2a485b42b58d7d5434e7aadede0",
+                "fetch_bytes_per_crossing": 10.274, "write_bytes_per_crossing": 4.459}
 
 
 WORKLOADS = {
