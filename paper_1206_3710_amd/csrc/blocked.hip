@@ -124,27 +124,28 @@ __global__ __launch_bounds__(256) void blk_emit_kernel(const BlkParams b, const 
     if (p.emit_acc && J.kind == RT_SRC_DUST)
       unsafeAtomicAdd(p.emit_acc + md.canon_base + canon_of(md, k.node), k.w0);
   }
-  const uint64_t mask = __ballot(have);
-  if (mask) {
-    uint32_t blo = 0, bhi = 0;
-    if (lane == 0) {
-      const unsigned long long base = atomicAdd(b.u_count, (unsigned long long)__popcll(mask));
-      blo = (uint32_t)base;
-      bhi = (uint32_t)(base >> 32);
-    }
-    blo = __shfl(blo, 0, 64);
-    bhi = __shfl(bhi, 0, 64);
-    if (have) {
-      const uint64_t idx = (((uint64_t)bhi << 32) | blo) + lane_rank(mask);
-      b.u_out[idx] = r;
-      b.u_key[idx] = key;
-    }
+  // the sweep reserved records [0, ne) of the output buffer for its births
+  if (have) {
+    const uint64_t idx = gid - g0;
+    b.u_out[idx] = r;
+    b.u_key[idx] = key;
   }
+  // one pair of statistics atomics per block
+  __shared__ double s_e[4];
+  __shared__ unsigned long long s_n[4];
   e_emit = wave_sum(e_emit);
   npk = wave_sum_u64(npk);
-  if (lane == 0 && npk) {
-    unsafeAtomicAdd(&p.stats->e_emit, e_emit);
-    atomicAdd(&p.stats->packets, npk);
+  if (lane == 0) {
+    s_e[threadIdx.x >> 6] = e_emit;
+    s_n[threadIdx.x >> 6] = npk;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long n = s_n[0] + s_n[1] + s_n[2] + s_n[3];
+    if (n) {
+      unsafeAtomicAdd(&p.stats->e_emit, s_e[0] + s_e[1] + s_e[2] + s_e[3]);
+      atomicAdd(&p.stats->packets, n);
+    }
   }
 }
 

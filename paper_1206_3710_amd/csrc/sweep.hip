@@ -49,13 +49,15 @@ __global__ void sw_begin_kernel(SweepState* st, int in, int slot, uint64_t batch
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int out = 1 - in;
   const unsigned long long n_in = st->count[in];
-  st->count[out] = 0;
   st->item_counter = 0;
   st->n_items = 0;
   const unsigned long long rem = st->total - st->emitted;
   unsigned long long ne = rem < batch ? rem : batch;
   const unsigned long long room = capq > n_in ? capq - n_in : 0;
   if (ne > room) ne = room;
+  // this sweep's births own the first ne records of the output buffer (packet e0 + i at i);
+  // packets leaving their regions are appended after them
+  st->count[out] = ne;
   st->e0 = st->emitted;
   st->ne = ne;
   st->emitted += ne;
