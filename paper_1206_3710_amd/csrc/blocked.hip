@@ -228,7 +228,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
                                          double* s_esc, double* s_misc, bool esc_lds, int lane,
                                          unsigned long long& c_cross, uint32_t& c_scat, uint32_t& c_kill,
                                          uint32_t& c_trunc, uint32_t& c_split, uint32_t& c_skill,
-                                         uint32_t& c_sskip) {
+                                         uint32_t& c_sskip, uint64_t& ch_base, uint32_t& ch_used) {
   const TraceParams& p = b.t;
   const float rr_thr = (float)p.rr_thr, rr_p = (float)p.rr_p;
   const float rr_gain = rr_p > 0.0f ? 1.0f / (1.0f - rr_p) : 1.0f;
@@ -503,16 +503,26 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
     }
     const uint64_t ex = __ballot(state == B_EXIT);
     if (ex) {
-      uint32_t blo = 0, bhi = 0;
-      if (lane == 0) {
-        const unsigned long long base = atomicAdd(b.u_count, (unsigned long long)__popcll(ex));
-        blo = (uint32_t)base;
-        bhi = (uint32_t)(base >> 32);
+      // the wave writes into its own chunk of kExitChunk records of the next queue and takes a
+      // new one from the shared counter only when the chunk runs out
+      const uint32_t n_ex = (uint32_t)__popcll(ex);
+      const uint32_t left = kExitChunk - ch_used;
+      uint64_t nb = 0;
+      if (n_ex > left) {
+        uint32_t blo = 0, bhi = 0;
+        if (lane == 0) {
+          const unsigned long long base = atomicAdd(b.u_count, (unsigned long long)kExitChunk);
+          blo = (uint32_t)base;
+          bhi = (uint32_t)(base >> 32);
+        }
+        // lane 0 is active here (the phase is wave-uniform): the cursor stays in scalar registers
+        blo = (uint32_t)__builtin_amdgcn_readfirstlane((int)blo);
+        bhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)bhi);
+        nb = ((uint64_t)bhi << 32) | blo;
       }
-      blo = __shfl(blo, 0, 64);
-      bhi = __shfl(bhi, 0, 64);
       if (state == B_EXIT) {
-        const uint64_t idx = (((uint64_t)bhi << 32) | blo) + lane_rank(ex);
+        const uint32_t r = lane_rank(ex);
+        const uint64_t idx = r < left ? ch_base + ch_used + r : nb + (r - left);
         PRec rc;
         rc.I[0] = I0;
         rc.I[1] = I1;
@@ -549,6 +559,12 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         b.u_key[idx] = key;
         xpark = false;
         state = B_EMPTY;
+      }
+      if (n_ex > left) {
+        ch_base = nb;
+        ch_used = n_ex - left;
+      } else {
+        ch_used += n_ex;
       }
     }
 
@@ -745,6 +761,8 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   if (tid < 5) s_misc[tid] = 0.0;
   unsigned long long c_cross = 0;
   uint32_t c_scat = 0, c_kill = 0, c_trunc = 0, c_split = 0, c_skill = 0, c_sskip = 0;
+  uint64_t ch_base = 0;          // this wave's chunk of next-queue records (none yet: full)
+  uint32_t ch_used = kExitChunk;
 
   for (;;) {
     __syncthreads();
@@ -770,10 +788,10 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     __syncthreads();
     if (R.n <= cap)
       run_item<true, SPLIT, PEEL, ALI, LVL>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
-                     c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip);
+                     c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip, ch_base, ch_used);
     else
       run_item<false, SPLIT, PEEL, ALI, LVL>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
-                      c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip);
+                      c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip, ch_base, ch_used);
     __syncthreads();
     if (b.accb64) {
       double* __restrict__ gacc64 = b.accb64 + (LVL ? (int64_t)it.slot * b.accb_stride : int64_t(0)) + R.gbase;
@@ -792,6 +810,9 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
       for (int i = tid; i < md.nl; i += BS)
         if (s_esc[i] != 0.0) unsafeAtomicAdd(p.esc + md.lam_base + i, s_esc[i]);
   }
+
+  // the unused end of the wave's chunk holds no packets: the next sweep's sort skips it
+  for (uint32_t j = ch_used + (uint32_t)lane; j < kExitChunk; j += 64) b.u_key[ch_base + j] = kInvalidKey;
 
   const unsigned long long sc_cross = wave_sum_u64(c_cross);
   const unsigned long long sc_scat = wave_sum_u64(c_scat);

@@ -224,6 +224,12 @@ struct BlkParams {
 };
 
 // Device-resident state of the sweeps of one trace (all sizes the sweep launches need).
+// Queue records: each wave of the region pass takes kExitChunk records of the next queue at a
+// time for the packets leaving its regions; the part of its last chunk it does not fill keeps
+// kInvalidKey and is skipped by the sort.
+constexpr uint32_t kExitChunk = 128;
+constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;
+
 struct SweepState {
   unsigned long long count[2];  // records appended to queue buffer 0 / 1
   unsigned long long emitted;   // packets emitted so far (global packet index)

@@ -1098,13 +1098,15 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     // records per queue buffer: emission keeps each sweep's input + births within capq; with
     // package splitting a second capq holds the packages split off during a sweep
     const int64_t cap_all = p.split_n > 1 ? 2 * capq : capq;
-    if (ctx->q_capacity < cap_all) {
+    // plus the unused ends of the pass waves' last chunks of records (at most one chunk each)
+    const int64_t cap_rec = cap_all + (int64_t)ctx->n_cu * reg_per_cu * (bs / 64) * (int64_t)kExitChunk;
+    if (ctx->q_capacity < cap_rec) {
       for (int k = 0; k < 2; ++k) {
-        HIPCHK(ctx->q_rec[k].ensure(sizeof(PRec) * cap_all));
-        HIPCHK(ctx->q_key[k].ensure(4 * cap_all));
+        HIPCHK(ctx->q_rec[k].ensure(sizeof(PRec) * cap_rec));
+        HIPCHK(ctx->q_key[k].ensure(4 * cap_rec));
       }
-      HIPCHK(ctx->q_perm.ensure(4 * cap_all));
-      ctx->q_capacity = cap_all;
+      HIPCHK(ctx->q_perm.ensure(4 * cap_rec));
+      ctx->q_capacity = cap_rec;
     }
     HIPCHK(ctx->q_hist.ensure(4 * n_keys));
     HIPCHK(ctx->q_kfill.ensure(4 * n_keys));

@@ -4,12 +4,13 @@
 // launches: it is captured once as a HIP graph and replayed until the queues drain.
 //
 // One sweep, on queue buffer `in` (its records were appended during the previous sweep):
-//   begin    clear the other buffer's count, pick this sweep's emission range
+//   begin    pick this sweep's emission range and reserve its records in the other buffer
 //   hist     count the records per key (slot * n_regions + region)
 //   scan     exclusive offsets per key; cut each key's run into work items
 //   scatter  record index -> its place in key order (the permutation the pass reads through)
-//   pass     the region pass (blocked.hip) appends leaving packets to the other buffer, while
-//   emit     on a second stream appends newly born packets to the same buffer.
+//   pass     the region pass (blocked.hip) appends leaving packets to the other buffer, in
+//            per-wave chunks (unused chunk ends carry kInvalidKey and are skipped here), while
+//   emit     on a second stream writes newly born packets to the records begin reserved.
 #include "device.h"
 
 using namespace rtd;
@@ -90,9 +91,9 @@ __global__ __launch_bounds__(256) void sw_hist_kernel(const uint32_t* __restrict
   const uint64_t span = (uint64_t)gridDim.x * 256;
   for (uint64_t i0 = (uint64_t)blockIdx.x * 256; i0 < n; i0 += span) {
     const uint64_t i = i0 + threadIdx.x;
-    const bool v = i < n;
-    const uint32_t k = v ? keys[i] : 0u;
-    (void)agg_count(lds ? s_h : hist, k, v);
+    const uint32_t k = i < n ? keys[i] : kInvalidKey;
+    const bool v = k != kInvalidKey;  // unused records of a pass wave's last chunk
+    (void)agg_count(lds ? s_h : hist, v ? k : 0u, v);
   }
   if (lds) {
     __syncthreads();
@@ -157,8 +158,9 @@ __global__ __launch_bounds__(256) void sw_scatter_kernel(const uint32_t* __restr
     const uint64_t span = (uint64_t)gridDim.x * 256;
     for (uint64_t i0 = (uint64_t)blockIdx.x * 256; i0 < n; i0 += span) {
       const uint64_t i = i0 + threadIdx.x;
-      const bool v = i < n;
-      const uint32_t pos = agg_count(kfill, v ? keys[i] : 0u, v);
+      const uint32_t k = i < n ? keys[i] : kInvalidKey;
+      const bool v = k != kInvalidKey;
+      const uint32_t pos = agg_count(kfill, v ? k : 0u, v);
       if (v) perm[pos] = (uint32_t)i;
     }
     return;
@@ -170,8 +172,9 @@ __global__ __launch_bounds__(256) void sw_scatter_kernel(const uint32_t* __restr
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const uint64_t i = t0 + (uint64_t)j * 256 + threadIdx.x;
-      key[j] = i < n ? keys[i] : 0u;
-      rank[j] = agg_count(s_c, key[j], i < n);
+      key[j] = i < n ? keys[i] : kInvalidKey;
+      const bool v = key[j] != kInvalidKey;
+      rank[j] = agg_count(s_c, v ? key[j] : 0u, v);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < n_keys; k += 256) {
@@ -182,7 +185,7 @@ __global__ __launch_bounds__(256) void sw_scatter_kernel(const uint32_t* __restr
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const uint64_t i = t0 + (uint64_t)j * 256 + threadIdx.x;
-      if (i < n) perm[s_c[key[j]] + rank[j]] = (uint32_t)i;
+      if (i < n && key[j] != kInvalidKey) perm[s_c[key[j]] + rank[j]] = (uint32_t)i;
     }
     __syncthreads();
   }
