@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # device-to-device copy (fetch x2.0, write x1.0), per leaf crossing.  Valid only for the kernel
 # sources the counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "06d9d57a3b243eaf65fa2c53b38ba06e0080b2a485b42b58d7d5434e7aadede0",
-                "fetch_bytes_per_crossing": 10.274, "write_bytes_per_crossing": 4.459}
+                "sha256": "01c8c1b90c70eda18d085589c31c88500a056b03173cb7b4d10bb468339de157",
+                "fetch_bytes_per_crossing": 10.433, "write_bytes_per_crossing": 4.878}
 
 
 WORKLOADS = {
