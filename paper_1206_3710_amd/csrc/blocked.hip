@@ -63,90 +63,62 @@ __device__ __forceinline__ int32_t region_walk(const BlkParams& b, const Dims& D
 }
 
 // ------------------------------------------------------------------------------------------
-// emission into the queue
+// emission into the queue (run by the pass kernel's blocks once the sweep's work items are
+// taken: the births fill the tail of the pass)
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void blk_emit_kernel(const BlkParams b, const SweepState* __restrict__ st) {
-  const uint64_t g0 = st->e0, g1 = st->e0 + st->ne;
-  __shared__ uint64_t s_start[RT_JOBS_LDS];
+// Birth of packet gid (global index over the trace's jobs) into record gid - g0 of the next
+// queue, which the sweep reserved for its births.  s_start: the jobs' first packet indices in
+// LDS when jobs_lds.
+__device__ __forceinline__ void emit_one(const BlkParams& b, uint64_t gid, uint64_t g0,
+                                         const uint64_t* s_start, bool jobs_lds, double& e_emit,
+                                         unsigned long long& npk) {
   const TraceParams& p = b.t;
-  const bool jobs_lds = p.n_jobs <= RT_JOBS_LDS;
-  if (jobs_lds)
-    for (int i = threadIdx.x; i < p.n_jobs; i += 256) s_start[i] = p.jobs[i].start;
-  __syncthreads();
-  const uint64_t gid = g0 + (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const bool have = gid < g1;
+  int lo = 0, hi = p.n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const uint64_t st = jobs_lds ? s_start[mid] : p.jobs[mid].start;
+    if (st <= gid) lo = mid;
+    else hi = mid - 1;
+  }
+  const JobDev& J = p.jobs[lo];
+  const ModelDev& md = p.models[J.model];
+  const Dims D = dims_of(md);
+  const uint32_t pid = (uint32_t)(gid - J.start);
+  Pk64 k;
+  emit64(p, J, D, md.n_leaves, md.leaf_base, pid, k, ChildWord{p.word});
   PRec r;
-  uint32_t key = 0;
-  double e_emit = 0.0;
-  unsigned long long npk = 0;
-  if (have) {
-    int lo = 0, hi = p.n_jobs - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      const uint64_t st = jobs_lds ? s_start[mid] : p.jobs[mid].start;
-      if (st <= gid) lo = mid;
-      else hi = mid - 1;
-    }
-    const JobDev& J = p.jobs[lo];
-    const ModelDev& md = p.models[J.model];
-    const Dims D = dims_of(md);
-    const uint32_t pid = (uint32_t)(gid - J.start);
-    Pk64 k;
-    emit64(p, J, D, md.n_leaves, md.leaf_base, pid, k, ChildWord{p.word});
-    const double sc = ldexp(1.0, k.lev);
+  const double sc = ldexp(1.0, k.lev);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      r.I[q] = k.I[q];
-      r.x[q] = clamp01((float)(k.P[q] * sc - (double)k.I[q]));
-      r.d[q] = (float)k.d[q];
-      r.O[q] = k.P[q];
-    }
-    r.lev = (uint8_t)k.lev;
-    r.ax = 0;
-    r.sg = 0;
-    // subiterations: the shallowest level visited starts at the birth cell's (0 for the external
-    // field, which enters through the root grid) and is the slot of the queue key
-    const uint32_t mslot = b.lvl_slots > 0 ? (J.kind == RT_SRC_BACKGROUND ? 0u : (uint32_t)k.lev) : (uint32_t)J.slot;
-    r.flag = b.lvl_slots > 0 ? (uint8_t)(mslot << 2) : 0;
-    r.w0 = (float)k.w0;
-    r.w = r.w0;
-    r.tau = (float)k.tau;
-    r.birth = k.node;
-    r.pid = pid;
-    r.job = lo;
-    r.ev = 0;
-    r.ncross = 1;
-    key = mslot * (uint32_t)b.n_regions +
-          (uint32_t)region_walk(b, D, k.lev, k.I[0], k.I[1], k.I[2], -1, 1, 0.5f, 0.5f, 0.5f);
-    e_emit = k.w0;
-    npk = 1;
-    if (p.emit_acc && J.kind == RT_SRC_DUST)
-      unsafeAtomicAdd(p.emit_acc + md.canon_base + canon_of(md, k.node), k.w0);
+  for (int q = 0; q < 3; ++q) {
+    r.I[q] = k.I[q];
+    r.x[q] = clamp01((float)(k.P[q] * sc - (double)k.I[q]));
+    r.d[q] = (float)k.d[q];
+    r.O[q] = k.P[q];
   }
-  // the sweep reserved records [0, ne) of the output buffer for its births
-  if (have) {
-    const uint64_t idx = gid - g0;
-    b.u_out[idx] = r;
-    b.u_key[idx] = key;
-  }
-  // one pair of statistics atomics per block
-  __shared__ double s_e[4];
-  __shared__ unsigned long long s_n[4];
-  e_emit = wave_sum(e_emit);
-  npk = wave_sum_u64(npk);
-  if (lane == 0) {
-    s_e[threadIdx.x >> 6] = e_emit;
-    s_n[threadIdx.x >> 6] = npk;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned long long n = s_n[0] + s_n[1] + s_n[2] + s_n[3];
-    if (n) {
-      unsafeAtomicAdd(&p.stats->e_emit, s_e[0] + s_e[1] + s_e[2] + s_e[3]);
-      atomicAdd(&p.stats->packets, n);
-    }
-  }
+  r.lev = (uint8_t)k.lev;
+  r.ax = 0;
+  r.sg = 0;
+  // subiterations: the shallowest level visited starts at the birth cell's (0 for the external
+  // field, which enters through the root grid) and is the slot of the queue key
+  const uint32_t mslot = b.lvl_slots > 0 ? (J.kind == RT_SRC_BACKGROUND ? 0u : (uint32_t)k.lev) : (uint32_t)J.slot;
+  r.flag = b.lvl_slots > 0 ? (uint8_t)(mslot << 2) : 0;
+  r.w0 = (float)k.w0;
+  r.w = r.w0;
+  r.tau = (float)k.tau;
+  r.birth = k.node;
+  r.pid = pid;
+  r.job = lo;
+  r.ev = 0;
+  r.ncross = 1;
+  const uint32_t key = mslot * (uint32_t)b.n_regions +
+                       (uint32_t)region_walk(b, D, k.lev, k.I[0], k.I[1], k.I[2], -1, 1, 0.5f, 0.5f, 0.5f);
+  e_emit += k.w0;
+  ++npk;
+  if (p.emit_acc && J.kind == RT_SRC_DUST)
+    unsafeAtomicAdd(p.emit_acc + md.canon_base + canon_of(md, k.node), k.w0);
+  const uint64_t idx = gid - g0;
+  b.u_out[idx] = r;
+  b.u_key[idx] = key;
 }
 
 // Land in the neighbour after a face crossing: from cell `cur` at level l (an ancestor-level
@@ -754,11 +726,13 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   int32_t* s_up = reinterpret_cast<int32_t*>(smem + 8 * (size_t)cap);
   __shared__ int s_item;
   __shared__ uint32_t s_next;
-  __shared__ double s_misc[5];
+  __shared__ double s_misc[6];
+  __shared__ unsigned long long s_npk;
   __shared__ double s_esc[kEscLds];
   const TraceParams& p = b.t;
   const int tid = threadIdx.x, lane = tid & 63;
-  if (tid < 5) s_misc[tid] = 0.0;
+  if (tid < 6) s_misc[tid] = 0.0;
+  if (tid == 0) s_npk = 0;
   unsigned long long c_cross = 0;
   uint32_t c_scat = 0, c_kill = 0, c_trunc = 0, c_split = 0, c_skill = 0, c_sskip = 0;
   uint64_t ch_base = 0;          // this wave's chunk of next-queue records (none yet: full)
@@ -811,6 +785,34 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
         if (s_esc[i] != 0.0) unsafeAtomicAdd(p.esc + md.lam_base + i, s_esc[i]);
   }
 
+  // this sweep's births, in chunks of BS packets, once every work item is taken
+  {
+    const uint64_t g0 = b.sweep->e0, g1 = g0 + b.sweep->ne;
+    if (g1 > g0) {
+      uint64_t* s_start = reinterpret_cast<uint64_t*>(smem);  // the region's LDS is free now
+      const bool jobs_lds = p.n_jobs <= RT_JOBS_LDS && p.n_jobs <= b.cap;
+      __syncthreads();
+      if (jobs_lds)
+        for (int i = tid; i < p.n_jobs; i += BS) s_start[i] = p.jobs[i].start;
+      double e_emit = 0.0;
+      unsigned long long npk = 0;
+      for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = (int)atomicAdd(b.emit_counter, 1u);
+        __syncthreads();
+        const uint64_t base = g0 + (uint64_t)(uint32_t)s_item * BS;
+        if (base >= g1) break;
+        if (base + (uint64_t)tid < g1) emit_one(b, base + (uint64_t)tid, g0, s_start, jobs_lds, e_emit, npk);
+      }
+      e_emit = wave_sum(e_emit);
+      npk = wave_sum_u64(npk);
+      if (lane == 0 && npk) {
+        atomicAdd(&s_misc[5], e_emit);
+        atomicAdd(&s_npk, npk);
+      }
+    }
+  }
+
   // the unused end of the wave's chunk holds no packets: the next sweep's sort skips it
   for (uint32_t j = ch_used + (uint32_t)lane; j < kExitChunk; j += 64) b.u_key[ch_base + j] = kInvalidKey;
 
@@ -841,6 +843,10 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     if (s_misc[2] != 0.0) unsafeAtomicAdd(&p.stats->e_trunc, s_misc[2]);
     if (s_misc[3] != 0.0) unsafeAtomicAdd(&p.stats->e_split_killed, s_misc[3]);
     if (s_misc[4] != 0.0) unsafeAtomicAdd(&p.stats->e_split_gain, s_misc[4]);
+    if (s_npk) {
+      unsafeAtomicAdd(&p.stats->e_emit, s_misc[5]);
+      atomicAdd(&p.stats->packets, s_npk);
+    }
   }
 }
 
@@ -891,11 +897,6 @@ __global__ __launch_bounds__(256) void blk_reduce_kernel(const ModelDev* __restr
 }
 
 }  // namespace
-
-hipError_t launch_blk_emit(const BlkParams& b, const SweepState* st, uint64_t batch, hipStream_t s) {
-  hipLaunchKernelGGL(blk_emit_kernel, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, b, st);
-  return hipGetLastError();
-}
 
 // Instances: any combination of splitting and peel-off, the accelerated-iteration tally with or
 // without splitting (the peel-off never runs inside a Lambda iteration), and the per-level

@@ -188,6 +188,8 @@ struct WorkItem {
   uint32_t start, count;
 };
 
+struct SweepState;
+
 struct BlkParams {
   TraceParams t;
   const RegionDev* regions;
@@ -213,6 +215,8 @@ struct BlkParams {
   const WorkItem* items;
   const uint32_t* n_items;
   uint32_t* item_counter;
+  const SweepState* sweep;   // this sweep's emission range [e0, e0 + ne)
+  uint32_t* emit_counter;    // chunks of births taken
   int32_t n_slots_key;       // accumulator slots (wavelengths, or levels) in the key
   int32_t lvl_slots;         // > 0: subiterations; the slots are the shallowest level visited
                              // (levels 0..lvl_slots-1), accumulated in FP64 (accb64)
@@ -238,6 +242,7 @@ struct SweepState {
   unsigned long long n_in;      // records in this sweep's input buffer
   uint32_t n_items, item_counter;
   uint32_t done;                // a sweep found nothing queued and nothing left to emit
+  uint32_t emit_counter;        // chunks of births taken by the pass kernel's blocks
   uint32_t sweeps;              // sweeps that had packets to follow
   unsigned long long split_room;  // queue room for split-off packages in this sweep
   unsigned long long split_used;  // records reserved for them so far
@@ -257,7 +262,6 @@ hipError_t launch_ali_absorbed(int64_t n, const double* a_stars, const double* a
                                const double* e_emit, double* out, hipStream_t s);
 hipError_t launch_peel_tables(const TraceParams& p, const PeelParams& q, hipStream_t s);
 hipError_t launch_peel(const TraceParams& p, const PeelParams& q, int grid, hipStream_t s);
-hipError_t launch_blk_emit(const BlkParams& b, const SweepState* st, uint64_t batch, hipStream_t s);
 hipError_t launch_sweep_sort(SweepState* st, int in, int slot, uint64_t batch, uint64_t capq, const uint32_t* keys,
                              int n_keys, int n_regions, int chunk, uint32_t* hist, uint32_t* kfill,
                              uint32_t* perm, WorkItem* items, int grid, hipStream_t s);

@@ -106,9 +106,7 @@ struct rt_ctx {
   std::vector<hipEvent_t> sweep_ev;        // 2 per sweep of the block: around each pass
   std::vector<int32_t> h_reg_nodes;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
-  // second stream: emission of the next batch runs beside the region pass
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
+  hipEvent_t ev_c = nullptr;
   hipStream_t work = nullptr;  // the sweeps of the region schedule (capturable: never the null stream)
 };
 
@@ -501,10 +499,7 @@ rt_status rt_create(rt_ctx** out, int32_t device, void* hip_stream) {
   ctx->n_cu = prop.multiProcessorCount;
   if (hipSetDevice(device) != hipSuccess || hipEventCreate(&ctx->ev0) != hipSuccess ||
       hipEventCreate(&ctx->ev1) != hipSuccess || hipEventCreate(&ctx->ev2) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ev_a, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ev_b, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_c, hipEventDisableTiming) != hipSuccess ||
-      hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&ctx->work, hipStreamNonBlocking) != hipSuccess) {
     delete ctx;
     return fail(nullptr, RT_EDEVICE, "cannot initialise device %d", device);
@@ -535,12 +530,9 @@ rt_status rt_destroy(rt_ctx* ctx) {
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
-  if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
-  if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
   if (ctx->sweep_exec) (void)hipGraphExecDestroy(ctx->sweep_exec);
   for (hipEvent_t e : ctx->sweep_ev) (void)hipEventDestroy(e);
   if (ctx->ev_c) (void)hipEventDestroy(ctx->ev_c);
-  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
   if (ctx->work) (void)hipStreamDestroy(ctx->work);
   delete ctx;
   return RT_OK;
@@ -1142,6 +1134,8 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     b.items = ctx->q_items.as<WorkItem>();
     b.n_items = &st->n_items;
     b.item_counter = &st->item_counter;
+    b.sweep = st;
+    b.emit_counter = &st->emit_counter;
     b.split_room = &st->split_room;
     b.split_used = &st->split_used;
     b.n_slots_key = key_slots;
@@ -1173,16 +1167,11 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
         bk.u_out = ctx->q_rec[out].as<PRec>();
         bk.u_key = ctx->q_key[out].as<uint32_t>();
         bk.u_count = &st->count[out];
-        // this sweep's new packets are born on the second stream while the pass runs
-        if ((e = hipEventRecord(ctx->ev_a, ctx->work)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(ctx->aux, ctx->ev_a, 0)) != hipSuccess) return e;
-        if ((e = launch_blk_emit(bk, st, (uint64_t)batch, ctx->aux)) != hipSuccess) return e;
-        if ((e = hipEventRecord(ctx->ev_b, ctx->aux)) != hipSuccess) return e;
+        // the pass kernel's blocks also write this sweep's births, once its work items are taken
         if (!capturing && (e = hipEventRecord(ctx->sweep_ev[2 * k], ctx->work)) != hipSuccess) return e;
         if ((e = launch_blk_pass(bk, grid_pass, bs, reg_lds, ctx->work)) != hipSuccess) return e;
         if (!capturing && (e = hipEventRecord(ctx->sweep_ev[2 * k + 1], ctx->work)) != hipSuccess) return e;
         if (peelp && (e = launch_peel(bk.t, *peelp, grid_peel, ctx->work)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(ctx->work, ctx->ev_b, 0)) != hipSuccess) return e;
       }
       return hipSuccess;
     };

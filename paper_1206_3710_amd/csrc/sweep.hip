@@ -9,8 +9,8 @@
 //   scan     exclusive offsets per key; cut each key's run into work items
 //   scatter  record index -> its place in key order (the permutation the pass reads through)
 //   pass     the region pass (blocked.hip) appends leaving packets to the other buffer, in
-//            per-wave chunks (unused chunk ends carry kInvalidKey and are skipped here), while
-//   emit     on a second stream writes newly born packets to the records begin reserved.
+//            per-wave chunks (unused chunk ends carry kInvalidKey and are skipped here); its
+//            blocks then write the sweep's births to the records begin reserved.
 #include "device.h"
 
 using namespace rtd;
@@ -51,6 +51,7 @@ __global__ void sw_begin_kernel(SweepState* st, int in, int slot, uint64_t batch
   const int out = 1 - in;
   const unsigned long long n_in = st->count[in];
   st->item_counter = 0;
+  st->emit_counter = 0;
   st->n_items = 0;
   const unsigned long long rem = st->total - st->emitted;
   unsigned long long ne = rem < batch ? rem : batch;
