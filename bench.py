@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # device-to-device copy (fetch x2.0, write x1.0), per leaf crossing.  Valid only for the kernel
 # sources the counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "01c8c1b90c70eda18d085589c31c88500a056b03173cb7b4d10bb468339de157",
-                "fetch_bytes_per_crossing": 10.433, "write_bytes_per_crossing": 4.878}
+                "sha256": "07b60a40fda63fa2bb812efbe1f5facda3ef409a301ebf9a141c0f4a8333eebb",
+                "fetch_bytes_per_crossing": 10.811, "write_bytes_per_crossing": 6.366}
 
 
 WORKLOADS = {

@@ -347,22 +347,20 @@ __device__ __forceinline__ void exit_coef(float d, float& n, float& c) {
   c = z ? INFINITY : (d > 0.0f ? r : 0.0f);
 }
 
-// 1 - exp(-q) for q >= 0 (the absorbed fraction of a segment).  Below 1/2 the Taylor
-// polynomial to q^8 (truncation below 2e-8 relative); above, the hardware base-2 exponential,
-// whose error of about one ulp of exp(-q) <= 0.61 stays below 2e-7 relative of the result.
+// 1 - exp(-q) for q >= 0 (the absorbed fraction of a segment).  Below 1/8 the Taylor
+// polynomial to q^5 (truncation below q^5/6! = 4.2e-8 relative); above, the hardware base-2
+// exponential, whose error of about one ulp of exp(-q) <= 0.89 is at most about 5e-7 relative
+// of the result (at q = 1/8).
 __device__ __forceinline__ float one_minus_exp(float q) {
-  // 1 - e^-q = q (1 - q Q(q)), Q(q) = 1/2! - q/3! + q^2/4! - ... + q^6/8!, in Horner form
-  float p = 2.48015873e-5f;         // 1/8!
-  p = fmaf(p, q, -1.98412698e-4f);  // -1/7!
-  p = fmaf(p, q, 1.38888889e-3f);   // 1/6!
-  p = fmaf(p, q, -8.33333333e-3f);  // -1/5!
-  p = fmaf(p, q, 4.16666667e-2f);   // 1/4!
-  p = fmaf(p, q, -1.66666667e-1f);  // -1/3!
-  p = fmaf(p, q, 0.5f);             // 1/2!
-  p = fmaf(p, -q, 1.0f);
+  // 1 - e^-q = q (1 - q/2 + q^2/3! - q^3/4! + q^4/5!), in Horner form
+  float p = 8.33333333e-3f;         // 1/5!
+  p = fmaf(p, q, -4.16666667e-2f);  // -1/4!
+  p = fmaf(p, q, 1.66666667e-1f);   // 1/3!
+  p = fmaf(p, q, -0.5f);            // -1/2!
+  p = fmaf(p, q, 1.0f);
   const float small = p * q;
   const float large = 1.0f - __builtin_amdgcn_exp2f(q * -1.44269504f);
-  return q < 0.5f ? small : large;
+  return q < 0.125f ? small : large;
 }
 
 // Henyey-Greenstein polar angle by inversion of its CDF (FP32), returned as its cosine and
