@@ -298,9 +298,12 @@ struct LamConst {
   double hnu;        // h nu
   double dnu;
 };
+// Temperatures of every leaf (tab: scratch of 4 + 2 kPlanckTable doubles for the inverse table
+// of the emission per unit mass, rebuilt by each call).
+constexpr int kPlanckTable = 2048;
 hipError_t launch_temperature(const ModelDev* models, int model, int64_t n_nodes,
                               const int32_t* child, const double* rho64, const double* a_node,
-                              const LamConst* lc, int nl, double t_min, double t_max,
+                              const LamConst* lc, int nl, double t_min, double t_max, double* tab,
                               double* t_out, hipStream_t s);
 hipError_t launch_dust_lum(const ModelDev* models, int model, int64_t n_leaves,
                            const int32_t* leaf_node, const uint8_t* leaf_level,

@@ -86,6 +86,7 @@ struct rt_ctx {
   std::vector<ModelDev> h_models;
   // work buffers
   DevBuf acc, esc, stats, counter, jobs, records, out_node, out_lamnode, out_esc, e_total;
+  DevBuf t_tab;  // inverse table of the emission per unit mass (temperature solves)
   DevBuf cdf_lum, cdf_q, cdf_qpre, lmax, scan_tmp;
   DevBuf tmp_in, tmp_out, tmp_out2, view, lamidx;
   DevBuf it_astars, it_adust, it_sum, it_told, it_crit, it_self, it_emit;
@@ -1306,9 +1307,10 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
 rt_status solve_T_impl(rt_ctx* ctx, int32_t model, const double* a_dev, double t_min, double t_max) {
   HostModel& h = ctx->models[model];
   HIPCHK(h.d_T.ensure(8 * h.n_nodes));
+  HIPCHK(ctx->t_tab.ensure(8 * (4 + 2 * (size_t)kPlanckTable)));
   HIPCHK(launch_temperature(ctx->d_models.as<ModelDev>(), model, h.n_nodes, ctx->d_child.as<int32_t>(),
                             ctx->d_rho64.as<double>(), a_dev, h.d_lc.as<LamConst>(), h.nl, t_min,
-                            t_max, h.d_T.as<double>(), ctx->stream));
+                            t_max, ctx->t_tab.as<double>(), h.d_T.as<double>(), ctx->stream));
   h.has_T = true;
   return RT_OK;
 }

@@ -24,12 +24,68 @@ __device__ __forceinline__ void planck_sum(const LamConst* __restrict__ lc, int 
   }
 }
 
+// Inverse table of the emission per unit mass, shared by every leaf of one solve: with
+// S(T) = sum kappa_abs B(T) dnu, tab = {S(t_min), S(t_max), y0 = ln S(t_min), dy} followed by n
+// pairs (u_i, du/dy at u_i), where u_i = ln T solves ln S = y0 + i dy (the same safeguarded
+// Newton as the leaves, from a linear guess).  dy is left non-positive when S is not
+// increasing and positive over [t_min, t_max]; the leaves then start from their linear guess.
+__global__ __launch_bounds__(256) void planck_table_kernel(const LamConst* __restrict__ lc, int nl, double t_min,
+                                                           double t_max, int n, double* __restrict__ tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s0, d0, s1, d1;
+  planck_sum(lc, nl, t_min, s0, d0);
+  planck_sum(lc, nl, t_max, s1, d1);
+  const bool ok = s0 > 0.0 && s1 > s0 && s1 < INFINITY;
+  const double y0 = ok ? log(s0) : 0.0, y1 = ok ? log(s1) : 0.0;
+  const double dy = ok ? (y1 - y0) / (double)(n - 1) : 0.0;
+  if (i == 0) {
+    tab[0] = s0;
+    tab[1] = s1;
+    tab[2] = y0;
+    tab[3] = dy;
+  }
+  if (i >= n || !ok) return;
+  const double y = i == n - 1 ? y1 : y0 + (double)i * dy;
+  double lo = log(t_min), hi = log(t_max);
+  double u = lo + (y - y0) / (y1 - y0) * (hi - lo);
+  if (!(u > lo && u < hi)) u = 0.5 * (lo + hi);
+  double s = 0.0, ds = 0.0, t = exp(u);
+  for (int it = 0; it < 200; ++it) {
+    t = exp(u);
+    planck_sum(lc, nl, t, s, ds);
+    const double g = log(s);
+    if (g < y) lo = u;
+    else hi = u;
+    double un;
+    if (s > 0.0 && ds > 0.0) {
+      un = u - (g - y) / (t * ds / s);
+      if (fabs(un - u) <= 1e-14) {  // converged (before the bracket test: see the leaves)
+        u = un;
+        break;
+      }
+      if (!(un > lo && un < hi)) un = 0.5 * (lo + hi);
+    } else {
+      un = 0.5 * (lo + hi);
+    }
+    const bool done = fabs(un - u) <= 1e-14 || hi - lo <= 1e-15;
+    u = un;
+    if (done) break;
+  }
+  t = exp(u);
+  planck_sum(lc, nl, t, s, ds);
+  tab[4 + 2 * i] = u;
+  tab[5 + 2 * i] = (s > 0.0 && ds > 0.0) ? s / (t * ds) : 0.0;
+}
+
 // Per leaf: the temperature at which the emitted power 4 pi m sum kappa_abs B(T) dnu equals
-// the absorbed power A.  Newton iteration on ln F(ln T), kept inside a shrinking bracket.
+// the absorbed power A.  Newton iteration on ln F(ln T), kept inside a shrinking bracket,
+// started from the inverse table (cubic Hermite in ln S): the root in one or two evaluations
+// of the sum.
 __global__ __launch_bounds__(256) void temperature_kernel(
     const ModelDev* __restrict__ models, int model, const int32_t* __restrict__ child,
     const double* __restrict__ rho64, const double* __restrict__ a_node,
-    const LamConst* __restrict__ lc, int nl, double t_min, double t_max, double* __restrict__ t_out) {
+    const LamConst* __restrict__ lc, int nl, double t_min, double t_max, const double* __restrict__ tab,
+    int n_tab, double* __restrict__ t_out) {
   const ModelDev& m = models[model];
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= m.n_nodes) return;
@@ -44,23 +100,36 @@ __global__ __launch_bounds__(256) void temperature_kernel(
   const double mass = rho64[internal] * (len * len * len);
   const double A = a_node[c];
   const double fpi = 4.0 * kPi;
-  double s, ds;
-  planck_sum(lc, nl, t_min, s, ds);
-  const double flo = fpi * mass * s;
+  const double flo = fpi * mass * tab[0];
   if (A <= flo) {
     t_out[c] = t_min;
     return;
   }
-  planck_sum(lc, nl, t_max, s, ds);
-  const double fhi = fpi * mass * s;
+  const double fhi = fpi * mass * tab[1];
   if (A >= fhi) {
     t_out[c] = t_max;
     return;
   }
   double lo = log(t_min), hi = log(t_max);
   const double la = log(A);
-  double u = lo + (la - log(flo)) / (log(fhi) - log(flo)) * (hi - lo);
+  double u;
+  const double y0 = tab[2], dy = tab[3];
+  if (dy > 0.0) {
+    double q = (la - log(fpi * mass) - y0) / dy;
+    // clamped into the table (a NaN absorbed power lands on entry 0)
+    q = q >= 0.0 ? (q <= (double)(n_tab - 1) ? q : (double)(n_tab - 1)) : 0.0;
+    int i = (int)q;
+    if (i > n_tab - 2) i = n_tab - 2;
+    const double f = q - (double)i;
+    const double u0 = tab[4 + 2 * i], g0 = tab[5 + 2 * i] * dy;
+    const double u1 = tab[6 + 2 * i], g1 = tab[7 + 2 * i] * dy;
+    const double f2 = f * f, f3 = f2 * f;
+    u = (2.0 * f3 - 3.0 * f2 + 1.0) * u0 + (f3 - 2.0 * f2 + f) * g0 + (3.0 * f2 - 2.0 * f3) * u1 + (f3 - f2) * g1;
+  } else {
+    u = lo + (la - log(flo)) / (log(fhi) - log(flo)) * (hi - lo);
+  }
   if (!(u > lo && u < hi)) u = 0.5 * (lo + hi);
+  double s, ds;
   for (int it = 0; it < 200; ++it) {
     const double t = exp(u);
     planck_sum(lc, nl, t, s, ds);
@@ -70,6 +139,13 @@ __global__ __launch_bounds__(256) void temperature_kernel(
     double un;
     if (f > 0.0 && ds > 0.0) {
       un = u - (log(f) - la) / (t * ds / s);
+      // a Newton step below the tolerance ends the iteration.  Tested before the bracket:
+      // where log(f) rounds to log(A) while f < A, the step is zero and un equals the new lower
+      // end, which the bracket test would replace by the midpoint of a wide bracket
+      if (fabs(un - u) <= 1e-14) {
+        u = un;
+        break;
+      }
       if (!(un > lo && un < hi)) un = 0.5 * (lo + hi);
     } else {
       un = 0.5 * (lo + hi);
@@ -184,10 +260,13 @@ hipError_t launch_subiter_update(const ModelDev* models, int model, int64_t n_le
 
 hipError_t launch_temperature(const ModelDev* models, int model, int64_t n_nodes,
                               const int32_t* child, const double* rho64, const double* a_node,
-                              const LamConst* lc, int nl, double t_min, double t_max,
+                              const LamConst* lc, int nl, double t_min, double t_max, double* tab,
                               double* t_out, hipStream_t s) {
+  hipLaunchKernelGGL(planck_table_kernel, dim3((kPlanckTable + 255) / 256), dim3(256), 0, s, lc, nl, t_min,
+                     t_max, kPlanckTable, tab);
   hipLaunchKernelGGL(temperature_kernel, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s,
-                     models, model, child, rho64, a_node, lc, nl, t_min, t_max, t_out);
+                     models, model, child, rho64, a_node, lc, nl, t_min, t_max, (const double*)tab,
+                     kPlanckTable, t_out);
   return hipGetLastError();
 }
 

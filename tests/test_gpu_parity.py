@@ -253,6 +253,28 @@ def test_temperature_parity(torch):
     assert np.all(tg[~leaf] == 0)
 
 
+@pytest.mark.parametrize("n_lambda", [12, 100])
+def test_temperature_converges_to_the_root(torch, n_lambda):
+    """The GPU solve (Newton started from an inverse table of the emission per unit mass) finds
+    the same root as the oracle's bisection to 1e-12, to 1e-10 relative, for radiation
+    temperatures spread over the whole bracket and past both ends."""
+    w = gen.c2(n_root=8, max_level=2, n_lambda=n_lambda, packets=1000)
+    ora = oracle.Model(w.trees[0], w.dusts[0])
+    rng = np.random.default_rng(11)
+    leaf = ora.leaf_mask
+    trad = np.exp(rng.uniform(np.log(1.0), np.log(5000.0), ora.n_nodes))
+    A = np.array([ora.emission(i, t) if leaf[i] else 0.0 for i, t in enumerate(trad)])
+    to = ora.solve_temperature(A, 2.0, 3000.0)
+    ctx = new_ctx(torch)
+    m = ctx.build_tree(w.trees[0])
+    ctx.set_dust(m, w.dusts[0])
+    tg = ctx.solve_temperature(m, A, 2.0, 3000.0).cpu().numpy()
+    np.testing.assert_allclose(tg[leaf], to[leaf], rtol=1e-10, atol=0)
+    inside = leaf & (trad > 2.5) & (trad < 2900.0)
+    np.testing.assert_allclose(tg[inside], trad[inside], rtol=1e-9)
+    assert np.all(tg[leaf & (trad <= 2.0)] == 2.0) and np.all(tg[leaf & (trad >= 3000.0)] == 3000.0)
+
+
 def test_render_parity(torch):
     """FP64 maps against the oracle: axis and oblique views, several wavelengths (two passes)."""
     w = gen.c2(n_root=16, max_level=2, n_lambda=20, packets=1000)
