@@ -36,14 +36,19 @@ sys.path.insert(0, ROOT)
 BYTES_PER_CROSSING_FP32 = 12.0   # packed density/subgrid word 4 B + FP32 accumulator RMW 8 B
 BYTES_PER_CROSSING_FP64 = 28.0   # FP64 density 8 B + child 4 B + FP64 accumulator RMW 16 B
 HBM_PEAK_GBS = 8000.0
+# VALU issue: 256 CUs x 4 SIMDs, one wave64 vector instruction per 4 cycles each (16 lanes per
+# SIMD; no packed FP32), 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0
 
 # HBM traffic of the region pass kernel, from two rocprofv3 --pmc runs of one trace step
 # (FETCH_SIZE, then WRITE_SIZE), each scaled by what the same counter reads for a 4 GiB
-# device-to-device copy (fetch x2.0, write x1.0), per leaf crossing.  Valid only for the kernel
-# sources the counters were taken on.
+# device-to-device copy (fetch x2.0, write x1.0), per leaf crossing; and its VALU wave-instructions
+# per leaf crossing (SQ_INSTS_VALU of the same step).  Valid only for the kernel sources the
+# counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "07b60a40fda63fa2bb812efbe1f5facda3ef409a301ebf9a141c0f4a8333eebb",
-                "fetch_bytes_per_crossing": 10.811, "write_bytes_per_crossing": 6.366}
+                "sha256": "8be39f5aa2ab71ef8f102d850368f1f8ad6375446d60393939c6f6fbb6a00fb0",
+                "fetch_bytes_per_crossing": 10.811, "write_bytes_per_crossing": 6.366,
+                "valu_per_crossing": 6.11}
 
 
 WORKLOADS = {
@@ -559,9 +564,16 @@ def main():
     else:  # replayed sweep graphs report no per-launch durations
         main_launch_s, achieved = float("nan"), float("nan")
     traffic = None
+    issue = None
     if a.workload == "cloud" and a.schedule == 0 and pass_sources_sha() == PASS_TRAFFIC["sha256"]:
         traffic = cr_step / launches * (PASS_TRAFFIC["fetch_bytes_per_crossing"]
                                         + PASS_TRAFFIC["write_bytes_per_crossing"])
+        # the limit the kernel actually meets: VALU issue (measured instructions per crossing x
+        # crossings per second while the pass kernel runs)
+        if main_launch_s == main_launch_s:
+            v = PASS_TRAFFIC["valu_per_crossing"] * cr_step / launches / main_launch_s
+            issue = {"unit": "VALU wave-instructions/s", "valu_per_crossing": PASS_TRAFFIC["valu_per_crossing"],
+                     "achieved": v, "peak": VALU_ISSUE_PEAK, "frac": v / VALU_ISSUE_PEAK}
 
     # plain FP64 form on the same inputs
     fp64 = None
@@ -637,7 +649,7 @@ def main():
                      "kernel": "blk_pass_kernel<%d>" % (kw32["block_size"] or 768) if a.schedule == 0
                                else "trace_fp32_kernel<%d>" % (kw32["block_size"] or 256),
                      "launches_per_step": launches, "avg_launch_ms": 1e3 * main_launch_s,
-                     "bytes_per_crossing": BYTES_PER_CROSSING_FP32},
+                     "bytes_per_crossing": BYTES_PER_CROSSING_FP32, "issue": issue},
         "autotune": tuned,
         "fp64": fp64,
         "accuracy": acc if fp64 is not None else None,

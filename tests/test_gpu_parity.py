@@ -418,6 +418,31 @@ def test_region_and_global_schedules_agree(torch):
     assert a["stats"]["scatterings"] == b["stats"]["scatterings"]
 
 
+@pytest.mark.parametrize("block,per_cu", [(256, 4), (512, 2), (768, 1), (1024, 1)])
+def test_region_launch_shapes_follow_the_same_histories(torch, block, per_cu):
+    """Every launch shape of the region pass, with small birth batches (many sweeps whose births
+    the pass kernel's blocks write after their work items) and small work items, follows the
+    global schedule's histories: the same per-packet fates, crossings and scatterings, the
+    same emitted energy, and per-node results equal to FP32 summation order.  Each pass wave
+    takes its next-queue records in chunks; the unused chunk ends must drop out of the sort."""
+    w = gen.c2(n_root=24, max_level=3, n_lambda=6, packets=20000)
+    ctx = new_ctx(torch)
+    m = ctx.build_tree(w.trees[0])
+    ctx.set_dust(m, w.dusts[0])
+    kw = dict(seed=w.seed, precision=rt.FP32_LOCAL, rr_threshold=w.rr_threshold, rr_prob=w.rr_prob,
+              rec_stride=5)
+    a = ctx.trace_packets(w.sources, schedule=rt.SCHED_GLOBAL, **kw)
+    b = ctx.trace_packets(w.sources, schedule=rt.SCHED_REGIONS, block_size=block, blocks_per_cu=per_cu,
+                          batch_packets=3000, chunk_packets=512, **kw)
+    for k in ("crossings", "scatterings", "kills", "packets"):
+        assert a["stats"][k] == b["stats"][k], k
+    assert abs(a["stats"]["e_emit"] - b["stats"]["e_emit"]) <= 1e-12 * a["stats"]["e_emit"]
+    ra, rb = a["records"], b["records"]
+    for f in ("status", "crossings", "events", "node", "birth"):
+        assert np.array_equal(ra[f], rb[f]), f
+    assert rel_rms(b["e_abs_node"].cpu().numpy(), a["e_abs_node"].cpu().numpy()) < 1e-5
+
+
 def test_region_tail_parking(torch):
     """Packets re-queued inside their cell when a work item's queue runs dry (forced after every
     crossing round here) resume without a counted crossing: same crossings, scatterings and
