@@ -47,7 +47,7 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0
 # counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
                 "sha256": "8be39f5aa2ab71ef8f102d850368f1f8ad6375446d60393939c6f6fbb6a00fb0",
-                "fetch_bytes_per_crossing": 10.811, "write_bytes_per_crossing": 6.366,
+                "fetch_bytes_per_crossing": 10.813, "write_bytes_per_crossing": 6.366,
                 "valu_per_crossing": 6.11}
 
 
