@@ -210,6 +210,7 @@ def peel_study(rt, gen, w, kw32, workload, packets=1_000_000, runs=3, tiles=4, l
         imgs["tabled"].append(b.double().cpu().numpy())
         events = st["peel_events"]
         table_ms = sb["table_ms"]
+        print(f"# peel study: run {r_ + 1} of {runs} done", file=sys.stderr, flush=True)
 
     def rel(x, ref):
         return float(np.sqrt(((x - ref) ** 2).sum() / (ref ** 2).sum()))
