@@ -191,8 +191,9 @@ typedef struct {
   double reduce_ms;         /* device time of the final FP64 reduction */
   double main_ms;           /* summed durations of the launches of the dominant transport
                                kernel (FP64: the per-job kernel; FP32-local: the persistent
-                               kernel, or the region pass of every sweep), HIP events recorded
-                               on the stream each launch runs on */
+                               kernel, or the region pass of every sweep, which also writes
+                               the sweep's new packets), HIP events recorded on the stream
+                               each launch runs on */
   uint64_t main_launches;   /* number of those launches */
   uint64_t splits;          /* crossings at which a package was split */
   uint64_t split_kills;     /* packages ended by the roulette at a subgrid exit */
