@@ -1027,7 +1027,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   p.rr_thr = o->rr_threshold;
   p.rr_p = o->rr_prob;
   p.max_events = o->max_events > 0 ? o->max_events : 1000000;
-  p.refill_thr = o->refill_threshold > 0.0f ? o->refill_threshold : (region_sched ? 0.15f : 0.5f);
+  p.refill_thr = o->refill_threshold > 0.0f ? o->refill_threshold : (region_sched ? 0.6f : 0.5f);
   p.split_n = o->split_n > 1 ? o->split_n : 1;
   p.cdf_qpre = ctx->cdf_qpre.as<uint64_t>();
   p.cdf_q = ctx->cdf_q.as<uint64_t>();
@@ -2019,7 +2019,7 @@ rt_status rt_autotune(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt
     if (regions) {
       if (!cur.block_size) cur.block_size = 768;
       if (!cur.blocks_per_cu) cur.blocks_per_cu = 1;
-      if (!(cur.refill_threshold > 0.0f)) cur.refill_threshold = 0.15f;
+      if (!(cur.refill_threshold > 0.0f)) cur.refill_threshold = 0.6f;
       if (!cur.tail_park) cur.tail_park = 16;
       if (!cur.chunk_packets) cur.chunk_packets = 16 * cur.block_size;
       if (!cur.batch_packets) cur.batch_packets = int64_t(1) << 23;
@@ -2036,8 +2036,8 @@ rt_status rt_autotune(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt
     };
     std::vector<Axis> axes;
     if (regions) {
-      axes = {{0, {512, 768, 1024}},   {2, {0.08, 0.15, 0.25}}, {4, {8, 16, 32}},
-              {3, {8, 16, 32, -1}},    {5, {22, 23, 24}}};
+      axes = {{0, {512, 768, 1024}},   {2, {0.15, 0.3, 0.45, 0.6, 0.75}}, {4, {8, 16, 32}},
+              {3, {4, 8, 16, 32, -1}}, {5, {22, 23, 24}}};
     } else if (global32) {
       axes = {{0, {64, 128, 256, 512}}, {2, {0.25, 0.5, 0.75}}, {1, {1, 2, 4}}};
     } else {
