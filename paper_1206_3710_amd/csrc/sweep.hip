@@ -88,13 +88,22 @@ __global__ __launch_bounds__(256) void sw_hist_kernel(const uint32_t* __restrict
     for (int k = threadIdx.x; k < n_keys; k += 256) s_h[k] = 0u;
     __syncthreads();
   }
-  // whole waves iterate together (agg_count needs every lane of the wave)
-  const uint64_t span = (uint64_t)gridDim.x * 256;
-  for (uint64_t i0 = (uint64_t)blockIdx.x * 256; i0 < n; i0 += span) {
-    const uint64_t i = i0 + threadIdx.x;
-    const uint32_t k = i < n ? keys[i] : kInvalidKey;
-    const bool v = k != kInvalidKey;  // unused records of a pass wave's last chunk
-    (void)agg_count(lds ? s_h : hist, v ? k : 0u, v);
+  // whole waves iterate together (agg_count needs every lane of the wave); kPerH keys per
+  // thread are loaded before any is counted, so that the loads overlap
+  constexpr int kPerH = 8;
+  const uint64_t span = (uint64_t)gridDim.x * 256 * kPerH;
+  for (uint64_t t0 = (uint64_t)blockIdx.x * 256 * kPerH; t0 < n; t0 += span) {
+    uint32_t kk[kPerH];
+#pragma unroll
+    for (int j = 0; j < kPerH; ++j) {
+      const uint64_t i = t0 + (uint64_t)j * 256 + threadIdx.x;
+      kk[j] = i < n ? keys[i] : kInvalidKey;
+    }
+#pragma unroll
+    for (int j = 0; j < kPerH; ++j) {
+      const bool v = kk[j] != kInvalidKey;  // unused records of a pass wave's last chunk
+      (void)agg_count(lds ? s_h : hist, v ? kk[j] : 0u, v);
+    }
   }
   if (lds) {
     __syncthreads();
