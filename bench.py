@@ -445,7 +445,7 @@ def cpu_baselines(a, gen, w, tree, dust, nl):
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
     import gen
