@@ -682,7 +682,9 @@ static int propagate(tctx* c, packet* p) {
       double de = p->w * (-expm1(-(sa * s)));
       if (c->e_abs) c->e_abs[p->node] += de;
       else c->e_abs_total += de;
-      if (c->e_self && c->dust && p->crossings == 1) c->e_self[p->node] += de;
+      /* before the package as emitted (branch 0) first leaves its birth cell; a package split
+         off later starts its count at 0 in another cell */
+      if (c->e_self && c->dust && p->crossings == 1 && p->br == 0) c->e_self[p->node] += de;
       if (c->e_lvl) c->e_lvl[(int64_t)p->mlev * m->nnodes + p->node] += de;
       p->w = p->w - de;
     }
