@@ -1,16 +1,22 @@
 """Benchmark on one MI355X.  Prints one JSON line.
 
-Default workload: the molecular cloud (root 64^3, up to 3 levels, 32 wavelengths, 1e7 packets
-per wavelength, dust temperatures, 256^2 maps toward 3 axes).  A step is one pass of the whole
-path over the resident model: trace all packets (FP32-local form, region schedule), reduce the
-absorbed energy to FP64, solve the temperatures, render the maps.  The plain FP64 form is timed
-on the same inputs for comparison.
+Default workload: the deep-hierarchy cloud (root 256^3, up to 5 levels, 1.13e8 nodes, 100
+wavelengths, 1e7 packets per wavelength, dust temperatures, 512^2 maps toward the 8 body
+diagonals), the largest configuration that fits one GPU.  A step is one pass of the whole path
+over the resident model: trace all packets (FP32-local form, region schedule), reduce the
+absorbed energy to FP64, solve the temperatures, render the maps.  The plain FP64 form and the
+one-queue FP32-local form are timed on the same inputs, which splits the gain over the FP64
+form into its schedule and precision parts.  The molecular cloud (root 64^3, 3 levels, 32
+wavelengths, 3.2e8 packets) is measured the same way after it and reported under "cloud".
+Before anything touches the GPU the oracle is timed on the host cores (cpu_baseline: one
+thread; cpu_all_cores: one thread per core of the box's share, on one shared model).
 
---workload disc: the circumstellar disc (root 96x96x32, 6 levels, 50 wavelengths); the star is
-traced once before timing, and a step is one Lambda-iteration step from those temperatures:
-trace the dust emission (3e7 packets per wavelength), solve the temperatures of A_stars +
-A_dust.  --workload clouds: 64 uneven clouds, 16 wavelengths, 1e6 packets per (model,
-wavelength), all traced in one call; a step is that trace.
+--workload cloud: the molecular cloud alone.  --workload disc: the circumstellar disc (root
+96x96x32, 6 levels, 50 wavelengths); the star is traced once before timing, and a step is one
+Lambda-iteration step from those temperatures: trace the dust emission (3e7 packets per
+wavelength), solve the temperatures of A_stars + A_dust.  --workload clouds: 64 uneven clouds,
+16 wavelengths, 1e6 packets per (model, wavelength), all traced in one call; a step is that
+trace.
 
 --split-study (cloud and deep workloads) adds, after the timed steps, the package-splitting
 study of Sect. 4.1 (Table 1): the radiation field at the wavelength nearest 4 um, traced 20
@@ -40,15 +46,15 @@ HBM_PEAK_GBS = 8000.0
 # SIMD; no packed FP32), 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0
 
-# HBM traffic of the region pass kernel, from two rocprofv3 --pmc runs of one trace step
-# (FETCH_SIZE, then WRITE_SIZE), each scaled by what the same counter reads for a 4 GiB
-# device-to-device copy (fetch x2.0, write x1.0), per leaf crossing; and its VALU wave-instructions
-# per leaf crossing (SQ_INSTS_VALU of the same step), at the launch settings the autotuner picked
-# in that run.  Valid only for the kernel sources the counters were taken on.
+# HBM traffic of the region pass kernel per workload, from two rocprofv3 --pmc runs of one
+# trace step (FETCH_SIZE, then WRITE_SIZE), each scaled by what the same counter reads for a
+# 4 GiB device-to-device copy (fetch x2.0, write x1.0), per leaf crossing; its VALU
+# wave-instructions per leaf crossing (SQ_INSTS_VALU) and lane utilisation
+# (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) in the same step, at the launch settings the
+# autotuner picked in that run.  Valid only for the kernel sources the counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "8be39f5aa2ab71ef8f102d850368f1f8ad6375446d60393939c6f6fbb6a00fb0",
-                "fetch_bytes_per_crossing": 11.005, "write_bytes_per_crossing": 6.535,
-                "valu_per_crossing": 5.34}
+                "sha256": "",
+                "per_workload": {}}
 
 
 WORKLOADS = {
@@ -349,15 +355,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["cloud", "disc", "clouds", "deep"], default="cloud")
+    ap.add_argument("--workload", choices=["cloud", "disc", "clouds", "deep"], default="deep")
     ap.add_argument("--packets", type=int, default=0,
                     help="packets per wavelength (0: 1e7 cloud and deep, 3e7 disc, 1e6 clouds)")
     ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--global-steps", type=int, default=1,
+                    help="steps of the one-queue FP32-local form (schedule-vs-precision split)")
+    ap.add_argument("--cloud-steps", type=int, default=5,
+                    help="deep workload: timed steps of the molecular cloud kept beside it (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-packets", type=int, default=1 << 18,
-                    help="oracle sample: packets per wavelength")
-    ap.add_argument("--cpu-workers", type=int, default=16,
-                    help="processes for the all-core oracle figure (1: skip it)")
+    ap.add_argument("--cpu-packets", type=int, default=0,
+                    help="oracle sample: packets per wavelength (0: 4096 deep, 2^18 cloud, 2^16 "
+                         "disc and clouds)")
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="threads for the all-core oracle figure (1: skip it)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--refill", type=float, default=0.0)
@@ -384,84 +395,302 @@ def parse():
     return ap.parse_args()
 
 
-_ORA = {}
+def cpu_info():
+    """CPU model (from /proc/cpuinfo), the processor count the OS reports and the count this
+    process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    return {"model": model or platform.machine(), "nproc": os.cpu_count(), "affinity": affinity}
 
 
-def _oracle_init(tree, dust):
+def cpu_baselines(a, gen, w, tree, dust, nl, threads_max=16):
+    """The oracle on the host cores, before anything touches the GPU: one thread on a packet-id
+    prefix of every wavelength (the reported baseline), then the same oracle in several threads
+    on a prefix that many times longer, split into one packet range per thread.  The threads
+    share the one oracle model (its trace only reads it) and each adds its deposits to an array
+    of its own, allocated and touched before the clock starts."""
+    import threading
+    import numpy as np
     import oracle
-    _ORA["model"] = oracle.Model(tree, dust)
-
-
-def _oracle_chunk(args):
-    src, seed, rr_t, rr_p, b, e = args
-    _, _, st, _ = _ORA["model"].trace(src, seed=seed, rr_threshold=rr_t, rr_prob=rr_p,
-                                      pid_begin=b, pid_end=e)
-    return st["crossings"]
-
-
-def cpu_baselines(a, gen, w, tree, dust, nl):
-    """The oracle on the host cores: one thread on a packet prefix (the reported baseline), and
-    the same oracle in one process per core on a prefix 16 times longer.  Runs before anything
-    touches the GPU (the worker processes are started fresh, not forked)."""
-    import multiprocessing as mp
-    from concurrent.futures import ProcessPoolExecutor
-    import oracle
+    info = cpu_info()
     src0 = [gen.Source(w.sources[0].kind, 0, pos=w.sources[0].pos, power=w.sources[0].power,
                        packets=w.sources[0].packets)]
     what = {"cloud": "", "disc": " of the star", "clouds": " of the first model",
             "deep": ""}[a.workload]
-    cpu_name = platform.processor() or platform.machine()
+    n1 = a.cpu_packets or {"deep": 4096, "cloud": 1 << 18, "disc": 1 << 16, "clouds": 1 << 16}[a.workload]
+    n1 = min(n1, int(w.sources[0].packets))
+    kw = dict(seed=w.seed, rr_threshold=w.rr_threshold, rr_prob=w.rr_prob)
     ora = oracle.Model(tree, dust)
+    out = np.zeros(ora.n_nodes)
+    out.fill(0.0)
     t2 = time.perf_counter()
-    _, _, sto, _ = ora.trace(src0, seed=w.seed, rr_threshold=w.rr_threshold,
-                             rr_prob=w.rr_prob, pid_end=a.cpu_packets)
+    _, _, sto, _ = ora.trace(src0, pid_end=n1, e_abs_out=out, **kw)
     dc = time.perf_counter() - t2
-    del ora
     cpu = {"value": sto["crossings"] / dc, "unit": "cell-crossings/s", "cores": 1,
            "kind": "oracle",
-           "sample": f"first {a.cpu_packets} packets{what} at each of the {nl} wavelengths "
-                     f"({sto['crossings']} crossings, {dc:.1f} s, single thread, {cpu_name})"}
-    workers = min(a.cpu_workers, os.cpu_count() or 1)
-    if workers <= 1:
+           "sample": f"first {n1} packets{what} at each of the {nl} wavelengths "
+                     f"({sto['crossings']} crossings, {dc:.1f} s, single thread, {info['model']})"}
+    threads = min(a.cpu_threads, info["affinity"], threads_max)
+    if threads <= 1:
         return cpu, None
-    n_all = min(16 * a.cpu_packets, int(w.sources[0].packets))
-    edges = [n_all * k // (4 * workers) for k in range(4 * workers + 1)]
-    tasks = [(src0, w.seed, w.rr_threshold, w.rr_prob, edges[k], edges[k + 1])
-             for k in range(4 * workers) if edges[k + 1] > edges[k]]
-    # a pool whose workers die raises instead of waiting
-    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn"), initializer=_oracle_init,
-                             initargs=(tree, dust)) as pool:
-        list(pool.map(_oracle_chunk, [(src0, w.seed, w.rr_threshold, w.rr_prob, 0, 1)] * workers))
-        t3 = time.perf_counter()
-        cr = sum(pool.map(_oracle_chunk, tasks))
-        d3 = time.perf_counter() - t3
-    cpu_all = {"value": cr / d3, "unit": "cell-crossings/s", "cores": workers, "kind": "oracle",
-               "sample": f"first {n_all} packets{what} at each of the {nl} wavelengths, "
-                         f"{len(tasks)} packet ranges over {workers} processes ({cr} crossings, "
-                         f"{d3:.1f} s, {cpu_name})"}
+    n_all = min(threads * n1, int(w.sources[0].packets))
+    edges = [n_all * k // threads for k in range(threads + 1)]
+    outs = [np.zeros(ora.n_nodes) for _ in range(threads)]
+    for o_ in outs:
+        o_.fill(0.0)
+    cross = [0] * threads
+    errors = []
+
+    def work(k):
+        try:
+            _, _, st, _ = ora.trace(src0, pid_begin=edges[k], pid_end=edges[k + 1], e_abs_out=outs[k], **kw)
+            cross[k] = st["crossings"]
+        except Exception as e:  # reported below
+            errors.append(e)
+    th = [threading.Thread(target=work, args=(k,)) for k in range(threads)]
+    t3 = time.perf_counter()
+    for t_ in th:
+        t_.start()
+    for t_ in th:
+        t_.join()
+    d3 = time.perf_counter() - t3
+    if errors:
+        raise errors[0]
+    cr = sum(cross)
+    cpu_all = {"value": cr / d3, "unit": "cell-crossings/s", "cores": threads, "kind": "oracle",
+               "nproc": info["nproc"], "affinity": info["affinity"],
+               "sample": f"first {n_all} packets{what} at each of the {nl} wavelengths, one packet "
+                         f"range per thread over {threads} threads sharing one model ({cr} "
+                         f"crossings, {d3:.1f} s, {info['model']}; the box's CPU share for one GPU "
+                         f"is 16 cores)"}
     return cpu, cpu_all
+
+
+def load_workload(gen, name, packets):
+    if name == "cloud":
+        return gen.c2(packets=packets or 10_000_000)
+    if name == "disc":
+        return gen.c3(packets=packets or 30_000_000)
+    if name == "deep":
+        return gen.c5(packets=packets or 10_000_000)
+    return gen.c4(packets=packets or 1_000_000)
+
+
+def measure(a, rt, gen, torch, w, workload, steps, warmup, copy_gbs, fp64_steps, global_steps,
+            explicit):
+    """Time `steps` whole-path steps of one workload in the FP32-local region schedule (after
+    `warmup` untimed ones), then the plain FP64 form and the one-queue FP32-local form on the same
+    inputs; returns the bench record's body for it."""
+    import numpy as np
+    ctx = rt.Context(0)
+    for t_, d_ in zip(w.trees, w.dusts):
+        m = ctx.build_tree(t_)
+        ctx.set_dust(m, d_)
+    m = 0
+    nl = w.dusts[0].n_lambda
+    lam_all = list(range(nl))
+    kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob, block_size=a.block,
+              blocks_per_cu=a.blocks_per_cu, refill_threshold=a.refill)
+    kw32 = dict(kw, schedule=a.schedule, chunk_packets=a.chunk, batch_packets=a.batch,
+                tail_park=a.tail_park, sweep_graph=1 if a.graph else 0)
+    if workload == "disc":
+        # constant sources once (FP64 form), then every timed step re-emits from T_0
+        a_stars = ctx.trace_packets(w.sources, seed=w.seed, iteration=0, precision=rt.FP64,
+                                    **kw)["e_abs_node"]
+        t0_disc = ctx.solve_temperature(m, a_stars, 2.0, 3000.0)
+        dust_src = [gen.Source(gen.SRC_DUST, 0, packets=w.sources[0].packets)]
+
+    tuned = None
+    if not a.no_autotune and not explicit:
+        # launch parameters from the autotuner (packet-id prefix of the workload, untimed)
+        t_tune = time.perf_counter()
+        if workload == "disc":
+            ctx.set_temperature(m, t0_disc)
+        tune_src = dust_src if workload == "disc" else w.sources
+        frac = 1.0 / 64.0 if workload == "deep" else 0.125
+        params, rate = ctx.autotune(tune_src, seed=w.seed, precision=rt.FP32_LOCAL,
+                                    schedule=a.schedule, sample_fraction=frac,
+                                    cache=a.tune_cache, rr_threshold=w.rr_threshold,
+                                    rr_prob=w.rr_prob)
+        tuned = dict(params, sample_fraction=frac, sample_crossings_per_s=rate,
+                     seconds=time.perf_counter() - t_tune)
+        kw32.update(params)
+
+    def step(precision, it, extra=None):
+        kwp = dict(kw32 if precision == rt.FP32_LOCAL else kw)
+        if extra:
+            kwp.update(extra)
+        if workload == "disc":
+            ctx.set_temperature(m, t0_disc)
+            r = ctx.trace_packets(dust_src, seed=w.seed, iteration=1 + it, precision=precision, **kwp)
+        else:
+            r = ctx.trace_packets(w.sources, seed=w.seed, iteration=it, precision=precision, **kwp)
+        t = time.perf_counter()
+        out = {"stats": r["stats"], "e_abs": r["e_abs_node"]}
+        if not a.trace_only:
+            if workload in ("cloud", "deep"):
+                ctx.solve_temperature(m, r["e_abs_node"], 2.0, 3000.0)
+                for d in w.map_dirs:
+                    ctx.render_map(m, d, w.map_npix, lam_all, precision=precision)
+            elif workload == "disc":
+                ctx.solve_temperature(m, a_stars + r["e_abs_node"], 2.0, 3000.0)
+        torch.cuda.synchronize()
+        out["post_s"] = time.perf_counter() - t
+        return out
+
+    e_warm = None
+    for i in range(warmup):
+        e_warm = step(rt.FP32_LOCAL, 1000 + i)["e_abs"]
+        print(f"# {workload}: warm-up step {i + 1} of {warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    crossings = 0
+    kernel_ms, main_ms, main_n, post = [], [], [], []
+    e32 = None
+    for i in range(steps):
+        o = step(rt.FP32_LOCAL, i)
+        if i == 0:
+            e32 = o["e_abs"]
+        crossings += o["stats"]["crossings"]
+        kernel_ms.append(o["stats"]["kernel_ms"])
+        main_ms.append(o["stats"]["main_ms"])
+        main_n.append(o["stats"]["main_launches"])
+        post.append(o["post_s"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"# {workload}: {steps} timed steps done ({dt:.1f} s)", file=sys.stderr, flush=True)
+    value = crossings / dt
+    k_avg = sum(kernel_ms) / len(kernel_ms) / 1e3
+    cr_step = crossings / steps
+    # dominant kernel: per-launch durations from HIP events on its own stream (summed by the
+    # library), algorithmic bytes = crossings handled x bytes per crossing
+    launches = sum(main_n) / steps
+    bytes_per_launch = cr_step / launches * BYTES_PER_CROSSING_FP32
+    if sum(main_ms) > 0:
+        main_launch_s = sum(main_ms) / sum(main_n) / 1e3
+        achieved = bytes_per_launch / main_launch_s / 1e9
+    else:  # replayed sweep graphs report no per-launch durations
+        main_launch_s, achieved = float("nan"), float("nan")
+    counters = PASS_TRAFFIC["per_workload"].get(workload)
+    traffic, measured_gbs, issue = None, None, None
+    if counters and a.schedule == 0 and pass_sources_sha() == PASS_TRAFFIC["sha256"]:
+        per_cross = counters["fetch_bytes_per_crossing"] + counters["write_bytes_per_crossing"]
+        traffic = cr_step / launches * per_cross
+        if main_launch_s == main_launch_s:
+            measured_gbs = traffic / main_launch_s / 1e9
+            # the limit the kernel actually meets: VALU issue (measured instructions per
+            # crossing x crossings per second while the pass kernel runs)
+            v = counters["valu_per_crossing"] * cr_step / launches / main_launch_s
+            issue = {"unit": "VALU wave-instructions/s", "valu_per_crossing": counters["valu_per_crossing"],
+                     "lane_utilisation": counters.get("lane_utilisation"),
+                     "achieved": v, "peak": VALU_ISSUE_PEAK, "frac": v / VALU_ISSUE_PEAK}
+
+    def rel_rms(x, ref):
+        x, ref = x.double().cpu().numpy(), ref.double().cpu().numpy()
+        return float(np.sqrt(((x - ref) ** 2).sum() / (ref ** 2).sum()))
+
+    def other_form(precision, n_steps, extra, label):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c_, k_, e_ = 0, [], None
+        for i in range(n_steps):
+            o = step(precision, i, extra)
+            if i == 0:
+                e_ = o["e_abs"]
+            c_ += o["stats"]["crossings"]
+            k_.append(o["stats"]["kernel_ms"])
+        torch.cuda.synchronize()
+        d_ = time.perf_counter() - t1
+        print(f"# {workload}: {label} done ({d_:.1f} s)", file=sys.stderr, flush=True)
+        ka = sum(k_) / len(k_) / 1e3
+        return e_, {"crossings_per_s": c_ / d_, "ms_per_step": 1e3 * d_ / n_steps,
+                    "trace_kernel_ms": 1e3 * ka, "trace_crossings_per_s": (c_ / n_steps) / ka}
+
+    fp64, acc, one_queue, gain = None, None, None, None
+    if fp64_steps > 0:
+        e64, fp64 = other_form(rt.FP64, fp64_steps, None, "plain FP64 form")
+        fp64["hbm_frac_algorithmic"] = (fp64["trace_crossings_per_s"] * BYTES_PER_CROSSING_FP64
+                                        / 1e9 / HBM_PEAK_GBS)
+        # same Philox streams (iteration 0) in both forms: the difference is the FP32-local
+        # rounding; an independent realisation (the warm-up) gives the Monte Carlo noise
+        acc = {"rel_rms_fp32_local_vs_fp64": rel_rms(e32, e64),
+               "mc_noise_rel_rms": rel_rms(e_warm, e64) / float(np.sqrt(2.0)) if e_warm is not None else None,
+               "definition": "sqrt(sum (E32 - E64)^2 / sum E64^2) over nodes, absorbed power per node"}
+    if global_steps > 0 and a.schedule == 0:
+        e_g, one_queue = other_form(rt.FP32_LOCAL, global_steps, {"schedule": 1, "sweep_graph": 0,
+                                                                 "block_size": 0, "blocks_per_cu": 0,
+                                                                 "refill_threshold": 0.0},
+                                    "one-queue FP32-local form")
+        one_queue["rel_rms_vs_fp64"] = rel_rms(e_g, e64) if fp64_steps > 0 else None
+    if fp64 and one_queue:
+        tr = cr_step / k_avg
+        gain = {"definition": "trace crossings/s ratios on the same inputs: precision = one-queue "
+                              "FP32-local form over the plain FP64 form (same one-packet-per-lane "
+                              "walk over the whole tree); schedule = the region (grid-by-grid, "
+                              "LDS) schedule over the one-queue form, both FP32-local",
+                "precision": one_queue["trace_crossings_per_s"] / fp64["trace_crossings_per_s"],
+                "schedule": tr / one_queue["trace_crossings_per_s"],
+                "total": tr / fp64["trace_crossings_per_s"]}
+    body = {
+        "value": value,
+        "ms_per_step": 1e3 * dt / steps,
+        "steps": steps,
+        "config": {"workload": WORKLOADS[workload] % w.sources[0].packets
+                               + (" (trace only)" if a.trace_only else ""),
+                   "nodes": sum(t_.n_nodes for t_ in w.trees),
+                   "leaves": sum(t_.n_leaves for t_ in w.trees),
+                   "packets_per_step": int(sum(s.packets for s in w.sources) * nl),
+                   "crossings_per_step": cr_step},
+        "trace_kernel_ms": 1e3 * k_avg,
+        "trace_crossings_per_s": cr_step / k_avg,
+        "post_trace_ms": 1e3 * sum(post) / len(post),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "measured_gbs": measured_gbs,
+                     "copy_gbs": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
+                     "kernel": "blk_pass_kernel<%d>" % (kw32["block_size"] or 768) if a.schedule == 0
+                               else "trace_fp32_kernel<%d>" % (kw32["block_size"] or 256),
+                     "launches_per_step": launches, "avg_launch_ms": 1e3 * main_launch_s,
+                     "bytes_per_crossing": BYTES_PER_CROSSING_FP32,
+                     "limiter": "VALU issue (see issue): the HBM figure is the method's roofline, "
+                                "the issue figure is what the kernel meets" if issue else None,
+                     "issue": issue},
+        "autotune": tuned,
+        "fp64": fp64,
+        "fp32_one_queue": one_queue,
+        "gain": gain,
+        "accuracy": acc,
+    }
+    ctx.close()
+    return body, kw32
 
 
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only: this build has no multi-GPU "
+                                   "path (--gpus must be 1)"}))
         sys.exit(2)
-    import numpy as np
     import gen
 
-    if a.workload == "cloud":
-        w = gen.c2(packets=a.packets or 10_000_000)
-    elif a.workload == "disc":
-        w = gen.c3(packets=a.packets or 30_000_000)
-    elif a.workload == "deep":
-        w = gen.c5(packets=a.packets or 10_000_000)
-    else:
-        w = gen.c4(packets=a.packets or 1_000_000)
+    w = load_workload(gen, a.workload, a.packets)
     tree, dust = w.trees[0], w.dusts[0]
     cpu, cpu_all = None, None
     if not a.no_cpu_baseline:
         cpu, cpu_all = cpu_baselines(a, gen, w, tree, dust, dust.n_lambda)
+        print("# CPU baselines done", file=sys.stderr, flush=True)
 
     import torch
     import paper_1206_3710_amd as rt
@@ -480,134 +709,23 @@ def main():
     copy_gbs = 2.0 * 4.0 * (1 << 30) / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     del src_t, dst_t
     torch.cuda.empty_cache()
-    ctx = rt.Context(0)
-    for t_, d_ in zip(w.trees, w.dusts):
-        m = ctx.build_tree(t_)
-        ctx.set_dust(m, d_)
-    m = 0
-    nl = dust.n_lambda
-    lam_all = list(range(nl))
-    kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob, block_size=a.block,
-              blocks_per_cu=a.blocks_per_cu, refill_threshold=a.refill)
-    kw32 = dict(kw, schedule=a.schedule, chunk_packets=a.chunk, batch_packets=a.batch,
-                tail_park=a.tail_park, sweep_graph=1 if a.graph else 0)
-    if a.workload == "disc":
-        # constant sources once (FP64 form), then every timed step re-emits from T_0
-        a_stars = ctx.trace_packets(w.sources, seed=w.seed, iteration=0, precision=rt.FP64,
-                                    **kw)["e_abs_node"]
-        t0_disc = ctx.solve_temperature(m, a_stars, 2.0, 3000.0)
-        dust_src = [gen.Source(gen.SRC_DUST, 0, packets=w.sources[0].packets)]
-
-    tuned = None
     explicit = a.block or a.blocks_per_cu or a.refill or a.chunk or a.batch or a.tail_park
-    if not a.no_autotune and not explicit:
-        # launch parameters from the autotuner (packet-id prefix of the workload, untimed)
-        t_tune = time.perf_counter()
-        if a.workload == "disc":
-            ctx.set_temperature(m, t0_disc)
-        tune_src = dust_src if a.workload == "disc" else w.sources
-        params, rate = ctx.autotune(tune_src, seed=w.seed, precision=rt.FP32_LOCAL,
-                                    schedule=a.schedule, sample_fraction=0.125,
-                                    cache=a.tune_cache, rr_threshold=w.rr_threshold,
-                                    rr_prob=w.rr_prob)
-        tuned = dict(params, sample_crossings_per_s=rate, seconds=time.perf_counter() - t_tune)
-        kw32.update(params)
+    body, kw32 = measure(a, rt, gen, torch, w, a.workload, a.steps, a.warmup, copy_gbs, a.fp64_steps,
+                         a.global_steps, explicit)
 
-    def step(precision, it):
-        kwp = kw32 if precision == rt.FP32_LOCAL else kw
-        if a.workload == "disc":
-            ctx.set_temperature(m, t0_disc)
-            r = ctx.trace_packets(dust_src, seed=w.seed, iteration=1 + it, precision=precision, **kwp)
-        else:
-            r = ctx.trace_packets(w.sources, seed=w.seed, iteration=it, precision=precision, **kwp)
-        t = time.perf_counter()
-        out = {"stats": r["stats"], "e_abs": r["e_abs_node"]}
-        if not a.trace_only:
-            if a.workload in ("cloud", "deep"):
-                ctx.solve_temperature(m, r["e_abs_node"], 2.0, 3000.0)
-                for d in w.map_dirs:
-                    ctx.render_map(m, d, w.map_npix, lam_all, precision=precision)
-            elif a.workload == "disc":
-                ctx.solve_temperature(m, a_stars + r["e_abs_node"], 2.0, 3000.0)
-        out["post_s"] = time.perf_counter() - t
-        return out
-
-    e_warm = None
-    for i in range(a.warmup):
-        e_warm = step(rt.FP32_LOCAL, 1000 + i)["e_abs"]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    crossings = 0
-    kernel_ms = []
-    main_ms, main_n = [], []
-    post = []
-    for i in range(a.steps):
-        o = step(rt.FP32_LOCAL, i)
-        if i == 0:
-            e32 = o["e_abs"]
-        crossings += o["stats"]["crossings"]
-        kernel_ms.append(o["stats"]["kernel_ms"])
-        main_ms.append(o["stats"]["main_ms"])
-        main_n.append(o["stats"]["main_launches"])
-        post.append(o["post_s"])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    value = crossings / dt
-    k_avg = sum(kernel_ms) / len(kernel_ms) / 1e3
-    cr_step = crossings / a.steps
-    # dominant kernel: per-launch durations from HIP events on its own stream (summed by the
-    # library), algorithmic bytes = crossings handled x bytes per crossing
-    launches = sum(main_n) / a.steps
-    bytes_per_launch = cr_step / launches * BYTES_PER_CROSSING_FP32
-    if sum(main_ms) > 0:
-        main_launch_s = sum(main_ms) / sum(main_n) / 1e3
-        achieved = bytes_per_launch / main_launch_s / 1e9
-    else:  # replayed sweep graphs report no per-launch durations
-        main_launch_s, achieved = float("nan"), float("nan")
-    traffic = None
-    issue = None
-    if a.workload == "cloud" and a.schedule == 0 and pass_sources_sha() == PASS_TRAFFIC["sha256"]:
-        traffic = cr_step / launches * (PASS_TRAFFIC["fetch_bytes_per_crossing"]
-                                        + PASS_TRAFFIC["write_bytes_per_crossing"])
-        # the limit the kernel actually meets: VALU issue (measured instructions per crossing x
-        # crossings per second while the pass kernel runs)
-        if main_launch_s == main_launch_s:
-            v = PASS_TRAFFIC["valu_per_crossing"] * cr_step / launches / main_launch_s
-            issue = {"unit": "VALU wave-instructions/s", "valu_per_crossing": PASS_TRAFFIC["valu_per_crossing"],
-                     "achieved": v, "peak": VALU_ISSUE_PEAK, "frac": v / VALU_ISSUE_PEAK}
-
-    # plain FP64 form on the same inputs
-    fp64 = None
-    if a.fp64_steps > 0:
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        c64 = 0
-        k64 = []
-        for i in range(a.fp64_steps):
-            o = step(rt.FP64, i)
-            if i == 0:
-                e64 = o["e_abs"]
-            c64 += o["stats"]["crossings"]
-            k64.append(o["stats"]["kernel_ms"])
-        torch.cuda.synchronize()
-        d64 = time.perf_counter() - t1
-        k64a = sum(k64) / len(k64) / 1e3
-        # same Philox streams (iteration 0) in both forms: the difference is the FP32-local
-        # rounding; an independent realisation (the warm-up) gives the Monte Carlo noise
-        def rel_rms(x, ref):
-            x, ref = x.double().cpu().numpy(), ref.double().cpu().numpy()
-            return float(np.sqrt(((x - ref) ** 2).sum() / (ref ** 2).sum()))
-        acc = {"rel_rms_fp32_local_vs_fp64": rel_rms(e32, e64),
-               "mc_noise_rel_rms": rel_rms(e_warm, e64) / float(np.sqrt(2.0)) if e_warm is not None else None,
-               "definition": "sqrt(sum (E32 - E64)^2 / sum E64^2) over nodes, absorbed power per node"}
-        fp64 = {"crossings_per_s": c64 / d64, "ms_per_step": 1e3 * d64 / a.fp64_steps,
-                "trace_kernel_ms": 1e3 * k64a,
-                "trace_crossings_per_s": (c64 / a.fp64_steps) / k64a,
-                "hbm_frac_algorithmic": (c64 / a.fp64_steps) * BYTES_PER_CROSSING_FP64 / k64a / 1e9 / HBM_PEAK_GBS}
+    extra = None
+    if a.workload == "deep" and a.cloud_steps > 0:
+        # the molecular cloud, the previous default workload, kept beside the headline
+        del w
+        wc = load_workload(gen, "cloud", 0)
+        b2, _ = measure(a, rt, gen, torch, wc, "cloud", a.cloud_steps, 1, copy_gbs, 1, 1, explicit)
+        extra = {k: b2[k] for k in ("value", "ms_per_step", "steps", "config", "trace_crossings_per_s",
+                                    "roofline", "fp64", "fp32_one_queue", "gain", "accuracy")}
+        del wc
 
     splitting = None
     if a.workload in ("cloud", "deep") and a.schedule == 0 and a.split_study:
-        splitting = split_study(rt, gen, w, kw32)
+        splitting = split_study(rt, gen, load_workload(gen, a.workload, a.packets), kw32)
 
     accel = None
     if a.schedule == 0 and a.ali_study:
@@ -619,50 +737,40 @@ def main():
 
     peeling = None
     if a.workload in ("cloud", "disc", "deep") and a.schedule == 0 and a.peel_study:
-        peeling = peel_study(rt, gen, w, kw32, a.workload)
+        peeling = peel_study(rt, gen, load_workload(gen, a.workload, a.packets), kw32, a.workload)
 
     res = {
         "metric": "cell-crossings/s (FP32-local form; FP64 form in fp64)",
-        "value": value,
+        "value": body["value"],
         "unit": "cell-crossings/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": 1e3 * dt / a.steps,
+        "ms_per_step": body["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[a.workload] % w.sources[0].packets
-                               + (" (trace only)" if a.trace_only else ""),
-                   "nodes": sum(t_.n_nodes for t_ in w.trees),
-                   "leaves": sum(t_.n_leaves for t_ in w.trees),
-                   "packets_per_step": int(sum(s.packets for s in w.sources) * nl),
-                   "crossings_per_step": cr_step},
-        "trace_kernel_ms": 1e3 * k_avg,
-        "trace_crossings_per_s": cr_step / k_avg,
-        "post_trace_ms": 1e3 * sum(post) / len(post),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "copy_gbs": copy_gbs,
-                     "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
-                     "kernel": "blk_pass_kernel<%d>" % (kw32["block_size"] or 768) if a.schedule == 0
-                               else "trace_fp32_kernel<%d>" % (kw32["block_size"] or 256),
-                     "launches_per_step": launches, "avg_launch_ms": 1e3 * main_launch_s,
-                     "bytes_per_crossing": BYTES_PER_CROSSING_FP32, "issue": issue},
-        "autotune": tuned,
-        "fp64": fp64,
-        "accuracy": acc if fp64 is not None else None,
+        "config": body["config"],
+        "trace_kernel_ms": body["trace_kernel_ms"],
+        "trace_crossings_per_s": body["trace_crossings_per_s"],
+        "post_trace_ms": body["post_trace_ms"],
+        "roofline": body["roofline"],
+        "autotune": body["autotune"],
+        "fp64": body["fp64"],
+        "fp32_one_queue": body["fp32_one_queue"],
+        "gain": body["gain"],
+        "accuracy": body["accuracy"],
         "cpu_baseline": cpu,
         "cpu_all_cores": cpu_all,
+        "cloud": extra,
         "splitting": splitting,
         "peel_off": peeling,
         "accelerated_iteration": accel,
         "subiterations": subiters,
     }
     print(json.dumps(res))
-    ctx.close()
 
 
 if __name__ == "__main__":

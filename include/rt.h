@@ -212,14 +212,19 @@ typedef struct {
  *   e_abs_node         [total nodes] absorbed power per canonical node, all wavelengths;
  *   e_abs_lambda_node  [total lambda_nodes] per (wavelength, node), model-major;
  *   e_esc_lambda       [total lambdas] escaped power per wavelength.
- * The absorbed energy is reduced to FP64 in a final pass in both precisions. */
+ * Deposits are accumulated in FP64 in both precisions (the region schedule first sums each work
+ * item's deposits in FP32 in LDS), then reduced to canonical order in a final pass.  A broken
+ * internal invariant of the region schedule (a queued packet record outside the region it was
+ * queued for) fails the call with RT_EDEVICE after the trace, naming the count. */
 rt_status rt_trace_packets(rt_ctx* ctx, int32_t n_src, const rt_source* src,
                            const rt_trace_opts* opts, double* e_abs_node,
                            double* e_abs_lambda_node, double* e_esc_lambda,
                            rt_trace_stats* stats);
 
 /* Equilibrium temperature per leaf (FP64): 4 pi m sum_i kappa_abs_i B_i(T) dnu_i = A, with A
- * the absorbed power per canonical node (host or device).  A at or below the emission at
+ * the absorbed power per canonical node of the model (host or device).  a_node = NULL takes
+ * the model's part of the e_abs_node result of the last rt_trace_packets call on this context
+ * (RT_ESTATE if there is none, or if models were added since).  A at or below the emission at
  * t_min gives t_min, at or above the emission at t_max gives t_max; refined nodes get 0.
  * Stores the result as the model's temperatures; t_node (host or device) may be NULL. */
 rt_status rt_solve_temperature(rt_ctx* ctx, int32_t model, const double* a_node, double t_min,

@@ -195,14 +195,16 @@ class Model:
     def trace(self, sources, seed, iteration=0, model_index=0, rr_threshold=0.0, rr_prob=0.0,
               max_events=0, per_lambda=False, pid_begin=0, pid_end=-1, lam_sel=-1,
               t_node=None, rec_stride=0, deposits=True, split_n=1, peel=None, self_absorption=False,
-              level_arrays=False, subtree=-1):
+              level_arrays=False, subtree=-1, e_abs_out=None):
         """Follow packets of ``sources`` (gen.Source list) -> (e_abs, e_esc, stats, records).
         ``peel``: dict(n_obs=[[x, y, z], ...], npix=, width=0.0, tiles=0) turns on the peel-off
         images, returned in stats["peel_image"] as [n_dir, n_lambda, npix, npix].
         ``self_absorption``: stats["e_self"] and stats["e_emit_node"] per node (the diagonal
         part of the accelerated Lambda iteration).  ``level_arrays``: stats["e_lvl"]
         [n_levels + 1, n_nodes], the deposits by the shallowest level visited; ``subtree``: a
-        refined node whose subtree alone emits and holds the packages (subiterations)."""
+        refined node whose subtree alone emits and holds the packages (subiterations).
+        ``e_abs_out``: a caller-owned float64 array the deposits are added to (instead of a new
+        zeroed one), so that repeated or concurrent calls need no new allocation."""
         L = lib()
         ns = len(sources)
         nl = self.n_lambda
@@ -214,7 +216,13 @@ class Model:
             if s.power is not None:
                 power[i * nl:(i + 1) * nl] = s.power
         packets = np.array([s.packets for s in sources], dtype=np.int64)
-        e_abs = np.zeros(self.n_nodes * (nl if per_lambda else 1)) if deposits else None
+        if e_abs_out is not None:
+            if (e_abs_out.dtype != np.float64 or not e_abs_out.flags.c_contiguous
+                    or e_abs_out.size != self.n_nodes * (nl if per_lambda else 1)):
+                raise OracleError("e_abs_out must be a contiguous float64 array of the output size")
+            e_abs = e_abs_out
+        else:
+            e_abs = np.zeros(self.n_nodes * (nl if per_lambda else 1)) if deposits else None
         e_esc = np.zeros(nl)
         st = Stats()
         tn = None if t_node is None else np.ascontiguousarray(t_node, dtype=np.float64)
@@ -390,16 +398,17 @@ def subiterate(model, star_sources, seed, schedule, dust_packets, rr_threshold=0
 
 def lambda_iterate(model, star_sources, seed, n_max=30, tol=1e-3, n_fixed=None,
                    dust_packets=None, rr_threshold=0.0, rr_prob=0.0, t_min=2.0, t_max=3000.0,
-                   ali=False):
+                   ali=False, split_n=1):
     """Lambda iteration (paper Sect. 3.1 Eq. 2; constant-source field kept, Sect. 3.2), or with
     ali=True the accelerated iteration with the diagonal operator (Eq. 3, ali_step_absorbed):
     A_stars from the constant sources once, T_0 = f(A_stars); then for n >= 1 the dust
     emission of T_{n-1} is traced with key iteration n, T_n = f(A_stars + A_dust).
     Stops when the mass-weighted mean |T_n - T_{n-1}|/T_{n-1} < tol, or after n_max steps
-    (or exactly n_fixed steps).  Returns (T history list, A_stars, per-step dust-trace stats)."""
+    (or exactly n_fixed steps).  ``split_n`` > 1: package splitting in every trace.  Returns
+    (T history list, A_stars, per-step dust-trace stats)."""
     import gen
     a_stars, _, _, _ = model.trace(star_sources, seed, iteration=0, rr_threshold=rr_threshold,
-                                   rr_prob=rr_prob)
+                                   rr_prob=rr_prob, split_n=split_n)
     t = model.solve_temperature(a_stars, t_min, t_max)
     hist = [t]
     leaf = model.leaf_mask
@@ -411,7 +420,8 @@ def lambda_iterate(model, star_sources, seed, n_max=30, tol=1e-3, n_fixed=None,
     for it in range(1, n_steps + 1):
         src = [gen.Source(gen.SRC_DUST, 0, packets=npk)]
         a_dust, _, st, _ = model.trace(src, seed, iteration=it, rr_threshold=rr_threshold,
-                                       rr_prob=rr_prob, t_node=t, self_absorption=ali)
+                                       rr_prob=rr_prob, t_node=t, self_absorption=ali,
+                                       split_n=split_n)
         stats.append(st)
         if ali:
             a_new = ali_step_absorbed(a_stars, a_dust, st["e_self"], st["e_emit_node"])

@@ -311,8 +311,9 @@ class Context:
         return img, st.as_dict()
 
     def solve_temperature(self, model: int, a_node, t_min: float = 2.0, t_max: float = 3000.0):
+        """Temperatures for absorbed power ``a_node``; None takes the last trace's result."""
         torch = _torch()
-        a = self._dev(a_node, torch.float64)
+        a = None if a_node is None else self._dev(a_node, torch.float64)
         t = torch.empty(self.models[model], dtype=torch.float64, device=self.tdev)
         self._check(lib().rt_solve_temperature(self.h, model, _ptr(a), t_min, t_max, _ptr(t)))
         return t
@@ -369,7 +370,8 @@ class Context:
                          kw.get("block_size", 0), kw.get("blocks_per_cu", 0),
                          kw.get("refill_threshold", 0.0), kw.get("schedule", SCHED_REGIONS),
                          kw.get("chunk_packets", 0), kw.get("tail_park", 0),
-                         kw.get("batch_packets", 0), 0, None)
+                         kw.get("batch_packets", 0), 0, None, kw.get("sweep_graph", 0),
+                         kw.get("split_n", 0))
         t = torch.empty(self.models[model], dtype=torch.float64, device=self.tdev)
         nd = C.c_int32()
         crit = np.zeros(max(n_max, 1))

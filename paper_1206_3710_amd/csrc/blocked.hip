@@ -205,9 +205,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   const float rr_thr = (float)p.rr_thr, rr_p = (float)p.rr_p;
   const float rr_gain = rr_p > 0.0f ? 1.0f / (1.0f - rr_p) : 1.0f;
   const int bx = R.hi[0] - R.lo[0], by = R.hi[1] - R.lo[1];
-  float* __restrict__ gacc = b.accb64 ? nullptr : b.accb + (int64_t)it.slot * b.accb_stride + R.gbase;
-  double* __restrict__ gacc64 =
-      b.accb64 ? b.accb64 + (LVL ? (int64_t)it.slot * b.accb_stride : int64_t(0)) + R.gbase : nullptr;
+  double* __restrict__ gacc64 = b.accb64 + (int64_t)it.slot * b.accb_stride + R.gbase;
   const int32_t* __restrict__ gword = b.rword + R.gbase;
   const int32_t* __restrict__ gup = b.rup + (R.gbase >> 3);
   auto word_of = [&](int32_t l) -> int32_t {
@@ -224,8 +222,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
     // straight into its own array
     if (LVL && mlev != it.slot) unsafeAtomicAdd(b.accb64 + (int64_t)mlev * b.accb_stride + R.gbase + l, (double)v);
     else if (FITS || l < nloc) atomicAdd(&s_acc[l], v);
-    else if (gacc64) unsafeAtomicAdd(gacc64 + l, (double)v);
-    else unsafeAtomicAdd(gacc + l, v);
+    else unsafeAtomicAdd(gacc64 + l, (double)v);
   };
   int state = B_EMPTY;
   int32_t node = 0, lev = 0, I0 = 0, I1 = 0, I2 = 0, birth = 0, job = 0;
@@ -328,10 +325,9 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           const bool misplaced = (L < R.rl && !crossing) || R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] ||
                                  R1 >= R.hi[1] || R2 < R.lo[2] || R2 >= R.hi[2];
           if (misplaced) {
-            // a record queued for the wrong region (never expected): retire it as truncated
-            ++c_trunc;
-            atomicAdd(&s_misc[2], (double)w);
-            c_cross += ncross;
+            // a record queued for the wrong region breaks the schedule's invariant: it is
+            // dropped and counted, and the call reports the count as a device error
+            atomicAdd(&s_misc[6], 1.0);
           } else if (crossing) {
             land(word_of, ax, sg, Lj, rec.I[0], rec.I[1], rec.I[2], J0, J1, J2, rootl, R.rl, x0, x1, x2, O0,
                  O1, O2, d0, d1, d2, node, lev, I0, I1, I2, raw);
@@ -388,8 +384,9 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           w -= de;
         }
         // accelerated Lambda iteration: what a dust-emission packet absorbs in its birth cell
-        // before it first leaves it
-        if (self_on && ncross == 1u && dust_lane && de > 0.0f)
+        // before it first leaves it (a package split off later starts its count at 0 in another
+        // cell, so only the package as emitted, branch 0, is counted)
+        if (self_on && ncross == 1u && br == 0u && dust_lane && de > 0.0f)
           unsafeAtomicAdd(p.self_acc + md.canon_base + b.rcanon[R.gbase + node], (double)de);
         x0 = clamp01(fmaf(s, d0, x0));
         x1 = clamp01(fmaf(s, d1, x1));
@@ -726,12 +723,13 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   int32_t* s_up = reinterpret_cast<int32_t*>(smem + 8 * (size_t)cap);
   __shared__ int s_item;
   __shared__ uint32_t s_next;
-  __shared__ double s_misc[6];
+  __shared__ double s_misc[7];  // killed, roulette gain, truncated, split-killed, split gain,
+                                // emitted, misplaced records (a count)
   __shared__ unsigned long long s_npk;
   __shared__ double s_esc[kEscLds];
   const TraceParams& p = b.t;
   const int tid = threadIdx.x, lane = tid & 63;
-  if (tid < 6) s_misc[tid] = 0.0;
+  if (tid < 7) s_misc[tid] = 0.0;
   if (tid == 0) s_npk = 0;
   unsigned long long c_cross = 0;
   uint32_t c_scat = 0, c_kill = 0, c_trunc = 0, c_split = 0, c_skill = 0, c_sskip = 0;
@@ -767,17 +765,11 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
       run_item<false, SPLIT, PEEL, ALI, LVL>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
                       c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip, ch_base, ch_used);
     __syncthreads();
-    if (b.accb64) {
-      double* __restrict__ gacc64 = b.accb64 + (LVL ? (int64_t)it.slot * b.accb_stride : int64_t(0)) + R.gbase;
+    {
+      double* __restrict__ gacc64 = b.accb64 + (int64_t)it.slot * b.accb_stride + R.gbase;
       for (int i = tid; i < nloc; i += BS) {
         const float v = s_acc[i];
         if (v != 0.0f) unsafeAtomicAdd(gacc64 + i, (double)v);
-      }
-    } else {
-      float* __restrict__ gacc = b.accb + (int64_t)it.slot * b.accb_stride + R.gbase;
-      for (int i = tid; i < nloc; i += BS) {
-        const float v = s_acc[i];
-        if (v != 0.0f) unsafeAtomicAdd(gacc + i, v);
       }
     }
     if (esc_lds)
@@ -843,6 +835,7 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     if (s_misc[2] != 0.0) unsafeAtomicAdd(&p.stats->e_trunc, s_misc[2]);
     if (s_misc[3] != 0.0) unsafeAtomicAdd(&p.stats->e_split_killed, s_misc[3]);
     if (s_misc[4] != 0.0) unsafeAtomicAdd(&p.stats->e_split_gain, s_misc[4]);
+    if (s_misc[6] != 0.0) atomicAdd(&p.stats->misplaced, (unsigned long long)s_misc[6]);
     if (s_npk) {
       unsafeAtomicAdd(&p.stats->e_emit, s_misc[5]);
       atomicAdd(&p.stats->packets, s_npk);
@@ -850,11 +843,13 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   }
 }
 
-// Region-major FP32 accumulators -> FP64 canonical outputs (one block row per region).
+// Region-major FP64 accumulators -> canonical outputs (one block row per region).  Slots: one
+// (wavelength-integrated), one per wavelength of the model (per-wavelength output, also written
+// to e_lam_node), or one per level (subiterations: the level arrays go to lvl_out).  Each node's
+// slots are summed into e_node.
 __global__ __launch_bounds__(256) void blk_reduce_kernel(const ModelDev* __restrict__ models,
                                                          const RegionDev* __restrict__ regions,
                                                          const int32_t* __restrict__ rcanon,
-                                                         const float* __restrict__ accb,
                                                          const double* __restrict__ accb64, int64_t stride,
                                                          int n_slots, double* __restrict__ e_node,
                                                          double* __restrict__ e_lam_node,
@@ -869,20 +864,12 @@ __global__ __launch_bounds__(256) void blk_reduce_kernel(const ModelDev* __restr
     const int64_t gidx = R.gbase + l;
     const int32_t c = rcanon[gidx];
     if (c >= 0) {
-      if (accb64) {
-        // one FP64 slot, or one per level (subiterations): the arrays and their sum
-        for (int s = 0; s < n_slots; ++s) {
-          const double v = accb64[s * stride + gidx];
-          sum += v;
-          if (lvl_out) lvl_out[s * lvl_stride + m.canon_base + c] = v;
-        }
-      } else {
-        const int ns = n_slots > 1 ? m.nl : 1;
-        for (int s = 0; s < ns; ++s) {
-          const double v = (double)accb[s * stride + gidx];
-          sum += v;
-          if (e_lam_node) e_lam_node[m.lamnode_base + (int64_t)s * m.n_nodes + c] = v;
-        }
+      const int ns = lvl_out ? n_slots : (n_slots > 1 ? m.nl : 1);
+      for (int s = 0; s < ns; ++s) {
+        const double v = accb64[s * stride + gidx];
+        sum += v;
+        if (lvl_out) lvl_out[s * lvl_stride + m.canon_base + c] = v;
+        if (e_lam_node) e_lam_node[m.lamnode_base + (int64_t)s * m.n_nodes + c] = v;
       }
       if (e_node) e_node[m.canon_base + c] = sum;
     }
@@ -955,11 +942,11 @@ hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_byte
 }
 
 hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, int n_regions,
-                             int32_t max_region_nodes, const int32_t* rcanon, const float* accb,
-                             const double* accb64, int64_t stride, int n_slots, double* e_node, double* e_lam_node,
+                             int32_t max_region_nodes, const int32_t* rcanon, const double* accb64,
+                             int64_t stride, int n_slots, double* e_node, double* e_lam_node,
                              double* lvl_out, int64_t lvl_stride, double* e_total, hipStream_t s) {
   if (n_regions == 0) return hipSuccess;
   hipLaunchKernelGGL(blk_reduce_kernel, dim3((max_region_nodes + 255) / 256, n_regions), dim3(256), 0, s, models,
-                     regions, rcanon, accb, accb64, stride, n_slots, e_node, e_lam_node, lvl_out, lvl_stride, e_total);
+                     regions, rcanon, accb64, stride, n_slots, e_node, e_lam_node, lvl_out, lvl_stride, e_total);
   return hipGetLastError();
 }

@@ -64,6 +64,8 @@ struct DevStats {
   double e_emit, e_killed, e_rr_gain, e_trunc;
   unsigned long long splits, split_kills, split_skips;
   double e_split_killed, e_split_gain;
+  unsigned long long misplaced;  // queue records found outside the region they were queued for
+                                 // (an internal invariant; the call fails when it is not 0)
 };
 
 // A scattering event kept for the peel-off (Sect. 2.4): position (root-cell units), incoming
@@ -90,8 +92,7 @@ struct TraceParams {
   int32_t n_esc;
   uint64_t total_packets;
   unsigned long long* counter;
-  float* acc32;
-  double* acc64;
+  double* acc64;             // FP64 accumulators [slots][internal ids] (plain and one-queue forms)
   double* esc;
   DevStats* stats;
   rt_record* rec;
@@ -201,10 +202,9 @@ struct BlkParams {
   const int32_t* root_region;  // per internal id of a root cell (old layout): its region, or
                                // ~s when the cell is split (split_tab entry s)
   const int32_t* split_tab;    // 8 per split cell, by child octant: region id, or ~s (split again)
-  float* accb;               // [slots][G] region-major FP32 accumulators (per-wavelength output)
-  double* accb64;            // [G] region-major FP64 accumulators (wavelength-integrated output);
-                             // when set, every key has slot 0 and accb is unused; with
-                             // lvl_slots > 0, [lvl_slots][G]
+  double* accb64;            // [slots][G] region-major FP64 accumulators: one slot (wavelength-
+                             // integrated output), one per wavelength (per-wavelength output) or
+                             // one per level (lvl_slots > 0); a key's slot selects the array
   int64_t accb_stride;       // G
   // queues
   PRec* u_out;               // append target
@@ -268,8 +268,7 @@ hipError_t launch_sweep_sort(SweepState* st, int in, int slot, uint64_t batch, u
 hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s);
 hipError_t attr_blk_pass(int block, int lds_bytes);
 hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, int n_regions,
-                             int32_t max_region_nodes, const int32_t* rcanon, const float* accb,
-                             const double* accb64,
+                             int32_t max_region_nodes, const int32_t* rcanon, const double* accb64,
                              int64_t stride, int n_slots, double* e_node, double* e_lam_node,
                              double* lvl_out, int64_t lvl_stride, double* e_total, hipStream_t s);
 
@@ -278,7 +277,7 @@ hipError_t launch_trace_fp64(const TraceParams& p, int job, uint64_t n, int bloc
 hipError_t launch_trace_fp32(const TraceParams& p, int grid, int block, hipStream_t s);
 hipError_t occupancy_trace_fp32(int block, int* blocks_per_cu);
 hipError_t launch_reduce_model(const ModelDev* models_dev, int model, int64_t n_nodes,
-                               const float* acc32, const double* acc64, int64_t slot_stride,
+                               const double* acc64, int64_t slot_stride,
                                int n_slots, double* e_node, double* e_lam_node, double* e_total,
                                hipStream_t s);
 hipError_t launch_locate(const int32_t* child, const ModelDev* models, int model, int64_t n,

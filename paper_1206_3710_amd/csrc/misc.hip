@@ -6,10 +6,9 @@ using namespace rtd;
 
 namespace {
 
-// Sum the wavelength slots of each node into FP64 (canonical order), optionally keep the
+// Sum the wavelength slots of each node (canonical order), optionally keep the
 // per-(wavelength, node) values, and add the model total.
 __global__ __launch_bounds__(256) void reduce_kernel(const ModelDev* __restrict__ models, int model,
-                                                     const float* __restrict__ acc32,
                                                      const double* __restrict__ acc64,
                                                      int64_t slot_stride, int n_slots,
                                                      double* __restrict__ e_node,
@@ -22,7 +21,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const ModelDev* __restrict_
   if (c < m.n_nodes) {
     const int64_t internal = m.base + (c < m.n_root ? c : c + (m.n_root_pad - m.n_root));
     for (int s = 0; s < n_slots; ++s) {
-      const double v = acc32 ? (double)acc32[s * slot_stride + internal] : acc64[s * slot_stride + internal];
+      const double v = acc64[s * slot_stride + internal];
       sum += v;
       if (e_lam_node) e_lam_node[m.lamnode_base + s * m.n_nodes + c] = v;
     }
@@ -148,12 +147,11 @@ hipError_t launch_crit(const ModelDev* models, int model, int64_t n_nodes, const
 }
 
 hipError_t launch_reduce_model(const ModelDev* models_dev, int model, int64_t n_nodes,
-                               const float* acc32, const double* acc64, int64_t slot_stride,
+                               const double* acc64, int64_t slot_stride,
                                int n_slots, double* e_node, double* e_lam_node, double* e_total,
                                hipStream_t s) {
   const int64_t grid = (n_nodes + 255) / 256;
-  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)grid), dim3(256), 0, s, models_dev, model, acc32,
-                     acc64, slot_stride, n_slots, e_node, e_lam_node, e_total);
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)grid), dim3(256), 0, s, models_dev, model, acc64, slot_stride, n_slots, e_node, e_lam_node, e_total);
   return hipGetLastError();
 }
 

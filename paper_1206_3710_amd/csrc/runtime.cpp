@@ -87,6 +87,8 @@ struct rt_ctx {
   // work buffers
   DevBuf acc, esc, stats, counter, jobs, records, out_node, out_lamnode, out_esc, e_total;
   DevBuf t_tab;  // inverse table of the emission per unit mass (temperature solves)
+  DevBuf last_node;          // absorbed power per node of the last rt_trace_packets call
+  int64_t last_nodes = -1;   // node total when it was written (-1: none yet)
   DevBuf cdf_lum, cdf_q, cdf_qpre, lmax, scan_tmp;
   DevBuf tmp_in, tmp_out, tmp_out2, view, lamidx;
   DevBuf it_astars, it_adust, it_sum, it_told, it_crit, it_self, it_emit;
@@ -522,11 +524,16 @@ rt_status rt_destroy(rt_ctx* ctx) {
                     &ctx->it_sum, &ctx->it_told, &ctx->it_crit, &ctx->d_regions, &ctx->d_rword,
                     &ctx->d_rup, &ctx->d_rcanon, &ctx->d_root_region, &ctx->d_split, &ctx->q_rec[0], &ctx->q_rec[1],
                     &ctx->q_key[0], &ctx->q_key[1], &ctx->q_perm, &ctx->q_hist, &ctx->q_kfill,
-                    &ctx->q_items, &ctx->q_state};
+                    &ctx->q_items, &ctx->q_state, &ctx->last_node, &ctx->t_tab, &ctx->it_self,
+                    &ctx->it_emit, &ctx->peel_ev, &ctx->peel_ctr, &ctx->peel_tab, &ctx->peel_roottab,
+                    &ctx->peel_tabroot, &ctx->peel_dnu, &ctx->peel_img};
   for (DevBuf* b : bufs) b->release();
   for (HostModel& m : ctx->models) {
     m.d_lc.release();
     m.d_T.release();
+    m.sub_astars.release();
+    m.sub_arrays.release();
+    m.sub_imb.release();
   }
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -910,13 +917,10 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   int max_nl = 1;
   for (const HostModel& h : ctx->models) max_nl = std::max(max_nl, h.nl);
   const bool fp32 = o->precision == RT_FP32_LOCAL;
-  // per-wavelength accumulator slots: for the one-queue FP32 form (its global FP32 sums stay
-  // short), and whenever per-(wavelength, node) output is requested.  The region schedule sums
-  // each work item in LDS and flushes to FP64 accumulators, so it needs no slots otherwise.
-  const bool region_form = fp32 && o->schedule == RT_SCHED_REGIONS;
-  int n_slots = ((fp32 && !region_form) || out.e_lamnode) ? max_nl : 1;
-  const size_t elem = fp32 ? 4 : 8;
-  if (fp32 && !out.e_lamnode && (double)n_slots * ctx->total_int * elem > 96e9) n_slots = 1;
+  // FP64 accumulators in every form: one slot per node, or one per (wavelength, node) when
+  // per-wavelength output is requested
+  const int n_slots = out.e_lamnode ? max_nl : 1;
+  const size_t elem = 8;
   const int64_t stride = ctx->total_int;
   HIPCHK(ctx->acc.ensure((size_t)n_slots * stride * elem));
   HIPCHK(hipMemsetAsync(ctx->acc.p, 0, (size_t)n_slots * stride * elem, ctx->stream));
@@ -1016,8 +1020,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   p.n_esc = (int32_t)tot_lam;
   p.total_packets = start;
   p.counter = ctx->counter.as<unsigned long long>();
-  p.acc32 = fp32 ? ctx->acc.as<float>() : nullptr;
-  p.acc64 = fp32 ? nullptr : ctx->acc.as<double>();
+  p.acc64 = ctx->acc.as<double>();
   p.esc = out.e_esc;
   p.stats = ctx->stats.as<DevStats>();
   p.rec = static_cast<rt_record*>(rec_dev);
@@ -1071,10 +1074,9 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     reg_lds = 8 * cap + 4 * (cap / 8);
     if (rt_status e = build_regions(ctx, cap)) return e;
     HIPCHK(attr_blk_pass(bs, reg_lds));
-    // per-wavelength output: FP32 slots; wavelength-integrated: one FP64 accumulator per node;
-    // subiterations: one FP64 accumulator per (level, node)
-    const size_t racc = n_lvl > 0 ? (size_t)n_lvl * ctx->reg_G * 8
-                                  : (n_slots > 1 ? (size_t)n_slots * ctx->reg_G * 4 : (size_t)ctx->reg_G * 8);
+    // region-major FP64 accumulators: one per node, per (wavelength, node) for per-wavelength
+    // output, per (level, node) for subiterations
+    const size_t racc = (size_t)key_slots * ctx->reg_G * 8;
     HIPCHK(ctx->acc.ensure(racc));
     HIPCHK(hipMemsetAsync(ctx->acc.p, 0, racc, ctx->stream));
   }
@@ -1118,7 +1120,6 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     BlkParams b;
     std::memset(&b, 0, sizeof b);
     b.t = p;
-    b.t.acc32 = nullptr;
     b.regions = ctx->d_regions.as<RegionDev>();
     b.n_regions = n_regions;
     b.cap = ctx->reg_cap;
@@ -1127,8 +1128,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     b.rcanon = ctx->d_rcanon.as<int32_t>();
     b.root_region = ctx->d_root_region.as<int32_t>();
     b.split_tab = ctx->d_split.as<int32_t>();
-    b.accb = (n_slots > 1 && n_lvl == 0) ? ctx->acc.as<float>() : nullptr;
-    b.accb64 = (n_slots > 1 && n_lvl == 0) ? nullptr : ctx->acc.as<double>();
+    b.accb64 = ctx->acc.as<double>();
     b.accb_stride = ctx->reg_G;
     b.lvl_slots = n_lvl;
     b.q_perm = ctx->q_perm.as<uint32_t>();
@@ -1247,19 +1247,16 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   if (regions) {
     HIPCHK(launch_blk_reduce(ctx->d_models.as<ModelDev>(), ctx->d_regions.as<RegionDev>(),
                              (int)ctx->h_regions.size(), ctx->reg_maxn, ctx->d_rcanon.as<int32_t>(),
-                             (n_slots > 1 && n_lvl == 0) ? ctx->acc.as<float>() : nullptr,
-                             (n_slots > 1 && n_lvl == 0) ? nullptr : ctx->acc.as<double>(), ctx->reg_G,
-                             key_slots, out.e_node, (n_slots > 1 && n_lvl == 0) ? out.e_lamnode : nullptr,
+                             ctx->acc.as<double>(), ctx->reg_G, key_slots, out.e_node,
+                             n_lvl == 0 ? out.e_lamnode : nullptr,
                              n_lvl > 0 ? out.lvl_acc : nullptr, out.lvl_stride, ctx->e_total.as<double>(),
                              ctx->stream));
   } else {
     for (size_t m = 0; m < ctx->models.size(); ++m) {
       const HostModel& h = ctx->models[m];
       const int ns = n_slots > 1 ? std::max(h.nl, 1) : 1;
-      HIPCHK(launch_reduce_model(ctx->d_models.as<ModelDev>(), (int)m, h.n_nodes,
-                                 fp32 ? ctx->acc.as<float>() : nullptr,
-                                 fp32 ? nullptr : ctx->acc.as<double>(), stride, ns, out.e_node,
-                                 n_slots > 1 ? out.e_lamnode : nullptr, ctx->e_total.as<double>(),
+      HIPCHK(launch_reduce_model(ctx->d_models.as<ModelDev>(), (int)m, h.n_nodes, ctx->acc.as<double>(),
+                                 stride, ns, out.e_node, out.e_lamnode, ctx->e_total.as<double>(),
                                  ctx->stream));
     }
   }
@@ -1274,6 +1271,11 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   HIPCHK(hipMemcpyAsync(&etot, ctx->e_total.p, 8, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipMemcpyAsync(esc.data(), out.e_esc, 8 * tot_lam, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ds.misplaced)
+    return fail(ctx, RT_EDEVICE,
+                "internal error: %llu packet records were queued for a region that does not hold "
+                "their cell; their energy is missing from the results",
+                (unsigned long long)ds.misplaced);
   if (st_out) {
     float k_ms = 0.f, r_ms = 0.f;
     HIPCHK(hipEventElapsedTime(&k_ms, ctx->ev0, ctx->ev1));
@@ -1341,10 +1343,15 @@ rt_status rt_trace_packets(rt_ctx* ctx, int32_t n_src, const rt_source* src, con
       HIPCHK(ctx->out_esc.ensure(8 * std::max<int64_t>(tl, 1)));
       pe = ctx->out_esc.p;
     }
-    out.e_node = static_cast<double*>(pn);
+    HIPCHK(ctx->last_node.ensure(8 * std::max<int64_t>(tn, 1)));
+    out.e_node = pn ? static_cast<double*>(pn) : ctx->last_node.as<double>();
     out.e_lamnode = static_cast<double*>(pln);
     out.e_esc = static_cast<double*>(pe);
+    ctx->last_nodes = -1;
     if (rt_status s = trace_impl(ctx, n_src, src, o, out, stats)) return s;
+    // kept for rt_solve_temperature(a_node = NULL)
+    if (pn) HIPCHK(hipMemcpyAsync(ctx->last_node.p, pn, 8 * tn, hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->last_nodes = tn;
     if (cn) HIPCHK(hipMemcpyAsync(e_abs_node, pn, 8 * tn, hipMemcpyDeviceToHost, ctx->stream));
     if (cln) HIPCHK(hipMemcpyAsync(e_abs_lambda_node, pln, 8 * tln, hipMemcpyDeviceToHost, ctx->stream));
     if (ce) HIPCHK(hipMemcpyAsync(e_esc_lambda, pe, 8 * tl, hipMemcpyDeviceToHost, ctx->stream));
@@ -1358,14 +1365,18 @@ rt_status rt_solve_temperature(rt_ctx* ctx, int32_t model, const double* a_node,
   if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
   GUARD({
     if (rt_status s = check_model(ctx, model)) return s;
-    if (!a_node) return fail(ctx, RT_EINVAL, "null absorbed power");
     if (!(t_min > 0.0) || !(t_max > t_min) || !std::isfinite(t_max))
       return fail(ctx, RT_EINVAL, "need 0 < t_min < t_max");
     HostModel& h = ctx->models[model];
     if (h.nl < 1) return fail(ctx, RT_ESTATE, "rt_set_dust not called for model %d", model);
+    int64_t tn = 0;
+    totals(ctx, &tn, nullptr, nullptr);
+    if (!a_node && ctx->last_nodes != tn)
+      return fail(ctx, RT_ESTATE, "a_node is NULL but no rt_trace_packets result covers the current models");
     if (rt_status s = sync_device(ctx)) return s;
     const void* da;
-    if (rt_status s = stage_in(ctx, a_node, 8 * h.n_nodes, ctx->tmp_in, &da)) return s;
+    if (!a_node) da = ctx->last_node.as<double>() + ctx->h_models[model].canon_base;
+    else if (rt_status s = stage_in(ctx, a_node, 8 * h.n_nodes, ctx->tmp_in, &da)) return s;
     if (rt_status s = solve_T_impl(ctx, model, static_cast<const double*>(da), t_min, t_max)) return s;
     if (t_node)
       HIPCHK(hipMemcpyAsync(t_node, h.d_T.p, 8 * h.n_nodes,

@@ -14,8 +14,9 @@
 //   the last emission or scattering) and the exact face coordinate.
 // * One 4-byte load per visited node: the density word doubles as the subgrid identification
 //   entry (negative = refined).
-// * Deposits go to FP32 per-(wavelength, node) accumulators; the final FP64 reduction is a
-//   separate pass.
+// * Deposits go straight to FP64 accumulators (one per node, or per (wavelength, node) when
+//   per-wavelength output is asked for); the final reduction to canonical order is a separate
+//   pass.
 #include "device.h"
 
 using namespace rtd;
@@ -162,7 +163,9 @@ __global__ __launch_bounds__(BS) void trace_fp32_kernel(const TraceParams p) {
         if (!event) tau -= tsc;
         const float de = w * one_minus_exp(sa * s);
         if (de > 0.0f) {
-          unsafeAtomicAdd(p.acc32 + acc_off + node, de);
+          // FP64 accumulators: a point source deposits every packet's first segment in one
+          // cell, far more terms than an FP32 running sum can add without stalling
+          unsafeAtomicAdd(p.acc64 + acc_off + node, (double)de);
           w -= de;
         }
         x0 = clamp01(fmaf(s, d0, x0));

@@ -118,3 +118,28 @@ def test_ali_rejects_the_global_schedule(torch):
     t, nd, _ = ctx.lambda_iterate(m, star, seed=1, dust_packets=100, n_max=1, ali=True)
     assert nd == 1 and float(t.max()) > 0
     ctx.close()
+
+
+def test_ali_with_splitting_against_oracle(torch):
+    """Accelerated iteration with package splitting (factor 4) in the region schedule, three
+    steps: the temperatures stay below the Monte Carlo noise of the oracle's run with the same
+    splitting, and every temperature stays inside the solver's bracket (a self-absorption tally
+    above the emission would drive lambda* to its clamp and the temperature to t_max)."""
+    tree, dust, star = _small_case()
+    ora = oracle.Model(tree, dust)
+    ha, _, _ = oracle.lambda_iterate(ora, star, seed=31, n_fixed=3, dust_packets=4000, ali=True, split_n=4)
+    hb, _, _ = oracle.lambda_iterate(ora, star, seed=77, n_fixed=3, dust_packets=4000, ali=True, split_n=4)
+    ctx, m = _ctx(tree, dust)
+    tg, _, _ = ctx.lambda_iterate(m, star, seed=31, dust_packets=4000, n_max=3, tol=0.0, ali=True,
+                                  precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS, split_n=4)
+    ctx.close()
+    leaf = ora.leaf_mask
+    lv = ora.level_of_nodes()
+    w = (ora.node_rho() * 8.0 ** -lv.astype(float))[leaf]
+    t = tg.cpu().numpy()
+    assert np.all(t[leaf] < 2999.0) and np.all(t[leaf] > 2.0)
+
+    def diff(a, ref):
+        return float((w * np.abs(a[leaf] - ref[leaf]) / ref[leaf]).sum() / w.sum())
+    err, noise = diff(t, ha[-1]), diff(hb[-1], ha[-1])
+    assert err < 0.5 * noise, (err, noise)

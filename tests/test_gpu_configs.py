@@ -6,8 +6,10 @@ on a coarser disc of the same shape (root 48x48x16 of 12.5 AU, 4 levels, 1.0e6 n
 wavelengths; the oracle's bisection temperature solve over 1.7e6 leaves x 50 wavelengths takes
 over a minute per step); the full disc (root 96x96x32, 6 levels, 1.9e6 nodes, 50 wavelengths,
 central 4000 K star, roulette on) for the FP32-local trace against the FP64 one.
-Batched clouds: 16 of the 64 uneven models (roots 16^3-48^3, 1-4 levels), 16 wavelengths,
-traced together in one call."""
+Batched clouds: all 64 uneven models (roots 16^3-48^3, 1-4 levels), 16 wavelengths, traced
+together in one call.
+Lambda iteration in the FP32-local forms: three steps against the oracle's on a small refined
+cube around a star, below a tenth of the seed-to-seed difference after every step."""
 import math
 
 import numpy as np
@@ -81,9 +83,10 @@ def test_disc_fp32_local_vs_fp64(torch):
 
 
 def test_batched_clouds_one_call(torch):
-    """16 uneven models in one trace call: per-node FP64 parity with the oracle model by model,
-    and the FP32-local form within 1e-3 of the oracle per model."""
-    w = gen.c4(packets=1500, max_models=16)
+    """All 64 uneven models in one trace call: per-node FP64 parity with the oracle model by
+    model, and the FP32-local form within 1e-3 of the oracle per model."""
+    w = gen.c4(packets=1000)
+    assert len(w.trees) == 64
     ctx = rt.Context(0)
     ids = []
     for t, d in zip(w.trees, w.dusts):
@@ -109,4 +112,49 @@ def test_batched_clouds_one_call(torch):
         assert rel_rms(e32[base:base + nn], eo) <= 1e-3, k
         base += nn
     assert base == len(e64)
+    ctx.close()
+
+
+def _star_cube():
+    """4^3 root refined once (512 leaves), 10 wavelengths, a 5000 K star off the centre."""
+    from tests import brute
+    lam = np.logspace(-1, 3, 10)
+    kap = 3.0 * (lam / 0.55) ** -1.6
+    alb = np.clip(0.5 * (1 - np.log10(lam / 0.1) / 4), 0, 0.5)
+    dust = gen.Dust(lam, kap, alb, alb.copy())
+    tree = gen.uniform_refined_tree((4, 4, 4), 1, rho=1.0, cell_cm=1.0)
+    tree.child_rho[0] = tree.child_rho[0] * np.linspace(0.5, 1.5, len(tree.child_rho[0]))
+    nu = brute.CL / (lam * 1e-4)
+    star = [gen.Source(gen.SRC_POINT, 0, pos=(2.1, 1.9, 2.05), power=1e-2 * brute.planck_nu(nu, 5000.0),
+                       packets=4000)]
+    return tree, dust, star
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_lambda_iteration_fp32_local_against_oracle(torch, schedule):
+    """rt_lambda_iterate in the FP32-local form (region schedule, and the one-queue schedule),
+    1, 2 and 3 steps from the constant sources: after every step the mass-weighted mean relative
+    temperature difference to the oracle is below a tenth of that between two oracle runs with
+    different seeds."""
+    tree, dust, star = _star_cube()
+    kw = dict(rr_threshold=1e-3, rr_prob=0.9)
+    ora = oracle.Model(tree, dust)
+    ha, _, _ = oracle.lambda_iterate(ora, star, seed=31, n_fixed=3, dust_packets=4000, **kw)
+    hb, _, _ = oracle.lambda_iterate(ora, star, seed=77, n_fixed=3, dust_packets=4000, **kw)
+    leaf = ora.leaf_mask
+    lv = ora.level_of_nodes()
+    mass = (ora.node_rho() * 8.0 ** -lv.astype(float))[leaf]
+
+    def diff(t, ref):
+        return float((mass * np.abs(t[leaf] - ref[leaf]) / ref[leaf]).sum() / mass.sum())
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    for n in (1, 2, 3):
+        tg, nd, _ = ctx.lambda_iterate(m, star, seed=31, dust_packets=4000, n_max=n, tol=0.0,
+                                       precision=rt.FP32_LOCAL, schedule=schedule, **kw)
+        assert nd == n
+        err, noise = diff(tg.cpu().numpy(), ha[n]), diff(hb[n], ha[n])
+        print(f"schedule {schedule} step {n}: {err:.2e} vs seed-to-seed {noise:.2e}")
+        assert err < 0.1 * noise, (n, err, noise)
     ctx.close()

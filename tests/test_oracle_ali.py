@@ -83,3 +83,30 @@ def test_ali_converges_faster():
         mean[ali] = [float(np.mean(h[leaf])) for h in hist]
         assert all(b > a for a, b in zip(mean[ali][:-1], mean[ali][1:]))  # rising
     assert mean[True][-1] > 1.08 * mean[False][-1], (mean[True][-1], mean[False][-1])
+
+
+def test_self_absorption_with_splitting_stays_below_emission():
+    """With package splitting the branches split off a package start counting their cells at 0
+    where they split; only the package as emitted, before its first crossing, is in its birth
+    cell.  Per cell the tally then never exceeds what the cell's own packets absorbed or emitted,
+    and it equals the unsplit tally in expectation (the first segment is never split)."""
+    lam = np.logspace(0, 3, 8)
+    dust = gen.Dust(lam, 5.0 * lam ** -1.2, np.full(8, 0.6), np.full(8, 0.3))
+    tree = gen.uniform_refined_tree((4, 4, 4), 2, rho=1.0, cell_cm=1.0)
+    # refine only part of the cube, so that crossings into deeper leaves (splits) happen
+    o = oracle.Model(tree, dust)
+    rng = np.random.default_rng(12)
+    leaf = o.leaf_mask
+    t = np.where(leaf, rng.uniform(30.0, 120.0, o.n_nodes), 0.0)
+    rb = gen.refined_block(2, n=4, rho=1.0)
+    ob = oracle.Model(rb, dust)
+    tb = np.where(ob.leaf_mask, rng.uniform(30.0, 120.0, ob.n_nodes), 0.0)
+    for model, temps in ((o, t), (ob, tb)):
+        _, _, s1, _ = model.trace(_dust_source(4000), seed=9, t_node=temps, self_absorption=True)
+        _, _, s4, _ = model.trace(_dust_source(4000), seed=9, t_node=temps, self_absorption=True,
+                                  split_n=4)
+        assert np.all(s4["e_self"] <= s4["e_emit_node"] * (1.0 + 1e-12))
+        # the package as emitted deposits the same before its first crossing with or without
+        # splitting (a split happens only at a crossing)
+        np.testing.assert_allclose(s4["e_self"], s1["e_self"], rtol=1e-12, atol=0.0)
+    assert s4["splits"] > 0
