@@ -299,6 +299,23 @@ rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32
                         double width, int32_t n_sel, const int32_t* lambda_idx,
                         int32_t precision, double* image, uint64_t* crossings);
 
+/* Allocation-free variant of rt_render_map, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same map,
+ * same kernels and arguments, except: image must be device memory of the context's GPU;
+ * lambda_idx is a host array of at most 512 entries (RT_EINVAL beyond: the per-call staging
+ * lives in a fixed 2.3 KB device array, not in context buffers); crossings (host, may be NULL).
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library routine): the view
+ * frame, the wavelength list and the crossing counter are written into a file-scope device
+ * array, located on each device once when a context is created there, and cleared by every
+ * call.  Every call on one GPU shares that array, so calls that overlap on one GPU (several
+ * contexts or threads on one device) race and must be serialised by the caller.  The
+ * context's device copies of the models must be current (RT_ESTATE otherwise): after
+ * rt_build_tree or rt_set_dust, one allocating call such as rt_render_map or
+ * rt_trace_packets uploads them. */
+rt_status rt_render_map_noalloc(rt_ctx* ctx, int32_t model, const double n_obs[3], int32_t npix,
+                                double width, int32_t n_sel, const int32_t* lambda_idx,
+                                int32_t precision, double* image, uint64_t* crossings);
+
 /* Peel-off images of the scattered light (Sect. 2.4).  The sources (all of one model) are
  * traced as by rt_trace_packets with the same options (RT_FP64, or RT_FP32_LOCAL with the
  * region schedule); at every scattering event, before the event roulette, the part of the

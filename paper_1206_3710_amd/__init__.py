@@ -25,7 +25,8 @@ SCHED_REGIONS, SCHED_GLOBAL = 0, 1
 EXPORTS = ["rt_last_error", "rt_create", "rt_destroy", "rt_build_tree", "rt_get_model_info",
            "rt_get_sizes", "rt_locate", "rt_set_dust", "rt_set_temperature", "rt_trace_packets",
            "rt_solve_temperature", "rt_lambda_iterate", "rt_ali_iterate", "rt_subiter_begin",
-           "rt_subiter_step", "rt_subiter_select", "rt_subiter_run", "rt_render_map", "rt_peel_map",
+           "rt_subiter_step", "rt_subiter_select", "rt_subiter_run", "rt_render_map",
+           "rt_render_map_noalloc", "rt_peel_map",
            "rt_autotune", "rt_philox"]
 
 
@@ -118,6 +119,7 @@ def lib():
             "rt_subiter_select": (I32, [P, I32, D, P, P]),
             "rt_subiter_run": (I32, [P, I32, I32, D, D, I64, U32, P, P, P, P, P]),
             "rt_render_map": (I32, [P, I32, P, I32, D, I32, P, I32, P, P]),
+            "rt_render_map_noalloc": (I32, [P, I32, P, I32, D, I32, P, I32, P, P]),
             "rt_peel_map": (I32, [P, I32, P, P, P, P]),
             "rt_autotune": (I32, [P, I32, P, P, D, C.c_char_p, P, P]),
             "rt_philox": (I32, [P, U32, U32, I64, P, P]),
@@ -443,6 +445,20 @@ class Context:
         self._check(lib().rt_render_map(self.h, model, _ptr(nv), npix, width, len(li), _ptr(li),
                                         precision, _ptr(img), C.byref(cr)))
         return img, int(cr.value)
+
+    def render_map_noalloc(self, model: int, n_obs, npix: int, lambda_idx, image=None,
+                           width: float = 0.0, precision: int = FP64):
+        """rt_render_map_noalloc: the map into ``image`` (a device tensor [n_sel, npix, npix]
+        float64, allocated here when None); returns (image, crossings)."""
+        torch = _torch()
+        nv = np.ascontiguousarray(n_obs, dtype=np.float64)
+        li = np.ascontiguousarray(lambda_idx, dtype=np.int32)
+        if image is None:
+            image = torch.empty((len(li), npix, npix), dtype=torch.float64, device=self.tdev)
+        cr = C.c_uint64()
+        self._check(lib().rt_render_map_noalloc(self.h, model, _ptr(nv), npix, width, len(li), _ptr(li),
+                                                precision, _ptr(image), C.byref(cr)))
+        return image, int(cr.value)
 
     def philox(self, key0: int, key1: int, ctr):
         torch = _torch()

@@ -321,3 +321,14 @@ hipError_t launch_render(bool f32, const ModelDev* models, int model, const int3
                          const LamConst* lc, const int32_t* lam_idx, int n_sel,
                          const double* view /* n, e1, e2, centre, W */, int npix,
                          double* image, unsigned long long* crossings, hipStream_t s);
+
+// Allocation-free maps (render.hip): wavelengths per call, the per-device scratch array's
+// location (found once per device when a context is created) and the launch.
+constexpr int kRenderNoAllocMaxSel = 512;
+hipError_t render_scratch_init(int device);
+void* render_scratch(int device);
+hipError_t launch_render_noalloc(bool f32, const ModelDev* models, int model, const int32_t* child,
+                                 const int32_t* up, const double* rho64, const double* t_node,
+                                 const LamConst* lc, const int32_t* lam_idx_host, int n_sel,
+                                 const double* view_host, int npix, double* image, void* scr,
+                                 unsigned long long* crossings_host, hipStream_t s);

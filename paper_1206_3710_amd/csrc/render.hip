@@ -6,6 +6,8 @@
 // Two forms share the ray geometry (FP64, so both visit the same cells): the FP64 form
 // evaluates the transfer in FP64; the FP32 form evaluates it per wavelength in FP32 (hardware
 // exponentials, constants staged in LDS), which is where the work of a map is.
+#include <mutex>
+
 #include "device.h"
 
 using namespace rtd;
@@ -198,4 +200,85 @@ hipError_t launch_render(bool f32, const ModelDev* models, int model, const int3
   }
 #undef RT_RENDER
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Allocation-free maps: the per-call staging (view frame, wavelength list) and the crossing
+// counter live in the file-scope device array `scratch` instead of context buffers.  Each
+// device's copy is located once, when a context is created on it (rt_create); calls on one
+// device share it, so calls that overlap on one device race.
+// ------------------------------------------------------------------------------------------
+namespace {
+
+constexpr int kScrView = 0;       // 13 doubles: n, e1, e2, box centre, width
+constexpr int kScrCount = 128;    // u64 crossing counter (cleared by every call)
+constexpr int kScrLam = 256;      // int32 wavelength indices
+constexpr int kScratchBytes = kScrLam + 4 * kRenderNoAllocMaxSel;
+constexpr int kMaxDevices = 64;
+
+struct RenderSetup {
+  double view[13];
+  int32_t n_sel;
+  int32_t lam[kRenderNoAllocMaxSel];
+};
+static_assert(sizeof(RenderSetup) <= 4096, "kernel argument size");
+
+// Writes one call's parameters into the scratch array and clears its counter (a kernel, not a
+// memset, so that the call can also be recorded into a graph).
+__global__ void render_setup_kernel(const RenderSetup a, unsigned char* __restrict__ scr) {
+  double* v = reinterpret_cast<double*>(scr + kScrView);
+  int32_t* li = reinterpret_cast<int32_t*>(scr + kScrLam);
+  for (int i = threadIdx.x; i < 13; i += blockDim.x) v[i] = a.view[i];
+  if (threadIdx.x == 0) *reinterpret_cast<unsigned long long*>(scr + kScrCount) = 0ull;
+  for (int i = threadIdx.x; i < a.n_sel; i += blockDim.x) li[i] = a.lam[i];
+}
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t render_scratch_init(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+void* render_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
+
+hipError_t launch_render_noalloc(bool f32, const ModelDev* models, int model, const int32_t* child,
+                                 const int32_t* up, const double* rho64, const double* t_node,
+                                 const LamConst* lc, const int32_t* lam_idx_host, int n_sel,
+                                 const double* view_host, int npix, double* image, void* scr,
+                                 unsigned long long* crossings_host, hipStream_t s) {
+  if (n_sel < 1 || n_sel > kRenderNoAllocMaxSel || !scr) return hipErrorInvalidValue;
+  RenderSetup a;
+  for (int i = 0; i < 13; ++i) a.view[i] = view_host[i];
+  a.n_sel = n_sel;
+  for (int i = 0; i < n_sel; ++i) a.lam[i] = lam_idx_host[i];
+  unsigned char* base = static_cast<unsigned char*>(scr);
+  hipLaunchKernelGGL(render_setup_kernel, dim3(1), dim3(256), 0, s, a, base);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const double* v = reinterpret_cast<const double*>(base + kScrView);
+  const int32_t* li = reinterpret_cast<const int32_t*>(base + kScrLam);
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(base + kScrCount);
+  for (int q0 = 0; q0 < n_sel; q0 += 16) {
+    const int nq = n_sel - q0 < 16 ? n_sel - q0 : 16;
+    e = launch_render(f32, models, model, child, up, rho64, t_node, lc, li + q0, nq, v, npix,
+                      image + (size_t)q0 * npix * npix, q0 == 0 ? cnt : nullptr, s);
+    if (e != hipSuccess) return e;
+  }
+  if (crossings_host) return hipMemcpyAsync(crossings_host, cnt, 8, hipMemcpyDeviceToHost, s);
+  return hipSuccess;
 }

@@ -507,6 +507,12 @@ rt_status rt_create(rt_ctx** out, int32_t device, void* hip_stream) {
     delete ctx;
     return fail(nullptr, RT_EDEVICE, "cannot initialise device %d", device);
   }
+  // the allocation-free maps' scratch array: its address on this device, once per device
+  if (render_scratch_init(device) != hipSuccess) {
+    (void)hipGetLastError();
+    rt_destroy(ctx);
+    return fail(nullptr, RT_EDEVICE, "cannot locate the scratch array on device %d", device);
+  }
   *out = ctx;
   return RT_OK;
 }
@@ -1306,6 +1312,40 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   return RT_OK;
 }
 
+// Orthographic view of the maps (Sect. 4.1): v = {n, e1, e2, box centre, width} with
+// e1 = z x n / |z x n| (x when n is along z), e2 = n x e1; width <= 0 takes the largest root
+// extent.  False for a zero or non-finite direction or a non-finite width.
+bool render_view(const HostModel& h, const double n_obs[3], double width, double v[13]) {
+  const double nn = std::sqrt(n_obs[0] * n_obs[0] + n_obs[1] * n_obs[1] + n_obs[2] * n_obs[2]);
+  if (!(nn > 0.0) || !std::isfinite(nn) || !std::isfinite(width)) return false;
+  const double n[3] = {n_obs[0] / nn, n_obs[1] / nn, n_obs[2] / nn};
+  double e1[3], e2[3];
+  if (n[0] == 0.0 && n[1] == 0.0) {
+    e1[0] = 1.0;
+    e1[1] = 0.0;
+    e1[2] = 0.0;
+  } else {
+    const double ex = -n[1], ey = n[0];
+    const double en = std::sqrt(ex * ex + ey * ey);
+    e1[0] = ex / en;
+    e1[1] = ey / en;
+    e1[2] = 0.0;
+  }
+  e2[0] = n[1] * e1[2] - n[2] * e1[1];
+  e2[1] = n[2] * e1[0] - n[0] * e1[2];
+  e2[2] = n[0] * e1[1] - n[1] * e1[0];
+  double W = width;
+  if (!(W > 0.0)) W = std::max<double>(h.n[0], std::max<double>(h.n[1], h.n[2]));
+  for (int a = 0; a < 3; ++a) {
+    v[a] = n[a];
+    v[3 + a] = e1[a];
+    v[6 + a] = e2[a];
+    v[9 + a] = 0.5 * h.n[a];
+  }
+  v[12] = W;
+  return true;
+}
+
 rt_status solve_T_impl(rt_ctx* ctx, int32_t model, const double* a_dev, double t_min, double t_max) {
   HostModel& h = ctx->models[model];
   HIPCHK(h.d_T.ensure(8 * h.n_nodes));
@@ -1736,35 +1776,8 @@ rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32
     if (!h.has_T) return fail(ctx, RT_ESTATE, "model %d has no temperatures", model);
     for (int q = 0; q < n_sel; ++q)
       if (lambda_idx[q] < 0 || lambda_idx[q] >= h.nl) return fail(ctx, RT_EINVAL, "bad wavelength index");
-    const double nn = std::sqrt(n_obs[0] * n_obs[0] + n_obs[1] * n_obs[1] + n_obs[2] * n_obs[2]);
-    if (!(nn > 0.0) || !std::isfinite(nn)) return fail(ctx, RT_EINVAL, "bad view direction");
-    if (!std::isfinite(width)) return fail(ctx, RT_EINVAL, "bad width");
     double v[13];
-    const double n[3] = {n_obs[0] / nn, n_obs[1] / nn, n_obs[2] / nn};
-    double e1[3], e2[3];
-    if (n[0] == 0.0 && n[1] == 0.0) {
-      e1[0] = 1.0;
-      e1[1] = 0.0;
-      e1[2] = 0.0;
-    } else {
-      const double ex = -n[1], ey = n[0];
-      const double en = std::sqrt(ex * ex + ey * ey);
-      e1[0] = ex / en;
-      e1[1] = ey / en;
-      e1[2] = 0.0;
-    }
-    e2[0] = n[1] * e1[2] - n[2] * e1[1];
-    e2[1] = n[2] * e1[0] - n[0] * e1[2];
-    e2[2] = n[0] * e1[1] - n[1] * e1[0];
-    double W = width;
-    if (!(W > 0.0)) W = std::max<double>(h.n[0], std::max<double>(h.n[1], h.n[2]));
-    for (int a = 0; a < 3; ++a) {
-      v[a] = n[a];
-      v[3 + a] = e1[a];
-      v[6 + a] = e2[a];
-      v[9 + a] = 0.5 * h.n[a];
-    }
-    v[12] = W;
+    if (!render_view(h, n_obs, width, v)) return fail(ctx, RT_EINVAL, "bad view direction or width");
     if (rt_status s = sync_device(ctx)) return s;
     HIPCHK(ctx->view.ensure(sizeof v));
     HIPCHK(hipMemcpyAsync(ctx->view.p, v, sizeof v, hipMemcpyHostToDevice, ctx->stream));
@@ -1790,6 +1803,46 @@ rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32
     if (copy) HIPCHK(hipMemcpyAsync(image, dimg, img_bytes, hipMemcpyDeviceToHost, ctx->stream));
     unsigned long long cr = 0;
     HIPCHK(hipMemcpyAsync(&cr, ctx->counter.p, 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (crossings) *crossings = cr;
+    return RT_OK;
+  })
+}
+
+rt_status rt_render_map_noalloc(rt_ctx* ctx, int32_t model, const double n_obs[3], int32_t npix, double width,
+                                int32_t n_sel, const int32_t* lambda_idx, int32_t precision, double* image,
+                                uint64_t* crossings) {
+  if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
+  GUARD({
+    if (rt_status s = check_model(ctx, model)) return s;
+    if (!n_obs || !lambda_idx || !image) return fail(ctx, RT_EINVAL, "null argument");
+    if (npix < 1 || npix > 16384) return fail(ctx, RT_EINVAL, "npix must be in [1, 16384]");
+    if (n_sel < 1 || n_sel > kRenderNoAllocMaxSel)
+      return fail(ctx, RT_EINVAL, "n_sel must be in [1, %d] (the scratch array holds %d wavelength indices)",
+                  kRenderNoAllocMaxSel, kRenderNoAllocMaxSel);
+    if (precision != RT_FP64 && precision != RT_FP32_LOCAL)
+      return fail(ctx, RT_EINVAL, "precision must be RT_FP64 or RT_FP32_LOCAL");
+    HostModel& h = ctx->models[model];
+    if (h.nl < 1) return fail(ctx, RT_ESTATE, "rt_set_dust not called for model %d", model);
+    if (!h.has_T) return fail(ctx, RT_ESTATE, "model %d has no temperatures", model);
+    for (int q = 0; q < n_sel; ++q)
+      if (lambda_idx[q] < 0 || lambda_idx[q] >= h.nl) return fail(ctx, RT_EINVAL, "bad wavelength index");
+    double v[13];
+    if (!render_view(h, n_obs, width, v)) return fail(ctx, RT_EINVAL, "bad view direction or width");
+    if (!is_device_ptr(image)) return fail(ctx, RT_EINVAL, "image must be device memory of the context's GPU");
+    // uploading changed models would allocate: the device copies must already be current
+    if (ctx->tree_dirty || ctx->table_dirty)
+      return fail(ctx, RT_ESTATE, "the device copies of the models are out of date: one allocating call "
+                                  "(e.g. rt_render_map or rt_trace_packets) is needed after rt_build_tree "
+                                  "or rt_set_dust");
+    void* scr = render_scratch(ctx->device);
+    if (!scr) return fail(ctx, RT_ESTATE, "no scratch array on device %d", ctx->device);
+    HIPCHK(hipSetDevice(ctx->device));
+    unsigned long long cr = 0;
+    HIPCHK(launch_render_noalloc(precision == RT_FP32_LOCAL, ctx->d_models.as<ModelDev>(), model,
+                                 ctx->d_child.as<int32_t>(), ctx->d_up.as<int32_t>(), ctx->d_rho64.as<double>(),
+                                 h.d_T.as<double>(), h.d_lc.as<LamConst>(), lambda_idx, n_sel, v, npix, image,
+                                 scr, crossings ? &cr : nullptr, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (crossings) *crossings = cr;
     return RT_OK;
