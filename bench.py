@@ -341,6 +341,45 @@ def subiter_study(rt, gen, ref_steps=40, packets=200_000, frac=0.5, stall=0.8):
     return res
 
 
+def lambda_graph_study(rt, gen, kw32, packets=1_000_000, steps=6):
+    """Lambda iteration on the circumstellar disc (Sect. 3.1 Eq. 2), FP32-local region schedule,
+    with every step launched directly against every step after the first replayed from one
+    captured HIP graph: time per step (the difference between a run of `steps` steps and a run
+    of one, both from the star's trace) and the temperature difference between the two."""
+    import numpy as np
+    import torch
+    w = gen.c3(packets=packets)
+    tree, dust = w.trees[0], w.dusts[0]
+    level, leaf, rho, _ = node_geometry(tree)
+    mass = (rho * 8.0 ** (-level.astype(np.float64)))[leaf]
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    base = {k_: v for k_, v in kw32.items() if k_ != "sweep_graph"}
+    base.update(precision=rt.FP32_LOCAL, rr_threshold=w.rr_threshold, rr_prob=w.rr_prob)
+    out = {"model": "circumstellar disc, root 96x96x32, 6 levels, 50 wavelengths",
+           "dust_packets_per_lambda": packets, "steps": steps}
+    temps = {}
+    for name, g in (("direct", 0), ("graph", 1)):
+        times = {}
+        for n in (1, steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t_, nd, crit = ctx.lambda_iterate(m, w.sources, seed=w.seed, dust_packets=packets, n_max=n, tol=0.0,
+                                              sweep_graph=g, **base)
+            torch.cuda.synchronize()
+            times[n] = time.perf_counter() - t0
+        temps[name] = t_.cpu().numpy()[leaf]
+        out[name] = {"ms_per_step": 1e3 * (times[steps] - times[1]) / (steps - 1),
+                     "criteria": [float(c) for c in crit]}
+        print(f"# Lambda-iteration graph study: {name} done", file=sys.stderr, flush=True)
+    a, b = temps["direct"], temps["graph"]
+    out["t_rel_diff_mass_weighted"] = float((mass * np.abs(a - b) / a).sum() / mass.sum())
+    out["speedup"] = out["direct"]["ms_per_step"] / out["graph"]["ms_per_step"]
+    ctx.close()
+    return out
+
+
 def pass_sources_sha():
     import hashlib
     h = hashlib.sha256()
@@ -388,6 +427,9 @@ def parse():
                     help="add the accelerated-iteration convergence study (a thick cube)")
     ap.add_argument("--subiter-study", action="store_true",
                     help="add the subiteration study (a thin cloud with a dense core)")
+    ap.add_argument("--lambda-graph-study", action="store_true",
+                    help="add Lambda-iteration steps on the disc launched directly against replayed "
+                         "from a captured graph")
     ap.add_argument("--peel-study", action="store_true",
                     help="add the peel-off timing study (cloud, disc and deep workloads)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -518,7 +560,7 @@ def measure(a, rt, gen, torch, w, workload, steps, warmup, copy_gbs, fp64_steps,
         if workload == "disc":
             ctx.set_temperature(m, t0_disc)
         tune_src = dust_src if workload == "disc" else w.sources
-        frac = 1.0 / 64.0 if workload == "deep" else 0.125
+        frac = 0.125
         params, rate = ctx.autotune(tune_src, seed=w.seed, precision=rt.FP32_LOCAL,
                                     schedule=a.schedule, sample_fraction=frac,
                                     cache=a.tune_cache, rr_threshold=w.rr_threshold,
@@ -735,6 +777,10 @@ def main():
     if a.subiter_study:
         subiters = subiter_study(rt, gen)
 
+    lgraph = None
+    if a.schedule == 0 and a.lambda_graph_study:
+        lgraph = lambda_graph_study(rt, gen, kw32)
+
     peeling = None
     if a.workload in ("cloud", "disc", "deep") and a.schedule == 0 and a.peel_study:
         peeling = peel_study(rt, gen, load_workload(gen, a.workload, a.packets), kw32, a.workload)
@@ -769,6 +815,7 @@ def main():
         "peel_off": peeling,
         "accelerated_iteration": accel,
         "subiterations": subiters,
+        "lambda_graph": lgraph,
     }
     print(json.dumps(res))
 

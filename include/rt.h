@@ -256,7 +256,13 @@ rt_status rt_ali_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_sou
  * the RT_FP32_LOCAL region schedule (without package splitting; RT_EINVAL otherwise).
  * rt_subiter_begin traces the constant sources (key iteration opts->iteration) into A_stars,
  * solves T_0 and clears the model's per-level arrays (one absorbed-energy array per hierarchy
- * level at or above each cell's own).
+ * level at or above each cell's own).  flux_frac > 0 turns on the tracking of the energy flow
+ * from each grid to its parent (Sect. 3.3): every step then also measures, per refined node,
+ * the weight of the packages leaving its subtree; when a step below root r changes the flow out
+ * of r's subtree by more than flux_frac times the energy absorbed in the subtree of r's parent
+ * (the whole model for a root cell) since that parent last took part in a step, the parent is
+ * tagged, and rt_subiter_select includes every tagged grid until a step includes it.
+ * flux_frac = 0: no tracking.
  * rt_subiter_step takes one step with the subtree below `root`, a refined canonical node of
  * the model, or the whole model (root = -1): the dust emission of the subtree's leaves at the
  * current temperatures is traced with key `iteration`; every deposit is filed under the
@@ -267,10 +273,10 @@ rt_status rt_ali_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_sou
  * arrays (Eq. 9).  crit (may be NULL): mass-weighted mean |T_new - T_old| / T_old over all
  * leaves; t_node (host or device, may be NULL): the temperatures after the step.
  * rt_subiter_select picks the next subtree (Sect. 3.3): the lowest common ancestor of every
- * leaf whose last recorded imbalance is within frac of the largest; root = -1 when that is the
- * whole model.  max_imbalance (may be NULL) receives the largest. */
+ * leaf whose last recorded imbalance is within frac of the largest and of every tagged grid;
+ * root = -1 when that is the whole model.  max_imbalance (may be NULL) receives the largest. */
 rt_status rt_subiter_begin(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
-                           const rt_trace_opts* opts, double t_min, double t_max);
+                           const rt_trace_opts* opts, double t_min, double t_max, double flux_frac);
 rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust_packets,
                           uint32_t iteration, const rt_trace_opts* opts, double* crit,
                           double* t_node, rt_trace_stats* stats);

@@ -74,7 +74,7 @@ def lib():
         L.om_trace.restype = C.c_int
         L.om_trace.argtypes = [P, C.c_int32, C.c_int32, P, P, P, P, P, P, C.c_uint64, C.c_uint32,
                                C.c_double, C.c_double, C.c_int64, C.c_int32, C.c_int64, C.c_int64,
-                               C.c_int32, P, P, P, C.c_int64, P, C.c_int32, P, P, P, P, C.c_int64]
+                               C.c_int32, P, P, P, C.c_int64, P, C.c_int32, P, P, P, P, C.c_int64, P]
         L.om_node_coords.argtypes = [P, P]
         L.om_emission_all.argtypes = [P, P, P]
         L.om_hg_phase.restype = C.c_double
@@ -195,7 +195,7 @@ class Model:
     def trace(self, sources, seed, iteration=0, model_index=0, rr_threshold=0.0, rr_prob=0.0,
               max_events=0, per_lambda=False, pid_begin=0, pid_end=-1, lam_sel=-1,
               t_node=None, rec_stride=0, deposits=True, split_n=1, peel=None, self_absorption=False,
-              level_arrays=False, subtree=-1, e_abs_out=None):
+              level_arrays=False, subtree=-1, e_abs_out=None, flux=False):
         """Follow packets of ``sources`` (gen.Source list) -> (e_abs, e_esc, stats, records).
         ``peel``: dict(n_obs=[[x, y, z], ...], npix=, width=0.0, tiles=0) turns on the peel-off
         images, returned in stats["peel_image"] as [n_dir, n_lambda, npix, npix].
@@ -204,7 +204,9 @@ class Model:
         [n_levels + 1, n_nodes], the deposits by the shallowest level visited; ``subtree``: a
         refined node whose subtree alone emits and holds the packages (subiterations).
         ``e_abs_out``: a caller-owned float64 array the deposits are added to (instead of a new
-        zeroed one), so that repeated or concurrent calls need no new allocation."""
+        zeroed one), so that repeated or concurrent calls need no new allocation.  ``flux``:
+        stats["e_flux"] per node, the weight of the packages leaving each refined node's subtree
+        (the energy flow from each grid to its parent, Sect. 3.3)."""
         L = lib()
         ns = len(sources)
         nl = self.n_lambda
@@ -233,6 +235,7 @@ class Model:
             rec = np.zeros(ns * nl * nrec, dtype=RECORD_DTYPE)
         e_lvl = np.zeros((self.n_levels + 1) * self.n_nodes) if level_arrays else None
         e_self = np.zeros(self.n_nodes) if self_absorption else None
+        e_flux = np.zeros(self.n_nodes) if flux else None
         e_emit_node = np.zeros(self.n_nodes) if self_absorption else None
         po, img = None, None
         if peel is not None:
@@ -250,11 +253,14 @@ class Model:
                         None if po is None else C.byref(po),
                         None if e_self is None else _p(e_self),
                         None if e_emit_node is None else _p(e_emit_node),
-                        None if e_lvl is None else _p(e_lvl), int(subtree))
+                        None if e_lvl is None else _p(e_lvl), int(subtree),
+                        None if e_flux is None else _p(e_flux))
         if rc != 0:
             raise OracleError(L.om_error().decode())
-        if img is not None or e_self is not None or e_lvl is not None:
+        if img is not None or e_self is not None or e_lvl is not None or e_flux is not None:
             out = st.as_dict()
+            if e_flux is not None:
+                out["e_flux"] = e_flux
             if img is not None:
                 out["peel_image"] = img
             if e_self is not None:
@@ -394,6 +400,118 @@ def subiterate(model, star_sources, seed, schedule, dust_packets, rr_threshold=0
         t = np.where(mask, t_new, t)
         hist.append(t.copy())
     return hist, a_stars, stats
+
+
+def canonical_parents(model):
+    """Canonical parent of every node (-1 for a root cell)."""
+    tree = model.tree
+    par = np.full(model.n_nodes, -1, dtype=np.int64)
+    for l, ref in enumerate(tree.refined):
+        lo = model.offsets[l + 1]
+        kids = np.arange(8 * len(ref), dtype=np.int64)
+        par[lo + kids] = model.offsets[l] + np.asarray(ref, dtype=np.int64)[kids // 8]
+    return par
+
+
+def subtree_select(imb, frac, parent, tagged, tag_root):
+    """The next subtree of the automatic iteration (Sect. 3.3): the lowest common ancestor of the
+    parents of every leaf whose imbalance is within ``frac`` of the largest, and of every tagged
+    grid (a refined node, which the subtree must hold); -1 for the whole model (no refined cell
+    holds them all, or the root grid is tagged)."""
+    mx = float(imb.max()) if len(imb) else 0.0
+    nodes = [int(parent[c]) for c in np.flatnonzero(imb >= frac * mx)] if mx > 0.0 else []
+    nodes += [int(g) for g in np.flatnonzero(tagged)]
+    if tag_root or not nodes:
+        return -1, mx
+
+    def chain(c):  # c and its ancestors, deepest first
+        out = []
+        while c >= 0:
+            out.append(c)
+            c = int(parent[c])
+        return out
+    common = None
+    for c in nodes:
+        if c < 0:
+            return -1, mx
+        ch = chain(c)
+        common = ch if common is None else [a for a in ch if a in set(common)]
+        if not common:
+            return -1, mx
+    return common[0], mx
+
+
+def subiterate_auto(model, star_sources, seed, n_steps, dust_packets, frac=0.5, stall=0.8,
+                    flux_frac=0.0, rr_threshold=0.0, rr_prob=0.0, t_min=2.0, t_max=3000.0):
+    """The automatic iteration of Sect. 3.3 over subiterations on complete subtrees (Sect. 3.1,
+    App. B), step by step from the oracle's own bookkeeping:
+      * per leaf, the energy imbalance |A - E(T_old)| / E(T_old) recorded at its last step, with
+        E the emission at the temperatures that step started from;
+      * the first step takes the whole model; each later one the subtree subtree_select picks
+        (leaves within ``frac`` of the largest imbalance, and the tagged grids);
+      * a repeat of the previous subtree without the largest imbalance dropping below ``stall``
+        times its previous value is the noise limit of that subtree: the whole model instead;
+      * flux_frac > 0: the energy flowing out of every refined node's subtree is measured in each
+        step; when a step below r changes the flow out of r's subtree by more than flux_frac
+        times the energy absorbed in its parent's subtree (since the parent last took part), the
+        parent grid is tagged until a step includes it.
+    Key iteration of step k is k.  Returns (temperatures after each step, the roots taken)."""
+    import gen
+    a_stars, _, _, _ = model.trace(star_sources, seed, iteration=0, rr_threshold=rr_threshold,
+                                   rr_prob=rr_prob)
+    t = model.solve_temperature(a_stars, t_min, t_max)
+    lv = model.level_of_nodes()
+    leaf = model.leaf_mask
+    parent = canonical_parents(model)
+    arrays = np.zeros((model.n_levels + 1, model.n_nodes))
+    imb = np.zeros(model.n_nodes)
+    flux_ref = np.zeros(model.n_nodes)
+    tagged = np.zeros(model.n_nodes, dtype=bool)
+    tag_root = False
+    hist, roots = [t.copy()], []
+    prev_root, prev_max = -2, 0.0
+    for k in range(n_steps):
+        root = -1
+        if k > 0:
+            root, mx = subtree_select(imb, frac, parent, tagged, tag_root)
+            if root >= 0 and root == prev_root and mx > stall * prev_max:
+                root = -1
+            prev_max = mx
+        lo = 0 if root < 0 else int(lv[root]) + 1
+        mask = model.subtree_mask(root)
+        src = [gen.Source(gen.SRC_DUST, 0, packets=dust_packets)]
+        _, _, st, _ = model.trace(src, seed, iteration=k + 1, rr_threshold=rr_threshold,
+                                  rr_prob=rr_prob, t_node=t, level_arrays=True, subtree=root,
+                                  flux=flux_frac > 0.0)
+        arrays[lo:, mask] = st["e_lvl"][lo:, mask]
+        a_tot = a_stars + arrays.sum(axis=0)
+        e_old = model.emission_all(t)
+        upd = mask & leaf
+        imb[upd] = np.where(e_old[upd] > 0.0, np.abs(a_tot[upd] - e_old[upd]) / np.where(e_old[upd] > 0.0,
+                                                                                        e_old[upd], 1.0), 0.0)
+        t_new = model.solve_temperature(a_tot, t_min, t_max)
+        t = np.where(mask, t_new, t)
+        if flux_frac > 0.0:
+            flow = st["e_flux"]
+            if root >= 0:
+                par = int(parent[root])
+                absorbed = float(a_tot[model.subtree_mask(par) & leaf].sum())
+                if abs(flow[root] - flux_ref[root]) > flux_frac * absorbed:
+                    if par < 0:
+                        tag_root = True
+                    else:
+                        tagged[par] = True
+            inner = mask & ~leaf
+            flux_ref[inner] = flow[inner]
+            tagged[inner] = False
+            if root >= 0:
+                tagged[root] = False
+            else:
+                tag_root = False
+        prev_root = root
+        roots.append(root)
+        hist.append(t.copy())
+    return hist, roots
 
 
 def lambda_iterate(model, star_sources, seed, n_max=30, tol=1e-3, n_fixed=None,

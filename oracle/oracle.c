@@ -404,6 +404,9 @@ typedef struct {
   int64_t sub_node;         /* refined cell whose subtree is iterated; -1: the whole model */
   int sub_lev;
   int64_t sub_I[3];
+  /* automatic iteration (Sect. 3.3): energy flowing out of each refined cell's subtree to its
+     parent level, per refined node; NULL when off */
+  double* e_flux;
 } tctx;
 
 /* Branch identifier of child c of branch b split at the package's crossing number n: the
@@ -641,6 +644,37 @@ static void peel_event(const tctx* c, const packet* p, double g) {
   }
 }
 
+/* Node of the cell at level lev with integer coordinates I (the cell must exist: an ancestor of
+   a leaf, or a leaf), found from the root along the coordinate bits. */
+static int64_t node_at(const om_model* m, int lev, const int64_t I[3]) {
+  const int64_t R[3] = {I[0] >> lev, I[1] >> lev, I[2] >> lev};
+  int64_t nd = root_index(m, R);
+  for (int l = 0; l < lev; ++l) {
+    int b = 0;
+    for (int c = 0; c < 3; ++c) b |= (int)((I[c] >> (lev - l - 1)) & 1) << c;
+    nd = m->off[l + 1] + 8 * m->child[nd] + b;
+  }
+  return nd;
+}
+
+/* A package of weight w crossed from the leaf (L_old, I_old) into the leaf (L_new, I_new), or
+   out of the model (escaped): it leaves the subtree of every refined ancestor of the old leaf
+   that does not hold the new one, and its weight flows from that grid to the grid's parent
+   (Sect. 3.3). */
+static void tally_exits(tctx* c, int L_old, const int64_t I_old[3], int escaped, int L_new,
+                        const int64_t I_new[3], double w) {
+  for (int l = 0; l < L_old; ++l) {
+    const int sh = L_old - l;
+    const int64_t A[3] = {I_old[0] >> sh, I_old[1] >> sh, I_old[2] >> sh};
+    int inside = 0;
+    if (!escaped && L_new > l) {
+      const int sn = L_new - l;
+      inside = (I_new[0] >> sn) == A[0] && (I_new[1] >> sn) == A[1] && (I_new[2] >> sn) == A[2];
+    }
+    if (!inside) c->e_flux[node_at(c->m, l, A)] += w;
+  }
+}
+
 /* Is the cell (lev, I) inside the subtree of the refined cell (sub_lev, sub_I)? */
 static int in_subtree(const tctx* c, int lev, const int64_t I[3]) {
   if (lev <= c->sub_lev) return 0;
@@ -723,10 +757,13 @@ static int propagate(tctx* c, packet* p) {
     p->P[ax] = face_ax;
     int sgn = p->d[ax] > 0.0 ? 1 : -1;
     const int old_lev = p->lev;
+    const int64_t old_I[3] = {p->I[0], p->I[1], p->I[2]};
     if (cross_face(m, ax, sgn, p->P, &p->node, &p->lev, p->I)) {
+      if (c->e_flux) tally_exits(c, old_lev, old_I, 1, 0, old_I, p->w);
       c->e_esc[c->lam] += p->w;
       return PK_ESCAPED;
     }
+    if (c->e_flux) tally_exits(c, old_lev, old_I, 0, p->lev, p->I, p->w);
     if (c->sub_node >= 0 && !in_subtree(c, p->lev, p->I)) {
       /* a subiteration follows packets only inside its subtree */
       c->e_esc[c->lam] += p->w;
@@ -842,7 +879,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
              double rr_prob, int64_t max_events, int32_t per_lambda, int64_t pid_begin,
              int64_t pid_end, int32_t lam_sel, double* e_abs, double* e_esc, om_stats* stats,
              int64_t rec_stride, om_record* rec, int32_t split_n, const om_peel_opts* peel,
-             double* e_self, double* e_emit_node, double* e_lvl, int64_t sub_node) {
+             double* e_self, double* e_emit_node, double* e_lvl, int64_t sub_node, double* e_flux) {
   if (m->nl < 1) { seterr("dust not set"); return -1; }
   if (split_n < 1 || split_n > 64) { seterr("split factor must be in [1, 64]"); return -1; }
   if (peel && (peel->n_dir < 1 || peel->n_dir > OM_MAXDIR || peel->npix < 1 || peel->tiles < 0 ||
@@ -891,6 +928,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
   c.e_emit_node = e_emit_node;
   c.dust = 0;
   c.e_lvl = e_lvl;
+  c.e_flux = e_flux;
   c.sub_node = sub_node;
   c.sub_lev = 0;
   c.sub_I[0] = c.sub_I[1] = c.sub_I[2] = 0;

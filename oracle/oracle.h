@@ -112,7 +112,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
              int64_t pid_begin, int64_t pid_end, int32_t lam_sel,
              double* e_abs, double* e_esc, om_stats* stats, int64_t rec_stride, om_record* rec,
              int32_t split_n, const om_peel_opts* peel, double* e_self, double* e_emit_node,
-             double* e_lvl, int64_t sub_node);
+             double* e_lvl, int64_t sub_node, double* e_flux);
 
 /* e_self, e_emit_node ([n_nodes], added to; NULL = off): for the accelerated Lambda iteration
  * (Sect. 3.1 Eq. 3, diagonal operator), the energy that dust-emission packets deposit in their
@@ -124,6 +124,10 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
  * level, lowered at every crossing into a shallower cell).  sub_node >= 0 (a refined node):
  * only the leaves of its subtree emit dust, and a package leaving the subtree is ended there
  * (tallied as escaped). */
+
+/* e_flux ([n_nodes], added to; NULL = off): for the automatic iteration (Sect. 3.3), the energy
+ * flowing from each grid to its parent: per refined node, the weight of the packages leaving its
+ * subtree (to a neighbour outside it, out of the model, or out of the iterated subtree). */
 
 /* Equilibrium temperature per leaf: 4 pi m sum_i kappa_abs_i B_i(T) dnu_i = A. */
 void om_solve_temperature(const om_model* m, const double* a_node, double t_min, double t_max,

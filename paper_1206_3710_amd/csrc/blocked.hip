@@ -71,7 +71,7 @@ __device__ __forceinline__ int32_t region_walk(const BlkParams& b, const Dims& D
 // LDS when jobs_lds.
 __device__ __forceinline__ void emit_one(const BlkParams& b, uint64_t gid, uint64_t g0,
                                          const uint64_t* s_start, bool jobs_lds, double& e_emit,
-                                         unsigned long long& npk) {
+                                         unsigned long long& npk, uint32_t k0, uint32_t k1) {
   const TraceParams& p = b.t;
   int lo = 0, hi = p.n_jobs - 1;
   while (lo < hi) {
@@ -81,11 +81,18 @@ __device__ __forceinline__ void emit_one(const BlkParams& b, uint64_t gid, uint6
     else hi = mid - 1;
   }
   const JobDev& J = p.jobs[lo];
+  const uint64_t idx = gid - g0;
+  if (J.kind == RT_SRC_DUST && J.qtot == 0) {
+    // a wavelength at which no cell emits (its table total is only known on the device in a
+    // captured iteration step): no packet, and the record is skipped by the sort
+    b.u_key[idx] = kInvalidKey;
+    return;
+  }
   const ModelDev& md = p.models[J.model];
   const Dims D = dims_of(md);
   const uint32_t pid = (uint32_t)(gid - J.start);
   Pk64 k;
-  emit64(p, J, D, md.n_leaves, md.leaf_base, pid, k, ChildWord{p.word});
+  emit64(p, J, D, md.n_leaves, md.leaf_base, pid, k, ChildWord{p.word}, k0, k1);
   PRec r;
   const double sc = ldexp(1.0, k.lev);
 #pragma unroll
@@ -116,7 +123,6 @@ __device__ __forceinline__ void emit_one(const BlkParams& b, uint64_t gid, uint6
   ++npk;
   if (p.emit_acc && J.kind == RT_SRC_DUST)
     unsafeAtomicAdd(p.emit_acc + md.canon_base + canon_of(md, k.node), k.w0);
-  const uint64_t idx = gid - g0;
   b.u_out[idx] = r;
   b.u_key[idx] = key;
 }
@@ -200,7 +206,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
                                          double* s_esc, double* s_misc, bool esc_lds, int lane,
                                          unsigned long long& c_cross, uint32_t& c_scat, uint32_t& c_kill,
                                          uint32_t& c_trunc, uint32_t& c_split, uint32_t& c_skill,
-                                         uint32_t& c_sskip, uint64_t& ch_base, uint32_t& ch_used) {
+                                         uint32_t& c_sskip, uint64_t& ch_base, uint32_t& ch_used,
+                                         const uint32_t k0, const uint32_t k1) {
   const TraceParams& p = b.t;
   const float rr_thr = (float)p.rr_thr, rr_p = (float)p.rr_p;
   const float rr_gain = rr_p > 0.0f ? 1.0f / (1.0f - rr_p) : 1.0f;
@@ -404,6 +411,13 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           const bool sub_out = LVL && p.sub_lev >= 0 &&
                                !in_subtree(p.sub_lev, p.sub_I, L, ax == 0 ? Ja : I0, ax == 1 ? Ja : I1,
                                            ax == 2 ? Ja : I2);
+          // automatic iteration: the weight leaving each refined ancestor's subtree (only when the
+          // crossing leaves the leaf's oct), walked up the tree's global parent links
+          if (LVL && p.flux_acc && (Ja >> 1) != (Ia >> 1) && L > 0) {
+            const int32_t c = b.rcanon[R.gbase + node];
+            const int32_t inode = md.base + (c < md.n_root ? c : c + (md.n_root_pad - md.n_root));
+            flux_exits(md, p.up, p.flux_acc, inode, L, Ia, Ja, Ja < 0 || Ja >= (D.na(ax) << L), (double)w);
+          }
           if (Ja < 0 || Ja >= (D.na(ax) << L) || sub_out) {
             // escape through the root boundary (or out of the subtree)
             // a region belongs to one model: its escapes are tallied per wavelength in LDS
@@ -542,7 +556,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
       const uint32_t N = (uint32_t)p.split_n;
       if (state == B_ROUL) {
         // survives with probability 1/N: (2 m + 1) 2^-24 < 1/N  <=>  (2 m + 1) N < 2^24
-        const uint4 xr = philox(pid, stream, ncross, (br << 2) | 3u, p.key0, p.key1);
+        const uint4 xr = philox(pid, stream, ncross, (br << 2) | 3u, k0, k1);
         if ((2u * (xr.x >> 9) + 1u) * (uint64_t)N < (1ull << 24)) {
           const float nw = w * (float)N;
           atomicAdd(&s_misc[4], (double)nw - (double)w);
@@ -611,7 +625,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
             rc.ncross = 0;
             for (uint32_t c = 1; c < N; ++c, ++idx) {
               const uint32_t bc = branch_id(br, ncross, c);
-              const uint4 xr = philox(pid, stream, ncross, (bc << 2) | 2u, p.key0, p.key1);
+              const uint4 xr = philox(pid, stream, ncross, (bc << 2) | 2u, k0, k1);
               rc.tau = -logf(unif32(xr.x));
               rc.birth = (int32_t)bc;
               b.u_out[idx] = rc;
@@ -679,7 +693,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
             p.peel_ev[idx] = e;
           }
         }
-        const uint4 xr = philox(pid, stream, ev, br << 2, p.key0, p.key1);
+        const uint4 xr = philox(pid, stream, ev, br << 2, k0, k1);
         bool killed = false;
         if (rr_p > 0.0f && w < rr_thr * w0) {
           if (unif32(xr.x) < rr_p) {
@@ -735,6 +749,10 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
   uint32_t c_scat = 0, c_kill = 0, c_trunc = 0, c_split = 0, c_skill = 0, c_sskip = 0;
   uint64_t ch_base = 0;          // this wave's chunk of next-queue records (none yet: full)
   uint32_t ch_used = kExitChunk;
+  // Philox key: from the parameters, or from device memory in a captured iteration step (whose
+  // key changes from step to step)
+  const uint32_t k0 = p.keys ? p.keys[0] : p.key0;
+  const uint32_t k1 = p.keys ? p.keys[1] : p.key1;
 
   for (;;) {
     __syncthreads();
@@ -760,10 +778,10 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     __syncthreads();
     if (R.n <= cap)
       run_item<true, SPLIT, PEEL, ALI, LVL>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
-                     c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip, ch_base, ch_used);
+                     c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip, ch_base, ch_used, k0, k1);
     else
       run_item<false, SPLIT, PEEL, ALI, LVL>(b, it, R, md, D, nloc, nup, s_word, s_acc, s_up, &s_next, s_esc, s_misc, esc_lds, lane,
-                      c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip, ch_base, ch_used);
+                      c_cross, c_scat, c_kill, c_trunc, c_split, c_skill, c_sskip, ch_base, ch_used, k0, k1);
     __syncthreads();
     {
       double* __restrict__ gacc64 = b.accb64 + (int64_t)it.slot * b.accb_stride + R.gbase;
@@ -794,7 +812,7 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
         __syncthreads();
         const uint64_t base = g0 + (uint64_t)(uint32_t)s_item * BS;
         if (base >= g1) break;
-        if (base + (uint64_t)tid < g1) emit_one(b, base + (uint64_t)tid, g0, s_start, jobs_lds, e_emit, npk);
+        if (base + (uint64_t)tid < g1) emit_one(b, base + (uint64_t)tid, g0, s_start, jobs_lds, e_emit, npk, k0, k1);
       }
       e_emit = wave_sum(e_emit);
       npk = wave_sum_u64(npk);

@@ -168,6 +168,25 @@ __device__ __forceinline__ bool cross_walk(Dims D, const int32_t* __restrict__ u
   return true;
 }
 
+// Energy flow from grids to their parents (Sect. 3.3): a package of weight w crossing from the
+// leaf `node` (internal id, level L) across axis a, from level-L coordinate Ia to Ja (escaped:
+// out of the model), leaves the subtree of every refined ancestor of the old leaf whose level-l
+// coordinate on that axis differs from the neighbour's (the other axes are shared); those are
+// the ancestors from level L - 1 up to the first that holds the neighbour.  w is added to each
+// one's outflow, per canonical node.
+__device__ __forceinline__ void flux_exits(const ModelDev& md, const int32_t* __restrict__ up,
+                                           double* __restrict__ flux, int32_t node, int L, int32_t Ia,
+                                           int32_t Ja, bool escaped, double w) {
+  int32_t cur = node;
+  for (int l = L - 1; l >= 0; --l) {
+    const int sh = L - l;
+    if (!escaped && (Ja >> sh) == (Ia >> sh)) break;
+    cur = up[cur >> 3];
+    const int32_t c = cur - md.base;
+    unsafeAtomicAdd(flux + md.canon_base + (c < md.n_root ? c : c - (md.n_root_pad - md.n_root)), w);
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Emission (FP64 in both forms)
 // ------------------------------------------------------------------------------------------
@@ -207,9 +226,9 @@ __device__ __forceinline__ int64_t cdf_pick(const uint64_t* __restrict__ qpre, i
 // emission with cells picked in proportion to their emission, equal-energy packets).
 template <class CH>
 __device__ void emit64(const TraceParams& p, const JobDev& job, Dims D, int64_t n_leaves,
-                       int64_t leaf_base, uint32_t j, Pk64& k, CH ch) {
-  const uint4 b0 = philox(j, job.stream, 0u, 0u, p.key0, p.key1);
-  const uint4 b1 = philox(j, job.stream, 0u, 1u, p.key0, p.key1);
+                       int64_t leaf_base, uint32_t j, Pk64& k, CH ch, uint32_t key0, uint32_t key1) {
+  const uint4 b0 = philox(j, job.stream, 0u, 0u, key0, key1);
+  const uint4 b1 = philox(j, job.stream, 0u, 1u, key0, key1);
   if (job.kind == RT_SRC_BACKGROUND) {
     const double n0 = (double)D.n0, n1 = (double)D.n1, n2 = (double)D.n2;
     const double area = 2.0 * (n0 * n1 + n1 * n2 + n0 * n2);

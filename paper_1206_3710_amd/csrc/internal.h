@@ -98,6 +98,8 @@ struct TraceParams {
   rt_record* rec;
   int64_t rec_stride;
   uint32_t key0, key1;
+  const uint32_t* keys;      // region pass: the Philox key from device memory when set (a
+                             // captured iteration step advances it on the device)
   double rr_thr, rr_p;
   int64_t max_events;
   float refill_thr;
@@ -120,6 +122,9 @@ struct TraceParams {
   int64_t lvl_stride;
   int32_t sub_lev;
   int32_t sub_I[3];
+  // automatic iteration (Sect. 3.3): per canonical node, the weight of the packages leaving each
+  // refined cell's subtree (the energy flow from a grid to its parent); null when off
+  double* flux_acc;
   // peel-off: scattering events of the current batch (null when off)
   PeelEv* peel_ev;
   unsigned long long* peel_count;
@@ -316,6 +321,9 @@ hipError_t launch_subiter_update(const ModelDev* models, int model, int64_t n_le
                                  const double* t_old, double* a_tot, double* imb, hipStream_t s);
 hipError_t launch_dust_quant(int64_t n_leaves, const double* lum,
                              const unsigned long long* lmax_bits, uint64_t* q, hipStream_t s);
+// Wavelengths per pass of the map kernel (registers per ray): FP64 and FP32 transfer.
+constexpr int kRenderPassF64 = 16;
+constexpr int kRenderPassF32 = 32;
 hipError_t launch_render(bool f32, const ModelDev* models, int model, const int32_t* child,
                          const int32_t* up, const double* rho64, const double* t_node,
                          const LamConst* lc, const int32_t* lam_idx, int n_sel,
@@ -332,3 +340,14 @@ hipError_t launch_render_noalloc(bool f32, const ModelDev* models, int model, co
                                  const LamConst* lc, const int32_t* lam_idx_host, int n_sel,
                                  const double* view_host, int npix, double* image, void* scr,
                                  unsigned long long* crossings_host, hipStream_t s);
+
+// A captured iteration step (Lambda iteration in the region schedule): device-only pieces.
+hipError_t launch_dust_scan(int64_t n, const uint64_t* q, uint64_t* qpre, uint64_t* tile_tmp, uint64_t* total_out,
+                            hipStream_t s);
+int64_t dust_scan_tiles(int64_t n);
+hipError_t launch_fill_u64(void* a, int64_t n_words, unsigned long long v, hipStream_t s);
+hipError_t launch_copy_u64(const void* a, void* b, int64_t n_words, hipStream_t s);
+hipError_t launch_step_key(uint32_t* keys, hipStream_t s);
+hipError_t launch_step_report(const double* crit, const SweepState* st, const DevStats* stats, double* out,
+                              hipStream_t s);
+hipError_t launch_sweep_init(SweepState* st, uint64_t total, uint64_t cap_all, hipStream_t s);

@@ -169,3 +169,63 @@ hipError_t launch_philox(uint32_t k0, uint32_t k1, int64_t n, const uint32_t* ct
   hipLaunchKernelGGL(philox_kernel, dim3((unsigned)grid), dim3(256), 0, s, k0, k1, n, ctr, out);
   return hipGetLastError();
 }
+
+// ---- small kernels of a captured iteration step (no memset or host copy inside a graph) ----
+namespace {
+
+__global__ void fill_u64_kernel(unsigned long long* __restrict__ a, int64_t n, unsigned long long v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+__global__ void copy_u64_kernel(const unsigned long long* __restrict__ a, unsigned long long* __restrict__ b,
+                                int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+// The step's Philox key: the second word advances by one per step (key iteration n + 1).
+__global__ void step_key_kernel(uint32_t* keys) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) keys[1] += 1u;
+}
+
+// What the host reads after a step: the stopping statistic (numerator, denominator), whether
+// the sweeps drained, the step's crossings and its misplaced queue records (an invariant).
+__global__ void step_report_kernel(const double* __restrict__ crit, const SweepState* __restrict__ st,
+                                   const DevStats* __restrict__ stats, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  out[0] = crit[0];
+  out[1] = crit[1];
+  out[2] = st->done ? 1.0 : 0.0;
+  out[3] = (double)stats->crossings;
+  out[4] = (double)stats->misplaced;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u64(void* a, int64_t n_words, unsigned long long v, hipStream_t s) {
+  if (n_words <= 0) return hipSuccess;
+  const int64_t g = (n_words + 255) / 256;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, s,
+                     static_cast<unsigned long long*>(a), n_words, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_u64(const void* a, void* b, int64_t n_words, hipStream_t s) {
+  if (n_words <= 0) return hipSuccess;
+  const int64_t g = (n_words + 255) / 256;
+  hipLaunchKernelGGL(copy_u64_kernel, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, s,
+                     static_cast<const unsigned long long*>(a), static_cast<unsigned long long*>(b), n_words);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_key(uint32_t* keys, hipStream_t s) {
+  hipLaunchKernelGGL(step_key_kernel, dim3(1), dim3(64), 0, s, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_report(const double* crit, const SweepState* st, const DevStats* stats, double* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(step_report_kernel, dim3(1), dim3(64), 0, s, crit, st, stats, out);
+  return hipGetLastError();
+}

@@ -1,6 +1,7 @@
 // Surface-brightness maps through the tree (paper Sect. 4.1): one ray per pixel, orthographic
 // view, I <- I exp(-dtau) + (1 - a) B(T) (1 - exp(-dtau)) cell by cell.  Up to NS wavelengths
-// are carried in registers per pass; the host splits longer selections into passes.
+// are carried in registers per pass (16 in FP64, 32 in FP32); the host splits longer selections
+// into passes, each of which walks the ray again.
 // Built with -ffp-contract=off like the FP64 trace.
 //
 // Two forms share the ray geometry (FP64, so both visit the same cells): the FP64 form
@@ -16,6 +17,19 @@ namespace {
 
 constexpr double kK = 1.380649e-16;
 
+// e^x - 1 for x >= 0 in FP32: below 1/8 the series to x^5 (truncation below x^5 / 6! =
+// 4.2e-8 relative), above it the hardware base-2 exponential (inf for large x).
+__device__ __forceinline__ float expm1_pos(float x) {
+  float p = 8.33333333e-3f;         // 1/5!
+  p = fmaf(p, x, 4.16666667e-2f);   // 1/4!
+  p = fmaf(p, x, 1.66666667e-1f);   // 1/3!
+  p = fmaf(p, x, 0.5f);             // 1/2!
+  p = fmaf(p, x, 1.0f);
+  const float small = p * x;
+  const float large = __builtin_amdgcn_exp2f(x * 1.44269504f) - 1.0f;
+  return x < 0.125f ? small : large;
+}
+
 template <int NS, bool F32>
 __global__ __launch_bounds__(256) void render_kernel(
     const ModelDev* __restrict__ models, int model, const int32_t* __restrict__ child,
@@ -26,15 +40,14 @@ __global__ __launch_bounds__(256) void render_kernel(
   const ModelDev& m = models[model];
   const Dims D = dims_of(m);
   const ChildPlain ch{child};
-  // FP32 form: per-wavelength constants kappa_ext * cell size, 1 - albedo, 2 h nu^3 / c^2,
+  // FP32 form: per-wavelength constants kappa_ext * cell size, (1 - albedo) 2 h nu^3 / c^2,
   // h nu / k
-  __shared__ float s_kc[NS], s_a1[NS], s_pre[NS], s_hk[NS];
+  __shared__ float s_kc[NS], s_ap[NS], s_hk[NS];
   if (F32) {
     if (threadIdx.x < NS && (int)threadIdx.x < n_sel) {
       const LamConst& L = lc[lam_idx[threadIdx.x]];
       s_kc[threadIdx.x] = (float)(L.kext * m.cell_cm);
-      s_a1[threadIdx.x] = (float)(1.0 - L.alb);
-      s_pre[threadIdx.x] = (float)L.pre;
+      s_ap[threadIdx.x] = (float)((1.0 - L.alb) * L.pre);
       s_hk[threadIdx.x] = (float)(L.hnu / kK);
     }
     __syncthreads();
@@ -108,17 +121,25 @@ __global__ __launch_bounds__(256) void render_kernel(
         }
         const double s = texit;
         if (F32 && rho > 0.0 && s > 0.0) {
+          // per wavelength: the segment's transmission e^-dtau, its emission weight 1 - e^-dtau
+          // (series below 1/8, else from the transmission), and the source (1 - a) B(T)
           const float tc = (float)t_node[canon_of(m, node)];
           const float f = (float)(rho * s);
-          const float inv_t = tc > 0.0f ? 1.0f / tc : 0.0f;
+          const bool warm = tc > 0.0f;
+          const float inv_t = warm ? __builtin_amdgcn_rcpf(tc) : 0.0f;
 #pragma unroll
           for (int q = 0; q < NS; ++q) {
             if (q < n_sel) {
               const float dtau = s_kc[q] * f;
               const float att = __builtin_amdgcn_exp2f(dtau * -1.44269504f);
-              const float em = one_minus_exp(dtau);
-              const float b = tc > 0.0f ? s_pre[q] / expm1f(s_hk[q] * inv_t) : 0.0f;
-              I32[q] = fmaf(I32[q], att, s_a1[q] * b * em);
+              float em = 8.33333333e-3f;
+              em = fmaf(em, dtau, -4.16666667e-2f);
+              em = fmaf(em, dtau, 1.66666667e-1f);
+              em = fmaf(em, dtau, -0.5f);
+              em = fmaf(em, dtau, 1.0f);
+              em = dtau < 0.125f ? em * dtau : 1.0f - att;
+              const float src = warm ? s_ap[q] * __builtin_amdgcn_rcpf(expm1_pos(s_hk[q] * inv_t)) : 0.0f;
+              I32[q] = fmaf(I32[q], att, src * em);
             }
           }
         } else if (!F32 && rho > 0.0 && s > 0.0) {
@@ -188,11 +209,12 @@ hipError_t launch_render(bool f32, const ModelDev* models, int model, const int3
 #define RT_RENDER(NS, F)                                                                        \
   hipLaunchKernelGGL((render_kernel<NS, F>), grid, block, 0, s, models, model, child, up, rho64, \
                      t_node, lc, lam_idx, n_sel, view, npix, image, crossings)
-  if (n_sel > 16) return hipErrorInvalidValue;
+  if (n_sel > (f32 ? kRenderPassF32 : kRenderPassF64)) return hipErrorInvalidValue;
   if (f32) {
     if (n_sel <= 4) RT_RENDER(4, true);
     else if (n_sel <= 8) RT_RENDER(8, true);
-    else RT_RENDER(16, true);
+    else if (n_sel <= 16) RT_RENDER(16, true);
+    else RT_RENDER(32, true);
   } else {
     if (n_sel <= 4) RT_RENDER(4, false);
     else if (n_sel <= 8) RT_RENDER(8, false);
@@ -273,8 +295,9 @@ hipError_t launch_render_noalloc(bool f32, const ModelDev* models, int model, co
   const double* v = reinterpret_cast<const double*>(base + kScrView);
   const int32_t* li = reinterpret_cast<const int32_t*>(base + kScrLam);
   unsigned long long* cnt = reinterpret_cast<unsigned long long*>(base + kScrCount);
-  for (int q0 = 0; q0 < n_sel; q0 += 16) {
-    const int nq = n_sel - q0 < 16 ? n_sel - q0 : 16;
+  const int pass = f32 ? kRenderPassF32 : kRenderPassF64;
+  for (int q0 = 0; q0 < n_sel; q0 += pass) {
+    const int nq = n_sel - q0 < pass ? n_sel - q0 : pass;
     e = launch_render(f32, models, model, child, up, rho64, t_node, lc, li + q0, nq, v, npix,
                       image + (size_t)q0 * npix * npix, q0 == 0 ? cnt : nullptr, s);
     if (e != hipSuccess) return e;

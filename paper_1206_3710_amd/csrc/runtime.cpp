@@ -65,6 +65,26 @@ struct HostModel {
   DevBuf sub_astars, sub_arrays, sub_imb;
   double sub_tmin = 0.0, sub_tmax = 0.0;
   bool sub_ready = false;
+  // automatic iteration (Sect. 3.3): canonical parent of each node (-1: a root cell), the outflow
+  // of each refined node's subtree as last measured with its parent grid in the step, and the
+  // grids tagged for the next step because the flow from a child changed (tag_root: the root
+  // grid, i.e. the whole model)
+  double sub_flux_frac = 0.0;
+  std::vector<int64_t> sub_parent;
+  std::vector<double> sub_flux_ref;
+  std::vector<char> sub_tag;
+  bool sub_tag_root = false;
+};
+
+// Launch configuration of one trace in the region schedule: what its sweeps need.
+constexpr int kSweepBlock = 16;  // sweeps enqueued (or captured) as one unit; even, so that
+                                 // queue buffer 0 is always the input of the first
+struct RegionLaunch {
+  BlkParams b;
+  SweepState* st = nullptr;
+  int64_t batch = 0, capq = 0, cap_all = 0, n_keys = 0;
+  int n_regions = 0, chunk = 0, grid_sort = 0, grid_pass = 0, grid_peel = 0, bs = 0, reg_lds = 0;
+  const PeelParams* peel = nullptr;
 };
 
 }  // namespace
@@ -111,6 +131,11 @@ struct rt_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
   hipEvent_t ev_c = nullptr;
   hipStream_t work = nullptr;  // the sweeps of the region schedule (capturable: never the null stream)
+  DevBuf g_jobs, g_keys, g_scan, g_report;  // captured iteration step: job table, Philox key,
+                                            // scan scratch, what the host reads per step
+  uint32_t g_keys_host[2] = {0, 0};
+  int64_t last_sweep_blocks = 0;  // blocks of kSweepBlock sweeps the last region trace needed
+  RegionLaunch rl_saved;          // its launch configuration (when the caller asked to keep it)
 };
 
 namespace {
@@ -532,7 +557,8 @@ rt_status rt_destroy(rt_ctx* ctx) {
                     &ctx->q_key[0], &ctx->q_key[1], &ctx->q_perm, &ctx->q_hist, &ctx->q_kfill,
                     &ctx->q_items, &ctx->q_state, &ctx->last_node, &ctx->t_tab, &ctx->it_self,
                     &ctx->it_emit, &ctx->peel_ev, &ctx->peel_ctr, &ctx->peel_tab, &ctx->peel_roottab,
-                    &ctx->peel_tabroot, &ctx->peel_dnu, &ctx->peel_img};
+                    &ctx->peel_tabroot, &ctx->peel_dnu, &ctx->peel_img, &ctx->g_jobs, &ctx->g_keys,
+                    &ctx->g_scan, &ctx->g_report};
   for (DevBuf* b : bufs) b->release();
   for (HostModel& m : ctx->models) {
     m.d_lc.release();
@@ -853,7 +879,102 @@ struct TraceOut {
   int64_t lvl_stride = 0;
   int32_t sub_lev = -1;              // subtree root (level, coordinates); -1 = whole model
   int32_t sub_I[3] = {0, 0, 0};
+  double* flux_acc = nullptr;        // automatic iteration: outflow of each refined node's subtree
+  bool save_launch = false;          // keep the region schedule's launch configuration in the ctx
 };
+
+// Queue buffers, sort scratch and the pass kernel's parameters of one region-schedule trace.
+rt_status region_launch_setup(rt_ctx* ctx, const rt_trace_opts* o, const TraceParams& p, const TraceOut& out,
+                              uint64_t start, int bs, int reg_per_cu, int reg_lds, int key_slots, int n_lvl,
+                              RegionLaunch* L) {
+  const int n_regions = (int)ctx->h_regions.size();
+  const int64_t n_keys = (int64_t)key_slots * n_regions;
+  if (n_keys > (int64_t(1) << 28)) return fail(ctx, RT_EINVAL, "too many (wavelength, region) keys");
+  const int64_t capq = std::min<int64_t>(int64_t(1) << 25, std::max<int64_t>((int64_t)start, 4096));
+  const int64_t batch = std::min<int64_t>(o->batch_packets > 0 ? o->batch_packets : int64_t(1) << 23, capq);
+  const int32_t chunk = o->chunk_packets > 0 ? o->chunk_packets : 16 * bs;
+  // records per queue buffer: emission keeps each sweep's input + births within capq; with
+  // package splitting a second capq holds the packages split off during a sweep
+  const int64_t cap_all = p.split_n > 1 ? 2 * capq : capq;
+  // plus the unused ends of the pass waves' last chunks of records (at most one chunk each)
+  const int64_t cap_rec = cap_all + (int64_t)ctx->n_cu * reg_per_cu * (bs / 64) * (int64_t)kExitChunk;
+  if (ctx->q_capacity < cap_rec) {
+    for (int k = 0; k < 2; ++k) {
+      HIPCHK(ctx->q_rec[k].ensure(sizeof(PRec) * cap_rec));
+      HIPCHK(ctx->q_key[k].ensure(4 * cap_rec));
+    }
+    HIPCHK(ctx->q_perm.ensure(4 * cap_rec));
+    ctx->q_capacity = cap_rec;
+  }
+  HIPCHK(ctx->q_hist.ensure(4 * n_keys));
+  HIPCHK(ctx->q_kfill.ensure(4 * n_keys));
+  HIPCHK(ctx->q_items.ensure(sizeof(WorkItem) * (cap_all / chunk + n_keys + 1)));
+  HIPCHK(ctx->q_state.ensure(sizeof(SweepState)));
+  SweepState* st = ctx->q_state.as<SweepState>();
+  BlkParams& b = L->b;
+  std::memset(&b, 0, sizeof b);
+  b.t = p;
+  b.regions = ctx->d_regions.as<RegionDev>();
+  b.n_regions = n_regions;
+  b.cap = ctx->reg_cap;
+  b.rword = ctx->d_rword.as<int32_t>();
+  b.rup = ctx->d_rup.as<int32_t>();
+  b.rcanon = ctx->d_rcanon.as<int32_t>();
+  b.root_region = ctx->d_root_region.as<int32_t>();
+  b.split_tab = ctx->d_split.as<int32_t>();
+  b.accb64 = ctx->acc.as<double>();
+  b.accb_stride = ctx->reg_G;
+  b.lvl_slots = n_lvl;
+  b.q_perm = ctx->q_perm.as<uint32_t>();
+  b.items = ctx->q_items.as<WorkItem>();
+  b.n_items = &st->n_items;
+  b.item_counter = &st->item_counter;
+  b.sweep = st;
+  b.emit_counter = &st->emit_counter;
+  b.split_room = &st->split_room;
+  b.split_used = &st->split_used;
+  b.n_slots_key = key_slots;
+  b.chunk = chunk;
+  b.tail_park = o->tail_park < 0 ? INT32_MAX : (o->tail_park > 0 ? o->tail_park : 16);
+  L->st = st;
+  L->batch = batch;
+  L->capq = capq;
+  L->cap_all = cap_all;
+  L->n_keys = n_keys;
+  L->n_regions = n_regions;
+  L->chunk = chunk;
+  L->grid_pass = ctx->n_cu * reg_per_cu;
+  L->grid_sort = ctx->n_cu * 4;
+  L->grid_peel = ctx->n_cu * 8;
+  L->bs = bs;
+  L->reg_lds = reg_lds;
+  L->peel = out.peel;
+  return RT_OK;
+}
+
+// kSweepBlock sweeps of a region-schedule trace on stream s; with ev, the pass of sweep k is
+// bracketed by events 2k and 2k + 1 (not while capturing a graph).
+hipError_t enqueue_sweeps(rt_ctx* ctx, const RegionLaunch& L, hipStream_t s, const std::vector<hipEvent_t>* ev) {
+  for (int k = 0; k < kSweepBlock; ++k) {
+    const int in = k & 1, out = 1 - in;
+    hipError_t e = launch_sweep_sort(L.st, in, k, (uint64_t)L.batch, (uint64_t)L.capq, ctx->q_key[in].as<uint32_t>(),
+                                     (int)L.n_keys, L.n_regions, L.chunk, ctx->q_hist.as<uint32_t>(),
+                                     ctx->q_kfill.as<uint32_t>(), ctx->q_perm.as<uint32_t>(),
+                                     ctx->q_items.as<WorkItem>(), L.grid_sort, s);
+    if (e != hipSuccess) return e;
+    BlkParams bk = L.b;
+    bk.q_in = ctx->q_rec[in].as<PRec>();
+    bk.u_out = ctx->q_rec[out].as<PRec>();
+    bk.u_key = ctx->q_key[out].as<uint32_t>();
+    bk.u_count = &L.st->count[out];
+    // the pass kernel's blocks also write this sweep's births, once its work items are taken
+    if (ev && (e = hipEventRecord((*ev)[2 * k], s)) != hipSuccess) return e;
+    if ((e = launch_blk_pass(bk, L.grid_pass, L.bs, L.reg_lds, s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord((*ev)[2 * k + 1], s)) != hipSuccess) return e;
+    if (L.peel && (e = launch_peel(bk.t, *L.peel, L.grid_peel, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_trace_opts* o,
                      const TraceOut& out, rt_trace_stats* st_out) {
@@ -1050,6 +1171,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   p.lvl_stride = out.lvl_stride;
   p.sub_lev = out.sub_lev;
   for (int a = 0; a < 3; ++a) p.sub_I[a] = out.sub_I[a];
+  p.flux_acc = out.flux_acc;
   if ((out.lvl_acc || out.sub_lev >= 0) && fp32) {
     if (o->schedule != RT_SCHED_REGIONS)
       return fail(ctx, RT_EINVAL, "subiterations run in the RT_FP64 form or the region schedule");
@@ -1090,69 +1212,19 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   uint64_t main_launches = 0;
   HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
   if (start > 0 && regions) {
-    const int n_regions = (int)ctx->h_regions.size();
-    const int64_t n_keys = (int64_t)key_slots * n_regions;
-    if (n_keys > (int64_t(1) << 28)) return fail(ctx, RT_EINVAL, "too many (wavelength, region) keys");
-    const int64_t capq = std::min<int64_t>(int64_t(1) << 25, std::max<int64_t>((int64_t)start, 4096));
-    const int64_t batch = std::min<int64_t>(o->batch_packets > 0 ? o->batch_packets : int64_t(1) << 23, capq);
-    const int32_t chunk = o->chunk_packets > 0 ? o->chunk_packets : 16 * bs;
-    // records per queue buffer: emission keeps each sweep's input + births within capq; with
-    // package splitting a second capq holds the packages split off during a sweep
-    const int64_t cap_all = p.split_n > 1 ? 2 * capq : capq;
-    // plus the unused ends of the pass waves' last chunks of records (at most one chunk each)
-    const int64_t cap_rec = cap_all + (int64_t)ctx->n_cu * reg_per_cu * (bs / 64) * (int64_t)kExitChunk;
-    if (ctx->q_capacity < cap_rec) {
-      for (int k = 0; k < 2; ++k) {
-        HIPCHK(ctx->q_rec[k].ensure(sizeof(PRec) * cap_rec));
-        HIPCHK(ctx->q_key[k].ensure(4 * cap_rec));
-      }
-      HIPCHK(ctx->q_perm.ensure(4 * cap_rec));
-      ctx->q_capacity = cap_rec;
-    }
-    HIPCHK(ctx->q_hist.ensure(4 * n_keys));
-    HIPCHK(ctx->q_kfill.ensure(4 * n_keys));
-    HIPCHK(ctx->q_items.ensure(sizeof(WorkItem) * (cap_all / chunk + n_keys + 1)));
-    HIPCHK(ctx->q_state.ensure(sizeof(SweepState)));
-    SweepState* st = ctx->q_state.as<SweepState>();
+    RegionLaunch L;
+    if (rt_status e = region_launch_setup(ctx, o, p, out, start, bs, reg_per_cu, reg_lds, key_slots, n_lvl, &L))
+      return e;
+    SweepState* st = L.st;
     SweepState init;  // stays alive until the first synchronisation below
     {
       std::memset(&init, 0, sizeof init);
       init.total = start;
-      init.cap_all = (unsigned long long)cap_all;
+      init.cap_all = (unsigned long long)L.cap_all;
       HIPCHK(hipEventRecord(ctx->ev_c, ctx->stream));
       HIPCHK(hipStreamWaitEvent(ctx->work, ctx->ev_c, 0));
       HIPCHK(hipMemcpyAsync(st, &init, sizeof init, hipMemcpyHostToDevice, ctx->work));
     }
-    BlkParams b;
-    std::memset(&b, 0, sizeof b);
-    b.t = p;
-    b.regions = ctx->d_regions.as<RegionDev>();
-    b.n_regions = n_regions;
-    b.cap = ctx->reg_cap;
-    b.rword = ctx->d_rword.as<int32_t>();
-    b.rup = ctx->d_rup.as<int32_t>();
-    b.rcanon = ctx->d_rcanon.as<int32_t>();
-    b.root_region = ctx->d_root_region.as<int32_t>();
-    b.split_tab = ctx->d_split.as<int32_t>();
-    b.accb64 = ctx->acc.as<double>();
-    b.accb_stride = ctx->reg_G;
-    b.lvl_slots = n_lvl;
-    b.q_perm = ctx->q_perm.as<uint32_t>();
-    b.items = ctx->q_items.as<WorkItem>();
-    b.n_items = &st->n_items;
-    b.item_counter = &st->item_counter;
-    b.sweep = st;
-    b.emit_counter = &st->emit_counter;
-    b.split_room = &st->split_room;
-    b.split_used = &st->split_used;
-    b.n_slots_key = key_slots;
-    b.chunk = chunk;
-    b.tail_park = o->tail_park < 0 ? INT32_MAX : (o->tail_park > 0 ? o->tail_park : 16);
-    const int grid_pass = ctx->n_cu * reg_per_cu;
-    const int grid_sort = ctx->n_cu * 4;
-    // kSweepBlock sweeps (an even number: buffer 0 is always the input of the first) are
-    // enqueued as one unit; the pass of sweep k is bracketed by events 2k, 2k+1
-    constexpr int kSweepBlock = 16;
     if ((int)ctx->sweep_ev.size() < 2 * kSweepBlock) {
       while ((int)ctx->sweep_ev.size() < 2 * kSweepBlock) {
         hipEvent_t e;
@@ -1160,36 +1232,14 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
         ctx->sweep_ev.push_back(e);
       }
     }
-    const PeelParams* peelp = out.peel;
-    auto enqueue_block = [&](bool capturing) -> hipError_t {
-      for (int k = 0; k < kSweepBlock; ++k) {
-        const int in = k & 1, out = 1 - in;
-        hipError_t e = launch_sweep_sort(st, in, k, (uint64_t)batch, (uint64_t)capq, ctx->q_key[in].as<uint32_t>(),
-                                         (int)n_keys, n_regions, chunk, ctx->q_hist.as<uint32_t>(),
-                                         ctx->q_kfill.as<uint32_t>(), ctx->q_perm.as<uint32_t>(),
-                                         ctx->q_items.as<WorkItem>(), grid_sort, ctx->work);
-        if (e != hipSuccess) return e;
-        BlkParams bk = b;
-        bk.q_in = ctx->q_rec[in].as<PRec>();
-        bk.u_out = ctx->q_rec[out].as<PRec>();
-        bk.u_key = ctx->q_key[out].as<uint32_t>();
-        bk.u_count = &st->count[out];
-        // the pass kernel's blocks also write this sweep's births, once its work items are taken
-        if (!capturing && (e = hipEventRecord(ctx->sweep_ev[2 * k], ctx->work)) != hipSuccess) return e;
-        if ((e = launch_blk_pass(bk, grid_pass, bs, reg_lds, ctx->work)) != hipSuccess) return e;
-        if (!capturing && (e = hipEventRecord(ctx->sweep_ev[2 * k + 1], ctx->work)) != hipSuccess) return e;
-        if (peelp && (e = launch_peel(bk.t, *peelp, grid_peel, ctx->work)) != hipSuccess) return e;
-      }
-      return hipSuccess;
-    };
     // capture the block as a graph (once per set of launch parameters), replay it until a
     // sweep finds the queues empty and nothing left to emit
-    std::vector<char> sig(sizeof b + 6 * sizeof(int64_t) + (out.peel ? sizeof(PeelParams) : 0));
+    std::vector<char> sig(sizeof L.b + 6 * sizeof(int64_t) + (out.peel ? sizeof(PeelParams) : 0));
     {
-      const int64_t extra[6] = {batch, capq, n_keys, grid_pass, bs, reg_lds};  // b holds split_n
-      std::memcpy(sig.data(), &b, sizeof b);
-      std::memcpy(sig.data() + sizeof b, extra, sizeof extra);
-      if (out.peel) std::memcpy(sig.data() + sizeof b + sizeof extra, out.peel, sizeof(PeelParams));
+      const int64_t extra[6] = {L.batch, L.capq, L.n_keys, L.grid_pass, L.bs, L.reg_lds};  // b holds split_n
+      std::memcpy(sig.data(), &L.b, sizeof L.b);
+      std::memcpy(sig.data() + sizeof L.b, extra, sizeof extra);
+      if (out.peel) std::memcpy(sig.data() + sizeof L.b + sizeof extra, out.peel, sizeof(PeelParams));
     }
     const bool use_graph = o->sweep_graph > 0;
     if (use_graph && (!ctx->sweep_exec || sig != ctx->sweep_sig)) {
@@ -1199,7 +1249,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
       }
       hipGraph_t graph = nullptr;
       HIPCHK(hipStreamBeginCapture(ctx->work, hipStreamCaptureModeThreadLocal));
-      const hipError_t ce = enqueue_block(true);
+      const hipError_t ce = enqueue_sweeps(ctx, L, ctx->work, nullptr);
       const hipError_t ee = hipStreamEndCapture(ctx->work, &graph);
       HIPCHK(ce);
       HIPCHK(ee);
@@ -1208,9 +1258,10 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
       HIPCHK(ie);
       ctx->sweep_sig = sig;
     }
-    for (int64_t blk = 0;; ++blk) {
+    int64_t blk = 0;
+    for (;; ++blk) {
       if (use_graph) HIPCHK(hipGraphLaunch(ctx->sweep_exec, ctx->work));
-      else HIPCHK(enqueue_block(false));
+      else HIPCHK(enqueue_sweeps(ctx, L, ctx->work, &ctx->sweep_ev));
       SweepState hs;
       HIPCHK(hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, ctx->work));
       HIPCHK(hipStreamSynchronize(ctx->work));
@@ -1227,6 +1278,8 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
       if (hs.done) break;
       if (blk > 2000000 / kSweepBlock) return fail(ctx, RT_EDEVICE, "region schedule did not drain");
     }
+    ctx->last_sweep_blocks = blk + 1;
+    if (out.save_launch) ctx->rl_saved = L;
     // later work on the caller's stream (the reduction) follows the sweeps
     HIPCHK(hipEventRecord(ctx->ev_c, ctx->work));
     HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_c, 0));
@@ -1427,6 +1480,175 @@ rt_status rt_solve_temperature(rt_ctx* ctx, int32_t model, const double* a_node,
   })
 }
 
+// A Lambda-iteration step captured as one HIP graph (region schedule): T_old <- T; the dust
+// emission tables of every wavelength with their totals kept on the device; the trace (zeroed
+// accumulators and tallies, sweep state, n_blocks blocks of sweeps); the FP64 reduction;
+// A = A_stars + A_dust (or the accelerated update); the temperature solve; the stopping
+// statistic.  The Philox key advances on the device at the start of each replay.  Built from the
+// launch configuration of a direct step of the same iteration (same buffers and parameters).
+struct StepGraph {
+  hipGraphExec_t exec = nullptr;
+  int64_t n_blocks = 0;
+  RegionLaunch L;   // the direct step's configuration with the device job table and key
+  uint64_t total = 0;
+  ~StepGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+
+// The step's work after its sweeps, on stream s (also run directly when a replay's sweeps did not
+// drain).
+static hipError_t step_post(rt_ctx* ctx, int32_t model, const StepGraph& G, bool ali, double t_min, double t_max,
+                            hipStream_t s) {
+  const HostModel& h = ctx->models[model];
+  const int64_t cb = ctx->h_models[model].canon_base;
+  hipError_t e;
+  if ((e = launch_blk_reduce(ctx->d_models.as<ModelDev>(), ctx->d_regions.as<RegionDev>(), (int)ctx->h_regions.size(),
+                             ctx->reg_maxn, ctx->d_rcanon.as<int32_t>(), ctx->acc.as<double>(), ctx->reg_G, 1,
+                             ctx->it_adust.as<double>(), nullptr, nullptr, 0, ctx->e_total.as<double>(), s)) !=
+      hipSuccess)
+    return e;
+  double* astars = ctx->it_astars.as<double>() + cb;
+  e = ali ? launch_ali_absorbed(h.n_nodes, astars, ctx->it_adust.as<double>() + cb, ctx->it_self.as<double>() + cb,
+                                ctx->it_emit.as<double>() + cb, ctx->it_sum.as<double>(), s)
+          : launch_add(h.n_nodes, astars, ctx->it_adust.as<double>() + cb, ctx->it_sum.as<double>(), s);
+  if (e != hipSuccess) return e;
+  if ((e = launch_temperature(ctx->d_models.as<ModelDev>(), model, h.n_nodes, ctx->d_child.as<int32_t>(),
+                              ctx->d_rho64.as<double>(), ctx->it_sum.as<double>(), h.d_lc.as<LamConst>(), h.nl, t_min,
+                              t_max, ctx->t_tab.as<double>(), h.d_T.as<double>(), s)) != hipSuccess)
+    return e;
+  if ((e = launch_fill_u64(ctx->it_crit.p, 2, 0ull, s)) != hipSuccess) return e;
+  if ((e = launch_crit(ctx->d_models.as<ModelDev>(), model, h.n_nodes, ctx->d_child.as<int32_t>(),
+                       ctx->d_rho64.as<double>(), h.d_T.as<double>(), ctx->it_told.as<double>(),
+                       ctx->it_crit.as<double>(), s)) != hipSuccess)
+    return e;
+  return launch_step_report(ctx->it_crit.as<double>(), G.L.st, ctx->stats.as<DevStats>(),
+                            ctx->g_report.as<double>(), s);
+}
+
+static hipError_t step_record(rt_ctx* ctx, int32_t model, const StepGraph& G, bool ali, double t_min, double t_max,
+                              hipStream_t s) {
+  const HostModel& h = ctx->models[model];
+  int64_t tn, tl, tln;
+  totals(ctx, &tn, &tl, &tln);
+  hipError_t e;
+  if ((e = launch_step_key(ctx->g_keys.as<uint32_t>(), s)) != hipSuccess) return e;
+  if ((e = launch_copy_u64(h.d_T.p, ctx->it_told.p, h.n_nodes, s)) != hipSuccess) return e;
+  if (ali) {
+    if ((e = launch_fill_u64(ctx->it_self.p, tn, 0ull, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(ctx->it_emit.p, tn, 0ull, s)) != hipSuccess) return e;
+  }
+  const int32_t no_sub[3] = {0, 0, 0};
+  JobDev* jobs = ctx->g_jobs.as<JobDev>();
+  for (int i = 0; i < h.nl; ++i) {
+    const int64_t off = (int64_t)i * h.n_leaves;
+    double* lum = ctx->cdf_lum.as<double>() + off;
+    uint64_t* q = ctx->cdf_q.as<uint64_t>() + off;
+    if ((e = launch_fill_u64(ctx->lmax.p, 2, 0ull, s)) != hipSuccess) return e;
+    if ((e = launch_dust_lum(ctx->d_models.as<ModelDev>(), model, h.n_leaves, ctx->d_leaf_node.as<int32_t>(),
+                             ctx->d_leaf_level.as<uint8_t>(), ctx->d_rho64.as<double>(), h.d_T.as<double>(),
+                             h.d_lc.as<LamConst>(), i, lum, ctx->lmax.as<unsigned long long>(),
+                             ctx->d_leaf_coord.as<int32_t>(), -1, no_sub, s)) != hipSuccess)
+      return e;
+    if ((e = launch_dust_quant(h.n_leaves, lum, ctx->lmax.as<unsigned long long>(), q, s)) != hipSuccess) return e;
+    if ((e = launch_dust_scan(h.n_leaves, q, ctx->cdf_qpre.as<uint64_t>() + off, ctx->g_scan.as<uint64_t>(),
+                              &jobs[i].qtot, s)) != hipSuccess)
+      return e;
+  }
+  if ((e = launch_fill_u64(ctx->acc.p, ctx->reg_G, 0ull, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u64(ctx->stats.p, sizeof(DevStats) / 8, 0ull, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u64(ctx->e_total.p, 1, 0ull, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u64(ctx->out_esc.p, tl, 0ull, s)) != hipSuccess) return e;
+  if ((e = launch_sweep_init(G.L.st, G.total, (uint64_t)G.L.cap_all, s)) != hipSuccess) return e;
+  for (int64_t k = 0; k < G.n_blocks; ++k)
+    if ((e = enqueue_sweeps(ctx, G.L, s, nullptr)) != hipSuccess) return e;
+  return step_post(ctx, model, G, ali, t_min, t_max, s);
+}
+
+// Capture the step graph after a direct step of the same iteration (which left its launch
+// configuration in ctx->rl_saved and its job table in ctx->jobs).  key1_done: the second key
+// word of the direct step; every replay advances it by one first.
+static rt_status step_build(rt_ctx* ctx, int32_t model, StepGraph& G, int64_t n_blocks, int64_t dust_packets,
+                            uint32_t key0, uint32_t key1_done, bool ali, double t_min, double t_max) {
+  const HostModel& h = ctx->models[model];
+  if (G.exec) {
+    HIPCHK(hipGraphExecDestroy(G.exec));
+    G.exec = nullptr;
+  }
+  // the job table with every wavelength present (a wavelength with no emission is skipped on
+  // the device from its table total) and the key in device memory
+  std::vector<JobDev> jobs(h.nl);
+  HIPCHK(hipMemcpyAsync(jobs.data(), ctx->jobs.p, sizeof(JobDev) * h.nl, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  uint64_t start = 0;
+  for (int i = 0; i < h.nl; ++i) {
+    if (jobs[i].kind != RT_SRC_DUST || jobs[i].lam != i || jobs[i].cdf_off != (int64_t)i * h.n_leaves)
+      return fail(ctx, RT_EDEVICE, "internal error: unexpected dust job table");
+    jobs[i].start = start;
+    jobs[i].n = (uint64_t)dust_packets;
+    jobs[i].qtot = 0;
+    start += jobs[i].n;
+  }
+  if (rt_status e = upload(ctx, ctx->g_jobs, jobs)) return e;
+  HIPCHK(ctx->g_keys.ensure(8));
+  HIPCHK(ctx->g_scan.ensure(8 * std::max<int64_t>(dust_scan_tiles(h.n_leaves), 1)));
+  HIPCHK(ctx->g_report.ensure(8 * 8));
+  HIPCHK(ctx->lmax.ensure(16));
+  ctx->g_keys_host[0] = key0;
+  ctx->g_keys_host[1] = key1_done;
+  HIPCHK(hipMemcpyAsync(ctx->g_keys.p, ctx->g_keys_host, 8, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  G.L = ctx->rl_saved;
+  G.L.b.t.jobs = ctx->g_jobs.as<JobDev>();
+  G.L.b.t.n_jobs = h.nl;
+  G.L.b.t.total_packets = start;
+  G.L.b.t.keys = ctx->g_keys.as<uint32_t>();
+  G.total = start;
+  G.n_blocks = n_blocks;
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(ctx->work, hipStreamCaptureModeThreadLocal));
+  const hipError_t ce = step_record(ctx, model, G, ali, t_min, t_max, ctx->work);
+  const hipError_t ee = hipStreamEndCapture(ctx->work, &graph);
+  HIPCHK(ce);
+  HIPCHK(ee);
+  const hipError_t ie = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(ie);
+  return RT_OK;
+}
+
+// One replay of the step graph; when its sweeps did not drain (more than the captured blocks
+// were needed), the remaining sweeps and the work after them run directly.  report: the
+// stopping statistic's numerator and denominator, whether the replayed sweeps drained, the
+// step's crossings and misplaced queue records.
+static rt_status step_replay(rt_ctx* ctx, int32_t model, StepGraph& G, bool ali, double t_min, double t_max,
+                             double report[5], bool* drained) {
+  HIPCHK(hipEventRecord(ctx->ev_c, ctx->stream));
+  HIPCHK(hipStreamWaitEvent(ctx->work, ctx->ev_c, 0));
+  HIPCHK(hipGraphLaunch(G.exec, ctx->work));
+  HIPCHK(hipMemcpyAsync(report, ctx->g_report.p, 40, hipMemcpyDeviceToHost, ctx->work));
+  HIPCHK(hipStreamSynchronize(ctx->work));
+  *drained = report[2] != 0.0;
+  if (!*drained) {
+    for (int64_t blk = 0;; ++blk) {
+      HIPCHK(enqueue_sweeps(ctx, G.L, ctx->work, nullptr));
+      SweepState hs;
+      HIPCHK(hipMemcpyAsync(&hs, G.L.st, sizeof hs, hipMemcpyDeviceToHost, ctx->work));
+      HIPCHK(hipStreamSynchronize(ctx->work));
+      if (hs.done) break;
+      if (blk > 2000000 / kSweepBlock) return fail(ctx, RT_EDEVICE, "region schedule did not drain");
+    }
+    HIPCHK(step_post(ctx, model, G, ali, t_min, t_max, ctx->work));
+    HIPCHK(hipMemcpyAsync(report, ctx->g_report.p, 40, hipMemcpyDeviceToHost, ctx->work));
+    HIPCHK(hipStreamSynchronize(ctx->work));
+  }
+  if (report[4] != 0.0)
+    return fail(ctx, RT_EDEVICE, "internal error: %.0f packet records were queued for the wrong region", report[4]);
+  HIPCHK(hipEventRecord(ctx->ev_c, ctx->work));
+  HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_c, 0));
+  return RT_OK;
+}
+
 static rt_status lambda_iterate_impl(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
                                      const rt_trace_opts* opts, int64_t dust_packets, int32_t n_max,
                                      double tol, double t_min, double t_max, double* t_node,
@@ -1473,8 +1695,29 @@ static rt_status lambda_iterate_impl(rt_ctx* ctx, int32_t model, int32_t n_src, 
       HIPCHK(hipMemsetAsync(ctx->it_astars.p, 0, 8 * tn, ctx->stream));
     }
     if (rt_status s = solve_T_impl(ctx, model, astars, t_min, t_max)) return s;
+    // captured steps: the region schedule with sweep_graph > 0; the first step runs directly
+    // and gives the launch configuration and the number of sweeps to capture
+    const bool graph = opts->sweep_graph > 0 && opts->precision == RT_FP32_LOCAL && opts->schedule == RT_SCHED_REGIONS;
+    StepGraph G;
+    const uint32_t key0 = (uint32_t)(opts->seed & 0xffffffffu);
+    const uint32_t key1_base = (uint32_t)(opts->seed >> 32) + opts->iteration;
     int32_t n = 0;
     for (int32_t it = 1; it <= n_max; ++it) {
+      if (graph && G.exec) {
+        double rep[5];
+        bool drained = false;
+        if (rt_status s = step_replay(ctx, model, G, ali, t_min, t_max, rep, &drained)) return s;
+        const double cval = rep[1] > 0.0 ? rep[0] / rep[1] : 0.0;
+        if (crit) crit[it - 1] = cval;
+        n = it;
+        // a replay whose sweeps did not drain was completed directly: capture more sweeps
+        if (!drained && it < n_max)
+          if (rt_status s = step_build(ctx, model, G, G.n_blocks + 2, dust_packets, key0,
+                                       key1_base + (uint32_t)it, ali, t_min, t_max))
+            return s;
+        if (cval < tol) break;
+        continue;
+      }
       rt_source ds;
       std::memset(&ds, 0, sizeof ds);
       ds.kind = RT_SRC_DUST;
@@ -1482,6 +1725,7 @@ static rt_status lambda_iterate_impl(rt_ctx* ctx, int32_t model, int32_t n_src, 
       ds.packets_per_lambda = dust_packets;
       o.iteration = opts->iteration + (uint32_t)it;
       out.e_node = ctx->it_adust.as<double>();
+      out.save_launch = graph;
       if (ali) {
         HIPCHK(hipMemsetAsync(ctx->it_self.p, 0, 8 * tn, ctx->stream));
         HIPCHK(hipMemsetAsync(ctx->it_emit.p, 0, 8 * tn, ctx->stream));
@@ -1509,6 +1753,10 @@ static rt_status lambda_iterate_impl(rt_ctx* ctx, int32_t model, int32_t n_src, 
       if (crit) crit[it - 1] = cval;
       n = it;
       if (cval < tol) break;
+      if (graph && it < n_max)
+        if (rt_status s = step_build(ctx, model, G, ctx->last_sweep_blocks + 1, dust_packets, key0,
+                                     key1_base + (uint32_t)it, ali, t_min, t_max))
+          return s;
     }
     if (n_done) *n_done = n;
     if (t_node)
@@ -1535,8 +1783,59 @@ rt_status rt_ali_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_sou
                              n_done, crit, true);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Nodes of the subtree below refined node `root` (root itself excluded; all nodes for -1), from
+// the canonical parents (a parent precedes its children in canonical order).
+std::vector<char> subtree_of(const HostModel& h, int64_t root) {
+  std::vector<char> in(h.n_nodes, root < 0 ? 1 : 0);
+  if (root >= 0)
+    for (int64_t c = h.n_root; c < h.n_nodes; ++c) {
+      const int64_t pc = h.sub_parent[c];
+      in[c] = (pc == root || in[pc]) ? 1 : 0;
+    }
+  return in;
+}
+
+// After a step below `root` (Sect. 3.3): the energy flow from the root's subtree into its parent
+// grid is compared with what it was when that parent grid last took part in a step; a change
+// above flux_frac of the energy the parent grid absorbs tags the parent grid for the next step.
+// The refined nodes below the root get their new reference flows (their parent grids took part),
+// and every grid of this step loses its tag.
+void subiter_flux_update(rt_ctx* ctx, int32_t model, int64_t root, const std::vector<double>& flux,
+                         const std::vector<double>& a_tot) {
+  HostModel& h = ctx->models[model];
+  const int64_t pad0 = h.n_root_pad - h.n_root;
+  auto refined = [&](int64_t c) { return ctx->h_child[h.base + (c < h.n_root ? c : c + pad0)] >= 0; };
+  const std::vector<char> in = subtree_of(h, root);
+  if (root >= 0) {
+    const int64_t par = h.sub_parent[root];  // -1: the root grid
+    const std::vector<char> in_par = subtree_of(h, par);
+    double absorbed = 0.0;
+    for (int64_t c = 0; c < h.n_nodes; ++c)
+      if (in_par[c] && !refined(c)) absorbed += a_tot[c];
+    if (std::fabs(flux[root] - h.sub_flux_ref[root]) > h.sub_flux_frac * absorbed) {
+      if (par < 0) h.sub_tag_root = true;
+      else h.sub_tag[par] = 1;
+    }
+  }
+  for (int64_t c = 0; c < h.n_nodes; ++c)
+    if (in[c] && refined(c)) {
+      h.sub_flux_ref[c] = flux[c];
+      h.sub_tag[c] = 0;
+    }
+  if (root >= 0) h.sub_tag[root] = 0;
+  else h.sub_tag_root = false;
+}
+
+}  // namespace
+
+extern "C" {
+
 rt_status rt_subiter_begin(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
-                           const rt_trace_opts* opts, double t_min, double t_max) {
+                           const rt_trace_opts* opts, double t_min, double t_max, double flux_frac) {
   if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
   GUARD({
     if (rt_status s = check_model(ctx, model)) return s;
@@ -1544,6 +1843,7 @@ rt_status rt_subiter_begin(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_s
     if (!(opts->precision == RT_FP64 || (opts->precision == RT_FP32_LOCAL && opts->schedule == RT_SCHED_REGIONS)))
       return fail(ctx, RT_EINVAL, "subiterations run in the RT_FP64 form or the region schedule");
     if (!(t_min > 0.0) || !(t_max > t_min)) return fail(ctx, RT_EINVAL, "need 0 < t_min < t_max");
+    if (!(flux_frac >= 0.0) || !std::isfinite(flux_frac)) return fail(ctx, RT_EINVAL, "flux_frac must be >= 0");
     for (int s = 0; s < n_src; ++s)
       if (src && (src[s].model != model || src[s].kind == RT_SRC_DUST))
         return fail(ctx, RT_EINVAL, "constant sources must belong to the model and not be dust");
@@ -1556,6 +1856,20 @@ rt_status rt_subiter_begin(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_s
     const int64_t cb = ctx->h_models[model].canon_base;
     HIPCHK(ctx->it_astars.ensure(8 * tn));
     HIPCHK(ctx->out_esc.ensure(8 * std::max<int64_t>(tl, 1)));
+    // canonical parents (the flux bookkeeping of the automatic iteration)
+    h.sub_parent.assign(h.n_nodes, -1);
+    {
+      const int64_t pad0 = h.n_root_pad - h.n_root;
+      for (int64_t c = h.n_root; c < h.n_nodes; ++c) {
+        const int64_t pi = ctx->h_up[(h.base + c + pad0) >> 3];
+        const int64_t pc = pi - h.base;
+        h.sub_parent[c] = pc < h.n_root ? pc : pc - pad0;
+      }
+    }
+    h.sub_flux_frac = flux_frac;
+    h.sub_flux_ref.assign(h.n_nodes, 0.0);
+    h.sub_tag.assign(h.n_nodes, 0);
+    h.sub_tag_root = false;
     if (n_src > 0) {
       TraceOut out;
       out.e_esc = ctx->out_esc.as<double>();
@@ -1652,6 +1966,11 @@ rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust
     out.lvl_stride = tn;
     out.sub_lev = sub_lev;
     for (int a = 0; a < 3; ++a) out.sub_I[a] = sub_I[a];
+    if (h.sub_flux_frac > 0.0) {
+      HIPCHK(ctx->it_emit.ensure(8 * tn));
+      HIPCHK(hipMemsetAsync(ctx->it_emit.p, 0, 8 * tn, ctx->stream));
+      out.flux_acc = ctx->it_emit.as<double>();
+    }
     if (rt_status s = trace_impl(ctx, 1, &ds, &o, out, stats)) return s;
     HIPCHK(launch_subiter_update(ctx->d_models.as<ModelDev>(), model, h.n_leaves, ctx->d_leaf_node.as<int32_t>(),
                                  ctx->d_leaf_level.as<uint8_t>(), ctx->d_leaf_coord.as<int32_t>(),
@@ -1669,8 +1988,17 @@ rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust
     if (t_node)
       HIPCHK(hipMemcpyAsync(t_node, h.d_T.p, 8 * h.n_nodes,
                             is_device_ptr(t_node) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<double> flux, a_tot;
+    if (h.sub_flux_frac > 0.0) {
+      flux.resize(h.n_nodes);
+      a_tot.resize(h.n_nodes);
+      HIPCHK(hipMemcpyAsync(flux.data(), ctx->it_emit.as<double>() + cb, 8 * h.n_nodes, hipMemcpyDeviceToHost,
+                            ctx->stream));
+      HIPCHK(hipMemcpyAsync(a_tot.data(), ctx->it_sum.p, 8 * h.n_nodes, hipMemcpyDeviceToHost, ctx->stream));
+    }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (crit) *crit = c2[1] > 0.0 ? c2[0] / c2[1] : 0.0;
+    if (h.sub_flux_frac > 0.0) subiter_flux_update(ctx, model, root, flux, a_tot);
     return RT_OK;
   })
 }
@@ -1706,10 +2034,13 @@ rt_status rt_subiter_select(rt_ctx* ctx, int32_t model, double frac, int64_t* ro
       const int64_t i = internal_of(c);
       return canon_of_h(ctx->h_up[i >> 3]);
     };
-    int64_t lca = -2;  // none yet
+    // a grid tagged because the energy flowing into it from a child changed (Sect. 3.3) must be
+    // in the next step too: the root grid's tag means the whole model
+    int64_t lca = h.sub_tag_root ? -1 : -2;  // -2: none yet
     for (int64_t c = 0; c < h.n_nodes && lca != -1; ++c) {
-      if (!(mx > 0.0) || imb[c] < frac * mx) continue;
-      int64_t a = parent(c);
+      const bool tagged = h.sub_tag.size() == (size_t)h.n_nodes && h.sub_tag[c];
+      if (!tagged && (!(mx > 0.0) || imb[c] < frac * mx)) continue;
+      int64_t a = tagged ? c : parent(c);
       if (lca == -2) {
         lca = a;
         continue;
@@ -1789,8 +2120,9 @@ rt_status rt_render_map(rt_ctx* ctx, int32_t model, const double n_obs[3], int32
     void* dimg;
     bool copy;
     if (rt_status s = stage_out(ctx, image, img_bytes, ctx->tmp_out, &dimg, &copy)) return s;
-    for (int q0 = 0; q0 < n_sel; q0 += 16) {
-      const int nq = std::min(16, n_sel - q0);
+    const int pass = precision == RT_FP32_LOCAL ? kRenderPassF32 : kRenderPassF64;
+    for (int q0 = 0; q0 < n_sel; q0 += pass) {
+      const int nq = std::min(pass, n_sel - q0);
       HIPCHK(launch_render(precision == RT_FP32_LOCAL, ctx->d_models.as<ModelDev>(), model,
                            ctx->d_child.as<int32_t>(),
                                 ctx->d_up.as<int32_t>(), ctx->d_rho64.as<double>(), h.d_T.as<double>(),

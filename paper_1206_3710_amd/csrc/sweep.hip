@@ -74,6 +74,18 @@ __global__ void sw_begin_kernel(SweepState* st, int in, int slot, uint64_t batch
   if (n_in > 0) st->sweeps += 1u;
 }
 
+// The sweep state at the start of a trace: nothing queued or emitted yet (a kernel, so that a
+// captured iteration step contains no host copy).
+__global__ void sw_init_kernel(SweepState* st, unsigned long long total, unsigned long long cap_all) {
+  unsigned long long* w = reinterpret_cast<unsigned long long*>(st);
+  for (int i = threadIdx.x; i < (int)(sizeof(SweepState) / 8); i += blockDim.x) w[i] = 0ull;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->total = total;
+    st->cap_all = cap_all;
+  }
+}
+
 __global__ void sw_zero_kernel(uint32_t* __restrict__ a, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = 0u;
 }
@@ -214,5 +226,12 @@ hipError_t launch_sweep_sort(SweepState* st, int in, int slot, uint64_t batch, u
                      kfill, items, st);
   hipLaunchKernelGGL(sw_scatter_kernel, dim3(grid), dim3(256), 0, s, keys, (const SweepState*)st, kfill, perm,
                      n_keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_init(SweepState* st, uint64_t total, uint64_t cap_all, hipStream_t s) {
+  static_assert(sizeof(SweepState) % 8 == 0, "sweep state of whole words");
+  hipLaunchKernelGGL(sw_init_kernel, dim3(1), dim3(64), 0, s, st, (unsigned long long)total,
+                     (unsigned long long)cap_all);
   return hipGetLastError();
 }

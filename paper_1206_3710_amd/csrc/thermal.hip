@@ -206,6 +206,84 @@ __global__ __launch_bounds__(256) void dust_quant_kernel(int64_t n, const double
   q[k] = lmax > 0.0 ? (uint64_t)floor((lum[k] / lmax) * 4294967296.0) : 0ull;
 }
 
+// Exact exclusive prefix sum of the quantised luminosities on the device (the dust-emission
+// table of a captured iteration step, whose total must stay on the device): tiles of
+// kScanTile values are summed, the tile sums scanned by one block, then each tile is scanned
+// from its offset.  Integer sums are exact, so the result equals any other summation order.
+constexpr int kScanPer = 16;
+constexpr int kScanTile = 256 * kScanPer;
+
+__device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t v, uint64_t* s_w, uint64_t& total) {
+  // wave-inclusive scan, then across the 4 waves of a 256-thread block
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_w[wv] = x;
+  __syncthreads();
+  uint64_t off = 0;
+  for (int k = 0; k < wv; ++k) off += s_w[k];
+  total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+  __syncthreads();
+  return off + x - v;
+}
+
+__global__ __launch_bounds__(256) void scan_tile_sums_kernel(const uint64_t* __restrict__ q, int64_t n,
+                                                             uint64_t* __restrict__ tile_sum) {
+  __shared__ uint64_t s_w[4];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+  uint64_t v = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const int64_t i = t0 + (int64_t)j * 256 + threadIdx.x;
+    if (i < n) v += q[i];
+  }
+  uint64_t total;
+  (void)block_exclusive_u64(v, s_w, total);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// One block: tile sums -> exclusive tile offsets (in place); the grand total to *total_out.
+__global__ __launch_bounds__(256) void scan_tile_offsets_kernel(uint64_t* __restrict__ tile_sum, int64_t n_tiles,
+                                                                uint64_t* __restrict__ total_out) {
+  __shared__ uint64_t s_w[4];
+  uint64_t carry = 0;
+  for (int64_t t0 = 0; t0 < n_tiles; t0 += 256) {
+    const int64_t i = t0 + threadIdx.x;
+    const uint64_t v = i < n_tiles ? tile_sum[i] : 0ull;
+    uint64_t total;
+    const uint64_t ex = block_exclusive_u64(v, s_w, total);
+    if (i < n_tiles) tile_sum[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ __launch_bounds__(256) void scan_tiles_kernel(const uint64_t* __restrict__ q, int64_t n,
+                                                         const uint64_t* __restrict__ tile_off,
+                                                         uint64_t* __restrict__ qpre) {
+  __shared__ uint64_t s_w[4];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  uint64_t v[kScanPer], sum = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const int64_t i = t0 + j;
+    v[j] = i < n ? q[i] : 0ull;
+    sum += v[j];
+  }
+  uint64_t total;
+  uint64_t run = tile_off[blockIdx.x] + block_exclusive_u64(sum, s_w, total);
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const int64_t i = t0 + j;
+    if (i < n) qpre[i] = run;
+    run += v[j];
+  }
+}
+
 // After a (sub)iteration step (App. B): for every leaf of the subtree, replace its arrays of
 // levels >= lo by the step's deposits and record the energy imbalance |A - E(T_old)| / E(T_old)
 // between what it now absorbs and what it emitted; for every leaf, A_tot = A_stars + the sum of
@@ -287,3 +365,16 @@ hipError_t launch_dust_quant(int64_t n_leaves, const double* lum,
                      n_leaves, lum, lmax_bits, q);
   return hipGetLastError();
 }
+
+hipError_t launch_dust_scan(int64_t n, const uint64_t* q, uint64_t* qpre, uint64_t* tile_tmp, uint64_t* total_out,
+                            hipStream_t s) {
+  if (n <= 0) return hipErrorInvalidValue;
+  const int64_t n_tiles = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(scan_tile_sums_kernel, dim3((unsigned)n_tiles), dim3(256), 0, s, q, n, tile_tmp);
+  hipLaunchKernelGGL(scan_tile_offsets_kernel, dim3(1), dim3(256), 0, s, tile_tmp, n_tiles, total_out);
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)n_tiles), dim3(256), 0, s, q, n, (const uint64_t*)tile_tmp,
+                     qpre);
+  return hipGetLastError();
+}
+
+int64_t dust_scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(BS) void trace_fp32_kernel(const TraceParams p) {
           acc_off = J.acc_off;
           esc_slot = J.esc_slot;
           Pk64 k;
-          emit64(p, J, D, md.n_leaves, md.leaf_base, pid, k, cw);
+          emit64(p, J, D, md.n_leaves, md.leaf_base, pid, k, cw, p.key0, p.key1);
           node = k.node;
           lev = k.lev;
           I0 = k.I[0];

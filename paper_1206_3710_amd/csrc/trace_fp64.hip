@@ -19,7 +19,7 @@ __global__ __launch_bounds__(256) void trace_fp64_kernel(const TraceParams p, co
 
   if (j < job.n) {
     Pk64 k;
-    emit64(p, job, D, md.n_leaves, md.leaf_base, (uint32_t)j, k, ch);
+    emit64(p, job, D, md.n_leaves, md.leaf_base, (uint32_t)j, k, ch, p.key0, p.key1);
     const int32_t birth = k.node;
     double w = k.w0;
     const double w0 = k.w0;
@@ -129,6 +129,11 @@ __global__ __launch_bounds__(256) void trace_fp64_kernel(const TraceParams p, co
       for (int b = 0; b < 3; ++b)
         if (b == ax) k.P[b] = face_ax;
       const int sg = sel3(ax, k.d[0], k.d[1], k.d[2]) > 0.0 ? 1 : -1;
+      if (p.flux_acc) {
+        // automatic iteration: the weight leaving each refined ancestor's subtree
+        const int32_t Ia = k.I[ax], Ja = Ia + sg;
+        flux_exits(md, p.up, p.flux_acc, k.node, k.lev, Ia, Ja, Ja < 0 || Ja >= (D.na(ax) << k.lev), w);
+      }
       int32_t raw;
       if (!cross_walk(D, p.up, ax, sg, k.node, k.lev, k.I, raw, ch)) {
         t_esc = w;

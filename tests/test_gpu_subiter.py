@@ -229,3 +229,54 @@ def test_subiterations_regions_reject_other_options(torch):
     t, _, _ = ctx.subiter_step(m, -1, dust_packets=100, seed=1, iteration=1, **kw)
     assert float(t.max()) > 0.0
     ctx.close()
+
+
+def test_automatic_iteration_against_oracle_fp64(torch):
+    """The automatic iteration of Sect. 3.3 with the flow tracking on, FP64 form, against the
+    oracle's own automatic iteration (its imbalances, stall rule and flow tags): the same root
+    at every step, including a parent grid taken because the flow from its child changed, and
+    the temperatures after every step within 1e-6."""
+    w = gen.core_cloud(packets=20000)
+    tree, dust = w.trees[0], w.dusts[0]
+    kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob)
+    o = oracle.Model(tree, dust)
+    n = 6
+    hist, roots = oracle.subiterate_auto(o, w.sources, seed=w.seed, n_steps=n, dust_packets=20000, frac=0.5,
+                                         stall=0.8, flux_frac=0.02, **kw)
+    par = oracle.canonical_parents(o)
+    assert any(roots[k] >= 0 and roots[k - 1] >= 0 and roots[k] == par[roots[k - 1]] for k in range(1, n)), roots
+    leaf = o.leaf_mask
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    for k in range(1, n + 1):
+        ctx.subiter_begin(m, w.sources, seed=w.seed, flux_frac=0.02, **kw)
+        t, r, crit, cross = ctx.subiter_run(m, k, dust_packets=20000, seed=w.seed, frac=0.5, stall=0.8, **kw)
+        assert [int(v) for v in r] == roots[:k], (k, list(r), roots)
+        np.testing.assert_allclose(t.cpu().numpy()[leaf], hist[k][leaf], rtol=1e-6)
+    ctx.close()
+
+
+def test_automatic_iteration_regions_follows_fp64(torch):
+    """The same automatic iteration in the FP32-local region schedule (the flow tallied in the
+    region pass): the same roots as the oracle's, and temperatures far below the Monte Carlo
+    noise from it."""
+    w = gen.core_cloud(packets=20000)
+    tree, dust = w.trees[0], w.dusts[0]
+    kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob)
+    o = oracle.Model(tree, dust)
+    n = 6
+    ha, roots = oracle.subiterate_auto(o, w.sources, seed=w.seed, n_steps=n, dust_packets=20000, frac=0.5,
+                                       stall=0.8, flux_frac=0.02, **kw)
+    hb, _, _ = oracle.subiterate(o, w.sources, w.seed + 1, roots, 20000, **kw)
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    reg = dict(precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS)
+    ctx.subiter_begin(m, w.sources, seed=w.seed, flux_frac=0.02, **kw, **reg)
+    t, r, crit, cross = ctx.subiter_run(m, n, dust_packets=20000, seed=w.seed, frac=0.5, stall=0.8, **kw, **reg)
+    ctx.close()
+    assert [int(v) for v in r] == roots, (list(r), roots)
+    err = _mass_weighted_diff(o, t.cpu().numpy(), ha[-1])
+    noise = _mass_weighted_diff(o, hb[-1], ha[-1])
+    assert err < 0.1 * noise, (err, noise)

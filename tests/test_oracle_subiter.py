@@ -103,3 +103,91 @@ def test_subiteration_changes_only_its_subtree():
     inside = o.subtree_mask(root)
     assert np.array_equal(hs[2][~inside], hs[1][~inside])
     assert np.any(hs[2][inside & o.leaf_mask] != hs[1][inside & o.leaf_mask])
+
+
+# ---------------------------------------------------------------------------------------
+# energy flow from each grid to its parent (Sect. 3.3)
+# ---------------------------------------------------------------------------------------
+
+def _beam_row():
+    """Root 4 x 1 x 1 of side 1 and density 1 (pure absorber, kappa 1): root cell 1 (x in
+    [1, 2)) refined once, and its child (0, 0, 0) (x in [1, 1.5), y, z in [0, 0.5)) refined
+    again."""
+    tree = gen.TreeDesc(4, 1, 1, 1.0, np.ones(4), [np.array([1]), np.array([0])],
+                        [np.ones(8), np.ones(8)])
+    dust = gen.Dust(np.array([1.0]), np.array([1.0]), np.array([0.0]), np.array([0.0]))
+    return oracle.Model(tree, dust)
+
+
+def test_flux_of_a_beam_closed_form():
+    """A beam along +x at y = z = 0.37 from x = 0.5 leaves the subtree of the level-1 refined
+    cell at x = 1.5 and that of root cell 1 at x = 2, each once per packet, with the weight it
+    has there: N w0 exp(-1.0) and N w0 exp(-1.5).  Along -x from x = 1.2 it leaves both at
+    x = 1 in the same crossing (N w0 exp(-0.2) each), then root cell 0 (a leaf: no subtree) and
+    the model."""
+    o = _beam_row()
+    inner = o.offsets[1] + 0            # root cell 1's child (0, 0, 0): the refined level-1 cell
+    assert o.child[1] >= 0 and o.child[inner] >= 0
+    n = 500
+    src = [gen.Source(gen.SRC_BEAM, 0, pos=(0.5, 0.37, 0.37), dir=(1.0, 0.0, 0.0),
+                      power=np.array([1.0]), packets=n)]
+    _, _, st, _ = o.trace(src, seed=1, flux=True)
+    f = st["e_flux"]
+    np.testing.assert_allclose(f[inner], np.exp(-1.0), rtol=1e-13)
+    np.testing.assert_allclose(f[1], np.exp(-1.5), rtol=1e-13)
+    others = np.ones(o.n_nodes, dtype=bool)
+    others[[1, inner]] = False
+    assert np.all(f[others] == 0.0)
+    src = [gen.Source(gen.SRC_BEAM, 0, pos=(1.2, 0.37, 0.37), dir=(-1.0, 0.0, 0.0),
+                      power=np.array([1.0]), packets=n)]
+    _, _, st, _ = o.trace(src, seed=1, flux=True)
+    f = st["e_flux"]
+    np.testing.assert_allclose(f[[1, inner]], np.exp(-0.2), rtol=1e-13)
+    assert np.all(f[others] == 0.0)
+
+
+def test_flux_out_of_the_iterated_subtree_is_what_leaves_it():
+    """In a subtree step every package that leaves the subtree is ended there: the flow out of
+    the subtree's root equals the escaped energy, no refined cell outside it sees any flow, and
+    the flows of the refined cells inside it are positive."""
+    tree = gen.refined_block(2)
+    o = oracle.Model(tree, _dust(0.6))
+    root = 1 + 4 * (1 + 4 * 1)
+    inside = o.subtree_mask(root)
+    t = np.where(o.leaf_mask, 60.0, 0.0)
+    _, _, st, _ = o.trace([gen.Source(gen.SRC_DUST, 0, packets=4000)], seed=4, t_node=t,
+                          level_arrays=True, subtree=root, flux=True)
+    f = st["e_flux"]
+    assert f[root] > 0.0
+    assert abs(f[root] - st["e_esc"]) <= 1e-12 * st["e_esc"]
+    refined = ~o.leaf_mask
+    outside = refined & ~inside
+    outside[root] = False
+    assert np.all(f[outside] == 0.0)
+    assert np.all(f[refined & inside] > 0.0)
+
+
+def test_automatic_iteration_follows_its_rules():
+    """The oracle's automatic iteration on a thin cloud with a dense core around a star: the
+    first step takes the whole model; a repeated subtree whose largest imbalance did not drop
+    below `stall` of its previous value is replaced by the whole model; with the flow tracking
+    on, a step below r whose outflow changed by more than flux_frac of what r's parent absorbs
+    makes the next step include that parent; the temperatures equal those of the explicit
+    schedule of the same roots."""
+    w = gen.core_cloud(packets=20000)
+    o = oracle.Model(w.trees[0], w.dusts[0])
+    kw = dict(seed=w.seed, n_steps=6, dust_packets=20000, frac=0.5, stall=0.8,
+              rr_threshold=w.rr_threshold, rr_prob=w.rr_prob)
+    h0, r0 = oracle.subiterate_auto(o, w.sources, flux_frac=0.0, **kw)
+    assert r0[0] == -1
+    for a, b in zip(r0[:-1], r0[1:]):   # no subtree twice in a row here (the stall rule)
+        assert not (a >= 0 and a == b)
+    hs, _, _ = oracle.subiterate(o, w.sources, w.seed, r0, 20000, rr_threshold=w.rr_threshold,
+                                 rr_prob=w.rr_prob)
+    for a, b in zip(h0, hs):
+        np.testing.assert_allclose(a, b, rtol=1e-13)
+    h1, r1 = oracle.subiterate_auto(o, w.sources, flux_frac=0.02, **kw)
+    par = oracle.canonical_parents(o)
+    tagged_steps = [k for k in range(1, len(r1)) if r1[k] >= 0 and r1[k - 1] >= 0 and r1[k] == par[r1[k - 1]]]
+    assert tagged_steps, r1   # a parent grid taken because its inflow from the child changed
+    assert r1 != r0
