@@ -74,7 +74,7 @@ def lib():
         L.om_trace.restype = C.c_int
         L.om_trace.argtypes = [P, C.c_int32, C.c_int32, P, P, P, P, P, P, C.c_uint64, C.c_uint32,
                                C.c_double, C.c_double, C.c_int64, C.c_int32, C.c_int64, C.c_int64,
-                               C.c_int32, P, P, P, C.c_int64, P, C.c_int32, P, P, P, P, C.c_int64, P]
+                               C.c_int32, P, P, P, C.c_int64, P, C.c_int32, P, P, P, P, C.c_int64, P, C.c_int32]
         L.om_node_coords.argtypes = [P, P]
         L.om_emission_all.argtypes = [P, P, P]
         L.om_hg_phase.restype = C.c_double
@@ -195,7 +195,7 @@ class Model:
     def trace(self, sources, seed, iteration=0, model_index=0, rr_threshold=0.0, rr_prob=0.0,
               max_events=0, per_lambda=False, pid_begin=0, pid_end=-1, lam_sel=-1,
               t_node=None, rec_stride=0, deposits=True, split_n=1, peel=None, self_absorption=False,
-              level_arrays=False, subtree=-1, e_abs_out=None, flux=False):
+              level_arrays=False, subtree=-1, e_abs_out=None, flux=False, split_depth=0):
         """Follow packets of ``sources`` (gen.Source list) -> (e_abs, e_esc, stats, records).
         ``peel``: dict(n_obs=[[x, y, z], ...], npix=, width=0.0, tiles=0) turns on the peel-off
         images, returned in stats["peel_image"] as [n_dir, n_lambda, npix, npix].
@@ -206,7 +206,9 @@ class Model:
         ``e_abs_out``: a caller-owned float64 array the deposits are added to (instead of a new
         zeroed one), so that repeated or concurrent calls need no new allocation.  ``flux``:
         stats["e_flux"] per node, the weight of the packages leaving each refined node's subtree
-        (the energy flow from each grid to its parent, Sect. 3.3)."""
+        (the energy flow from each grid to its parent, Sect. 3.3).  ``split_depth``: the reading
+        of "grid" for splitting, 0 every oct, d > 0 all levels below d one grid with their
+        level-d ancestor (1: the root grid and one grid per refined root cell)."""
         L = lib()
         ns = len(sources)
         nl = self.n_lambda
@@ -254,7 +256,7 @@ class Model:
                         None if e_self is None else _p(e_self),
                         None if e_emit_node is None else _p(e_emit_node),
                         None if e_lvl is None else _p(e_lvl), int(subtree),
-                        None if e_flux is None else _p(e_flux))
+                        None if e_flux is None else _p(e_flux), int(split_depth))
         if rc != 0:
             raise OracleError(L.om_error().decode())
         if img is not None or e_self is not None or e_lvl is not None or e_flux is not None:

@@ -390,6 +390,9 @@ typedef struct {
   double* e_esc;
   om_stats* st;
   int32_t split_n;          /* package splitting factor at subgrid entry (1: none) */
+  int32_t split_depth;      /* what a "grid" is: 0, every oct (a level change enters or leaves
+                               one); d > 0, levels below d are one grid with their ancestor at
+                               level d (d = 1: the root grid and one grid per refined root cell) */
   packet* stack;            /* split packages waiting to be followed */
   int64_t n_stack, cap_stack;
   const peel_ctx* peel;     /* NULL: no peel-off */
@@ -408,6 +411,13 @@ typedef struct {
      parent level, per refined node; NULL when off */
   double* e_flux;
 } tctx;
+
+/* The level of the grid holding a cell of level lev, in the reading of "grid" chosen for
+ * splitting (Sect. 2.3): entering a grid of a higher level splits, leaving for a lower one is
+ * rouletted. */
+static int grid_level(const tctx* c, int lev) {
+  return c->split_depth > 0 && lev > c->split_depth ? c->split_depth : lev;
+}
 
 /* Branch identifier of child c of branch b split at the package's crossing number n: the
  * MurmurHash3 32-bit finaliser (A. Appleby) of a mix of the three, limited to 30 bits so that
@@ -771,7 +781,8 @@ static int propagate(tctx* c, packet* p) {
     }
     if (p->lev < p->mlev) p->mlev = p->lev;
     p->crossings += 1;
-    if (c->split_n > 1 && p->lev > old_lev) {
+    const int g_old = grid_level(c, old_lev), g_new = grid_level(c, p->lev);
+    if (c->split_n > 1 && g_new > g_old) {
       /* entering a subgrid: split_n packages of equal weight; this one continues, the others
          (new branches) draw their own free paths and wait on the stack */
       const double wn = p->w / (double)c->split_n;
@@ -787,7 +798,7 @@ static int propagate(tctx* c, packet* p) {
       }
       p->w = wn;
       c->st->splits += 1;
-    } else if (c->split_n > 1 && p->lev < old_lev) {
+    } else if (c->split_n > 1 && g_new < g_old) {
       /* leaving a subgrid: survives with probability 1/split_n, weight multiplied by split_n */
       uint32_t ctr[4] = {c->pid, c->stream, p->crossings, (p->br << 2) | 3u}, x[4];
       philox10(c->key0, c->key1, ctr, x);
@@ -879,9 +890,11 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
              double rr_prob, int64_t max_events, int32_t per_lambda, int64_t pid_begin,
              int64_t pid_end, int32_t lam_sel, double* e_abs, double* e_esc, om_stats* stats,
              int64_t rec_stride, om_record* rec, int32_t split_n, const om_peel_opts* peel,
-             double* e_self, double* e_emit_node, double* e_lvl, int64_t sub_node, double* e_flux) {
+             double* e_self, double* e_emit_node, double* e_lvl, int64_t sub_node, double* e_flux,
+             int32_t split_depth) {
   if (m->nl < 1) { seterr("dust not set"); return -1; }
   if (split_n < 1 || split_n > 64) { seterr("split factor must be in [1, 64]"); return -1; }
+  if (split_depth < 0) { seterr("split depth must be >= 0"); return -1; }
   if (peel && (peel->n_dir < 1 || peel->n_dir > OM_MAXDIR || peel->npix < 1 || peel->tiles < 0 ||
                !peel->n_obs || !peel->image)) {
     seterr("bad peel-off arguments");
@@ -920,6 +933,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
   c.e_abs = NULL;
   c.e_abs_total = 0.0;
   c.split_n = split_n;
+  c.split_depth = split_depth;
   c.stack = NULL;
   c.n_stack = 0;
   c.cap_stack = 0;

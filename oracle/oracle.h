@@ -112,7 +112,7 @@ int om_trace(om_model* m, int32_t model_index, int32_t n_src, const int32_t* kin
              int64_t pid_begin, int64_t pid_end, int32_t lam_sel,
              double* e_abs, double* e_esc, om_stats* stats, int64_t rec_stride, om_record* rec,
              int32_t split_n, const om_peel_opts* peel, double* e_self, double* e_emit_node,
-             double* e_lvl, int64_t sub_node, double* e_flux);
+             double* e_lvl, int64_t sub_node, double* e_flux, int32_t split_depth);
 
 /* e_self, e_emit_node ([n_nodes], added to; NULL = off): for the accelerated Lambda iteration
  * (Sect. 3.1 Eq. 3, diagonal operator), the energy that dust-emission packets deposit in their

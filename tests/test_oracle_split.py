@@ -136,3 +136,97 @@ def test_split_reduces_noise_in_refined_cells():
         return float(np.sqrt(((es - ref) ** 2).mean() / (ref ** 2).mean()))
     n1, n4 = noise(1), noise(4)
     assert n4 < 0.85 * n1, (n1, n4)
+
+
+# ------------------------------------------------------------------------------------------
+# A coarser reading of "grid": all levels below d form one grid with their level-d ancestor
+# (d = 1: the root grid and one grid per refined root cell's subtree).
+# ------------------------------------------------------------------------------------------
+
+def staircase_tree():
+    """Three root cells along x; the middle one is refined, and of its children the one at
+    bx = 1, by = bz = 0 is refined again.  A beam along x at y = z = 0.3 passes root cell 0,
+    one level-1 cell, two level-2 cells and root cell 2."""
+    refined = [np.array([1], dtype=np.int64), np.array([1], dtype=np.int64)]
+    kids = [np.full(8, 1.0), np.full(8, 1.0)]
+    return gen.TreeDesc(3, 1, 1, 1.0, np.full(3, 1.0), refined, kids)
+
+
+def _beam(packets):
+    return [gen.Source(gen.SRC_BEAM, 0, pos=(0.3, 0.3, 0.3), dir=(1.0, 0.0, 0.0),
+                       power=np.array([1.0]), packets=packets)]
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_split_depth_crossing_counts_closed_form(n):
+    """Pure absorber, no events, so every history is the straight line through the staircase:
+    root 0, level 1, level 2, level 2, root 2 (5 cells per package as emitted).
+    * Every oct a grid (d = 0, and d = 2 >= the deepest level): the package splits entering
+      level 1 (N - 1 new packages, each entering 3 more cells), all N split again entering
+      level 2 (N (N - 1) new ones, 2 more cells each), and the N^2 are rouletted once leaving
+      for root 2 (one level change of the grid level, 2 -> 0).
+    * d = 1: one split entering the refined root cell (N - 1 new packages, 3 cells each); the
+      step from level 1 into level 2 stays inside that grid, so no second split, and one
+      roulette on leaving it."""
+    dust = gen.Dust(np.array([1.0]), np.array([0.3]), np.array([0.0]), np.array([0.0]))
+    o = oracle.Model(staircase_tree(), dust)
+    npk = 400
+    every = 5 + 3 * (n - 1) + 2 * n * (n - 1)
+    for depth, per, splits in ((0, every, n + 1), (2, every, n + 1), (5, every, n + 1),
+                               (1, 5 + 3 * (n - 1), 1)):
+        _, _, st, rec = o.trace(_beam(npk), seed=8, split_n=n, rec_stride=1, split_depth=depth)
+        assert st["crossings"] == npk * per, (depth, st["crossings"])
+        assert st["splits"] == npk * splits, (depth, st["splits"])
+        assert np.all(rec["crossings"] == 5)
+        assert energy_gap(st) < 1e-12
+
+
+def test_split_depth_at_or_below_the_deepest_level_is_the_oct_reading():
+    """With d at least the deepest level every level is its own grid: results identical, bit
+    for bit, to d = 0 (same splits, same roulette draws).  A random three-level tree in an
+    isotropic field; with d = 1 the level changes inside refined root cells no longer split."""
+    tree = gen.random_tree(np.random.default_rng(5), root=(4, 4, 4), max_level=3, p_refine=0.4)
+    assert tree.n_levels == 3
+    dust = gen.Dust(np.array([1.0]), np.array([0.5]), np.array([0.6]), np.array([0.2]))
+    o = oracle.Model(tree, dust)
+    src = [gen.Source(gen.SRC_BACKGROUND, 0, power=np.array([1.0]), packets=3000)]
+    a = o.trace(src, seed=21, split_n=4, rec_stride=5)
+    for deepest in (3, 7):
+        b = o.trace(src, seed=21, split_n=4, rec_stride=5, split_depth=deepest)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[3], b[3])
+        assert a[2]["splits"] == b[2]["splits"] > 0
+    c = o.trace(src, seed=21, split_n=4, rec_stride=5, split_depth=1)
+    assert 0 < c[2]["splits"] < a[2]["splits"]
+    assert energy_gap(c[2]) < 1e-12
+
+
+@pytest.mark.parametrize("n", [2, 4])
+def test_split_depth_one_unbiased_beam_closed_form(n):
+    """Pure absorber, beam through the staircase: the escaped energy has mean w0 exp(-tau)
+    and, with one split and one roulette per package, variance e^-2tau (1 - 1/N) w0^2."""
+    kappa = 0.3
+    dust = gen.Dust(np.array([1.0]), np.array([kappa]), np.array([0.0]), np.array([0.0]))
+    o = oracle.Model(staircase_tree(), dust)
+    npk = 20000
+    _, esc, st, _ = o.trace(_beam(npk), seed=13, split_n=n, split_depth=1)
+    w0 = st["e_emit"] / npk
+    tau = kappa * (3.0 - 0.3)
+    mean = esc[0] / npk
+    sd = w0 * math.exp(-tau) * math.sqrt((1.0 - 1.0 / n) / npk)
+    assert abs(mean - w0 * math.exp(-tau)) < 4.0 * sd
+    assert st["split_kills"] > 0
+
+
+def test_split_depth_one_unbiased_per_level():
+    """Scattering random tree in an isotropic field: with the coarser reading the absorbed energy
+    per level agrees in expectation with the unsplit estimator (8 seeds each, 4 standard
+    errors)."""
+    tree = gen.random_tree(np.random.default_rng(5), root=(4, 4, 4), max_level=3, p_refine=0.4)
+    dust = gen.Dust(np.array([1.0]), np.array([0.5]), np.array([0.6]), np.array([0.2]))
+    o = oracle.Model(tree, dust)
+    src = [gen.Source(gen.SRC_BACKGROUND, 0, power=np.array([1.0]), packets=4000)]
+    a = np.array([_per_level(o, o.trace(src, seed=50 + 100 * k)[0]) for k in range(8)])
+    b = np.array([_per_level(o, o.trace(src, seed=50 + 100 * k, split_n=4, split_depth=1)[0])
+                  for k in range(8)])
+    se = np.sqrt(a.var(axis=0, ddof=1) / len(a) + b.var(axis=0, ddof=1) / len(b))
+    assert np.all(np.abs(a.mean(axis=0) - b.mean(axis=0)) < 4.0 * se)
