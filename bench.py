@@ -128,37 +128,48 @@ def split_study(rt, gen, w, kw32, runs=20, packets=1_000_000, split_n=4, lam_um=
     out = {"wavelength_um": float(dust.lambda_um[i]), "packets": packets, "runs": runs,
            "split_n": split_n, "star_root_cell_units": star,
            "cells_per_level": [int(v) for v in n_cells.tolist()]}
+    # three estimators: no splitting, every oct a grid, and the coarser reading in which a
+    # refined root cell's whole subtree is one grid (split_depth 1)
+    variants = {"none": (1, 0), "oct": (split_n, 0), "root_subtree": (split_n, 1)}
     for name, src in cases.items():
-        js, ms, cr, sp = {1: [], split_n: []}, {1: [], split_n: []}, {1: [], split_n: []}, []
+        js = {v: [] for v in variants}
+        ms = {v: [] for v in variants}
+        cr = {v: [] for v in variants}
+        sp = {v: [] for v in variants}
         for r in range(runs):
-            for n in (1, split_n):
+            for v, (n, depth) in variants.items():
                 res = ctx.trace_packets(src, seed=w.seed + 7919 * r, precision=rt.FP32_LOCAL,
-                                        split_n=n, **kw)
-                js[n].append((res["e_abs_node"][use_idx] * inv_mass).float())
-                ms[n].append(res["stats"]["kernel_ms"])
-                cr[n].append(res["stats"]["crossings"])
-                if n > 1:
-                    sp.append(res["stats"]["splits"])
-        ref = torch.stack(js[1] + js[split_n]).double().mean(dim=0)
+                                        split_n=n, split_depth=depth, **kw)
+                js[v].append((res["e_abs_node"][use_idx] * inv_mass).float())
+                ms[v].append(res["stats"]["kernel_ms"])
+                cr[v].append(res["stats"]["crossings"])
+                sp[v].append(res["stats"]["splits"])
+        ref = torch.stack([j for v in variants for j in js[v]]).double().mean(dim=0)
         noise = {}
-        for n in (1, split_n):
+        for v in variants:
             acc = torch.zeros(n_lev, dtype=torch.float64, device=dev)
-            for j in js[n]:
+            for j in js[v]:
                 d2 = (j.double() - ref) ** 2
                 acc += torch.sqrt(torch.bincount(lv, weights=d2, minlength=n_lev) / n_cells)
-            noise[n] = (acc / len(js[n])).tolist()
+            noise[v] = (acc / len(js[v])).tolist()
         del js, ref
-        top = max(max(noise[1]), max(noise[split_n]))
-        t1, tn = float(np.mean(ms[1])), float(np.mean(ms[split_n]))
+        top = max(max(noise[v]) for v in variants)
+        t = {v: float(np.mean(ms[v])) for v in variants}
         out[name] = {
-            "noise_per_level_split": [v / top for v in noise[split_n]],
-            "noise_per_level_no_split": [v / top for v in noise[1]],
-            "ms_per_run_split": tn, "ms_per_run_no_split": t1,
-            "crossings_per_run_split": float(np.mean(cr[split_n])),
-            "crossings_per_run_no_split": float(np.mean(cr[1])),
-            "splits_per_run": float(np.mean(sp)),
+            "noise_per_level_split": [x / top for x in noise["oct"]],
+            "noise_per_level_no_split": [x / top for x in noise["none"]],
+            "noise_per_level_split_root_subtree": [x / top for x in noise["root_subtree"]],
+            "ms_per_run_split": t["oct"], "ms_per_run_no_split": t["none"],
+            "ms_per_run_split_root_subtree": t["root_subtree"],
+            "crossings_per_run_split": float(np.mean(cr["oct"])),
+            "crossings_per_run_no_split": float(np.mean(cr["none"])),
+            "crossings_per_run_split_root_subtree": float(np.mean(cr["root_subtree"])),
+            "splits_per_run": float(np.mean(sp["oct"])),
+            "splits_per_run_root_subtree": float(np.mean(sp["root_subtree"])),
             # packets needed for equal noise scale as noise^2: speed-up at the deepest level
-            "gain_deepest_level": (noise[1][-1] / noise[split_n][-1]) ** 2 * t1 / tn,
+            "gain_deepest_level": (noise["none"][-1] / noise["oct"][-1]) ** 2 * t["none"] / t["oct"],
+            "gain_deepest_level_root_subtree":
+                (noise["none"][-1] / noise["root_subtree"][-1]) ** 2 * t["none"] / t["root_subtree"],
         }
     ctx.close()
     return out

@@ -180,6 +180,11 @@ typedef struct {
                                package as emitted (branch 0).  A split that would overrun the
                                sweep's queue room is skipped (counted in split_skips); either
                                choice leaves every expectation unchanged */
+  int32_t split_depth;      /* with split_n > 1, what a "grid" is (Sect. 2.3): 0 (default) every
+                               oct, so every change of level splits or roulettes; d > 0 all
+                               levels below d belong to the grid of their level-d ancestor (d = 1:
+                               the root grid and one grid per refined root cell), and only a
+                               change of min(level, d) splits or roulettes.  Must be >= 0 */
 } rt_trace_opts;
 
 typedef struct {

@@ -62,7 +62,7 @@ class TraceOpts(C.Structure):
                 ("refill_threshold", C.c_float), ("schedule", C.c_int32),
                 ("chunk_packets", C.c_int32), ("tail_park", C.c_int32), ("batch_packets", C.c_int64),
                 ("rec_stride", C.c_int64), ("records", C.c_void_p), ("sweep_graph", C.c_int32),
-                ("split_n", C.c_int32)]
+                ("split_n", C.c_int32), ("split_depth", C.c_int32)]
 
 
 class PeelOpts(C.Structure):
@@ -256,10 +256,11 @@ class Context:
                       block_size: int = 0, blocks_per_cu: int = 0, refill_threshold: float = 0.0,
                       rec_stride: int = 0, per_lambda: bool = False, schedule: int = SCHED_REGIONS,
                       chunk_packets: int = 0, batch_packets: int = 0, tail_park: int = 0,
-                      sweep_graph: int = 0, split_n: int = 1):
+                      sweep_graph: int = 0, split_n: int = 1, split_depth: int = 0):
         """Trace the packets of ``sources`` (objects with kind, model, pos, dir, power,
         packets).  ``split_n`` > 1 turns on package splitting at subgrid entry with the
-        roulette at subgrid exit (region schedule).  Returns a dict of device tensors and the
+        roulette at subgrid exit (region schedule); ``split_depth`` > 0 makes all levels below
+        it one grid with their ancestor at that level (0: every oct is a grid).  Returns a dict of device tensors and the
         statistics."""
         torch = _torch()
         n = len(sources)
@@ -279,7 +280,7 @@ class Context:
         opts = TraceOpts(seed, iteration, precision, rr_threshold, rr_prob, max_events, block_size,
                          blocks_per_cu, refill_threshold, schedule, chunk_packets, tail_park,
                          batch_packets, rec_stride, None if rec is None else rec.data_ptr(),
-                         sweep_graph, split_n)
+                         sweep_graph, split_n, split_depth)
         st = TraceStats()
         self._check(lib().rt_trace_packets(self.h, n, arr, C.byref(opts), _ptr(e_node),
                                            _ptr(e_lam), _ptr(e_esc), C.byref(st)))
@@ -295,7 +296,7 @@ class Context:
                  rr_threshold: float = 0.0, rr_prob: float = 0.0, max_events: int = 0,
                  block_size: int = 0, blocks_per_cu: int = 0, refill_threshold: float = 0.0,
                  schedule: int = SCHED_REGIONS, chunk_packets: int = 0, batch_packets: int = 0,
-                 tail_park: int = 0, split_n: int = 1):
+                 tail_park: int = 0, split_n: int = 1, split_depth: int = 0):
         """Peel-off images of the scattered light toward the directions ``n_obs`` ([n_dir, 3]):
         a device tensor [n_dir, n_lambda, npix, npix] and the statistics."""
         torch = _torch()
@@ -307,7 +308,7 @@ class Context:
         po = PeelOpts(len(nv), npix, _ptr(nv).value, width, tiles, 0, event_buffer, img.data_ptr())
         opts = TraceOpts(seed, iteration, precision, rr_threshold, rr_prob, max_events, block_size,
                          blocks_per_cu, refill_threshold, schedule, chunk_packets, tail_park,
-                         batch_packets, 0, None, 0, split_n)
+                         batch_packets, 0, None, 0, split_n, split_depth)
         st = TraceStats()
         self._check(lib().rt_peel_map(self.h, n, arr, C.byref(opts), C.byref(po), C.byref(st)))
         return img, st.as_dict()
@@ -373,7 +374,7 @@ class Context:
                          kw.get("refill_threshold", 0.0), kw.get("schedule", SCHED_REGIONS),
                          kw.get("chunk_packets", 0), kw.get("tail_park", 0),
                          kw.get("batch_packets", 0), 0, None, kw.get("sweep_graph", 0),
-                         kw.get("split_n", 0))
+                         kw.get("split_n", 0), kw.get("split_depth", 0))
         t = torch.empty(self.models[model], dtype=torch.float64, device=self.tdev)
         nd = C.c_int32()
         crit = np.zeros(max(n_max, 1))

@@ -18,8 +18,9 @@ using namespace rtd;
 namespace {
 
 // lane states; B_SPLIT / B_ROUL: just crossed into a deeper / shallower leaf with package
-// splitting on (Sect. 2.3), waiting for the split or the exit roulette
-enum : int { B_EMPTY = 0, B_CROSS = 1, B_EVENT = 2, B_DONE = 3, B_EXIT = 4, B_SPLIT = 5, B_ROUL = 6 };
+// splitting on (Sect. 2.3), waiting for the split or the exit roulette; B_FAR: at a face whose
+// neighbour is not in the leaf's own brick or oct, waiting for the phase that walks the tree
+enum : int { B_EMPTY = 0, B_CROSS = 1, B_EVENT = 2, B_DONE = 3, B_EXIT = 4, B_SPLIT = 5, B_ROUL = 6, B_FAR = 7 };
 
 constexpr uint32_t kMaxCrossings = 1u << 30;
 constexpr int kRecoverLevel = 2;
@@ -127,6 +128,36 @@ __device__ __forceinline__ void emit_one(const BlkParams& b, uint64_t gid, uint6
   b.u_key[idx] = key;
 }
 
+// Entering a neighbour at the packet's own level (word r of cell cur at level l): coordinate
+// ax goes to the near face; while the cell is refined, step into the child on that face and,
+// on the other axes, into the half holding the packet (the midpoint rule).
+template <typename WF>
+__device__ __forceinline__ void descend(WF word_of, int ax, int sg, float& x0, float& x1, float& x2,
+                                        int32_t& I0, int32_t& I1, int32_t& I2, int32_t& cur, int& l,
+                                        int32_t& r) {
+  const float nearf = sg > 0 ? 0.0f : 1.0f;
+  x0 = ax == 0 ? nearf : x0;
+  x1 = ax == 1 ? nearf : x1;
+  x2 = ax == 2 ? nearf : x2;
+  int32_t c = child_of(r);
+  while (c >= 0) {
+    const int b0 = ax == 0 ? (sg > 0 ? 0 : 1) : (x0 >= 0.5f ? 1 : 0);
+    const int b1 = ax == 1 ? (sg > 0 ? 0 : 1) : (x1 >= 0.5f ? 1 : 0);
+    const int b2 = ax == 2 ? (sg > 0 ? 0 : 1) : (x2 >= 0.5f ? 1 : 0);
+    x0 = 2.0f * x0 - (float)b0;
+    x1 = 2.0f * x1 - (float)b1;
+    x2 = 2.0f * x2 - (float)b2;
+    I0 = 2 * I0 + b0;
+    I1 = 2 * I1 + b1;
+    I2 = 2 * I2 + b2;
+    cur = c + (b0 | (b1 << 1) | (b2 << 2));
+    ++l;
+    r = word_of(cur);
+    c = child_of(r);
+  }
+}
+
+
 // Land in the neighbour after a face crossing: from cell `cur` at level l (an ancestor-level
 // cell containing the neighbour J of the old cell Io at level L), descend along J's bits; a
 // coarser landing cell rescales the lateral local coordinates (recovered in FP64 from the
@@ -165,25 +196,7 @@ __device__ __forceinline__ void land(WF word_of, int ax, int sg, int L, int32_t 
       if (ax != 2) x2 = clamp01((float)(fma(t, (double)d2, O2) * inv - (double)I2));
     }
   } else {
-    x0 = ax == 0 ? nearf : x0;
-    x1 = ax == 1 ? nearf : x1;
-    x2 = ax == 2 ? nearf : x2;
-    int32_t c = child_of(r);
-    while (c >= 0) {
-      const int b0 = ax == 0 ? (sg > 0 ? 0 : 1) : (x0 >= 0.5f ? 1 : 0);
-      const int b1 = ax == 1 ? (sg > 0 ? 0 : 1) : (x1 >= 0.5f ? 1 : 0);
-      const int b2 = ax == 2 ? (sg > 0 ? 0 : 1) : (x2 >= 0.5f ? 1 : 0);
-      x0 = 2.0f * x0 - (float)b0;
-      x1 = 2.0f * x1 - (float)b1;
-      x2 = 2.0f * x2 - (float)b2;
-      I0 = 2 * I0 + b0;
-      I1 = 2 * I1 + b1;
-      I2 = 2 * I2 + b2;
-      cur = c + (b0 | (b1 << 1) | (b2 << 2));
-      ++l;
-      r = word_of(cur);
-      c = child_of(r);
-    }
+    descend(word_of, ax, sg, x0, x1, x2, I0, I1, I2, cur, l, r);
   }
   node = cur;
   lev = l;
@@ -211,7 +224,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   const TraceParams& p = b.t;
   const float rr_thr = (float)p.rr_thr, rr_p = (float)p.rr_p;
   const float rr_gain = rr_p > 0.0f ? 1.0f / (1.0f - rr_p) : 1.0f;
-  const int bx = R.hi[0] - R.lo[0], by = R.hi[1] - R.lo[1];
+  const int bx = R.hi[0] - R.lo[0], by = R.hi[1] - R.lo[1], bxy = bx * by;
   double* __restrict__ gacc64 = b.accb64 + (int64_t)it.slot * b.accb_stride + R.gbase;
   const int32_t* __restrict__ gword = b.rword + R.gbase;
   const int32_t* __restrict__ gup = b.rup + (R.gbase >> 3);
@@ -242,6 +255,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   bool dust_lane = false;      // the packet comes from dust emission
   constexpr bool self_on = ALI;
   constexpr bool splitting = SPLIT;
+  // the grid of a cell (Sect. 2.3) is that of its ancestor at level sdep when it is deeper
+  const int sdep = SPLIT ? p.split_depth : 0;
   float ks = 0.f, ka = 0.f, g = 0.f;  // scattering / absorption opacity per root-cell length per unit density
   int esc_slot = 0;
   int32_t xax = 0, xsg = 0;
@@ -249,6 +264,80 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   bool pool_done = false;      // this item's packets are all taken (wave-uniform)
   int tail_it = 0;             // crossing rounds since then (wave-uniform)
   const uint32_t own_key = (uint32_t)it.slot * (uint32_t)b.n_regions + (uint32_t)it.region;
+
+  // A crossing whose neighbour is not in the leaf's own brick or oct: ascend to the common
+  // ancestor, leave the region or the model, or land in the neighbour (subiterations send every
+  // crossing here: it tests the subtree and tallies the flow between levels).
+  auto far_cross = [&](const int ax, const int sg) {
+    const int32_t Ia = sel3(ax, I0, I1, I2);
+    const int32_t Ja = Ia + sg;
+    const int L = lev;
+    // a subiteration follows packages only inside its subtree: crossing out of it ends
+    // them as escaped (the test on the neighbour at the old level is exact, since the
+    // subtree root is refined and the packet is below it)
+    const bool sub_out = LVL && p.sub_lev >= 0 &&
+                         !in_subtree(p.sub_lev, p.sub_I, L, ax == 0 ? Ja : I0, ax == 1 ? Ja : I1,
+                                     ax == 2 ? Ja : I2);
+    // automatic iteration: the weight leaving each refined ancestor's subtree (only when the
+    // crossing leaves the leaf's oct), walked up the tree's global parent links
+    if (LVL && p.flux_acc && (Ja >> 1) != (Ia >> 1) && L > 0) {
+      const int32_t c = b.rcanon[R.gbase + node];
+      const int32_t inode = md.base + (c < md.n_root ? c : c + (md.n_root_pad - md.n_root));
+      flux_exits(md, p.up, p.flux_acc, inode, L, Ia, Ja, Ja < 0 || Ja >= (D.na(ax) << L), (double)w);
+    }
+    if (Ja < 0 || Ja >= (D.na(ax) << L) || sub_out) {
+      // escape through the root boundary (or out of the subtree)
+      // a region belongs to one model: its escapes are tallied per wavelength in LDS
+      if (esc_lds) atomicAdd(&s_esc[esc_slot - (int)md.lam_base], (double)w);
+      else unsafeAtomicAdd(p.esc + esc_slot, (double)w);
+      if (p.rec_stride > 0 && br == 0 && (pid % (uint32_t)p.rec_stride) == 0) {
+        const JobDev& J = p.jobs[job];
+        rt_record rc{0u, ncross, ev, 0u, -1, canon_of(md, birth), (double)w};
+        p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
+      }
+      c_cross += ncross;
+      state = B_EMPTY;
+    } else {
+      int32_t cur = node;
+      int l = L;
+      while (l > R.rl && ((Ja >> (L - l + 1)) != (Ia >> (L - l + 1)))) {
+        cur = up_of(cur);
+        --l;
+      }
+      const int32_t J0 = ax == 0 ? Ja : I0, J1 = ax == 1 ? Ja : I1, J2 = ax == 2 ? Ja : I2;
+      bool leave = false;
+      if (l == R.rl) {
+        const int sh = L - R.rl;
+        const int32_t R0 = J0 >> sh, R1 = J1 >> sh, R2 = J2 >> sh;
+        if (R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] || R1 >= R.hi[1] || R2 < R.lo[2] ||
+            R2 >= R.hi[2]) {
+          // the neighbour lies in another region: its region is looked up when the record
+          // is written, outside the crossing loop
+          leave = true;
+          xax = ax;
+          xsg = sg;
+          state = B_EXIT;
+        } else {
+          cur = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
+        }
+      } else {
+        cur += sg > 0 ? (1 << ax) : -(1 << ax);
+      }
+      if (!leave) {
+        int32_t raw;
+        land(word_of, ax, sg, L, I0, I1, I2, J0, J1, J2, cur, l, x0, x1, x2, O0, O1, O2, d0, d1, d2,
+             node, lev, I0, I1, I2, raw);
+        rho = __int_as_float(raw);
+        if (LVL && lev < mlev) mlev = lev;
+        if (++ncross >= kMaxCrossings) {
+          ev = (uint32_t)p.max_events;
+          state = B_EVENT;
+        } else if (splitting && min(lev, sdep) != min(L, sdep)) {
+          state = lev > L ? B_SPLIT : B_ROUL;
+        }
+      }
+    }
+  };
 
   for (;;) {
     // ---------------- refill from this item's queue ----------------
@@ -358,7 +447,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           rho = __int_as_float(raw);
           if (LVL && lev < mlev) mlev = lev;
           state = misplaced ? B_EMPTY : B_CROSS;
-          if (!misplaced && crossing && splitting && lev != L) state = lev > L ? B_SPLIT : B_ROUL;
+          if (!misplaced && crossing && splitting && min(lev, sdep) != min(L, sdep))
+            state = lev > L ? B_SPLIT : B_ROUL;
         }
       }
     }
@@ -398,82 +488,54 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         x0 = clamp01(fmaf(s, d0, x0));
         x1 = clamp01(fmaf(s, d1, x1));
         x2 = clamp01(fmaf(s, d2, x2));
+        const int sg = sel3(ax, d0, d1, d2) > 0.0f ? 1 : -1;
+        const int32_t Ia = sel3(ax, I0, I1, I2);
+        const int32_t Ja = Ia + sg;
+        // the common crossing: into the neighbour in the same brick (at the region's brick level)
+        // or in the same oct (below it).  Its local id is one stride away, so no tree walk and no
+        // brick lookup; a refined neighbour is descended as landing does.
+        const bool at_brick = lev == R.rl;
+        const bool near_move =
+            !LVL && (at_brick ? (Ja >= sel3(ax, R.lo[0], R.lo[1], R.lo[2]) && Ja < sel3(ax, R.hi[0], R.hi[1], R.hi[2]))
+                              : (Ja >> 1) == (Ia >> 1));
         if (event) {
           state = B_EVENT;
-        } else {
-          const int sg = sel3(ax, d0, d1, d2) > 0.0f ? 1 : -1;
+        } else if (near_move) {
           const int L = lev;
-          const int32_t Ia = sel3(ax, I0, I1, I2);
-          const int32_t Ja = Ia + sg;
-          // a subiteration follows packages only inside its subtree: crossing out of it ends
-          // them as escaped (the test on the neighbour at the old level is exact, since the
-          // subtree root is refined and the packet is below it)
-          const bool sub_out = LVL && p.sub_lev >= 0 &&
-                               !in_subtree(p.sub_lev, p.sub_I, L, ax == 0 ? Ja : I0, ax == 1 ? Ja : I1,
-                                           ax == 2 ? Ja : I2);
-          // automatic iteration: the weight leaving each refined ancestor's subtree (only when the
-          // crossing leaves the leaf's oct), walked up the tree's global parent links
-          if (LVL && p.flux_acc && (Ja >> 1) != (Ia >> 1) && L > 0) {
-            const int32_t c = b.rcanon[R.gbase + node];
-            const int32_t inode = md.base + (c < md.n_root ? c : c + (md.n_root_pad - md.n_root));
-            flux_exits(md, p.up, p.flux_acc, inode, L, Ia, Ja, Ja < 0 || Ja >= (D.na(ax) << L), (double)w);
+          const int32_t stride = at_brick ? (ax == 0 ? 1 : (ax == 1 ? bx : bxy)) : (1 << ax);
+          I0 = ax == 0 ? Ja : I0;
+          I1 = ax == 1 ? Ja : I1;
+          I2 = ax == 2 ? Ja : I2;
+          node += sg > 0 ? stride : -stride;
+          int32_t raw = word_of(node);
+          descend(word_of, ax, sg, x0, x1, x2, I0, I1, I2, node, lev, raw);
+          rho = __int_as_float(raw);
+          if (++ncross >= kMaxCrossings) {
+            ev = (uint32_t)p.max_events;
+            state = B_EVENT;
+          } else if (splitting && min(lev, sdep) != min(L, sdep)) {
+            state = B_SPLIT;
           }
-          if (Ja < 0 || Ja >= (D.na(ax) << L) || sub_out) {
-            // escape through the root boundary (or out of the subtree)
-            // a region belongs to one model: its escapes are tallied per wavelength in LDS
-            if (esc_lds) atomicAdd(&s_esc[esc_slot - (int)md.lam_base], (double)w);
-            else unsafeAtomicAdd(p.esc + esc_slot, (double)w);
-            if (p.rec_stride > 0 && br == 0 && (pid % (uint32_t)p.rec_stride) == 0) {
-              const JobDev& J = p.jobs[job];
-              rt_record rc{0u, ncross, ev, 0u, -1, canon_of(md, birth), (double)w};
-              p.rec[J.rec_base + pid / (uint32_t)p.rec_stride] = rc;
-            }
-            c_cross += ncross;
-            state = B_EMPTY;
-          } else {
-            int32_t cur = node;
-            int l = L;
-            while (l > R.rl && ((Ja >> (L - l + 1)) != (Ia >> (L - l + 1)))) {
-              cur = up_of(cur);
-              --l;
-            }
-            const int32_t J0 = ax == 0 ? Ja : I0, J1 = ax == 1 ? Ja : I1, J2 = ax == 2 ? Ja : I2;
-            bool leave = false;
-            if (l == R.rl) {
-              const int sh = L - R.rl;
-              const int32_t R0 = J0 >> sh, R1 = J1 >> sh, R2 = J2 >> sh;
-              if (R0 < R.lo[0] || R0 >= R.hi[0] || R1 < R.lo[1] || R1 >= R.hi[1] || R2 < R.lo[2] ||
-                  R2 >= R.hi[2]) {
-                // the neighbour lies in another region: its region is looked up when the record
-                // is written, outside the crossing loop
-                leave = true;
-                xax = ax;
-                xsg = sg;
-                state = B_EXIT;
-              } else {
-                cur = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
-              }
-            } else {
-              cur += sg > 0 ? (1 << ax) : -(1 << ax);
-            }
-            if (!leave) {
-              int32_t raw;
-              land(word_of, ax, sg, L, I0, I1, I2, J0, J1, J2, cur, l, x0, x1, x2, O0, O1, O2, d0, d1, d2,
-                   node, lev, I0, I1, I2, raw);
-              rho = __int_as_float(raw);
-              if (LVL && lev < mlev) mlev = lev;
-              if (++ncross >= kMaxCrossings) {
-                ev = (uint32_t)p.max_events;
-                state = B_EVENT;
-              } else if (splitting && lev != L) {
-                state = lev > L ? B_SPLIT : B_ROUL;
-              }
-            }
-          }
+        } else if (LVL) {
+          far_cross(ax, sg);
+        } else {
+          xax = ax;
+          xsg = sg;
+          // leaving the brick at its level into the model: no tree walk, the record is written
+          // in the exit phase; every other crossing waits for the far-crossing phase
+          state = lev == R.rl && Ja >= 0 && Ja < (D.na(ax) << lev) ? B_EXIT : B_FAR;
         }
       }
       if (pool_done && ++tail_it >= b.tail_park) break;
       if (__popcll(__ballot(state == B_CROSS)) < want) break;
+    }
+
+    // ---------------- crossings that walk the tree, serviced together ----------------
+    if (!LVL && __ballot(state == B_FAR)) {
+      if (state == B_FAR) {
+        state = B_CROSS;
+        far_cross(xax, xsg);
+      }
     }
 
     // ---------------- packets leaving the region: append to the next queue ----------------

@@ -104,6 +104,8 @@ struct TraceParams {
   int64_t max_events;
   float refill_thr;
   int32_t split_n;           // package splitting factor at subgrid entry (1: none)
+  int32_t split_depth;       // levels past this one belong to the grid of their ancestor at it
+                             // (a large value: every oct is a grid)
   // dust emission tables
   const uint64_t* cdf_qpre;
   const uint64_t* cdf_q;

@@ -1008,6 +1008,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   if (o->chunk_packets < 0 || o->batch_packets < 0)
     return fail(ctx, RT_EINVAL, "chunk_packets and batch_packets must be >= 0");
   if (o->split_n < 0 || o->split_n > 64) return fail(ctx, RT_EINVAL, "split_n must be in [0, 64]");
+  if (o->split_depth < 0) return fail(ctx, RT_EINVAL, "split_depth must be >= 0");
   if (o->split_n > 1 && !region_sched)
     return fail(ctx, RT_EINVAL, "package splitting needs the FP32-local region schedule");
   if (o->rec_stride < 0 || (o->rec_stride > 0 && !o->records))
@@ -1159,6 +1160,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   p.max_events = o->max_events > 0 ? o->max_events : 1000000;
   p.refill_thr = o->refill_threshold > 0.0f ? o->refill_threshold : (region_sched ? 0.6f : 0.5f);
   p.split_n = o->split_n > 1 ? o->split_n : 1;
+  p.split_depth = o->split_depth > 0 ? o->split_depth : 127;
   p.cdf_qpre = ctx->cdf_qpre.as<uint64_t>();
   p.cdf_q = ctx->cdf_q.as<uint64_t>();
   p.cdf_lum = ctx->cdf_lum.as<double>();

@@ -50,6 +50,16 @@ def _box_case():
     return tree, dust, src, 17
 
 
+def _rand_case():
+    """Random three-level tree (level changes inside refined root cells, for the coarser reading
+    of "grid"), scattering dust, isotropic field and a point source."""
+    tree = gen.random_tree(np.random.default_rng(5), root=(4, 4, 4), max_level=3, p_refine=0.4)
+    dust = gen.Dust(np.array([1.0]), np.array([0.5]), np.array([0.6]), np.array([0.2]))
+    src = [gen.Source(gen.SRC_BACKGROUND, 0, power=np.array([1.0]), packets=20000),
+           gen.Source(gen.SRC_POINT, 0, pos=(1.4, 2.6, 2.5), power=np.array([3.0]), packets=20000)]
+    return tree, dust, src, 23
+
+
 def _c1_case():
     w = gen.c1("A", packets=40000)
     return w.trees[0], w.dusts[0], w.sources, w.seed
@@ -77,10 +87,14 @@ def test_split_factor_one_changes_nothing(torch):
         assert np.array_equal(a["records"][f], b["records"][f]), f
 
 
-@pytest.mark.parametrize("case,n,per_cu", [("c1", 2, 0), ("c1", 4, 16), ("box", 4, 0), ("box", 8, 8)])
-def test_split_parity_against_oracle(torch, case, n, per_cu):
-    tree, dust, src, seed = _c1_case() if case == "c1" else _box_case()
-    kw = dict(rr_threshold=1e-2, rr_prob=0.8)
+@pytest.mark.parametrize("case,n,per_cu,depth", [("c1", 2, 0, 0), ("c1", 4, 16, 0), ("box", 4, 0, 0),
+                                                ("box", 8, 8, 0), ("rand", 4, 0, 0), ("rand", 4, 0, 1),
+                                                ("rand", 2, 8, 2)])
+def test_split_parity_against_oracle(torch, case, n, per_cu, depth):
+    """depth > 0: the coarser readings of "grid" (levels below depth one grid with their
+    ancestor at depth)."""
+    tree, dust, src, seed = {"c1": _c1_case, "box": _box_case, "rand": _rand_case}[case]()
+    kw = dict(rr_threshold=1e-2, rr_prob=0.8, split_depth=depth)
     ora = oracle.Model(tree, dust)
     eo, _, sto, reco = ora.trace(src, seed=seed, rec_stride=1, split_n=n, **kw)
     # a few thousand births per sweep keep the split-off packages within the sweep's room
