@@ -890,7 +890,11 @@ rt_status region_launch_setup(rt_ctx* ctx, const rt_trace_opts* o, const TracePa
   const int n_regions = (int)ctx->h_regions.size();
   const int64_t n_keys = (int64_t)key_slots * n_regions;
   if (n_keys > (int64_t(1) << 28)) return fail(ctx, RT_EINVAL, "too many (wavelength, region) keys");
-  const int64_t capq = std::min<int64_t>(int64_t(1) << 25, std::max<int64_t>((int64_t)start, 4096));
+  // up to 2^27 records per buffer (13 GB of 96-byte records, 2^26 with splitting, whose buffers
+  // hold two capacities): a trace of 1e9 packets keeps ~1e8 in flight, and a smaller capacity
+  // would cut each sweep's births short and multiply the sweeps
+  const int64_t cap_max = int64_t(1) << (p.split_n > 1 ? 26 : 27);
+  const int64_t capq = std::min<int64_t>(cap_max, std::max<int64_t>((int64_t)start, 4096));
   const int64_t batch = std::min<int64_t>(o->batch_packets > 0 ? o->batch_packets : int64_t(1) << 23, capq);
   const int32_t chunk = o->chunk_packets > 0 ? o->chunk_packets : 16 * bs;
   // records per queue buffer: emission keeps each sweep's input + births within capq; with

@@ -97,9 +97,10 @@ def test_split_parity_against_oracle(torch, case, n, per_cu, depth):
     kw = dict(rr_threshold=1e-2, rr_prob=0.8, split_depth=depth)
     ora = oracle.Model(tree, dust)
     eo, _, sto, reco = ora.trace(src, seed=seed, rec_stride=1, split_n=n, **kw)
-    # a few thousand births per sweep keep the split-off packages within the sweep's room
+    # a few thousand births per sweep keep the split-off packages within the sweep's room (the
+    # random tree, one region, splits about 13 times per emitted packet with every oct a grid)
     r = _run(torch, tree, dust, src, seed, rec_stride=1, split_n=n, blocks_per_cu=per_cu,
-             batch_packets=4096, **kw)
+             batch_packets=1024 if case == "rand" else 4096, **kw)
     st = r["stats"]
     assert st["split_skips"] == 0
     assert sto["splits"] > 0 and sto["split_kills"] > 0
