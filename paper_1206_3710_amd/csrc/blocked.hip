@@ -829,13 +829,35 @@ __global__ __launch_bounds__(BS) void blk_pass_kernel(const BlkParams b) {
     const int nloc = min(R.n, cap);
     const int nup = (nloc + 7) >> 3;
     const bool esc_lds = md.nl <= kEscLds;
-    for (int i = tid; i < nloc; i += BS) {
-      s_word[i] = b.rword[R.gbase + i];
-      s_acc[i] = 0.0f;
+    // the region's words and parent links: U loads per thread are issued before their LDS
+    // stores, so a region costs a few global latencies instead of one per element
+    {
+      constexpr int U = 8;
+      const int32_t* __restrict__ gw = b.rword + R.gbase;
+      const int32_t* __restrict__ gu = b.rup + (R.gbase >> 3);
+      for (int i0 = tid; i0 < nloc; i0 += BS * U) {
+        int32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = i0 + u * BS < nloc ? gw[i0 + u * BS] : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (i0 + u * BS < nloc) {
+            s_word[i0 + u * BS] = v[u];
+            s_acc[i0 + u * BS] = 0.0f;
+          }
+        }
+      }
+      for (int i0 = tid; i0 < nup; i0 += BS * U) {
+        int32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = i0 + u * BS < nup ? gu[i0 + u * BS] : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (i0 + u * BS < nup) s_up[i0 + u * BS] = v[u];
+      }
     }
     if (esc_lds)
       for (int i = tid; i < md.nl; i += BS) s_esc[i] = 0.0;
-    for (int i = tid; i < nup; i += BS) s_up[i] = b.rup[(R.gbase >> 3) + i];
     if (tid == 0) s_next = 0;
     __syncthreads();
     if (R.n <= cap)

@@ -325,7 +325,7 @@ hipError_t launch_dust_quant(int64_t n_leaves, const double* lum,
                              const unsigned long long* lmax_bits, uint64_t* q, hipStream_t s);
 // Wavelengths per pass of the map kernel (registers per ray): FP64 and FP32 transfer.
 constexpr int kRenderPassF64 = 16;
-constexpr int kRenderPassF32 = 32;
+constexpr int kRenderPassF32 = 128;
 hipError_t launch_render(bool f32, const ModelDev* models, int model, const int32_t* child,
                          const int32_t* up, const double* rho64, const double* t_node,
                          const LamConst* lc, const int32_t* lam_idx, int n_sel,

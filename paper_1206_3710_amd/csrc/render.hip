@@ -1,6 +1,6 @@
 // Surface-brightness maps through the tree (paper Sect. 4.1): one ray per pixel, orthographic
 // view, I <- I exp(-dtau) + (1 - a) B(T) (1 - exp(-dtau)) cell by cell.  Up to NS wavelengths
-// are carried in registers per pass (16 in FP64, 32 in FP32); the host splits longer selections
+// are carried in registers per pass (16 in FP64, 128 in FP32); the host splits longer selections
 // into passes, each of which walks the ray again.
 // Built with -ffp-contract=off like the FP64 trace.
 //
@@ -16,6 +16,7 @@ using namespace rtd;
 namespace {
 
 constexpr double kK = 1.380649e-16;
+constexpr int kG = 8;  // wavelengths per group of the FP32 transfer
 
 // e^x - 1 for x >= 0 in FP32: below 1/8 the series to x^5 (truncation below x^5 / 6! =
 // 4.2e-8 relative), above it the hardware base-2 exponential (inf for large x).
@@ -31,7 +32,7 @@ __device__ __forceinline__ float expm1_pos(float x) {
 }
 
 template <int NS, bool F32>
-__global__ __launch_bounds__(256) void render_kernel(
+__global__ __launch_bounds__(256, NS > 32 ? 2 : 1) void render_kernel(
     const ModelDev* __restrict__ models, int model, const int32_t* __restrict__ child,
     const int32_t* __restrict__ up, const double* __restrict__ rho64,
     const double* __restrict__ t_node, const LamConst* __restrict__ lc,
@@ -42,13 +43,16 @@ __global__ __launch_bounds__(256) void render_kernel(
   const ChildPlain ch{child};
   // FP32 form: per-wavelength constants kappa_ext * cell size, (1 - albedo) 2 h nu^3 / c^2,
   // h nu / k
+  // Wavelengths past n_sel (up to the next multiple of kG) are padded with kappa = 0 and no
+  // source, which leaves their intensity at 0 and is never written out.
   __shared__ float s_kc[NS], s_ap[NS], s_hk[NS];
   if (F32) {
-    if (threadIdx.x < NS && (int)threadIdx.x < n_sel) {
-      const LamConst& L = lc[lam_idx[threadIdx.x]];
-      s_kc[threadIdx.x] = (float)(L.kext * m.cell_cm);
-      s_ap[threadIdx.x] = (float)((1.0 - L.alb) * L.pre);
-      s_hk[threadIdx.x] = (float)(L.hnu / kK);
+    if (threadIdx.x < NS) {
+      const bool real = (int)threadIdx.x < n_sel;
+      const LamConst& L = lc[lam_idx[real ? threadIdx.x : 0]];
+      s_kc[threadIdx.x] = real ? (float)(L.kext * m.cell_cm) : 0.0f;
+      s_ap[threadIdx.x] = real ? (float)((1.0 - L.alb) * L.pre) : 0.0f;
+      s_hk[threadIdx.x] = real ? (float)(L.hnu / kK) : 1.0f;
     }
     __syncthreads();
   }
@@ -103,6 +107,10 @@ __global__ __launch_bounds__(256) void render_kernel(
       int32_t node = locate_face(D, P, ax, nax > 0.0 ? 1 : -1, lev, Ic, ch);
       ncross = 1;
       for (;;) {
+        // past 32 wavelengths the per-wavelength constants are read from LDS at every cell (a
+        // compiler barrier keeps them from being hoisted into registers, which hold the
+        // intensities)
+        if (F32 && NS > 32) asm volatile("" ::: "memory");
         const double rho = rho64[node];
         const double h = ldexp(1.0, -lev);
         double texit = INFINITY, face_ax = 0.0;
@@ -127,19 +135,24 @@ __global__ __launch_bounds__(256) void render_kernel(
           const float f = (float)(rho * s);
           const bool warm = tc > 0.0f;
           const float inv_t = warm ? __builtin_amdgcn_rcpf(tc) : 0.0f;
+          // groups of kG wavelengths: a group past the selection is skipped with a scalar
+          // branch, the padded ones inside the last group are computed
 #pragma unroll
-          for (int q = 0; q < NS; ++q) {
-            if (q < n_sel) {
-              const float dtau = s_kc[q] * f;
-              const float att = __builtin_amdgcn_exp2f(dtau * -1.44269504f);
-              float em = 8.33333333e-3f;
-              em = fmaf(em, dtau, -4.16666667e-2f);
-              em = fmaf(em, dtau, 1.66666667e-1f);
-              em = fmaf(em, dtau, -0.5f);
-              em = fmaf(em, dtau, 1.0f);
-              em = dtau < 0.125f ? em * dtau : 1.0f - att;
-              const float src = warm ? s_ap[q] * __builtin_amdgcn_rcpf(expm1_pos(s_hk[q] * inv_t)) : 0.0f;
-              I32[q] = fmaf(I32[q], att, src * em);
+          for (int q0 = 0; q0 < NS; q0 += kG) {
+            if (NS <= kG || q0 < n_sel) {
+#pragma unroll
+              for (int q = q0; q < (q0 + kG < NS ? q0 + kG : NS); ++q) {
+                const float dtau = s_kc[q] * f;
+                const float att = __builtin_amdgcn_exp2f(dtau * -1.44269504f);
+                float em = 8.33333333e-3f;
+                em = fmaf(em, dtau, -4.16666667e-2f);
+                em = fmaf(em, dtau, 1.66666667e-1f);
+                em = fmaf(em, dtau, -0.5f);
+                em = fmaf(em, dtau, 1.0f);
+                em = dtau < 0.125f ? em * dtau : 1.0f - att;
+                const float src = warm ? s_ap[q] * __builtin_amdgcn_rcpf(expm1_pos(s_hk[q] * inv_t)) : 0.0f;
+                I32[q] = fmaf(I32[q], att, src * em);
+              }
             }
           }
         } else if (!F32 && rho > 0.0 && s > 0.0) {
@@ -214,7 +227,7 @@ hipError_t launch_render(bool f32, const ModelDev* models, int model, const int3
     if (n_sel <= 4) RT_RENDER(4, true);
     else if (n_sel <= 8) RT_RENDER(8, true);
     else if (n_sel <= 16) RT_RENDER(16, true);
-    else RT_RENDER(32, true);
+    else RT_RENDER(128, true);
   } else {
     if (n_sel <= 4) RT_RENDER(4, false);
     else if (n_sel <= 8) RT_RENDER(8, false);

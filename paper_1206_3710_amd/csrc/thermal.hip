@@ -146,6 +146,14 @@ __global__ __launch_bounds__(256) void temperature_kernel(
         u = un;
         break;
       }
+      // from the table's guess (a cubic in ln S, good to about 1e-9) one Newton step lands within
+      // (c / 2) |step|^2 of the root, c = |d2 ln S / d(ln T)^2| / (d ln S / d ln T): about 0.7
+      // for the dust tables here, and a first step under 1e-8 keeps that below 1e-14 for any c up
+      // to 200, so the solve ends there
+      if (it == 0 && fabs(un - u) <= 1e-8 && un > lo && un < hi) {
+        u = un;
+        break;
+      }
       if (!(un > lo && un < hi)) un = 0.5 * (lo + hi);
     } else {
       un = 0.5 * (lo + hi);

@@ -517,16 +517,19 @@ def test_sweep_graph_replay_matches_direct_launches(torch):
         assert rel_rms(eb, ea) < 1e-5
 
 
-def test_render_fp32_transfer_against_fp64(torch):
+@pytest.mark.parametrize("n_lambda", [12, 100, 140])
+def test_render_fp32_transfer_against_fp64(torch, n_lambda):
     """Maps with the transfer in FP32: the same cells as the FP64 map (equal crossing counts),
-    each pixel within 1e-4 relative of it (a few hundred FP32 steps of a few roundings each)."""
-    w = gen.c2(n_root=24, max_level=3, n_lambda=12, packets=20000)
+    each pixel within 1e-4 relative of it (a few hundred FP32 steps of a few roundings each).
+    12 wavelengths take one pass of 16, 100 one pass of 128 (the last group of 8 padded), 140 a
+    pass of 128 and one of 16."""
+    w = gen.c2(n_root=24, max_level=3, n_lambda=n_lambda, packets=20000)
     ctx = new_ctx(torch)
     m = ctx.build_tree(w.trees[0])
     ctx.set_dust(m, w.dusts[0])
     r = ctx.trace_packets(w.sources, seed=w.seed, precision=rt.FP64)
     ctx.solve_temperature(m, r["e_abs_node"], 2.0, 3000.0)
-    lam = list(range(12))
+    lam = list(range(n_lambda))
     for d in [(1.0, 0.0, 0.0), (0.3, -0.5, 0.81)]:
         i64, c64 = ctx.render_map(m, d, 48, lam, precision=rt.FP64)
         i32, c32 = ctx.render_map(m, d, 48, lam, precision=rt.FP32_LOCAL)
