@@ -224,7 +224,9 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   const TraceParams& p = b.t;
   const float rr_thr = (float)p.rr_thr, rr_p = (float)p.rr_p;
   const float rr_gain = rr_p > 0.0f ? 1.0f / (1.0f - rr_p) : 1.0f;
-  const int bx = R.hi[0] - R.lo[0], by = R.hi[1] - R.lo[1], bxy = bx * by;
+  const int bx = R.hi[0] - R.lo[0], by = R.hi[1] - R.lo[1];
+  // (opaque to the compiler, which would otherwise rebuild a brick-level stride as a multiply)
+  const int bxy = __builtin_amdgcn_readfirstlane(bx * by);
   double* __restrict__ gacc64 = b.accb64 + (int64_t)it.slot * b.accb_stride + R.gbase;
   const int32_t* __restrict__ gword = b.rword + R.gbase;
   const int32_t* __restrict__ gup = b.rup + (R.gbase >> 3);
@@ -502,7 +504,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           state = B_EVENT;
         } else if (near_move) {
           const int L = lev;
-          const int32_t stride = at_brick ? (ax == 0 ? 1 : (ax == 1 ? bx : bxy)) : (1 << ax);
+          const int32_t stride = at_brick ? sel3(ax, 1, bx, bxy) : (1 << ax);
           I0 = ax == 0 ? Ja : I0;
           I1 = ax == 1 ? Ja : I1;
           I2 = ax == 2 ? Ja : I2;
@@ -510,12 +512,10 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           int32_t raw = word_of(node);
           descend(word_of, ax, sg, x0, x1, x2, I0, I1, I2, node, lev, raw);
           rho = __int_as_float(raw);
-          if (++ncross >= kMaxCrossings) {
-            ev = (uint32_t)p.max_events;
-            state = B_EVENT;
-          } else if (splitting && min(lev, sdep) != min(L, sdep)) {
-            state = B_SPLIT;
-          }
+          // (the guard on the crossing count is tested on the far crossings: between two of them
+          // a packet crosses at most the cells of one brick along a straight line)
+          ++ncross;
+          if (splitting && min(lev, sdep) != min(L, sdep)) state = B_SPLIT;
         } else if (LVL) {
           far_cross(ax, sg);
         } else {
