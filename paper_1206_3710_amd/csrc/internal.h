@@ -269,9 +269,14 @@ hipError_t launch_ali_absorbed(int64_t n, const double* a_stars, const double* a
                                const double* e_emit, double* out, hipStream_t s);
 hipError_t launch_peel_tables(const TraceParams& p, const PeelParams& q, hipStream_t s);
 hipError_t launch_peel(const TraceParams& p, const PeelParams& q, int grid, hipStream_t s);
+// Sort of one sweep's queue by key.  With at most kSortLdsKeys keys the counts are kept per
+// block (bhist: kSortBlocks(grid) x n_keys) and no global atomic is used; otherwise hist and the
+// cursors are counted with global atomics.
+constexpr int kSortLdsKeys = 16384;
+inline int kSortBlocks(int grid) { return grid / 4 > 0 ? grid / 4 : 1; }
 hipError_t launch_sweep_sort(SweepState* st, int in, int slot, uint64_t batch, uint64_t capq, const uint32_t* keys,
                              int n_keys, int n_regions, int chunk, uint32_t* hist, uint32_t* kfill,
-                             uint32_t* perm, WorkItem* items, int grid, hipStream_t s);
+                             uint32_t* bhist, uint32_t* perm, WorkItem* items, int grid, hipStream_t s);
 hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s);
 hipError_t attr_blk_pass(int block, int lds_bytes);
 hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, int n_regions,

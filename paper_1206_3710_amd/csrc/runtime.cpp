@@ -121,7 +121,7 @@ struct rt_ctx {
   int64_t reg_G = 0;
   int32_t reg_maxn = 0;
   DevBuf d_regions, d_rword, d_rup, d_rcanon, d_root_region, d_split;
-  DevBuf q_rec[2], q_key[2], q_perm, q_hist, q_kfill, q_items, q_state;
+  DevBuf q_rec[2], q_key[2], q_perm, q_hist, q_kfill, q_bhist, q_items, q_state;
   int64_t q_capacity = 0;
   // sweep graph: kSweepBlock sweeps captured once per trace configuration, replayed
   hipGraphExec_t sweep_exec = nullptr;
@@ -554,7 +554,7 @@ rt_status rt_destroy(rt_ctx* ctx) {
                     &ctx->tmp_out2, &ctx->view, &ctx->lamidx, &ctx->it_astars, &ctx->it_adust,
                     &ctx->it_sum, &ctx->it_told, &ctx->it_crit, &ctx->d_regions, &ctx->d_rword,
                     &ctx->d_rup, &ctx->d_rcanon, &ctx->d_root_region, &ctx->d_split, &ctx->q_rec[0], &ctx->q_rec[1],
-                    &ctx->q_key[0], &ctx->q_key[1], &ctx->q_perm, &ctx->q_hist, &ctx->q_kfill,
+                    &ctx->q_key[0], &ctx->q_key[1], &ctx->q_perm, &ctx->q_hist, &ctx->q_kfill, &ctx->q_bhist,
                     &ctx->q_items, &ctx->q_state, &ctx->last_node, &ctx->t_tab, &ctx->it_self,
                     &ctx->it_emit, &ctx->peel_ev, &ctx->peel_ctr, &ctx->peel_tab, &ctx->peel_roottab,
                     &ctx->peel_tabroot, &ctx->peel_dnu, &ctx->peel_img, &ctx->g_jobs, &ctx->g_keys,
@@ -912,6 +912,7 @@ rt_status region_launch_setup(rt_ctx* ctx, const rt_trace_opts* o, const TracePa
   }
   HIPCHK(ctx->q_hist.ensure(4 * n_keys));
   HIPCHK(ctx->q_kfill.ensure(4 * n_keys));
+  if (n_keys <= kSortLdsKeys) HIPCHK(ctx->q_bhist.ensure(4 * n_keys * (int64_t)kSortBlocks(ctx->n_cu * 4)));
   HIPCHK(ctx->q_items.ensure(sizeof(WorkItem) * (cap_all / chunk + n_keys + 1)));
   HIPCHK(ctx->q_state.ensure(sizeof(SweepState)));
   SweepState* st = ctx->q_state.as<SweepState>();
@@ -963,8 +964,8 @@ hipError_t enqueue_sweeps(rt_ctx* ctx, const RegionLaunch& L, hipStream_t s, con
     const int in = k & 1, out = 1 - in;
     hipError_t e = launch_sweep_sort(L.st, in, k, (uint64_t)L.batch, (uint64_t)L.capq, ctx->q_key[in].as<uint32_t>(),
                                      (int)L.n_keys, L.n_regions, L.chunk, ctx->q_hist.as<uint32_t>(),
-                                     ctx->q_kfill.as<uint32_t>(), ctx->q_perm.as<uint32_t>(),
-                                     ctx->q_items.as<WorkItem>(), L.grid_sort, s);
+                                     ctx->q_kfill.as<uint32_t>(), ctx->q_bhist.as<uint32_t>(),
+                                     ctx->q_perm.as<uint32_t>(), ctx->q_items.as<WorkItem>(), L.grid_sort, s);
     if (e != hipSuccess) return e;
     BlkParams bk = L.b;
     bk.q_in = ctx->q_rec[in].as<PRec>();

@@ -5,7 +5,9 @@
 //
 // One sweep, on queue buffer `in` (its records were appended during the previous sweep):
 //   begin    pick this sweep's emission range and reserve its records in the other buffer
-//   hist     count the records per key (slot * n_regions + region)
+//   hist     count the records per key (slot * n_regions + region); with few enough keys each
+//            block counts a contiguous range of records in LDS and writes its counts, and a
+//            column scan turns them into the block's offsets within each key (no global atomic)
 //   scan     exclusive offsets per key; cut each key's run into work items
 //   scatter  record index -> its place in key order (the permutation the pass reads through)
 //   pass     the region pass (blocked.hip) appends leaving packets to the other buffer, in
@@ -17,7 +19,9 @@ using namespace rtd;
 
 namespace {
 
-constexpr int kHistLds = 16384;  // keys counted in LDS (larger key sets use global atomics)
+constexpr int kHistLds = kSortLdsKeys;  // keys counted in LDS (larger key sets use global atomics)
+constexpr int kSortBS = 1024;            // threads per block of the block-histogram sort
+constexpr int kSortPer = 8;              // records per thread per round of its loops
 constexpr int kAgg = 4;          // distinct keys per wave counted with one atomic each
 
 // Add 1 per valid lane to cnt[key]; returns each lane's rank among the lanes (and earlier
@@ -213,12 +217,116 @@ __global__ __launch_bounds__(256) void sw_scatter_kernel(const uint32_t* __restr
   }
 }
 
+// Records [lo, hi) of block b: whole rounds of kSortBS * kSortPer records, split evenly over the
+// blocks.  The counting and the scatter kernels take the same ranges, so each block's counts
+// are exactly the records it places.
+__device__ __forceinline__ void block_range(uint64_t n, int b, int nb, uint64_t& lo, uint64_t& hi) {
+  constexpr uint64_t kRound = (uint64_t)kSortBS * kSortPer;
+  const uint64_t rounds = (n + kRound - 1) / kRound;
+  const uint64_t per = (rounds + (uint64_t)nb - 1) / (uint64_t)nb;
+  lo = min(n, (uint64_t)b * per * kRound);
+  hi = min(n, (uint64_t)(b + 1) * per * kRound);
+}
+
+// Per-block key counts of the block's record range, written as row b of bh.
+__global__ __launch_bounds__(kSortBS) void sw_bhist_kernel(const uint32_t* __restrict__ keys,
+                                                           const SweepState* __restrict__ st,
+                                                           uint32_t* __restrict__ bh, int n_keys) {
+  __shared__ uint32_t s_h[kHistLds];
+  for (int k = threadIdx.x; k < n_keys; k += kSortBS) s_h[k] = 0u;
+  __syncthreads();
+  uint64_t lo, hi;
+  block_range(st->n_in, blockIdx.x, gridDim.x, lo, hi);
+  for (uint64_t t0 = lo; t0 < hi; t0 += (uint64_t)kSortBS * kSortPer) {
+    uint32_t kk[kSortPer];
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+      const uint64_t i = t0 + (uint64_t)j * kSortBS + threadIdx.x;
+      kk[j] = i < hi ? keys[i] : kInvalidKey;
+    }
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+      const bool v = kk[j] != kInvalidKey;
+      (void)agg_count(s_h, v ? kk[j] : 0u, v);
+    }
+  }
+  __syncthreads();
+  uint32_t* __restrict__ row = bh + (size_t)blockIdx.x * n_keys;
+  for (int k = threadIdx.x; k < n_keys; k += kSortBS) row[k] = s_h[k];
+}
+
+// Per key: the blocks' counts become their exclusive offsets within the key, and hist the key's
+// total.
+__global__ __launch_bounds__(256) void sw_colscan_kernel(uint32_t* __restrict__ bh, int nb, int n_keys,
+                                                         uint32_t* __restrict__ hist) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n_keys) return;
+  uint32_t run = 0;
+  int b = 0;
+  for (; b + 8 <= nb; b += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = bh[(size_t)(b + j) * n_keys + k];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      bh[(size_t)(b + j) * n_keys + k] = run;
+      run += v[j];
+    }
+  }
+  for (; b < nb; ++b) {
+    const uint32_t v = bh[(size_t)b * n_keys + k];
+    bh[(size_t)b * n_keys + k] = run;
+    run += v;
+  }
+  hist[k] = run;
+}
+
+// Record index -> position in key order: the block's cursor for key k starts at the key's start
+// plus the block's offset within it, and is advanced in LDS.
+__global__ __launch_bounds__(kSortBS) void sw_bscatter_kernel(const uint32_t* __restrict__ keys,
+                                                              const SweepState* __restrict__ st,
+                                                              const uint32_t* __restrict__ kfill,
+                                                              const uint32_t* __restrict__ bh,
+                                                              uint32_t* __restrict__ perm, int n_keys) {
+  __shared__ uint32_t s_c[kHistLds];
+  const uint32_t* __restrict__ row = bh + (size_t)blockIdx.x * n_keys;
+  for (int k = threadIdx.x; k < n_keys; k += kSortBS) s_c[k] = kfill[k] + row[k];
+  __syncthreads();
+  uint64_t lo, hi;
+  block_range(st->n_in, blockIdx.x, gridDim.x, lo, hi);
+  for (uint64_t t0 = lo; t0 < hi; t0 += (uint64_t)kSortBS * kSortPer) {
+    uint32_t kk[kSortPer];
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+      const uint64_t i = t0 + (uint64_t)j * kSortBS + threadIdx.x;
+      kk[j] = i < hi ? keys[i] : kInvalidKey;
+    }
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+      const uint64_t i = t0 + (uint64_t)j * kSortBS + threadIdx.x;
+      const bool v = kk[j] != kInvalidKey;
+      const uint32_t pos = agg_count(s_c, v ? kk[j] : 0u, v);
+      if (v) perm[pos] = (uint32_t)i;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_sweep_sort(SweepState* st, int in, int slot, uint64_t batch, uint64_t capq, const uint32_t* keys,
                              int n_keys, int n_regions, int chunk, uint32_t* hist, uint32_t* kfill,
-                             uint32_t* perm, WorkItem* items, int grid, hipStream_t s) {
+                             uint32_t* bhist, uint32_t* perm, WorkItem* items, int grid, hipStream_t s) {
   hipLaunchKernelGGL(sw_begin_kernel, dim3(1), dim3(64), 0, s, st, in, slot, batch, capq);
+  if (n_keys <= kHistLds) {
+    const int nb = kSortBlocks(grid);
+    hipLaunchKernelGGL(sw_bhist_kernel, dim3(nb), dim3(kSortBS), 0, s, keys, (const SweepState*)st, bhist, n_keys);
+    hipLaunchKernelGGL(sw_colscan_kernel, dim3((n_keys + 255) / 256), dim3(256), 0, s, bhist, nb, n_keys, hist);
+    hipLaunchKernelGGL(sw_scan_kernel, dim3(1), dim3(1024), 0, s, (const uint32_t*)hist, n_keys, n_regions, chunk,
+                       kfill, items, st);
+    hipLaunchKernelGGL(sw_bscatter_kernel, dim3(nb), dim3(kSortBS), 0, s, keys, (const SweepState*)st,
+                       (const uint32_t*)kfill, (const uint32_t*)bhist, perm, n_keys);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(sw_zero_kernel, dim3((n_keys + 255) / 256 < 1024 ? (n_keys + 255) / 256 : 1024), dim3(256),
                      0, s, hist, n_keys);
   hipLaunchKernelGGL(sw_hist_kernel, dim3(grid), dim3(256), 0, s, keys, (const SweepState*)st, hist, n_keys);

@@ -295,6 +295,31 @@ def test_render_parity(torch):
         np.testing.assert_allclose(ig, io, rtol=1e-6, atol=1e-12 * io.max())
 
 
+@pytest.mark.parametrize("n_lambda", [20, 100])
+def test_render_fp32_against_oracle(torch, n_lambda):
+    """FP32-transfer maps against the oracle's FP64 maps directly (same cells, equal crossing
+    counts): each pixel within 1e-4 relative, values below 1e-7 of the brightest map of the
+    selection counted against that floor (the same FP32 error model as against the GPU's FP64
+    map).  100 wavelengths take one pass of 128."""
+    w = gen.c2(n_root=16, max_level=2, n_lambda=n_lambda, packets=1000)
+    ora = oracle.Model(w.trees[0], w.dusts[0])
+    rng = np.random.default_rng(6)
+    tn = np.where(ora.leaf_mask, rng.uniform(8, 40, ora.n_nodes), 0.0)
+    ctx = new_ctx(torch)
+    m = ctx.build_tree(w.trees[0])
+    ctx.set_dust(m, w.dusts[0])
+    ctx.set_temperature(m, tn)
+    lam = list(range(n_lambda))
+    for n_obs, npix, width in [((1.0, 0, 0), 32, 0.0), ((0.3, -0.7, 0.5), 33, 20.0)]:
+        io, co = ora.render(n_obs, npix, tn, lam, width=width)
+        ig, cg = ctx.render_map(m, n_obs, npix, lam, width=width, precision=rt.FP32_LOCAL)
+        ig = ig.cpu().numpy()
+        assert cg == co
+        floor = 1e-7 * np.abs(io).max()
+        err = np.abs(ig - io)
+        assert np.all(err <= 1e-4 * np.abs(io) + floor), (err / np.maximum(np.abs(io), floor)).max()
+
+
 def test_dust_emission_parity(torch):
     """Dust-emission source (fixed temperatures): identical cell picks and deposits."""
     w = gen.c2(n_root=12, max_level=2, n_lambda=6, packets=1000)
