@@ -51,10 +51,17 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0
 # 4 GiB device-to-device copy (fetch x2.0, write x1.0), per leaf crossing; its VALU
 # wave-instructions per leaf crossing (SQ_INSTS_VALU) and lane utilisation
 # (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) in the same step, at the launch settings the
-# autotuner picked in that run.  Valid only for the kernel sources the counters were taken on.
+# autotuner picks for the workload (given explicitly to those runs).  Valid only for the kernel
+# sources the counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "",
-                "per_workload": {}}
+                "sha256": "4915789511652473a3f59a6d6c75c2fbb688d14083c18bdd1f66187fda628df0",
+                "per_workload": {
+                    # profiles/blk_pass_kernel_deep_hierarchy_cloud.md
+                    "deep": {"fetch_bytes_per_crossing": 10.8388, "write_bytes_per_crossing": 5.0755,
+                             "valu_per_crossing": 2.7213, "lane_utilisation": 0.5551},
+                    # profiles/blk_pass_kernel_molecular_cloud.md
+                    "cloud": {"fetch_bytes_per_crossing": 10.8685, "write_bytes_per_crossing": 6.4036,
+                              "valu_per_crossing": 4.0899, "lane_utilisation": 0.4205}}}
 
 
 WORKLOADS = {
@@ -553,9 +560,11 @@ def measure(a, rt, gen, torch, w, workload, steps, warmup, copy_gbs, fp64_steps,
     m = 0
     nl = w.dusts[0].n_lambda
     lam_all = list(range(nl))
-    kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob, block_size=a.block,
-              blocks_per_cu=a.blocks_per_cu, refill_threshold=a.refill)
-    kw32 = dict(kw, schedule=a.schedule, chunk_packets=a.chunk, batch_packets=a.batch,
+    # launch parameters given on the command line are the FP32-local form's; the FP64 form
+    # keeps its own defaults
+    kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob)
+    kw32 = dict(kw, block_size=a.block, blocks_per_cu=a.blocks_per_cu, refill_threshold=a.refill,
+                schedule=a.schedule, chunk_packets=a.chunk, batch_packets=a.batch,
                 tail_park=a.tail_park, sweep_graph=1 if a.graph else 0)
     if workload == "disc":
         # constant sources once (FP64 form), then every timed step re-emits from T_0
