@@ -39,9 +39,9 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 // or the neighbour across a face).  Below level L (a coarse cell entering a split cell through
 // face ax with sign sg) the child is picked as the landing picks it: the near side on the
 // crossing axis, the midpoint on the others (y: local coordinates in the level-L cell).
-// e: the root cell's entry of the region table (a region, or ~split index).
-__device__ __forceinline__ int32_t region_walk_from(const BlkParams& b, int32_t e, int L, int32_t J0, int32_t J1,
-                                                    int32_t J2, int ax, int sg, float y0, float y1, float y2) {
+__device__ __forceinline__ int32_t region_walk(const BlkParams& b, const Dims& D, int L, int32_t J0, int32_t J1,
+                                               int32_t J2, int ax, int sg, float y0, float y1, float y2) {
+  int32_t e = b.root_region[D.root(J0 >> L, J1 >> L, J2 >> L)];
   int l = 0;
   while (e < 0) {
     ++l;
@@ -61,11 +61,6 @@ __device__ __forceinline__ int32_t region_walk_from(const BlkParams& b, int32_t 
     e = b.split_tab[(size_t)(~e) * 8 + oc];
   }
   return e;
-}
-
-__device__ __forceinline__ int32_t region_walk(const BlkParams& b, const Dims& D, int L, int32_t J0, int32_t J1,
-                                               int32_t J2, int ax, int sg, float y0, float y1, float y2) {
-  return region_walk_from(b, b.root_region[D.root(J0 >> L, J1 >> L, J2 >> L)], L, J0, J1, J2, ax, sg, y0, y1, y2);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -267,9 +262,6 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
   float ks = 0.f, ka = 0.f, g = 0.f;  // scattering / absorption opacity per root-cell length per unit density
   int esc_slot = 0;
   int32_t xax = 0, xsg = 0;
-  // region-table entry of the root cell holding the neighbour a packet leaves the region for,
-  // read when the exit is found so that its latency passes before the record is written
-  int32_t xroot = 0;
   bool xpark = false;          // re-queued in this region without crossing a face
   bool pool_done = false;      // this item's packets are all taken (wave-uniform)
   int tail_it = 0;             // crossing rounds since then (wave-uniform)
@@ -326,7 +318,6 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           leave = true;
           xax = ax;
           xsg = sg;
-          xroot = b.root_region[D.root(J0 >> L, J1 >> L, J2 >> L)];
           state = B_EXIT;
         } else {
           cur = (R0 - R.lo[0]) + bx * ((R1 - R.lo[1]) + by * (R2 - R.lo[2]));
@@ -532,11 +523,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           xsg = sg;
           // leaving the brick at its level into the model: no tree walk, the record is written
           // in the exit phase; every other crossing waits for the far-crossing phase
-          const bool leave = lev == R.rl && Ja >= 0 && Ja < (D.na(ax) << lev);
-          if (leave)
-            xroot = b.root_region[D.root((ax == 0 ? Ja : I0) >> lev, (ax == 1 ? Ja : I1) >> lev,
-                                         (ax == 2 ? Ja : I2) >> lev)];
-          state = leave ? B_EXIT : B_FAR;
+          state = lev == R.rl && Ja >= 0 && Ja < (D.na(ax) << lev) ? B_EXIT : B_FAR;
         }
       }
       if (pool_done && ++tail_it >= b.tail_park) break;
@@ -612,7 +599,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         if (!xpark) {
           const int32_t K0 = I0 + (xax == 0 ? xsg : 0), K1 = I1 + (xax == 1 ? xsg : 0), K2 = I2 + (xax == 2 ? xsg : 0);
           key = kslot * (uint32_t)b.n_regions +
-                (uint32_t)region_walk_from(b, xroot, lev, K0, K1, K2, xax, xsg, x0, x1, x2);
+                (uint32_t)region_walk(b, D, lev, K0, K1, K2, xax, xsg, x0, x1, x2);
         }
         b.u_key[idx] = key;
         xpark = false;
