@@ -310,8 +310,9 @@ struct LamConst {
   double dnu;
 };
 // Temperatures of every leaf (tab: scratch of 4 + 2 kPlanckTable doubles for the inverse table
-// of the emission per unit mass, rebuilt by each call).
-constexpr int kPlanckTable = 2048;
+// of the emission per unit mass, rebuilt by each call; dense enough that its cubic Hermite
+// interpolation is the root to rounding).
+constexpr int kPlanckTable = 65536;
 hipError_t launch_temperature(const ModelDev* models, int model, int64_t n_nodes,
                               const int32_t* child, const double* rho64, const double* a_node,
                               const LamConst* lc, int nl, double t_min, double t_max, double* tab,

@@ -22,18 +22,21 @@ namespace {
 constexpr int kHistLds = kSortLdsKeys;  // keys counted in LDS (larger key sets use global atomics)
 constexpr int kSortBS = 1024;            // threads per block of the block-histogram sort
 constexpr int kSortPer = 8;              // records per thread per round of its loops
-constexpr int kAgg = 4;          // distinct keys per wave counted with one atomic each
+constexpr int kAgg = 4;          // distinct keys per wave counted with one atomic each (global counters)
 
 // Add 1 per valid lane to cnt[key]; returns each lane's rank among the lanes (and earlier
-// callers) with its key.  Lanes sharing one of the first kAgg distinct keys of the wave are
+// callers) with its key.  Lanes sharing one of the first AGG distinct keys of the wave are
 // counted with a single atomic per key (queues are often dominated by a few regions, whose
-// counters would otherwise serialise); the remaining lanes use one atomic each.
+// global counters would otherwise serialise); the remaining lanes use one atomic each.  LDS
+// counters take AGG = 0: one LDS atomic per lane is cheaper than the wave's ballot rounds.
+template <int AGG = kAgg>
 __device__ __forceinline__ uint32_t agg_count(uint32_t* cnt, uint32_t key, bool valid) {
+  if (AGG == 0) return valid ? atomicAdd(&cnt[key], 1u) : 0u;
   const int lane = threadIdx.x & 63;
   uint64_t todo = __ballot(valid);
   uint32_t rank = 0;
   bool done = !valid;
-  for (int it = 0; it < kAgg && todo; ++it) {
+  for (int it = 0; it < AGG && todo; ++it) {
     const int leader = __builtin_ctzll(todo);
     const uint32_t kl = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
     const uint64_t same = __ballot(valid && key == kl) & todo;
@@ -94,16 +97,11 @@ __global__ void sw_zero_kernel(uint32_t* __restrict__ a, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = 0u;
 }
 
+// Key counts with global atomics (key sets too large for LDS).
 __global__ __launch_bounds__(256) void sw_hist_kernel(const uint32_t* __restrict__ keys,
                                                       const SweepState* __restrict__ st,
-                                                      uint32_t* __restrict__ hist, int n_keys) {
-  __shared__ uint32_t s_h[kHistLds];
+                                                      uint32_t* __restrict__ hist) {
   const uint64_t n = st->n_in;
-  const bool lds = n_keys <= kHistLds;
-  if (lds) {
-    for (int k = threadIdx.x; k < n_keys; k += 256) s_h[k] = 0u;
-    __syncthreads();
-  }
   // whole waves iterate together (agg_count needs every lane of the wave); kPerH keys per
   // thread are loaded before any is counted, so that the loads overlap
   constexpr int kPerH = 8;
@@ -118,13 +116,8 @@ __global__ __launch_bounds__(256) void sw_hist_kernel(const uint32_t* __restrict
 #pragma unroll
     for (int j = 0; j < kPerH; ++j) {
       const bool v = kk[j] != kInvalidKey;  // unused records of a pass wave's last chunk
-      (void)agg_count(lds ? s_h : hist, v ? kk[j] : 0u, v);
+      (void)agg_count(hist, v ? kk[j] : 0u, v);
     }
-  }
-  if (lds) {
-    __syncthreads();
-    for (int k = threadIdx.x; k < n_keys; k += 256)
-      if (s_h[k]) atomicAdd(&hist[k], s_h[k]);
   }
 }
 
@@ -170,50 +163,19 @@ __global__ __launch_bounds__(1024) void sw_scan_kernel(const uint32_t* __restric
   if (t == 0) st->n_items = carry_i;
 }
 
-// Record index -> position in key order.  A block takes tiles of 4096 records: their ranks
-// within the tile come from LDS counters, one global atomic per (tile, key) reserves the
-// tile's range of each key.
+// Record index -> position in key order, with global cursors (key sets too large for LDS).
 __global__ __launch_bounds__(256) void sw_scatter_kernel(const uint32_t* __restrict__ keys,
                                                          const SweepState* __restrict__ st,
                                                          uint32_t* __restrict__ kfill,
-                                                         uint32_t* __restrict__ perm, int n_keys) {
-  constexpr int kPer = 16, kTile = 256 * kPer;
-  __shared__ uint32_t s_c[kHistLds];
+                                                         uint32_t* __restrict__ perm) {
   const uint64_t n = st->n_in;
-  if (n_keys > kHistLds) {
-    const uint64_t span = (uint64_t)gridDim.x * 256;
-    for (uint64_t i0 = (uint64_t)blockIdx.x * 256; i0 < n; i0 += span) {
-      const uint64_t i = i0 + threadIdx.x;
-      const uint32_t k = i < n ? keys[i] : kInvalidKey;
-      const bool v = k != kInvalidKey;
-      const uint32_t pos = agg_count(kfill, v ? k : 0u, v);
-      if (v) perm[pos] = (uint32_t)i;
-    }
-    return;
-  }
-  for (uint64_t t0 = (uint64_t)blockIdx.x * kTile; t0 < n; t0 += (uint64_t)gridDim.x * kTile) {
-    for (int k = threadIdx.x; k < n_keys; k += 256) s_c[k] = 0u;
-    __syncthreads();
-    uint32_t key[kPer], rank[kPer];
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const uint64_t i = t0 + (uint64_t)j * 256 + threadIdx.x;
-      key[j] = i < n ? keys[i] : kInvalidKey;
-      const bool v = key[j] != kInvalidKey;
-      rank[j] = agg_count(s_c, v ? key[j] : 0u, v);
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < n_keys; k += 256) {
-      const uint32_t c = s_c[k];
-      if (c) s_c[k] = atomicAdd(&kfill[k], c);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const uint64_t i = t0 + (uint64_t)j * 256 + threadIdx.x;
-      if (i < n && key[j] != kInvalidKey) perm[s_c[key[j]] + rank[j]] = (uint32_t)i;
-    }
-    __syncthreads();
+  const uint64_t span = (uint64_t)gridDim.x * 256;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * 256; i0 < n; i0 += span) {
+    const uint64_t i = i0 + threadIdx.x;
+    const uint32_t k = i < n ? keys[i] : kInvalidKey;
+    const bool v = k != kInvalidKey;
+    const uint32_t pos = agg_count(kfill, v ? k : 0u, v);
+    if (v) perm[pos] = (uint32_t)i;
   }
 }
 
@@ -247,7 +209,7 @@ __global__ __launch_bounds__(kSortBS) void sw_bhist_kernel(const uint32_t* __res
 #pragma unroll
     for (int j = 0; j < kSortPer; ++j) {
       const bool v = kk[j] != kInvalidKey;
-      (void)agg_count(s_h, v ? kk[j] : 0u, v);
+      (void)agg_count<0>(s_h, v ? kk[j] : 0u, v);
     }
   }
   __syncthreads();
@@ -305,7 +267,7 @@ __global__ __launch_bounds__(kSortBS) void sw_bscatter_kernel(const uint32_t* __
     for (int j = 0; j < kSortPer; ++j) {
       const uint64_t i = t0 + (uint64_t)j * kSortBS + threadIdx.x;
       const bool v = kk[j] != kInvalidKey;
-      const uint32_t pos = agg_count(s_c, v ? kk[j] : 0u, v);
+      const uint32_t pos = agg_count<0>(s_c, v ? kk[j] : 0u, v);
       if (v) perm[pos] = (uint32_t)i;
     }
   }
@@ -329,11 +291,10 @@ hipError_t launch_sweep_sort(SweepState* st, int in, int slot, uint64_t batch, u
   }
   hipLaunchKernelGGL(sw_zero_kernel, dim3((n_keys + 255) / 256 < 1024 ? (n_keys + 255) / 256 : 1024), dim3(256),
                      0, s, hist, n_keys);
-  hipLaunchKernelGGL(sw_hist_kernel, dim3(grid), dim3(256), 0, s, keys, (const SweepState*)st, hist, n_keys);
+  hipLaunchKernelGGL(sw_hist_kernel, dim3(grid), dim3(256), 0, s, keys, (const SweepState*)st, hist);
   hipLaunchKernelGGL(sw_scan_kernel, dim3(1), dim3(1024), 0, s, (const uint32_t*)hist, n_keys, n_regions, chunk,
                      kfill, items, st);
-  hipLaunchKernelGGL(sw_scatter_kernel, dim3(grid), dim3(256), 0, s, keys, (const SweepState*)st, kfill, perm,
-                     n_keys);
+  hipLaunchKernelGGL(sw_scatter_kernel, dim3(grid), dim3(256), 0, s, keys, (const SweepState*)st, kfill, perm);
   return hipGetLastError();
 }
 

@@ -78,9 +78,12 @@ __global__ __launch_bounds__(256) void planck_table_kernel(const LamConst* __res
 }
 
 // Per leaf: the temperature at which the emitted power 4 pi m sum kappa_abs B(T) dnu equals
-// the absorbed power A.  Newton iteration on ln F(ln T), kept inside a shrinking bracket,
-// started from the inverse table (cubic Hermite in ln S): the root in one or two evaluations
-// of the sum.
+// the absorbed power A.  With S increasing over the range, the inverse table's cubic Hermite
+// interpolation in ln S is the root to rounding: its truncation error, h^4 / 384 times the fourth
+// derivative of ln T in ln S, is of order 1e-16 at h = ln(S(t_max) / S(t_min)) / 65535 (about
+// 7e-4 for the dust tables here, where the interpolated ln T is within 3e-15 of the root).
+// Otherwise a Newton iteration on ln F(ln T), kept inside a shrinking bracket, from a linear
+// guess.
 __global__ __launch_bounds__(256) void temperature_kernel(
     const ModelDev* __restrict__ models, int model, const int32_t* __restrict__ child,
     const double* __restrict__ rho64, const double* __restrict__ a_node,
@@ -125,6 +128,8 @@ __global__ __launch_bounds__(256) void temperature_kernel(
     const double u1 = tab[6 + 2 * i], g1 = tab[7 + 2 * i] * dy;
     const double f2 = f * f, f3 = f2 * f;
     u = (2.0 * f3 - 3.0 * f2 + 1.0) * u0 + (f3 - 2.0 * f2 + f) * g0 + (3.0 * f2 - 2.0 * f3) * u1 + (f3 - f2) * g1;
+    t_out[c] = exp(u < lo ? lo : (u > hi ? hi : u));
+    return;
   } else {
     u = lo + (la - log(flo)) / (log(fhi) - log(flo)) * (hi - lo);
   }
@@ -143,14 +148,6 @@ __global__ __launch_bounds__(256) void temperature_kernel(
       // where log(f) rounds to log(A) while f < A, the step is zero and un equals the new lower
       // end, which the bracket test would replace by the midpoint of a wide bracket
       if (fabs(un - u) <= 1e-14) {
-        u = un;
-        break;
-      }
-      // from the table's guess (a cubic in ln S, good to about 1e-9) one Newton step lands within
-      // (c / 2) |step|^2 of the root, c = |d2 ln S / d(ln T)^2| / (d ln S / d ln T): about 0.7
-      // for the dust tables here, and a first step under 1e-8 keeps that below 1e-14 for any c up
-      // to 200, so the solve ends there
-      if (it == 0 && fabs(un - u) <= 1e-8 && un > lo && un < hi) {
         u = un;
         break;
       }
