@@ -133,8 +133,8 @@ __global__ __launch_bounds__(256, NS > 32 ? 2 : 1) void render_kernel(
           // (series below 1/8, else from the transmission), and the source (1 - a) B(T)
           const float tc = (float)t_node[canon_of(m, node)];
           const float f = (float)(rho * s);
-          const bool warm = tc > 0.0f;
-          const float inv_t = warm ? __builtin_amdgcn_rcpf(tc) : 0.0f;
+          // a cell without a temperature emits nothing: 1 / T = inf makes the source term 0
+          const float inv_t = tc > 0.0f ? __builtin_amdgcn_rcpf(tc) : INFINITY;
           // groups of kG wavelengths: a group past the selection is skipped with a scalar
           // branch, the padded ones inside the last group are computed
 #pragma unroll
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256, NS > 32 ? 2 : 1) void render_kernel(
                 em = fmaf(em, dtau, -0.5f);
                 em = fmaf(em, dtau, 1.0f);
                 em = dtau < 0.125f ? em * dtau : 1.0f - att;
-                const float src = warm ? s_ap[q] * __builtin_amdgcn_rcpf(expm1_pos(s_hk[q] * inv_t)) : 0.0f;
+                const float src = s_ap[q] * __builtin_amdgcn_rcpf(expm1_pos(s_hk[q] * inv_t));
                 I32[q] = fmaf(I32[q], att, src * em);
               }
             }

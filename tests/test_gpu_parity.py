@@ -304,7 +304,8 @@ def test_render_fp32_against_oracle(torch, n_lambda):
     w = gen.c2(n_root=16, max_level=2, n_lambda=n_lambda, packets=1000)
     ora = oracle.Model(w.trees[0], w.dusts[0])
     rng = np.random.default_rng(6)
-    tn = np.where(ora.leaf_mask, rng.uniform(8, 40, ora.n_nodes), 0.0)
+    # a tenth of the leaves without a temperature: they attenuate and emit nothing
+    tn = np.where(ora.leaf_mask & (rng.random(ora.n_nodes) > 0.1), rng.uniform(8, 40, ora.n_nodes), 0.0)
     ctx = new_ctx(torch)
     m = ctx.build_tree(w.trees[0])
     ctx.set_dust(m, w.dusts[0])
