@@ -171,15 +171,18 @@ typedef struct {
   int32_t sweep_graph;      /* region schedule: > 0 replays a captured HIP graph of 16 sweeps
                                until the queues drain (per-pass durations are then not
                                reported); <= 0 (default) launches the same kernels directly */
-  int32_t split_n;          /* package splitting (paper Sect. 2.3), region schedule only: at a
+  int32_t split_n;          /* package splitting (paper Sect. 2.3), in the region schedule and
+                               the RT_FP64 form (there without subiterations, energy-flow tallies
+                               or peel-off; RT_EINVAL otherwise): at a
                                face crossing into a deeper leaf the package becomes split_n
                                packages of 1/split_n its weight (the new ones draw their own
                                free path); at a crossing into a shallower leaf it survives with
                                probability 1/split_n and its weight is multiplied by split_n.
                                0 or 1 = off, at most 64.  Records (rec_stride) follow the
                                package as emitted (branch 0).  A split that would overrun the
-                               sweep's queue room is skipped (counted in split_skips); either
-                               choice leaves every expectation unchanged */
+                               sweep's queue room (the FP64 form's queue of split-off packages,
+                               up to 2^22) is skipped (counted in split_skips); either choice
+                               leaves every expectation unchanged */
   int32_t split_depth;      /* with split_n > 1, what a "grid" is (Sect. 2.3): 0 (default) every
                                oct, so every change of level splits or roulettes; d > 0 all
                                levels below d belong to the grid of their level-d ancestor (d = 1:

@@ -81,6 +81,21 @@ struct PeelEv {
   int32_t lev;
 };
 
+// A package split off in the plain FP64 form (Sect. 2.3), waiting in a queue to be followed from
+// the cell where it was split: position, direction, weight and free path, the packet it came
+// from, its job, event count and branch identifier (128 bytes).
+struct Split64 {
+  double P[3], d[3];
+  double w, w0, tau;
+  int32_t node, lev;
+  int32_t I[3];
+  uint32_t pid;
+  int32_t job;
+  uint32_t ev;
+  uint32_t br;
+  int32_t pad[5];
+};
+
 struct TraceParams {
   const int32_t* word;
   const double* rho64;
@@ -131,6 +146,11 @@ struct TraceParams {
   PeelEv* peel_ev;
   unsigned long long* peel_count;
   unsigned long long peel_cap;
+  // package splitting in the plain FP64 form: packages split off are appended here (a split
+  // that does not fit is skipped and counted), and followed by launch_split_fp64
+  Split64* sq_out;
+  unsigned long long* sq_count;
+  unsigned long long sq_cap;
 };
 
 #define RT_PEEL_MAXDIR 16
@@ -286,6 +306,9 @@ hipError_t launch_blk_reduce(const ModelDev* models, const RegionDev* regions, i
 
 // Launch wrappers (defined in the .hip files)
 hipError_t launch_trace_fp64(const TraceParams& p, int job, uint64_t n, int block, hipStream_t s);
+// Follows the n packages in `in` (split off in the plain FP64 form); packages they split off in
+// turn go to p.sq_out.
+hipError_t launch_split_fp64(const TraceParams& p, const Split64* in, uint64_t n, int block, hipStream_t s);
 hipError_t launch_trace_fp32(const TraceParams& p, int grid, int block, hipStream_t s);
 hipError_t occupancy_trace_fp32(int block, int* blocks_per_cu);
 hipError_t launch_reduce_model(const ModelDev* models_dev, int model, int64_t n_nodes,

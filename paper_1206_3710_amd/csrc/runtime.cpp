@@ -122,6 +122,7 @@ struct rt_ctx {
   int32_t reg_maxn = 0;
   DevBuf d_regions, d_rword, d_rup, d_rcanon, d_root_region, d_split;
   DevBuf q_rec[2], q_key[2], q_perm, q_hist, q_kfill, q_bhist, q_items, q_state;
+  DevBuf sq[2], sq_cnt;  // plain FP64 form with splitting: queues of split-off packages
   int64_t q_capacity = 0;
   // sweep graph: kSweepBlock sweeps captured once per trace configuration, replayed
   hipGraphExec_t sweep_exec = nullptr;
@@ -555,6 +556,7 @@ rt_status rt_destroy(rt_ctx* ctx) {
                     &ctx->it_sum, &ctx->it_told, &ctx->it_crit, &ctx->d_regions, &ctx->d_rword,
                     &ctx->d_rup, &ctx->d_rcanon, &ctx->d_root_region, &ctx->d_split, &ctx->q_rec[0], &ctx->q_rec[1],
                     &ctx->q_key[0], &ctx->q_key[1], &ctx->q_perm, &ctx->q_hist, &ctx->q_kfill, &ctx->q_bhist,
+                    &ctx->sq[0], &ctx->sq[1], &ctx->sq_cnt,
                     &ctx->q_items, &ctx->q_state, &ctx->last_node, &ctx->t_tab, &ctx->it_self,
                     &ctx->it_emit, &ctx->peel_ev, &ctx->peel_ctr, &ctx->peel_tab, &ctx->peel_roottab,
                     &ctx->peel_tabroot, &ctx->peel_dnu, &ctx->peel_img, &ctx->g_jobs, &ctx->g_keys,
@@ -1014,8 +1016,8 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
     return fail(ctx, RT_EINVAL, "chunk_packets and batch_packets must be >= 0");
   if (o->split_n < 0 || o->split_n > 64) return fail(ctx, RT_EINVAL, "split_n must be in [0, 64]");
   if (o->split_depth < 0) return fail(ctx, RT_EINVAL, "split_depth must be >= 0");
-  if (o->split_n > 1 && !region_sched)
-    return fail(ctx, RT_EINVAL, "package splitting needs the FP32-local region schedule");
+  if (o->split_n > 1 && !region_sched && o->precision != RT_FP64)
+    return fail(ctx, RT_EINVAL, "package splitting runs in the region schedule or the RT_FP64 form");
   if (o->rec_stride < 0 || (o->rec_stride > 0 && !o->records))
     return fail(ctx, RT_EINVAL, "records needed when rec_stride > 0");
   for (int s = 0; s < n_src; ++s) {
@@ -1186,6 +1188,9 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
       return fail(ctx, RT_EINVAL, "subiterations in the region schedule take no splitting, peel-off, "
                                   "accelerated tally or per-wavelength output");
   }
+  if (!fp32 && p.split_n > 1 && (out.lvl_acc || out.sub_lev >= 0 || out.flux_acc || out.peel))
+    return fail(ctx, RT_EINVAL, "splitting in the RT_FP64 form takes no subiteration, energy-flow "
+                                "tally or peel-off");
   if (out.peel) {
     p.peel_ev = const_cast<PeelEv*>(out.peel->ev);
     p.peel_count = out.peel->count;
@@ -1300,6 +1305,20 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
       HIPCHK(launch_trace_fp32(p, ctx->n_cu * per_cu, bs, ctx->stream));
       main_launches = 1;
     } else {
+      // splitting: packages split off go to a queue, followed by launches over the queue (each
+      // appending to the other one) until it is empty
+      const unsigned long long sq_cap = (unsigned long long)std::min<int64_t>(int64_t(1) << 22,
+                                                                            std::max<int64_t>(4 * (int64_t)start, 4096));
+      unsigned long long* cnt = nullptr;
+      if (p.split_n > 1) {
+        for (int k = 0; k < 2; ++k) HIPCHK(ctx->sq[k].ensure(sizeof(Split64) * sq_cap));
+        HIPCHK(ctx->sq_cnt.ensure(2 * sizeof(unsigned long long)));
+        cnt = ctx->sq_cnt.as<unsigned long long>();
+        HIPCHK(hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned long long), ctx->stream));
+        p.sq_out = ctx->sq[0].as<Split64>();
+        p.sq_count = cnt;
+        p.sq_cap = sq_cap;
+      }
       // back-to-back launches on one stream: their summed durations are the span ev0 -> ev1
       for (size_t k = 0; k < jobs.size(); ++k)
         if (jobs[k].n > 0) {
@@ -1307,6 +1326,18 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
           ++main_launches;
           if (out.peel) HIPCHK(launch_peel(p, *out.peel, grid_peel, ctx->stream));
         }
+      for (int cur = 0, round = 0; p.split_n > 1; cur = 1 - cur, ++round) {
+        unsigned long long n_q = 0;
+        HIPCHK(hipMemcpyAsync(&n_q, cnt + cur, sizeof n_q, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (n_q == 0) break;
+        if (round > 100000) return fail(ctx, RT_EDEVICE, "split packages did not drain");
+        HIPCHK(hipMemsetAsync(cnt + (1 - cur), 0, sizeof(unsigned long long), ctx->stream));
+        p.sq_out = ctx->sq[1 - cur].as<Split64>();
+        p.sq_count = cnt + (1 - cur);
+        HIPCHK(launch_split_fp64(p, ctx->sq[cur].as<Split64>(), std::min(n_q, sq_cap), bs, ctx->stream));
+        ++main_launches;
+      }
     }
   }
   HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));

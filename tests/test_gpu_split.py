@@ -188,19 +188,83 @@ def test_split_room_exhausted_stays_unbiased(torch, n):
     assert abs(esc - w0 * math.exp(-tau)) < 4.0 * sd, (esc, w0 * math.exp(-tau), sd)
 
 
-def test_split_rejected_outside_region_schedule(torch):
+@pytest.mark.parametrize("n", [16, 64])
+def test_split_fp64_queue_exhausted_stays_unbiased(torch, n):
+    """The FP64 form's queue of split-off packages holds 4 per emitted packet here (16384 for
+    4096 beam packets), so with N - 1 = 15 or 63 new packages per split most splits do not fit
+    and are skipped, and the last reservation straddles the end of the queue (its slots inside
+    the queue are marked empty).  Crossing count, energy identity and the mean escaped energy
+    as for the region schedule."""
+    tree = gen.refined_block(2)
+    kappa = 0.2
+    dust = gen.Dust(np.array([1.0]), np.array([kappa]), np.array([0.0]), np.array([0.0]))
+    npk = 4096
+    src = [gen.Source(gen.SRC_BEAM, 0, pos=(0.3, 1.7, 2.2), dir=(1.0, 0.0, 0.0),
+                      power=np.array([1.0]), packets=npk)]
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    r = ctx.trace_packets(src, seed=11, precision=rt.FP64, split_n=n)
+    ctx.close()
+    st = r["stats"]
+    assert st["split_skips"] > 0 and st["splits"] > 0
+    assert st["splits"] + st["split_skips"] == npk
+    assert st["splits"] * (n - 1) <= 4 * npk
+    assert st["crossings"] == 10 * npk + 8 * (n - 1) * st["splits"]
+    assert energy_gap(st) < 1e-12
+    w0 = st["e_emit"] / npk
+    tau = kappa * (4.0 - 0.3)
+    esc = float(r["e_esc"].cpu().numpy()[0]) / npk
+    sd = w0 * math.exp(-tau) * math.sqrt((n - 1.0) / npk)
+    assert abs(esc - w0 * math.exp(-tau)) < 4.0 * sd, (esc, w0 * math.exp(-tau), sd)
+
+
+def test_split_rejected_in_the_one_queue_form(torch):
+    """Splitting runs in the region schedule and the FP64 form; the one-queue FP32-local form
+    and factors above 64 are rejected, and the context stays usable."""
     tree, dust, src, seed = _c1_case()
     ctx = rt.Context(0)
     m = ctx.build_tree(tree)
     ctx.set_dust(m, dust)
-    for kw in (dict(precision=rt.FP64), dict(precision=rt.FP32_LOCAL, schedule=rt.SCHED_GLOBAL)):
-        with pytest.raises(rt.RTError):
-            ctx.trace_packets(src, seed=seed, split_n=2, **kw)
     with pytest.raises(rt.RTError):
-        ctx.trace_packets(src, seed=seed, precision=rt.FP32_LOCAL, split_n=65)
-    r = ctx.trace_packets(src, seed=seed, precision=rt.FP32_LOCAL, split_n=2)
-    assert r["stats"]["splits"] > 0
+        ctx.trace_packets(src, seed=seed, split_n=2, precision=rt.FP32_LOCAL, schedule=rt.SCHED_GLOBAL)
+    for prec in (rt.FP32_LOCAL, rt.FP64):
+        with pytest.raises(rt.RTError):
+            ctx.trace_packets(src, seed=seed, precision=prec, split_n=65)
+        r = ctx.trace_packets(src, seed=seed, precision=prec, split_n=2)
+        assert r["stats"]["splits"] > 0
     ctx.close()
+
+
+@pytest.mark.parametrize("case,n,depth", [("c1", 2, 0), ("c1", 4, 0), ("box", 4, 0), ("box", 8, 0),
+                                          ("rand", 4, 0), ("rand", 4, 1), ("rand", 3, 2)])
+def test_split_fp64_equals_oracle(torch, case, n, depth):
+    """The FP64 form with splitting follows the oracle's histories exactly: every main-line
+    record (fate, crossings, events, end node, birth) equal and its weight to 1e-9; the counts
+    of splits, exit-roulette kills, crossings, scatterings and event kills equal over all
+    branches; the absorbed energy per node and the escaped energy to 1e-9 (the order of the
+    FP64 atomic sums), with the split packages followed from a queue in later launches."""
+    tree, dust, src, seed = {"c1": _c1_case, "box": _box_case, "rand": _rand_case}[case]()
+    kw = dict(rr_threshold=1e-2, rr_prob=0.8, split_n=n, split_depth=depth)
+    ora = oracle.Model(tree, dust)
+    eo, esco, sto, reco = ora.trace(src, seed=seed, rec_stride=1, **kw)
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    r = ctx.trace_packets(src, seed=seed, precision=rt.FP64, rec_stride=1, **kw)
+    ctx.close()
+    st, rg = r["stats"], r["records"]
+    assert st["split_skips"] == 0 and sto["splits"] > 0 and sto["split_kills"] > 0
+    for f in ("status", "crossings", "events", "node", "birth"):
+        assert np.array_equal(rg[f], reco[f]), f
+    np.testing.assert_allclose(rg["w"], reco["w"], rtol=1e-9)
+    for k in ("splits", "split_kills", "crossings", "scatterings", "kills", "packets"):
+        assert st[k] == sto[k], (k, st[k], sto[k])
+    for k in ("e_split_gain", "e_split_killed", "e_rr_gain", "e_killed", "e_emit"):
+        assert abs(st[k] - sto[k]) <= 1e-9 * abs(sto[k]) + 1e-300, (k, st[k], sto[k])
+    np.testing.assert_allclose(r["e_abs_node"].cpu().numpy(), eo, rtol=1e-9, atol=1e-12 * eo.max())
+    np.testing.assert_allclose(r["e_esc"].cpu().numpy(), esco, rtol=1e-9)
+    assert energy_gap(st) < 1e-12
 
 
 def test_split_reduces_noise_in_refined_block(torch):
