@@ -54,14 +54,14 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0
 # autotuner picks for the workload (given explicitly to those runs).  Valid only for the kernel
 # sources the counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "547fa738d451d97cca576e0a7d6a6bd565b247d832d99a8a6673098f04dd8012",
+                "sha256": "087011ce6a3f3acea64dcb38b0c2ca0363df9a43b30b22376bbb79efed8ee2bf",
                 "per_workload": {
                     # profiles/blk_pass_kernel_deep_hierarchy_cloud.md
-                    "deep": {"fetch_bytes_per_crossing": 10.8474, "write_bytes_per_crossing": 5.0755,
+                    "deep": {"fetch_bytes_per_crossing": 10.8534, "write_bytes_per_crossing": 5.0754,
                              "valu_per_crossing": 2.7222, "lane_utilisation": 0.5549},
                     # profiles/blk_pass_kernel_molecular_cloud.md
-                    "cloud": {"fetch_bytes_per_crossing": 10.8669, "write_bytes_per_crossing": 6.3948,
-                              "valu_per_crossing": 4.0900, "lane_utilisation": 0.4205}}}
+                    "cloud": {"fetch_bytes_per_crossing": 10.8687, "write_bytes_per_crossing": 6.3949,
+                              "valu_per_crossing": 4.0908, "lane_utilisation": 0.4205}}}
 
 
 WORKLOADS = {
