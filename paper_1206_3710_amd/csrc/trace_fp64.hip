@@ -20,7 +20,9 @@ struct Tally64 {
 
 // Follows one package (state k, weight w, free path tau, crossings and events so far, branch br
 // of packet pid) to its end.  Returns the fate: 0 escaped, 1 killed by the event roulette,
-// 2 truncated, 3 killed by the exit roulette of splitting.
+// 2 truncated, 3 killed by the exit roulette of splitting.  SPLIT: package splitting is on
+// (the instance without it keeps the registers of the plain walk).
+template <bool SPLIT>
 __device__ int follow64(const TraceParams& p, const int job_idx, const JobDev& job, const ModelDev& md,
                         const Dims& D, const ChildPlain& ch, const uint32_t pid, const uint32_t br, Pk64& k,
                         double& w, const double w0, double& tau, uint32_t& crossings, uint32_t& ev, int& mlev,
@@ -28,6 +30,7 @@ __device__ int follow64(const TraceParams& p, const int job_idx, const JobDev& j
   const double kext = job.kext, alb = job.alb, g = job.g, cm = md.cell_cm;
   double* __restrict__ acc = p.acc64 + job.acc_off;
   const int N = p.split_n;
+  int status = 0;
   for (;;) {
     const double rho = p.rho64[k.node];
     const double se = (kext * rho) * cm;
@@ -81,9 +84,8 @@ __device__ int follow64(const TraceParams& p, const int job_idx, const JobDev& j
     if (event) {
       ++ev;
       if ((int64_t)ev > p.max_events) {
-        T.truncs += 1;
-        T.trunc += w;
-        return 2;
+        status = 2;
+        break;
       }
       ++T.scat;
       if (p.peel_ev) {
@@ -106,9 +108,8 @@ __device__ int follow64(const TraceParams& p, const int job_idx, const JobDev& j
       const uint4 x = philox(pid, job.stream, ev, br << 2, p.key0, p.key1);
       if (p.rr_p > 0.0 && w < p.rr_thr * w0) {
         if (unif64(x.x) < p.rr_p) {
-          T.kills += 1;
-          T.kill += w;
-          return 1;
+          status = 1;
+          break;
         }
         const double nw = w / (1.0 - p.rr_p);
         T.gain += nw - w;
@@ -131,8 +132,8 @@ __device__ int follow64(const TraceParams& p, const int job_idx, const JobDev& j
     const int old_lev = k.lev;
     int32_t raw;
     if (!cross_walk(D, p.up, ax, sg, k.node, k.lev, k.I, raw, ch)) {
-      T.esc += w;
-      return 0;
+      status = 0;
+      break;
     }
     // a refined neighbour at the original level: near side on the crossing axis, midpoint
     // rule on the others
@@ -153,16 +154,15 @@ __device__ int follow64(const TraceParams& p, const int job_idx, const JobDev& j
     }
     if (p.sub_lev >= 0 && !in_subtree(p.sub_lev, p.sub_I, k.lev, k.I[0], k.I[1], k.I[2])) {
       // a subiteration follows packets only inside its subtree
-      T.esc += w;
-      return 0;
+      status = 0;
+      break;
     }
     if (k.lev < mlev) mlev = k.lev;
     if (++crossings >= (1u << 30)) {  // guards termination; never reached by valid input
-      T.truncs += 1;
-      T.trunc += w;
-      return 2;
+      status = 2;
+      break;
     }
-    if (N > 1) {
+    if (SPLIT && N > 1) {
       // splitting: the level of the grid the package is in (a grid holds the levels down to
       // split_depth below its top cell)
       const int gl_old = old_lev < p.split_depth ? old_lev : p.split_depth;
@@ -210,13 +210,26 @@ __device__ int follow64(const TraceParams& p, const int job_idx, const JobDev& j
           T.sgain += nw - w;
           w = nw;
         } else {
-          T.skills += 1;
-          T.skilled += w;
-          return 3;
+          status = 3;
+          break;
         }
       }
     }
   }
+  // the package's end, with its weight there
+  if (status == 0) {
+    T.esc += w;
+  } else if (status == 1) {
+    T.kills += 1;
+    T.kill += w;
+  } else if (status == 2) {
+    T.truncs += 1;
+    T.trunc += w;
+  } else {
+    T.skills += 1;
+    T.skilled += w;
+  }
+  return status;
 }
 
 __device__ __forceinline__ void flush_tallies(const TraceParams& p, int esc_slot, Tally64& T, double t_emit,
@@ -247,6 +260,7 @@ __device__ __forceinline__ void flush_tallies(const TraceParams& p, int esc_slot
   }
 }
 
+template <bool SPLIT>
 __global__ __launch_bounds__(256) void trace_fp64_kernel(const TraceParams p, const int job_idx) {
   const JobDev& job = p.jobs[job_idx];
   const ModelDev& md = p.models[job.model];
@@ -270,7 +284,7 @@ __global__ __launch_bounds__(256) void trace_fp64_kernel(const TraceParams p, co
     // shallowest level visited: the external field enters through the root grid
     int mlev = job.kind == RT_SRC_BACKGROUND ? 0 : k.lev;
     uint32_t crossings = 1, ev = 0;
-    const int status = follow64(p, job_idx, job, md, D, ch, (uint32_t)j, 0u, k, w, w0, tau, crossings, ev, mlev, T);
+    const int status = follow64<SPLIT>(p, job_idx, job, md, D, ch, (uint32_t)j, 0u, k, w, w0, tau, crossings, ev, mlev, T);
     T.cross += crossings;
     if (p.rec_stride > 0 && (j % (uint64_t)p.rec_stride) == 0) {
       rt_record r;
@@ -312,7 +326,7 @@ __global__ __launch_bounds__(256) void split_fp64_kernel(const TraceParams p, co
     // its cell was counted by the package it split from
     uint32_t crossings = 0, ev = q.ev;
     int mlev = 0;
-    (void)follow64(p, q.job, job, md, D, ch, q.pid, q.br, k, w, q.w0, tau, crossings, ev, mlev, T);
+    (void)follow64<true>(p, q.job, job, md, D, ch, q.pid, q.br, k, w, q.w0, tau, crossings, ev, mlev, T);
     T.cross += crossings;
     esc_slot = job.esc_slot;
   }
@@ -326,7 +340,8 @@ __global__ __launch_bounds__(256) void split_fp64_kernel(const TraceParams p, co
 
 hipError_t launch_trace_fp64(const TraceParams& p, int job, uint64_t n, int block, hipStream_t s) {
   const uint64_t grid = (n + block - 1) / block;
-  hipLaunchKernelGGL(trace_fp64_kernel, dim3((unsigned)grid), dim3(block), 0, s, p, job);
+  if (p.split_n > 1) hipLaunchKernelGGL(trace_fp64_kernel<true>, dim3((unsigned)grid), dim3(block), 0, s, p, job);
+  else hipLaunchKernelGGL(trace_fp64_kernel<false>, dim3((unsigned)grid), dim3(block), 0, s, p, job);
   return hipGetLastError();
 }
 
