@@ -232,8 +232,11 @@ __device__ int follow64(const TraceParams& p, const int job_idx, const JobDev& j
   return status;
 }
 
+// Adds a wave's tallies to the totals.  followed: this lane followed a package (a split-off
+// package may end, by the event roulette or an escape, before its first crossing, so neither
+// the packet count nor the crossings tell whether a wave has something to add).
 __device__ __forceinline__ void flush_tallies(const TraceParams& p, int esc_slot, Tally64& T, double t_emit,
-                                              unsigned long long c_pk) {
+                                              unsigned long long c_pk, bool followed) {
   const double t_esc = wave_sum(T.esc), e_emit = wave_sum(t_emit), t_kill = wave_sum(T.kill),
                t_gain = wave_sum(T.gain), t_trunc = wave_sum(T.trunc), t_sk = wave_sum(T.skilled),
                t_sg = wave_sum(T.sgain);
@@ -241,7 +244,8 @@ __device__ __forceinline__ void flush_tallies(const TraceParams& p, int esc_slot
                            c_kill = wave_sum_u64(T.kills), c_trunc = wave_sum_u64(T.truncs),
                            c_split = wave_sum_u64(T.splits), c_skill = wave_sum_u64(T.skills),
                            c_sskip = wave_sum_u64(T.sskips), n_pk = wave_sum_u64(c_pk);
-  if ((threadIdx.x & 63) == 0 && (n_pk > 0 || c_cross > 0)) {
+  const bool any = __ballot(followed) != 0;  // every lane takes part in the vote
+  if ((threadIdx.x & 63) == 0 && any) {
     unsafeAtomicAdd(p.esc + esc_slot, t_esc);
     if (e_emit != 0.0) unsafeAtomicAdd(&p.stats->e_emit, e_emit);
     if (t_kill != 0.0) unsafeAtomicAdd(&p.stats->e_killed, t_kill);
@@ -298,7 +302,7 @@ __global__ __launch_bounds__(256) void trace_fp64_kernel(const TraceParams p, co
       p.rec[job.rec_base + (int64_t)(j / (uint64_t)p.rec_stride)] = r;
     }
   }
-  flush_tallies(p, job.esc_slot, T, t_emit, c_pk);
+  flush_tallies(p, job.esc_slot, T, t_emit, c_pk, c_pk != 0);
 }
 
 // Packages split off in the FP64 form, one per lane, from where they were split.
@@ -307,7 +311,8 @@ __global__ __launch_bounds__(256) void split_fp64_kernel(const TraceParams p, co
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   Tally64 T;
   int esc_slot = 0;
-  if (i < n && in[i].job >= 0) {
+  const bool followed = i < n && in[i].job >= 0;
+  if (followed) {
     const Split64 q = in[i];
     const JobDev& job = p.jobs[q.job];
     const ModelDev& md = p.models[job.model];
@@ -333,7 +338,7 @@ __global__ __launch_bounds__(256) void split_fp64_kernel(const TraceParams p, co
   // a wave's packages may belong to different jobs: escapes are added lane by lane
   if (T.esc != 0.0) unsafeAtomicAdd(p.esc + esc_slot, T.esc);
   T.esc = 0.0;
-  flush_tallies(p, esc_slot, T, 0.0, 0);
+  flush_tallies(p, esc_slot, T, 0.0, 0, followed);
 }
 
 }  // namespace

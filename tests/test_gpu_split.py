@@ -267,6 +267,32 @@ def test_split_fp64_equals_oracle(torch, case, n, depth):
     assert energy_gap(st) < 1e-12
 
 
+def test_split_fp64_counts_packages_that_end_before_a_crossing(torch):
+    """Split-off packages in an optically thick block (40 per root cell) with the event roulette
+    on every event nearly all scatter and are killed in the cell they were split in, with no
+    crossing of their own; whole waves of the queue launches end that way.  Their scatterings,
+    kills and killed energy still reach the totals: the counts equal the oracle's and the
+    energy identity holds."""
+    tree = gen.refined_block(2)
+    dust = gen.Dust(np.array([1.0]), np.array([40.0]), np.array([0.9]), np.array([0.0]))
+    src = [gen.Source(gen.SRC_POINT, 0, pos=(0.99, 2.1, 2.2), power=np.array([1.0]), packets=4000)]
+    kw = dict(rr_threshold=1.0, rr_prob=0.99, split_n=8, split_depth=0)
+    eo, esco, sto, _ = oracle.Model(tree, dust).trace(src, seed=29, rec_stride=0, **kw)
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    r = ctx.trace_packets(src, seed=29, precision=rt.FP64, **kw)
+    ctx.close()
+    st = r["stats"]
+    assert sto["splits"] > 500 and sto["kills"] > 2 * sto["packets"]
+    for k in ("splits", "split_kills", "crossings", "scatterings", "kills", "packets"):
+        assert st[k] == sto[k], (k, st[k], sto[k])
+    for k in ("e_split_gain", "e_split_killed", "e_rr_gain", "e_killed", "e_emit"):
+        assert abs(st[k] - sto[k]) <= 1e-9 * abs(sto[k]) + 1e-300, (k, st[k], sto[k])
+    np.testing.assert_allclose(r["e_abs_node"].cpu().numpy(), eo, rtol=1e-9, atol=1e-12 * eo.max())
+    assert energy_gap(st) < 1e-12
+
+
 def test_split_reduces_noise_in_refined_block(torch):
     """The oracle's noise pin on the GPU: strongly scattering block refined three levels deep in
     an isotropic field, same number of emitted packages; splitting by 4 lowers the relative RMS
