@@ -171,18 +171,17 @@ typedef struct {
   int32_t sweep_graph;      /* region schedule: > 0 replays a captured HIP graph of 16 sweeps
                                until the queues drain (per-pass durations are then not
                                reported); <= 0 (default) launches the same kernels directly */
-  int32_t split_n;          /* package splitting (paper Sect. 2.3), in the region schedule and
-                               the RT_FP64 form (there without subiterations, energy-flow tallies
-                               or peel-off; RT_EINVAL otherwise): at a
-                               face crossing into a deeper leaf the package becomes split_n
-                               packages of 1/split_n its weight (the new ones draw their own
-                               free path); at a crossing into a shallower leaf it survives with
-                               probability 1/split_n and its weight is multiplied by split_n.
-                               0 or 1 = off, at most 64.  Records (rec_stride) follow the
-                               package as emitted (branch 0).  A split that would overrun the
-                               sweep's queue room (the FP64 form's queue of split-off packages,
-                               up to 2^22) is skipped (counted in split_skips); either choice
-                               leaves every expectation unchanged */
+  int32_t split_n;          /* package splitting (paper Sect. 2.3), in the RT_FP64 form and the
+                               region schedule (RT_EINVAL in the one-queue FP32 form): at a
+                               face crossing into a deeper leaf the package
+                               becomes split_n packages of 1/split_n its weight (the new ones
+                               draw their own free path); at a crossing into a shallower leaf
+                               it survives with probability 1/split_n and its weight is
+                               multiplied by split_n.  0 or 1 = off, at most 64.  Records
+                               (rec_stride) follow the package as emitted (branch 0).  A split
+                               that would overrun the sweep's queue room (the FP64 form's queue
+                               of split-off packages, up to 2^22) is skipped (counted in
+                               split_skips); either choice leaves every expectation unchanged */
   int32_t split_depth;      /* with split_n > 1, what a "grid" is (Sect. 2.3): 0 (default) every
                                oct, so every change of level splits or roulettes; d > 0 all
                                levels below d belong to the grid of their level-d ancestor (d = 1:
@@ -260,8 +259,10 @@ rt_status rt_ali_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_sou
                          const rt_trace_opts* opts, int64_t dust_packets, int32_t n_max, double tol,
                          double t_min, double t_max, double* t_node, int32_t* n_done, double* crit);
 
-/* Subiterations on complete subtrees (Sect. 3.1, Sect. 3.3, App. B), in the RT_FP64 form or
- * the RT_FP32_LOCAL region schedule (without package splitting; RT_EINVAL otherwise).
+/* Subiterations on complete subtrees (Sect. 3.1, Sect. 3.3, App. B), in the RT_FP64 form or the
+ * RT_FP32_LOCAL region schedule (RT_EINVAL in the one-queue FP32 form), with or without package
+ * splitting (a split-off package inherits the shallowest level visited of the package it split
+ * from).
  * rt_subiter_begin traces the constant sources (key iteration opts->iteration) into A_stars,
  * solves T_0 and clears the model's per-level arrays (one absorbed-energy array per hierarchy
  * level at or above each cell's own).  flux_frac > 0 turns on the tracking of the energy flow

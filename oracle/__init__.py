@@ -374,18 +374,21 @@ def ali_step_absorbed(a_stars, a_dust, e_self, e_emit_node):
 
 
 def subiterate(model, star_sources, seed, schedule, dust_packets, rr_threshold=0.0, rr_prob=0.0,
-               t_min=2.0, t_max=3000.0):
+               t_min=2.0, t_max=3000.0, split_n=1, split_depth=0):
     """Lambda iteration with subiterations on complete subtrees (paper Sect. 3.1 and App. B).
     ``schedule``: the subtree root of each step, a refined node or -1 for the whole model.  Each
     cell keeps one absorbed-energy array per hierarchy level above or at its own; a step with
     root r (level l_r) traces the dust emission of r's subtree only, keeps its packages inside
     it, and replaces the arrays of levels > l_r (all levels for the whole model) of the cells in
     the subtree with what it deposits; the temperatures of those cells then follow from
-    A_stars + the sum of their arrays (Eq. 9).  Key iteration of step k is k.  Returns
-    (temperature after each step, A_stars, per-step trace statistics)."""
+    A_stars + the sum of their arrays (Eq. 9).  Key iteration of step k is k.  ``split_n`` > 1:
+    package splitting (Sect. 2.3) in every trace, a split-off package filing its deposits under
+    the shallowest level of the package it split from.  Returns (temperature after each step,
+    A_stars, per-step trace statistics)."""
     import gen
+    sp = dict(split_n=split_n, split_depth=split_depth)
     a_stars, _, _, _ = model.trace(star_sources, seed, iteration=0, rr_threshold=rr_threshold,
-                                   rr_prob=rr_prob)
+                                   rr_prob=rr_prob, **sp)
     t = model.solve_temperature(a_stars, t_min, t_max)
     lv = model.level_of_nodes()
     arrays = np.zeros((model.n_levels + 1, model.n_nodes))
@@ -395,7 +398,7 @@ def subiterate(model, star_sources, seed, schedule, dust_packets, rr_threshold=0
         mask = model.subtree_mask(root)
         src = [gen.Source(gen.SRC_DUST, 0, packets=dust_packets)]
         _, _, st, _ = model.trace(src, seed, iteration=it, rr_threshold=rr_threshold,
-                                  rr_prob=rr_prob, t_node=t, level_arrays=True, subtree=root)
+                                  rr_prob=rr_prob, t_node=t, level_arrays=True, subtree=root, **sp)
         stats.append(st)
         arrays[lo:, mask] = st["e_lvl"][lo:, mask]
         t_new = model.solve_temperature(a_stars + arrays.sum(axis=0), t_min, t_max)
@@ -444,7 +447,8 @@ def subtree_select(imb, frac, parent, tagged, tag_root):
 
 
 def subiterate_auto(model, star_sources, seed, n_steps, dust_packets, frac=0.5, stall=0.8,
-                    flux_frac=0.0, rr_threshold=0.0, rr_prob=0.0, t_min=2.0, t_max=3000.0):
+                    flux_frac=0.0, rr_threshold=0.0, rr_prob=0.0, t_min=2.0, t_max=3000.0,
+                    split_n=1, split_depth=0):
     """The automatic iteration of Sect. 3.3 over subiterations on complete subtrees (Sect. 3.1,
     App. B), step by step from the oracle's own bookkeeping:
       * per leaf, the energy imbalance |A - E(T_old)| / E(T_old) recorded at its last step, with
@@ -457,10 +461,12 @@ def subiterate_auto(model, star_sources, seed, n_steps, dust_packets, frac=0.5, 
         step; when a step below r changes the flow out of r's subtree by more than flux_frac
         times the energy absorbed in its parent's subtree (since the parent last took part), the
         parent grid is tagged until a step includes it.
-    Key iteration of step k is k.  Returns (temperatures after each step, the roots taken)."""
+    Key iteration of step k is k; ``split_n``, ``split_depth`` as for subiterate.  Returns
+    (temperatures after each step, the roots taken)."""
     import gen
+    sp = dict(split_n=split_n, split_depth=split_depth)
     a_stars, _, _, _ = model.trace(star_sources, seed, iteration=0, rr_threshold=rr_threshold,
-                                   rr_prob=rr_prob)
+                                   rr_prob=rr_prob, **sp)
     t = model.solve_temperature(a_stars, t_min, t_max)
     lv = model.level_of_nodes()
     leaf = model.leaf_mask
@@ -484,7 +490,7 @@ def subiterate_auto(model, star_sources, seed, n_steps, dust_packets, frac=0.5, 
         src = [gen.Source(gen.SRC_DUST, 0, packets=dust_packets)]
         _, _, st, _ = model.trace(src, seed, iteration=k + 1, rr_threshold=rr_threshold,
                                   rr_prob=rr_prob, t_node=t, level_arrays=True, subtree=root,
-                                  flux=flux_frac > 0.0)
+                                  flux=flux_frac > 0.0, **sp)
         arrays[lo:, mask] = st["e_lvl"][lo:, mask]
         a_tot = a_stars + arrays.sum(axis=0)
         e_old = model.emission_all(t)

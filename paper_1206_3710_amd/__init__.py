@@ -389,7 +389,8 @@ class Context:
                          kw.get("block_size", 0), kw.get("blocks_per_cu", 0),
                          kw.get("refill_threshold", 0.0), kw.get("schedule", SCHED_REGIONS),
                          kw.get("chunk_packets", 0), kw.get("tail_park", 0),
-                         kw.get("batch_packets", 0), 0, None, 0, kw.get("split_n", 0))
+                         kw.get("batch_packets", 0), 0, None, 0, kw.get("split_n", 0),
+                         kw.get("split_depth", 0))
 
     def subiter_begin(self, model: int, sources: Sequence, seed: int, t_min: float = 2.0,
                       t_max: float = 3000.0, iteration: int = 0, rr_threshold: float = 0.0,

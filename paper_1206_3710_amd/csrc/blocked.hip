@@ -669,7 +669,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
             rc.lev = (uint8_t)lev;
             rc.ax = 0;
             rc.sg = 0;
-            rc.flag = 2;
+            rc.flag = (uint8_t)(2 | (LVL ? mlev << 2 : 0));
             rc.x[0] = x0;
             rc.x[1] = x1;
             rc.x[2] = x2;
@@ -691,7 +691,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
               rc.tau = -logf(unif32(xr.x));
               rc.birth = (int32_t)bc;
               b.u_out[idx] = rc;
-              b.u_key[idx] = own_key;
+              // subiterations: a split-off package keeps the shallowest level of its parent
+              b.u_key[idx] = LVL ? (uint32_t)mlev * (uint32_t)b.n_regions + (uint32_t)it.region : own_key;
             }
             w = wn;
             ++c_split;
@@ -1028,9 +1029,10 @@ static hipError_t launch_pass(const BlkParams& b, int grid, int block, int lds_b
 hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s) {
   const bool split = b.t.split_n > 1, peel = b.t.peel_ev != nullptr, ali = b.t.self_acc != nullptr;
   if (b.lvl_slots > 0) {
-    // the per-level arrays need one FP64 accumulator slot per level; nothing else rides along
-    if (split || peel || ali || !b.accb64) return hipErrorInvalidValue;
-    return launch_pass<false, false, false, true>(b, grid, block, lds_bytes, s);
+    // the per-level arrays need one FP64 accumulator slot per level; only splitting rides along
+    if (peel || ali || !b.accb64) return hipErrorInvalidValue;
+    return split ? launch_pass<true, false, false, true>(b, grid, block, lds_bytes, s)
+                 : launch_pass<false, false, false, true>(b, grid, block, lds_bytes, s);
   }
   if (ali) {
     if (peel) return hipErrorInvalidValue;

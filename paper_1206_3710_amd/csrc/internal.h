@@ -93,8 +93,10 @@ struct Split64 {
   int32_t job;
   uint32_t ev;
   uint32_t br;
-  int32_t pad[5];
+  int32_t mlev;  // shallowest level visited by the package it split from (subiterations)
+  int32_t pad[4];
 };
+static_assert(sizeof(Split64) == 128, "split package layout");
 
 struct TraceParams {
   const int32_t* word;

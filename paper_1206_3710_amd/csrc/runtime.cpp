@@ -1184,13 +1184,10 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   if ((out.lvl_acc || out.sub_lev >= 0) && fp32) {
     if (o->schedule != RT_SCHED_REGIONS)
       return fail(ctx, RT_EINVAL, "subiterations run in the RT_FP64 form or the region schedule");
-    if (!out.lvl_acc || p.split_n > 1 || out.peel || out.self_acc || out.e_lamnode)
-      return fail(ctx, RT_EINVAL, "subiterations in the region schedule take no splitting, peel-off, "
-                                  "accelerated tally or per-wavelength output");
+    if (!out.lvl_acc || out.peel || out.self_acc || out.e_lamnode)
+      return fail(ctx, RT_EINVAL, "subiterations in the region schedule take no peel-off, accelerated "
+                                  "tally or per-wavelength output");
   }
-  if (!fp32 && p.split_n > 1 && (out.lvl_acc || out.sub_lev >= 0 || out.flux_acc || out.peel))
-    return fail(ctx, RT_EINVAL, "splitting in the RT_FP64 form takes no subiteration, energy-flow "
-                                "tally or peel-off");
   if (out.peel) {
     p.peel_ev = const_cast<PeelEv*>(out.peel->ev);
     p.peel_count = out.peel->count;
@@ -1337,6 +1334,7 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
         p.sq_count = cnt + (1 - cur);
         HIPCHK(launch_split_fp64(p, ctx->sq[cur].as<Split64>(), std::min(n_q, sq_cap), bs, ctx->stream));
         ++main_launches;
+        if (out.peel) HIPCHK(launch_peel(p, *out.peel, grid_peel, ctx->stream));
       }
     }
   }

@@ -192,6 +192,7 @@ __device__ int follow64(const TraceParams& p, const int job_idx, const JobDev& j
             q.job = job_idx;
             q.ev = ev;
             q.br = bc;
+            q.mlev = mlev;
           }
           w = wn;
           T.splits += 1;
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(256) void split_fp64_kernel(const TraceParams p, co
     double w = q.w, tau = q.tau;
     // its cell was counted by the package it split from
     uint32_t crossings = 0, ev = q.ev;
-    int mlev = 0;
+    int mlev = q.mlev;
     (void)follow64<true>(p, q.job, job, md, D, ch, q.pid, q.br, k, w, q.w0, tau, crossings, ev, mlev, T);
     T.cross += crossings;
     esc_slot = job.esc_slot;

@@ -57,13 +57,14 @@ def rel_rms(a, ref):
     return float(np.sqrt(((a - ref) ** 2).sum() / (ref ** 2).sum()))
 
 
-@pytest.mark.parametrize("case", ["box", "random"])
+@pytest.mark.parametrize("case,split_n", [("box", 1), ("random", 1), ("random", 4)])
 @pytest.mark.parametrize("tiles", [0, 3])
-def test_peel_fp64_against_oracle(torch, case, tiles):
+def test_peel_fp64_against_oracle(torch, case, tiles, split_n):
     """Per pixel |I_gpu - I_ora| <= 1e-9 |I_ora| + 1e-12 max I_ora; as many events peeled as
-    the oracle scattered."""
+    the oracle scattered (with splitting: the events of the split-off packages too, peeled
+    after each launch over their queue)."""
     tree, dust, src = _scattering_box() if case == "box" else _random_tree_case()
-    kw = dict(rr_threshold=0.05, rr_prob=0.5)
+    kw = dict(rr_threshold=0.05, rr_prob=0.5, split_n=split_n)
     ora = oracle.Model(tree, dust)
     _, _, sto, _ = ora.trace(src, seed=9, peel=dict(n_obs=DIRS, npix=12, width=6.0, tiles=tiles), **kw)
     ctx = _ctx(tree, dust)

@@ -72,6 +72,31 @@ def test_subiterations_fp64_against_oracle(torch):
     ctx.close()
 
 
+def test_subiterations_fp64_split_against_oracle(torch):
+    """The same schedule with package splitting (factor 4, every level change) in both: split-off
+    packages file their deposits under the shallowest level of the package they split from and
+    end at the subtree's border like any other; temperatures after every step within 1e-6."""
+    tree, dust, star = _block_case()
+    root = 2 + 4 * (1 + 4 * 2)
+    schedule = [-1, root, -1]
+    o = oracle.Model(tree, dust)
+    hist, _, stats = oracle.subiterate(o, star, seed=8, schedule=schedule, dust_packets=3000, split_n=4)
+    assert stats[0]["splits"] > 0
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    ctx.subiter_begin(m, star, seed=8, split_n=4)
+    for k, r in enumerate(schedule, start=1):
+        t, crit, st = ctx.subiter_step(m, r, dust_packets=3000, seed=8, iteration=k, split_n=4)
+        np.testing.assert_allclose(t.cpu().numpy(), hist[k], rtol=1e-6, err_msg=f"step {k}")
+        # at the shortest wavelength a package scatters some 600 times; over such histories the
+        # last-bit differences of the device's and the host's log, sin and cos move a few
+        # packages across a face differently, so the counts agree only to a few per cent
+        assert abs(st["splits"] - stats[k - 1]["splits"]) <= 0.05 * stats[k - 1]["splits"] + 1
+        assert st["split_skips"] == 0
+    ctx.close()
+
+
 def _reference_select(o, imbalance, frac):
     """Lowest common ancestor of the leaves within frac of the largest imbalance (-1: the whole
     model), from the oracle's tree."""
@@ -197,6 +222,34 @@ def test_subiterations_regions_against_oracle(torch):
     ctx.close()
 
 
+def test_subiterations_regions_split_against_oracle(torch):
+    """Package splitting (factor 4) inside subiterations of the region schedule: a split-off
+    record is queued under the shallowest level of the package it split from, so the level
+    arrays, and the temperatures, follow the oracle's split subiterations far below the noise
+    between two of its runs with different seeds."""
+    tree, dust, star = _block_case()
+    root = 2 + 4 * (1 + 4 * 2)
+    schedule = [-1, root, -1]
+    o = oracle.Model(tree, dust)
+    ha, _, sa = oracle.subiterate(o, star, seed=8, schedule=schedule, dust_packets=3000, split_n=4)
+    hb, _, _ = oracle.subiterate(o, star, seed=41, schedule=schedule, dust_packets=3000, split_n=4)
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    kw = dict(precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS, split_n=4)
+    ctx.subiter_begin(m, star, seed=8, **kw)
+    for k, r in enumerate(schedule, start=1):
+        t, crit, st = ctx.subiter_step(m, r, dust_packets=3000, seed=8, iteration=k, **kw)
+        err = _mass_weighted_diff(o, t.cpu().numpy(), ha[k])
+        noise = _mass_weighted_diff(o, hb[k], ha[k])
+        assert err < 0.1 * noise, (k, err, noise)
+        assert st["split_skips"] == 0
+        # FP32 histories of some 600 events part from the oracle's: the split count is another
+        # Monte Carlo sample (its seed-to-seed spread here is about 7 %)
+        assert abs(st["splits"] - sa[k - 1]["splits"]) <= 0.2 * sa[k - 1]["splits"] + 1
+    ctx.close()
+
+
 def test_subtree_selection_regions(torch):
     """The region schedule's whole-model step records the same imbalances as the FP64 form's up
     to the FP32 rounding of the histories: the same subtree is chosen."""
@@ -224,8 +277,6 @@ def test_subiterations_regions_reject_other_options(torch):
     with pytest.raises(rt.RTError):  # the one-queue FP32 form keeps no level arrays
         ctx.subiter_begin(m, star, seed=1, precision=rt.FP32_LOCAL, schedule=rt.SCHED_GLOBAL)
     ctx.subiter_begin(m, star, seed=1, **kw)
-    with pytest.raises(rt.RTError):  # no package splitting inside a subiteration
-        ctx.subiter_step(m, -1, dust_packets=100, seed=1, iteration=1, split_n=2, **kw)
     t, _, _ = ctx.subiter_step(m, -1, dust_packets=100, seed=1, iteration=1, **kw)
     assert float(t.max()) > 0.0
     ctx.close()
@@ -255,6 +306,29 @@ def test_automatic_iteration_against_oracle_fp64(torch):
         assert [int(v) for v in r] == roots[:k], (k, list(r), roots)
         np.testing.assert_allclose(t.cpu().numpy()[leaf], hist[k][leaf], rtol=1e-6)
     ctx.close()
+
+
+def test_automatic_iteration_with_splitting_against_oracle_fp64(torch):
+    """The automatic iteration with the flow tracking and package splitting (factor 2, every
+    level change; split-off packages add to the flow out of each subtree they leave), FP64
+    form: the oracle's roots at every step and its temperatures after the last within 1e-6."""
+    w = gen.core_cloud(packets=20000)
+    tree, dust = w.trees[0], w.dusts[0]
+    kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob, split_n=2)
+    o = oracle.Model(tree, dust)
+    n = 5
+    hist, roots = oracle.subiterate_auto(o, w.sources, seed=w.seed, n_steps=n, dust_packets=20000, frac=0.5,
+                                         stall=0.8, flux_frac=0.02, **kw)
+    assert any(r >= 0 for r in roots), roots
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    ctx.subiter_begin(m, w.sources, seed=w.seed, flux_frac=0.02, **kw)
+    t, r, crit, cross = ctx.subiter_run(m, n, dust_packets=20000, seed=w.seed, frac=0.5, stall=0.8, **kw)
+    ctx.close()
+    assert [int(v) for v in r] == roots, (list(r), roots)
+    leaf = o.leaf_mask
+    np.testing.assert_allclose(t.cpu().numpy()[leaf], hist[n][leaf], rtol=1e-6)
 
 
 def test_automatic_iteration_regions_follows_fp64(torch):

@@ -105,6 +105,61 @@ def test_subiteration_changes_only_its_subtree():
     assert np.any(hs[2][inside & o.leaf_mask] != hs[1][inside & o.leaf_mask])
 
 
+def _nested_corner():
+    """Root 2^3 of side 1 and density 1: root cell 0 refined once, and its level-1 child 7
+    (x, y, z in [0.5, 1)) refined again; every other child of root cell 0 is a level-1 leaf."""
+    return gen.TreeDesc(2, 2, 2, 1.0, np.ones(8), [np.array([0]), np.array([7])],
+                        [np.ones(8), np.ones(8)])
+
+
+def test_split_packages_file_under_the_level_of_the_package_they_split_from():
+    """With package splitting (every level change splits or roulettes) a split-off package keeps
+    the shallowest level visited of the package it split from:
+      * a pure absorber lit by a star in a level-1 leaf: the packages entering the level-2 cells
+        split there, and everything deposited in level-2 cells lands in the level-1 array (none
+        in the level-0 or level-2 arrays: a straight path that leaves the root cell never comes
+        back into it);
+      * the external field, split on every entry into a deeper cell: everything is level 0."""
+    tree = _nested_corner()
+    absorber = gen.Dust(np.array([1.0]), np.array([1.0]), np.array([0.0]), np.array([0.0]))
+    o = oracle.Model(tree, absorber)
+    lv = o.level_of_nodes()
+    star = [gen.Source(gen.SRC_POINT, 0, pos=(0.2, 0.3, 0.25), power=np.array([1.0]), packets=6000)]
+    a, _, st, _ = o.trace(star, seed=5, level_arrays=True, split_n=4)
+    e = st["e_lvl"]
+    assert st["splits"] > 100 and st["split_kills"] > 0
+    assert a[lv == 2].sum() > 0.0
+    np.testing.assert_allclose(e[1][lv == 2], a[lv == 2], rtol=1e-12)
+    assert np.all(e[2] == 0.0) and np.all(e[0][lv >= 1] == 0.0)
+    np.testing.assert_allclose(e.sum(axis=0), a, rtol=1e-12, atol=1e-300)
+    bg = [gen.Source(gen.SRC_BACKGROUND, 0, power=np.array([1.0]), packets=6000)]
+    o2 = oracle.Model(tree, _dust(0.7, n=1))
+    a2, _, st2, _ = o2.trace(bg, seed=6, level_arrays=True, split_n=4)
+    assert st2["splits"] > 100 and a2[lv == 2].sum() > 0.0
+    np.testing.assert_allclose(st2["e_lvl"][0], a2, rtol=1e-12, atol=1e-300)
+    assert np.all(st2["e_lvl"][1:] == 0.0)
+
+
+def test_split_subiterations_agree_with_unsplit_ones():
+    """Subiterations with package splitting estimate the same temperatures as without: after a
+    whole-model step and a subtree step the mass-weighted mean |T_split - T| / T over the leaves
+    is within the spread between two unsplit runs with different keys (times 2)."""
+    tree, dust, star = _small_case()
+    o = oracle.Model(tree, dust)
+    root = 2 + 4 * (1 + 4 * 2)
+    sched = [-1, root]
+    ha, _, _ = oracle.subiterate(o, star, seed=8, schedule=sched, dust_packets=3000)
+    hb, _, _ = oracle.subiterate(o, star, seed=9, schedule=sched, dust_packets=3000)
+    hs, _, sts = oracle.subiterate(o, star, seed=10, schedule=sched, dust_packets=3000, split_n=4)
+    assert sts[0]["splits"] > 0  # (the subtree holds one level of leaves only)
+    leaf = o.leaf_mask
+    mass = o.node_rho() * 8.0 ** -o.level_of_nodes().astype(float)
+
+    def diff(x, y):
+        return float((mass[leaf] * np.abs(x[leaf] - y[leaf]) / y[leaf]).sum() / mass[leaf].sum())
+    assert diff(hs[-1], ha[-1]) < 2.0 * diff(hb[-1], ha[-1]), (diff(hs[-1], ha[-1]), diff(hb[-1], ha[-1]))
+
+
 # ---------------------------------------------------------------------------------------
 # energy flow from each grid to its parent (Sect. 3.3)
 # ---------------------------------------------------------------------------------------
