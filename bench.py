@@ -54,14 +54,14 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0
 # autotuner picks for the workload (given explicitly to those runs).  Valid only for the kernel
 # sources the counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "5cab9022d14ad7d73e1ec76c656189577b614c2617935814b6c541884a4946e9",
+                "sha256": "e83d036eda3367bfd1ba6f5c019b5852f6a4918bcb35ba265f0e750310534163",
                 "per_workload": {
                     # profiles/blk_pass_kernel_deep_hierarchy_cloud.md
-                    "deep": {"fetch_bytes_per_crossing": 10.8471, "write_bytes_per_crossing": 5.0755,
-                             "valu_per_crossing": 2.7222, "lane_utilisation": 0.5549},
+                    "deep": {"fetch_bytes_per_crossing": 10.8276, "write_bytes_per_crossing": 5.0769,
+                             "valu_per_crossing": 2.8837, "lane_utilisation": 0.613},
                     # profiles/blk_pass_kernel_molecular_cloud.md
-                    "cloud": {"fetch_bytes_per_crossing": 10.8687, "write_bytes_per_crossing": 6.3949,
-                              "valu_per_crossing": 4.0907, "lane_utilisation": 0.4205}}}
+                    "cloud": {"fetch_bytes_per_crossing": 10.8428, "write_bytes_per_crossing": 6.4081,
+                              "valu_per_crossing": 4.3032, "lane_utilisation": 0.4629}}}
 
 
 WORKLOADS = {

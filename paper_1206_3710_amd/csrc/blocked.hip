@@ -128,6 +128,11 @@ __device__ __forceinline__ void emit_one(const BlkParams& b, uint64_t gid, uint6
   b.u_key[idx] = key;
 }
 
+template <typename WF>
+__device__ __forceinline__ void descend_loop(WF word_of, int ax, int sg, float& x0, float& x1, float& x2,
+                                             int32_t& I0, int32_t& I1, int32_t& I2, int32_t& cur, int& l,
+                                             int32_t& r);
+
 // Entering a neighbour at the packet's own level (word r of cell cur at level l): coordinate
 // ax goes to the near face; while the cell is refined, step into the child on that face and,
 // on the other axes, into the half holding the packet (the midpoint rule).
@@ -139,6 +144,14 @@ __device__ __forceinline__ void descend(WF word_of, int ax, int sg, float& x0, f
   x0 = ax == 0 ? nearf : x0;
   x1 = ax == 1 ? nearf : x1;
   x2 = ax == 2 ? nearf : x2;
+  descend_loop(word_of, ax, sg, x0, x1, x2, I0, I1, I2, cur, l, r);
+}
+
+// The walk of descend without the face reset: nothing happens while r is a leaf's word.
+template <typename WF>
+__device__ __forceinline__ void descend_loop(WF word_of, int ax, int sg, float& x0, float& x1, float& x2,
+                                             int32_t& I0, int32_t& I1, int32_t& I2, int32_t& cur, int& l,
+                                             int32_t& r) {
   int32_t c = child_of(r);
   while (c >= 0) {
     const int b0 = ax == 0 ? (sg > 0 ? 0 : 1) : (x0 >= 0.5f ? 1 : 0);
@@ -497,33 +510,41 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         // or in the same oct (below it).  Its local id is one stride away, so no tree walk and no
         // brick lookup; a refined neighbour is descended as landing does.
         const bool at_brick = lev == R.rl;
-        const bool near_move =
-            !LVL && (at_brick ? (Ja >= sel3(ax, R.lo[0], R.lo[1], R.lo[2]) && Ja < sel3(ax, R.hi[0], R.hi[1], R.hi[2]))
-                              : (Ja >> 1) == (Ia >> 1));
-        if (event) {
-          state = B_EVENT;
-        } else if (near_move) {
+        const bool in_brick = (Ja >= sel3(ax, R.lo[0], R.lo[1], R.lo[2])) & (Ja < sel3(ax, R.hi[0], R.hi[1], R.hi[2]));
+        const bool in_oct = (Ja >> 1) == (Ia >> 1);
+        const bool near_move = !LVL && (at_brick ? in_brick : in_oct);
+        if (LVL) {
+          if (event) state = B_EVENT;
+          else far_cross(ax, sg);
+        } else {
+          // one path for every lane, with selects: a lane that moves (nm) takes the neighbour
+          // and its word, the others keep their cell and re-read its word, which is a leaf's, so
+          // the walk down does nothing for them
+          const bool nm = !event && near_move;
           const int L = lev;
           const int32_t stride = at_brick ? sel3(ax, 1, bx, bxy) : (1 << ax);
-          I0 = ax == 0 ? Ja : I0;
-          I1 = ax == 1 ? Ja : I1;
-          I2 = ax == 2 ? Ja : I2;
-          node += sg > 0 ? stride : -stride;
+          const float nearf = sg > 0 ? 0.0f : 1.0f;
+          I0 = nm && ax == 0 ? Ja : I0;
+          I1 = nm && ax == 1 ? Ja : I1;
+          I2 = nm && ax == 2 ? Ja : I2;
+          x0 = nm && ax == 0 ? nearf : x0;
+          x1 = nm && ax == 1 ? nearf : x1;
+          x2 = nm && ax == 2 ? nearf : x2;
+          node += nm ? (sg > 0 ? stride : -stride) : 0;
           int32_t raw = word_of(node);
-          descend(word_of, ax, sg, x0, x1, x2, I0, I1, I2, node, lev, raw);
+          descend_loop(word_of, ax, sg, x0, x1, x2, I0, I1, I2, node, lev, raw);
           rho = __int_as_float(raw);
           // (the guard on the crossing count is tested on the far crossings: between two of them
           // a packet crosses at most the cells of one brick along a straight line)
-          ++ncross;
-          if (splitting && min(lev, sdep) != min(L, sdep)) state = B_SPLIT;
-        } else if (LVL) {
-          far_cross(ax, sg);
-        } else {
+          ncross += nm ? 1u : 0u;
           xax = ax;
           xsg = sg;
-          // leaving the brick at its level into the model: no tree walk, the record is written
-          // in the exit phase; every other crossing waits for the far-crossing phase
-          state = lev == R.rl && Ja >= 0 && Ja < (D.na(ax) << lev) ? B_EXIT : B_FAR;
+          // a lane that does not move either stops at its event, or leaves the brick at its level
+          // into the model (no tree walk: the record is written in the exit phase), or waits for
+          // the far-crossing phase
+          const int s_exit = ((L == R.rl) & (Ja >= 0) & (Ja < (D.na(ax) << L))) ? B_EXIT : B_FAR;
+          const int s_near = splitting && min(lev, sdep) != min(L, sdep) ? B_SPLIT : B_CROSS;
+          state = event ? B_EVENT : (nm ? s_near : s_exit);
         }
       }
       if (pool_done && ++tail_it >= b.tail_park) break;
