@@ -54,14 +54,14 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0
 # autotuner picks for the workload (given explicitly to those runs).  Valid only for the kernel
 # sources the counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "e83d036eda3367bfd1ba6f5c019b5852f6a4918bcb35ba265f0e750310534163",
+                "sha256": "9149f1e806144dc334b6fe83002f268a91f265a8a893f37b051a24f8464ff7b1",
                 "per_workload": {
                     # profiles/blk_pass_kernel_deep_hierarchy_cloud.md
-                    "deep": {"fetch_bytes_per_crossing": 10.8276, "write_bytes_per_crossing": 5.0769,
-                             "valu_per_crossing": 2.8837, "lane_utilisation": 0.613},
+                    "deep": {"fetch_bytes_per_crossing": 10.8197, "write_bytes_per_crossing": 5.0763,
+                             "valu_per_crossing": 2.8342, "lane_utilisation": 0.618},
                     # profiles/blk_pass_kernel_molecular_cloud.md
-                    "cloud": {"fetch_bytes_per_crossing": 10.8428, "write_bytes_per_crossing": 6.4081,
-                              "valu_per_crossing": 4.3032, "lane_utilisation": 0.4629}}}
+                    "cloud": {"fetch_bytes_per_crossing": 10.8403, "write_bytes_per_crossing": 6.4065,
+                              "valu_per_crossing": 4.2471, "lane_utilisation": 0.4658}}}
 
 
 WORKLOADS = {

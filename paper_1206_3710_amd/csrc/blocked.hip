@@ -133,6 +133,22 @@ __device__ __forceinline__ void descend_loop(WF word_of, int ax, int sg, float& 
                                              int32_t& I0, int32_t& I1, int32_t& I2, int32_t& cur, int& l,
                                              int32_t& r);
 
+// A queue record read as six 16-byte loads issued together (read field by field, the byte
+// fields came as separate narrow loads, one of them only after the others had arrived).
+__device__ __forceinline__ PRec load_rec(const PRec* __restrict__ src) {
+  const uint4* __restrict__ v = reinterpret_cast<const uint4*>(src);
+  uint4 t[sizeof(PRec) / 16];
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(PRec) / 16); ++k) t[k] = v[k];
+  // (keeps the compiler from narrowing the loads to the fields each branch reads)
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(PRec) / 16); ++k)
+    asm volatile("" : "+v"(t[k].x), "+v"(t[k].y), "+v"(t[k].z), "+v"(t[k].w));
+  PRec r;
+  __builtin_memcpy(&r, t, sizeof r);
+  return r;
+}
+
 // Entering a neighbour at the packet's own level (word r of cell cur at level l): coordinate
 // ax goes to the near face; while the cell is refined, step into the child on that face and,
 // on the other axes, into the half holding the packet (the midpoint rule).
@@ -367,7 +383,7 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
         if (idx >= it.count) {
           state = B_DONE;
         } else {
-          const PRec rec = b.q_in[b.q_perm[it.start + idx]];
+          const PRec rec = load_rec(b.q_in + b.q_perm[it.start + idx]);
           job = rec.job;
           const JobDev& J = p.jobs[job];
           ks = J.kc32 * J.alb32;
@@ -542,7 +558,8 @@ __device__ __forceinline__ void run_item(const BlkParams& b, const WorkItem& it,
           // a lane that does not move either stops at its event, or leaves the brick at its level
           // into the model (no tree walk: the record is written in the exit phase), or waits for
           // the far-crossing phase
-          const int s_exit = ((L == R.rl) & (Ja >= 0) & (Ja < (D.na(ax) << L))) ? B_EXIT : B_FAR;
+          // (the root extent as sel3: written as D.na(ax) it compiled to a three-way branch here)
+          const int s_exit = ((L == R.rl) & (Ja >= 0) & (Ja < (sel3(ax, D.n0, D.n1, D.n2) << L))) ? B_EXIT : B_FAR;
           const int s_near = splitting && min(lev, sdep) != min(L, sdep) ? B_SPLIT : B_CROSS;
           state = event ? B_EVENT : (nm ? s_near : s_exit);
         }
