@@ -120,6 +120,21 @@ def test_ali_rejects_the_global_schedule(torch):
     ctx.close()
 
 
+def test_ali_with_splitting_fp64_equals_oracle(torch):
+    """The same accelerated iteration with package splitting in the FP64 form, whose histories
+    are the oracle's: the self-absorption tally counts the package as emitted only, so the
+    temperatures after three steps agree to 1e-6."""
+    tree, dust, star = _small_case()
+    ora = oracle.Model(tree, dust)
+    ha, _, _ = oracle.lambda_iterate(ora, star, seed=31, n_fixed=3, dust_packets=4000, ali=True, split_n=4)
+    ctx, m = _ctx(tree, dust)
+    tg, nd, _ = ctx.lambda_iterate(m, star, seed=31, dust_packets=4000, n_max=3, tol=0.0, ali=True,
+                                   precision=rt.FP64, split_n=4)
+    ctx.close()
+    assert nd == 3
+    np.testing.assert_allclose(tg.cpu().numpy(), ha[-1], rtol=1e-6)
+
+
 def test_ali_with_splitting_against_oracle(torch):
     """Accelerated iteration with package splitting (factor 4) in the region schedule, three
     steps: the temperatures stay below the Monte Carlo noise of the oracle's run with the same
