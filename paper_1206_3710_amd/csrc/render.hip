@@ -16,19 +16,19 @@ using namespace rtd;
 namespace {
 
 constexpr double kK = 1.380649e-16;
+constexpr double kLog2e = 1.4426950408889634;
 constexpr int kG = 8;  // wavelengths per group of the FP32 transfer
 
-// e^x - 1 for x >= 0 in FP32: below 1/8 the series to x^5 (truncation below x^5 / 6! =
-// 4.2e-8 relative), above it the hardware base-2 exponential (inf for large x).
-__device__ __forceinline__ float expm1_pos(float x) {
-  float p = 8.33333333e-3f;         // 1/5!
-  p = fmaf(p, x, 4.16666667e-2f);   // 1/4!
-  p = fmaf(p, x, 1.66666667e-1f);   // 1/3!
-  p = fmaf(p, x, 0.5f);             // 1/2!
-  p = fmaf(p, x, 1.0f);
-  const float small = p * x;
-  const float large = __builtin_amdgcn_exp2f(x * 1.44269504f) - 1.0f;
-  return x < 0.125f ? small : large;
+// e^x - 1 for x >= 0 in FP32, from y = x log2(e): below x = 1/32 the series to x^3
+// (truncation below x^3 / 4! = 1.3e-6 relative), above it the hardware base-2 exponential
+// (cancellation below 2 ulp / x = 7.6e-6 relative; inf for large x).
+__device__ __forceinline__ float expm1_pos2(float y) {
+  float p = 5.55041087e-2f;         // ln2^3 / 3!
+  p = fmaf(p, y, 2.40226507e-1f);   // ln2^2 / 2!
+  p = fmaf(p, y, 6.93147181e-1f);   // ln2
+  const float small = p * y;
+  const float large = __builtin_amdgcn_exp2f(y) - 1.0f;
+  return y < 4.50842200e-2f ? small : large;  // log2(e) / 32
 }
 
 template <int NS, bool F32>
@@ -41,8 +41,8 @@ __global__ __launch_bounds__(256, NS > 32 ? 2 : 1) void render_kernel(
   const ModelDev& m = models[model];
   const Dims D = dims_of(m);
   const ChildPlain ch{child};
-  // FP32 form: per-wavelength constants kappa_ext * cell size, (1 - albedo) 2 h nu^3 / c^2,
-  // h nu / k
+  // FP32 form: per-wavelength constants -kappa_ext * cell size * log2(e), (1 - albedo)
+  // 2 h nu^3 / c^2, h nu / k * log2(e) (the base-2 exponentials then take them directly)
   // Wavelengths past n_sel (up to the next multiple of kG) are padded with kappa = 0 and no
   // source, which leaves their intensity at 0 and is never written out.
   __shared__ float s_kc[NS], s_ap[NS], s_hk[NS];
@@ -50,9 +50,9 @@ __global__ __launch_bounds__(256, NS > 32 ? 2 : 1) void render_kernel(
     if (threadIdx.x < NS) {
       const bool real = (int)threadIdx.x < n_sel;
       const LamConst& L = lc[lam_idx[real ? threadIdx.x : 0]];
-      s_kc[threadIdx.x] = real ? (float)(L.kext * m.cell_cm) : 0.0f;
+      s_kc[threadIdx.x] = real ? (float)(-L.kext * m.cell_cm * kLog2e) : 0.0f;
       s_ap[threadIdx.x] = real ? (float)((1.0 - L.alb) * L.pre) : 0.0f;
-      s_hk[threadIdx.x] = real ? (float)(L.hnu / kK) : 1.0f;
+      s_hk[threadIdx.x] = real ? (float)(L.hnu / kK * kLog2e) : 1.0f;
     }
     __syncthreads();
   }
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256, NS > 32 ? 2 : 1) void render_kernel(
         const double s = texit;
         if (F32 && rho > 0.0 && s > 0.0) {
           // per wavelength: the segment's transmission e^-dtau, its emission weight 1 - e^-dtau
-          // (series below 1/8, else from the transmission), and the source (1 - a) B(T)
+          // (series below 1/32, else from the transmission), and the source (1 - a) B(T)
           const float tc = (float)t_node[canon_of(m, node)];
           const float f = (float)(rho * s);
           // a cell without a temperature emits nothing: 1 / T = inf makes the source term 0
@@ -142,15 +142,14 @@ __global__ __launch_bounds__(256, NS > 32 ? 2 : 1) void render_kernel(
             if (NS <= kG || q0 < n_sel) {
 #pragma unroll
               for (int q = q0; q < (q0 + kG < NS ? q0 + kG : NS); ++q) {
-                const float dtau = s_kc[q] * f;
-                const float att = __builtin_amdgcn_exp2f(dtau * -1.44269504f);
-                float em = 8.33333333e-3f;
-                em = fmaf(em, dtau, -4.16666667e-2f);
-                em = fmaf(em, dtau, 1.66666667e-1f);
-                em = fmaf(em, dtau, -0.5f);
-                em = fmaf(em, dtau, 1.0f);
-                em = dtau < 0.125f ? em * dtau : 1.0f - att;
-                const float src = s_ap[q] * __builtin_amdgcn_rcpf(expm1_pos(s_hk[q] * inv_t));
+                const float z = s_kc[q] * f;  // -dtau log2(e)
+                const float att = __builtin_amdgcn_exp2f(z);
+                // 1 - e^-dtau: below dtau = 1/32 the series to dtau^3 in z
+                float em = -5.55041087e-2f;
+                em = fmaf(em, z, -2.40226507e-1f);
+                em = fmaf(em, z, -6.93147181e-1f);
+                em = z > -4.50842200e-2f ? em * z : 1.0f - att;
+                const float src = s_ap[q] * __builtin_amdgcn_rcpf(expm1_pos2(s_hk[q] * inv_t));
                 I32[q] = fmaf(I32[q], att, src * em);
               }
             }
