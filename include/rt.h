@@ -271,7 +271,11 @@ rt_status rt_ali_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_sou
  * of r's subtree by more than flux_frac times the energy absorbed in the subtree of r's parent
  * (the whole model for a root cell) since that parent last took part in a step, the parent is
  * tagged, and rt_subiter_select includes every tagged grid until a step includes it.
- * flux_frac = 0: no tracking.
+ * flux_frac = 0: no tracking.  ali != 0 (RT_FP64 form only; RT_EINVAL otherwise): every step
+ * uses the accelerated iteration with the diagonal operator (Sect. 3.1 Eq. 3) inside its subtree:
+ * each subtree leaf's temperature balances (A - e_self) / (1 - lambda*), with A = A_stars
+ * plus the leaf's arrays (Eq. 9) and e_self, lambda* = e_self / e_emit from the step's own
+ * trace as in rt_ali_iterate; the recorded imbalances and the flows use A itself.
  * rt_subiter_step takes one step with the subtree below `root`, a refined canonical node of
  * the model, or the whole model (root = -1): the dust emission of the subtree's leaves at the
  * current temperatures is traced with key `iteration`; every deposit is filed under the
@@ -285,7 +289,8 @@ rt_status rt_ali_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_sou
  * leaf whose last recorded imbalance is within frac of the largest and of every tagged grid;
  * root = -1 when that is the whole model.  max_imbalance (may be NULL) receives the largest. */
 rt_status rt_subiter_begin(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
-                           const rt_trace_opts* opts, double t_min, double t_max, double flux_frac);
+                           const rt_trace_opts* opts, double t_min, double t_max, double flux_frac,
+                           int32_t ali);
 rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust_packets,
                           uint32_t iteration, const rt_trace_opts* opts, double* crit,
                           double* t_node, rt_trace_stats* stats);

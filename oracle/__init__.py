@@ -373,8 +373,20 @@ def ali_step_absorbed(a_stars, a_dust, e_self, e_emit_node):
     return (a_stars + a_dust - e_self) / (1.0 - lam)
 
 
+def subtree_ali_absorbed(a_tot, mask, st):
+    """The absorbed power a subiteration step balances with the new emission when it uses the
+    accelerated iteration (Sect. 3.1 Eq. 3 inside the subtree, Sect. 3.2): for the cells of the
+    subtree, whose emission the step traced, ali_step_absorbed with A_stars + A_dust replaced by
+    the sum of the cell's arrays (e_self, the part of its own emission it absorbed before the
+    packets first left it, lies in its own level's array); elsewhere a_tot unchanged."""
+    lam = np.where(st["e_emit_node"] > 0.0,
+                   st["e_self"] / np.where(st["e_emit_node"] > 0.0, st["e_emit_node"], 1.0), 0.0)
+    lam = np.minimum(lam, 1.0 - 1e-9)
+    return np.where(mask, (a_tot - st["e_self"]) / (1.0 - lam), a_tot)
+
+
 def subiterate(model, star_sources, seed, schedule, dust_packets, rr_threshold=0.0, rr_prob=0.0,
-               t_min=2.0, t_max=3000.0, split_n=1, split_depth=0):
+               t_min=2.0, t_max=3000.0, split_n=1, split_depth=0, ali=False):
     """Lambda iteration with subiterations on complete subtrees (paper Sect. 3.1 and App. B).
     ``schedule``: the subtree root of each step, a refined node or -1 for the whole model.  Each
     cell keeps one absorbed-energy array per hierarchy level above or at its own; a step with
@@ -383,8 +395,9 @@ def subiterate(model, star_sources, seed, schedule, dust_packets, rr_threshold=0
     the subtree with what it deposits; the temperatures of those cells then follow from
     A_stars + the sum of their arrays (Eq. 9).  Key iteration of step k is k.  ``split_n`` > 1:
     package splitting (Sect. 2.3) in every trace, a split-off package filing its deposits under
-    the shallowest level of the package it split from.  Returns (temperature after each step,
-    A_stars, per-step trace statistics)."""
+    the shallowest level of the package it split from.  ``ali``: every step uses the
+    accelerated iteration inside its subtree (subtree_ali_absorbed).  Returns (temperature
+    after each step, A_stars, per-step trace statistics)."""
     import gen
     sp = dict(split_n=split_n, split_depth=split_depth)
     a_stars, _, _, _ = model.trace(star_sources, seed, iteration=0, rr_threshold=rr_threshold,
@@ -398,10 +411,13 @@ def subiterate(model, star_sources, seed, schedule, dust_packets, rr_threshold=0
         mask = model.subtree_mask(root)
         src = [gen.Source(gen.SRC_DUST, 0, packets=dust_packets)]
         _, _, st, _ = model.trace(src, seed, iteration=it, rr_threshold=rr_threshold,
-                                  rr_prob=rr_prob, t_node=t, level_arrays=True, subtree=root, **sp)
+                                  rr_prob=rr_prob, t_node=t, level_arrays=True, subtree=root,
+                                  self_absorption=ali, **sp)
         stats.append(st)
         arrays[lo:, mask] = st["e_lvl"][lo:, mask]
-        t_new = model.solve_temperature(a_stars + arrays.sum(axis=0), t_min, t_max)
+        a_tot = a_stars + arrays.sum(axis=0)
+        t_new = model.solve_temperature(subtree_ali_absorbed(a_tot, mask, st) if ali else a_tot,
+                                         t_min, t_max)
         t = np.where(mask, t_new, t)
         hist.append(t.copy())
     return hist, a_stars, stats
@@ -448,7 +464,7 @@ def subtree_select(imb, frac, parent, tagged, tag_root):
 
 def subiterate_auto(model, star_sources, seed, n_steps, dust_packets, frac=0.5, stall=0.8,
                     flux_frac=0.0, rr_threshold=0.0, rr_prob=0.0, t_min=2.0, t_max=3000.0,
-                    split_n=1, split_depth=0):
+                    split_n=1, split_depth=0, ali=False):
     """The automatic iteration of Sect. 3.3 over subiterations on complete subtrees (Sect. 3.1,
     App. B), step by step from the oracle's own bookkeeping:
       * per leaf, the energy imbalance |A - E(T_old)| / E(T_old) recorded at its last step, with
@@ -461,8 +477,9 @@ def subiterate_auto(model, star_sources, seed, n_steps, dust_packets, frac=0.5, 
         step; when a step below r changes the flow out of r's subtree by more than flux_frac
         times the energy absorbed in its parent's subtree (since the parent last took part), the
         parent grid is tagged until a step includes it.
-    Key iteration of step k is k; ``split_n``, ``split_depth`` as for subiterate.  Returns
-    (temperatures after each step, the roots taken)."""
+    Key iteration of step k is k; ``split_n``, ``split_depth`` and ``ali`` as for subiterate
+    (the imbalances and the flows use the absorbed power itself).  Returns (temperatures after
+    each step, the roots taken)."""
     import gen
     sp = dict(split_n=split_n, split_depth=split_depth)
     a_stars, _, _, _ = model.trace(star_sources, seed, iteration=0, rr_threshold=rr_threshold,
@@ -490,14 +507,15 @@ def subiterate_auto(model, star_sources, seed, n_steps, dust_packets, frac=0.5, 
         src = [gen.Source(gen.SRC_DUST, 0, packets=dust_packets)]
         _, _, st, _ = model.trace(src, seed, iteration=k + 1, rr_threshold=rr_threshold,
                                   rr_prob=rr_prob, t_node=t, level_arrays=True, subtree=root,
-                                  flux=flux_frac > 0.0, **sp)
+                                  flux=flux_frac > 0.0, self_absorption=ali, **sp)
         arrays[lo:, mask] = st["e_lvl"][lo:, mask]
         a_tot = a_stars + arrays.sum(axis=0)
         e_old = model.emission_all(t)
         upd = mask & leaf
         imb[upd] = np.where(e_old[upd] > 0.0, np.abs(a_tot[upd] - e_old[upd]) / np.where(e_old[upd] > 0.0,
                                                                                         e_old[upd], 1.0), 0.0)
-        t_new = model.solve_temperature(a_tot, t_min, t_max)
+        t_new = model.solve_temperature(subtree_ali_absorbed(a_tot, mask, st) if ali else a_tot,
+                                         t_min, t_max)
         t = np.where(mask, t_new, t)
         if flux_frac > 0.0:
             flow = st["e_flux"]

@@ -114,7 +114,7 @@ def lib():
             "rt_solve_temperature": (I32, [P, I32, P, D, D, P]),
             "rt_lambda_iterate": (I32, [P, I32, I32, P, P, I64, I32, D, D, D, P, P, P]),
             "rt_ali_iterate": (I32, [P, I32, I32, P, P, I64, I32, D, D, D, P, P, P]),
-            "rt_subiter_begin": (I32, [P, I32, I32, P, P, D, D, D]),
+            "rt_subiter_begin": (I32, [P, I32, I32, P, P, D, D, D, I32]),
             "rt_subiter_step": (I32, [P, I32, I64, I64, U32, P, P, P, P]),
             "rt_subiter_select": (I32, [P, I32, D, P, P]),
             "rt_subiter_run": (I32, [P, I32, I32, D, D, I64, U32, P, P, P, P, P]),
@@ -394,14 +394,16 @@ class Context:
 
     def subiter_begin(self, model: int, sources: Sequence, seed: int, t_min: float = 2.0,
                       t_max: float = 3000.0, iteration: int = 0, rr_threshold: float = 0.0,
-                      rr_prob: float = 0.0, precision: int = FP64, flux_frac: float = 0.0, **kw):
+                      rr_prob: float = 0.0, precision: int = FP64, flux_frac: float = 0.0,
+                      ali: bool = False, **kw):
         """Subiterations (FP64 form, or FP32_LOCAL with the region schedule): trace the
         constant sources, T_0, clear the level arrays; flux_frac > 0 tracks the energy flow
-        from each grid to its parent and tags grids whose inflow changed."""
+        from each grid to its parent and tags grids whose inflow changed; ali: the steps use
+        the accelerated iteration inside their subtree (FP64 form)."""
         arr, keep = _source_array(sources) if sources else ((Source * 1)(), [])
         opts = self._sub_opts(seed, iteration, precision, rr_threshold, rr_prob, kw)
         self._check(lib().rt_subiter_begin(self.h, model, len(sources), arr, C.byref(opts), t_min, t_max,
-                                           float(flux_frac)))
+                                           float(flux_frac), 1 if ali else 0))
 
     def subiter_step(self, model: int, root: int, dust_packets: int, seed: int, iteration: int,
                      rr_threshold: float = 0.0, rr_prob: float = 0.0, precision: int = FP64, **kw):

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "subiter.h"
 
 namespace {
 
@@ -65,6 +66,7 @@ struct HostModel {
   DevBuf sub_astars, sub_arrays, sub_imb;
   double sub_tmin = 0.0, sub_tmax = 0.0;
   bool sub_ready = false;
+  bool sub_ali = false;  // steps use the accelerated iteration inside their subtree
   // automatic iteration (Sect. 3.3): canonical parent of each node (-1: a root cell), the outflow
   // of each refined node's subtree as last measured with its parent grid in the step, and the
   // grids tagged for the next step because the flow from a child changed (tag_root: the root
@@ -112,6 +114,7 @@ struct rt_ctx {
   DevBuf cdf_lum, cdf_q, cdf_qpre, lmax, scan_tmp;
   DevBuf tmp_in, tmp_out, tmp_out2, view, lamidx;
   DevBuf it_astars, it_adust, it_sum, it_told, it_crit, it_self, it_emit;
+  DevBuf it_aself, it_aemit, it_asolve;  // accelerated subiteration steps
   // peel-off
   DevBuf peel_ev, peel_ctr, peel_tab, peel_roottab, peel_tabroot, peel_dnu, peel_img;
   // grid-by-grid schedule: region-major copy of the trees
@@ -560,7 +563,7 @@ rt_status rt_destroy(rt_ctx* ctx) {
                     &ctx->q_items, &ctx->q_state, &ctx->last_node, &ctx->t_tab, &ctx->it_self,
                     &ctx->it_emit, &ctx->peel_ev, &ctx->peel_ctr, &ctx->peel_tab, &ctx->peel_roottab,
                     &ctx->peel_tabroot, &ctx->peel_dnu, &ctx->peel_img, &ctx->g_jobs, &ctx->g_keys,
-                    &ctx->g_scan, &ctx->g_report};
+                    &ctx->g_scan, &ctx->g_report, &ctx->it_aself, &ctx->it_aemit, &ctx->it_asolve};
   for (DevBuf* b : bufs) b->release();
   for (HostModel& m : ctx->models) {
     m.d_lc.release();
@@ -1871,7 +1874,8 @@ void subiter_flux_update(rt_ctx* ctx, int32_t model, int64_t root, const std::ve
 extern "C" {
 
 rt_status rt_subiter_begin(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_source* src,
-                           const rt_trace_opts* opts, double t_min, double t_max, double flux_frac) {
+                           const rt_trace_opts* opts, double t_min, double t_max, double flux_frac,
+                           int32_t ali) {
   if (!ctx) return fail(nullptr, RT_EINVAL, "null context");
   GUARD({
     if (rt_status s = check_model(ctx, model)) return s;
@@ -1880,6 +1884,8 @@ rt_status rt_subiter_begin(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_s
       return fail(ctx, RT_EINVAL, "subiterations run in the RT_FP64 form or the region schedule");
     if (!(t_min > 0.0) || !(t_max > t_min)) return fail(ctx, RT_EINVAL, "need 0 < t_min < t_max");
     if (!(flux_frac >= 0.0) || !std::isfinite(flux_frac)) return fail(ctx, RT_EINVAL, "flux_frac must be >= 0");
+    if (ali && opts->precision != RT_FP64)
+      return fail(ctx, RT_EINVAL, "accelerated subiterations run in the RT_FP64 form");
     for (int s = 0; s < n_src; ++s)
       if (src && (src[s].model != model || src[s].kind == RT_SRC_DUST))
         return fail(ctx, RT_EINVAL, "constant sources must belong to the model and not be dust");
@@ -1903,6 +1909,7 @@ rt_status rt_subiter_begin(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_s
       }
     }
     h.sub_flux_frac = flux_frac;
+    h.sub_ali = ali != 0;
     h.sub_flux_ref.assign(h.n_nodes, 0.0);
     h.sub_tag.assign(h.n_nodes, 0);
     h.sub_tag_root = false;
@@ -1942,6 +1949,8 @@ rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust
     HostModel& h = ctx->models[model];
     if (!h.sub_ready) return fail(ctx, RT_ESTATE, "rt_subiter_begin not called for model %d", model);
     if (dust_packets < 1 || dust_packets > (int64_t(1) << 32)) return fail(ctx, RT_EINVAL, "bad dust_packets");
+    if (h.sub_ali && opts->precision != RT_FP64)
+      return fail(ctx, RT_EINVAL, "accelerated subiterations run in the RT_FP64 form");
     if (root < -1 || root >= h.n_nodes) return fail(ctx, RT_EINVAL, "bad subtree root");
     int32_t sub_lev = -1, sub_I[3] = {0, 0, 0};
     if (root >= 0) {
@@ -2007,6 +2016,17 @@ rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust
       HIPCHK(hipMemsetAsync(ctx->it_emit.p, 0, 8 * tn, ctx->stream));
       out.flux_acc = ctx->it_emit.as<double>();
     }
+    if (h.sub_ali) {
+      // the diagonal operator's tallies: what each leaf's own emission deposited in it before its
+      // packets first left it, and what it emitted
+      HIPCHK(ctx->it_aself.ensure(8 * tn));
+      HIPCHK(ctx->it_aemit.ensure(8 * tn));
+      HIPCHK(ctx->it_asolve.ensure(8 * h.n_nodes));
+      HIPCHK(hipMemsetAsync(ctx->it_aself.p, 0, 8 * tn, ctx->stream));
+      HIPCHK(hipMemsetAsync(ctx->it_aemit.p, 0, 8 * tn, ctx->stream));
+      out.self_acc = ctx->it_aself.as<double>();
+      out.emit_acc = ctx->it_aemit.as<double>();
+    }
     if (rt_status s = trace_impl(ctx, 1, &ds, &o, out, stats)) return s;
     HIPCHK(launch_subiter_update(ctx->d_models.as<ModelDev>(), model, h.n_leaves, ctx->d_leaf_node.as<int32_t>(),
                                  ctx->d_leaf_level.as<uint8_t>(), ctx->d_leaf_coord.as<int32_t>(),
@@ -2014,7 +2034,20 @@ rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust
                                  sub_lev + 1, ctx->it_self.as<double>(), tn, h.sub_arrays.as<double>(),
                                  h.sub_astars.as<double>(), ctx->it_told.as<double>(), ctx->it_sum.as<double>(),
                                  h.sub_imb.as<double>(), ctx->stream));
-    if (rt_status s = solve_T_impl(ctx, model, ctx->it_sum.as<double>(), h.sub_tmin, h.sub_tmax)) return s;
+    const double* a_solve = ctx->it_sum.as<double>();
+    if (h.sub_ali) {
+      HIPCHK(launch_subiter_ali(ctx->d_models.as<ModelDev>(), model, h.n_nodes, h.n_leaves,
+                                ctx->d_leaf_node.as<int32_t>(), ctx->d_leaf_level.as<uint8_t>(),
+                                ctx->d_leaf_coord.as<int32_t>(), sub_lev, sub_I, ctx->it_sum.as<double>(),
+                                ctx->it_aself.as<double>() + cb, ctx->it_aemit.as<double>() + cb,
+                                ctx->it_asolve.as<double>(), ctx->stream));
+      a_solve = ctx->it_asolve.as<double>();
+    }
+    if (rt_status s = solve_T_impl(ctx, model, a_solve, h.sub_tmin, h.sub_tmax)) return s;
+    if (h.sub_ali)
+      HIPCHK(launch_subiter_keep(ctx->d_models.as<ModelDev>(), model, h.n_leaves, ctx->d_leaf_node.as<int32_t>(),
+                                 ctx->d_leaf_level.as<uint8_t>(), ctx->d_leaf_coord.as<int32_t>(), sub_lev, sub_I,
+                                 ctx->it_told.as<double>(), h.d_T.as<double>(), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->it_crit.p, 0, 16, ctx->stream));
     HIPCHK(launch_crit(ctx->d_models.as<ModelDev>(), model, h.n_nodes, ctx->d_child.as<int32_t>(),
                        ctx->d_rho64.as<double>(), h.d_T.as<double>(), ctx->it_told.as<double>(),

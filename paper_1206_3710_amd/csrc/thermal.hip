@@ -1,6 +1,7 @@
 // Dust model f(J) of the paper's Sect. 3.1 (one grain component at its equilibrium
 // temperature, Sect. 4) and the per-leaf dust-emission luminosities used as a source.
 #include "device.h"
+#include "subiter.h"
 
 using namespace rtd;
 
@@ -338,6 +339,70 @@ hipError_t launch_subiter_update(const ModelDev* models, int model, int64_t n_le
   hipLaunchKernelGGL(subiter_update_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, s, models,
                      model, n_leaves, leaf_node, leaf_level, leaf_coord, rho64, lc, nl, sub_lev, sub_I[0], sub_I[1],
                      sub_I[2], lo, lvl_new, lvl_stride, arrays, a_stars, t_old, a_tot, imb);
+  return hipGetLastError();
+}
+
+namespace {
+
+__global__ __launch_bounds__(256) void subiter_ali_kernel(
+    const ModelDev* __restrict__ models, int model, int64_t n_nodes, int64_t n_leaves,
+    const int32_t* __restrict__ leaf_node, const uint8_t* __restrict__ leaf_level,
+    const int32_t* __restrict__ leaf_coord, int sub_lev, int32_t s0, int32_t s1, int32_t s2,
+    const double* __restrict__ a_tot, const double* __restrict__ e_self, const double* __restrict__ e_emit,
+    double* __restrict__ a_solve) {
+  const ModelDev& m = models[model];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // refined nodes first take a_tot; the leaves then overwrite theirs
+  if (i < n_nodes) a_solve[i] = a_tot[i];
+  if (i >= n_leaves) return;
+  const int32_t node = leaf_node[m.leaf_base + i];
+  const int lev = leaf_level[m.leaf_base + i];
+  const int64_t c = canon_of(m, node);
+  const int32_t* xyz = leaf_coord + 3 * (m.leaf_base + i);
+  const int32_t sI[3] = {s0, s1, s2};
+  if (!(sub_lev < 0 || in_subtree(sub_lev, sI, lev, xyz[0], xyz[1], xyz[2]))) return;
+  double lam = e_emit[c] > 0.0 ? e_self[c] / e_emit[c] : 0.0;
+  lam = lam < 1.0 - 1e-9 ? lam : 1.0 - 1e-9;
+  a_solve[c] = (a_tot[c] - e_self[c]) / (1.0 - lam);
+}
+
+__global__ __launch_bounds__(256) void subiter_keep_kernel(
+    const ModelDev* __restrict__ models, int model, int64_t n_leaves, const int32_t* __restrict__ leaf_node,
+    const uint8_t* __restrict__ leaf_level, const int32_t* __restrict__ leaf_coord, int sub_lev, int32_t s0,
+    int32_t s1, int32_t s2, const double* __restrict__ t_old, double* __restrict__ t_node) {
+  const ModelDev& m = models[model];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_leaves || sub_lev < 0) return;
+  const int32_t node = leaf_node[m.leaf_base + k];
+  const int lev = leaf_level[m.leaf_base + k];
+  const int32_t* xyz = leaf_coord + 3 * (m.leaf_base + k);
+  const int32_t sI[3] = {s0, s1, s2};
+  if (in_subtree(sub_lev, sI, lev, xyz[0], xyz[1], xyz[2])) return;
+  const int64_t c = canon_of(m, node);
+  t_node[c] = t_old[c];
+}
+
+}  // namespace
+
+hipError_t launch_subiter_ali(const ModelDev* models, int model, int64_t n_nodes, int64_t n_leaves,
+                              const int32_t* leaf_node, const uint8_t* leaf_level, const int32_t* leaf_coord,
+                              int sub_lev, const int32_t sub_I[3], const double* a_tot, const double* e_self,
+                              const double* e_emit, double* a_solve, hipStream_t s) {
+  const int64_t n = n_nodes > n_leaves ? n_nodes : n_leaves;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(subiter_ali_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, models, model,
+                     n_nodes, n_leaves, leaf_node, leaf_level, leaf_coord, sub_lev, sub_I[0], sub_I[1], sub_I[2],
+                     a_tot, e_self, e_emit, a_solve);
+  return hipGetLastError();
+}
+
+hipError_t launch_subiter_keep(const ModelDev* models, int model, int64_t n_leaves, const int32_t* leaf_node,
+                               const uint8_t* leaf_level, const int32_t* leaf_coord, int sub_lev,
+                               const int32_t sub_I[3], const double* t_old, double* t_node, hipStream_t s) {
+  if (n_leaves == 0 || sub_lev < 0) return hipSuccess;
+  hipLaunchKernelGGL(subiter_keep_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, s, models,
+                     model, n_leaves, leaf_node, leaf_level, leaf_coord, sub_lev, sub_I[0], sub_I[1], sub_I[2],
+                     t_old, t_node);
   return hipGetLastError();
 }
 

@@ -97,6 +97,33 @@ def test_subiterations_fp64_split_against_oracle(torch):
     ctx.close()
 
 
+def test_accelerated_subiterations_fp64_against_oracle(torch):
+    """Subiterations with the accelerated iteration inside each subtree (FP64 form): the
+    oracle's temperatures after every step of a schedule of whole-model and subtree steps within
+    1e-6, and the subtree steps leave every temperature outside the subtree as it was."""
+    tree, dust, star, core = _core_case()
+    star = [gen.Source(s.kind, s.model, pos=s.pos, power=s.power, packets=1000) for s in star]
+    schedule = [-1, core, core, -1]
+    o = oracle.Model(tree, dust)
+    hist, _, _ = oracle.subiterate(o, star, seed=3, schedule=schedule, dust_packets=1000, ali=True)
+    inside = o.subtree_mask(core)
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    ctx.subiter_begin(m, star, seed=3, ali=True)
+    prev = None
+    for k, r in enumerate(schedule, start=1):
+        t, crit, st = ctx.subiter_step(m, r, dust_packets=1000, seed=3, iteration=k)
+        t = t.cpu().numpy()
+        np.testing.assert_allclose(t, hist[k], rtol=1e-6, err_msg=f"step {k}")
+        if r >= 0:
+            assert np.array_equal(t[~inside], prev[~inside])
+        prev = t
+    with pytest.raises(rt.RTError):  # the region schedule keeps no self-absorption per level
+        ctx.subiter_begin(m, star, seed=3, ali=True, precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS)
+    ctx.close()
+
+
 def _reference_select(o, imbalance, frac):
     """Lowest common ancestor of the leaves within frac of the largest imbalance (-1: the whole
     model), from the oracle's tree."""

@@ -105,6 +105,46 @@ def test_subiteration_changes_only_its_subtree():
     assert np.any(hs[2][inside & o.leaf_mask] != hs[1][inside & o.leaf_mask])
 
 
+def test_accelerated_whole_model_steps_are_the_accelerated_iteration():
+    """Subiterations with the accelerated iteration (Eq. 3 inside the subtree) whose subtree is
+    the whole model give the accelerated Lambda iteration's temperatures: the cell's arrays sum
+    to A_dust, and its own-level array holds the self-absorption the diagonal operator removes."""
+    tree, dust, star = _small_case()
+    o = oracle.Model(tree, dust)
+    hs, _, _ = oracle.subiterate(o, star, seed=8, schedule=[-1, -1, -1], dust_packets=3000, ali=True)
+    hl, _, _ = oracle.lambda_iterate(o, star, seed=8, n_fixed=3, dust_packets=3000, ali=True)
+    for a, b in zip(hs, hl):
+        np.testing.assert_allclose(a, b, rtol=1e-12)
+
+
+def test_accelerated_subiterations_converge_faster_in_a_thick_core():
+    """A star inside a dense refined root cell (density 20 against 0.05 outside): after a
+    whole-model step and two steps on the core's subtree, the accelerated form has heated the
+    core more than the plain one (both start from the same first step and rise toward the same
+    fixed point from below), and neither changes a temperature outside the subtree in its
+    subtree steps."""
+    lam = np.logspace(-1, 3, 10)
+    dust = gen.Dust(lam, 3.0 * (lam / 0.55) ** -1.6, np.clip(0.5 * (1 - np.log10(lam / 0.1) / 4), 0, 0.5),
+                    np.clip(0.5 * (1 - np.log10(lam / 0.1) / 4), 0, 0.5))
+    core = 1 + 4 * (1 + 4 * 1)
+    tree = gen.TreeDesc(4, 4, 4, 1.0, np.full(64, 0.05), [np.array([core]), np.arange(8)],
+                        [np.full(8, 20.0), np.full(64, 20.0)])
+    nu = brute.CL / (lam * 1e-4)
+    star = [gen.Source(gen.SRC_POINT, 0, pos=(1.55, 1.45, 1.6), power=1e-2 * brute.planck_nu(nu, 5000.0),
+                       packets=1000)]
+    o = oracle.Model(tree, dust)
+    sched = [-1, core, core]
+    hp, _, _ = oracle.subiterate(o, star, seed=3, schedule=sched, dust_packets=1000)
+    ha, _, _ = oracle.subiterate(o, star, seed=3, schedule=sched, dust_packets=1000, ali=True)
+    inside = o.subtree_mask(core)
+    leaf = o.leaf_mask
+    assert ha[1][inside & leaf].mean() > hp[1][inside & leaf].mean()
+    assert ha[-1][inside & leaf].mean() > 1.03 * hp[-1][inside & leaf].mean()
+    for h in (hp, ha):
+        for k in (2, 3):
+            assert np.array_equal(h[k][~inside], h[k - 1][~inside])
+
+
 def _nested_corner():
     """Root 2^3 of side 1 and density 1: root cell 0 refined once, and its level-1 child 7
     (x, y, z in [0.5, 1)) refined again; every other child of root cell 0 is a level-1 leaf."""
