@@ -271,9 +271,8 @@ rt_status rt_ali_iterate(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_sou
  * of r's subtree by more than flux_frac times the energy absorbed in the subtree of r's parent
  * (the whole model for a root cell) since that parent last took part in a step, the parent is
  * tagged, and rt_subiter_select includes every tagged grid until a step includes it.
- * flux_frac = 0: no tracking.  ali != 0 (RT_FP64 form only; RT_EINVAL otherwise): every step
- * uses the accelerated iteration with the diagonal operator (Sect. 3.1 Eq. 3) inside its subtree:
- * each subtree leaf's temperature balances (A - e_self) / (1 - lambda*), with A = A_stars
+ * flux_frac = 0: no tracking.  ali != 0: every step uses the accelerated iteration with the
+ * diagonal operator (Sect. 3.1 Eq. 3) inside its subtree: each subtree leaf's temperature balances (A - e_self) / (1 - lambda*), with A = A_stars
  * plus the leaf's arrays (Eq. 9) and e_self, lambda* = e_self / e_emit from the step's own
  * trace as in rt_ali_iterate; the recorded imbalances and the flows use A itself.
  * rt_subiter_step takes one step with the subtree below `root`, a refined canonical node of

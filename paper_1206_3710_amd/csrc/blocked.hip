@@ -1044,7 +1044,8 @@ hipError_t attr_blk_pass(int block, int lds_bytes) {
   for (const void* f : {pass_fn<false, false, false, false>(block), pass_fn<true, false, false, false>(block),
                         pass_fn<false, true, false, false>(block), pass_fn<true, true, false, false>(block),
                         pass_fn<false, false, true, false>(block), pass_fn<true, false, true, false>(block),
-                        pass_fn<false, false, false, true>(block)}) {
+                        pass_fn<false, false, false, true>(block), pass_fn<true, false, false, true>(block),
+                        pass_fn<false, false, true, true>(block), pass_fn<true, false, true, true>(block)}) {
     if (!f) return hipErrorInvalidValue;
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
@@ -1067,8 +1068,12 @@ static hipError_t launch_pass(const BlkParams& b, int grid, int block, int lds_b
 hipError_t launch_blk_pass(const BlkParams& b, int grid, int block, int lds_bytes, hipStream_t s) {
   const bool split = b.t.split_n > 1, peel = b.t.peel_ev != nullptr, ali = b.t.self_acc != nullptr;
   if (b.lvl_slots > 0) {
-    // the per-level arrays need one FP64 accumulator slot per level; only splitting rides along
-    if (peel || ali || !b.accb64) return hipErrorInvalidValue;
+    // the per-level arrays need one FP64 accumulator slot per level; splitting and the
+    // accelerated tally ride along
+    if (peel || !b.accb64) return hipErrorInvalidValue;
+    if (ali)
+      return split ? launch_pass<true, false, true, true>(b, grid, block, lds_bytes, s)
+                   : launch_pass<false, false, true, true>(b, grid, block, lds_bytes, s);
     return split ? launch_pass<true, false, false, true>(b, grid, block, lds_bytes, s)
                  : launch_pass<false, false, false, true>(b, grid, block, lds_bytes, s);
   }

@@ -1187,9 +1187,9 @@ rt_status trace_impl(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt_
   if ((out.lvl_acc || out.sub_lev >= 0) && fp32) {
     if (o->schedule != RT_SCHED_REGIONS)
       return fail(ctx, RT_EINVAL, "subiterations run in the RT_FP64 form or the region schedule");
-    if (!out.lvl_acc || out.peel || out.self_acc || out.e_lamnode)
-      return fail(ctx, RT_EINVAL, "subiterations in the region schedule take no peel-off, accelerated "
-                                  "tally or per-wavelength output");
+    if (!out.lvl_acc || out.peel || out.e_lamnode)
+      return fail(ctx, RT_EINVAL, "subiterations in the region schedule take no peel-off or per-wavelength "
+                                  "output");
   }
   if (out.peel) {
     p.peel_ev = const_cast<PeelEv*>(out.peel->ev);
@@ -1884,8 +1884,6 @@ rt_status rt_subiter_begin(rt_ctx* ctx, int32_t model, int32_t n_src, const rt_s
       return fail(ctx, RT_EINVAL, "subiterations run in the RT_FP64 form or the region schedule");
     if (!(t_min > 0.0) || !(t_max > t_min)) return fail(ctx, RT_EINVAL, "need 0 < t_min < t_max");
     if (!(flux_frac >= 0.0) || !std::isfinite(flux_frac)) return fail(ctx, RT_EINVAL, "flux_frac must be >= 0");
-    if (ali && opts->precision != RT_FP64)
-      return fail(ctx, RT_EINVAL, "accelerated subiterations run in the RT_FP64 form");
     for (int s = 0; s < n_src; ++s)
       if (src && (src[s].model != model || src[s].kind == RT_SRC_DUST))
         return fail(ctx, RT_EINVAL, "constant sources must belong to the model and not be dust");
@@ -1949,8 +1947,6 @@ rt_status rt_subiter_step(rt_ctx* ctx, int32_t model, int64_t root, int64_t dust
     HostModel& h = ctx->models[model];
     if (!h.sub_ready) return fail(ctx, RT_ESTATE, "rt_subiter_begin not called for model %d", model);
     if (dust_packets < 1 || dust_packets > (int64_t(1) << 32)) return fail(ctx, RT_EINVAL, "bad dust_packets");
-    if (h.sub_ali && opts->precision != RT_FP64)
-      return fail(ctx, RT_EINVAL, "accelerated subiterations run in the RT_FP64 form");
     if (root < -1 || root >= h.n_nodes) return fail(ctx, RT_EINVAL, "bad subtree root");
     int32_t sub_lev = -1, sub_I[3] = {0, 0, 0};
     if (root >= 0) {

@@ -119,8 +119,29 @@ def test_accelerated_subiterations_fp64_against_oracle(torch):
         if r >= 0:
             assert np.array_equal(t[~inside], prev[~inside])
         prev = t
-    with pytest.raises(rt.RTError):  # the region schedule keeps no self-absorption per level
-        ctx.subiter_begin(m, star, seed=3, ali=True, precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS)
+    ctx.close()
+
+
+def test_accelerated_subiterations_regions_against_oracle(torch):
+    """The same accelerated subiterations in the FP32-local region schedule (the level-keyed pass
+    with the self-absorption tally): the mass-weighted temperature difference to the oracle
+    stays below half that between two oracle runs with different seeds, after every step."""
+    tree, dust, star, core = _core_case()
+    star = [gen.Source(s.kind, s.model, pos=s.pos, power=s.power, packets=1000) for s in star]
+    schedule = [-1, core, core]
+    o = oracle.Model(tree, dust)
+    ha, _, _ = oracle.subiterate(o, star, seed=3, schedule=schedule, dust_packets=1000, ali=True)
+    hb, _, _ = oracle.subiterate(o, star, seed=44, schedule=schedule, dust_packets=1000, ali=True)
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    kw = dict(precision=rt.FP32_LOCAL, schedule=rt.SCHED_REGIONS)
+    ctx.subiter_begin(m, star, seed=3, ali=True, **kw)
+    for k, r in enumerate(schedule, start=1):
+        t, crit, st = ctx.subiter_step(m, r, dust_packets=1000, seed=3, iteration=k, **kw)
+        err = _mass_weighted_diff(o, t.cpu().numpy(), ha[k])
+        noise = _mass_weighted_diff(o, hb[k], ha[k])
+        assert err < 0.5 * noise, (k, err, noise)
     ctx.close()
 
 
