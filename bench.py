@@ -54,14 +54,14 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0
 # autotuner picks for the workload (given explicitly to those runs).  Valid only for the kernel
 # sources the counters were taken on.
 PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
-                "sha256": "9149f1e806144dc334b6fe83002f268a91f265a8a893f37b051a24f8464ff7b1",
+                "sha256": "14afdc5f6ed60dab4e9b5d223999d99594a2e9a37d0d6a85be91c99c12377c96",
                 "per_workload": {
                     # profiles/blk_pass_kernel_deep_hierarchy_cloud.md
-                    "deep": {"fetch_bytes_per_crossing": 10.8197, "write_bytes_per_crossing": 5.0763,
+                    "deep": {"fetch_bytes_per_crossing": 10.8202, "write_bytes_per_crossing": 5.0762,
                              "valu_per_crossing": 2.8342, "lane_utilisation": 0.618},
                     # profiles/blk_pass_kernel_molecular_cloud.md
-                    "cloud": {"fetch_bytes_per_crossing": 10.8403, "write_bytes_per_crossing": 6.4065,
-                              "valu_per_crossing": 4.2471, "lane_utilisation": 0.4658}}}
+                    "cloud": {"fetch_bytes_per_crossing": 10.8378, "write_bytes_per_crossing": 6.4064,
+                              "valu_per_crossing": 4.2472, "lane_utilisation": 0.4658}}}
 
 
 WORKLOADS = {
