@@ -344,16 +344,15 @@ hipError_t launch_subiter_update(const ModelDev* models, int model, int64_t n_le
 
 namespace {
 
+// Leaf i of the subtree: a_solve (already a copy of a_tot) takes the balanced power.
 __global__ __launch_bounds__(256) void subiter_ali_kernel(
-    const ModelDev* __restrict__ models, int model, int64_t n_nodes, int64_t n_leaves,
+    const ModelDev* __restrict__ models, int model, int64_t n_leaves,
     const int32_t* __restrict__ leaf_node, const uint8_t* __restrict__ leaf_level,
     const int32_t* __restrict__ leaf_coord, int sub_lev, int32_t s0, int32_t s1, int32_t s2,
     const double* __restrict__ a_tot, const double* __restrict__ e_self, const double* __restrict__ e_emit,
     double* __restrict__ a_solve) {
   const ModelDev& m = models[model];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // refined nodes first take a_tot; the leaves then overwrite theirs
-  if (i < n_nodes) a_solve[i] = a_tot[i];
   if (i >= n_leaves) return;
   const int32_t node = leaf_node[m.leaf_base + i];
   const int lev = leaf_level[m.leaf_base + i];
@@ -388,11 +387,13 @@ hipError_t launch_subiter_ali(const ModelDev* models, int model, int64_t n_nodes
                               const int32_t* leaf_node, const uint8_t* leaf_level, const int32_t* leaf_coord,
                               int sub_lev, const int32_t sub_I[3], const double* a_tot, const double* e_self,
                               const double* e_emit, double* a_solve, hipStream_t s) {
-  const int64_t n = n_nodes > n_leaves ? n_nodes : n_leaves;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(subiter_ali_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, models, model,
-                     n_nodes, n_leaves, leaf_node, leaf_level, leaf_coord, sub_lev, sub_I[0], sub_I[1], sub_I[2],
-                     a_tot, e_self, e_emit, a_solve);
+  // every node first takes a_tot (the copy is ordered before the kernel on the stream, so the
+  // subtree leaves' values are written last)
+  hipError_t e = hipMemcpyAsync(a_solve, a_tot, 8 * (size_t)n_nodes, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess || n_leaves == 0) return e;
+  hipLaunchKernelGGL(subiter_ali_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, s, models, model,
+                     n_leaves, leaf_node, leaf_level, leaf_coord, sub_lev, sub_I[0], sub_I[1], sub_I[2], a_tot,
+                     e_self, e_emit, a_solve);
   return hipGetLastError();
 }
 

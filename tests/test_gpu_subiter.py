@@ -379,6 +379,29 @@ def test_automatic_iteration_with_splitting_against_oracle_fp64(torch):
     np.testing.assert_allclose(t.cpu().numpy()[leaf], hist[n][leaf], rtol=1e-6)
 
 
+def test_automatic_accelerated_iteration_against_oracle_fp64(torch):
+    """The automatic iteration with the flow tracking and accelerated steps, FP64 form: the
+    oracle's roots at every step (subtrees and a parent grid among them) and its temperatures
+    after the last within 1e-6."""
+    w = gen.core_cloud(packets=20000)
+    tree, dust = w.trees[0], w.dusts[0]
+    kw = dict(rr_threshold=w.rr_threshold, rr_prob=w.rr_prob)
+    o = oracle.Model(tree, dust)
+    n = 6
+    hist, roots = oracle.subiterate_auto(o, w.sources, seed=w.seed, n_steps=n, dust_packets=20000, frac=0.5,
+                                         stall=0.8, flux_frac=0.02, ali=True, **kw)
+    assert sum(r >= 0 for r in roots) >= 2, roots
+    ctx = rt.Context(0)
+    m = ctx.build_tree(tree)
+    ctx.set_dust(m, dust)
+    ctx.subiter_begin(m, w.sources, seed=w.seed, flux_frac=0.02, ali=True, **kw)
+    t, r, crit, cross = ctx.subiter_run(m, n, dust_packets=20000, seed=w.seed, frac=0.5, stall=0.8, **kw)
+    ctx.close()
+    assert [int(v) for v in r] == roots, (list(r), roots)
+    leaf = o.leaf_mask
+    np.testing.assert_allclose(t.cpu().numpy()[leaf], hist[n][leaf], rtol=1e-6)
+
+
 def test_automatic_iteration_regions_follows_fp64(torch):
     """The same automatic iteration in the FP32-local region schedule (the flow tallied in the
     region pass): the same roots as the oracle's, and temperatures far below the Monte Carlo
