@@ -580,7 +580,7 @@ def measure(a, rt, gen, torch, w, workload, steps, warmup, copy_gbs, fp64_steps,
         if workload == "disc":
             ctx.set_temperature(m, t0_disc)
         tune_src = dust_src if workload == "disc" else w.sources
-        frac = 0.125
+        frac = 0.25
         params, rate = ctx.autotune(tune_src, seed=w.seed, precision=rt.FP32_LOCAL,
                                     schedule=a.schedule, sample_fraction=frac,
                                     cache=a.tune_cache, rr_threshold=w.rr_threshold,

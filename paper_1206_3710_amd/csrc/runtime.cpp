@@ -2497,8 +2497,8 @@ rt_status rt_autotune(rt_ctx* ctx, int32_t n_src, const rt_source* src, const rt
     };
     std::vector<Axis> axes;
     if (regions) {
-      axes = {{0, {512, 768, 1024}},   {2, {0.15, 0.3, 0.45, 0.6, 0.75}}, {4, {8, 16, 32}},
-              {3, {4, 8, 16, 32, -1}}, {5, {22, 23, 24}}};
+      axes = {{0, {512, 768, 1024}},        {2, {0.15, 0.3, 0.4, 0.45, 0.6, 0.75}}, {4, {8, 12, 16, 24, 32}},
+              {3, {4, 8, 12, 16, 24, 32, -1}}, {5, {22, 23, 24}}};
     } else if (global32) {
       axes = {{0, {64, 128, 256, 512}}, {2, {0.25, 0.5, 0.75}}, {1, {1, 2, 4}}};
     } else {
