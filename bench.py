@@ -742,7 +742,7 @@ def measure(a, rt, gen, torch, w, workload, steps, warmup, copy_gbs, fp64_steps,
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "bench.py runs on one GPU only: this build has no multi-GPU "
+        print(json.dumps({"error": "bench.py runs on one GPU only: the library has no multi-GPU "
                                    "path (--gpus must be 1)"}))
         sys.exit(2)
     import gen
