@@ -9,7 +9,7 @@ one-queue FP32-local form are timed on the same inputs, which splits the gain ov
 form into its schedule and precision parts.  The molecular cloud (root 64^3, 3 levels, 32
 wavelengths, 3.2e8 packets) is measured the same way after it and reported under "cloud".
 Before anything touches the GPU the oracle is timed on the host cores (cpu_baseline: one
-thread; cpu_all_cores: one thread per core of the box's share, on one shared model).
+thread; cpu_all_cores: one thread per core of the host's share, on one shared model).
 
 --workload cloud: the molecular cloud alone.  --workload disc: the circumstellar disc (root
 96x96x32, 6 levels, 50 wavelengths); the star is traced once before timing, and a step is one
@@ -532,8 +532,8 @@ def cpu_baselines(a, gen, w, tree, dust, nl, threads_max=16):
                "nproc": info["nproc"], "affinity": info["affinity"],
                "sample": f"first {n_all} packets{what} at each of the {nl} wavelengths, one packet "
                          f"range per thread over {threads} threads sharing one model ({cr} "
-                         f"crossings, {d3:.1f} s, {info['model']}; the box's CPU share for one GPU "
-                         f"is 16 cores)"}
+                         f"crossings, {d3:.1f} s, {info['model']}; the host's CPU share for one "
+                         f"GPU is 16 cores)"}
     return cpu, cpu_all
 
 
