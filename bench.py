@@ -57,11 +57,11 @@ PASS_TRAFFIC = {"sources": ["blocked.hip", "device.h", "internal.h"],
                 "sha256": "14afdc5f6ed60dab4e9b5d223999d99594a2e9a37d0d6a85be91c99c12377c96",
                 "per_workload": {
                     # profiles/blk_pass_kernel_deep_hierarchy_cloud.md
-                    "deep": {"fetch_bytes_per_crossing": 10.8202, "write_bytes_per_crossing": 5.0762,
-                             "valu_per_crossing": 2.8342, "lane_utilisation": 0.618},
+                    "deep": {"fetch_bytes_per_crossing": 10.9418, "write_bytes_per_crossing": 4.9506,
+                             "valu_per_crossing": 2.8701, "lane_utilisation": 0.6084},
                     # profiles/blk_pass_kernel_molecular_cloud.md
-                    "cloud": {"fetch_bytes_per_crossing": 10.8378, "write_bytes_per_crossing": 6.4064,
-                              "valu_per_crossing": 4.2472, "lane_utilisation": 0.4658}}}
+                    "cloud": {"fetch_bytes_per_crossing": 10.8368, "write_bytes_per_crossing": 6.3967,
+                              "valu_per_crossing": 4.2469, "lane_utilisation": 0.4659}}}
 
 
 WORKLOADS = {
